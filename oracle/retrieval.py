@@ -1,0 +1,253 @@
+"""Per-row TM retrieval, FP64 (test infrastructure only).
+
+Follows Sec. 2.2 of the paper: the per-pixel least-squares problem
+f(t) = || I - |A t|^2 ||^2 (Eq. optTMsmall2), its gradient
+(Eq. derivative, App. A), the back-propagation start (Eq.
+backpropagation) and Algorithm 1 (f, gradient, L-BFGS direction, update,
+stop at maxiter). Also the amplitude-projection form (error reduction, the
+Gerchberg-Saxton / Fienup family the paper's Discussion names) and a
+spectral start.
+
+Readings where the paper is silent:
+  * Gradient packing: the paper's (df/dt)^H = df/dx + j df/dy, i.e. the real
+    gradient over R^{2N} stored as a complex vector; inner products over
+    R^{2N} are Re(a^H b).
+  * L-BFGS (Nocedal & Wright Alg. 7.4, Liu & Nocedal 1989, both cited by
+    the paper): memory m (default 5), H0 = gamma I with
+    gamma = s^T y / y^T y of the newest pair (or a fixed gamma on request),
+    pairs with s^T y <= 0 are skipped, a non-descent direction resets the
+    history and falls back to the negative gradient.
+  * Line search: f(t + a d) is a quartic in a; its exact minimiser over
+    a > 0 is taken among the real roots of the cubic f'(a) = 0 (smallest
+    f, ties to the smaller a).
+  * Zero field in the projection: y/|y| := 1 where y = 0.
+  * Spectral start (plain starts are random or spectral; the paper's
+    back-propagation start does not reach the truth at K = 4): power
+    iteration on A^H diag(w) A with truncated weights
+    w = min(I / mean(I_p), tau), optionally heavy-ball accelerated, then
+    scaled so that ||t||^2 = sum(I_p) / (K N) (Parseval, A^H A = K N I).
+  * Fidelity |t_hat^H t|^2 / (||t_hat||^2 ||t||^2), invariant to a row's
+    phase (Sec. 2.3, Eq. phaseoffset) and scale.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rdot(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Inner product over R^{2N} of complex-packed vectors, per row: Re(a^H b)."""
+    return np.real(np.sum(np.conj(a) * b, axis=-1))
+
+
+def intensity_loss(I: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """f = sum (I - |y|^2)^2 per row (Eq. optTMsmall2)."""
+    r = I - np.abs(y) ** 2
+    return np.sum(r.reshape(r.shape[0], -1) ** 2, axis=1)
+
+
+def amplitude_residual(I: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """sum (sqrt(I) - |y|)^2 per row: the amplitude-based cost the paper's
+    Discussion names for Poisson noise."""
+    d = np.sqrt(I) - np.abs(y)
+    return np.sum(d.reshape(d.shape[0], -1) ** 2, axis=1)
+
+
+def intensity_grad(op, I: np.ndarray, t: np.ndarray):
+    """(df/dt)^H = -4 A^H diag(A t) (I - |A t|^2) (Eq. derivative).
+    Returns (f, grad, y)."""
+    y = op.forward(t)
+    r = I - np.abs(y) ** 2
+    g = -4.0 * op.adjoint(y * r)
+    return np.sum(r.reshape(r.shape[0], -1) ** 2, axis=1), g, y
+
+
+def acceptance_residual(op, I: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """rho_p = ||I_p - |A t_p|^2||^2 / ||I_p||^2, a ground-truth-free
+    per-row error flag."""
+    f = intensity_loss(I, op.forward(t))
+    return f / np.sum(I.reshape(I.shape[0], -1) ** 2, axis=1)
+
+
+def phase_of(y: np.ndarray) -> np.ndarray:
+    """y / |y| with the zero-field convention 1 at y == 0."""
+    a = np.abs(y)
+    out = np.ones_like(y)
+    nz = a > 0
+    out[nz] = y[nz] / a[nz]
+    return out
+
+
+def er_step(op, I: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """One projection (error-reduction) step: keep the measured amplitudes,
+    keep the current phases, project back: t <- A^H(sqrt(I) y/|y|) / (K N).
+    A A^H / (K N) is the orthogonal projector onto range(A), so the amplitude
+    residual cannot increase."""
+    y = op.forward(t)
+    return op.adjoint(np.sqrt(I) * phase_of(y)) / (op.K * op.N)
+
+
+def backprop_start(op, I: np.ndarray) -> np.ndarray:
+    """t0 = (A^H A)^{-1} A^H sqrt(I) = A^H sqrt(I) / (K N) (Eq. backpropagation)."""
+    return op.adjoint(np.sqrt(I)) / (op.K * op.N)
+
+
+def spectral_weights(I: np.ndarray, tau: float) -> np.ndarray:
+    m = np.mean(I.reshape(I.shape[0], -1), axis=1)
+    m = np.where(m > 0, m, 1.0)
+    return np.minimum(I / m[:, None, None], tau)
+
+
+def spectral_start(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3.0,
+                   momentum: float = 0.0) -> np.ndarray:
+    """Truncated spectral start: power iteration on M = A^H diag(w) A from v0
+    (unit-normalised each step), then scaled to ||t||^2 = sum(I)/(K N).
+
+    momentum = c > 0 selects the heavy-ball power method (Xu et al.,
+    "Accelerated stochastic power iteration", 2018): x_{k+1} = M x_k -
+    beta_k x_{k-1} with beta_k = (c lambda_k)^2 / 4 and lambda_k the
+    Rayleigh quotient of the current unit vector; both x_{k+1} and x_k are
+    divided by ||x_{k+1}|| so the recurrence keeps its ratios. It converges
+    to the same top eigenvector in fewer steps. c = 0 is plain power
+    iteration."""
+    w = spectral_weights(I, tau)
+    v = np.array(v0, dtype=np.complex128)
+    n = np.linalg.norm(v, axis=1)
+    v = v / np.where(n > 0, n, 1.0)[:, None]
+    vp = np.zeros_like(v)
+    for _ in range(iters):
+        Mv = op.adjoint(w * op.forward(v))
+        lam = rdot(v, Mv)
+        beta = (momentum * lam) ** 2 / 4.0
+        x = Mv - beta[:, None] * vp
+        n = np.linalg.norm(x, axis=1)
+        n = np.where(n > 0, n, 1.0)[:, None]
+        vp = v / n
+        v = x / n
+    scale = np.sqrt(np.sum(I.reshape(I.shape[0], -1), axis=1) / (op.K * op.N))
+    return v * scale[:, None]
+
+
+def fidelity(t_hat: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Per-row |t_hat^H t|^2 / (||t_hat||^2 ||t||^2)."""
+    num = np.abs(np.sum(np.conj(t_hat) * t, axis=-1)) ** 2
+    den = np.sum(np.abs(t_hat) ** 2, axis=-1) * np.sum(np.abs(t) ** 2, axis=-1)
+    return num / np.where(den > 0, den, 1.0)
+
+
+def quartic_coeffs(I: np.ndarray, y: np.ndarray, z: np.ndarray):
+    """Coefficients of phi(a) = f(t + a d) - f(t) = c1 a + c2 a^2 + c3 a^3 + c4 a^4,
+    with y = A t, z = A d, r = I - |y|^2, b = Re(conj(y) z), c = |z|^2:
+    |y + a z|^2 = |y|^2 + 2ab + a^2 c, so f(a) = sum (r - 2ab - a^2 c)^2."""
+    r = I - np.abs(y) ** 2
+    b = np.real(np.conj(y) * z)
+    c = np.abs(z) ** 2
+    ax = tuple(range(1, r.ndim))
+    c1 = -4.0 * np.sum(r * b, axis=ax)
+    c2 = np.sum(4.0 * b * b - 2.0 * r * c, axis=ax)
+    c3 = 4.0 * np.sum(b * c, axis=ax)
+    c4 = np.sum(c * c, axis=ax)
+    return c1, c2, c3, c4
+
+
+def exact_step(c1: float, c2: float, c3: float, c4: float) -> float:
+    """Minimiser over a > 0 of c1 a + c2 a^2 + c3 a^3 + c4 a^4: among the
+    real positive roots of 4 c4 a^3 + 3 c3 a^2 + 2 c2 a + c1 = 0 take the
+    one of smallest value (ties: smaller a). Returns 0 when there is none."""
+    if not (c4 > 0):
+        if c2 > 0 and c1 < 0:
+            return -c1 / (2 * c2)
+        return 0.0
+    roots = np.roots([4 * c4, 3 * c3, 2 * c2, c1])
+    cand = []
+    for rt in roots:
+        if abs(rt.imag) <= 1e-7 * max(1.0, abs(rt)) and rt.real > 0:
+            a = rt.real
+            cand.append((c1 * a + c2 * a * a + c3 * a ** 3 + c4 * a ** 4, a))
+    if not cand:
+        return 0.0
+    cand.sort()
+    return float(cand[0][1])
+
+
+def lbfgs_core(eval_fg, line_min, t0: np.ndarray, iters: int, m: int = 5,
+               gamma: float | None = None, callback=None):
+    """Generic per-row L-BFGS loop of Algorithm 1: `eval_fg(t) -> (f, g, aux)`
+    gives the error and packed gradient, `line_min(t, d, aux) -> alpha` the
+    step along d. Returns (t, per-iteration f history [iters+1, P])."""
+    t = np.array(t0, dtype=np.complex128)
+    P = t.shape[0]
+    S = [[] for _ in range(P)]
+    Y = [[] for _ in range(P)]
+    f, g, aux = eval_fg(t)
+    hist = [f.copy()]
+    for _ in range(iters):
+        d = two_loop(g, S, Y, gamma)
+        slope = rdot(g, d)
+        bad = ~(slope < 0)
+        if np.any(bad):
+            for p in np.nonzero(bad)[0]:
+                S[p], Y[p] = [], []
+            d[bad] = -g[bad]
+        alpha = line_min(t, d, aux)
+        t_new = t + alpha[:, None] * d
+        f_new, g_new, aux_new = eval_fg(t_new)
+        s_vec = t_new - t
+        y_vec = g_new - g
+        sy = rdot(s_vec, y_vec)
+        for p in range(P):
+            if sy[p] > 0:
+                S[p].append(s_vec[p])
+                Y[p].append(y_vec[p])
+                if len(S[p]) > m:
+                    S[p].pop(0)
+                    Y[p].pop(0)
+        t, f, g, aux = t_new, f_new, g_new, aux_new
+        hist.append(f.copy())
+        if callback is not None:
+            callback(t)
+    return t, np.array(hist)
+
+
+def lbfgs(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5,
+          gamma: float | None = None, callback=None):
+    """Algorithm 1 of the paper for every row at once: per iteration the
+    error and gradient at the current t (Eq. optTMsmall2, Eq. derivative),
+    an L-BFGS direction from the last m (s, y) pairs (two-loop recursion
+    over R^{2N}), the exact line search on the quartic, and the update
+    t <- t + a d (the paper's t - Delta t). Stops at `iters` (maxiter).
+    Returns (t, per-iteration f history [iters+1, P])."""
+
+    def eval_fg(t):
+        return intensity_grad(op, I, t)
+
+    def line_min(t, d, y):
+        z = op.forward(d)
+        c1, c2, c3, c4 = quartic_coeffs(I, y, z)
+        return np.array([exact_step(c1[p], c2[p], c3[p], c4[p]) for p in range(t.shape[0])])
+
+    return lbfgs_core(eval_fg, line_min, t0, iters, m, gamma, callback)
+
+
+def two_loop(g: np.ndarray, S, Y, gamma: float | None) -> np.ndarray:
+    """L-BFGS two-loop recursion per row (Nocedal & Wright Alg. 7.4):
+    returns d = -H g with the inverse-Hessian approximation built from the
+    stored pairs, oldest first in S[p], Y[p]."""
+    d = np.empty_like(g)
+    for p in range(g.shape[0]):
+        q = g[p].copy()
+        a = []
+        for s_, y_ in zip(reversed(S[p]), reversed(Y[p])):
+            rho = 1.0 / np.real(np.vdot(y_, s_))
+            ai = rho * np.real(np.vdot(s_, q))
+            q = q - ai * y_
+            a.append(ai)
+        if gamma is not None:
+            q = q * gamma
+        elif S[p]:
+            q = q * (np.real(np.vdot(S[p][-1], Y[p][-1])) / np.real(np.vdot(Y[p][-1], Y[p][-1])))
+        for (s_, y_), ai in zip(zip(S[p], Y[p]), reversed(a)):
+            rho = 1.0 / np.real(np.vdot(y_, s_))
+            b = rho * np.real(np.vdot(y_, q))
+            q = q + (ai - b) * s_
+        d[p] = -q
+    return d
