@@ -1,0 +1,194 @@
+/*
+ * tm.h - C ABI of the MI355X (gfx950) library for reference-less
+ * transmission-matrix (TM) retrieval with Fourier-structured probing.
+ *
+ * Method: Zhong et al., "Efficient reference-less transmission matrix
+ * retrieval for a multimode fiber using fast Fourier transform",
+ * arXiv 2302.13524. Each TM row t_p (length N = n1*n2 input modes) is
+ * recovered from its K*N intensities I_p = |A t_p|^2 where
+ *   A = [F diag(psi_1); ...; F diag(psi_K)]                (Sec. 2.2, Eq. probingmatrix)
+ * F is the unnormalised 2-D DFT (kernel exp(-2 pi j k i / n)) of the
+ * row-major n1 x n2 mode grid (index i = i1*n2 + i2), psi_m are K
+ * unit-modulus random-phase masks shared by all rows. A is never stored:
+ * A x is K masked 2-D FFTs, A^H y is K inverse FFTs (unnormalised,
+ * F^H = N * inverse) multiplied by conj(psi_m) and summed.
+ *
+ * Conventions for every entry point
+ *  - Ownership: every array argument is a caller-owned DEVICE pointer
+ *    (hipMalloc / torch), unless the comment says host. The library never
+ *    frees or keeps caller pointers after the call returns; it allocates
+ *    only its own workspace inside the context (twiddle tables, solver
+ *    history), which tm_destroy releases.
+ *  - Streams: `stream` is a hipStream_t (NULL = default stream). Calls are
+ *    stream-ordered and asynchronous unless the comment says otherwise.
+ *  - Layout: row-major, contiguous. Complex values are interleaved
+ *    (re, im) float pairs (tm_c32) or double pairs (tm_c64).
+ *    Intensities are [P][K][n1][n2] (mask-major per row).
+ *  - Errors: functions return TM_OK (0) or a negative code; argument
+ *    checks run on the host before any device work is queued, so an error
+ *    return means nothing was launched. tm_last_error() gives a message.
+ *  - Threads: one context must not be used by two host threads at once.
+ *  - Supported grids: n1, n2 powers of two, 16 <= N <= 8192, each of
+ *    n1, n2 <= 128, or 1-D grids (n1 = 1) with N <= 8192;
+ *    tm_grid_supported() tells.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tm_ctx tm_ctx;
+
+typedef struct { float re, im; } tm_c32;
+typedef struct { double re, im; } tm_c64;
+
+enum {
+  TM_OK = 0,
+  TM_EINVAL = -1,        /* bad argument (null pointer, size, enum value)  */
+  TM_EUNSUPPORTED = -2,  /* grid not in the compiled FFT plan set          */
+  TM_EHIP = -3,          /* a HIP runtime call failed (message kept)       */
+  TM_ENOMEM = -4         /* workspace allocation failed                    */
+};
+
+/* Problem size: N = n1*n2 modes, K masks, P rows. */
+typedef struct {
+  int32_t n1, n2, K, P;
+} tm_dims;
+
+/* Intensity storage type. */
+enum { TM_F32 = 0, TM_BF16 = 1 };
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device`. *ctx receives the handle. */
+int tm_create(tm_ctx **ctx, int device);
+/* Destroy a context and free its workspace (synchronises its device). */
+int tm_destroy(tm_ctx *ctx);
+/* Message for the last error on this context (never NULL). ctx may be NULL
+ * for errors from tm_create. */
+const char *tm_last_error(const tm_ctx *ctx);
+/* 1 if the (n1, n2) grid has compiled FFT kernels, else 0. */
+int tm_grid_supported(int32_t n1, int32_t n2);
+
+/* ---- probing operator (Sec. 2.2, Eq. probingmatrix) --------------------- */
+
+enum { TM_FIELD = 0, TM_INTENSITY = 1 };
+
+/* Forward model y = A t for every row.
+ *   masks [K][N] tm_c32 unit-modulus mask fields e^{j psi_m}
+ *   t     [P][N] tm_c32 TM rows
+ *   out_kind TM_FIELD:     out is tm_c32 y[P][K][N]
+ *            TM_INTENSITY: out is I[P][K][N] = |y|^2 of type out_dtype
+ *                          (TM_F32 float or TM_BF16 bfloat16 bits, RNE)
+ * (Eq. forwardmodel applied per pixel as Eq. optTMsmall2.) */
+int tm_forward(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const tm_c32 *t,
+               int out_kind, int out_dtype, void *out, void *stream);
+
+/* Adjoint x = A^H y = sum_m conj(psi_m) * F^H y_m for every row
+ * (the inverse FFTs the paper uses for Q^H, Sec. 2.2).
+ *   y [P][K][N] tm_c32, x [P][N] tm_c32 (overwritten). */
+int tm_adjoint(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const tm_c32 *y,
+               tm_c32 *x, void *stream);
+
+/* Packed gradient of f(t) = ||I - |A t|^2||^2 (Eq. derivative, App. A):
+ *   grad = -4 A^H ( (A t) (I - |A t|^2) ),  packed as d/dRe + j d/dIm.
+ *   I [P][K][N] (I_dtype), grad [P][N] tm_c32, f [P] float (may be NULL):
+ *   f_p = sum (I - |A t|^2)^2 with compensated FP32 summation. */
+int tm_gradient(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, int I_dtype,
+                const tm_c32 *t, tm_c32 *grad, float *f, void *stream);
+
+/* FP64 acceptance residual per row:
+ *   rho_p = ||I_p - |A t_p|^2||^2 / ||I_p||^2
+ * evaluated with FP64 FFTs and FP64 sums from the FP32 inputs.
+ *   rho [P] double. */
+int tm_residual_f64(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, int I_dtype,
+                    const tm_c32 *t, double *rho, void *stream);
+
+/* ---- retrieval (Sec. 2.2, Alg. 1) --------------------------------------- */
+
+enum { TM_METHOD_ER = 0, TM_METHOD_LBFGS = 1 };
+enum {
+  TM_START_GIVEN = 0,     /* use t as passed in                                  */
+  TM_START_BACKPROP = 1,  /* t = A^H sqrt(I) / (K N)          (Eq. backpropagation) */
+  TM_START_SPECTRAL = 2   /* truncated spectral start seeded with the t passed in  */
+};
+
+typedef struct {
+  int32_t method;          /* TM_METHOD_ER (projection) or TM_METHOD_LBFGS (Alg. 1)     */
+  int32_t iters;           /* solver iterations (the paper's maxiter), >= 0              */
+  int32_t lbfgs_m;         /* L-BFGS memory, 1..16 (default 5)                           */
+  int32_t I_dtype;         /* TM_F32 or TM_BF16                                          */
+  int32_t start;           /* TM_START_*                                                 */
+  int32_t spectral_iters;  /* power-iteration steps for TM_START_SPECTRAL                */
+  float spectral_tau;      /* weight truncation w = min(I/mean(I_p), tau), e.g. 3        */
+  float spectral_momentum; /* heavy-ball factor c in [0, 1): beta = (c lambda)^2/4       */
+} tm_retrieve_opts;
+
+/* Per-row results written to device memory. */
+typedef struct {
+  double rho;      /* FP64 acceptance residual of the returned row              */
+  float f;         /* intensity loss sum (I - |A t|^2)^2 at the last evaluation  */
+  float amp_res;   /* amplitude residual sum (sqrt(I) - |A t|)^2 (ER only)       */
+  int32_t iters;   /* iterations run                                           */
+  int32_t flags;   /* bit 0: rho > 1e-2 (row not accepted); bit 1: non-finite   */
+} tm_row_stats;
+
+/* Retrieve every row. t is in/out: the start (or the spectral seed) on
+ * entry, the result on exit. stats [P] may be NULL. Asynchronous. */
+int tm_retrieve(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I,
+                tm_c32 *t, const tm_retrieve_opts *opts, tm_row_stats *stats,
+                void *stream);
+
+/* ---- phase-offset correction (Sec. 2.3) -------------------------------- */
+
+typedef struct {
+  int32_t P;            /* rows (pixels) with a retrieved TM row                   */
+  int32_t N;            /* modes per row                                           */
+  int32_t Nd;           /* defocus images                                          */
+  int32_t nf1, nf2;     /* field grid; images are (2 nf1) x (2 nf2)                */
+} tm_defocus_dims;
+
+typedef struct {
+  double lambda;   /* wavelength                                   */
+  double ps_field; /* field-grid pixel size (same length unit)     */
+  double NA;       /* numerical aperture of the pupil              */
+  double z;        /* defocus distance z_d                         */
+} tm_optics;
+
+typedef struct {
+  int32_t iters;       /* L-BFGS iterations over phi            */
+  int32_t m;           /* L-BFGS memory (1..16)                 */
+} tm_phase_opts;
+
+/* Solve the per-row phase offsets phi of TM_true = diag(e^{j phi}) TM_est
+ * (Eq. phaseoffset) from defocus intensities by L-BFGS on
+ *   g(phi) = sum_n || I_n - | K2^H P diag(h) K1 diag(c_n) e^{j phi} |^2 ||^2
+ * (Eq. forwarddefocusImage, Eq. optphase, gradient Eq. phasederive), FP64.
+ *   pix    [P] int32 raster index of each row's pixel in the nf1 x nf2 grid
+ *   tm_est [P][N] tm_c32, theta [Nd][N] tm_c32 unit-modulus inputs e^{j theta_n}
+ *   I_d    [Nd][2nf1][2nf2] float defocus images
+ *   phi    [P] double: start on entry (zeros in the paper), result on exit
+ *   g_out  host double* (may be NULL): final objective value.
+ * Synchronous with respect to the host (the line search reads the
+ * objective back); work is queued on `stream`. */
+int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,
+                            const tm_c32 *tm_est, const tm_c32 *theta, const float *I_d,
+                            const tm_optics *optics, double *phi, const tm_phase_opts *opts,
+                            double *g_out, void *stream);
+
+/* Objective and gradient of the phase-offset problem at phi (FP64):
+ *   g_dev [1] double, grad [P] double (both device). */
+int tm_phase_objective(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,
+                       const tm_c32 *tm_est, const tm_c32 *theta, const float *I_d,
+                       const tm_optics *optics, const double *phi, double *g_dev,
+                       double *grad, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

@@ -1,0 +1,270 @@
+"""Python binding of libtm.so (include/tm.h): reference-less TM retrieval with
+Fourier-structured probing on MI355X (gfx950).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. Tensors are torch device tensors (contiguous; complex64 for
+complex data, float32 or bfloat16 for intensities); the current torch
+stream of the tensor's device is passed to the library. The names mirror
+the C entry points. Importing works without a GPU; calling anything needs
+the built library and a GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtm.so")
+
+TM_OK, TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENOMEM = 0, -1, -2, -3, -4
+TM_F32, TM_BF16 = 0, 1
+TM_FIELD, TM_INTENSITY = 0, 1
+TM_METHOD_ER, TM_METHOD_LBFGS = 0, 1
+TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL = 0, 1, 2
+
+EXPORTED = (
+    "tm_create", "tm_destroy", "tm_last_error", "tm_grid_supported", "tm_forward", "tm_adjoint",
+    "tm_gradient", "tm_residual_f64", "tm_retrieve", "tm_phase_offset_correct", "tm_phase_objective",
+)
+
+
+class tm_dims(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("K", ctypes.c_int32), ("P", ctypes.c_int32)]
+
+
+class tm_retrieve_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("iters", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
+                ("I_dtype", ctypes.c_int32), ("start", ctypes.c_int32), ("spectral_iters", ctypes.c_int32),
+                ("spectral_tau", ctypes.c_float), ("spectral_momentum", ctypes.c_float)]
+
+
+class tm_defocus_dims(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("N", ctypes.c_int32), ("Nd", ctypes.c_int32),
+                ("nf1", ctypes.c_int32), ("nf2", ctypes.c_int32)]
+
+
+class tm_optics(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("ps_field", ctypes.c_double), ("NA", ctypes.c_double),
+                ("z", ctypes.c_double)]
+
+
+class tm_phase_opts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("m", ctypes.c_int32)]
+
+
+ROW_STATS_BYTES = 24
+
+_lib = None
+
+
+class TMError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise TMError(f"{path} not found: build it with paper_2302_13524_amd/build.py "
+                      "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.tm_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.tm_destroy.argtypes = [vp]
+    lib.tm_last_error.argtypes = [vp]
+    lib.tm_last_error.restype = ctypes.c_char_p
+    lib.tm_grid_supported.argtypes = [i32, i32]
+    lib.tm_forward.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.tm_adjoint.argtypes = [vp, tm_dims, vp, vp, vp, vp]
+    lib.tm_gradient.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.tm_residual_f64.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp]
+    lib.tm_retrieve.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), vp, vp]
+    lib.tm_phase_offset_correct.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
+                                            ctypes.POINTER(tm_optics), vp, ctypes.POINTER(tm_phase_opts),
+                                            ctypes.POINTER(dp), vp]
+    lib.tm_phase_objective.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
+                                       ctypes.POINTER(tm_optics), vp, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if not x.is_cuda:
+        raise TMError("tensor must live on the GPU")
+    if not x.is_contiguous():
+        raise TMError("tensor must be contiguous")
+    return x.data_ptr()
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _idtype(I: torch.Tensor) -> int:
+    if I.dtype == torch.float32:
+        return TM_F32
+    if I.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return TM_BF16
+    raise TMError(f"intensity dtype {I.dtype} (float32 or bfloat16)")
+
+
+class Context:
+    """A library context on one GPU (tm_create / tm_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = self.lib.tm_create(ctypes.byref(h), device)
+        if rc != TM_OK:
+            raise TMError(f"tm_create: {self.lib.tm_last_error(None).decode()} ({rc})")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int, what: str):
+        if rc != TM_OK:
+            raise TMError(f"{what}: {self.lib.tm_last_error(self.h).decode()} (code {rc})")
+
+    def grid_supported(self, n1: int, n2: int) -> bool:
+        return bool(self.lib.tm_grid_supported(n1, n2))
+
+
+def _dims(n1, n2, K, P) -> tm_dims:
+    return tm_dims(int(n1), int(n2), int(K), int(P))
+
+
+def tm_forward(ctx: Context, masks, t, n1, n2, intensity: bool = False, bf16: bool = False, out=None):
+    """y = A t ([P, K, N] complex64) or I = |A t|^2 ([P, K, N] float32 / bfloat16)."""
+    K, N = masks.shape
+    P = t.shape[0]
+    if out is None:
+        dt = torch.complex64 if not intensity else (torch.bfloat16 if bf16 else torch.float32)
+        out = torch.empty((P, K, N), dtype=dt, device=t.device)
+    rc = ctx.lib.tm_forward(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(t),
+                            TM_INTENSITY if intensity else TM_FIELD, TM_BF16 if bf16 else TM_F32,
+                            _ptr(out), _stream(t.device))
+    ctx.check(rc, "tm_forward")
+    return out
+
+
+def tm_adjoint(ctx: Context, masks, y, n1, n2, out=None):
+    """x = A^H y, y [P, K, N] complex64 -> [P, N] complex64."""
+    K, N = masks.shape
+    P = y.shape[0]
+    out = torch.empty((P, N), dtype=torch.complex64, device=y.device) if out is None else out
+    rc = ctx.lib.tm_adjoint(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(y), _ptr(out), _stream(y.device))
+    ctx.check(rc, "tm_adjoint")
+    return out
+
+
+def tm_gradient(ctx: Context, masks, I, t, n1, n2):
+    """Packed gradient -4 A^H((A t)(I - |A t|^2)) and f per row."""
+    K, N = masks.shape
+    P = t.shape[0]
+    g = torch.empty((P, N), dtype=torch.complex64, device=t.device)
+    f = torch.empty((P,), dtype=torch.float32, device=t.device)
+    rc = ctx.lib.tm_gradient(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t), _ptr(g),
+                             _ptr(f), _stream(t.device))
+    ctx.check(rc, "tm_gradient")
+    return g, f
+
+
+def tm_residual_f64(ctx: Context, masks, I, t, n1, n2):
+    """FP64 acceptance residual ||I - |A t|^2||^2 / ||I||^2 per row."""
+    K, N = masks.shape
+    P = t.shape[0]
+    rho = torch.empty((P,), dtype=torch.float64, device=t.device)
+    rc = ctx.lib.tm_residual_f64(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t),
+                                 _ptr(rho), _stream(t.device))
+    ctx.check(rc, "tm_residual_f64")
+    return rho
+
+
+@dataclass
+class RowStats:
+    rho: torch.Tensor
+    f: torch.Tensor
+    amp_res: torch.Tensor
+    iters: torch.Tensor
+    flags: torch.Tensor
+
+
+def decode_stats(raw: torch.Tensor) -> RowStats:
+    b = raw.cpu()
+    return RowStats(rho=b[:, 0:8].contiguous().view(torch.float64).reshape(-1),
+                    f=b[:, 8:12].contiguous().view(torch.float32).reshape(-1),
+                    amp_res=b[:, 12:16].contiguous().view(torch.float32).reshape(-1),
+                    iters=b[:, 16:20].contiguous().view(torch.int32).reshape(-1),
+                    flags=b[:, 20:24].contiguous().view(torch.int32).reshape(-1))
+
+
+def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", spectral_iters=30,
+                  spectral_tau=3.0, spectral_momentum=0.98) -> tm_retrieve_opts:
+    m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS}[method]
+    s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL}[start]
+    return tm_retrieve_opts(m, int(iters), int(lbfgs_m), TM_BF16 if bf16 else TM_F32, s, int(spectral_iters),
+                            float(spectral_tau), float(spectral_momentum))
+
+
+def tm_retrieve(ctx: Context, masks, I, t, n1, n2, opts: tm_retrieve_opts | None = None, stats=True, **kw):
+    """Retrieve every row in place in t ([P, N] complex64); returns the raw
+    per-row stats tensor ([P, 24] uint8, see decode_stats) or None."""
+    K, N = masks.shape
+    P = t.shape[0]
+    if opts is None:
+        opts = retrieve_opts(bf16=(I.dtype != torch.float32), **kw)
+    raw = torch.empty((P, ROW_STATS_BYTES), dtype=torch.uint8, device=t.device) if stats else None
+    rc = ctx.lib.tm_retrieve(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _ptr(t), ctypes.byref(opts),
+                             _ptr(raw), _stream(t.device))
+    ctx.check(rc, "tm_retrieve")
+    return raw
+
+
+def _ddims(P, N, Nd, nf1, nf2):
+    return tm_defocus_dims(int(P), int(N), int(Nd), int(nf1), int(nf2))
+
+
+def tm_phase_objective(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2):
+    """g(phi) and dg/dphi of the defocus problem (FP64)."""
+    P, N = tm_est.shape
+    Nd = theta.shape[0]
+    g = torch.empty((1,), dtype=torch.float64, device=tm_est.device)
+    grad = torch.empty((P,), dtype=torch.float64, device=tm_est.device)
+    dd = _ddims(P, N, Nd, nf1, nf2)
+    op = tm_optics(*[float(v) for v in optics])
+    rc = ctx.lib.tm_phase_objective(ctx.h, ctypes.byref(dd), _ptr(pix), _ptr(tm_est), _ptr(theta), _ptr(I_d),
+                                    ctypes.byref(op), _ptr(phi), _ptr(g), _ptr(grad), _stream(tm_est.device))
+    ctx.check(rc, "tm_phase_objective")
+    return g, grad
+
+
+def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2, iters=100, m=5):
+    """Solve the per-row phase offsets in place in phi ([P] float64); returns g."""
+    P, N = tm_est.shape
+    Nd = theta.shape[0]
+    dd = _ddims(P, N, Nd, nf1, nf2)
+    op = tm_optics(*[float(v) for v in optics])
+    po = tm_phase_opts(int(iters), int(m))
+    g = ctypes.c_double(0.0)
+    rc = ctx.lib.tm_phase_offset_correct(ctx.h, ctypes.byref(dd), _ptr(pix), _ptr(tm_est), _ptr(theta),
+                                         _ptr(I_d), ctypes.byref(op), _ptr(phi), ctypes.byref(po),
+                                         ctypes.byref(g), _stream(tm_est.device))
+    ctx.check(rc, "tm_phase_offset_correct")
+    return g.value

@@ -1,0 +1,13 @@
+// Host-side launchers of the helper kernels (aux_kernels.hip).
+#pragma once
+#include <stdint.h>
+
+namespace tmk {
+int launch_row_isum(const void* I, int bf16, int64_t len, int P, double* rowsum, float* rowmean,
+                    void* stream);
+int launch_row_rescale(void* t, int N, int P, int mode, const double* rowsum, double denom,
+                       void* stream);
+int launch_fill_zero(void* p, int64_t bytes, void* stream);
+int launch_finalize(void* stats, int P, const double* sums64, const float* sums, int nsum,
+                    int f_idx, int amp_idx, int iters, double rho_flag, void* stream);
+}  // namespace tmk

@@ -1,0 +1,132 @@
+// Small row-wise helper kernels around the fused FFT kernels: per-row
+// intensity statistics, normalisation and scaling of rows, zero fill (used
+// instead of memset so the launches stay graph-capturable), and the per-row
+// result record.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "aux.hpp"
+
+namespace tmk {
+
+static __device__ __forceinline__ float bf16f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <int WG>
+static __device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < WG / 64; ++i) s += red[i];
+  return s;
+}
+
+// rowsum[p] = sum_k I[p][k] (FP64 accumulation), rowmean = rowsum / len.
+__global__ void __launch_bounds__(256) k_row_isum(const void* I, int bf16, int64_t len, int P,
+                                                   double* rowsum, float* rowmean) {
+  __shared__ double red[4];
+  int p = blockIdx.x;
+  if (p >= P) return;
+  double s = 0;
+  if (bf16) {
+    const uint16_t* src = (const uint16_t*)I + (size_t)p * len;
+    for (int64_t i = threadIdx.x; i < len; i += 256) s += (double)bf16f(src[i]);
+  } else {
+    const float* src = (const float*)I + (size_t)p * len;
+    for (int64_t i = threadIdx.x; i < len; i += 256) s += (double)src[i];
+  }
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) {
+    if (rowsum) rowsum[p] = s;
+    if (rowmean) rowmean[p] = (float)(s / (double)len);
+  }
+}
+
+// t[p] *= scale_p where scale_p = 1/||t_p|| (mode 0) or
+// sqrt(rowsum[p] / denom) / ||t_p|| (mode 1).
+__global__ void __launch_bounds__(256) k_row_rescale(float2* t, int N, int P, int mode,
+                                                      const double* rowsum, double denom) {
+  __shared__ double red[4];
+  int p = blockIdx.x;
+  if (p >= P) return;
+  float2* r = t + (size_t)p * N;
+  double s = 0;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    float2 v = r[i];
+    s += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  s = block_sum<256>(s, red);
+  double sc = (s > 0) ? 1.0 / sqrt(s) : 1.0;
+  if (mode == 1) sc *= sqrt(fmax(rowsum[p], 0.0) / denom);
+  float f = (float)sc;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    float2 v = r[i];
+    r[i] = make_float2(v.x * f, v.y * f);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(uint32_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) p[i] = 0u;
+}
+
+// Per-row result record (layout of tm_row_stats).
+struct RowStats {
+  double rho;
+  float f;
+  float amp_res;
+  int32_t iters;
+  int32_t flags;
+};
+
+__global__ void __launch_bounds__(256) k_finalize(RowStats* st, int P, const double* sums64,
+                                                   const float* sums, int nsum, int f_idx,
+                                                   int amp_idx, int iters, double rho_flag) {
+  int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  double sr = sums64[2 * p], si = sums64[2 * p + 1];
+  double rho = (si > 0) ? sr / si : (sr > 0 ? INFINITY : 0.0);
+  RowStats r;
+  r.rho = rho;
+  r.f = (sums && f_idx >= 0) ? sums[(size_t)p * nsum + f_idx] : (float)sr;
+  r.amp_res = (sums && amp_idx >= 0) ? sums[(size_t)p * nsum + amp_idx] : 0.f;
+  r.iters = iters;
+  int flags = 0;
+  if (!(rho <= rho_flag)) flags |= 1;
+  if (!isfinite(rho)) flags |= 2;
+  r.flags = flags;
+  st[p] = r;
+}
+
+// ------------------------------------------------------------------ launchers
+int launch_row_isum(const void* I, int bf16, int64_t len, int P, double* rowsum, float* rowmean,
+                    void* s) {
+  if (P <= 0) return 0;
+  k_row_isum<<<P, 256, 0, (hipStream_t)s>>>(I, bf16, len, P, rowsum, rowmean);
+  return (int)hipGetLastError();
+}
+int launch_row_rescale(void* t, int N, int P, int mode, const double* rowsum, double denom,
+                       void* s) {
+  if (P <= 0) return 0;
+  k_row_rescale<<<P, 256, 0, (hipStream_t)s>>>((float2*)t, N, P, mode, rowsum, denom);
+  return (int)hipGetLastError();
+}
+int launch_fill_zero(void* p, int64_t bytes, void* s) {
+  int64_t n = bytes / 4;
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_fill_zero<<<(int)blocks, 256, 0, (hipStream_t)s>>>((uint32_t*)p, n);
+  return (int)hipGetLastError();
+}
+int launch_finalize(void* st, int P, const double* sums64, const float* sums, int nsum, int f_idx,
+                    int amp_idx, int iters, double rho_flag, void* s) {
+  if (P <= 0) return 0;
+  k_finalize<<<(P + 255) / 256, 256, 0, (hipStream_t)s>>>((RowStats*)st, P, sums64, sums, nsum,
+                                                           f_idx, amp_idx, iters, rho_flag);
+  return (int)hipGetLastError();
+}
+
+}  // namespace tmk

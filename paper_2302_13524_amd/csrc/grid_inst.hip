@@ -1,0 +1,54 @@
+// Instantiates the row kernels for one grid, selected at compile time by
+// -DGL1=<log2 n1> -DGL2=<log2 n2>.
+#include "row_kernels.hpp"
+#include "grids.hpp"
+
+#ifndef GL1
+#error "GL1 / GL2 must be defined"
+#endif
+
+namespace tmk {
+
+#define TM_CAT2(a, b, c) a##_##b##_##c
+#define TM_CAT(a, b, c) TM_CAT2(a, b, c)
+
+using PLg = Plan<GL1, GL2>;
+
+template <typename IT>
+static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
+  using LC = Launch<PLg>;
+  dim3 grid((a.P + LC::RPW - 1) / LC::RPW), block(LC::WG);
+  if (a.P <= 0) return 0;
+  switch (mode) {
+    case M_FWD_FIELD: row_kernel<PLg, M_FWD_FIELD, IT><<<grid, block, 0, s>>>(a); break;
+    case M_FWD_INT: row_kernel<PLg, M_FWD_INT, IT><<<grid, block, 0, s>>>(a); break;
+    case M_ADJ: row_kernel<PLg, M_ADJ, IT><<<grid, block, 0, s>>>(a); break;
+    case M_ER: row_kernel<PLg, M_ER, IT><<<grid, block, 0, s>>>(a); break;
+    case M_GRAD: row_kernel<PLg, M_GRAD, IT><<<grid, block, 0, s>>>(a); break;
+    case M_SPEC: row_kernel<PLg, M_SPEC, IT><<<grid, block, 0, s>>>(a); break;
+    case M_LS: row_kernel<PLg, M_LS, IT><<<grid, block, 0, s>>>(a); break;
+    case M_BACKPROP: row_kernel<PLg, M_BACKPROP, IT><<<grid, block, 0, s>>>(a); break;
+    case M_RES64: {
+      size_t lds = (size_t)LC::RPW * PLg::LDS_ROW * sizeof(cx<double>) + (LC::WG / 64 + 1) * sizeof(double);
+      auto fn = res64_kernel<PLg, IT>;
+      hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return (int)e;
+      fn<<<grid, block, lds, s>>>(a);
+      break;
+    }
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int TM_CAT(row_launch, GL1, GL2)(int mode, int ibf16, const RowArgs& a, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  return ibf16 ? launch_t<uint16_t>(mode, a, s) : launch_t<float>(mode, a, s);
+}
+
+void TM_CAT(row_shape, GL1, GL2)(int* wg, int* rpw) {
+  *wg = Launch<PLg>::WG;
+  *rpw = Launch<PLg>::RPW;
+}
+
+}  // namespace tmk

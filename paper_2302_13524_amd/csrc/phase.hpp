@@ -1,0 +1,52 @@
+// Phase-offset correction from defocus images (Sec. 2.3), FP64 device code.
+#pragma once
+#include <stdint.h>
+
+namespace tmk {
+
+struct PhaseDims {
+  int P, N, Nd, nf1, nf2;
+};
+
+struct PhaseOptics {
+  double lambda, ps, NA, z;
+};
+
+// Device workspace for one problem (all device pointers).
+struct PhaseWork {
+  double* c;      // [Nd][P] complex (2 doubles)  c_n = TM_est e^{j theta_n}
+  double* h;      // [nf1][nf2] complex kernel
+  double* A;      // [Nd][nf1][nf2] complex field-grid scratch
+  double* B;      // [Nd][2nf1][2nf2] complex image-grid scratch
+  double* gpart;  // [Nd] per-image objective
+  double* w;      // [P] gradient
+  double* gval;   // [1] objective
+};
+
+size_t phase_work_bytes(const PhaseDims& d);
+void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w);
+
+// c = theta * tm_est^T and the kernel table h. Returns hipError_t.
+int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
+                PhaseWork& w, void* stream);
+// g(phi) into w.gval[0] and dg/dphi into grad[P].
+int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const double* phi,
+               double* grad, PhaseWork& w, const double* tw64, void* stream);
+
+// L-BFGS helpers over phi (single-workgroup kernels).
+struct PhaseLb {
+  double* phi;    // [P]
+  double* g;      // [P] gradient at phi
+  double* gt;     // [P] gradient at trial
+  double* phit;   // [P] trial point
+  double* d;      // [P]
+  double* S;      // [m][P]
+  double* Y;      // [m][P]
+  double* sc;     // [8 + 2m]: head, count, slope, dnorm, ..., sy[m], yy[m]
+};
+int phase_lb_init(PhaseLb& L, int P, int m, void* stream);
+int phase_lb_direction(PhaseLb& L, int P, int m, void* stream);
+int phase_lb_trial(PhaseLb& L, int P, double alpha, void* stream);
+int phase_lb_accept(PhaseLb& L, int P, int m, double alpha, void* stream);
+
+}  // namespace tmk

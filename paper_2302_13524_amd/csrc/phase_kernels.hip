@@ -1,0 +1,441 @@
+// Phase-offset correction from defocus intensities (Sec. 2.3), FP64.
+//
+// Forward model per defocus input n (Eq. forwarddefocusImage):
+//   field F_n = scatter(c_n * u) on the nf1 x nf2 grid, u = e^{j phi},
+//   S = K1 F_n (unitary 2-D DFT), S *= h (Eq. angularspectrum with pupil),
+//   zero-pad S to (2nf1) x (2nf2) keeping signed frequencies, a_n = K2^H S.
+// Objective g = sum_n || I_n - |a_n|^2 ||^2 (Eq. optphase) and gradient
+// dg/dphi = -4 Im(conj(u) w), w = sum_n A_n^H (a_n r_n) (Eq. phasederive).
+// The 2-D transforms are batched 1-D FP64 line FFTs along each axis.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "phase.hpp"
+
+namespace tmk {
+
+namespace {
+
+struct z2 {
+  double x, y;
+};
+__device__ __forceinline__ z2 zmul(z2 a, z2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ z2 zmulc(z2 a, z2 b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// ---- GEMM c[n][p] = sum_k theta[n][k] * tm[p][k] (FP32 inputs, FP64 accumulation)
+constexpr int GT_N = 8, GT_P = 32, GT_K = 64;
+__global__ void __launch_bounds__(256) k_cgemm(const float2* __restrict__ theta, const float2* __restrict__ tm,
+                                                double* __restrict__ c, int Nd, int P, int N) {
+  __shared__ float2 sa[GT_N][GT_K];
+  __shared__ float2 sb[GT_P][GT_K + 1];
+  int n0 = blockIdx.y * GT_N, p0 = blockIdx.x * GT_P;
+  int tid = threadIdx.x;
+  int tn = tid / GT_P, tp = tid % GT_P;  // 8 x 32 outputs, one per thread
+  double ar = 0, ai = 0;
+  for (int k0 = 0; k0 < N; k0 += GT_K) {
+    for (int i = tid; i < GT_N * GT_K; i += 256) {
+      int r = i / GT_K, k = i % GT_K;
+      int n = n0 + r, kk = k0 + k;
+      sa[r][k] = (n < Nd && kk < N) ? theta[(size_t)n * N + kk] : make_float2(0.f, 0.f);
+    }
+    for (int i = tid; i < GT_P * GT_K; i += 256) {
+      int r = i / GT_K, k = i % GT_K;
+      int p = p0 + r, kk = k0 + k;
+      sb[r][k] = (p < P && kk < N) ? tm[(size_t)p * N + kk] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < GT_K; ++k) {
+      float2 a = sa[tn][k], b = sb[tp][k];
+      ar += (double)a.x * b.x - (double)a.y * b.y;
+      ai += (double)a.x * b.y + (double)a.y * b.x;
+    }
+    __syncthreads();
+  }
+  int n = n0 + tn, p = p0 + tp;
+  if (n < Nd && p < P) {
+    c[((size_t)n * P + p) * 2] = ar;
+    c[((size_t)n * P + p) * 2 + 1] = ai;
+  }
+}
+
+__device__ __forceinline__ double freq(int k, int n, double ps) {
+  int s = (k < (n + 1) / 2) ? k : k - n;
+  return (double)s / ((double)n * ps);
+}
+
+__global__ void k_make_h(double* h, int nf1, int nf2, double lam, double ps, double NA, double z) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nf1 * nf2) return;
+  int a = i / nf2, b = i % nf2;
+  double u = freq(a, nf1, ps), v = freq(b, nf2, ps);
+  double rho2 = (lam * u) * (lam * u) + (lam * v) * (lam * v);
+  z2 r{0.0, 0.0};
+  if (sqrt(rho2) <= NA) {
+    double ph = 2.0 * M_PI / lam * sqrt(1.0 - rho2) * z;
+    r = {cos(ph), sin(ph)};
+  }
+  h[2 * i] = r.x;
+  h[2 * i + 1] = r.y;
+}
+
+__global__ void k_zero(double* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  size_t st = (size_t)gridDim.x * 256;
+  for (; i < n; i += st) p[i] = 0.0;
+}
+
+// A[n][pix[p]] = c[n][p] * e^{j phi_p}
+__global__ void k_scatter(double* A, const double* c, const double* phi, const int32_t* pix, int Nd, int P,
+                          int G) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= Nd * P) return;
+  int n = i / P, p = i % P;
+  z2 cv{c[2 * (size_t)i], c[2 * (size_t)i + 1]};
+  z2 u{cos(phi[p]), sin(phi[p])};
+  z2 v = zmul(cv, u);
+  size_t o = ((size_t)n * G + pix[p]) * 2;
+  A[o] = v.x;
+  A[o + 1] = v.y;
+}
+
+// Batched in-LDS FFT of lines of length L = 2^LL (radix-2 Stockham).
+// Line li: outer = li / inner_n, inner = li % inner_n; element j at
+// (outer * os + inner * is + j * es) complex entries. sign -1: forward DFT.
+__global__ void __launch_bounds__(256) k_lines(double* buf, int nlines, int inner_n, long os, long is, long es,
+                                               int LL, int sign, double scale, const double* tw64) {
+  extern __shared__ double sm[];
+  const int L = 1 << LL;
+  const int half = L >> 1;
+  const int lpw = 256 / half > 0 ? 256 / half : 1;
+  const int tl = threadIdx.x / half;   // line within workgroup
+  const int tj = threadIdx.x % half;   // butterfly within line
+  int li = blockIdx.x * lpw + tl;
+  bool act = (tl < lpw) && (li < nlines);
+  z2* a = (z2*)sm + (size_t)tl * 2 * L;
+  z2* b = a + L;
+  long base = 0;
+  if (act) {
+    int outer = li / inner_n, inner = li % inner_n;
+    base = outer * os + inner * is;
+    for (int j = tj; j < L; j += half) a[j] = ((z2*)buf)[base + j * es];
+  }
+  __syncthreads();
+  const z2* tw = (const z2*)tw64 + (L - 1);
+  // Stockham radix-2: stage with sub-length p (1, 2, 4, ...)
+  for (int p = 1; p < L; p <<= 1) {
+    if (act) {
+      int k = tj;                 // butterfly 0..L/2-1
+      int i = k % p;
+      z2 x0 = a[k], x1 = a[k + half];
+      z2 w = tw[(i * (L / (2 * p))) & (L - 1)];
+      if (sign > 0) w.y = -w.y;
+      x1 = zmul(x1, w);
+      int o = (k - i) * 2 + i;
+      b[o] = {x0.x + x1.x, x0.y + x1.y};
+      b[o + p] = {x0.x - x1.x, x0.y - x1.y};
+    }
+    __syncthreads();
+    z2* t = a;
+    a = b;
+    b = t;
+  }
+  if (act) {
+    for (int j = tj; j < L; j += half) {
+      z2 v = a[j];
+      ((z2*)buf)[base + j * es] = {v.x * scale, v.y * scale};
+    }
+  }
+}
+
+__device__ __forceinline__ int padpos(int k, int n) {
+  int s = (k < (n + 1) / 2) ? k : k - n;
+  return (s + 2 * n) % (2 * n);
+}
+
+// B[n][pad(a)][pad(b)] = h[a][b] * A[n][a][b]   (B pre-zeroed)
+__global__ void k_pad(double* B, const double* A, const double* h, int Nd, int nf1, int nf2) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  size_t G = (size_t)nf1 * nf2;
+  if (i >= Nd * G) return;
+  int n = (int)(i / G);
+  int r = (int)(i % G);
+  int a = r / nf2, b = r % nf2;
+  z2 v{A[2 * i], A[2 * i + 1]};
+  z2 hv{h[2 * r], h[2 * r + 1]};
+  z2 o = zmul(v, hv);
+  size_t q = ((size_t)n * 4 * G + (size_t)padpos(a, nf1) * 2 * nf2 + padpos(b, nf2)) * 2;
+  B[q] = o.x;
+  B[q + 1] = o.y;
+}
+
+// A[n][a][b] = conj(h[a][b]) * B[n][pad(a)][pad(b)]
+__global__ void k_crop(double* A, const double* B, const double* h, int Nd, int nf1, int nf2) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  size_t G = (size_t)nf1 * nf2;
+  if (i >= Nd * G) return;
+  int n = (int)(i / G);
+  int r = (int)(i % G);
+  int a = r / nf2, b = r % nf2;
+  size_t q = ((size_t)n * 4 * G + (size_t)padpos(a, nf1) * 2 * nf2 + padpos(b, nf2)) * 2;
+  z2 v{B[q], B[q + 1]};
+  z2 hv{h[2 * r], h[2 * r + 1]};
+  z2 o = zmulc(v, hv);
+  A[2 * i] = o.x;
+  A[2 * i + 1] = o.y;
+}
+
+// r = I - |a|^2, a <- a r (in place), per-image sum of r^2 into gpart[n]
+__global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, double* gpart, int npix) {
+  __shared__ double red[4];
+  int n = blockIdx.x;
+  double s = 0;
+  for (int i = threadIdx.x; i < npix; i += 256) {
+    size_t q = (size_t)n * npix + i;
+    z2 v{B[2 * q], B[2 * q + 1]};
+    double r = (double)Id[q] - (v.x * v.x + v.y * v.y);
+    s += r * r;
+    B[2 * q] = v.x * r;
+    B[2 * q + 1] = v.y * r;
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) gpart[n] = red[0] + red[1] + red[2] + red[3];
+}
+
+// grad[p] = -4 Im(conj(u_p) sum_n conj(c[n][p]) A[n][pix[p]]); gval = sum_n gpart[n]
+__global__ void k_gather(double* grad, double* gval, const double* A, const double* c, const double* phi,
+                         const int32_t* pix, const double* gpart, int Nd, int P, int G) {
+  int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < P) {
+    z2 w{0.0, 0.0};
+    for (int n = 0; n < Nd; ++n) {
+      size_t o = ((size_t)n * G + pix[p]) * 2;
+      z2 v{A[o], A[o + 1]};
+      z2 cv{c[((size_t)n * P + p) * 2], c[((size_t)n * P + p) * 2 + 1]};
+      z2 t = zmulc(v, cv);
+      w.x += t.x;
+      w.y += t.y;
+    }
+    z2 u{cos(phi[p]), sin(phi[p])};
+    z2 q = zmulc(w, u);  // w conj(u)
+    grad[p] = -4.0 * q.y;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0;
+    for (int n = 0; n < Nd; ++n) s += gpart[n];
+    gval[0] = s;
+  }
+}
+
+int lines(double* buf, int nlines, int inner_n, long os, long is, long es, int L, int sign, double scale,
+          const double* tw64, hipStream_t s) {
+  int LL = ilog2(L);
+  int half = L / 2 > 0 ? L / 2 : 1;
+  int lpw = 256 / half > 0 ? 256 / half : 1;
+  int blocks = (nlines + lpw - 1) / lpw;
+  size_t lds = (size_t)lpw * 2 * L * 16;
+  if (L == 1) {
+    return 0;
+  }
+  k_lines<<<blocks, 256, lds, s>>>(buf, nlines, inner_n, os, is, es, LL, sign, scale, tw64);
+  return (int)hipGetLastError();
+}
+
+// 2-D transform of Nd grids g1 x g2 in buf; sign -1 forward, +1 inverse, unitary scaling.
+int fft2(double* buf, int Nd, int g1, int g2, int sign, const double* tw64, hipStream_t s) {
+  int e;
+  // along axis 2 (contiguous rows): lines = Nd*g1, element stride 1
+  if ((e = lines(buf, Nd * g1, 1, g2, 0, 1, g2, sign, 1.0 / sqrt((double)g2), tw64, s))) return e;
+  // along axis 1: lines = Nd*g2, outer n stride g1*g2, inner column stride 1, element stride g2
+  if ((e = lines(buf, Nd * g2, g2, (long)g1 * g2, 1, g2, g1, sign, 1.0 / sqrt((double)g1), tw64, s))) return e;
+  return 0;
+}
+
+}  // namespace
+
+size_t phase_work_bytes(const PhaseDims& d) {
+  size_t G = (size_t)d.nf1 * d.nf2;
+  size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 4 * G * 2 + d.Nd + d.P + 8;
+  return dbl * sizeof(double) + 8 * 256;
+}
+
+void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
+  size_t G = (size_t)d.nf1 * d.nf2;
+  char* p = (char*)base;
+  auto take = [&](size_t ndbl) {
+    double* r = (double*)p;
+    p += ((ndbl * sizeof(double) + 255) / 256) * 256;
+    return r;
+  };
+  w->c = take((size_t)d.Nd * d.P * 2);
+  w->h = take(G * 2);
+  w->A = take((size_t)d.Nd * G * 2);
+  w->B = take((size_t)d.Nd * 4 * G * 2);
+  w->gpart = take(d.Nd);
+  w->w = take(d.P);
+  w->gval = take(8);
+}
+
+int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta, PhaseWork& w,
+                void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  dim3 g((d.P + GT_P - 1) / GT_P, (d.Nd + GT_N - 1) / GT_N);
+  k_cgemm<<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm_est, w.c, d.Nd, d.P, d.N);
+  int G = d.nf1 * d.nf2;
+  k_make_h<<<(G + 255) / 256, 256, 0, s>>>(w.h, d.nf1, d.nf2, o.lambda, o.ps, o.NA, o.z);
+  return (int)hipGetLastError();
+}
+
+int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const double* phi, double* grad,
+               PhaseWork& w, const double* tw64, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int e;
+  const int G = d.nf1 * d.nf2;
+  const size_t nA = (size_t)d.Nd * G * 2, nB = (size_t)d.Nd * 4 * G * 2;
+  auto blocks = [](size_t n) { return (unsigned)((n + 255) / 256 > 65535 ? 65535 : (n + 255) / 256); };
+  k_zero<<<blocks(nA), 256, 0, s>>>(w.A, nA);
+  k_zero<<<blocks(nB), 256, 0, s>>>(w.B, nB);
+  k_scatter<<<(d.Nd * d.P + 255) / 256, 256, 0, s>>>(w.A, w.c, phi, pix, d.Nd, d.P, G);
+  if ((e = (int)hipGetLastError())) return e;
+  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s))) return e;
+  k_pad<<<blocks((size_t)d.Nd * G), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
+  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s))) return e;
+  k_resid<<<d.Nd, 256, 0, s>>>(w.B, Id, w.gpart, 4 * G);
+  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, -1, tw64, s))) return e;
+  k_crop<<<blocks((size_t)d.Nd * G), 256, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2);
+  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, +1, tw64, s))) return e;
+  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.A, w.c, phi, pix, w.gpart, d.Nd, d.P, G);
+  return (int)hipGetLastError();
+}
+
+// ------------------------------------------------------------ L-BFGS over phi
+namespace {
+constexpr int PWG = 1024;
+
+__device__ double bsum(double v, double* red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < PWG / 64; ++i) s += red[i];
+  return s;
+}
+
+__device__ double dotv(const double* a, const double* b, int P, double* red) {
+  double s = 0;
+  for (int i = threadIdx.x; i < P; i += PWG) s += a[i] * b[i];
+  return bsum(s, red);
+}
+
+// sc: [0] head, [1] count, [2] slope of d, [3] unused, [8..8+m) sy, [8+m..8+2m) yy
+__global__ void __launch_bounds__(PWG) k_pdir(PhaseLb L, int P, int m) {
+  __shared__ double red[PWG / 64];
+  double* sc = L.sc;
+  int head = (int)sc[0], count = (int)sc[1];
+  const double* sy = sc + 8;
+  const double* yy = sc + 8 + m;
+  for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = L.g[i];
+  __syncthreads();
+  double al[16];
+  for (int j = 0; j < count; ++j) {
+    int idx = (head - 1 - j + 2 * m) % m;
+    double a = dotv(L.S + (size_t)idx * P, L.d, P, red) / sy[idx];
+    al[j] = a;
+    for (int i = threadIdx.x; i < P; i += PWG) L.d[i] -= a * L.Y[(size_t)idx * P + i];
+    __syncthreads();
+  }
+  double gam;
+  if (count > 0) {
+    int nw = (head - 1 + m) % m;
+    gam = sy[nw] / yy[nw];
+  } else {
+    double gn = sqrt(dotv(L.g, L.g, P, red));
+    gam = gn > 0 ? 1.0 / gn : 0.0;
+  }
+  for (int i = threadIdx.x; i < P; i += PWG) L.d[i] *= gam;
+  __syncthreads();
+  for (int j = count - 1; j >= 0; --j) {
+    int idx = (head - 1 - j + 2 * m) % m;
+    double b = dotv(L.Y + (size_t)idx * P, L.d, P, red) / sy[idx];
+    double cf = al[j] - b;
+    for (int i = threadIdx.x; i < P; i += PWG) L.d[i] += cf * L.S[(size_t)idx * P + i];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = -L.d[i];
+  __syncthreads();
+  double slope = dotv(L.g, L.d, P, red);
+  if (!(slope < 0.0)) {
+    double gn = sqrt(dotv(L.g, L.g, P, red));
+    double inv = gn > 0 ? 1.0 / gn : 0.0;
+    for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = -L.g[i] * inv;
+    __syncthreads();
+    slope = dotv(L.g, L.d, P, red);
+    if (threadIdx.x == 0) sc[1] = 0;
+  }
+  if (threadIdx.x == 0) sc[2] = slope;
+}
+
+__global__ void k_ptrial(PhaseLb L, int P, double alpha) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < P) L.phit[i] = L.phi[i] + alpha * L.d[i];
+}
+
+__global__ void __launch_bounds__(PWG) k_paccept(PhaseLb L, int P, int m, double alpha) {
+  __shared__ double red[PWG / 64];
+  double* sc = L.sc;
+  int head = (int)sc[0], count = (int)sc[1];
+  double* Sh = L.S + (size_t)head * P;
+  double* Yh = L.Y + (size_t)head * P;
+  for (int i = threadIdx.x; i < P; i += PWG) {
+    Sh[i] = alpha * L.d[i];
+    Yh[i] = L.gt[i] - L.g[i];
+  }
+  __syncthreads();
+  double sy = dotv(Sh, Yh, P, red);
+  double yy = dotv(Yh, Yh, P, red);
+  for (int i = threadIdx.x; i < P; i += PWG) {
+    L.phi[i] = L.phi[i] + Sh[i];
+    L.g[i] = L.gt[i];
+  }
+  if (threadIdx.x == 0 && sy > 0.0) {
+    sc[8 + head] = sy;
+    sc[8 + m + head] = yy;
+    sc[0] = (head + 1) % m;
+    sc[1] = count < m ? count + 1 : m;
+  }
+}
+
+__global__ void k_pinit(double* sc, int n) {
+  int i = threadIdx.x;
+  if (i < n) sc[i] = 0.0;
+}
+}  // namespace
+
+int phase_lb_init(PhaseLb& L, int P, int m, void* stream) {
+  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, 8 + 2 * m);
+  return (int)hipGetLastError();
+}
+int phase_lb_direction(PhaseLb& L, int P, int m, void* stream) {
+  k_pdir<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m);
+  return (int)hipGetLastError();
+}
+int phase_lb_trial(PhaseLb& L, int P, double alpha, void* stream) {
+  k_ptrial<<<(P + 255) / 256, 256, 0, (hipStream_t)stream>>>(L, P, alpha);
+  return (int)hipGetLastError();
+}
+int phase_lb_accept(PhaseLb& L, int P, int m, double alpha, void* stream) {
+  k_paccept<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, alpha);
+  return (int)hipGetLastError();
+}
+
+}  // namespace tmk

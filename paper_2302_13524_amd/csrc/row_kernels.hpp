@@ -1,0 +1,414 @@
+// Fused per-row kernels: mask multiply + 2-D FFT + pointwise measurement
+// step + inverse 2-D FFT + conj-mask accumulation, one row per thread group,
+// rows independent (the per-pixel decomposition of Sec. 2.2).
+#pragma once
+#include "fft_core.hpp"
+
+namespace tmk {
+
+enum Mode : int {
+  M_FWD_FIELD = 0,   // y = A t                                     -> yout c32 [P][K][N]
+  M_FWD_INT = 1,     // I = |A t|^2                                 -> yout float/bf16 [P][K][N]
+  M_ADJ = 2,         // x = A^H y                                   -> tout
+  M_ER = 3,          // t <- A^H(sqrt(I) y/|y|)/(K N)               -> tout, sums {amp_res, f}
+  M_GRAD = 4,        // g = -4 A^H(y (I - |y|^2))                   -> tout, sums {f}
+  M_SPEC = 5,        // heavy-ball power step on A^H diag(w) A      -> tout (v), tout2 (v_prev)
+  M_LS = 6,          // quartic line-search sums for y = A t, z = A d -> sums[6]
+  M_RES64 = 7,       // FP64 residual: sums64 {sum r^2, sum I^2}
+  M_BACKPROP = 8     // x = A^H sqrt(I) / (K N)                     -> tout
+};
+
+constexpr int NSUM = 6;
+
+struct RowArgs {
+  int P, K;
+  const cx<float>* masks;  // [K][N]
+  const cx<float>* tin;    // [P][N]
+  const cx<float>* din;    // [P][N]  (M_LS: direction d; M_SPEC: previous v)
+  const void* I;           // [P][K][N] float or bf16
+  const cx<float>* yin;    // [P][K][N] (M_ADJ)
+  cx<float>* tout;         // [P][N]
+  cx<float>* tout2;        // [P][N]  (M_SPEC: new previous v)
+  void* yout;              // [P][K][N] (M_FWD_*)
+  float* sums;             // [P][NSUM]
+  double* sums64;          // [P][2] (M_RES64)
+  const float* rowmean;    // [P] mean of I per row (M_SPEC)
+  float tau;               // M_SPEC truncation
+  float momentum;          // M_SPEC heavy-ball factor c
+  int out_bf16;            // M_FWD_INT output type
+  const cx<float>* tw32;   // twiddle tables, table of length L at offset L-1
+  const cx<double>* tw64;
+};
+
+__device__ __forceinline__ float bf16_to_f(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename IT>
+__device__ __forceinline__ float load_I(const void* I, size_t idx) {
+  if constexpr (sizeof(IT) == 2) return bf16_to_f(((const uint16_t*)I)[idx]);
+  else return ((const float*)I)[idx];
+}
+
+// Compensated (TwoSum) accumulation in FP32.
+struct KSum {
+  float s, c;
+  __device__ __forceinline__ void add(float v) {
+    float t = s + v;
+    float bp = t - s;
+    float e = (s - (t - bp)) + (v - bp);
+    s = t;
+    c += e;
+  }
+  __device__ __forceinline__ void merge(float s2, float c2) {
+    float t = s + s2;
+    float bp = t - s;
+    float e = (s - (t - bp)) + (s2 - bp);
+    s = t;
+    c += c2 + e;
+  }
+};
+
+// Reduce NS compensated sums over the T threads of a row group. `red` is LDS
+// scratch of at least (WG/64) * NS * 2 floats. Result valid in every thread.
+template <int T, int WG, int NS>
+__device__ __forceinline__ void row_reduce(KSum* acc, float* red, int tid, float* out) {
+  if constexpr (T <= 64) {
+#pragma unroll
+    for (int off = T / 2; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        float s2 = __shfl_xor(acc[i].s, off, 64);
+        float c2 = __shfl_xor(acc[i].c, off, 64);
+        acc[i].merge(s2, c2);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) out[i] = acc[i].s + acc[i].c;
+  } else {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        float s2 = __shfl_xor(acc[i].s, off, 64);
+        float c2 = __shfl_xor(acc[i].c, off, 64);
+        acc[i].merge(s2, c2);
+      }
+    }
+    constexpr int WPR = T / 64;  // waves per row
+    int wave = tid >> 6;
+    __syncthreads();
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        red[(wave * NS + i) * 2 + 0] = acc[i].s;
+        red[(wave * NS + i) * 2 + 1] = acc[i].c;
+      }
+    }
+    __syncthreads();
+    int w0 = (wave / WPR) * WPR;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      KSum a{red[(w0 * NS + i) * 2], red[(w0 * NS + i) * 2 + 1]};
+      for (int w = 1; w < WPR; ++w) a.merge(red[((w0 + w) * NS + i) * 2], red[((w0 + w) * NS + i) * 2 + 1]);
+      out[i] = a.s + a.c;
+    }
+  }
+}
+
+template <int T, int WG>
+__device__ __forceinline__ double row_reduce64(double v, double* red, int tid) {
+  if constexpr (T <= 64) {
+#pragma unroll
+    for (int off = T / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+  } else {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    constexpr int WPR = T / 64;
+    int wave = tid >> 6;
+    __syncthreads();
+    if ((tid & 63) == 0) red[wave] = v;
+    __syncthreads();
+    int w0 = (wave / WPR) * WPR;
+    double s = 0;
+    for (int w = 0; w < WPR; ++w) s += red[w0 + w];
+    return s;
+  }
+}
+
+template <class PL>
+struct Launch {
+  static constexpr int WG = (PL::T >= 256) ? PL::T : 256;
+  static constexpr int RPW = WG / PL::T;  // rows per workgroup
+};
+
+// ---------------------------------------------------------------- FP32 kernel
+template <class PL, int MODE, typename IT>
+__global__ void __launch_bounds__(Launch<PL>::WG)
+row_kernel(RowArgs a) {
+  using T = float;
+  using C = cx<T>;
+  constexpr int E = PL::E, N = PL::N, WG = Launch<PL>::WG, RPW = Launch<PL>::RPW;
+  __shared__ C lds_all[RPW * PL::LDS_ROW];
+  __shared__ float red[(WG / 64 + 1) * NSUM * 2];
+
+  const int tid = threadIdx.x;
+  const int rloc = tid / PL::T;
+  const int ltid = tid % PL::T;
+  const int row = blockIdx.x * RPW + rloc;
+  const bool valid = row < a.P;
+  const size_t prow = valid ? (size_t)row : 0;
+  C* lds = lds_all + rloc * PL::LDS_ROW;
+  Tw<T> tw{a.tw32 + (PL::N1 - 1), a.tw32 + (PL::N2 - 1)};
+
+  using L0 = Layout0<PL>;
+  using LL = LayoutL<PL>;
+  int b0[L0::NB];  // pass-0 butterfly bases (natural element index)
+#pragma unroll
+  for (int j = 0; j < L0::NB; ++j) b0[j] = L0::base(ltid, j);
+  int kb[LL::NB];  // last-pass butterfly spectrum bases
+#pragma unroll
+  for (int j = 0; j < LL::NB; ++j) kb[j] = LL::kbase(ltid, j);
+#define E0(i) (b0[(i) / L0::R] + ((i) % L0::R) * L0::HS)
+#define KL(i) (kb[(i) / LL::R] + ((i) % LL::R) * LL::KS)
+
+  C t[E], g[E], x[E];
+  C dvec[E];
+  if constexpr (MODE != M_ADJ && MODE != M_BACKPROP) {
+    const C* src = a.tin + prow * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) t[i] = src[E0(i)];
+  }
+  if constexpr (MODE == M_LS) {
+    const C* src = a.din + prow * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) dvec[i] = src[E0(i)];
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) g[i] = C{0.f, 0.f};
+
+  KSum acc[NSUM];
+#pragma unroll
+  for (int i = 0; i < NSUM; ++i) acc[i] = KSum{0.f, 0.f};
+
+  float inv_mean = 0.f;
+  if constexpr (MODE == M_SPEC) {
+    float m = valid ? a.rowmean[prow] : 1.f;
+    inv_mean = (m > 0.f) ? 1.f / m : 1.f;
+  }
+
+  for (int m = 0; m < a.K; ++m) {
+    const C* mk = a.masks + (size_t)m * N;
+    const size_t mbase = (prow * a.K + m) * (size_t)N;
+    if constexpr (MODE == M_ADJ || MODE == M_BACKPROP) {
+      // spectrum arrives in natural order; place it at the digit-reversed slots
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        int k = KL(i);
+        if constexpr (MODE == M_ADJ) x[i] = a.yin[mbase + k];
+        else x[i] = C{sqrtf(fmaxf(load_I<IT>(a.I, mbase + k), 0.f)), 0.f};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) x[i] = cmul(t[i], mk[E0(i)]);
+      fft_forward<PL, T>(x, lds, ltid, tw);
+    }
+
+    if constexpr (MODE == M_FWD_FIELD || MODE == M_FWD_INT) {
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          int k = KL(i);
+          if constexpr (MODE == M_FWD_FIELD) ((C*)a.yout)[mbase + k] = x[i];
+          else {
+            float v = norm2(x[i]);
+            if (a.out_bf16) ((uint16_t*)a.yout)[mbase + k] = f_to_bf16(v);
+            else ((float*)a.yout)[mbase + k] = v;
+          }
+        }
+      }
+      continue;
+    } else if constexpr (MODE == M_LS) {
+      C y[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) y[i] = x[i];
+#pragma unroll
+      for (int i = 0; i < E; ++i) x[i] = cmul(dvec[i], mk[E0(i)]);
+      fft_forward<PL, T>(x, lds, ltid, tw);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        int k = KL(i);
+        float iv = load_I<IT>(a.I, mbase + k);
+        float r = iv - norm2(y[i]);
+        float b = y[i].x * x[i].x + y[i].y * x[i].y;
+        float c = norm2(x[i]);
+        acc[0].add(r * r);
+        acc[1].add(r * b);
+        acc[2].add(b * b);
+        acc[3].add(r * c);
+        acc[4].add(b * c);
+        acc[5].add(c * c);
+      }
+      continue;
+    } else {
+      if constexpr (MODE == M_ER || MODE == M_GRAD || MODE == M_SPEC) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          int k = KL(i);
+          float iv = load_I<IT>(a.I, mbase + k);
+          float n = norm2(x[i]);
+          if constexpr (MODE == M_ER) {
+            float amp = sqrtf(fmaxf(iv, 0.f));
+            float mag = sqrtf(n);
+            float dr = amp - mag, ri = iv - n;
+            acc[0].add(dr * dr);
+            acc[1].add(ri * ri);
+            x[i] = (n > 0.f) ? scl(x[i], amp / mag) : C{amp, 0.f};
+          } else if constexpr (MODE == M_GRAD) {
+            float r = iv - n;
+            acc[0].add(r * r);
+            x[i] = scl(x[i], r);
+          } else {
+            float w = fminf(iv * inv_mean, a.tau);
+            x[i] = scl(x[i], w);
+          }
+        }
+      }
+      fft_inverse<PL, T>(x, lds, ltid, tw);
+#pragma unroll
+      for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], mk[E0(i)]);
+    }
+  }
+
+  if constexpr (MODE == M_FWD_FIELD || MODE == M_FWD_INT) {
+    return;
+  } else if constexpr (MODE == M_LS) {
+    float out[NSUM];
+    row_reduce<PL::T, WG, NSUM>(acc, red, tid, out);
+    if (valid && ltid == 0) {
+#pragma unroll
+      for (int i = 0; i < NSUM; ++i) a.sums[prow * NSUM + i] = out[i];
+    }
+  } else if constexpr (MODE == M_SPEC) {
+    // lambda = Re <v, M v> (v has unit norm), x = M v - beta v_prev, normalise.
+    C vp[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) vp[i] = a.din[prow * N + E0(i)];
+    KSum l1[1] = {KSum{0.f, 0.f}};
+#pragma unroll
+    for (int i = 0; i < E; ++i) l1[0].add(t[i].x * g[i].x + t[i].y * g[i].y);
+    float lam;
+    row_reduce<PL::T, WG, 1>(l1, red, tid, &lam);
+    float cl = a.momentum * lam;
+    float beta = 0.25f * cl * cl;
+    KSum n1[1] = {KSum{0.f, 0.f}};
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      g[i] = g[i] - scl(vp[i], beta);
+      n1[0].add(norm2(g[i]));
+    }
+    float nn;
+    row_reduce<PL::T, WG, 1>(n1, red, tid, &nn);
+    float inv = (nn > 0.f) ? rsqrtf(nn) : 1.f;
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        a.tout[prow * N + E0(i)] = scl(g[i], inv);
+        a.tout2[prow * N + E0(i)] = scl(t[i], inv);
+      }
+      if (ltid == 0 && a.sums) a.sums[prow * NSUM + 0] = lam;
+    }
+  } else {
+    float scale = 1.f;
+    if constexpr (MODE == M_ER || MODE == M_BACKPROP) scale = 1.f / (float)(a.K * N);
+    if constexpr (MODE == M_GRAD) scale = -4.f;
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) a.tout[prow * N + E0(i)] = scl(g[i], scale);
+    }
+    if constexpr (MODE == M_ER || MODE == M_GRAD) {
+      float out[NSUM];
+      row_reduce<PL::T, WG, (MODE == M_ER) ? 2 : 1>(acc, red, tid, out);
+      if (valid && ltid == 0 && a.sums) {
+        if constexpr (MODE == M_ER) {
+          a.sums[prow * NSUM + 0] = out[0];
+          a.sums[prow * NSUM + 1] = out[1];
+        } else {
+          a.sums[prow * NSUM + 0] = out[0];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP64 residual
+template <class PL, typename IT>
+__global__ void __launch_bounds__(Launch<PL>::WG)
+res64_kernel(RowArgs a) {
+  using T = double;
+  using C = cx<T>;
+  constexpr int E = PL::E, N = PL::N, WG = Launch<PL>::WG, RPW = Launch<PL>::RPW;
+  extern __shared__ char dyn_lds[];
+  C* lds_all = (C*)dyn_lds;
+  double* red = (double*)(lds_all + RPW * PL::LDS_ROW);
+
+  const int tid = threadIdx.x;
+  const int rloc = tid / PL::T;
+  const int ltid = tid % PL::T;
+  const int row = blockIdx.x * RPW + rloc;
+  const bool valid = row < a.P;
+  const size_t prow = valid ? (size_t)row : 0;
+  C* lds = lds_all + rloc * PL::LDS_ROW;
+  Tw<T> tw{a.tw64 + (PL::N1 - 1), a.tw64 + (PL::N2 - 1)};
+
+  using L0 = Layout0<PL>;
+  using LL = LayoutL<PL>;
+  int b0[L0::NB];
+#pragma unroll
+  for (int j = 0; j < L0::NB; ++j) b0[j] = L0::base(ltid, j);
+  int kb[LL::NB];
+#pragma unroll
+  for (int j = 0; j < LL::NB; ++j) kb[j] = LL::kbase(ltid, j);
+  C t[E], x[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    cx<float> v = a.tin[prow * N + E0(i)];
+    t[i] = C{(double)v.x, (double)v.y};
+  }
+  double sr = 0.0, si = 0.0;
+  for (int m = 0; m < a.K; ++m) {
+    const cx<float>* mk = a.masks + (size_t)m * N;
+    const size_t mbase = (prow * a.K + m) * (size_t)N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      cx<float> w = mk[E0(i)];
+      x[i] = cmul(t[i], C{(double)w.x, (double)w.y});
+    }
+    fft_forward<PL, T>(x, lds, ltid, tw);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      int k = KL(i);
+      double iv = (double)load_I<IT>(a.I, mbase + k);
+      double r = iv - norm2(x[i]);
+      sr += r * r;
+      si += iv * iv;
+    }
+  }
+  sr = row_reduce64<PL::T, WG>(sr, red, tid);
+  si = row_reduce64<PL::T, WG>(si, red, tid);
+  if (valid && ltid == 0) {
+    a.sums64[prow * 2 + 0] = sr;
+    a.sums64[prow * 2 + 1] = si;
+  }
+}
+
+#undef E0
+#undef KL
+}  // namespace tmk

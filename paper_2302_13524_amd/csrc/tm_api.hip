@@ -1,0 +1,490 @@
+// C ABI of the retrieval library (declared in include/tm.h): argument
+// validation, context and workspace, twiddle tables, and the host-side
+// sequencing of the device kernels. All arithmetic of the method runs in
+// the device kernels; the host only launches them in order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tm.h"
+#include "aux.hpp"
+#include "grids.hpp"
+#include "lbfgs.hpp"
+#include "phase.hpp"
+#include "row_kernels.hpp"
+
+struct tm_ctx {
+  int device = 0;
+  std::string err;
+  tmk::cx<float>* tw32 = nullptr;
+  tmk::cx<double>* tw64 = nullptr;
+  struct Slot {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<int, Slot> ws;
+};
+
+namespace {
+
+constexpr int TW_MAX = 8192;  // longest FFT axis
+thread_local std::string g_create_err;
+
+int fail(tm_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_err = buf;
+  return code;
+}
+
+int hipfail(tm_ctx* c, int e, const char* what) {
+  return fail(c, TM_EHIP, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+#define HIPCHK(ctx, expr)                                 \
+  do {                                                    \
+    int _e = (int)(expr);                                 \
+    if (_e != 0) return hipfail(ctx, _e, #expr);          \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Workspace slot `id` of at least `bytes` bytes (grown on demand). Growing
+// synchronises the device first so that no queued kernel still uses it.
+void* ws_get(tm_ctx* c, int id, size_t bytes) {
+  auto& s = c->ws[id];
+  if (s.bytes >= bytes && s.p) return s.p;
+  if (s.p) {
+    hipDeviceSynchronize();
+    hipFree(s.p);
+    s.p = nullptr;
+    s.bytes = 0;
+  }
+  size_t want = bytes < 256 ? 256 : bytes;
+  if (hipMalloc(&s.p, want) != hipSuccess) {
+    s.p = nullptr;
+    return nullptr;
+  }
+  s.bytes = want;
+  return s.p;
+}
+
+enum WsId {
+  WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
+  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST,
+  WS_PH_BASE = 100
+};
+
+int check_dims(tm_ctx* c, const tm_dims& d, tmk::row_launcher* fn) {
+  if (d.n1 < 1 || d.n2 < 1 || !is_pow2(d.n1) || !is_pow2(d.n2))
+    return fail(c, TM_EINVAL, "n1=%d n2=%d: both must be powers of two >= 1", d.n1, d.n2);
+  if (d.K < 1 || d.K > 64) return fail(c, TM_EINVAL, "K=%d outside 1..64", d.K);
+  if (d.P < 0) return fail(c, TM_EINVAL, "P=%d < 0", d.P);
+  if ((int64_t)d.n1 * d.n2 > TW_MAX) return fail(c, TM_EUNSUPPORTED, "N=%d > %d", d.n1 * d.n2, TW_MAX);
+  *fn = tmk::find_row_launcher(ilog2(d.n1), ilog2(d.n2));
+  if (!*fn) return fail(c, TM_EUNSUPPORTED, "grid %dx%d has no compiled FFT plan", d.n1, d.n2);
+  return TM_OK;
+}
+
+tmk::RowArgs base_args(tm_ctx* c, const tm_dims& d, const tm_c32* masks) {
+  tmk::RowArgs a;
+  memset(&a, 0, sizeof a);
+  a.P = d.P;
+  a.K = d.K;
+  a.masks = (const tmk::cx<float>*)masks;
+  a.tw32 = c->tw32;
+  a.tw64 = c->tw64;
+  return a;
+}
+
+int run_row(tm_ctx* c, tmk::row_launcher fn, int mode, int ibf16, const tmk::RowArgs& a, void* s) {
+  int e = fn(mode, ibf16, a, s);
+  if (e) return hipfail(c, e, "row kernel launch");
+  return TM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tm_grid_supported(int32_t n1, int32_t n2) {
+  if (!is_pow2(n1) || !is_pow2(n2) || (int64_t)n1 * n2 > TW_MAX) return 0;
+  return tmk::find_row_launcher(ilog2(n1), ilog2(n2)) ? 1 : 0;
+}
+
+int tm_create(tm_ctx** out, int device) {
+  if (!out) return fail(nullptr, TM_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, TM_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, TM_EINVAL, "device %d of %d", device, ndev);
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, TM_EHIP, "hipSetDevice(%d) failed", device);
+  tm_ctx* c = new tm_ctx;
+  c->device = device;
+  // Twiddle tables W_L^i = exp(-2 pi j i / L) for every power of two L <= TW_MAX,
+  // the table of length L at offset L - 1; FP64 values, FP32 rounded once.
+  std::vector<tmk::cx<double>> h64(2 * TW_MAX);
+  std::vector<tmk::cx<float>> h32(2 * TW_MAX);
+  for (int L = 1; L <= TW_MAX; L <<= 1) {
+    for (int i = 0; i < L; ++i) {
+      double ang = -2.0 * M_PI * ((double)i / (double)L);
+      tmk::cx<double> w{std::cos(ang), std::sin(ang)};
+      h64[L - 1 + i] = w;
+      h32[L - 1 + i] = tmk::cx<float>{(float)w.x, (float)w.y};
+    }
+  }
+  if (hipMalloc(&c->tw32, h32.size() * sizeof(h32[0])) != hipSuccess ||
+      hipMalloc(&c->tw64, h64.size() * sizeof(h64[0])) != hipSuccess ||
+      hipMemcpy(c->tw32, h32.data(), h32.size() * sizeof(h32[0]), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->tw64, h64.data(), h64.size() * sizeof(h64[0]), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(c->tw32);
+    hipFree(c->tw64);
+    delete c;
+    return fail(nullptr, TM_EHIP, "twiddle table upload failed");
+  }
+  *out = c;
+  return TM_OK;
+}
+
+int tm_destroy(tm_ctx* c) {
+  if (!c) return TM_EINVAL;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto& kv : c->ws) hipFree(kv.second.p);
+  hipFree(c->tw32);
+  hipFree(c->tw64);
+  delete c;
+  return TM_OK;
+}
+
+const char* tm_last_error(const tm_ctx* c) {
+  if (!c) return g_create_err.c_str();
+  return c->err.c_str();
+}
+
+int tm_forward(tm_ctx* c, tm_dims d, const tm_c32* masks, const tm_c32* t, int out_kind,
+               int out_dtype, void* out, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (d.P == 0) return TM_OK;
+  if (!masks || !t || !out) return fail(c, TM_EINVAL, "null pointer argument");
+  if (out_kind != TM_FIELD && out_kind != TM_INTENSITY) return fail(c, TM_EINVAL, "out_kind %d", out_kind);
+  if (out_kind == TM_INTENSITY && out_dtype != TM_F32 && out_dtype != TM_BF16)
+    return fail(c, TM_EINVAL, "out_dtype %d", out_dtype);
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.tin = (const tmk::cx<float>*)t;
+  a.yout = out;
+  a.out_bf16 = (out_dtype == TM_BF16);
+  return run_row(c, fn, out_kind == TM_FIELD ? tmk::M_FWD_FIELD : tmk::M_FWD_INT, 0, a, stream);
+}
+
+int tm_adjoint(tm_ctx* c, tm_dims d, const tm_c32* masks, const tm_c32* y, tm_c32* x, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (d.P == 0) return TM_OK;
+  if (!masks || !y || !x) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.yin = (const tmk::cx<float>*)y;
+  a.tout = (tmk::cx<float>*)x;
+  return run_row(c, fn, tmk::M_ADJ, 0, a, stream);
+}
+
+int tm_gradient(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, int I_dtype,
+                const tm_c32* t, tm_c32* grad, float* f, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (d.P == 0) return TM_OK;
+  if (!masks || !I || !t || !grad) return fail(c, TM_EINVAL, "null pointer argument");
+  if (I_dtype != TM_F32 && I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", I_dtype);
+  HIPCHK(c, hipSetDevice(c->device));
+  float* sums = (float*)ws_get(c, WS_SUMS, (size_t)d.P * tmk::NSUM * sizeof(float));
+  if (!sums) return fail(c, TM_ENOMEM, "workspace");
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.I = I;
+  a.tin = (const tmk::cx<float>*)t;
+  a.tout = (tmk::cx<float>*)grad;
+  a.sums = sums;
+  r = run_row(c, fn, tmk::M_GRAD, I_dtype == TM_BF16, a, stream);
+  if (r) return r;
+  if (f) {
+    HIPCHK(c, hipMemcpy2DAsync(f, sizeof(float), sums, tmk::NSUM * sizeof(float), sizeof(float), d.P,
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  }
+  return TM_OK;
+}
+
+static int residual_into(tm_ctx* c, tmk::row_launcher fn, const tm_dims& d, const tm_c32* masks,
+                         const void* I, int I_dtype, const tm_c32* t, double* sums64, void* stream) {
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.I = I;
+  a.tin = (const tmk::cx<float>*)t;
+  a.sums64 = sums64;
+  return run_row(c, fn, tmk::M_RES64, I_dtype == TM_BF16, a, stream);
+}
+
+int tm_residual_f64(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, int I_dtype,
+                    const tm_c32* t, double* rho, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (d.P == 0) return TM_OK;
+  if (!masks || !I || !t || !rho) return fail(c, TM_EINVAL, "null pointer argument");
+  if (I_dtype != TM_F32 && I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", I_dtype);
+  HIPCHK(c, hipSetDevice(c->device));
+  double* s64 = (double*)ws_get(c, WS_SUMS64, (size_t)d.P * 2 * sizeof(double));
+  void* st = ws_get(c, WS_LB_ST, (size_t)d.P * sizeof(tm_row_stats));
+  if (!s64 || !st) return fail(c, TM_ENOMEM, "workspace");
+  r = residual_into(c, fn, d, masks, I, I_dtype, t, s64, stream);
+  if (r) return r;
+  int e = tmk::launch_finalize(st, d.P, s64, nullptr, 0, -1, -1, 0, 1e-2, stream);
+  if (e) return hipfail(c, e, "finalize");
+  HIPCHK(c, hipMemcpy2DAsync(rho, sizeof(double), st, sizeof(tm_row_stats), sizeof(double), d.P,
+                             hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return TM_OK;
+}
+
+int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32* t,
+                const tm_retrieve_opts* o, tm_row_stats* stats, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (!o) return fail(c, TM_EINVAL, "opts is NULL");
+  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_LBFGS) return fail(c, TM_EINVAL, "method %d", o->method);
+  if (o->iters < 0) return fail(c, TM_EINVAL, "iters %d < 0", o->iters);
+  if (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", o->I_dtype);
+  if (o->start < TM_START_GIVEN || o->start > TM_START_SPECTRAL) return fail(c, TM_EINVAL, "start %d", o->start);
+  if (o->start == TM_START_SPECTRAL) {
+    if (o->spectral_iters < 0) return fail(c, TM_EINVAL, "spectral_iters %d", o->spectral_iters);
+    if (!(o->spectral_tau > 0.f)) return fail(c, TM_EINVAL, "spectral_tau must be > 0");
+    if (!(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f))
+      return fail(c, TM_EINVAL, "spectral_momentum must be in [0, 1)");
+  }
+  if (o->method == TM_METHOD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
+    return fail(c, TM_EINVAL, "lbfgs_m %d outside 1..16", o->lbfgs_m);
+  if (d.P == 0) return TM_OK;
+  if (!masks || !I || !t) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int N = d.n1 * d.n2;
+  const int ibf = o->I_dtype == TM_BF16;
+  float* sums = (float*)ws_get(c, WS_SUMS, (size_t)d.P * tmk::NSUM * sizeof(float));
+  double* s64 = (double*)ws_get(c, WS_SUMS64, (size_t)d.P * 2 * sizeof(double));
+  if (!sums || !s64) return fail(c, TM_ENOMEM, "workspace");
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.I = I;
+  tmk::cx<float>* tt = (tmk::cx<float>*)t;
+
+  // ---- start
+  if (o->start == TM_START_BACKPROP) {
+    a.tout = tt;
+    r = run_row(c, fn, tmk::M_BACKPROP, ibf, a, stream);
+    if (r) return r;
+  } else if (o->start == TM_START_SPECTRAL) {
+    double* rowsum = (double*)ws_get(c, WS_ROWSUM, (size_t)d.P * sizeof(double));
+    float* rowmean = (float*)ws_get(c, WS_ROWMEAN, (size_t)d.P * sizeof(float));
+    void* vprev = ws_get(c, WS_VPREV, (size_t)d.P * N * sizeof(tm_c32));
+    if (!rowsum || !rowmean || !vprev) return fail(c, TM_ENOMEM, "workspace");
+    int e = tmk::launch_row_isum(I, ibf, (int64_t)d.K * N, d.P, rowsum, rowmean, stream);
+    if (!e) e = tmk::launch_row_rescale(t, N, d.P, 0, nullptr, 1.0, stream);
+    if (!e) e = tmk::launch_fill_zero(vprev, (int64_t)d.P * N * sizeof(tm_c32), stream);
+    if (e) return hipfail(c, e, "spectral setup");
+    tmk::RowArgs s = a;
+    s.tin = tt;
+    s.tout = tt;
+    s.din = (const tmk::cx<float>*)vprev;
+    s.tout2 = (tmk::cx<float>*)vprev;
+    s.rowmean = rowmean;
+    s.tau = o->spectral_tau;
+    s.momentum = o->spectral_momentum;
+    s.sums = sums;
+    for (int it = 0; it < o->spectral_iters; ++it) {
+      r = run_row(c, fn, tmk::M_SPEC, ibf, s, stream);
+      if (r) return r;
+    }
+    e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
+    if (e) return hipfail(c, e, "spectral scale");
+  }
+
+  // ---- iterations
+  int f_idx = -1, amp_idx = -1;
+  if (o->method == TM_METHOD_ER) {
+    a.tin = tt;
+    a.tout = tt;
+    a.sums = sums;
+    for (int it = 0; it < o->iters; ++it) {
+      r = run_row(c, fn, tmk::M_ER, ibf, a, stream);
+      if (r) return r;
+    }
+    if (o->iters > 0) {
+      amp_idx = 0;
+      f_idx = 1;
+    }
+  } else {
+    tmk::LbfgsBuffers b;
+    size_t vec = (size_t)d.P * N * sizeof(tm_c32);
+    b.g = ws_get(c, WS_LB_G, vec);
+    b.gp = ws_get(c, WS_LB_GP, vec);
+    b.d = ws_get(c, WS_LB_D, vec);
+    b.S = ws_get(c, WS_LB_S, vec * o->lbfgs_m);
+    b.Y = ws_get(c, WS_LB_Y, vec * o->lbfgs_m);
+    b.sc = ws_get(c, WS_LB_SC, (size_t)d.P * tmk::LB_SCALARS(o->lbfgs_m) * sizeof(double));
+    if (!b.g || !b.gp || !b.d || !b.S || !b.Y || !b.sc) return fail(c, TM_ENOMEM, "L-BFGS workspace");
+    b.sums = sums;
+    int e = tmk::run_lbfgs(fn, a, ibf, N, o->iters, o->lbfgs_m, tt, b, stream);
+    if (e) return hipfail(c, e, "L-BFGS");
+    f_idx = 0;
+  }
+
+  // ---- FP64 acceptance residual and per-row record
+  r = residual_into(c, fn, d, masks, I, o->I_dtype, t, s64, stream);
+  if (r) return r;
+  if (stats) {
+    int e = tmk::launch_finalize(stats, d.P, s64, (f_idx >= 0) ? sums : nullptr, tmk::NSUM, f_idx,
+                                 amp_idx, o->iters, 1e-2, stream);
+    if (e) return hipfail(c, e, "finalize");
+  }
+  return TM_OK;
+}
+
+}  // extern "C"
+
+static int phase_check(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
+                       const tm_c32* theta, const float* I_d, const tm_optics* o) {
+  if (!dd || !o) return fail(c, TM_EINVAL, "dims/optics pointer is NULL");
+  if (dd->P < 1 || dd->N < 1 || dd->Nd < 1) return fail(c, TM_EINVAL, "P=%d N=%d Nd=%d must be >= 1", dd->P, dd->N, dd->Nd);
+  if (!is_pow2(dd->nf1) || !is_pow2(dd->nf2) || dd->nf1 < 2 || dd->nf2 < 2 || dd->nf1 > 256 || dd->nf2 > 256)
+    return fail(c, TM_EINVAL, "field grid %dx%d: powers of two in 2..256", dd->nf1, dd->nf2);
+  if ((int64_t)dd->P > (int64_t)dd->nf1 * dd->nf2) return fail(c, TM_EINVAL, "P=%d exceeds the field grid", dd->P);
+  if (!pix || !tm_est || !theta || !I_d) return fail(c, TM_EINVAL, "null pointer argument");
+  if (!(o->lambda > 0) || !(o->ps_field > 0) || !(o->NA > 0) || !(o->NA < 1) || !std::isfinite(o->z))
+    return fail(c, TM_EINVAL, "optics: lambda, ps_field > 0, 0 < NA < 1, finite z");
+  // pixel indices address the field grid: check range and distinctness on the host
+  std::vector<int32_t> hp(dd->P);
+  if (hipMemcpy(hp.data(), pix, dd->P * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, TM_EHIP, "reading pix");
+  std::vector<char> seen((size_t)dd->nf1 * dd->nf2, 0);
+  for (int i = 0; i < dd->P; ++i) {
+    if (hp[i] < 0 || hp[i] >= dd->nf1 * dd->nf2) return fail(c, TM_EINVAL, "pix[%d]=%d outside the field grid", i, hp[i]);
+    if (seen[hp[i]]) return fail(c, TM_EINVAL, "pix[%d]=%d repeats a pixel", i, hp[i]);
+    seen[hp[i]] = 1;
+  }
+  return TM_OK;
+}
+
+static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const tm_c32* tm_est, const tm_c32* theta,
+                         const tm_optics* o, tmk::PhaseDims& pd, tmk::PhaseWork& w, void* stream) {
+  pd = tmk::PhaseDims{dd->P, dd->N, dd->Nd, dd->nf1, dd->nf2};
+  void* base = ws_get(c, WS_PH_BASE, tmk::phase_work_bytes(pd));
+  if (!base) return fail(c, TM_ENOMEM, "phase workspace");
+  tmk::phase_work_carve(base, pd, &w);
+  tmk::PhaseOptics po{o->lambda, o->ps_field, o->NA, o->z};
+  int e = tmk::phase_setup(pd, po, tm_est, theta, w, stream);
+  if (e) return hipfail(c, e, "phase setup");
+  return TM_OK;
+}
+
+extern "C" int tm_phase_objective(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
+                                  const tm_c32* theta, const float* I_d, const tm_optics* o, const double* phi,
+                                  double* g_dev, double* grad, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = phase_check(c, dd, pix, tm_est, theta, I_d, o);
+  if (r) return r;
+  if (!phi || !g_dev || !grad) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::PhaseDims pd;
+  tmk::PhaseWork w;
+  if ((r = phase_prepare(c, dd, tm_est, theta, o, pd, w, stream))) return r;
+  int e = tmk::phase_eval(pd, pix, I_d, phi, grad, w, (const double*)c->tw64, stream);
+  if (e) return hipfail(c, e, "phase eval");
+  HIPCHK(c, hipMemcpyAsync(g_dev, w.gval, sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return TM_OK;
+}
+
+extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
+                                       const tm_c32* tm_est, const tm_c32* theta, const float* I_d,
+                                       const tm_optics* o, double* phi, const tm_phase_opts* po,
+                                       double* g_out, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = phase_check(c, dd, pix, tm_est, theta, I_d, o);
+  if (r) return r;
+  if (!phi || !po) return fail(c, TM_EINVAL, "null pointer argument");
+  if (po->iters < 0 || po->m < 1 || po->m > 16) return fail(c, TM_EINVAL, "iters >= 0 and 1 <= m <= 16");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  tmk::PhaseDims pd;
+  tmk::PhaseWork w;
+  if ((r = phase_prepare(c, dd, tm_est, theta, o, pd, w, stream))) return r;
+  const int P = dd->P, m = po->m;
+  size_t vb = ((P * sizeof(double) + 255) / 256) * 256;
+  char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (5 + 2 * m) + 256 * sizeof(double));
+  if (!lb) return fail(c, TM_ENOMEM, "phase L-BFGS workspace");
+  tmk::PhaseLb L;
+  L.phi = (double*)(lb);
+  L.g = (double*)(lb + vb);
+  L.gt = (double*)(lb + 2 * vb);
+  L.phit = (double*)(lb + 3 * vb);
+  L.d = (double*)(lb + 4 * vb);
+  L.S = (double*)(lb + 5 * vb);
+  L.Y = (double*)(lb + (5 + m) * vb);
+  L.sc = (double*)(lb + (5 + 2 * m) * vb);
+  HIPCHK(c, hipMemcpyAsync(L.phi, phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
+  int e = tmk::phase_lb_init(L, P, m, stream);
+  if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
+  if (e) return hipfail(c, e, "phase eval");
+  double f = 0;
+  HIPCHK(c, hipMemcpyAsync(&f, w.gval, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int it = 0; it < po->iters; ++it) {
+    if ((e = tmk::phase_lb_direction(L, P, m, stream))) return hipfail(c, e, "phase direction");
+    double slope = 0;
+    HIPCHK(c, hipMemcpyAsync(&slope, L.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!(slope < 0.0)) break;  // zero gradient
+    double a = 1.0, fn = 0.0;
+    bool ok = false;
+    for (int h = 0; h < 40; ++h) {
+      if ((e = tmk::phase_lb_trial(L, P, a, stream))) return hipfail(c, e, "phase trial");
+      if ((e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, stream)))
+        return hipfail(c, e, "phase eval");
+      HIPCHK(c, hipMemcpyAsync(&fn, w.gval, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (fn <= f + 1e-4 * a * slope) {  // Armijo sufficient decrease
+        ok = true;
+        break;
+      }
+      a *= 0.5;
+    }
+    if (!ok) break;
+    if ((e = tmk::phase_lb_accept(L, P, m, a, stream))) return hipfail(c, e, "phase accept");
+    f = fn;
+  }
+  HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (g_out) *g_out = f;
+  return TM_OK;
+}

@@ -1,0 +1,232 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+Per-step operators must agree to 1e-5 relative (max-abs error over max-abs
+value); the FP64 residual to 1e-9."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2302_13524_amd as tm
+import tm_synth
+from oracle import operators as ops
+from oracle import retrieval as rt
+
+from gpu_util import c64, dev, f32, problem, relerr, rounded
+
+pytestmark = pytest.mark.gpu
+
+OPTOL = 1e-5
+GRIDS = [(8, 8), (4, 16), (16, 4), (1, 64), (16, 16), (8, 32), (32, 32), (64, 32), (32, 64), (64, 64),
+         (128, 64), (64, 128), (128, 32), (1, 1024)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tm.Context(0)
+    yield c
+    c.close()
+
+
+def rows_for(N):
+    # several workgroups and a ragged tail
+    return {64: 150, 256: 37, 1024: 21, 2048: 9, 4096: 7, 8192: 5}.get(N, 13)
+
+
+@pytest.mark.parametrize("n1,n2", GRIDS)
+def test_forward_field_and_intensity(ctx, n1, n2):
+    P = rows_for(n1 * n2)
+    print(f"forward grid {n1}x{n2} P={P}", flush=True)
+    masks, T, _, _ = problem(n1, n2, 4, P, cfg=901)
+    m, t, _ = rounded(masks, T, np.zeros(1))
+    ref = ops.FFTOp(m, n1, n2).forward(t)
+    y = tm.tm_forward(ctx, c64(masks), c64(T), n1, n2).cpu().numpy()
+    assert relerr(y, ref) < OPTOL
+    I = tm.tm_forward(ctx, c64(masks), c64(T), n1, n2, intensity=True).cpu().numpy()
+    assert relerr(I, np.abs(ref) ** 2) < 2 * OPTOL
+
+
+@pytest.mark.parametrize("n1,n2", [(8, 8), (32, 32), (128, 64)])
+def test_forward_matches_dense_definition(ctx, n1, n2):
+    P = 3
+    print(f"dense grid {n1}x{n2}", flush=True)
+    masks, T, _, _ = problem(n1, n2, 2 if n1 * n2 > 2048 else 4, P, cfg=902)
+    m, t, _ = rounded(masks, T, np.zeros(1))
+    if n1 * n2 <= 1024:
+        ref = ops.DenseOp(m, n1, n2).forward(t)
+    else:  # dense 2-D DFT applied as two dense 1-D DFT matrices (Kronecker factors)
+        F1, F2 = ops.dft_matrix(n1), ops.dft_matrix(n2)
+        x = m[None] * t[:, None, :]
+        ref = np.einsum("ai,pkij,bj->pkab", F1, x.reshape(P, -1, n1, n2), F2).reshape(P, -1, n1 * n2)
+    y = tm.tm_forward(ctx, c64(masks), c64(T), n1, n2).cpu().numpy()
+    assert relerr(y, ref) < OPTOL
+
+
+def test_forward_bf16_intensity_is_rounded_f32(ctx):
+    masks, T, _, _ = problem(32, 32, 4, 9, cfg=903)
+    I32 = tm.tm_forward(ctx, c64(masks), c64(T), 32, 32, intensity=True).cpu().numpy()
+    I16 = tm.tm_forward(ctx, c64(masks), c64(T), 32, 32, intensity=True, bf16=True)
+    bits = I16.view(torch.int16).cpu().numpy().view(np.uint16)
+    assert np.array_equal(bits, tm_synth.to_bf16_bits(I32))
+
+
+@pytest.mark.parametrize("n1,n2", GRIDS)
+def test_adjoint(ctx, n1, n2):
+    P = rows_for(n1 * n2)
+    print(f"adjoint grid {n1}x{n2} P={P}", flush=True)
+    masks, _, _, _ = problem(n1, n2, 4, 1, cfg=904)
+    g = np.random.default_rng(5)
+    y = (g.standard_normal((P, 4, n1 * n2)) + 1j * g.standard_normal((P, 4, n1 * n2))).astype(np.complex64)
+    ref = ops.FFTOp(masks.astype(np.complex64).astype(np.complex128), n1, n2).adjoint(y.astype(np.complex128))
+    x = tm.tm_adjoint(ctx, c64(masks), c64(y), n1, n2).cpu().numpy()
+    assert relerr(x, ref) < OPTOL
+
+
+@pytest.mark.parametrize("n1,n2", [(8, 8), (32, 32), (64, 64), (128, 64)])
+def test_gradient(ctx, n1, n2):
+    P = rows_for(n1 * n2)
+    print(f"gradient grid {n1}x{n2}", flush=True)
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=905, noise=1e4)
+    t0 = T + 0.5 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(905, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    f_ref, g_ref, _ = rt.intensity_grad(ops.FFTOp(m, n1, n2), Ir.reshape(P, 4, -1), t)
+    g, f = tm.tm_gradient(ctx, c64(masks), f32(I), c64(t0), n1, n2)
+    assert relerr(g.cpu().numpy(), g_ref) < OPTOL
+    assert relerr(f.cpu().numpy(), f_ref) < OPTOL
+
+
+@pytest.mark.parametrize("n1,n2", [(8, 8), (32, 32), (128, 64)])
+def test_residual_f64(ctx, n1, n2):
+    P = rows_for(n1 * n2)
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=906, noise=1e4)
+    t0 = T + 0.1 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(906, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    ref = rt.acceptance_residual(ops.FFTOp(m, n1, n2), Ir.reshape(P, 4, -1), t)
+    rho = tm.tm_residual_f64(ctx, c64(masks), f32(I), c64(t0), n1, n2).cpu().numpy()
+    assert relerr(rho, ref) < 1e-9
+
+
+def test_er_one_step(ctx):
+    n1, n2, P = 32, 32, 21
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=907, noise=1e4)
+    t0 = T + 0.7 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(907, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    ref = rt.er_step(ops.FFTOp(m, n1, n2), Ir, t)
+    tt = c64(t0)
+    tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("er", iters=1))
+    assert relerr(tt.cpu().numpy(), ref) < OPTOL
+
+
+def test_backprop_start(ctx):
+    n1, n2, P = 64, 32, 9
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=908, noise=1e4)
+    m, t, Ir = rounded(masks, T, I)
+    ref = rt.backprop_start(ops.FFTOp(m, n1, n2), Ir)
+    tt = torch.zeros((P, n1 * n2), dtype=torch.complex64, device=dev())
+    tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("er", iters=0, start="backprop"))
+    assert relerr(tt.cpu().numpy(), ref) < OPTOL
+
+
+@pytest.mark.parametrize("mom", [0.0, 0.98])
+def test_spectral_start_steps(ctx, mom):
+    n1, n2, P = 32, 32, 21
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=909, noise=1e4)
+    v0 = tm_synth.random_start(P, n1 * n2, np.ones(P), tm_synth.rng(909, 3))
+    m, v, Ir = rounded(masks, v0, I)
+    for steps in (1, 3):
+        ref = rt.spectral_start(ops.FFTOp(m, n1, n2), Ir, v, steps, tau=3.0, momentum=mom)
+        tt = c64(v0)
+        tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
+                       tm.retrieve_opts("er", iters=0, start="spectral", spectral_iters=steps,
+                                        spectral_momentum=mom))
+        assert relerr(tt.cpu().numpy(), ref) < 1e-4 * steps
+
+
+def test_line_search_sums(ctx):
+    # drive one L-BFGS iteration and compare the exact step with the oracle's
+    n1, n2, P = 32, 32, 13
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=910, noise=1e4)
+    t0 = T + 0.3 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(910, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    ref, _ = rt.lbfgs(ops.FFTOp(m, n1, n2), Ir, t, 1)
+    tt = c64(t0)
+    tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("lbfgs", iters=1))
+    assert relerr(tt.cpu().numpy(), ref) < 1e-4
+
+
+def _fid(a, b):
+    return rt.fidelity(a, b)
+
+
+@pytest.mark.parametrize("method,iters", [("er", 200), ("lbfgs", 100)])
+def test_retrieve_noiseless_tiny(ctx, method, iters):
+    # 8x8 modes, 32 rows, K = 4, noiseless: spectral start then the solver
+    n1, n2, P = 8, 8, 32
+    masks = tm_synth.mask_phases(4, 64, tm_synth.rng(1, 0))
+    T = tm_synth.tm_iid(P, 64, tm_synth.rng(1, 1))
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, T)
+    v0 = tm_synth.random_start(P, 64, np.ones(P), tm_synth.rng(1, 3))
+    m, v, Ir = rounded(masks, v0, I)
+    opr = ops.FFTOp(m, n1, n2)
+    s0 = rt.spectral_start(opr, Ir, v, 30, momentum=0.98)
+    if method == "er":
+        ref = s0
+        for _ in range(iters):
+            ref = rt.er_step(opr, Ir, ref)
+    else:
+        ref, _ = rt.lbfgs(opr, Ir, s0, iters)
+    tt = c64(v0)
+    raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
+                         tm.retrieve_opts(method, iters=iters, start="spectral", spectral_iters=30))
+    got = tt.cpu().numpy().astype(np.complex128)
+    fg, fo = _fid(got, T), _fid(ref, T)
+    print(method, "gpu mean fid", fg.mean(), "oracle", fo.mean())
+    assert abs(fg.mean() - fo.mean()) < 1e-4 or (fg.mean() >= fo.mean())
+    st = tm.decode_stats(raw)
+    ok = fg >= 0.9999
+    assert np.all(st.rho.numpy()[ok] < 1e-6)
+    assert np.all((st.flags.numpy() & 2) == 0)
+
+
+def test_empty_and_errors(ctx):
+    masks, T, I, _ = problem(8, 8, 4, 2, cfg=911)
+    e = torch.empty((0, 64), dtype=torch.complex64, device=dev())
+    out = tm.tm_forward(ctx, c64(masks), e, 8, 8)
+    assert out.shape == (0, 4, 64)
+    with pytest.raises(tm.TMError, match="no compiled FFT plan|powers of two"):
+        tm.tm_forward(ctx, c64(masks[:, :48]), c64(T[:, :48]), 6, 8)
+    big = torch.zeros((1, 16384), dtype=torch.complex64, device=dev())
+    with pytest.raises(tm.TMError, match="N=16384"):
+        tm.tm_forward(ctx, torch.zeros((1, 16384), dtype=torch.complex64, device=dev()), big, 128, 128)
+
+
+def test_full_size_sampled_rows(ctx):
+    # the benchmark's shape and launch configuration: 2286 rows x 8192 modes
+    # (128 x 64), K = 4. The oracle recomputes a seeded sample of rows (rows
+    # are independent problems).
+    n1, n2, K, P = 128, 64, 4, 2286
+    N = n1 * n2
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
+    g = np.random.default_rng(77)
+    T = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
+    T2 = (T + 0.5 * (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N)))).astype(np.complex64)
+    mk = c64(masks)
+    I = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True)
+    grad, f = tm.tm_gradient(ctx, mk, I, c64(T2), n1, n2)
+    t_er = c64(T2)
+    tm.tm_retrieve(ctx, mk, I, t_er, n1, n2, tm.retrieve_opts("er", iters=1))
+    t_sp = c64(T2)
+    tm.tm_retrieve(ctx, mk, I, t_sp, n1, n2, tm.retrieve_opts("er", iters=0, start="spectral", spectral_iters=1,
+                                                               spectral_momentum=0.0))
+    rows = np.sort(g.choice(P, 6, replace=False))
+    rows = np.unique(np.concatenate([rows, [0, P - 1]]))
+    m = masks.astype(np.complex64).astype(np.complex128)
+    op = ops.FFTOp(m, n1, n2)
+    Iref = ops.intensities(op, T[rows].astype(np.complex128))
+    Ig = I.cpu().numpy()[rows].astype(np.float64)
+    assert relerr(Ig, Iref) < 2 * OPTOL
+    t2 = T2[rows].astype(np.complex128)
+    _, gref, _ = rt.intensity_grad(op, Ig, t2)
+    assert relerr(grad.cpu().numpy()[rows], gref) < OPTOL
+    assert relerr(t_er.cpu().numpy()[rows], rt.er_step(op, Ig, t2)) < OPTOL
+    sref = rt.spectral_start(op, Ig, t2, 1, tau=3.0, momentum=0.0)
+    assert relerr(t_sp.cpu().numpy()[rows], sref) < 1e-4
