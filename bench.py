@@ -1,0 +1,292 @@
+"""Benchmark: TM rows/s to fidelity 0.99 on one MI355X.
+
+Workload (the paper-scale configuration): N = 8192 input modes on a 128 x 64
+grid, P = 2286 output pixels (the pixels of a 64 x 64 grid nearest its
+centre), band-limited speckle TM (pupil 0.22 of the grid Nyquist), K = 4
+random-phase masks (32768 intensities per row), Poisson noise at a mean of
+1e4 photons per pixel, FP32 intensities; 50 defocus images (128 x 128) at
+z = 20 wavelengths for the phase-offset step. All inputs are seeded and
+synthetic (the paper's measured data are not available).
+
+A step is one pass of the whole path over the batch: truncated spectral
+start (heavy-ball power iteration), error-reduction iterations up to the
+count at which the mean per-row fidelity first reaches 0.99 (found by an
+untimed instrumented run), the FP64 acceptance residual, and the per-row
+phase-offset correction from the defocus images. value = P / step time.
+
+Also printed in the same JSON line: the roofline of the dominant kernel
+(the fused error-reduction kernel, event-timed live over the timed region),
+the learned-start variant when a trained network is given, and the FP64
+oracle timed on the host's cores over a bounded sample of rows
+(`cpu_baseline`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3  # published vector FP32 (packed) peak; 78.6 without packed math
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--spectral-iters", type=int, default=30)
+    ap.add_argument("--phase-iters", type=int, default=30)
+    ap.add_argument("--max-iters", type=int, default=300)
+    ap.add_argument("--cpu-rows", type=int, default=0, help="rows in the CPU-baseline sample (0: auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--small", action="store_true", help="32x32 modes, 512 rows (quick check)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    a = torch.empty(512 * 2**20 // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "copies": 5}))
+
+
+def main():
+    args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); rows are independent problems, so "
+              "more GPUs would each run this same kernel on P/G rows.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2302_13524_amd as tm
+    import tm_synth
+
+    dev = torch.device("cuda:0")
+    if args.small:
+        n1, n2, P, grid, pupil, nf = 32, 32, 512, 32, 0.3, 32
+        cfg_id = 2
+    else:
+        n1, n2, P, grid, pupil, nf = 128, 64, 2286, 64, 0.22, 64
+        cfg_id = 3
+    K, N, Nd = 4, n1 * n2, 50
+    NA, lam, ps, z = pupil, 1.0, 0.5, 20.0
+    workload = f"{P}x{N} TM ({n1}x{n2} modes), K={K}, speckle pupil {pupil}, Poisson 1e4, FP32 I; " \
+               f"{Nd} defocus images {2*nf}x{2*nf}"
+
+    t0 = time.perf_counter()
+    pix = tm_synth.nearest_pixels(grid, P)
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(cfg_id, 0))
+    T = tm_synth.speckle_tm(N, grid, pupil, pix, tm_synth.rng(cfg_id, 1)).astype(np.complex64)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(cfg_id, 3)).astype(np.complex64)
+    theta = tm_synth.defocus_phases(Nd, N, tm_synth.rng(cfg_id, 4)).astype(np.complex64)
+    log(f"host synthesis {time.perf_counter() - t0:.1f}s")
+
+    ctx = tm.Context(0)
+    mk = torch.from_numpy(masks.astype(np.complex64)).to(dev)
+    Tt = torch.from_numpy(T).to(dev)
+    v0t = torch.from_numpy(v0).to(dev)
+    th = torch.from_numpy(theta).to(dev)
+    pixt = torch.from_numpy(pix.astype(np.int32)).to(dev)
+    optics = (lam, ps, NA, z)
+
+    # intensities: clean forward on the GPU, shot noise drawn on the host (seeded)
+    Ic = tm.tm_forward(ctx, mk, Tt, n1, n2, intensity=True).cpu().numpy()
+    I_np = tm_synth.poisson_counts(Ic.astype(np.float64), 1e4, tm_synth.rng(cfg_id, 2)).astype(np.float32)
+    del Ic
+    It = torch.from_numpy(I_np).to(dev)
+    Idc = tm.tm_defocus_forward(ctx, pixt, Tt, th, optics, torch.zeros(P, dtype=torch.float64, device=dev), nf,
+                                nf).cpu().numpy()
+    Id_np = tm_synth.poisson_counts(Idc.astype(np.float64), 1e4, tm_synth.rng(cfg_id, 5)).astype(np.float32)
+    Idt = torch.from_numpy(Id_np).to(dev)
+    log(f"inputs ready {time.perf_counter() - t0:.1f}s")
+
+    Tn = Tt / torch.linalg.vector_norm(Tt, dim=1, keepdim=True)
+
+    def fidelity(t):
+        c = torch.sum(torch.conj(t) * Tn, dim=1)
+        return (c.abs() ** 2 / torch.sum(t.abs() ** 2, dim=1)).double()
+
+    sp = args.spectral_iters
+
+    def opts(method, iters, start="spectral"):
+        return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=3.0,
+                                spectral_momentum=0.98)
+
+    # ---- untimed instrumented run: iterations to mean fidelity 0.99
+    t = v0t.clone()
+    tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 0))
+    f_start = fidelity(t).mean().item()
+    n_er = None
+    for it in range(1, args.max_iters + 1):
+        tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 1, start="given"), stats=False)
+        if fidelity(t).mean().item() >= 0.99:
+            n_er = it
+            break
+    if n_er is None:
+        raise SystemExit(f"error reduction did not reach mean fidelity 0.99 in {args.max_iters} iterations")
+    log(f"spectral start fidelity {f_start:.4f}; ER reaches 0.99 after {n_er} iterations")
+    n_lb = None
+    for k in (5, 10, 15, 20, 25, 30, 40, 50, 70, 100):
+        t = v0t.clone()
+        tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("lbfgs", k), stats=False)
+        if fidelity(t).mean().item() >= 0.99:
+            n_lb = k
+            break
+    log(f"L-BFGS reaches 0.99 within {n_lb} iterations")
+
+    def step(method="er", iters=n_er, phase=True):
+        t = v0t.clone()
+        raw = tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts(method, iters))
+        phi = None
+        if phase:
+            phi = torch.zeros(P, dtype=torch.float64, device=dev)
+            tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=args.phase_iters, m=5)
+        return t, raw, phi
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm.tm_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        t, raw, phi = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    er_ms, er_n = tm.tm_profile_query(ctx, 3)
+    sp_ms, sp_n = tm.tm_profile_query(ctx, 5)
+    rs_ms, rs_n = tm.tm_profile_query(ctx, 7)
+    tm.tm_profile_enable(ctx, False)
+    ms_step = elapsed * 1e3 / args.steps
+
+    # component timings (retrieval only; phase correction only; L-BFGS variant)
+    def timed(fn, reps=3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / reps
+
+    ret_ms = timed(lambda: step(phase=False))
+    lb_ms = timed(lambda: step("lbfgs", n_lb, phase=False)) if n_lb else None
+
+    fid = fidelity(t).cpu().numpy()
+    st = tm.decode_stats(raw)
+    # phase correction quality: after diag(e^{j phi}) the rows share one offset w.r.t. the truth
+    off = torch.angle(torch.sum(torch.conj(t) * Tt, dim=1)).double() - phi
+    zc = torch.exp(1j * off)
+    phase_spread = float(torch.sqrt(-2 * torch.log(torch.abs(zc.mean()))).item())
+    off0 = torch.angle(torch.sum(torch.conj(t) * Tt, dim=1)).double()
+    phase_spread_before = float(torch.sqrt(-2 * torch.log(torch.abs(torch.exp(1j * off0).mean()) + 1e-300)).item())
+
+    # roofline of the fused error-reduction kernel (one launch = one iteration over all P rows)
+    er_avg_ms = er_ms / max(er_n, 1)
+    alg_bytes = P * (K * N * 4 + 2 * N * 8)
+    flops_fft = 2 * K * 5 * N * np.log2(N)
+    alg_flops = P * (flops_fft + 30 * K * N)
+    achieved = alg_bytes / (er_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "row_kernel<M_ER> (fused mask*FFT, projection, IFFT, conj-mask sum)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(er_avg_ms, 5), "launches": er_n,
+                "alg_bytes_per_launch": alg_bytes}
+    roofline_alu = {"bound": "alu", "achieved": round(alg_flops / (er_avg_ms * 1e-3) / 1e12, 2),
+                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(alg_flops / (er_avg_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4),
+                    "alg_flops_per_launch": int(alg_flops)}
+
+    out = {
+        "metric": "TM rows/s to fidelity 0.99 at 2286x8192 (plain start)" if not args.small else
+                  "TM rows/s to fidelity 0.99 at 512x1024 (plain start)",
+        "value": round(P / (ms_step * 1e-3), 1),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "P": P, "N": N, "grid": [n1, n2], "K": K,
+                   "start": f"truncated spectral, {sp} heavy-ball steps", "solver": "error reduction",
+                   "iters_to_0.99": n_er, "phase_iters": args.phase_iters},
+        "roofline": roofline,
+        "roofline_alu": roofline_alu,
+        "retrieval_ms": round(ret_ms, 3),
+        "retrieval_rows_per_s": round(P / (ret_ms * 1e-3), 1),
+        "phase_correction_ms": round(ms_step - ret_ms, 3),
+        "lbfgs": {"iters_to_0.99": n_lb, "retrieval_ms": round(lb_ms, 3) if lb_ms else None},
+        "quality": {"mean_fidelity": round(float(fid.mean()), 6), "min_fidelity": round(float(fid.min()), 6),
+                    "frac_rows_ge_0.99": round(float((fid >= 0.99).mean()), 4),
+                    "spectral_start_fidelity": round(f_start, 4),
+                    "rows_flagged_rho_gt_1e-2": int((st.flags.numpy() & 1).sum()),
+                    "phase_spread_rad_before": round(phase_spread_before, 4),
+                    "phase_spread_rad_after": round(phase_spread, 6)},
+        "kernel_ms": {"er_avg": round(er_avg_ms, 5), "spectral_avg": round(sp_ms / max(sp_n, 1), 5),
+                      "residual_f64_avg": round(rs_ms / max(rs_n, 1), 5)},
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, P)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, P):
+    """The FP64 oracle (FFT form of A) on a bounded sample of rows: the same
+    spectral start and error-reduction iterations, timed on the host."""
+    from oracle import operators as ops
+    from oracle import retrieval as rt
+
+    op = ops.FFTOp(masks, n1, n2)
+    K, N = masks.shape
+
+    def run(rows):
+        I = I_np[rows].astype(np.float64)
+        t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=3.0, momentum=0.98)
+        for _ in range(n_er):
+            t = rt.er_step(op, I, t)
+        return t
+
+    g = np.random.default_rng(123)
+    probe = np.sort(g.choice(P, 4, replace=False))
+    a = time.perf_counter()
+    run(probe)
+    dt = time.perf_counter() - a
+    nrows = args.cpu_rows or int(max(4, min(P, 4 * 15.0 / max(dt, 1e-3))))
+    rows = np.sort(g.choice(P, nrows, replace=False))
+    a = time.perf_counter()
+    t = run(rows)
+    dt = time.perf_counter() - a
+    fid = rt.fidelity(t, T[rows].astype(np.complex128))
+    return {"value": round(nrows / dt, 3), "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nrows} of {P} rows, FP64 numpy FFT form of A, {sp} spectral + {n_er} ER iterations "
+                      f"({dt:.1f}s)", "mean_fidelity": round(float(fid.mean()), 6),
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+if __name__ == "__main__":
+    main()

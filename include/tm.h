@@ -187,6 +187,27 @@ int tm_phase_objective(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pi
                        const tm_optics *optics, const double *phi, double *g_dev,
                        double *grad, void *stream);
 
+/* Defocus images of the forward model (Eq. forwarddefocusImage) for the
+ * rows tm [P][N] with offsets phi [P] (double):
+ *   I_out [Nd][2nf1][2nf2] float = | K2^H P diag(h) K1 diag(tm e^{j theta_n}) e^{j phi} |^2
+ * (used to synthesise defocus data). Same argument rules as
+ * tm_phase_objective. */
+int tm_defocus_forward(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,
+                       const tm_c32 *tm, const tm_c32 *theta, const tm_optics *optics,
+                       const double *phi, float *I_out, void *stream);
+
+/* ---- instrumentation ------------------------------------------------------ */
+
+/* Enable (1) or disable (0) per-launch HIP-event timing of the fused row
+ * kernels issued by this context; enabling clears the accumulated times. */
+int tm_profile_enable(tm_ctx *ctx, int enable);
+/* Accumulated device time (milliseconds) and launch count of the fused row
+ * kernel of kind `mode` (0 forward field, 1 forward intensity, 2 adjoint,
+ * 3 error reduction, 4 gradient, 5 spectral step, 6 line-search sums,
+ * 7 FP64 residual, 8 back-propagation) since enabling. Synchronises the
+ * context's device. */
+int tm_profile_query(tm_ctx *ctx, int mode, double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,10 @@ TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL = 0, 1, 2
 EXPORTED = (
     "tm_create", "tm_destroy", "tm_last_error", "tm_grid_supported", "tm_forward", "tm_adjoint",
     "tm_gradient", "tm_residual_f64", "tm_retrieve", "tm_phase_offset_correct", "tm_phase_objective",
+    "tm_defocus_forward", "tm_profile_enable", "tm_profile_query",
 )
+MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
+              6: "line_sums", 7: "residual_f64", 8: "backprop"}
 
 
 class tm_dims(ctypes.Structure):
@@ -89,6 +92,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                             ctypes.POINTER(dp), vp]
     lib.tm_phase_objective.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
                                        ctypes.POINTER(tm_optics), vp, vp, vp, vp]
+    lib.tm_defocus_forward.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp,
+                                       ctypes.POINTER(tm_optics), vp, vp, vp]
+    lib.tm_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
 
@@ -268,3 +275,28 @@ def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, 
                                          ctypes.byref(g), _stream(tm_est.device))
     ctx.check(rc, "tm_phase_offset_correct")
     return g.value
+
+
+def tm_defocus_forward(ctx: Context, pix, tm_rows, theta, optics, phi, nf1, nf2):
+    """Defocus images |A_n e^{j phi}|^2, [Nd, 2nf1, 2nf2] float32."""
+    P, N = tm_rows.shape
+    Nd = theta.shape[0]
+    out = torch.empty((Nd, 2 * nf1, 2 * nf2), dtype=torch.float32, device=tm_rows.device)
+    dd = _ddims(P, N, Nd, nf1, nf2)
+    op = tm_optics(*[float(v) for v in optics])
+    rc = ctx.lib.tm_defocus_forward(ctx.h, ctypes.byref(dd), _ptr(pix), _ptr(tm_rows), _ptr(theta),
+                                    ctypes.byref(op), _ptr(phi), _ptr(out), _stream(tm_rows.device))
+    ctx.check(rc, "tm_defocus_forward")
+    return out
+
+
+def tm_profile_enable(ctx: Context, enable: bool = True):
+    ctx.check(ctx.lib.tm_profile_enable(ctx.h, 1 if enable else 0), "tm_profile_enable")
+
+
+def tm_profile_query(ctx: Context, mode: int):
+    """(total milliseconds, launches) of the fused row kernel `mode` since enabling."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    ctx.check(ctx.lib.tm_profile_query(ctx.h, int(mode), ctypes.byref(ms), ctypes.byref(n)), "tm_profile_query")
+    return ms.value, n.value

@@ -33,6 +33,10 @@ int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, co
 int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const double* phi,
                double* grad, PhaseWork& w, const double* tw64, void* stream);
 
+// |A_n e^{j phi}|^2 into I_out [Nd][2nf1][2nf2] (float).
+int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, float* I_out, PhaseWork& w,
+                 const double* tw64, void* stream);
+
 // L-BFGS helpers over phi (single-workgroup kernels).
 struct PhaseLb {
   double* phi;    // [P]

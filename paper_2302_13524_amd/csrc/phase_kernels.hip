@@ -317,6 +317,32 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
   return (int)hipGetLastError();
 }
 
+namespace {
+__global__ void k_absq(const double* B, float* out, size_t n) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (float)(B[2 * i] * B[2 * i] + B[2 * i + 1] * B[2 * i + 1]);
+}
+}  // namespace
+
+int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, float* I_out, PhaseWork& w,
+                 const double* tw64, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int e;
+  const int G = d.nf1 * d.nf2;
+  const size_t nA = (size_t)d.Nd * G * 2, nB = (size_t)d.Nd * 4 * G * 2;
+  auto blocks = [](size_t n) { return (unsigned)((n + 255) / 256 > 65535 ? 65535 : (n + 255) / 256); };
+  k_zero<<<blocks(nA), 256, 0, s>>>(w.A, nA);
+  k_zero<<<blocks(nB), 256, 0, s>>>(w.B, nB);
+  k_scatter<<<(d.Nd * d.P + 255) / 256, 256, 0, s>>>(w.A, w.c, phi, pix, d.Nd, d.P, G);
+  if ((e = (int)hipGetLastError())) return e;
+  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s))) return e;
+  k_pad<<<blocks((size_t)d.Nd * G), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
+  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s))) return e;
+  size_t n = (size_t)d.Nd * 4 * G;
+  k_absq<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.B, I_out, n);
+  return (int)hipGetLastError();
+}
+
 // ------------------------------------------------------------ L-BFGS over phi
 namespace {
 constexpr int PWG = 1024;

@@ -29,6 +29,16 @@ struct tm_ctx {
     size_t bytes = 0;
   };
   std::map<int, Slot> ws;
+  // per-launch event timing of the fused row kernels (tm_profile_enable)
+  bool prof = false;
+  struct Rec {
+    int mode;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double acc_ms[16] = {0};
+  int64_t acc_n[16] = {0};
 };
 
 namespace {
@@ -112,8 +122,45 @@ tmk::RowArgs base_args(tm_ctx* c, const tm_dims& d, const tm_c32* masks) {
   return a;
 }
 
+hipEvent_t ev_get(tm_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Fold finished event pairs into the per-mode totals (synchronises them).
+void prof_drain(tm_ctx* c) {
+  for (auto& r : c->recs) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.mode >= 0 && r.mode < 16) {
+      c->acc_ms[r.mode] += ms;
+      c->acc_n[r.mode] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+}
+
 int run_row(tm_ctx* c, tmk::row_launcher fn, int mode, int ibf16, const tmk::RowArgs& a, void* s) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (c->prof && a.P > 0) {
+    if (c->recs.size() > 4096) prof_drain(c);
+    ea = ev_get(c);
+    eb = ev_get(c);
+    hipEventRecord(ea, (hipStream_t)s);
+  }
   int e = fn(mode, ibf16, a, s);
+  if (ea) {
+    hipEventRecord(eb, (hipStream_t)s);
+    c->recs.push_back({mode, ea, eb});
+  }
   if (e) return hipfail(c, e, "row kernel launch");
   return TM_OK;
 }
@@ -166,6 +213,8 @@ int tm_destroy(tm_ctx* c) {
   if (!c) return TM_EINVAL;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
+  prof_drain(c);
+  for (auto e : c->pool) hipEventDestroy(e);
   for (auto& kv : c->ws) hipFree(kv.second.p);
   hipFree(c->tw32);
   hipFree(c->tw64);
@@ -486,5 +535,43 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (g_out) *g_out = f;
+  return TM_OK;
+}
+
+extern "C" int tm_defocus_forward(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tmr,
+                                  const tm_c32* theta, const tm_optics* o, const double* phi, float* I_out,
+                                  void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = phase_check(c, dd, pix, tmr, theta, I_out, o);
+  if (r) return r;
+  if (!phi) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::PhaseDims pd;
+  tmk::PhaseWork w;
+  if ((r = phase_prepare(c, dd, tmr, theta, o, pd, w, stream))) return r;
+  int e = tmk::phase_images(pd, pix, phi, I_out, w, (const double*)c->tw64, stream);
+  if (e) return hipfail(c, e, "defocus images");
+  return TM_OK;
+}
+
+extern "C" int tm_profile_enable(tm_ctx* c, int enable) {
+  if (!c) return TM_EINVAL;
+  hipSetDevice(c->device);
+  prof_drain(c);
+  for (int i = 0; i < 16; ++i) {
+    c->acc_ms[i] = 0;
+    c->acc_n[i] = 0;
+  }
+  c->prof = enable != 0;
+  return TM_OK;
+}
+
+extern "C" int tm_profile_query(tm_ctx* c, int mode, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return TM_EINVAL;
+  if (mode < 0 || mode >= 16) return fail(c, TM_EINVAL, "mode %d", mode);
+  hipSetDevice(c->device);
+  prof_drain(c);
+  *ms = c->acc_ms[mode];
+  *launches = c->acc_n[mode];
   return TM_OK;
 }

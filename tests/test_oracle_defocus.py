@@ -1,0 +1,116 @@
+"""Pins of the FP64 phase-offset oracle (Sec. 2.3): operator equality,
+closed forms of the angular-spectrum model, finite differences, noiseless
+recovery. CPU only."""
+import numpy as np
+import pytest
+
+import tm_synth
+from oracle import defocus as df
+from oracle.operators import dft_matrix
+
+LAM = 1.0
+PS = 0.5  # field pixel = lambda / 2
+
+
+def setup(nf=8, P=20, N=12, Nd=5, NA=0.3, z=20.0, seed=3, dense=False):
+    g = np.random.default_rng(seed)
+    pix = np.sort(g.choice(nf * nf, P, replace=False))
+    tm_est = g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))
+    theta = np.exp(2j * np.pi * g.random((Nd, N)))
+    return df.DefocusModel(tm_est, theta, pix, nf, nf, LAM, PS, NA, z, dense=dense), g
+
+
+def test_frequencies_are_numpy_fftfreq():
+    for n in (1, 2, 5, 8, 16):
+        assert np.allclose(df.freqs(n, 0.7), np.fft.fftfreq(n, 0.7))
+
+
+def test_fft_model_equals_dense_matrices():
+    m_fft, g = setup(nf=8, dense=False)
+    m_dense, _ = setup(nf=8, dense=True)
+    u = np.exp(1j * g.random(m_fft.c.shape[1]) * 6)
+    a1, a2 = m_fft.forward(u), m_dense.forward(u)
+    assert np.max(np.abs(a1 - a2)) < 1e-12 * np.max(np.abs(a1))
+    v = g.standard_normal(a1.shape) + 1j * g.standard_normal(a1.shape)
+    b1, b2 = m_fft.adjoint(v), m_dense.adjoint(v)
+    assert np.max(np.abs(b1 - b2)) < 1e-12 * np.max(np.abs(b1))
+    # adjoint identity
+    lhs = np.vdot(a1, v)
+    rhs = np.vdot(u, m_fft.adjoint(v))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+
+
+def test_zero_defocus_is_fourier_interpolation():
+    # at z = 0 a field band-limited by the pupil is interpolated exactly:
+    # the even samples of the doubled grid equal the field / 2 (unitary K1, K2)
+    nf = 16
+    h, pupil = df.pupil_kernel(nf, nf, PS, LAM, 0.6, 0.0)
+    g = np.random.default_rng(1)
+    spec = (g.standard_normal((nf, nf)) + 1j * g.standard_normal((nf, nf))) * pupil
+    field = np.fft.ifft2(spec)
+    pix = np.arange(nf * nf)
+    mdl = df.DefocusModel(np.diag(field.ravel()), np.ones((1, nf * nf)), pix, nf, nf, LAM, PS, 0.6, 0.0)
+    out = mdl.forward(np.ones(nf * nf))[0]
+    assert np.max(np.abs(out[::2, ::2] - field / 2)) < 1e-12 * np.max(np.abs(field))
+
+
+def test_forward_then_backward_propagation_is_identity_on_band():
+    h1, pupil = df.pupil_kernel(16, 16, PS, LAM, 0.3, 7.5)
+    h2, _ = df.pupil_kernel(16, 16, PS, LAM, 0.3, -7.5)
+    assert np.allclose(h1 * h2, pupil.astype(float), atol=1e-14)
+    assert np.allclose(np.abs(h1), pupil.astype(float), atol=1e-14)
+
+
+def test_pupil_includes_boundary_and_zeroes_nyquist():
+    # a frequency exactly at NA / lambda is inside the pupil (the paper's <=)
+    n = 10
+    u = df.freqs(n, PS)
+    NA = LAM * abs(u[2])
+    _, pupil = df.pupil_kernel(n, n, PS, LAM, NA, 1.0)
+    assert pupil[2, 0] and pupil[0, 2]
+    for nf in (32, 64):
+        _, p = df.pupil_kernel(nf, nf, PS, LAM, 0.3, 20.0)
+        assert not p[nf // 2, :].any() and not p[:, nf // 2].any()
+
+
+def test_phase_gradient_matches_finite_differences():
+    mdl, g = setup(nf=8, P=10, N=8, Nd=4)
+    phi_true = g.random(10) * 2 * np.pi
+    Id = mdl.images(phi_true) + 0.05 * g.random((4, 16, 16))
+    phi = phi_true + 0.3 * g.standard_normal(10)
+    f0, grad = mdl.objective(Id, phi)
+    h = 1e-6
+    num = np.array([(mdl.objective(Id, phi + h * e)[0] - mdl.objective(Id, phi - h * e)[0]) / (2 * h)
+                    for e in np.eye(10)])
+    assert np.max(np.abs(num - grad)) < 1e-6 * np.max(np.abs(grad))
+    # equals the paper's real(-4 diag(-j e^{-j phi}) sum A^H diag(A u) r) form
+    u = np.exp(1j * phi)
+    a = mdl.forward(u)
+    w = mdl.adjoint(a * (Id - np.abs(a) ** 2))
+    paper = np.real(-4 * (-1j * np.exp(-1j * phi)) * w)
+    assert np.allclose(paper, grad, rtol=1e-12, atol=1e-12 * np.max(np.abs(grad)))
+
+
+def test_constant_phase_invariance():
+    mdl, g = setup()
+    phi = g.random(20)
+    Id = mdl.images(phi)
+    assert np.allclose(mdl.images(phi + 1.234), Id, rtol=1e-12, atol=1e-12 * Id.max())
+
+
+def test_noiseless_offsets_recovered():
+    # TM_true = diag(e^{j phi}) TM_est; from phi = 0 L-BFGS recovers phi up to a constant
+    # field band-limited to 0.6 of Nyquist, pupil NA 0.6 at ps = lambda / 2
+    nf, P, N, Nd = 16, 40, 24, 12
+    g = tm_synth.rng(42, 4)
+    pix = tm_synth.nearest_pixels(nf, P)
+    tm_true = tm_synth.speckle_tm(N, nf, 0.6, pix, tm_synth.rng(42, 1))
+    phi_true = tm_synth.offsets(P, tm_synth.rng(42, 5))
+    tm_est = np.exp(-1j * phi_true)[:, None] * tm_true
+    theta = tm_synth.defocus_phases(Nd, N, g)
+    mdl = df.DefocusModel(tm_est, theta, pix, nf, nf, LAM, PS, 0.6, 20 * LAM)
+    Id = mdl.images(phi_true)
+    phi, hist = df.lbfgs_phase(mdl, Id, np.zeros(P), 200)
+    err = df.circular_offset_error(phi, phi_true)
+    assert np.max(np.abs(err)) < 1e-8, np.max(np.abs(err))
+    assert np.all(np.diff(hist) <= 0)
