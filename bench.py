@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows in the CPU-baseline sample (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="32x32 modes, 512 rows (quick check)")
+    ap.add_argument("--er-iters", type=int, default=0, help="skip the instrumented search and use this count")
+    ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
     return ap.parse_args()
@@ -136,8 +138,8 @@ def main():
     t = v0t.clone()
     tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 0))
     f_start = fidelity(t).mean().item()
-    n_er = None
-    for it in range(1, args.max_iters + 1):
+    n_er = args.er_iters or None
+    for it in range(1, 0 if n_er else args.max_iters + 1):
         tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 1, start="given"), stats=False)
         if fidelity(t).mean().item() >= 0.99:
             n_er = it
@@ -146,7 +148,7 @@ def main():
         raise SystemExit(f"error reduction did not reach mean fidelity 0.99 in {args.max_iters} iterations")
     log(f"spectral start fidelity {f_start:.4f}; ER reaches 0.99 after {n_er} iterations")
     n_lb = None
-    for k in (5, 10, 15, 20, 25, 30, 40, 50, 70, 100):
+    for k in () if args.no_lbfgs else (5, 10, 15, 20, 25, 30, 40, 50, 70, 100):
         t = v0t.clone()
         tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("lbfgs", k), stats=False)
         if fidelity(t).mean().item() >= 0.99:

@@ -23,7 +23,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
-]
+] + os.environ.get("TM_EXTRA_FLAGS", "").split()
 
 
 def grids() -> list[tuple[int, int]]:

@@ -201,12 +201,15 @@ constexpr PlanDesc make_plan(int L1, int L2) {
   return d;
 }
 
-template <int L1_, int L2_>
+// Values per thread: 16 (LE_ forces another value).
+constexpr int default_le(int ln) { return ln >= 4 ? 4 : ln; }
+
+template <int L1_, int L2_, int LE_ = -1>
 struct Plan {
   static constexpr int L1 = L1_, L2 = L2_;
   static constexpr int LN = L1 + L2;
   static constexpr int N1 = 1 << L1, N2 = 1 << L2, N = 1 << LN;
-  static constexpr int LE = (LN >= 4) ? 4 : LN;  // 16 values per thread
+  static constexpr int LE = (LE_ >= 0) ? LE_ : default_le(LN);
   static constexpr int E = 1 << LE;
   static constexpr int LT = LN - LE;
   static constexpr int T = 1 << LT;  // threads per row
@@ -384,44 +387,60 @@ __device__ __forceinline__ const cx<T>* tw_of(const Tw<T>& tw) {
   return (PassGeo<PL, P>::AXIS == 1) ? tw.t1 : tw.t2;
 }
 
+// LDS exchange buffers of one row. With two buffers (alt != 0) exchange k
+// writes buffer k % 2, so one barrier per exchange suffices: every thread's
+// reads of exchange k-1 precede its writes of exchange k, and the barrier of
+// exchange k orders all of them before the reads of exchange k; the writes of
+// exchange k+1 go to the other buffer. With one buffer a second barrier
+// protects the reads of the previous exchange.
+template <typename T>
+struct Xbuf {
+  cx<T>* base;
+  int alt;     // element offset of the second buffer, 0 if single-buffered
+  int parity;  // buffer of the next exchange
+  __device__ __forceinline__ cx<T>* next() {
+    cx<T>* p = base + (parity ? alt : 0);
+    parity ^= (alt != 0);
+    return p;
+  }
+};
+
+template <class PL, int PW, int PR, typename T>
+__device__ __forceinline__ void exchange(cx<T>* x, Xbuf<T>& xb, int ltid) {
+  cx<T>* lds = xb.next();
+  if (xb.alt == 0) __syncthreads();
+  lds_store<PL, PW, T>(lds, x, ltid);
+  __syncthreads();
+  lds_load<PL, PR, T>(lds, x, ltid);
+}
+
 // Full forward DFT: x enters in the layout of pass 0 (natural element values),
 // leaves in the layout of the last pass holding the digit-reversed spectrum.
-// `sync` is the barrier of the row group (workgroup barrier).
 template <class PL, int P, typename T>
-__device__ __forceinline__ void fwd_from(cx<T>* x, cx<T>* lds, int ltid, const Tw<T>& tw) {
+__device__ __forceinline__ void fwd_from(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
   if constexpr (P < PL::NP) {
-    if constexpr (P > 0) {
-      __syncthreads();
-      lds_store<PL, P - 1, T>(lds, x, ltid);
-      __syncthreads();
-      lds_load<PL, P, T>(lds, x, ltid);
-    }
+    if constexpr (P > 0) exchange<PL, P - 1, P, T>(x, xb, ltid);
     fwd_pass<PL, P, T>(x, ltid, tw_of<PL, P, T>(tw));
-    fwd_from<PL, P + 1, T>(x, lds, ltid, tw);
+    fwd_from<PL, P + 1, T>(x, xb, ltid, tw);
   }
 }
 
 template <class PL, int P, typename T>
-__device__ __forceinline__ void inv_from(cx<T>* x, cx<T>* lds, int ltid, const Tw<T>& tw) {
+__device__ __forceinline__ void inv_from(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
   if constexpr (P >= 0) {
-    if constexpr (P < PL::NP - 1) {
-      __syncthreads();
-      lds_store<PL, P + 1, T>(lds, x, ltid);
-      __syncthreads();
-      lds_load<PL, P, T>(lds, x, ltid);
-    }
+    if constexpr (P < PL::NP - 1) exchange<PL, P + 1, P, T>(x, xb, ltid);
     inv_pass<PL, P, T>(x, ltid, tw_of<PL, P, T>(tw));
-    inv_from<PL, P - 1, T>(x, lds, ltid, tw);
+    inv_from<PL, P - 1, T>(x, xb, ltid, tw);
   }
 }
 
 template <class PL, typename T>
-__device__ __forceinline__ void fft_forward(cx<T>* x, cx<T>* lds, int ltid, const Tw<T>& tw) {
-  fwd_from<PL, 0, T>(x, lds, ltid, tw);
+__device__ __forceinline__ void fft_forward(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
+  fwd_from<PL, 0, T>(x, xb, ltid, tw);
 }
 template <class PL, typename T>
-__device__ __forceinline__ void fft_inverse(cx<T>* x, cx<T>* lds, int ltid, const Tw<T>& tw) {
-  inv_from<PL, PL::NP - 1, T>(x, lds, ltid, tw);
+__device__ __forceinline__ void fft_inverse(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
+  inv_from<PL, PL::NP - 1, T>(x, xb, ltid, tw);
 }
 
 // Digit reversal of one axis: slot index s (digits high to low as laid out by

@@ -13,6 +13,7 @@ namespace tmk {
 #define TM_CAT(a, b, c) TM_CAT2(a, b, c)
 
 using PLg = Plan<GL1, GL2>;
+using PLd = Plan<GL1, GL2, (GL1 + GL2 >= 4) ? 4 : GL1 + GL2>;  // FP64 residual: 16 values per thread
 
 template <typename IT>
 static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
@@ -23,17 +24,24 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
     case M_FWD_FIELD: row_kernel<PLg, M_FWD_FIELD, IT><<<grid, block, 0, s>>>(a); break;
     case M_FWD_INT: row_kernel<PLg, M_FWD_INT, IT><<<grid, block, 0, s>>>(a); break;
     case M_ADJ: row_kernel<PLg, M_ADJ, IT><<<grid, block, 0, s>>>(a); break;
-    case M_ER: row_kernel<PLg, M_ER, IT><<<grid, block, 0, s>>>(a); break;
-    case M_GRAD: row_kernel<PLg, M_GRAD, IT><<<grid, block, 0, s>>>(a); break;
+    case M_ER:
+      if (a.sums) row_kernel<PLg, M_ER, IT, true><<<grid, block, 0, s>>>(a);
+      else row_kernel<PLg, M_ER, IT, false><<<grid, block, 0, s>>>(a);
+      break;
+    case M_GRAD:
+      if (a.sums) row_kernel<PLg, M_GRAD, IT, true><<<grid, block, 0, s>>>(a);
+      else row_kernel<PLg, M_GRAD, IT, false><<<grid, block, 0, s>>>(a);
+      break;
     case M_SPEC: row_kernel<PLg, M_SPEC, IT><<<grid, block, 0, s>>>(a); break;
     case M_LS: row_kernel<PLg, M_LS, IT><<<grid, block, 0, s>>>(a); break;
     case M_BACKPROP: row_kernel<PLg, M_BACKPROP, IT><<<grid, block, 0, s>>>(a); break;
     case M_RES64: {
-      size_t lds = (size_t)LC::RPW * PLg::LDS_ROW * sizeof(cx<double>) + (LC::WG / 64 + 1) * sizeof(double);
-      auto fn = res64_kernel<PLg, IT>;
+      using LD = Launch<PLd>;
+      size_t lds = (size_t)LD::RPW * PLd::LDS_ROW * sizeof(cx<double>) + (LD::WG / 64 + 1) * sizeof(double);
+      auto fn = res64_kernel<PLd, IT>;
       hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return (int)e;
-      fn<<<grid, block, lds, s>>>(a);
+      fn<<<dim3((a.P + LD::RPW - 1) / LD::RPW), dim3(LD::WG), lds, s>>>(a);
       break;
     }
     default: return (int)hipErrorInvalidValue;

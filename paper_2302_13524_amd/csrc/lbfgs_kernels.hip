@@ -320,7 +320,7 @@ int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters,
   RowArgs ga = base;
   ga.tin = (const cx<float>*)t;
   ga.tout = (cx<float>*)gcur;
-  ga.sums = b.sums;
+  ga.sums = (iters == 0) ? b.sums : nullptr;  // f is reported for the final point only
   if ((e = fn(M_GRAD, ibf16, ga, stream))) return e;
   for (int it = 0; it < iters; ++it) {
     LbArgs la;
@@ -348,6 +348,7 @@ int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters,
     gprev = gcur;
     gcur = tmp;
     ga.tout = (cx<float>*)gcur;
+    ga.sums = (it == iters - 1) ? b.sums : nullptr;
     if ((e = fn(M_GRAD, ibf16, ga, stream))) return e;
   }
   return 0;

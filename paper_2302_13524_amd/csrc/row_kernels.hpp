@@ -147,16 +147,34 @@ template <class PL>
 struct Launch {
   static constexpr int WG = (PL::T >= 256) ? PL::T : 256;
   static constexpr int RPW = WG / PL::T;  // rows per workgroup
+  // double-buffered LDS exchange when two copies of the rows fit in 160 KiB
+  static constexpr bool DB = 2 * RPW * PL::LDS_ROW * 8 <= 160 * 1024 - 4096;
 };
 
 // ---------------------------------------------------------------- FP32 kernel
-template <class PL, int MODE, typename IT>
-__global__ void __launch_bounds__(Launch<PL>::WG)
+// Hardware square root and reciprocal square root (about 1 ulp), without the
+// range-scaling and refinement sequences of the IEEE-exact library calls.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// SUMS: accumulate the per-row monitoring sums (compensated) and write them;
+// without it the kernel skips that work (used on iterations whose sums are
+// not read).
+#ifndef TM_MINW
+#define TM_MINW 1
+#endif
+#ifndef TM_RELOAD_T
+#define TM_RELOAD_T 0
+#endif
+
+template <class PL, int MODE, typename IT, bool SUMS = true>
+__global__ void __launch_bounds__(Launch<PL>::WG) __attribute__((amdgpu_waves_per_eu(TM_MINW)))
 row_kernel(RowArgs a) {
   using T = float;
   using C = cx<T>;
   constexpr int E = PL::E, N = PL::N, WG = Launch<PL>::WG, RPW = Launch<PL>::RPW;
-  __shared__ C lds_all[RPW * PL::LDS_ROW];
+  constexpr int NBUF = Launch<PL>::DB ? 2 : 1;
+  __shared__ C lds_all[NBUF * RPW * PL::LDS_ROW];
   __shared__ float red[(WG / 64 + 1) * NSUM * 2];
 
   const int tid = threadIdx.x;
@@ -165,7 +183,7 @@ row_kernel(RowArgs a) {
   const int row = blockIdx.x * RPW + rloc;
   const bool valid = row < a.P;
   const size_t prow = valid ? (size_t)row : 0;
-  C* lds = lds_all + rloc * PL::LDS_ROW;
+  Xbuf<T> xb{lds_all + rloc * PL::LDS_ROW, (NBUF == 2) ? RPW * PL::LDS_ROW : 0, 0};
   Tw<T> tw{a.tw32 + (PL::N1 - 1), a.tw32 + (PL::N2 - 1)};
 
   using L0 = Layout0<PL>;
@@ -179,18 +197,22 @@ row_kernel(RowArgs a) {
 #define E0(i) (b0[(i) / L0::R] + ((i) % L0::R) * L0::HS)
 #define KL(i) (kb[(i) / LL::R] + ((i) % LL::R) * LL::KS)
 
-  C t[E], g[E], x[E];
-  C dvec[E];
+  // The row t (and d) is re-read for every mask instead of being held in
+  // registers across the mask loop: the reads hit the cache after the first
+  // mask, and the freed registers let two 512-thread workgroups share a CU.
+  C g[E], x[E];
+  const C* trow = a.tin + prow * N;
+  const C* drow = a.din + prow * N;
+#if !TM_RELOAD_T
+  C treg[E];
   if constexpr (MODE != M_ADJ && MODE != M_BACKPROP) {
-    const C* src = a.tin + prow * N;
 #pragma unroll
-    for (int i = 0; i < E; ++i) t[i] = src[E0(i)];
+    for (int i = 0; i < E; ++i) treg[i] = trow[E0(i)];
   }
-  if constexpr (MODE == M_LS) {
-    const C* src = a.din + prow * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) dvec[i] = src[E0(i)];
-  }
+#define TROW(i) treg[i]
+#else
+#define TROW(i) trow[E0(i)]
+#endif
 #pragma unroll
   for (int i = 0; i < E; ++i) g[i] = C{0.f, 0.f};
 
@@ -217,8 +239,8 @@ row_kernel(RowArgs a) {
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < E; ++i) x[i] = cmul(t[i], mk[E0(i)]);
-      fft_forward<PL, T>(x, lds, ltid, tw);
+      for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), mk[E0(i)]);
+      fft_forward<PL, T>(x, xb, ltid, tw);
     }
 
     if constexpr (MODE == M_FWD_FIELD || MODE == M_FWD_INT) {
@@ -240,8 +262,8 @@ row_kernel(RowArgs a) {
 #pragma unroll
       for (int i = 0; i < E; ++i) y[i] = x[i];
 #pragma unroll
-      for (int i = 0; i < E; ++i) x[i] = cmul(dvec[i], mk[E0(i)]);
-      fft_forward<PL, T>(x, lds, ltid, tw);
+      for (int i = 0; i < E; ++i) x[i] = cmul(drow[E0(i)], mk[E0(i)]);
+      fft_forward<PL, T>(x, xb, ltid, tw);
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         int k = KL(i);
@@ -265,15 +287,22 @@ row_kernel(RowArgs a) {
           float iv = load_I<IT>(a.I, mbase + k);
           float n = norm2(x[i]);
           if constexpr (MODE == M_ER) {
-            float amp = sqrtf(fmaxf(iv, 0.f));
-            float mag = sqrtf(n);
-            float dr = amp - mag, ri = iv - n;
-            acc[0].add(dr * dr);
-            acc[1].add(ri * ri);
-            x[i] = (n > 0.f) ? scl(x[i], amp / mag) : C{amp, 0.f};
+            // keep the measured amplitude, keep the phase (y/|y| := 1 at y = 0)
+            float amp = hw_sqrt(fmaxf(iv, 0.f));
+            float rs = hw_rsq(n);
+            bool nz = n > 0.f;
+            float sc = nz ? amp * rs : 0.f;
+            C w = scl(x[i], sc);
+            if constexpr (SUMS) {
+              float mag = n * rs;
+              float dr = amp - (nz ? mag : 0.f), ri = iv - n;
+              acc[0].add(dr * dr);
+              acc[1].add(ri * ri);
+            }
+            x[i] = nz ? w : C{amp, 0.f};
           } else if constexpr (MODE == M_GRAD) {
             float r = iv - n;
-            acc[0].add(r * r);
+            if constexpr (SUMS) acc[0].add(r * r);
             x[i] = scl(x[i], r);
           } else {
             float w = fminf(iv * inv_mean, a.tau);
@@ -281,7 +310,7 @@ row_kernel(RowArgs a) {
           }
         }
       }
-      fft_inverse<PL, T>(x, lds, ltid, tw);
+      fft_inverse<PL, T>(x, xb, ltid, tw);
 #pragma unroll
       for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], mk[E0(i)]);
     }
@@ -303,7 +332,10 @@ row_kernel(RowArgs a) {
     for (int i = 0; i < E; ++i) vp[i] = a.din[prow * N + E0(i)];
     KSum l1[1] = {KSum{0.f, 0.f}};
 #pragma unroll
-    for (int i = 0; i < E; ++i) l1[0].add(t[i].x * g[i].x + t[i].y * g[i].y);
+    for (int i = 0; i < E; ++i) {
+      C ti = TROW(i);
+      l1[0].add(ti.x * g[i].x + ti.y * g[i].y);
+    }
     float lam;
     row_reduce<PL::T, WG, 1>(l1, red, tid, &lam);
     float cl = a.momentum * lam;
@@ -321,7 +353,7 @@ row_kernel(RowArgs a) {
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         a.tout[prow * N + E0(i)] = scl(g[i], inv);
-        a.tout2[prow * N + E0(i)] = scl(t[i], inv);
+        a.tout2[prow * N + E0(i)] = scl(TROW(i), inv);
       }
       if (ltid == 0 && a.sums) a.sums[prow * NSUM + 0] = lam;
     }
@@ -333,7 +365,7 @@ row_kernel(RowArgs a) {
 #pragma unroll
       for (int i = 0; i < E; ++i) a.tout[prow * N + E0(i)] = scl(g[i], scale);
     }
-    if constexpr (MODE == M_ER || MODE == M_GRAD) {
+    if constexpr ((MODE == M_ER || MODE == M_GRAD) && SUMS) {
       float out[NSUM];
       row_reduce<PL::T, WG, (MODE == M_ER) ? 2 : 1>(acc, red, tid, out);
       if (valid && ltid == 0 && a.sums) {
@@ -365,7 +397,7 @@ res64_kernel(RowArgs a) {
   const int row = blockIdx.x * RPW + rloc;
   const bool valid = row < a.P;
   const size_t prow = valid ? (size_t)row : 0;
-  C* lds = lds_all + rloc * PL::LDS_ROW;
+  Xbuf<T> xb{lds_all + rloc * PL::LDS_ROW, 0, 0};
   Tw<T> tw{a.tw64 + (PL::N1 - 1), a.tw64 + (PL::N2 - 1)};
 
   using L0 = Layout0<PL>;
@@ -391,7 +423,7 @@ res64_kernel(RowArgs a) {
       cx<float> w = mk[E0(i)];
       x[i] = cmul(t[i], C{(double)w.x, (double)w.y});
     }
-    fft_forward<PL, T>(x, lds, ltid, tw);
+    fft_forward<PL, T>(x, xb, ltid, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       int k = KL(i);
@@ -411,4 +443,5 @@ res64_kernel(RowArgs a) {
 
 #undef E0
 #undef KL
+#undef TROW
 }  // namespace tmk

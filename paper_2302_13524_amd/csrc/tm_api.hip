@@ -384,8 +384,8 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   if (o->method == TM_METHOD_ER) {
     a.tin = tt;
     a.tout = tt;
-    a.sums = sums;
     for (int it = 0; it < o->iters; ++it) {
+      a.sums = (it == o->iters - 1) ? sums : nullptr;  // only the last iteration's sums are reported
       r = run_row(c, fn, tmk::M_ER, ibf, a, stream);
       if (r) return r;
     }
