@@ -196,6 +196,57 @@ int tm_defocus_forward(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pi
                        const tm_c32 *tm, const tm_c32 *theta, const tm_optics *optics,
                        const double *phi, float *I_out, void *stream);
 
+/* ---- learned start (not in the paper; its start is Eq. backpropagation) --- */
+
+/* Network x = I_p / mean(I_p) (n_in = K N features) -> Linear(n_in, hidden)
+ * -> GELU -> Linear(hidden, hidden) -> GELU -> Linear(hidden, n_out = 2N),
+ * read as u = o[:N] + j o[N:]; the start row is u rescaled to
+ * ||t||^2 = sum(I_p) / (K N) (Parseval for A^H A = K N I). GEMMs run on
+ * MFMA with BF16 operands and FP32 accumulation. */
+typedef struct {
+  int32_t n_in, hidden, n_out;
+} tm_mlp_dims;
+
+/* Parameters (all device pointers, caller-owned). W[l] is FP32
+ * [fan_in][fan_out] row-major; Wh[l] its BF16 copy, written by the library
+ * (tm_mlp_sync_bf16, tm_mlp_train_step); b[l] FP32 biases; mW/vW/mb/vb the
+ * Adam moments (FP32, same shapes; training only, zero-initialised by the
+ * caller). */
+typedef struct {
+  float *W[3];
+  uint16_t *Wh[3];
+  float *b[3];
+  float *mW[3], *vW[3], *mb[3], *vb[3];
+} tm_mlp_params;
+
+/* Write the BF16 weight copies Wh from the FP32 masters W. */
+int tm_mlp_sync_bf16(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, void *stream);
+
+/* Learned start rows t0 [P][N] from intensities I [P][K][N] (float),
+ * n_in = K N and n_out = 2 N. */
+int tm_mlp_start(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, int32_t K, int32_t N,
+                 const float *I, int32_t P, tm_c32 *t0, void *stream);
+
+/* Gradients of the mean phase-invariant loss over a batch of B rows
+ * (I [B][K][N] float, targets t [B][N]); dW[l], db[l] FP32 device buffers
+ * shaped like W[l], b[l]; loss [B] per-row loss (device, may be NULL). */
+int tm_mlp_gradients(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, int32_t K, int32_t N,
+                     const float *I, const tm_c32 *t, int32_t B, float *const dW[3], float *const db[3],
+                     float *loss, void *stream);
+
+/* One training step: gradients as above, then Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected with step number `step` >= 1) on the FP32
+ * masters, and the BF16 copies refreshed. */
+int tm_mlp_train_step(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, int32_t K, int32_t N,
+                      const float *I, const tm_c32 *t, int32_t B, float lr, int32_t step, float *loss,
+                      void *stream);
+
+/* C [M][N] (float) = op(A) op(B) with BF16 A and B: A is [M][K] (ta = 0) or
+ * [K][M] (ta = 1), B is [K][N] (tb = 0) or [N][K] (tb = 1). The MFMA tile
+ * used by the network. */
+int tm_gemm_bf16(tm_ctx *ctx, int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t ta,
+                 const uint16_t *B, int32_t tb, float *C, void *stream);
+
 /* ---- instrumentation ------------------------------------------------------ */
 
 /* Enable (1) or disable (0) per-launch HIP-event timing of the fused row

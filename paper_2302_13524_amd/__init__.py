@@ -29,6 +29,7 @@ EXPORTED = (
     "tm_create", "tm_destroy", "tm_last_error", "tm_grid_supported", "tm_forward", "tm_adjoint",
     "tm_gradient", "tm_residual_f64", "tm_retrieve", "tm_phase_offset_correct", "tm_phase_objective",
     "tm_defocus_forward", "tm_profile_enable", "tm_profile_query",
+    "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -56,6 +57,17 @@ class tm_optics(ctypes.Structure):
 
 class tm_phase_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("m", ctypes.c_int32)]
+
+
+class tm_mlp_dims(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("hidden", ctypes.c_int32), ("n_out", ctypes.c_int32)]
+
+
+_P3 = ctypes.c_void_p * 3
+
+
+class tm_mlp_params(ctypes.Structure):
+    _fields_ = [("W", _P3), ("Wh", _P3), ("b", _P3), ("mW", _P3), ("vW", _P3), ("mb", _P3), ("vb", _P3)]
 
 
 ROW_STATS_BYTES = 24
@@ -95,6 +107,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_defocus_forward.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp,
                                        ctypes.POINTER(tm_optics), vp, vp, vp]
     lib.tm_profile_enable.argtypes = [vp, ctypes.c_int]
+    MD, MP = ctypes.POINTER(tm_mlp_dims), ctypes.POINTER(tm_mlp_params)
+    lib.tm_mlp_sync_bf16.argtypes = [vp, MD, MP, vp]
+    lib.tm_mlp_start.argtypes = [vp, MD, MP, i32, i32, vp, i32, vp, vp]
+    lib.tm_mlp_gradients.argtypes = [vp, MD, MP, i32, i32, vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     vp, vp]
+    lib.tm_mlp_train_step.argtypes = [vp, MD, MP, i32, i32, vp, vp, i32, ctypes.c_float, i32, vp, vp]
+    lib.tm_gemm_bf16.argtypes = [vp, i32, i32, i32, vp, i32, vp, i32, vp, vp]
     lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
@@ -300,3 +319,75 @@ def tm_profile_query(ctx: Context, mode: int):
     n = ctypes.c_int64(0)
     ctx.check(ctx.lib.tm_profile_query(ctx.h, int(mode), ctypes.byref(ms), ctypes.byref(n)), "tm_profile_query")
     return ms.value, n.value
+
+
+class MLP:
+    """Learned-start network parameters on the GPU (FP32 masters, BF16 copies,
+    Adam moments); shapes W[l]: [fan_in][fan_out]."""
+
+    def __init__(self, n_in: int, hidden: int, n_out: int, device="cuda:0", weights=None, seed: int = 0):
+        self.dims = tm_mlp_dims(n_in, hidden, n_out)
+        shapes = [(n_in, hidden), (hidden, hidden), (hidden, n_out)]
+        if weights is None:
+            g = torch.Generator().manual_seed(seed)
+            weights = []
+            for fi, fo in shapes:
+                weights.append((torch.randn((fi, fo), generator=g) / fi ** 0.5, torch.zeros(fo)))
+        self.W = [torch.as_tensor(w, dtype=torch.float32).contiguous().to(device) for w, _ in weights]
+        self.b = [torch.as_tensor(b, dtype=torch.float32).contiguous().to(device) for _, b in weights]
+        self.Wh = [torch.empty(w.shape, dtype=torch.bfloat16, device=device) for w in self.W]
+        self.mW = [torch.zeros_like(w) for w in self.W]
+        self.vW = [torch.zeros_like(w) for w in self.W]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.step = 0
+        P3 = lambda xs: _P3(*[x.data_ptr() for x in xs])
+        self.p = tm_mlp_params(P3(self.W), P3(self.Wh), P3(self.b), P3(self.mW), P3(self.vW), P3(self.mb),
+                               P3(self.vb))
+
+    def sync(self, ctx: Context):
+        ctx.check(ctx.lib.tm_mlp_sync_bf16(ctx.h, ctypes.byref(self.dims), ctypes.byref(self.p),
+                                           _stream(self.W[0].device)), "tm_mlp_sync_bf16")
+
+
+def tm_mlp_start(ctx: Context, net: MLP, I, K: int, N: int):
+    """Learned start rows [P, N] complex64 from intensities [P, K, N] float32."""
+    P = I.shape[0]
+    t0 = torch.empty((P, N), dtype=torch.complex64, device=I.device)
+    rc = ctx.lib.tm_mlp_start(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), K, N, _ptr(I), P, _ptr(t0),
+                              _stream(I.device))
+    ctx.check(rc, "tm_mlp_start")
+    return t0
+
+
+def tm_mlp_gradients(ctx: Context, net: MLP, I, t, K: int, N: int):
+    """(dW list, db list, per-row loss) of the mean loss over the batch."""
+    B = I.shape[0]
+    dW = [torch.empty_like(w) for w in net.W]
+    db = [torch.empty_like(b) for b in net.b]
+    loss = torch.empty((B,), dtype=torch.float32, device=I.device)
+    pw = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in dW])
+    pb = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in db])
+    rc = ctx.lib.tm_mlp_gradients(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), K, N, _ptr(I), _ptr(t), B,
+                                  pw, pb, _ptr(loss), _stream(I.device))
+    ctx.check(rc, "tm_mlp_gradients")
+    return dW, db, loss
+
+
+def tm_mlp_train_step(ctx: Context, net: MLP, I, t, K: int, N: int, lr: float, loss=None):
+    B = I.shape[0]
+    net.step += 1
+    rc = ctx.lib.tm_mlp_train_step(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), K, N, _ptr(I), _ptr(t), B,
+                                   float(lr), net.step, _ptr(loss), _stream(I.device))
+    ctx.check(rc, "tm_mlp_train_step")
+
+
+def tm_gemm_bf16(ctx: Context, A, B, ta=False, tb=False):
+    """C = op(A) op(B) in FP32 from BF16 A, B."""
+    M = A.shape[1] if ta else A.shape[0]
+    K = A.shape[0] if ta else A.shape[1]
+    N = B.shape[0] if tb else B.shape[1]
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    rc = ctx.lib.tm_gemm_bf16(ctx.h, M, N, K, _ptr(A), int(ta), _ptr(B), int(tb), _ptr(C), _stream(A.device))
+    ctx.check(rc, "tm_gemm_bf16")
+    return C

@@ -16,6 +16,7 @@
 #include "aux.hpp"
 #include "grids.hpp"
 #include "lbfgs.hpp"
+#include "mlp.hpp"
 #include "phase.hpp"
 #include "row_kernels.hpp"
 
@@ -573,5 +574,151 @@ extern "C" int tm_profile_query(tm_ctx* c, int mode, double* ms, int64_t* launch
   prof_drain(c);
   *ms = c->acc_ms[mode];
   *launches = c->acc_n[mode];
+  return TM_OK;
+}
+
+// ---------------------------------------------------------------- learned start
+static int mlp_check(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int K, int N, bool train) {
+  if (!md || !p) return fail(c, TM_EINVAL, "dims/params pointer is NULL");
+  if (md->n_in < 1 || md->hidden < 1 || md->n_out < 2) return fail(c, TM_EINVAL, "network sizes must be positive");
+  if (K >= 1 && N >= 1) {
+    if (md->n_in != K * N) return fail(c, TM_EINVAL, "n_in=%d must equal K*N=%d", md->n_in, K * N);
+    if (md->n_out != 2 * N) return fail(c, TM_EINVAL, "n_out=%d must equal 2N=%d", md->n_out, 2 * N);
+  }
+  for (int l = 0; l < 3; ++l) {
+    if (!p->W[l] || !p->Wh[l] || !p->b[l]) return fail(c, TM_EINVAL, "layer %d weights missing", l);
+    if (train && (!p->mW[l] || !p->vW[l] || !p->mb[l] || !p->vb[l]))
+      return fail(c, TM_EINVAL, "layer %d Adam moments missing", l);
+  }
+  return TM_OK;
+}
+
+static tmk::MlpParams mlp_params(const tm_mlp_params* p) {
+  tmk::MlpParams q;
+  for (int l = 0; l < 3; ++l) {
+    q.W[l] = p->W[l];
+    q.Wh[l] = p->Wh[l];
+    q.b[l] = p->b[l];
+  }
+  return q;
+}
+
+static int mlp_run(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int K, int N, const float* I,
+                   int B, tmk::MlpWork& w, void* stream) {
+  tmk::MlpShape sh{md->n_in, md->hidden, md->n_out};
+  void* base = ws_get(c, WS_PH_BASE + 10, tmk::mlp_work_bytes(sh, B));
+  if (!base) return fail(c, TM_ENOMEM, "network workspace");
+  tmk::mlp_work_carve(base, sh, B, &w);
+  tmk::MlpParams q = mlp_params(p);
+  int e = tmk::mlp_forward(sh, q, I, B, K * N, w, stream);
+  if (e) return hipfail(c, e, "network forward");
+  return TM_OK;
+}
+
+extern "C" int tm_mlp_sync_bf16(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = mlp_check(c, md, p, 0, 0, false);
+  if (r) return r;
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::MlpShape sh{md->n_in, md->hidden, md->n_out};
+  tmk::MlpParams q = mlp_params(p);
+  int e = tmk::mlp_weights_to_bf16(sh, q, stream);
+  if (e) return hipfail(c, e, "bf16 copy");
+  return TM_OK;
+}
+
+extern "C" int tm_mlp_start(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int32_t K, int32_t N,
+                            const float* I, int32_t P, tm_c32* t0, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = mlp_check(c, md, p, K, N, false);
+  if (r) return r;
+  if (K < 1 || N < 1 || P < 0) return fail(c, TM_EINVAL, "K, N >= 1 and P >= 0");
+  if (P == 0) return TM_OK;
+  if (!I || !t0) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::MlpWork w;
+  if ((r = mlp_run(c, md, p, K, N, I, P, w, stream))) return r;
+  int e = tmk::mlp_start(w, P, N, t0, stream);
+  if (e) return hipfail(c, e, "network start");
+  return TM_OK;
+}
+
+static int mlp_grads(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int K, int N, const float* I,
+                     const tm_c32* t, int B, tmk::MlpGrads& G, float* loss, void* stream) {
+  tmk::MlpWork w;
+  int r = mlp_run(c, md, p, K, N, I, B, w, stream);
+  if (r) return r;
+  tmk::MlpShape sh{md->n_in, md->hidden, md->n_out};
+  tmk::MlpParams q = mlp_params(p);
+  int e = tmk::mlp_backward(sh, q, t, B, w, G, stream);
+  if (e) return hipfail(c, e, "network backward");
+  if (loss) HIPCHK(c, hipMemcpyAsync(loss, w.loss, (size_t)B * sizeof(float), hipMemcpyDeviceToDevice,
+                                     (hipStream_t)stream));
+  return TM_OK;
+}
+
+extern "C" int tm_mlp_gradients(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int32_t K, int32_t N,
+                                const float* I, const tm_c32* t, int32_t B, float* const dW[3],
+                                float* const db[3], float* loss, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = mlp_check(c, md, p, K, N, false);
+  if (r) return r;
+  if (B < 1 || !I || !t || !dW || !db) return fail(c, TM_EINVAL, "B >= 1 and non-null arguments");
+  for (int l = 0; l < 3; ++l)
+    if (!dW[l] || !db[l]) return fail(c, TM_EINVAL, "gradient buffer %d is NULL", l);
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::MlpGrads G;
+  for (int l = 0; l < 3; ++l) {
+    G.dW[l] = dW[l];
+    G.db[l] = db[l];
+  }
+  return mlp_grads(c, md, p, K, N, I, t, B, G, loss, stream);
+}
+
+extern "C" int tm_mlp_train_step(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int32_t K, int32_t N,
+                                 const float* I, const tm_c32* t, int32_t B, float lr, int32_t step, float* loss,
+                                 void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = mlp_check(c, md, p, K, N, true);
+  if (r) return r;
+  if (B < 1 || !I || !t || step < 1 || !(lr >= 0.f)) return fail(c, TM_EINVAL, "B >= 1, step >= 1, lr >= 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  size_t nw[3] = {(size_t)md->n_in * md->hidden, (size_t)md->hidden * md->hidden, (size_t)md->hidden * md->n_out};
+  size_t nb[3] = {(size_t)md->hidden, (size_t)md->hidden, (size_t)md->n_out};
+  size_t tot = 0;
+  for (int l = 0; l < 3; ++l) tot += ((nw[l] + nb[l]) * 4 + 512);
+  char* gb = (char*)ws_get(c, WS_PH_BASE + 11, tot);
+  if (!gb) return fail(c, TM_ENOMEM, "gradient workspace");
+  tmk::MlpGrads G;
+  for (int l = 0; l < 3; ++l) {
+    G.dW[l] = (float*)gb;
+    gb += (nw[l] * 4 + 255) / 256 * 256;
+    G.db[l] = (float*)gb;
+    gb += (nb[l] * 4 + 255) / 256 * 256;
+  }
+  if ((r = mlp_grads(c, md, p, K, N, I, t, B, G, loss, stream))) return r;
+  tmk::MlpShape sh{md->n_in, md->hidden, md->n_out};
+  tmk::MlpParams q = mlp_params(p);
+  tmk::MlpAdam A;
+  for (int l = 0; l < 3; ++l) {
+    A.mW[l] = p->mW[l];
+    A.vW[l] = p->vW[l];
+    A.mb[l] = p->mb[l];
+    A.vb[l] = p->vb[l];
+  }
+  int e = tmk::mlp_adam(sh, q, G, A, lr, step, stream);
+  if (e) return hipfail(c, e, "Adam");
+  return TM_OK;
+}
+
+extern "C" int tm_gemm_bf16(tm_ctx* c, int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t ta,
+                            const uint16_t* B, int32_t tb, float* C, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (M < 0 || N < 0 || K < 0) return fail(c, TM_EINVAL, "negative size");
+  if (M == 0 || N == 0) return TM_OK;
+  if (!A || !B || !C) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  int e = tmk::gemm_bf16(M, N, K, A, ta != 0, B, tb != 0, C, stream);
+  if (e) return hipfail(c, e, "gemm");
   return TM_OK;
 }
