@@ -143,6 +143,48 @@ int tm_retrieve(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I,
                 tm_c32 *t, const tm_retrieve_opts *opts, tm_row_stats *stats,
                 void *stream);
 
+/* ---- uneven batches of TMs ----------------------------------------------- */
+
+/* One retrieval problem of a batch. d.n1 x d.n2 must be one of the grids
+ * compiled for batches (32x32, 64x32, 64x64, 128x64); each problem has its
+ * own masks [K][N], intensities I [P][K][N] (type opts->I_dtype), in/out
+ * rows t [P][N] and optional stats [P]. */
+typedef struct {
+  tm_dims d;
+  const tm_c32 *masks;
+  const void *I;
+  tm_c32 *t;
+  tm_row_stats *stats;
+} tm_problem;
+
+typedef struct tm_batch tm_batch;
+
+/* Plan the retrieval of n problems with the same options (method ER;
+ * start GIVEN, BACKPROP or SPECTRAL). Every iteration is one persistent
+ * launch whose work items are (problem, row tile): 1 row of 8192 modes, 2 of
+ * 4096, 4 of 2048 or 8 of 1024, each run with its grid's FFT specialisation
+ * and the digit order chosen by tm_set_variant. With use_graph = 1 the whole
+ * sequence (start, iterations, FP64 residuals, stats) is captured once into a
+ * HIP graph. The plan keeps the problem pointers: tm_batch_run reuses them.
+ * Allocates its workspace here (not in tm_batch_run). */
+int tm_batch_create(tm_ctx *ctx, int32_t n, const tm_problem *probs, const tm_retrieve_opts *opts,
+                    int32_t use_graph, tm_batch **out);
+/* Run the planned sequence on `stream` (asynchronous). */
+int tm_batch_run(tm_batch *b, void *stream);
+/* Release the plan (synchronises the device). */
+int tm_batch_destroy(tm_batch *b);
+
+/* ---- autotuning ------------------------------------------------------------ */
+
+/* Average device time (microseconds) of one error-reduction launch over P
+ * rows of an n1 x n2 grid with K masks, FFT digit-order variant `variant`
+ * (0: larger radices first, 1: smaller first), on synthetic data in library
+ * workspace. */
+int tm_tune_time(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t K, int32_t P, int32_t I_dtype,
+                 int32_t variant, int32_t reps, double *us);
+/* Use digit-order variant `variant` for the grid n1 x n2 in this context. */
+int tm_set_variant(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t variant);
+
 /* ---- phase-offset correction (Sec. 2.3) -------------------------------- */
 
 typedef struct {

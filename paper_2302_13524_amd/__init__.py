@@ -30,6 +30,7 @@ EXPORTED = (
     "tm_gradient", "tm_residual_f64", "tm_retrieve", "tm_phase_offset_correct", "tm_phase_objective",
     "tm_defocus_forward", "tm_profile_enable", "tm_profile_query",
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
+    "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -68,6 +69,11 @@ _P3 = ctypes.c_void_p * 3
 
 class tm_mlp_params(ctypes.Structure):
     _fields_ = [("W", _P3), ("Wh", _P3), ("b", _P3), ("mW", _P3), ("vW", _P3), ("mb", _P3), ("vb", _P3)]
+
+
+class tm_problem(ctypes.Structure):
+    _fields_ = [("d", tm_dims), ("masks", ctypes.c_void_p), ("I", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
 
 
 ROW_STATS_BYTES = 24
@@ -114,6 +120,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                      vp, vp]
     lib.tm_mlp_train_step.argtypes = [vp, MD, MP, i32, i32, vp, vp, i32, ctypes.c_float, i32, vp, vp]
     lib.tm_gemm_bf16.argtypes = [vp, i32, i32, i32, vp, i32, vp, i32, vp, vp]
+    lib.tm_batch_create.argtypes = [vp, i32, ctypes.POINTER(tm_problem), ctypes.POINTER(tm_retrieve_opts), i32,
+                                    ctypes.POINTER(vp)]
+    lib.tm_batch_run.argtypes = [vp, vp]
+    lib.tm_batch_destroy.argtypes = [vp]
+    lib.tm_tune_time.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
+    lib.tm_set_variant.argtypes = [vp, i32, i32, i32]
     lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
@@ -391,3 +403,74 @@ def tm_gemm_bf16(ctx: Context, A, B, ta=False, tb=False):
     rc = ctx.lib.tm_gemm_bf16(ctx.h, M, N, K, _ptr(A), int(ta), _ptr(B), int(tb), _ptr(C), _stream(A.device))
     ctx.check(rc, "tm_gemm_bf16")
     return C
+
+
+class Batch:
+    """A planned retrieval of several problems of uneven size (tm_batch_*).
+    problems: list of dicts with masks [K, N], I [P, K, N], t [P, N] (in/out),
+    n1, n2 and optionally stats ([P, 24] uint8 device tensor)."""
+
+    def __init__(self, ctx: Context, problems, opts: tm_retrieve_opts, use_graph: bool = True):
+        self.ctx = ctx
+        self.problems = problems  # keeps the tensors alive
+        arr = (tm_problem * len(problems))()
+        for i, p in enumerate(problems):
+            K, N = p["masks"].shape
+            arr[i] = tm_problem(_dims(p["n1"], p["n2"], K, p["t"].shape[0]), _ptr(p["masks"]), _ptr(p["I"]),
+                                _ptr(p["t"]), _ptr(p.get("stats")))
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.tm_batch_create(ctx.h, len(problems), arr, ctypes.byref(opts), int(use_graph),
+                                          ctypes.byref(h)), "tm_batch_create")
+        self.h = h
+
+    def run(self, stream=None):
+        dev = self.problems[0]["t"].device
+        self.ctx.check(self.ctx.lib.tm_batch_run(self.h, stream if stream is not None else _stream(dev)),
+                       "tm_batch_run")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tm_tune_time(ctx: Context, n1, n2, K, P, variant, bf16=False, reps=5) -> float:
+    us = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.tm_tune_time(ctx.h, n1, n2, K, P, TM_BF16 if bf16 else TM_F32, variant, reps,
+                                   ctypes.byref(us)), "tm_tune_time")
+    return us.value
+
+
+def tm_set_variant(ctx: Context, n1, n2, variant):
+    ctx.check(ctx.lib.tm_set_variant(ctx.h, n1, n2, variant), "tm_set_variant")
+
+
+def autotune(ctx: Context, n1: int, n2: int, K: int, P: int, bf16: bool = False, cache: str | None = None,
+             reps: int = 5) -> dict:
+    """Choose the FFT digit order for an n1 x n2 grid by timing both variants of
+    the error-reduction kernel (P rows, K masks), apply it to the context and
+    record it in the JSON cache `cache` (keyed by architecture, grid, K and
+    intensity type). A cached entry is applied without timing."""
+    import json
+    key = f"gfx950:{n1}x{n2}:K{K}:{'bf16' if bf16 else 'f32'}"
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    if key in table:
+        entry = table[key]
+    else:
+        times = [tm_tune_time(ctx, n1, n2, K, P, v, bf16, reps) for v in (0, 1)]
+        entry = {"variant": int(times[1] < times[0]), "us": times, "rows": P}
+        if cache:
+            table[key] = entry
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+    tm_set_variant(ctx, n1, n2, entry["variant"])
+    return entry

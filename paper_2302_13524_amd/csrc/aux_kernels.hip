@@ -72,6 +72,20 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint32_t* p, int64_t n) {
   for (; i < n; i += stride) p[i] = 0u;
 }
 
+__global__ void __launch_bounds__(256) k_fill_hash(float* p, int64_t n, uint32_t seed, float lo, float hi) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    p[i] = lo + (hi - lo) * ((h >> 8) * (1.0f / 16777216.0f));
+  }
+}
+
 // Per-row result record (layout of tm_row_stats).
 struct RowStats {
   double rho;
@@ -119,6 +133,13 @@ int launch_fill_zero(void* p, int64_t bytes, void* s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   k_fill_zero<<<(int)blocks, 256, 0, (hipStream_t)s>>>((uint32_t*)p, n);
+  return (int)hipGetLastError();
+}
+int launch_fill_hash(float* p, int64_t n, uint32_t seed, float lo, float hi, void* s) {
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_fill_hash<<<(int)blocks, 256, 0, (hipStream_t)s>>>(p, n, seed, lo, hi);
   return (int)hipGetLastError();
 }
 int launch_finalize(void* st, int P, const double* sums64, const float* sums, int nsum, int f_idx,

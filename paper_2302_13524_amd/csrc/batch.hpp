@@ -1,0 +1,45 @@
+// Uneven multi-TM batches: one persistent launch per iteration covers every
+// row of every problem; work items are (problem, row tile).
+#pragma once
+#include <stdint.h>
+
+#include "fft_core.hpp"
+
+namespace tmk {
+
+constexpr int BATCH_WG = 512;
+
+// Grids the batched kernel is compiled for; code = 2 * grid_id + variant.
+// 0: 32 x 32, 1: 64 x 32, 2: 64 x 64, 3: 128 x 64.
+int batch_grid_id(int n1, int n2);
+// rows per work item (rows of that grid one 512-thread workgroup handles)
+int batch_rows_per_item(int grid_id);
+
+struct BatchProb {
+  const cx<float>* masks;
+  const void* I;
+  cx<float>* t;
+  cx<float>* vprev;
+  float* sums;          // [P][6] or null
+  const float* rowmean;
+  int K, P, code;
+};
+
+struct BatchItem {
+  int prob, blk;
+};
+
+struct BatchArgs {
+  const BatchProb* probs;
+  const BatchItem* items;
+  int n_items;
+  int with_sums;         // pass the problems' sums pointers (else null)
+  float tau, momentum;
+  const cx<float>* tw32;
+};
+
+enum BatchMode { BATCH_ER = 0, BATCH_SPEC = 1 };
+// Launch one batched pass (mode BATCH_*) over all items with `grid` workgroups.
+int batch_launch(int mode, int ibf16, int with_sums, const BatchArgs& a, int grid, void* stream);
+
+}  // namespace tmk

@@ -1,0 +1,106 @@
+// Persistent batched pass over uneven problems. Every work item is one row
+// tile of one problem (1 row of 8192 modes, 2 of 4096, 4 of 2048, 8 of
+// 1024: tiles of similar FFT work); workgroups stride over the item list, and
+// each item runs the same fused row body as the single-problem kernels,
+// specialised for its grid and FFT digit order.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "row_kernels.hpp"
+
+namespace tmk {
+
+int batch_grid_id(int n1, int n2) {
+  if (n1 == 32 && n2 == 32) return 0;
+  if (n1 == 64 && n2 == 32) return 1;
+  if (n1 == 64 && n2 == 64) return 2;
+  if (n1 == 128 && n2 == 64) return 3;
+  return -1;
+}
+
+int batch_rows_per_item(int g) {
+  switch (g) {
+    case 0: return Launch<Plan<5, 5>, BATCH_WG>::RPW;
+    case 1: return Launch<Plan<6, 5>, BATCH_WG>::RPW;
+    case 2: return Launch<Plan<6, 6>, BATCH_WG>::RPW;
+    case 3: return Launch<Plan<7, 6>, BATCH_WG>::RPW;
+  }
+  return 0;
+}
+
+namespace {
+
+template <class PL>
+constexpr int lds_of() {
+  return Launch<PL, BATCH_WG>::LDS_ELEMS;
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kLds = cmax(cmax(lds_of<Plan<5, 5>>(), lds_of<Plan<6, 5>>()), cmax(lds_of<Plan<6, 6>>(), lds_of<Plan<7, 6>>()));
+
+// One out-of-line body per specialisation, so that each gets its own register
+// allocation instead of the union of all of them.
+template <class PL, int M, typename IT, bool SUMS>
+__device__ __attribute__((noinline)) void item_body(const RowArgs& a, int blk, cx<float>* lds, float* red) {
+  row_body<PL, M, IT, SUMS, BATCH_WG>(a, blk, lds, red);
+}
+
+template <int MODE, typename IT, bool SUMS>
+__global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
+  __shared__ cx<float> lds[kLds];
+  __shared__ float red[Launch<Plan<7, 6>, BATCH_WG>::RED_FLOATS];
+  for (int it = blockIdx.x; it < b.n_items; it += gridDim.x) {
+    const BatchItem w = b.items[it];
+    const BatchProb pr = b.probs[w.prob];
+    RowArgs a;
+    a.P = pr.P;
+    a.K = pr.K;
+    a.masks = pr.masks;
+    a.tin = pr.t;
+    a.tout = pr.t;
+    a.din = pr.vprev;
+    a.tout2 = pr.vprev;
+    a.I = pr.I;
+    a.yin = nullptr;
+    a.yout = nullptr;
+    a.sums = SUMS ? pr.sums : nullptr;
+    a.sums64 = nullptr;
+    a.rowmean = pr.rowmean;
+    a.tau = b.tau;
+    a.momentum = b.momentum;
+    a.out_bf16 = 0;
+    a.tw32 = b.tw32;
+    a.tw64 = nullptr;
+    constexpr int M = (MODE == BATCH_ER) ? M_ER : M_SPEC;
+    switch (pr.code) {
+      case 0: item_body<Plan<5, 5, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 1: item_body<Plan<5, 5, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 2: item_body<Plan<6, 5, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 3: item_body<Plan<6, 5, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 4:
+      case 5: item_body<Plan<6, 6, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 6: item_body<Plan<7, 6, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 7: item_body<Plan<7, 6, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      default: break;
+    }
+    __syncthreads();  // LDS of this item is free before the next item writes it
+  }
+}
+
+template <int MODE, typename IT>
+int launch_m(int with_sums, const BatchArgs& a, int grid, hipStream_t s) {
+  if (with_sums) batch_kernel<MODE, IT, true><<<grid, BATCH_WG, 0, s>>>(a);
+  else batch_kernel<MODE, IT, false><<<grid, BATCH_WG, 0, s>>>(a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int batch_launch(int mode, int ibf16, int with_sums, const BatchArgs& a, int grid, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (a.n_items <= 0) return 0;
+  if (mode == BATCH_ER) return ibf16 ? launch_m<BATCH_ER, uint16_t>(with_sums, a, grid, s)
+                                     : launch_m<BATCH_ER, float>(with_sums, a, grid, s);
+  return ibf16 ? launch_m<BATCH_SPEC, uint16_t>(0, a, grid, s) : launch_m<BATCH_SPEC, float>(0, a, grid, s);
+}
+
+}  // namespace tmk

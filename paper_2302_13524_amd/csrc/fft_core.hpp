@@ -174,14 +174,16 @@ struct PlanDesc {
 
 // digits (log2 radices) of a length 2^b axis, most significant first
 constexpr int ndigits(int b) { return b == 0 ? 0 : (b <= 4 ? 1 : (b <= 8 ? 2 : (b <= 12 ? 3 : 4))); }
-constexpr int digit_bits(int b, int i) {
-  // split b bits into ndigits(b) digits of 2..4 bits, larger ones first
+// Split b bits into ndigits(b) digits of 1..4 bits; variant 0 puts the
+// larger digits first (most significant), variant 1 the smaller ones.
+constexpr int digit_bits(int b, int i, int var = 0) {
   int n = ndigits(b);
   int base = b / n, extra = b % n;
-  return base + (i < extra ? 1 : 0);
+  int j = var ? (n - 1 - i) : i;
+  return base + (j < extra ? 1 : 0);
 }
 
-constexpr PlanDesc make_plan(int L1, int L2) {
+constexpr PlanDesc make_plan(int L1, int L2, int var) {
   PlanDesc d{};
   d.np = 0;
   int n1d = ndigits(L1), n2d = ndigits(L2);
@@ -195,17 +197,19 @@ constexpr PlanDesc make_plan(int L1, int L2) {
     d.np++;
   };
   int i1 = 0;
-  if (n1d >= 2) { push(1, digit_bits(L1, 0)); i1 = 1; }
-  for (int i = 0; i < n2d; ++i) push(2, digit_bits(L2, i));
-  for (int i = i1; i < n1d; ++i) push(1, digit_bits(L1, i));
+  if (n1d >= 2) { push(1, digit_bits(L1, 0, var)); i1 = 1; }
+  for (int i = 0; i < n2d; ++i) push(2, digit_bits(L2, i, var));
+  for (int i = i1; i < n1d; ++i) push(1, digit_bits(L1, i, var));
   return d;
 }
 
 // Values per thread: 16 (LE_ forces another value).
 constexpr int default_le(int ln) { return ln >= 4 ? 4 : ln; }
 
-template <int L1_, int L2_, int LE_ = -1>
+// VAR_ selects the digit order (see digit_bits); the autotuner picks it per grid.
+template <int L1_, int L2_, int LE_ = -1, int VAR_ = 0>
 struct Plan {
+  static constexpr int VAR = VAR_;
   static constexpr int L1 = L1_, L2 = L2_;
   static constexpr int LN = L1 + L2;
   static constexpr int N1 = 1 << L1, N2 = 1 << L2, N = 1 << LN;
@@ -213,7 +217,7 @@ struct Plan {
   static constexpr int E = 1 << LE;
   static constexpr int LT = LN - LE;
   static constexpr int T = 1 << LT;  // threads per row
-  static constexpr PlanDesc desc = make_plan(L1, L2);
+  static constexpr PlanDesc desc = make_plan(L1, L2, VAR_);
   static constexpr int NP = desc.np;
   // LDS: row-major grid with one pad slot after every n2 slots (n2 >= 16)
   static constexpr int PADSH = (L2 >= 4) ? L2 : 30;
@@ -445,13 +449,13 @@ __device__ __forceinline__ void fft_inverse(cx<T>* x, Xbuf<T>& xb, int ltid, con
 
 // Digit reversal of one axis: slot index s (digits high to low as laid out by
 // the DIF passes) -> frequency index k = d_0 + R_0 d_1 + R_0 R_1 d_2 + ...
-template <int LA>
+template <int LA, int VAR>
 __device__ __forceinline__ int digit_rev(int s) {
   constexpr int nd = ndigits(LA);
   int k = 0, shift_out = 0, rem = LA;
 #pragma unroll
   for (int i = 0; i < nd; ++i) {
-    int b = digit_bits(LA, i);
+    int b = digit_bits(LA, i, VAR);
     rem -= b;
     int d = (s >> rem) & ((1 << b) - 1);
     k |= d << shift_out;
@@ -464,7 +468,7 @@ __device__ __forceinline__ int digit_rev(int s) {
 template <class PL>
 __device__ __forceinline__ int spectrum_index(int e) {
   int s1 = e >> PL::L2, s2 = e & (PL::N2 - 1);
-  return (digit_rev<PL::L1>(s1) << PL::L2) | digit_rev<PL::L2>(s2);
+  return (digit_rev<PL::L1, PL::VAR>(s1) << PL::L2) | digit_rev<PL::L2, PL::VAR>(s2);
 }
 
 template <class PL>

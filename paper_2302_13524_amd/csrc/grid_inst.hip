@@ -12,10 +12,9 @@ namespace tmk {
 #define TM_CAT2(a, b, c) a##_##b##_##c
 #define TM_CAT(a, b, c) TM_CAT2(a, b, c)
 
-using PLg = Plan<GL1, GL2>;
 using PLd = Plan<GL1, GL2, (GL1 + GL2 >= 4) ? 4 : GL1 + GL2>;  // FP64 residual: 16 values per thread
 
-template <typename IT>
+template <class PLg, typename IT>
 static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
   using LC = Launch<PLg>;
   dim3 grid((a.P + LC::RPW - 1) / LC::RPW), block(LC::WG);
@@ -49,14 +48,31 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
+// Digit-order variant 1 differs from variant 0 only when an axis splits
+// into digits of unequal size.
+constexpr bool uneven(int b) { return ndigits(b) >= 2 && b % ndigits(b) != 0; }
+constexpr bool kHasVar = uneven(GL1) || uneven(GL2);
+
 int TM_CAT(row_launch, GL1, GL2)(int mode, int ibf16, const RowArgs& a, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  return ibf16 ? launch_t<uint16_t>(mode, a, s) : launch_t<float>(mode, a, s);
+  using P0 = Plan<GL1, GL2>;
+  return ibf16 ? launch_t<P0, uint16_t>(mode, a, s) : launch_t<P0, float>(mode, a, s);
+}
+
+int TM_CAT(row_launchv, GL1, GL2)(int mode, int ibf16, const RowArgs& a, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if constexpr (kHasVar) {
+    using P1 = Plan<GL1, GL2, -1, 1>;
+    return ibf16 ? launch_t<P1, uint16_t>(mode, a, s) : launch_t<P1, float>(mode, a, s);
+  } else {
+    using P0 = Plan<GL1, GL2>;
+    return ibf16 ? launch_t<P0, uint16_t>(mode, a, s) : launch_t<P0, float>(mode, a, s);
+  }
 }
 
 void TM_CAT(row_shape, GL1, GL2)(int* wg, int* rpw) {
-  *wg = Launch<PLg>::WG;
-  *rpw = Launch<PLg>::RPW;
+  *wg = Launch<Plan<GL1, GL2>>::WG;
+  *rpw = Launch<Plan<GL1, GL2>>::RPW;
 }
 
 }  // namespace tmk

@@ -3,14 +3,15 @@
 
 namespace tmk {
 
-#define TM_DECL(a, b)                                                      \
-  int row_launch_##a##_##b(int mode, int ibf16, const RowArgs& x, void* s); \
+#define TM_DECL(a, b)                                                       \
+  int row_launch_##a##_##b(int mode, int ibf16, const RowArgs& x, void* s);  \
+  int row_launchv_##a##_##b(int mode, int ibf16, const RowArgs& x, void* s); \
   void row_shape_##a##_##b(int* wg, int* rpw);
 TM_GRID_LIST(TM_DECL)
 
-row_launcher find_row_launcher(int L1, int L2) {
+row_launcher find_row_launcher(int L1, int L2, int var) {
 #define TM_FIND(a, b) \
-  if (L1 == a && L2 == b) return &row_launch_##a##_##b;
+  if (L1 == a && L2 == b) return var ? &row_launchv_##a##_##b : &row_launch_##a##_##b;
   TM_GRID_LIST(TM_FIND)
   return nullptr;
 }

@@ -10,7 +10,8 @@ struct RowArgs;
 // Launch one row kernel. mode: tmk::Mode; ibf16: intensities are bf16.
 // Returns hipSuccess, or hipErrorInvalidValue when (L1, L2) is not compiled.
 typedef int (*row_launcher)(int mode, int ibf16, const RowArgs& a, void* stream);
-row_launcher find_row_launcher(int L1, int L2);
+// var: FFT digit-order variant (0: larger digits first, 1: smaller first)
+row_launcher find_row_launcher(int L1, int L2, int var = 0);
 // threads per workgroup and rows per workgroup of a grid
 void row_launch_shape(int L1, int L2, int* wg, int* rpw);
 }  // namespace tmk

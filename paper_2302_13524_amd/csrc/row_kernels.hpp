@@ -143,12 +143,16 @@ __device__ __forceinline__ double row_reduce64(double v, double* red, int tid) {
   }
 }
 
-template <class PL>
+// Shape of one workgroup of WGT threads (default: one row of T threads, at
+// least 256 threads).
+template <class PL, int WGT = ((PL::T >= 256) ? PL::T : 256)>
 struct Launch {
-  static constexpr int WG = (PL::T >= 256) ? PL::T : 256;
+  static constexpr int WG = WGT;
   static constexpr int RPW = WG / PL::T;  // rows per workgroup
   // double-buffered LDS exchange when two copies of the rows fit in 160 KiB
   static constexpr bool DB = 2 * RPW * PL::LDS_ROW * 8 <= 160 * 1024 - 4096;
+  static constexpr int LDS_ELEMS = (DB ? 2 : 1) * RPW * PL::LDS_ROW;
+  static constexpr int RED_FLOATS = (WG / 64 + 1) * 6 * 2;
 };
 
 // ---------------------------------------------------------------- FP32 kernel
@@ -167,20 +171,21 @@ __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(
 #define TM_RELOAD_T 0
 #endif
 
-template <class PL, int MODE, typename IT, bool SUMS = true>
-__global__ void __launch_bounds__(Launch<PL>::WG) __attribute__((amdgpu_waves_per_eu(TM_MINW)))
-row_kernel(RowArgs a) {
+// Body of the fused kernel for the rows [blk * RPW, (blk + 1) * RPW) of one
+// problem, run by a workgroup of WGT threads with LDS at lds_all (at least
+// Launch<PL, WGT>::LDS_ELEMS elements) and red (RED_FLOATS floats).
+template <class PL, int MODE, typename IT, bool SUMS, int WGT>
+__device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* lds_all, float* red) {
   using T = float;
   using C = cx<T>;
-  constexpr int E = PL::E, N = PL::N, WG = Launch<PL>::WG, RPW = Launch<PL>::RPW;
-  constexpr int NBUF = Launch<PL>::DB ? 2 : 1;
-  __shared__ C lds_all[NBUF * RPW * PL::LDS_ROW];
-  __shared__ float red[(WG / 64 + 1) * NSUM * 2];
+  using LC = Launch<PL, WGT>;
+  constexpr int E = PL::E, N = PL::N, WG = LC::WG, RPW = LC::RPW;
+  constexpr int NBUF = LC::DB ? 2 : 1;
 
   const int tid = threadIdx.x;
   const int rloc = tid / PL::T;
   const int ltid = tid % PL::T;
-  const int row = blockIdx.x * RPW + rloc;
+  const int row = blk * RPW + rloc;
   const bool valid = row < a.P;
   const size_t prow = valid ? (size_t)row : 0;
   Xbuf<T> xb{lds_all + rloc * PL::LDS_ROW, (NBUF == 2) ? RPW * PL::LDS_ROW : 0, 0};
@@ -378,6 +383,14 @@ row_kernel(RowArgs a) {
       }
     }
   }
+}
+
+template <class PL, int MODE, typename IT, bool SUMS = true>
+__global__ void __launch_bounds__(Launch<PL>::WG) __attribute__((amdgpu_waves_per_eu(TM_MINW)))
+row_kernel(RowArgs a) {
+  __shared__ cx<float> lds_all[Launch<PL>::LDS_ELEMS];
+  __shared__ float red[Launch<PL>::RED_FLOATS];
+  row_body<PL, MODE, IT, SUMS, Launch<PL>::WG>(a, blockIdx.x, lds_all, red);
 }
 
 // ---------------------------------------------------------------- FP64 residual

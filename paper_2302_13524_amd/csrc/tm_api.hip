@@ -4,6 +4,7 @@
 // the device kernels; the host only launches them in order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +15,7 @@
 
 #include "../../include/tm.h"
 #include "aux.hpp"
+#include "batch.hpp"
 #include "grids.hpp"
 #include "lbfgs.hpp"
 #include "mlp.hpp"
@@ -40,6 +42,7 @@ struct tm_ctx {
   std::vector<hipEvent_t> pool;
   double acc_ms[16] = {0};
   int64_t acc_n[16] = {0};
+  std::map<int, int> variant;  // (L1 << 8 | L2) -> FFT digit-order variant
 };
 
 namespace {
@@ -107,7 +110,9 @@ int check_dims(tm_ctx* c, const tm_dims& d, tmk::row_launcher* fn) {
   if (d.K < 1 || d.K > 64) return fail(c, TM_EINVAL, "K=%d outside 1..64", d.K);
   if (d.P < 0) return fail(c, TM_EINVAL, "P=%d < 0", d.P);
   if ((int64_t)d.n1 * d.n2 > TW_MAX) return fail(c, TM_EUNSUPPORTED, "N=%d > %d", d.n1 * d.n2, TW_MAX);
-  *fn = tmk::find_row_launcher(ilog2(d.n1), ilog2(d.n2));
+  int L1 = ilog2(d.n1), L2 = ilog2(d.n2);
+  auto v = c->variant.find((L1 << 8) | L2);
+  *fn = tmk::find_row_launcher(L1, L2, v == c->variant.end() ? 0 : v->second);
   if (!*fn) return fail(c, TM_EUNSUPPORTED, "grid %dx%d has no compiled FFT plan", d.n1, d.n2);
   return TM_OK;
 }
@@ -720,5 +725,244 @@ extern "C" int tm_gemm_bf16(tm_ctx* c, int32_t M, int32_t N, int32_t K, const ui
   HIPCHK(c, hipSetDevice(c->device));
   int e = tmk::gemm_bf16(M, N, K, A, ta != 0, B, tb != 0, C, stream);
   if (e) return hipfail(c, e, "gemm");
+  return TM_OK;
+}
+
+// ---------------------------------------------------------------- batches
+struct tm_batch {
+  tm_ctx* c = nullptr;
+  std::vector<tm_problem> probs;
+  tm_retrieve_opts opts{};
+  std::vector<tmk::row_launcher> fns;
+  void* dmem = nullptr;
+  tmk::BatchArgs args{};
+  int grid = 0;
+  std::vector<double*> rowsum, sums64;
+  std::vector<float*> rowmean, sums;
+  std::vector<void*> vprev;
+  hipStream_t cap = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+};
+
+static int batch_enqueue(tm_batch* b, void* stream) {
+  tm_ctx* c = b->c;
+  const tm_retrieve_opts& o = b->opts;
+  const int n = (int)b->probs.size();
+  const int ibf = o.I_dtype == TM_BF16;
+  int e = 0;
+  if (o.start == TM_START_SPECTRAL) {
+    for (int i = 0; i < n; ++i) {
+      const tm_problem& p = b->probs[i];
+      int N = p.d.n1 * p.d.n2;
+      if (p.d.P == 0) continue;
+      if (!e) e = tmk::launch_row_isum(p.I, ibf, (int64_t)p.d.K * N, p.d.P, b->rowsum[i], b->rowmean[i], stream);
+      if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 0, nullptr, 1.0, stream);
+      if (!e) e = tmk::launch_fill_zero(b->vprev[i], (int64_t)p.d.P * N * sizeof(tm_c32), stream);
+    }
+    tmk::BatchArgs a = b->args;
+    a.tau = o.spectral_tau;
+    a.momentum = o.spectral_momentum;
+    for (int it = 0; it < o.spectral_iters && !e; ++it) e = tmk::batch_launch(tmk::BATCH_SPEC, ibf, 0, a, b->grid, stream);
+    for (int i = 0; i < n && !e; ++i) {
+      const tm_problem& p = b->probs[i];
+      if (p.d.P) e = tmk::launch_row_rescale(p.t, p.d.n1 * p.d.n2, p.d.P, 1, b->rowsum[i], (double)p.d.K * p.d.n1 * p.d.n2, stream);
+    }
+  } else if (o.start == TM_START_BACKPROP) {
+    for (int i = 0; i < n && !e; ++i) {
+      const tm_problem& p = b->probs[i];
+      tmk::RowArgs a = base_args(c, p.d, p.masks);
+      a.I = p.I;
+      a.tout = (tmk::cx<float>*)p.t;
+      e = b->fns[i](tmk::M_BACKPROP, ibf, a, stream);
+    }
+  }
+  for (int it = 0; it < o.iters && !e; ++it)
+    e = tmk::batch_launch(tmk::BATCH_ER, ibf, it == o.iters - 1, b->args, b->grid, stream);
+  for (int i = 0; i < n && !e; ++i) {
+    const tm_problem& p = b->probs[i];
+    if (p.d.P == 0) continue;
+    tmk::RowArgs a = base_args(c, p.d, p.masks);
+    a.I = p.I;
+    a.tin = (const tmk::cx<float>*)p.t;
+    a.sums64 = b->sums64[i];
+    e = b->fns[i](tmk::M_RES64, ibf, a, stream);
+    if (!e && p.stats)
+      e = tmk::launch_finalize(p.stats, p.d.P, b->sums64[i], o.iters > 0 ? b->sums[i] : nullptr, tmk::NSUM,
+                               o.iters > 0 ? 1 : -1, o.iters > 0 ? 0 : -1, o.iters, 1e-2, stream);
+  }
+  return e;
+}
+
+extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, const tm_retrieve_opts* o,
+                               int32_t use_graph, tm_batch** out) {
+  if (!c) return TM_EINVAL;
+  if (!out || !o || n < 1 || !probs) return fail(c, TM_EINVAL, "n >= 1 and non-null probs, opts, out");
+  *out = nullptr;
+  if (o->method != TM_METHOD_ER) return fail(c, TM_EUNSUPPORTED, "batches run the error-reduction method");
+  if (o->iters < 0 || (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) || o->start < TM_START_GIVEN ||
+      o->start > TM_START_SPECTRAL)
+    return fail(c, TM_EINVAL, "bad options");
+  if (o->start == TM_START_SPECTRAL &&
+      (o->spectral_iters < 0 || !(o->spectral_tau > 0.f) || !(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f)))
+    return fail(c, TM_EINVAL, "bad spectral options");
+  HIPCHK(c, hipSetDevice(c->device));
+  tm_batch* b = new tm_batch;
+  b->c = c;
+  b->opts = *o;
+  b->probs.assign(probs, probs + n);
+  std::vector<tmk::BatchProb> hp(n);
+  std::vector<tmk::BatchItem> items;
+  size_t ws_bytes = 0;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  for (int i = 0; i < n; ++i) {
+    const tm_problem& p = probs[i];
+    tmk::row_launcher fn;
+    int r = check_dims(c, p.d, &fn);
+    if (r) { delete b; return r; }
+    int gid = tmk::batch_grid_id(p.d.n1, p.d.n2);
+    if (gid < 0) { delete b; return fail(c, TM_EUNSUPPORTED, "problem %d: grid %dx%d is not compiled for batches", i, p.d.n1, p.d.n2); }
+    if (p.d.P > 0 && (!p.masks || !p.I || !p.t)) { delete b; return fail(c, TM_EINVAL, "problem %d: null pointer", i); }
+    b->fns.push_back(fn);
+    auto v = c->variant.find((ilog2(p.d.n1) << 8) | ilog2(p.d.n2));
+    int var = (v == c->variant.end()) ? 0 : v->second;
+    hp[i].code = 2 * gid + var;
+    int rpi = tmk::batch_rows_per_item(gid);
+    for (int blk = 0; blk * rpi < p.d.P; ++blk) items.push_back({i, blk});
+    size_t N = (size_t)p.d.n1 * p.d.n2;
+    ws_bytes += al(p.d.P * 8) + al(p.d.P * 4) + al(p.d.P * tmk::NSUM * 4) + al(p.d.P * 16) + al(p.d.P * N * 8);
+  }
+  size_t tab = al(n * sizeof(tmk::BatchProb)) + al(items.size() * sizeof(tmk::BatchItem));
+  if (hipMalloc(&b->dmem, tab + ws_bytes + 256) != hipSuccess) { delete b; return fail(c, TM_ENOMEM, "batch workspace"); }
+  char* w = (char*)b->dmem + tab;
+  for (int i = 0; i < n; ++i) {
+    const tm_problem& p = probs[i];
+    size_t N = (size_t)p.d.n1 * p.d.n2;
+    b->rowsum.push_back((double*)w); w += al(p.d.P * 8);
+    b->rowmean.push_back((float*)w); w += al(p.d.P * 4);
+    b->sums.push_back((float*)w); w += al(p.d.P * tmk::NSUM * 4);
+    b->sums64.push_back((double*)w); w += al(p.d.P * 16);
+    b->vprev.push_back(w); w += al(p.d.P * N * 8);
+    hp[i].masks = (const tmk::cx<float>*)p.masks;
+    hp[i].I = p.I;
+    hp[i].t = (tmk::cx<float>*)p.t;
+    hp[i].vprev = (tmk::cx<float>*)b->vprev[i];
+    hp[i].sums = b->sums[i];
+    hp[i].rowmean = b->rowmean[i];
+    hp[i].K = p.d.K;
+    hp[i].P = p.d.P;
+  }
+  tmk::BatchProb* dprobs = (tmk::BatchProb*)b->dmem;
+  tmk::BatchItem* ditems = (tmk::BatchItem*)((char*)b->dmem + al(n * sizeof(tmk::BatchProb)));
+  if (hipMemcpy(dprobs, hp.data(), n * sizeof(tmk::BatchProb), hipMemcpyHostToDevice) != hipSuccess ||
+      (!items.empty() && hipMemcpy(ditems, items.data(), items.size() * sizeof(tmk::BatchItem), hipMemcpyHostToDevice) != hipSuccess)) {
+    hipFree(b->dmem);
+    delete b;
+    return fail(c, TM_EHIP, "batch table upload");
+  }
+  b->args.probs = dprobs;
+  b->args.items = ditems;
+  b->args.n_items = (int)items.size();
+  b->args.tw32 = c->tw32;
+  // persistent grid: every CU holds one 512-thread workgroup (LDS and registers)
+  int cus = 0;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+  b->grid = std::max(1, std::min((int)items.size(), cus > 0 ? cus : 256));
+  if (use_graph) {
+    hipError_t he = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+    int e = (he == hipSuccess) ? batch_enqueue(b, b->cap) : (int)he;
+    hipGraph_t g = nullptr;
+    hipError_t he2 = b->cap ? hipStreamEndCapture(b->cap, &g) : hipErrorInvalidValue;
+    if (!e && he2 == hipSuccess) {
+      b->g = g;
+      he2 = hipGraphInstantiate(&b->ge, g, nullptr, nullptr, 0);
+    }
+    if (e || he2 != hipSuccess) {
+      int code = e ? e : (int)he2;
+      tm_batch_destroy(b);
+      return hipfail(c, code, "batch graph capture");
+    }
+  }
+  *out = b;
+  return TM_OK;
+}
+
+extern "C" int tm_batch_run(tm_batch* b, void* stream) {
+  if (!b) return TM_EINVAL;
+  tm_ctx* c = b->c;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (b->ge) {
+    HIPCHK(c, hipGraphLaunch(b->ge, (hipStream_t)stream));
+    return TM_OK;
+  }
+  int e = batch_enqueue(b, stream);
+  if (e) return hipfail(c, e, "batch launch");
+  return TM_OK;
+}
+
+extern "C" int tm_batch_destroy(tm_batch* b) {
+  if (!b) return TM_EINVAL;
+  hipSetDevice(b->c->device);
+  hipDeviceSynchronize();
+  if (b->ge) hipGraphExecDestroy(b->ge);
+  if (b->g) hipGraphDestroy(b->g);
+  if (b->cap) hipStreamDestroy(b->cap);
+  hipFree(b->dmem);
+  delete b;
+  return TM_OK;
+}
+
+// ---------------------------------------------------------------- autotuning
+extern "C" int tm_set_variant(tm_ctx* c, int32_t n1, int32_t n2, int32_t variant) {
+  if (!c) return TM_EINVAL;
+  if (variant < 0 || variant > 1) return fail(c, TM_EINVAL, "variant %d", variant);
+  if (!tm_grid_supported(n1, n2)) return fail(c, TM_EUNSUPPORTED, "grid %dx%d", n1, n2);
+  c->variant[(ilog2(n1) << 8) | ilog2(n2)] = variant;
+  return TM_OK;
+}
+
+extern "C" int tm_tune_time(tm_ctx* c, int32_t n1, int32_t n2, int32_t K, int32_t P, int32_t I_dtype,
+                            int32_t variant, int32_t reps, double* us) {
+  if (!c) return TM_EINVAL;
+  if (!us || reps < 1 || P < 1 || K < 1 || variant < 0 || variant > 1 || (I_dtype != TM_F32 && I_dtype != TM_BF16))
+    return fail(c, TM_EINVAL, "bad tuning arguments");
+  tm_dims d{n1, n2, K, P};
+  tmk::row_launcher fn0;
+  int r = check_dims(c, d, &fn0);
+  if (r) return r;
+  tmk::row_launcher fn = tmk::find_row_launcher(ilog2(n1), ilog2(n2), variant);
+  HIPCHK(c, hipSetDevice(c->device));
+  size_t N = (size_t)n1 * n2;
+  float* mk = (float*)ws_get(c, WS_PH_BASE + 20, K * N * 8);
+  float* t = (float*)ws_get(c, WS_PH_BASE + 21, P * N * 8);
+  float* I = (float*)ws_get(c, WS_PH_BASE + 22, (size_t)P * K * N * 4);
+  if (!mk || !t || !I) return fail(c, TM_ENOMEM, "tuning workspace");
+  hipStream_t s = nullptr;
+  int e = tmk::launch_fill_hash(mk, (int64_t)K * N * 2, 11u, -0.7f, 0.7f, s);
+  if (!e) e = tmk::launch_fill_hash(t, (int64_t)P * N * 2, 12u, -1.f, 1.f, s);
+  // intensities in [0.5, 2); read as bf16 the buffer holds arbitrary values,
+  // which leaves the timing unchanged (only the timing is used)
+  if (!e) e = tmk::launch_fill_hash(I, (int64_t)P * K * N, 13u, 0.5f, 2.f, s);
+  if (e) return hipfail(c, e, "tuning data");
+  tmk::RowArgs a = base_args(c, d, (const tm_c32*)mk);
+  a.I = I;
+  a.tin = (const tmk::cx<float>*)t;
+  a.tout = (tmk::cx<float>*)t;
+  int ibf = I_dtype == TM_BF16;
+  if ((e = fn(tmk::M_ER, ibf, a, s))) return hipfail(c, e, "tuning warm-up");
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  hipEventRecord(e0, s);
+  for (int i = 0; i < reps && !e; ++i) e = fn(tmk::M_ER, ibf, a, s);
+  hipEventRecord(e1, s);
+  hipEventSynchronize(e1);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e) return hipfail(c, e, "tuning launch");
+  *us = 1e3 * ms / reps;
   return TM_OK;
 }
