@@ -19,8 +19,9 @@ struct PhaseWork {
   double* A;      // [Nd][nf1][nf2] complex field-grid scratch
   double* B;      // [Nd][2nf1][2nf2] complex image-grid scratch
   double* gpart;  // [Nd] per-image objective
-  double* w;      // [P] gradient
+  double* w;      // [slices][P] complex partial sums of the gradient gather
   double* gval;   // [1] objective
+  int32_t* inv;   // [nf1 nf2] row index of each field pixel, -1 outside the rows
 };
 
 size_t phase_work_bytes(const PhaseDims& d);
@@ -28,7 +29,7 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w);
 
 // c = theta * tm_est^T and the kernel table h. Returns hipError_t.
 int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
-                PhaseWork& w, void* stream);
+                const int32_t* pix, PhaseWork& w, void* stream);
 // g(phi) into w.gval[0] and dg/dphi into grad[P].
 int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const double* phi,
                double* grad, PhaseWork& w, const double* tw64, void* stream);

@@ -17,6 +17,9 @@ namespace tmk {
 
 namespace {
 
+constexpr int RESID_BLOCKS = 16;  // partial-sum blocks per defocus image
+constexpr int GATHER_SLICES = 8;  // image slices of the gradient gather
+
 struct z2 {
   double x, y;
 };
@@ -86,24 +89,32 @@ __global__ void k_make_h(double* h, int nf1, int nf2, double lam, double ps, dou
   h[2 * i + 1] = r.y;
 }
 
-__global__ void k_zero(double* p, size_t n) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  size_t st = (size_t)gridDim.x * 256;
-  for (; i < n; i += st) p[i] = 0.0;
+// inv[g] = p for g = pix[p], -1 elsewhere (pixels are distinct and in range)
+__global__ void k_invmap(int32_t* inv, const int32_t* pix, int P, int G) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < G) inv[i] = -1;
+}
+__global__ void k_invmap2(int32_t* inv, const int32_t* pix, int P) {
+  int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < P) inv[pix[p]] = p;
 }
 
-// A[n][pix[p]] = c[n][p] * e^{j phi_p}
-__global__ void k_scatter(double* A, const double* c, const double* phi, const int32_t* pix, int Nd, int P,
-                          int G) {
-  int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= Nd * P) return;
-  int n = i / P, p = i % P;
-  z2 cv{c[2 * (size_t)i], c[2 * (size_t)i + 1]};
-  z2 u{cos(phi[p]), sin(phi[p])};
-  z2 v = zmul(cv, u);
-  size_t o = ((size_t)n * G + pix[p]) * 2;
-  A[o] = v.x;
-  A[o + 1] = v.y;
+// A[n][g] = c[n][p] e^{j phi_p} where g = pix[p], 0 elsewhere (writes the whole grid)
+__global__ void k_scatter_full(double* A, const double* c, const double* phi, const int32_t* inv, int Nd, int P,
+                               int G) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)Nd * G) return;
+  int n = (int)(i / G), g = (int)(i % G);
+  int p = inv[g];
+  z2 v{0.0, 0.0};
+  if (p >= 0) {
+    z2 cv{c[((size_t)n * P + p) * 2], c[((size_t)n * P + p) * 2 + 1]};
+    double sn, cs;
+    sincos(phi[p], &sn, &cs);
+    v = zmul(cv, z2{cs, sn});
+  }
+  A[2 * i] = v.x;
+  A[2 * i + 1] = v.y;
 }
 
 // Batched in-LDS FFT of lines of length L = 2^LL (radix-2 Stockham).
@@ -160,20 +171,32 @@ __device__ __forceinline__ int padpos(int k, int n) {
   return (s + 2 * n) % (2 * n);
 }
 
-// B[n][pad(a)][pad(b)] = h[a][b] * A[n][a][b]   (B pre-zeroed)
-__global__ void k_pad(double* B, const double* A, const double* h, int Nd, int nf1, int nf2) {
+// field bin of a doubled-spectrum index (inverse of padpos), -1 if that bin is padding
+__device__ __forceinline__ int unpad(int a2, int n) {
+  int hp = (n + 1) / 2;
+  if (a2 < hp) return a2;
+  if (a2 >= n + hp) return a2 - n;
+  return -1;
+}
+
+// B[n][a2][b2] = h[a][b] A[n][a][b] at the padded positions, 0 elsewhere (whole grid)
+__global__ void k_pad_full(double* B, const double* A, const double* h, int Nd, int nf1, int nf2) {
   size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  size_t G = (size_t)nf1 * nf2;
-  if (i >= Nd * G) return;
-  int n = (int)(i / G);
-  int r = (int)(i % G);
-  int a = r / nf2, b = r % nf2;
-  z2 v{A[2 * i], A[2 * i + 1]};
-  z2 hv{h[2 * r], h[2 * r + 1]};
-  z2 o = zmul(v, hv);
-  size_t q = ((size_t)n * 4 * G + (size_t)padpos(a, nf1) * 2 * nf2 + padpos(b, nf2)) * 2;
-  B[q] = o.x;
-  B[q + 1] = o.y;
+  size_t G4 = (size_t)4 * nf1 * nf2;
+  if (i >= Nd * G4) return;
+  int n = (int)(i / G4);
+  int r = (int)(i % G4);
+  int a2 = r / (2 * nf2), b2 = r % (2 * nf2);
+  int a = unpad(a2, nf1), b = unpad(b2, nf2);
+  z2 o{0.0, 0.0};
+  if (a >= 0 && b >= 0) {
+    size_t q = (size_t)n * nf1 * nf2 + (size_t)a * nf2 + b;
+    z2 v{A[2 * q], A[2 * q + 1]};
+    z2 hv{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
+    o = zmul(v, hv);
+  }
+  B[2 * i] = o.x;
+  B[2 * i + 1] = o.y;
 }
 
 // A[n][a][b] = conj(h[a][b]) * B[n][pad(a)][pad(b)]
@@ -192,12 +215,13 @@ __global__ void k_crop(double* A, const double* B, const double* h, int Nd, int 
   A[2 * i + 1] = o.y;
 }
 
-// r = I - |a|^2, a <- a r (in place), per-image sum of r^2 into gpart[n]
+// r = I - |a|^2, a <- a r (in place); partial sums of r^2 per (image, block)
+// into gpart[n * gridDim.y + blockIdx.y]
 __global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, double* gpart, int npix) {
   __shared__ double red[4];
   int n = blockIdx.x;
   double s = 0;
-  for (int i = threadIdx.x; i < npix; i += 256) {
+  for (int i = blockIdx.y * 256 + threadIdx.x; i < npix; i += 256 * gridDim.y) {
     size_t q = (size_t)n * npix + i;
     z2 v{B[2 * q], B[2 * q + 1]};
     double r = (double)Id[q] - (v.x * v.x + v.y * v.y);
@@ -208,30 +232,49 @@ __global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, doubl
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) gpart[n] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) gpart[(size_t)n * gridDim.y + blockIdx.y] = red[0] + red[1] + red[2] + red[3];
 }
 
-// grad[p] = -4 Im(conj(u_p) sum_n conj(c[n][p]) A[n][pix[p]]); gval = sum_n gpart[n]
-__global__ void k_gather(double* grad, double* gval, const double* A, const double* c, const double* phi,
-                         const int32_t* pix, const double* gpart, int Nd, int P, int G) {
+// Partial w_s[p] = sum over the images n of slice s of conj(c[n][p]) A[n][pix[p]]:
+// threads run over consecutive p (coalesced c reads), grid.y over image slices.
+__global__ void __launch_bounds__(256) k_gather_part(double* wpart, const double* A, const double* c,
+                                                      const int32_t* pix, int Nd, int P, int G, int per) {
+  int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  int n0 = blockIdx.y * per, n1 = min(Nd, n0 + per);
+  int g = pix[p];
+  z2 w{0.0, 0.0};
+  for (int n = n0; n < n1; ++n) {
+    size_t o = ((size_t)n * G + g) * 2;
+    z2 v{A[o], A[o + 1]};
+    z2 cv{c[((size_t)n * P + p) * 2], c[((size_t)n * P + p) * 2 + 1]};
+    z2 t = zmulc(v, cv);
+    w.x += t.x;
+    w.y += t.y;
+  }
+  wpart[((size_t)blockIdx.y * P + p) * 2] = w.x;
+  wpart[((size_t)blockIdx.y * P + p) * 2 + 1] = w.y;
+}
+
+// grad[p] = -4 Im(conj(u_p) w[p]) with w the sum of the slices; gval = sum of
+// the residual partials
+__global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, const double* wpart, const double* phi,
+                                                 const double* gpart, int ngp, int nslice, int P) {
   int p = blockIdx.x * 256 + threadIdx.x;
   if (p < P) {
     z2 w{0.0, 0.0};
-    for (int n = 0; n < Nd; ++n) {
-      size_t o = ((size_t)n * G + pix[p]) * 2;
-      z2 v{A[o], A[o + 1]};
-      z2 cv{c[((size_t)n * P + p) * 2], c[((size_t)n * P + p) * 2 + 1]};
-      z2 t = zmulc(v, cv);
-      w.x += t.x;
-      w.y += t.y;
+    for (int sl = 0; sl < nslice; ++sl) {
+      w.x += wpart[((size_t)sl * P + p) * 2];
+      w.y += wpart[((size_t)sl * P + p) * 2 + 1];
     }
-    z2 u{cos(phi[p]), sin(phi[p])};
-    z2 q = zmulc(w, u);  // w conj(u)
+    double sn, cs;
+    sincos(phi[p], &sn, &cs);
+    z2 q = zmulc(w, z2{cs, sn});  // w conj(u)
     grad[p] = -4.0 * q.y;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double s = 0;
-    for (int n = 0; n < Nd; ++n) s += gpart[n];
+    for (int i = 0; i < ngp; ++i) s += gpart[i];
     gval[0] = s;
   }
 }
@@ -264,7 +307,8 @@ int fft2(double* buf, int Nd, int g1, int g2, int sign, const double* tw64, hipS
 
 size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
-  size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 4 * G * 2 + d.Nd + d.P + 8;
+  size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 4 * G * 2 +
+               (size_t)d.Nd * RESID_BLOCKS + (size_t)GATHER_SLICES * d.P * 2 + 8 + G;
   return dbl * sizeof(double) + 8 * 256;
 }
 
@@ -280,18 +324,21 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->h = take(G * 2);
   w->A = take((size_t)d.Nd * G * 2);
   w->B = take((size_t)d.Nd * 4 * G * 2);
-  w->gpart = take(d.Nd);
-  w->w = take(d.P);
+  w->gpart = take((size_t)d.Nd * RESID_BLOCKS);
+  w->w = take((size_t)GATHER_SLICES * d.P * 2);
   w->gval = take(8);
+  w->inv = (int32_t*)take(G);
 }
 
-int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta, PhaseWork& w,
-                void* stream) {
+int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
+                const int32_t* pix, PhaseWork& w, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   dim3 g((d.P + GT_P - 1) / GT_P, (d.Nd + GT_N - 1) / GT_N);
   k_cgemm<<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm_est, w.c, d.Nd, d.P, d.N);
   int G = d.nf1 * d.nf2;
   k_make_h<<<(G + 255) / 256, 256, 0, s>>>(w.h, d.nf1, d.nf2, o.lambda, o.ps, o.NA, o.z);
+  k_invmap<<<(G + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G);
+  k_invmap2<<<(d.P + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P);
   return (int)hipGetLastError();
 }
 
@@ -302,18 +349,23 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
   const int G = d.nf1 * d.nf2;
   const size_t nA = (size_t)d.Nd * G * 2, nB = (size_t)d.Nd * 4 * G * 2;
   auto blocks = [](size_t n) { return (unsigned)((n + 255) / 256 > 65535 ? 65535 : (n + 255) / 256); };
-  k_zero<<<blocks(nA), 256, 0, s>>>(w.A, nA);
-  k_zero<<<blocks(nB), 256, 0, s>>>(w.B, nB);
-  k_scatter<<<(d.Nd * d.P + 255) / 256, 256, 0, s>>>(w.A, w.c, phi, pix, d.Nd, d.P, G);
+  (void)nA;
+  (void)nB;
+  (void)blocks;
+  const size_t nG = (size_t)d.Nd * G, nG4 = (size_t)d.Nd * 4 * G;
+  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G);
   if ((e = (int)hipGetLastError())) return e;
   if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s))) return e;
-  k_pad<<<blocks((size_t)d.Nd * G), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
+  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
   if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s))) return e;
-  k_resid<<<d.Nd, 256, 0, s>>>(w.B, Id, w.gpart, 4 * G);
+  k_resid<<<dim3(d.Nd, RESID_BLOCKS), 256, 0, s>>>(w.B, Id, w.gpart, 4 * G);
   if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, -1, tw64, s))) return e;
-  k_crop<<<blocks((size_t)d.Nd * G), 256, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2);
+  k_crop<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2);
   if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, +1, tw64, s))) return e;
-  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.A, w.c, phi, pix, w.gpart, d.Nd, d.P, G);
+  const int per = (d.Nd + GATHER_SLICES - 1) / GATHER_SLICES;
+  const int nsl = (d.Nd + per - 1) / per;
+  k_gather_part<<<dim3((d.P + 255) / 256, nsl), 256, 0, s>>>(w.w, w.A, w.c, pix, d.Nd, d.P, G, per);
+  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, d.Nd * RESID_BLOCKS, nsl, d.P);
   return (int)hipGetLastError();
 }
 
@@ -331,12 +383,14 @@ int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, floa
   const int G = d.nf1 * d.nf2;
   const size_t nA = (size_t)d.Nd * G * 2, nB = (size_t)d.Nd * 4 * G * 2;
   auto blocks = [](size_t n) { return (unsigned)((n + 255) / 256 > 65535 ? 65535 : (n + 255) / 256); };
-  k_zero<<<blocks(nA), 256, 0, s>>>(w.A, nA);
-  k_zero<<<blocks(nB), 256, 0, s>>>(w.B, nB);
-  k_scatter<<<(d.Nd * d.P + 255) / 256, 256, 0, s>>>(w.A, w.c, phi, pix, d.Nd, d.P, G);
+  (void)nA;
+  (void)nB;
+  (void)blocks;
+  const size_t nG = (size_t)d.Nd * G, nG4 = (size_t)d.Nd * 4 * G;
+  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G);
   if ((e = (int)hipGetLastError())) return e;
   if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s))) return e;
-  k_pad<<<blocks((size_t)d.Nd * G), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
+  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
   if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s))) return e;
   size_t n = (size_t)d.Nd * 4 * G;
   k_absq<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.B, I_out, n);

@@ -43,6 +43,7 @@ struct tm_ctx {
   double acc_ms[16] = {0};
   int64_t acc_n[16] = {0};
   std::map<int, int> variant;  // (L1 << 8 | L2) -> FFT digit-order variant
+  double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
 };
 
 namespace {
@@ -221,6 +222,7 @@ int tm_destroy(tm_ctx* c) {
   hipDeviceSynchronize();
   prof_drain(c);
   for (auto e : c->pool) hipEventDestroy(e);
+  if (c->pinned) hipHostFree(c->pinned);
   for (auto& kv : c->ws) hipFree(kv.second.p);
   hipFree(c->tw32);
   hipFree(c->tw64);
@@ -451,14 +453,15 @@ static int phase_check(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
   return TM_OK;
 }
 
-static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const tm_c32* tm_est, const tm_c32* theta,
-                         const tm_optics* o, tmk::PhaseDims& pd, tmk::PhaseWork& w, void* stream) {
+static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
+                         const tm_c32* theta, const tm_optics* o, tmk::PhaseDims& pd, tmk::PhaseWork& w,
+                         void* stream) {
   pd = tmk::PhaseDims{dd->P, dd->N, dd->Nd, dd->nf1, dd->nf2};
   void* base = ws_get(c, WS_PH_BASE, tmk::phase_work_bytes(pd));
   if (!base) return fail(c, TM_ENOMEM, "phase workspace");
   tmk::phase_work_carve(base, pd, &w);
   tmk::PhaseOptics po{o->lambda, o->ps_field, o->NA, o->z};
-  int e = tmk::phase_setup(pd, po, tm_est, theta, w, stream);
+  int e = tmk::phase_setup(pd, po, tm_est, theta, pix, w, stream);
   if (e) return hipfail(c, e, "phase setup");
   return TM_OK;
 }
@@ -473,7 +476,7 @@ extern "C" int tm_phase_objective(tm_ctx* c, const tm_defocus_dims* dd, const in
   HIPCHK(c, hipSetDevice(c->device));
   tmk::PhaseDims pd;
   tmk::PhaseWork w;
-  if ((r = phase_prepare(c, dd, tm_est, theta, o, pd, w, stream))) return r;
+  if ((r = phase_prepare(c, dd, pix, tm_est, theta, o, pd, w, stream))) return r;
   int e = tmk::phase_eval(pd, pix, I_d, phi, grad, w, (const double*)c->tw64, stream);
   if (e) return hipfail(c, e, "phase eval");
   HIPCHK(c, hipMemcpyAsync(g_dev, w.gval, sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -493,7 +496,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   hipStream_t s = (hipStream_t)stream;
   tmk::PhaseDims pd;
   tmk::PhaseWork w;
-  if ((r = phase_prepare(c, dd, tm_est, theta, o, pd, w, stream))) return r;
+  if ((r = phase_prepare(c, dd, pix, tm_est, theta, o, pd, w, stream))) return r;
   const int P = dd->P, m = po->m;
   size_t vb = ((P * sizeof(double) + 255) / 256) * 256;
   char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (5 + 2 * m) + 256 * sizeof(double));
@@ -511,23 +514,60 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   int e = tmk::phase_lb_init(L, P, m, stream);
   if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
   if (e) return hipfail(c, e, "phase eval");
-  double f = 0;
-  HIPCHK(c, hipMemcpyAsync(&f, w.gval, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
+  double* hb = c->pinned;
+  HIPCHK(c, hipMemcpyAsync(hb, w.gval, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  double f = hb[0];
+  // One iteration's direction, first trial (a = 1) and objective/gradient
+  // evaluation replay as a captured graph; one synchronisation then reads the
+  // slope and the trial objective. Further trials (rare) run eagerly.
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  if (po->iters > 0) {
+    hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (he == hipSuccess) {
+      e = tmk::phase_lb_direction(L, P, m, cap);
+      if (!e) e = tmk::phase_lb_trial(L, P, 1.0, cap);
+      if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
+      hipError_t he2 = hipStreamEndCapture(cap, &graph);
+      if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      if (e || he2 != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        hipStreamDestroy(cap);
+        return hipfail(c, e ? e : (int)he2, "phase iteration graph");
+      }
+    } else {
+      if (cap) hipStreamDestroy(cap);
+      return hipfail(c, (int)he, "phase capture stream");
+    }
+  }
+  auto release = [&]() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    if (cap) hipStreamDestroy(cap);
+  };
   for (int it = 0; it < po->iters; ++it) {
-    if ((e = tmk::phase_lb_direction(L, P, m, stream))) return hipfail(c, e, "phase direction");
-    double slope = 0;
-    HIPCHK(c, hipMemcpyAsync(&slope, L.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (!(slope < 0.0)) break;  // zero gradient
-    double a = 1.0, fn = 0.0;
+    double slope = 0, a = 1.0, fn = 0.0;
     bool ok = false;
     for (int h = 0; h < 40; ++h) {
-      if ((e = tmk::phase_lb_trial(L, P, a, stream))) return hipfail(c, e, "phase trial");
-      if ((e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, stream)))
-        return hipfail(c, e, "phase eval");
-      HIPCHK(c, hipMemcpyAsync(&fn, w.gval, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
+      if (h == 0) {
+        hipError_t he = hipGraphLaunch(gexec, s);
+        if (he == hipSuccess) he = hipMemcpyAsync(hb + 1, L.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (he != hipSuccess) { release(); return hipfail(c, (int)he, "phase iteration"); }
+      } else {
+        e = tmk::phase_lb_trial(L, P, a, stream);
+        if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, stream);
+        if (e) { release(); return hipfail(c, e, "phase eval"); }
+      }
+      hipError_t he = hipMemcpyAsync(hb + 2, w.gval, sizeof(double), hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he != hipSuccess) { release(); return hipfail(c, (int)he, "phase read-back"); }
+      slope = hb[1];
+      fn = hb[2];
+      if (!(slope < 0.0)) break;  // zero gradient: nothing to do
       if (fn <= f + 1e-4 * a * slope) {  // Armijo sufficient decrease
         ok = true;
         break;
@@ -535,9 +575,10 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
       a *= 0.5;
     }
     if (!ok) break;
-    if ((e = tmk::phase_lb_accept(L, P, m, a, stream))) return hipfail(c, e, "phase accept");
+    if ((e = tmk::phase_lb_accept(L, P, m, a, stream))) { release(); return hipfail(c, e, "phase accept"); }
     f = fn;
   }
+  release();
   HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (g_out) *g_out = f;
@@ -554,7 +595,7 @@ extern "C" int tm_defocus_forward(tm_ctx* c, const tm_defocus_dims* dd, const in
   HIPCHK(c, hipSetDevice(c->device));
   tmk::PhaseDims pd;
   tmk::PhaseWork w;
-  if ((r = phase_prepare(c, dd, tmr, theta, o, pd, w, stream))) return r;
+  if ((r = phase_prepare(c, dd, pix, tmr, theta, o, pd, w, stream))) return r;
   int e = tmk::phase_images(pd, pix, phi, I_out, w, (const double*)c->tw64, stream);
   if (e) return hipfail(c, e, "defocus images");
   return TM_OK;
