@@ -272,10 +272,14 @@ __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, cons
     z2 q = zmulc(w, z2{cs, sn});  // w conj(u)
     grad[p] = -4.0 * q.y;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0) {  // objective: block-wide sum of the residual partials
+    __shared__ double red[4];
     double s = 0;
-    for (int i = 0; i < ngp; ++i) s += gpart[i];
-    gval[0] = s;
+    for (int i = threadIdx.x; i < ngp; i += 256) s += gpart[i];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) gval[0] = red[0] + red[1] + red[2] + red[3];
   }
 }
 
