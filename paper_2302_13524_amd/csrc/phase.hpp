@@ -22,6 +22,7 @@ struct PhaseWork {
   double* w;      // [slices][P] complex partial sums of the gradient gather
   double* gval;   // [1] objective
   int32_t* inv;   // [nf1 nf2] row index of each field pixel, -1 outside the rows
+  int* skip;      // [1] set to 1 when the L-BFGS solve has ended: evaluation kernels return at once
 };
 
 size_t phase_work_bytes(const PhaseDims& d);
@@ -47,11 +48,13 @@ struct PhaseLb {
   double* d;      // [P]
   double* S;      // [m][P]
   double* Y;      // [m][P]
-  double* sc;     // [8 + 2m]: head, count, slope, dnorm, ..., sy[m], yy[m]
+  double* sc;     // [8 + 2m] iteration state (see phase_kernels.hip)
 };
-int phase_lb_init(PhaseLb& L, int P, int m, void* stream);
-int phase_lb_direction(PhaseLb& L, int P, int m, void* stream);
-int phase_lb_trial(PhaseLb& L, int P, double alpha, void* stream);
-int phase_lb_accept(PhaseLb& L, int P, int m, double alpha, void* stream);
+// Device-controlled iterations (see phase_kernels.hip): init after the first
+// evaluation, then per iteration step, trial, evaluation at phit, decide.
+int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream);
+int phase_lb_step(PhaseLb& L, int P, int m, int iters, int* skip, void* stream);
+int phase_lb_trial(PhaseLb& L, int P, const int* skip, void* stream);
+int phase_lb_decide(PhaseLb& L, int P, int m, const double* gval, const int* skip, void* stream);
 
 }  // namespace tmk

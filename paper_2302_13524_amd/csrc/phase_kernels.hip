@@ -89,6 +89,8 @@ __global__ void k_make_h(double* h, int nf1, int nf2, double lam, double ps, dou
   h[2 * i + 1] = r.y;
 }
 
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
 // inv[g] = p for g = pix[p], -1 elsewhere (pixels are distinct and in range)
 __global__ void k_invmap(int32_t* inv, const int32_t* pix, int P, int G) {
   int i = blockIdx.x * 256 + threadIdx.x;
@@ -101,7 +103,8 @@ __global__ void k_invmap2(int32_t* inv, const int32_t* pix, int P) {
 
 // A[n][g] = c[n][p] e^{j phi_p} where g = pix[p], 0 elsewhere (writes the whole grid)
 __global__ void k_scatter_full(double* A, const double* c, const double* phi, const int32_t* inv, int Nd, int P,
-                               int G) {
+                               int G, const int* skip) {
+  if (skip && *skip) return;
   size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (size_t)Nd * G) return;
   int n = (int)(i / G), g = (int)(i % G);
@@ -121,7 +124,9 @@ __global__ void k_scatter_full(double* A, const double* c, const double* phi, co
 // Line li: outer = li / inner_n, inner = li % inner_n; element j at
 // (outer * os + inner * is + j * es) complex entries. sign -1: forward DFT.
 __global__ void __launch_bounds__(256) k_lines(double* buf, int nlines, int inner_n, long os, long is, long es,
-                                               int LL, int sign, double scale, const double* tw64) {
+                                               int LL, int sign, double scale, const double* tw64,
+                                               const int* skip) {
+  if (skip && *skip) return;
   extern __shared__ double sm[];
   const int L = 1 << LL;
   const int half = L >> 1;
@@ -180,7 +185,8 @@ __device__ __forceinline__ int unpad(int a2, int n) {
 }
 
 // B[n][a2][b2] = h[a][b] A[n][a][b] at the padded positions, 0 elsewhere (whole grid)
-__global__ void k_pad_full(double* B, const double* A, const double* h, int Nd, int nf1, int nf2) {
+__global__ void k_pad_full(double* B, const double* A, const double* h, int Nd, int nf1, int nf2, const int* skip) {
+  if (skip && *skip) return;
   size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   size_t G4 = (size_t)4 * nf1 * nf2;
   if (i >= Nd * G4) return;
@@ -200,7 +206,8 @@ __global__ void k_pad_full(double* B, const double* A, const double* h, int Nd, 
 }
 
 // A[n][a][b] = conj(h[a][b]) * B[n][pad(a)][pad(b)]
-__global__ void k_crop(double* A, const double* B, const double* h, int Nd, int nf1, int nf2) {
+__global__ void k_crop(double* A, const double* B, const double* h, int Nd, int nf1, int nf2, const int* skip) {
+  if (skip && *skip) return;
   size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   size_t G = (size_t)nf1 * nf2;
   if (i >= Nd * G) return;
@@ -217,7 +224,8 @@ __global__ void k_crop(double* A, const double* B, const double* h, int Nd, int 
 
 // r = I - |a|^2, a <- a r (in place); partial sums of r^2 per (image, block)
 // into gpart[n * gridDim.y + blockIdx.y]
-__global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, double* gpart, int npix) {
+__global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, double* gpart, int npix, const int* skip) {
+  if (skip && *skip) return;
   __shared__ double red[4];
   int n = blockIdx.x;
   double s = 0;
@@ -238,7 +246,9 @@ __global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, doubl
 // Partial w_s[p] = sum over the images n of slice s of conj(c[n][p]) A[n][pix[p]]:
 // threads run over consecutive p (coalesced c reads), grid.y over image slices.
 __global__ void __launch_bounds__(256) k_gather_part(double* wpart, const double* A, const double* c,
-                                                      const int32_t* pix, int Nd, int P, int G, int per) {
+                                                      const int32_t* pix, int Nd, int P, int G, int per,
+                                                      const int* skip) {
+  if (skip && *skip) return;
   int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
   int n0 = blockIdx.y * per, n1 = min(Nd, n0 + per);
@@ -259,7 +269,8 @@ __global__ void __launch_bounds__(256) k_gather_part(double* wpart, const double
 // grad[p] = -4 Im(conj(u_p) w[p]) with w the sum of the slices; gval = sum of
 // the residual partials
 __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, const double* wpart, const double* phi,
-                                                 const double* gpart, int ngp, int nslice, int P) {
+                                                 const double* gpart, int ngp, int nslice, int P, const int* skip) {
+  if (skip && *skip) return;
   int p = blockIdx.x * 256 + threadIdx.x;
   if (p < P) {
     z2 w{0.0, 0.0};
@@ -284,7 +295,7 @@ __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, cons
 }
 
 int lines(double* buf, int nlines, int inner_n, long os, long is, long es, int L, int sign, double scale,
-          const double* tw64, hipStream_t s) {
+          const double* tw64, hipStream_t s, const int* skip) {
   int LL = ilog2(L);
   int half = L / 2 > 0 ? L / 2 : 1;
   int lpw = 256 / half > 0 ? 256 / half : 1;
@@ -293,17 +304,17 @@ int lines(double* buf, int nlines, int inner_n, long os, long is, long es, int L
   if (L == 1) {
     return 0;
   }
-  k_lines<<<blocks, 256, lds, s>>>(buf, nlines, inner_n, os, is, es, LL, sign, scale, tw64);
+  k_lines<<<blocks, 256, lds, s>>>(buf, nlines, inner_n, os, is, es, LL, sign, scale, tw64, skip);
   return (int)hipGetLastError();
 }
 
 // 2-D transform of Nd grids g1 x g2 in buf; sign -1 forward, +1 inverse, unitary scaling.
-int fft2(double* buf, int Nd, int g1, int g2, int sign, const double* tw64, hipStream_t s) {
+int fft2(double* buf, int Nd, int g1, int g2, int sign, const double* tw64, hipStream_t s, const int* skip) {
   int e;
   // along axis 2 (contiguous rows): lines = Nd*g1, element stride 1
-  if ((e = lines(buf, Nd * g1, 1, g2, 0, 1, g2, sign, 1.0 / sqrt((double)g2), tw64, s))) return e;
+  if ((e = lines(buf, Nd * g1, 1, g2, 0, 1, g2, sign, 1.0 / sqrt((double)g2), tw64, s, skip))) return e;
   // along axis 1: lines = Nd*g2, outer n stride g1*g2, inner column stride 1, element stride g2
-  if ((e = lines(buf, Nd * g2, g2, (long)g1 * g2, 1, g2, g1, sign, 1.0 / sqrt((double)g1), tw64, s))) return e;
+  if ((e = lines(buf, Nd * g2, g2, (long)g1 * g2, 1, g2, g1, sign, 1.0 / sqrt((double)g1), tw64, s, skip))) return e;
   return 0;
 }
 
@@ -312,7 +323,7 @@ int fft2(double* buf, int Nd, int g1, int g2, int sign, const double* tw64, hipS
 size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
   size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 4 * G * 2 +
-               (size_t)d.Nd * RESID_BLOCKS + (size_t)GATHER_SLICES * d.P * 2 + 8 + G;
+               (size_t)d.Nd * RESID_BLOCKS + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1;
   return dbl * sizeof(double) + 8 * 256;
 }
 
@@ -332,6 +343,7 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->w = take((size_t)GATHER_SLICES * d.P * 2);
   w->gval = take(8);
   w->inv = (int32_t*)take(G);
+  w->skip = (int*)take(1);
 }
 
 int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
@@ -343,6 +355,7 @@ int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, co
   k_make_h<<<(G + 255) / 256, 256, 0, s>>>(w.h, d.nf1, d.nf2, o.lambda, o.ps, o.NA, o.z);
   k_invmap<<<(G + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G);
   k_invmap2<<<(d.P + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P);
+  k_set_int<<<1, 1, 0, s>>>(w.skip, 0);
   return (int)hipGetLastError();
 }
 
@@ -357,19 +370,19 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
   (void)nB;
   (void)blocks;
   const size_t nG = (size_t)d.Nd * G, nG4 = (size_t)d.Nd * 4 * G;
-  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G);
+  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G, w.skip);
   if ((e = (int)hipGetLastError())) return e;
-  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s))) return e;
-  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
-  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s))) return e;
-  k_resid<<<dim3(d.Nd, RESID_BLOCKS), 256, 0, s>>>(w.B, Id, w.gpart, 4 * G);
-  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, -1, tw64, s))) return e;
-  k_crop<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2);
-  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, +1, tw64, s))) return e;
+  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s, w.skip))) return e;
+  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2, w.skip);
+  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s, w.skip))) return e;
+  k_resid<<<dim3(d.Nd, RESID_BLOCKS), 256, 0, s>>>(w.B, Id, w.gpart, 4 * G, w.skip);
+  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, -1, tw64, s, w.skip))) return e;
+  k_crop<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2, w.skip);
+  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, +1, tw64, s, w.skip))) return e;
   const int per = (d.Nd + GATHER_SLICES - 1) / GATHER_SLICES;
   const int nsl = (d.Nd + per - 1) / per;
-  k_gather_part<<<dim3((d.P + 255) / 256, nsl), 256, 0, s>>>(w.w, w.A, w.c, pix, d.Nd, d.P, G, per);
-  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, d.Nd * RESID_BLOCKS, nsl, d.P);
+  k_gather_part<<<dim3((d.P + 255) / 256, nsl), 256, 0, s>>>(w.w, w.A, w.c, pix, d.Nd, d.P, G, per, w.skip);
+  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, d.Nd * RESID_BLOCKS, nsl, d.P, w.skip);
   return (int)hipGetLastError();
 }
 
@@ -391,11 +404,11 @@ int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, floa
   (void)nB;
   (void)blocks;
   const size_t nG = (size_t)d.Nd * G, nG4 = (size_t)d.Nd * 4 * G;
-  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G);
+  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G, w.skip);
   if ((e = (int)hipGetLastError())) return e;
-  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s))) return e;
-  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2);
-  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s))) return e;
+  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s, w.skip))) return e;
+  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2, w.skip);
+  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s, w.skip))) return e;
   size_t n = (size_t)d.Nd * 4 * G;
   k_absq<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.B, I_out, n);
   return (int)hipGetLastError();
@@ -421,10 +434,16 @@ __device__ double dotv(const double* a, const double* b, int P, double* red) {
   return bsum(s, red);
 }
 
-// sc: [0] head, [1] count, [2] slope of d, [3] unused, [8..8+m) sy, [8+m..8+2m) yy
-__global__ void __launch_bounds__(PWG) k_pdir(PhaseLb L, int P, int m) {
-  __shared__ double red[PWG / 64];
-  double* sc = L.sc;
+// Line search and iteration control on the device, so that iterations replay
+// back-to-back without host synchronisation. State sc (doubles):
+// [0] head, [1] count, [2] slope of d, [3] step a, [4] objective f at phi,
+// [5] accepted iterations, [6] last trial accepted, [7] halvings of this
+// direction; [8..8+m) s^T y, [8+m..8+2m) y^T y. *skip = 1 ends the solve
+// (every later kernel returns at once).
+// Per iteration: k_pstep (new direction after an accepted trial, else halve
+// a), k_ptrial (phi_t = phi + a d), objective and gradient at phi_t,
+// k_pdecide (Armijo f_t <= f + 1e-4 a slope: accept and update the history).
+__device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc) {
   int head = (int)sc[0], count = (int)sc[1];
   const double* sy = sc + 8;
   const double* yy = sc + 8 + m;
@@ -458,7 +477,7 @@ __global__ void __launch_bounds__(PWG) k_pdir(PhaseLb L, int P, int m) {
   for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = -L.d[i];
   __syncthreads();
   double slope = dotv(L.g, L.d, P, red);
-  if (!(slope < 0.0)) {
+  if (!(slope < 0.0)) {  // not a descent direction: drop the history, use -g/||g||
     double gn = sqrt(dotv(L.g, L.g, P, red));
     double inv = gn > 0 ? 1.0 / gn : 0.0;
     for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = -L.g[i] * inv;
@@ -469,19 +488,52 @@ __global__ void __launch_bounds__(PWG) k_pdir(PhaseLb L, int P, int m) {
   if (threadIdx.x == 0) sc[2] = slope;
 }
 
-__global__ void k_ptrial(PhaseLb L, int P, double alpha) {
-  int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < P) L.phit[i] = L.phi[i] + alpha * L.d[i];
-}
-
-__global__ void __launch_bounds__(PWG) k_paccept(PhaseLb L, int P, int m, double alpha) {
+__global__ void __launch_bounds__(PWG) k_pstep(PhaseLb L, int P, int m, int iters, int* skip) {
   __shared__ double red[PWG / 64];
   double* sc = L.sc;
+  if (*skip) return;
+  __syncthreads();  // every thread has read *skip before thread 0 may set it
+  if (sc[6] != 0.0) {
+    if (sc[5] >= (double)iters) {
+      if (threadIdx.x == 0) *skip = 1;
+      return;
+    }
+    direction(L, P, m, red, sc);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sc[3] = 1.0;
+      sc[7] = 0.0;
+      if (!(sc[2] < 0.0)) *skip = 1;  // zero gradient
+    }
+  } else if (threadIdx.x == 0) {
+    sc[7] += 1.0;
+    if (sc[7] >= 40.0) *skip = 1;  // no sufficient decrease along d: stop
+    else sc[3] *= 0.5;
+  }
+}
+
+__global__ void k_ptrial(PhaseLb L, int P, const int* skip) {
+  if (*skip) return;
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < P) L.phit[i] = L.phi[i] + L.sc[3] * L.d[i];
+}
+
+__global__ void __launch_bounds__(PWG) k_pdecide(PhaseLb L, int P, int m, const double* gval, const int* skip) {
+  __shared__ double red[PWG / 64];
+  if (*skip) return;
+  double* sc = L.sc;
+  double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
+  bool ok = fn <= f + 1e-4 * a * slope;
+  __syncthreads();
+  if (!ok) {
+    if (threadIdx.x == 0) sc[6] = 0.0;
+    return;
+  }
   int head = (int)sc[0], count = (int)sc[1];
   double* Sh = L.S + (size_t)head * P;
   double* Yh = L.Y + (size_t)head * P;
   for (int i = threadIdx.x; i < P; i += PWG) {
-    Sh[i] = alpha * L.d[i];
+    Sh[i] = a * L.d[i];
     Yh[i] = L.gt[i] - L.g[i];
   }
   __syncthreads();
@@ -491,34 +543,46 @@ __global__ void __launch_bounds__(PWG) k_paccept(PhaseLb L, int P, int m, double
     L.phi[i] = L.phi[i] + Sh[i];
     L.g[i] = L.gt[i];
   }
-  if (threadIdx.x == 0 && sy > 0.0) {
-    sc[8 + head] = sy;
-    sc[8 + m + head] = yy;
-    sc[0] = (head + 1) % m;
-    sc[1] = count < m ? count + 1 : m;
+  if (threadIdx.x == 0) {
+    if (sy > 0.0) {
+      sc[8 + head] = sy;
+      sc[8 + m + head] = yy;
+      sc[0] = (head + 1) % m;
+      sc[1] = count < m ? count + 1 : m;
+    }
+    sc[4] = fn;
+    sc[5] += 1.0;
+    sc[6] = 1.0;
   }
 }
 
-__global__ void k_pinit(double* sc, int n) {
+// start: clear the state, take f at the start point, allow the first direction
+__global__ void k_pinit(double* sc, int n, const double* gval, int* skip) {
   int i = threadIdx.x;
   if (i < n) sc[i] = 0.0;
+  __syncthreads();
+  if (i == 0) {
+    sc[4] = gval[0];
+    sc[6] = 1.0;
+    *skip = 0;
+  }
 }
 }  // namespace
 
-int phase_lb_init(PhaseLb& L, int P, int m, void* stream) {
-  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, 8 + 2 * m);
+int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream) {
+  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, 8 + 2 * m, gval, skip);
   return (int)hipGetLastError();
 }
-int phase_lb_direction(PhaseLb& L, int P, int m, void* stream) {
-  k_pdir<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m);
+int phase_lb_step(PhaseLb& L, int P, int m, int iters, int* skip, void* stream) {
+  k_pstep<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, iters, skip);
   return (int)hipGetLastError();
 }
-int phase_lb_trial(PhaseLb& L, int P, double alpha, void* stream) {
-  k_ptrial<<<(P + 255) / 256, 256, 0, (hipStream_t)stream>>>(L, P, alpha);
+int phase_lb_trial(PhaseLb& L, int P, const int* skip, void* stream) {
+  k_ptrial<<<(P + 255) / 256, 256, 0, (hipStream_t)stream>>>(L, P, skip);
   return (int)hipGetLastError();
 }
-int phase_lb_accept(PhaseLb& L, int P, int m, double alpha, void* stream) {
-  k_paccept<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, alpha);
+int phase_lb_decide(PhaseLb& L, int P, int m, const double* gval, const int* skip, void* stream) {
+  k_pdecide<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, gval, skip);
   return (int)hipGetLastError();
 }
 

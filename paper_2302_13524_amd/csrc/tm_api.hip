@@ -511,74 +511,59 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   L.Y = (double*)(lb + (5 + m) * vb);
   L.sc = (double*)(lb + (5 + 2 * m) * vb);
   HIPCHK(c, hipMemcpyAsync(L.phi, phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
-  int e = tmk::phase_lb_init(L, P, m, stream);
-  if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
-  if (e) return hipfail(c, e, "phase eval");
+  int e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
+  if (!e) e = tmk::phase_lb_init(L, P, m, w.gval, w.skip, stream);
+  if (e) return hipfail(c, e, "phase start");
   if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
   double* hb = c->pinned;
-  HIPCHK(c, hipMemcpyAsync(hb, w.gval, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  double f = hb[0];
-  // One iteration's direction, first trial (a = 1) and objective/gradient
-  // evaluation replay as a captured graph; one synchronisation then reads the
-  // slope and the trial objective. Further trials (rare) run eagerly.
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // One iteration (new direction or halved step, trial point, objective and
+  // gradient there, Armijo decision) is a captured graph; the line-search
+  // control lives in device state, so replays are queued back-to-back and
+  // the host reads the state only between batches of replays.
   if (po->iters > 0) {
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
     if (he == hipSuccess) {
-      e = tmk::phase_lb_direction(L, P, m, cap);
-      if (!e) e = tmk::phase_lb_trial(L, P, 1.0, cap);
+      e = tmk::phase_lb_step(L, P, m, po->iters, w.skip, cap);
+      if (!e) e = tmk::phase_lb_trial(L, P, w.skip, cap);
       if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
+      if (!e) e = tmk::phase_lb_decide(L, P, m, w.gval, w.skip, cap);
       hipError_t he2 = hipStreamEndCapture(cap, &graph);
       if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-      if (e || he2 != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
-        hipStreamDestroy(cap);
-        return hipfail(c, e ? e : (int)he2, "phase iteration graph");
-      }
+      if (!e && he2 != hipSuccess) e = (int)he2;
     } else {
-      if (cap) hipStreamDestroy(cap);
-      return hipfail(c, (int)he, "phase capture stream");
+      e = (int)he;
     }
-  }
-  auto release = [&]() {
+    // at most 40 trials per accepted iteration, plus the replay that ends the solve
+    const long limit = (long)po->iters * 41 + 1;
+    long launched = 0, batch = po->iters + 8;
+    while (!e && launched < limit) {
+      long nb = std::min(batch, limit - launched);
+      for (long i = 0; i < nb && !e; ++i) e = (int)hipGraphLaunch(gexec, s);
+      launched += nb;
+      if (e) break;
+      int* hs = (int*)(hb + 2);
+      he = hipMemcpyAsync(hb, L.sc + 5, sizeof(double), hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipMemcpyAsync(hs, w.skip, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he != hipSuccess) {
+        e = (int)he;
+        break;
+      }
+      if (*hs != 0 || hb[0] >= (double)po->iters) break;
+      batch = 16;
+    }
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
     if (cap) hipStreamDestroy(cap);
-  };
-  for (int it = 0; it < po->iters; ++it) {
-    double slope = 0, a = 1.0, fn = 0.0;
-    bool ok = false;
-    for (int h = 0; h < 40; ++h) {
-      if (h == 0) {
-        hipError_t he = hipGraphLaunch(gexec, s);
-        if (he == hipSuccess) he = hipMemcpyAsync(hb + 1, L.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s);
-        if (he != hipSuccess) { release(); return hipfail(c, (int)he, "phase iteration"); }
-      } else {
-        e = tmk::phase_lb_trial(L, P, a, stream);
-        if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, stream);
-        if (e) { release(); return hipfail(c, e, "phase eval"); }
-      }
-      hipError_t he = hipMemcpyAsync(hb + 2, w.gval, sizeof(double), hipMemcpyDeviceToHost, s);
-      if (he == hipSuccess) he = hipStreamSynchronize(s);
-      if (he != hipSuccess) { release(); return hipfail(c, (int)he, "phase read-back"); }
-      slope = hb[1];
-      fn = hb[2];
-      if (!(slope < 0.0)) break;  // zero gradient: nothing to do
-      if (fn <= f + 1e-4 * a * slope) {  // Armijo sufficient decrease
-        ok = true;
-        break;
-      }
-      a *= 0.5;
-    }
-    if (!ok) break;
-    if ((e = tmk::phase_lb_accept(L, P, m, a, stream))) { release(); return hipfail(c, e, "phase accept"); }
-    f = fn;
+    if (e) return hipfail(c, e, "phase iterations");
   }
-  release();
+  HIPCHK(c, hipMemcpyAsync(hb + 3, L.sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double f = hb[3];
   HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (g_out) *g_out = f;
