@@ -46,13 +46,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--spectral-iters", type=int, default=30)
+    ap.add_argument("--spectral-iters", type=int, default=40)
     ap.add_argument("--phase-iters", type=int, default=100)
     ap.add_argument("--max-iters", type=int, default=300)
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows in the CPU-baseline sample (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="32x32 modes, 512 rows (quick check)")
     ap.add_argument("--er-iters", type=int, default=0, help="skip the instrumented search and use this count")
+    ap.add_argument("--er-momentum", type=float, default=0.8,
+                    help="Nesterov factor of the error-reduction iterations (0: plain ER)")
+    ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 12-TM batch")
@@ -133,17 +136,21 @@ def main():
 
     sp = args.spectral_iters
 
+    beta = args.er_momentum
+
     def opts(method, iters, start="spectral"):
         return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=3.0,
-                                spectral_momentum=0.98)
+                                spectral_momentum=0.98, er_momentum=beta if method == "er" else 0.0)
 
-    # ---- untimed instrumented run: iterations to mean fidelity 0.99
+    # ---- untimed instrumented run: iterations to mean fidelity 0.99 (each count run
+    # from the start, since the momentum iteration carries the previous iterate)
     t = v0t.clone()
     tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 0))
     f_start = fidelity(t).mean().item()
     n_er = args.er_iters or None
     for it in range(1, 0 if n_er else args.max_iters + 1):
-        tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 1, start="given"), stats=False)
+        t = v0t.clone()
+        tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", it), stats=False)
         if fidelity(t).mean().item() >= 0.99:
             n_er = it
             break
@@ -212,7 +219,7 @@ def main():
 
     # roofline of the fused error-reduction kernel (one launch = one iteration over all P rows)
     er_avg_ms = er_ms / max(er_n, 1)
-    alg_bytes = P * (K * N * 4 + 2 * N * 8)
+    alg_bytes = P * (K * N * 4 + (4 if beta > 0 else 2) * N * 8)
     flops_fft = 2 * K * 5 * N * np.log2(N)
     alg_flops = P * (flops_fft + 30 * K * N)
     achieved = alg_bytes / (er_avg_ms * 1e-3) / 1e9
@@ -241,7 +248,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "P": P, "N": N, "grid": [n1, n2], "K": K,
-                   "start": f"truncated spectral, {sp} heavy-ball steps", "solver": "error reduction",
+                   "start": f"truncated spectral, {sp} heavy-ball steps",
+                   "solver": f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction",
                    "iters_to_0.99": n_er, "phase_iters": args.phase_iters},
         "roofline": roofline,
         "roofline_alu": roofline_alu,
@@ -265,7 +273,7 @@ def main():
     if not args.no_batch and not args.small:
         out["batch"] = batch_variant(ctx, args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, P)
+        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P)
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -285,11 +293,13 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
     torch.cuda.synchronize()
     train_s = time.perf_counter() - a
     f_start = float(fidelity(tm.tm_mlp_start(ctx, net, It, K, N)).mean().item())
-    t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp)
+    t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp,
+                                                   er_momentum=args.er_momentum)
     torch.cuda.synchronize()
     a = time.perf_counter()
     for _ in range(3):
-        t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp)
+        t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp,
+                                                   er_momentum=args.er_momentum)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) * 1e3 / 3
     return {"rows_per_s": round(P / (ms * 1e-3), 1), "retrieval_ms": round(ms, 3),
@@ -325,9 +335,9 @@ def batch_variant(ctx, args):
         truths.append(T / torch.linalg.vector_norm(T, dim=1, keepdim=True))
     log(f"batch inputs {time.perf_counter() - a:.1f}s")
     tuned = {f"{n1}x{n2}": tm.autotune(ctx, n1, n2, 4, 512, bf16=True) for n1, n2, _, _ in shapes[:4]}
-    iters, sp = 60, args.spectral_iters
-    b = tm.Batch(ctx, probs, tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True),
-                 use_graph=True)
+    iters, sp, beta = args.batch_iters, args.spectral_iters, args.er_momentum
+    b = tm.Batch(ctx, probs, tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True,
+                                              er_momentum=beta), use_graph=True)
 
     def run():
         for p in probs:
@@ -355,10 +365,10 @@ def batch_variant(ctx, args):
                        "rows_flagged": int((tm.decode_stats(p["stats"]).flags.numpy() & 1).sum())})
     b.close()
     return {"rows_per_s": round(rows / (ms * 1e-3), 1), "ms": round(ms, 3), "rows": rows, "tms": len(shapes),
-            "iters": iters, "spectral_iters": sp, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
+            "iters": iters, "er_momentum": beta, "spectral_iters": sp, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
 
 
-def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, P):
+def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P):
     """The FP64 oracle (FFT form of A) on a bounded sample of rows: the same
     spectral start and error-reduction iterations, timed on the host."""
     from oracle import operators as ops
@@ -370,9 +380,7 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, P):
     def run(rows):
         I = I_np[rows].astype(np.float64)
         t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=3.0, momentum=0.98)
-        for _ in range(n_er):
-            t = rt.er_step(op, I, t)
-        return t
+        return rt.er_accelerated(op, I, t, n_er, beta)
 
     g = np.random.default_rng(123)
     probe = np.sort(g.choice(P, 4, replace=False))
@@ -387,6 +395,7 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, P):
     fid = rt.fidelity(t, T[rows].astype(np.complex128))
     return {"value": round(nrows / dt, 3), "unit": "rows/s", "cores": 1, "kind": "oracle",
             "sample": f"{nrows} of {P} rows, FP64 numpy FFT form of A, {sp} spectral + {n_er} ER iterations "
+                      f"(Nesterov factor {beta}) "
                       f"({dt:.1f}s)", "mean_fidelity": round(float(fid.mean()), 6),
             "host_cpus": len(os.sched_getaffinity(0))}
 

@@ -126,6 +126,7 @@ typedef struct {
   int32_t spectral_iters;  /* power-iteration steps for TM_START_SPECTRAL                */
   float spectral_tau;      /* weight truncation w = min(I/mean(I_p), tau), e.g. 3        */
   float spectral_momentum; /* heavy-ball factor c in [0, 1): beta = (c lambda)^2/4       */
+  float er_momentum;       /* ER only: Nesterov factor b in [0, 1): t <- ER(t + b (t - t_prev)); 0 = plain ER */
 } tm_retrieve_opts;
 
 /* Per-row results written to device memory. */

@@ -86,6 +86,19 @@ def er_step(op, I: np.ndarray, t: np.ndarray) -> np.ndarray:
     return op.adjoint(np.sqrt(I) * phase_of(y)) / (op.K * op.N)
 
 
+def er_accelerated(op, I: np.ndarray, t0: np.ndarray, iters: int, beta: float) -> np.ndarray:
+    """Error reduction with Nesterov momentum: z = t + beta (t - t_prev),
+    t_new = er_step(z); t_prev starts equal to t0 (so the first step is plain
+    ER). ER is a gradient step of length 1/(K N) on the amplitude cost, and
+    this is Nesterov's acceleration of that step. beta = 0 gives plain ER."""
+    t = np.array(t0, dtype=np.complex128)
+    tp = t.copy()
+    for _ in range(iters):
+        z = t + beta * (t - tp)
+        tp, t = t, er_step(op, I, z)
+    return t
+
+
 def backprop_start(op, I: np.ndarray) -> np.ndarray:
     """t0 = (A^H A)^{-1} A^H sqrt(I) = A^H sqrt(I) / (K N) (Eq. backpropagation)."""
     return op.adjoint(np.sqrt(I)) / (op.K * op.N)

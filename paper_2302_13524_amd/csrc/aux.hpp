@@ -8,6 +8,9 @@ int launch_row_isum(const void* I, int bf16, int64_t len, int P, double* rowsum,
 int launch_row_rescale(void* t, int N, int P, int mode, const double* rowsum, double denom,
                        void* stream);
 int launch_fill_zero(void* p, int64_t bytes, void* stream);
+// device-to-device copy by a kernel (graph-capturable); bytes and both
+// pointers must be multiples of 8
+int launch_copy(void* dst, const void* src, int64_t bytes, void* stream);
 // fill n floats with hash-derived values in [lo, hi) (synthetic tuning data)
 int launch_fill_hash(float* p, int64_t n, uint32_t seed, float lo, float hi, void* stream);
 int launch_finalize(void* stats, int P, const double* sums64, const float* sums, int nsum,

@@ -72,6 +72,13 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint32_t* p, int64_t n) {
   for (; i < n; i += stride) p[i] = 0u;
 }
 
+template <typename V>
+__global__ void __launch_bounds__(256) k_copy(V* dst, const V* src, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(256) k_fill_hash(float* p, int64_t n, uint32_t seed, float lo, float hi) {
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * 256;
@@ -133,6 +140,18 @@ int launch_fill_zero(void* p, int64_t bytes, void* s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   k_fill_zero<<<(int)blocks, 256, 0, (hipStream_t)s>>>((uint32_t*)p, n);
+  return (int)hipGetLastError();
+}
+int launch_copy(void* dst, const void* src, int64_t bytes, void* s) {
+  if (bytes <= 0) return 0;
+  const uintptr_t al = (uintptr_t)dst | (uintptr_t)src | (uintptr_t)bytes;
+  if (al & 7) return (int)hipErrorInvalidValue;
+  const int w = (al & 15) ? 8 : 16;
+  int64_t n = bytes / w;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (w == 16) k_copy<uint4><<<(int)blocks, 256, 0, (hipStream_t)s>>>((uint4*)dst, (const uint4*)src, n);
+  else k_copy<uint2><<<(int)blocks, 256, 0, (hipStream_t)s>>>((uint2*)dst, (const uint2*)src, n);
   return (int)hipGetLastError();
 }
 int launch_fill_hash(float* p, int64_t n, uint32_t seed, float lo, float hi, void* s) {

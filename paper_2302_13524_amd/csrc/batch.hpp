@@ -35,6 +35,8 @@ struct BatchArgs {
   int n_items;
   int with_sums;         // pass the problems' sums pointers (else null)
   float tau, momentum;
+  float er_beta;         // ER Nesterov factor; t and t_prev alternate between t and vprev
+  int er_swap;           // with er_beta: the current iterate is in vprev (odd iterations)
   const cx<float>* tw32;
 };
 

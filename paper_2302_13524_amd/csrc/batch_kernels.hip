@@ -55,10 +55,15 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.P = pr.P;
     a.K = pr.K;
     a.masks = pr.masks;
-    a.tin = pr.t;
-    a.tout = pr.t;
-    a.din = pr.vprev;
-    a.tout2 = pr.vprev;
+    // ER with momentum reads t and t_prev and overwrites t_prev; the two
+    // buffers swap roles every iteration
+    const bool mom = MODE == BATCH_ER && b.er_beta != 0.f;
+    cx<float>* cur = (mom && b.er_swap) ? pr.vprev : pr.t;
+    cx<float>* oth = (mom && b.er_swap) ? pr.t : pr.vprev;
+    a.tin = cur;
+    a.tout = mom ? oth : cur;
+    a.din = oth;
+    a.tout2 = oth;
     a.I = pr.I;
     a.yin = nullptr;
     a.yout = nullptr;
@@ -67,6 +72,7 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.rowmean = pr.rowmean;
     a.tau = b.tau;
     a.momentum = b.momentum;
+    a.er_beta = mom ? b.er_beta : 0.f;
     a.out_bf16 = 0;
     a.tw32 = b.tw32;
     a.tw64 = nullptr;

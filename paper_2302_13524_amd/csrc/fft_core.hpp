@@ -267,11 +267,16 @@ struct PassGeo {
 };
 
 // Twiddle W_B^{l k} = W_LA^{l k 2^(LA-LB)} from an axis table of W_LA^i.
+// The tables are read through the constant address space: they are never
+// written while a kernel runs, so a wave-uniform index becomes a scalar load
+// even where the compiler cannot prove it (after stores, in non-inlined
+// functions).
 template <class PL, int P, typename T>
 __device__ __forceinline__ cx<T> twid(const cx<T>* __restrict__ tw, int l, int k) {
   using G = PassGeo<PL, P>;
   int idx = (l * k) << (G::LA - G::LB);
-  return tw[idx];
+  const __attribute__((address_space(4))) T* c = (const __attribute__((address_space(4))) T*)tw;
+  return cx<T>{c[2 * idx], c[2 * idx + 1]};
 }
 
 // Twiddle position l of butterfly j. Lanes of a wave run along the other
@@ -379,11 +384,22 @@ struct LayoutL {
   static __device__ __forceinline__ int kbase(int ltid, int j);
 };
 
+// A pointer every lane of the wave holds, moved to scalar registers (inside
+// non-inlined functions arguments are otherwise taken to differ per lane).
+template <typename V>
+__device__ __forceinline__ V* wave_uniform(V* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (V*)(((uint64_t)hi << 32) | lo);
+}
+
 // Twiddle tables: axis 1 at tw1 (n1 entries W_n1^i), axis 2 at tw2.
 template <typename T>
 struct Tw {
   const cx<T>* __restrict__ t1;
   const cx<T>* __restrict__ t2;
+  __device__ Tw(const cx<T>* a, const cx<T>* b) : t1(wave_uniform(a)), t2(wave_uniform(b)) {}
 };
 
 template <class PL, int P, typename T>

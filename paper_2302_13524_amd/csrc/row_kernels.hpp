@@ -35,6 +35,7 @@ struct RowArgs {
   const float* rowmean;    // [P] mean of I per row (M_SPEC)
   float tau;               // M_SPEC truncation
   float momentum;          // M_SPEC heavy-ball factor c
+  float er_beta;           // M_ER Nesterov factor b: iterate from z = tin + b (tin - din), din = t_prev
   int out_bf16;            // M_FWD_INT output type
   const cx<float>* tw32;   // twiddle tables, table of length L at offset L-1
   const cx<double>* tw64;
@@ -50,10 +51,28 @@ __device__ __forceinline__ uint16_t f_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
+
+
+// Accesses through global-address-space pointers (complex values as 8-byte
+// vectors; complex buffers are 8-byte aligned).
+#define TM_GLOBAL __attribute__((address_space(1)))
+typedef float tm_v2f __attribute__((ext_vector_type(2)));
+template <typename V>
+__device__ __forceinline__ const TM_GLOBAL V* gc(const V* p) { return (const TM_GLOBAL V*)p; }
+template <typename V>
+__device__ __forceinline__ TM_GLOBAL V* gw(V* p) { return (TM_GLOBAL V*)p; }
+__device__ __forceinline__ cx<float> gload(const cx<float>* p) {
+  tm_v2f v = *(const TM_GLOBAL tm_v2f*)p;
+  return cx<float>{v.x, v.y};
+}
+__device__ __forceinline__ void gstore(cx<float>* p, cx<float> v) {
+  *(TM_GLOBAL tm_v2f*)p = tm_v2f{v.x, v.y};
+}
+
 template <typename IT>
 __device__ __forceinline__ float load_I(const void* I, size_t idx) {
-  if constexpr (sizeof(IT) == 2) return bf16_to_f(((const uint16_t*)I)[idx]);
-  else return ((const float*)I)[idx];
+  if constexpr (sizeof(IT) == 2) return bf16_to_f(gc((const uint16_t*)I)[idx]);
+  else return gc((const float*)I)[idx];
 }
 
 // Compensated (TwoSum) accumulation in FP32.
@@ -167,15 +186,17 @@ __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(
 #ifndef TM_MINW
 #define TM_MINW 1
 #endif
-#ifndef TM_RELOAD_T
-#define TM_RELOAD_T 0
-#endif
 
 // Body of the fused kernel for the rows [blk * RPW, (blk + 1) * RPW) of one
 // problem, run by a workgroup of WGT threads with LDS at lds_all (at least
 // Launch<PL, WGT>::LDS_ELEMS elements) and red (RED_FLOATS floats).
 template <class PL, int MODE, typename IT, bool SUMS, int WGT>
-__device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* lds_all, float* red) {
+__device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>* lds_all, float* red) {
+  // Every buffer is in device global memory: the accesses below go through
+  // global-address-space pointers, so that where this body is not inlined into
+  // a kernel they stay global (not flat) loads and stores, which do not share
+  // a wait counter with the LDS exchanges.
+  const RowArgs a = args;
   using T = float;
   using C = cx<T>;
   using LC = Launch<PL, WGT>;
@@ -202,22 +223,30 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
 #define E0(i) (b0[(i) / L0::R] + ((i) % L0::R) * L0::HS)
 #define KL(i) (kb[(i) / LL::R] + ((i) % LL::R) * LL::KS)
 
-  // The row t (and d) is re-read for every mask instead of being held in
-  // registers across the mask loop: the reads hit the cache after the first
-  // mask, and the freed registers let two 512-thread workgroups share a CU.
+  // The row t is held in registers across the mask loop (re-reading it per
+  // mask from cache measured slower); d (M_LS) is re-read per mask.
   C g[E], x[E];
   const C* trow = a.tin + prow * N;
   const C* drow = a.din + prow * N;
-#if !TM_RELOAD_T
   C treg[E];
   if constexpr (MODE != M_ADJ && MODE != M_BACKPROP) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) treg[i] = trow[E0(i)];
+    for (int i = 0; i < E; ++i) treg[i] = gload(trow + E0(i));
+  }
+  if constexpr (MODE == M_ER) {
+    if (a.er_beta != 0.f) {
+      // Nesterov extrapolation from the previous iterate. The caller swaps the
+      // two buffers every iteration (tout = din), so t is never copied, and no
+      // store precedes the FFTs (the twiddle tables stay scalar loads).
+      const float b = a.er_beta;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        C tp = gload(drow + E0(i));
+        treg[i] = C{treg[i].x + b * (treg[i].x - tp.x), treg[i].y + b * (treg[i].y - tp.y)};
+      }
+    }
   }
 #define TROW(i) treg[i]
-#else
-#define TROW(i) trow[E0(i)]
-#endif
 #pragma unroll
   for (int i = 0; i < E; ++i) g[i] = C{0.f, 0.f};
 
@@ -227,7 +256,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
 
   float inv_mean = 0.f;
   if constexpr (MODE == M_SPEC) {
-    float m = valid ? a.rowmean[prow] : 1.f;
+    float m = valid ? gc(a.rowmean)[prow] : 1.f;
     inv_mean = (m > 0.f) ? 1.f / m : 1.f;
   }
 
@@ -239,12 +268,12 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         int k = KL(i);
-        if constexpr (MODE == M_ADJ) x[i] = a.yin[mbase + k];
+        if constexpr (MODE == M_ADJ) x[i] = gload(a.yin + mbase + k);
         else x[i] = C{sqrtf(fmaxf(load_I<IT>(a.I, mbase + k), 0.f)), 0.f};
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), mk[E0(i)]);
+      for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), gload(mk + E0(i)));
       fft_forward<PL, T>(x, xb, ltid, tw);
     }
 
@@ -253,11 +282,11 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           int k = KL(i);
-          if constexpr (MODE == M_FWD_FIELD) ((C*)a.yout)[mbase + k] = x[i];
+          if constexpr (MODE == M_FWD_FIELD) gstore((C*)a.yout + mbase + k, x[i]);
           else {
             float v = norm2(x[i]);
-            if (a.out_bf16) ((uint16_t*)a.yout)[mbase + k] = f_to_bf16(v);
-            else ((float*)a.yout)[mbase + k] = v;
+            if (a.out_bf16) gw((uint16_t*)a.yout)[mbase + k] = f_to_bf16(v);
+            else gw((float*)a.yout)[mbase + k] = v;
           }
         }
       }
@@ -267,7 +296,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
 #pragma unroll
       for (int i = 0; i < E; ++i) y[i] = x[i];
 #pragma unroll
-      for (int i = 0; i < E; ++i) x[i] = cmul(drow[E0(i)], mk[E0(i)]);
+      for (int i = 0; i < E; ++i) x[i] = cmul(gload(drow + E0(i)), gload(mk + E0(i)));
       fft_forward<PL, T>(x, xb, ltid, tw);
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -317,7 +346,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
       }
       fft_inverse<PL, T>(x, xb, ltid, tw);
 #pragma unroll
-      for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], mk[E0(i)]);
+      for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], gload(mk + E0(i)));
     }
   }
 
@@ -328,13 +357,13 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
     row_reduce<PL::T, WG, NSUM>(acc, red, tid, out);
     if (valid && ltid == 0) {
 #pragma unroll
-      for (int i = 0; i < NSUM; ++i) a.sums[prow * NSUM + i] = out[i];
+      for (int i = 0; i < NSUM; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
     }
   } else if constexpr (MODE == M_SPEC) {
     // lambda = Re <v, M v> (v has unit norm), x = M v - beta v_prev, normalise.
     C vp[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) vp[i] = a.din[prow * N + E0(i)];
+    for (int i = 0; i < E; ++i) vp[i] = gload(drow + E0(i));
     KSum l1[1] = {KSum{0.f, 0.f}};
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -357,10 +386,10 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
     if (valid) {
 #pragma unroll
       for (int i = 0; i < E; ++i) {
-        a.tout[prow * N + E0(i)] = scl(g[i], inv);
-        a.tout2[prow * N + E0(i)] = scl(TROW(i), inv);
+        gstore(a.tout + prow * N + E0(i), scl(g[i], inv));
+        gstore(a.tout2 + prow * N + E0(i), scl(TROW(i), inv));
       }
-      if (ltid == 0 && a.sums) a.sums[prow * NSUM + 0] = lam;
+      if (ltid == 0 && a.sums) gw(a.sums)[prow * NSUM + 0] = lam;
     }
   } else {
     float scale = 1.f;
@@ -368,17 +397,17 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int blk, cx<float>* l
     if constexpr (MODE == M_GRAD) scale = -4.f;
     if (valid) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) a.tout[prow * N + E0(i)] = scl(g[i], scale);
+      for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i], scale));
     }
     if constexpr ((MODE == M_ER || MODE == M_GRAD) && SUMS) {
       float out[NSUM];
       row_reduce<PL::T, WG, (MODE == M_ER) ? 2 : 1>(acc, red, tid, out);
       if (valid && ltid == 0 && a.sums) {
         if constexpr (MODE == M_ER) {
-          a.sums[prow * NSUM + 0] = out[0];
-          a.sums[prow * NSUM + 1] = out[1];
+          gw(a.sums)[prow * NSUM + 0] = out[0];
+          gw(a.sums)[prow * NSUM + 1] = out[1];
         } else {
-          a.sums[prow * NSUM + 0] = out[0];
+          gw(a.sums)[prow * NSUM + 0] = out[0];
         }
       }
     }

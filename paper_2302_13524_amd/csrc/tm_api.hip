@@ -101,7 +101,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
-  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST,
+  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV,
   WS_PH_BASE = 100
 };
 
@@ -342,6 +342,7 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     if (!(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f))
       return fail(c, TM_EINVAL, "spectral_momentum must be in [0, 1)");
   }
+  if (!(o->er_momentum >= 0.f && o->er_momentum < 1.f)) return fail(c, TM_EINVAL, "er_momentum must be in [0, 1)");
   if (o->method == TM_METHOD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
     return fail(c, TM_EINVAL, "lbfgs_m %d outside 1..16", o->lbfgs_m);
   if (d.P == 0) return TM_OK;
@@ -392,10 +393,30 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   if (o->method == TM_METHOD_ER) {
     a.tin = tt;
     a.tout = tt;
+    const bool mom = o->er_momentum > 0.f && o->iters > 0;
+    tmk::cx<float>* buf[2] = {tt, nullptr};
+    if (mom) {
+      // t_prev starts equal to t; t and t_prev then alternate between the
+      // caller's buffer and the workspace (the new iterate overwrites t_prev)
+      buf[1] = (tmk::cx<float>*)ws_get(c, WS_TPREV, (size_t)d.P * N * sizeof(tm_c32));
+      if (!buf[1]) return fail(c, TM_ENOMEM, "workspace");
+      int ce = tmk::launch_copy(buf[1], t, (int64_t)d.P * N * sizeof(tm_c32), stream);
+      if (ce) return hipfail(c, ce, "momentum copy");
+      a.er_beta = o->er_momentum;
+    }
     for (int it = 0; it < o->iters; ++it) {
       a.sums = (it == o->iters - 1) ? sums : nullptr;  // only the last iteration's sums are reported
+      if (mom) {
+        a.tin = buf[it & 1];
+        a.din = buf[(it & 1) ^ 1];
+        a.tout = buf[(it & 1) ^ 1];
+      }
       r = run_row(c, fn, tmk::M_ER, ibf, a, stream);
       if (r) return r;
+    }
+    if (mom && (o->iters & 1)) {
+      int ce = tmk::launch_copy(t, buf[1], (int64_t)d.P * N * sizeof(tm_c32), stream);
+      if (ce) return hipfail(c, ce, "momentum copy");
     }
     if (o->iters > 0) {
       amp_idx = 0;
@@ -803,8 +824,29 @@ static int batch_enqueue(tm_batch* b, void* stream) {
       e = b->fns[i](tmk::M_BACKPROP, ibf, a, stream);
     }
   }
-  for (int it = 0; it < o.iters && !e; ++it)
-    e = tmk::batch_launch(tmk::BATCH_ER, ibf, it == o.iters - 1, b->args, b->grid, stream);
+  tmk::BatchArgs ea = b->args;
+  const bool mom = o.er_momentum > 0.f && o.iters > 0;
+  if (mom) {
+    // t_prev starts equal to t in the per-problem vprev buffer (free after the
+    // spectral start); the two buffers then swap roles every iteration
+    for (int i = 0; i < n && !e; ++i) {
+      const tm_problem& p = b->probs[i];
+      if (p.d.P)
+        e = tmk::launch_copy(b->vprev[i], p.t, (int64_t)p.d.P * p.d.n1 * p.d.n2 * sizeof(tm_c32), stream);
+    }
+    ea.er_beta = o.er_momentum;
+  }
+  for (int it = 0; it < o.iters && !e; ++it) {
+    ea.er_swap = mom ? (it & 1) : 0;
+    e = tmk::batch_launch(tmk::BATCH_ER, ibf, it == o.iters - 1, ea, b->grid, stream);
+  }
+  if (mom && (o.iters & 1)) {
+    for (int i = 0; i < n && !e; ++i) {
+      const tm_problem& p = b->probs[i];
+      if (p.d.P)
+        e = tmk::launch_copy(p.t, b->vprev[i], (int64_t)p.d.P * p.d.n1 * p.d.n2 * sizeof(tm_c32), stream);
+    }
+  }
   for (int i = 0; i < n && !e; ++i) {
     const tm_problem& p = b->probs[i];
     if (p.d.P == 0) continue;
@@ -826,6 +868,7 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
   if (!out || !o || n < 1 || !probs) return fail(c, TM_EINVAL, "n >= 1 and non-null probs, opts, out");
   *out = nullptr;
   if (o->method != TM_METHOD_ER) return fail(c, TM_EUNSUPPORTED, "batches run the error-reduction method");
+  if (!(o->er_momentum >= 0.f && o->er_momentum < 1.f)) return fail(c, TM_EINVAL, "er_momentum must be in [0, 1)");
   if (o->iters < 0 || (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) || o->start < TM_START_GIVEN ||
       o->start > TM_START_SPECTRAL)
     return fail(c, TM_EINVAL, "bad options");

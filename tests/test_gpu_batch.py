@@ -39,24 +39,24 @@ def make_problems(ctx, shapes, cfg=970, bf16=True):
     return out
 
 
-def opts():
-    return tm.retrieve_opts("er", iters=4, start="spectral", spectral_iters=5, bf16=True)
+def opts(mom=0.0):
+    return tm.retrieve_opts("er", iters=4, start="spectral", spectral_iters=5, bf16=True, er_momentum=mom)
 
 
-def singles(ctx, probs):
+def singles(ctx, probs, mom=0.0):
     res = []
     for p in probs:
         t = p["seed"].clone()
-        tm.tm_retrieve(ctx, p["masks"], p["I"], t, p["n1"], p["n2"], opts())
+        tm.tm_retrieve(ctx, p["masks"], p["I"], t, p["n1"], p["n2"], opts(mom))
         res.append(t)
     return res
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_equals_single_problem_runs(ctx, graph):
+@pytest.mark.parametrize("graph,mom", [(False, 0.0), (True, 0.0), (True, 0.8)])
+def test_batch_equals_single_problem_runs(ctx, graph, mom):
     probs = make_problems(ctx, SHAPES)
-    ref = singles(ctx, probs)
-    b = tm.Batch(ctx, probs, opts(), use_graph=graph)
+    ref = singles(ctx, probs, mom)
+    b = tm.Batch(ctx, probs, opts(mom), use_graph=graph)
     for rep in range(3):
         for p in probs:
             p["t"].copy_(p["seed"])
@@ -65,7 +65,7 @@ def test_batch_equals_single_problem_runs(ctx, graph):
         for p, r in zip(probs, ref):
             assert torch.equal(p["t"], r), (rep, p["n1"], p["n2"])
         # eager work between replays
-        ref = singles(ctx, probs)
+        ref = singles(ctx, probs, mom)
     st = tm.decode_stats(probs[0]["stats"])
     assert np.all(st.iters.numpy() == 4)
     b.close()

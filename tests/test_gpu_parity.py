@@ -115,6 +115,22 @@ def test_er_one_step(ctx):
     assert relerr(tt.cpu().numpy(), ref) < OPTOL
 
 
+@pytest.mark.parametrize("n1,n2,P", [(32, 32, 21), (8, 8, 150), (64, 128, 5)])
+def test_er_momentum_steps(ctx, n1, n2, P):
+    # Nesterov-extrapolated ER: t_prev starts at t0, z = t + b (t - t_prev)
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=912, noise=1e4)
+    t0 = T + 0.7 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(912, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    op = ops.FFTOp(m, n1, n2)
+    for iters in (1, 2, 5):
+        ref = rt.er_accelerated(op, Ir, t, iters, 0.8)
+        tt = c64(t0)
+        tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("er", iters=iters, er_momentum=0.8))
+        assert relerr(tt.cpu().numpy(), ref) < OPTOL * iters, iters
+    with pytest.raises(tm.TMError, match="er_momentum"):
+        tm.tm_retrieve(ctx, c64(masks), f32(I), c64(t0), n1, n2, tm.retrieve_opts("er", iters=1, er_momentum=1.0))
+
+
 def test_backprop_start(ctx):
     n1, n2, P = 64, 32, 9
     masks, T, I, _ = problem(n1, n2, 4, P, cfg=908, noise=1e4)

@@ -290,3 +290,37 @@ def test_momentum_power_iteration_reaches_same_eigenvector():
     v0 = g.standard_normal((1, 8)) + 1j * g.standard_normal((1, 8))
     v = rt.spectral_start(d, I, v0, 400, momentum=0.98 * ev[-2] / ev[-1])
     assert np.abs(np.vdot(V[:, -1], v[0])) ** 2 / np.vdot(v[0], v[0]).real > 1 - 1e-8
+
+
+def test_accelerated_er_special_cases():
+    # beta = 0 is plain ER; one step from t_prev = t0 is one plain ER step for
+    # any beta; the noiseless truth is a fixed point of the accelerated map
+    masks, t, g = small_problem(4, 4, K=4, P=3)
+    op = ops.FFTOp(masks, 4, 4)
+    I = ops.intensities(op, t)
+    t0 = (g.standard_normal(t.shape) + 1j * g.standard_normal(t.shape)) / np.sqrt(2)
+    plain = t0.copy()
+    for _ in range(4):
+        plain = rt.er_step(op, I, plain)
+    assert np.max(np.abs(rt.er_accelerated(op, I, t0, 4, 0.0) - plain)) < 1e-13
+    assert np.max(np.abs(rt.er_accelerated(op, I, t0, 1, 0.9) - rt.er_step(op, I, t0))) < 1e-13
+    truth = t * np.exp(1j * 0.7)
+    assert np.max(np.abs(rt.er_accelerated(op, I, truth, 10, 0.8) - truth)) < 1e-10
+
+
+def test_accelerated_er_converges_faster_on_noiseless_rows():
+    # Nesterov extrapolation of the ER step: with a positive factor the
+    # noiseless 16x16 rows (K = 4, spectral start) reach the truth in fewer
+    # iterations than plain ER; a negative factor slows it down
+    n1 = n2 = 16
+    N, K, P = n1 * n2, 4, 16
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(5, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(5, 1))
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, T)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(5, 3))
+    t0 = rt.spectral_start(op, I, v0, 40, momentum=0.98)
+    f = {b: rt.fidelity(rt.er_accelerated(op, I, t0, 20, b), T) for b in (0.0, 0.8, -0.3)}
+    assert f[0.8].min() > 0.95 and f[0.0].mean() < 0.95
+    assert f[-0.3].mean() < f[0.0].mean() < f[0.8].mean()
+    assert rt.fidelity(rt.er_accelerated(op, I, t0, 40, 0.8), T).min() > 0.999
