@@ -6,7 +6,8 @@
 //   zero-pad S to (2nf1) x (2nf2) keeping signed frequencies, a_n = K2^H S.
 // Objective g = sum_n || I_n - |a_n|^2 ||^2 (Eq. optphase) and gradient
 // dg/dphi = -4 Im(conj(u) w), w = sum_n A_n^H (a_n r_n) (Eq. phasederive).
-// The 2-D transforms are batched 1-D FP64 line FFTs along each axis.
+// The 2-D transforms run one axis at a time as FP64 line FFTs in LDS, fused
+// with the pointwise steps between them.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -17,7 +18,6 @@ namespace tmk {
 
 namespace {
 
-constexpr int RESID_BLOCKS = 16;  // partial-sum blocks per defocus image
 constexpr int GATHER_SLICES = 8;  // image slices of the gradient gather
 
 struct z2 {
@@ -101,74 +101,48 @@ __global__ void k_invmap2(int32_t* inv, const int32_t* pix, int P) {
   if (p < P) inv[pix[p]] = p;
 }
 
-// A[n][g] = c[n][p] e^{j phi_p} where g = pix[p], 0 elsewhere (writes the whole grid)
-__global__ void k_scatter_full(double* A, const double* c, const double* phi, const int32_t* inv, int Nd, int P,
-                               int G, const int* skip) {
-  if (skip && *skip) return;
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (size_t)Nd * G) return;
-  int n = (int)(i / G), g = (int)(i % G);
-  int p = inv[g];
-  z2 v{0.0, 0.0};
-  if (p >= 0) {
-    z2 cv{c[((size_t)n * P + p) * 2], c[((size_t)n * P + p) * 2 + 1]};
-    double sn, cs;
-    sincos(phi[p], &sn, &cs);
-    v = zmul(cv, z2{cs, sn});
-  }
-  A[2 * i] = v.x;
-  A[2 * i + 1] = v.y;
-}
+// ---- separable evaluation of the forward model and its adjoint
+// The 2-D transforms are done one axis at a time, each fused with the
+// pointwise step that follows it, so every kernel reads one line (a row or a
+// column of one image) from memory, transforms it in LDS and writes it once:
+//   rows_fwd   F = scatter(c_n u) row by row, DFT along axis 2
+//   cols_fwd   DFT along axis 1, times h, zero-pad axis 1, inverse DFT (2 nf1)
+//   rows_mid   zero-pad axis 2, inverse DFT (2 nf2) = a_n row; residual
+//              r = I - |a|^2 (objective partial sums), a r, DFT (2 nf2), crop
+//              (or |a|^2 written out for the image-only forward model)
+//   cols_adj   DFT along axis 1 (2 nf1), crop, times conj(h), inverse DFT (nf1)
+//   rows_adj   inverse DFT along axis 2 -> A_n^H (a_n r_n) on the field grid
+// Every DFT is unitary per axis. The intermediate B holds [Nd][2 nf1][nf2]
+// (image rows, axis 2 still in the unpadded frequency order).
+constexpr int LINE_ELEMS = 512;  // complex doubles per LDS buffer (lines per workgroup x longest line)
+constexpr int LWG = 256;
 
-// Batched in-LDS FFT of lines of length L = 2^LL (radix-2 Stockham).
-// Line li: outer = li / inner_n, inner = li % inner_n; element j at
-// (outer * os + inner * is + j * es) complex entries. sign -1: forward DFT.
-__global__ void __launch_bounds__(256) k_lines(double* buf, int nlines, int inner_n, long os, long is, long es,
-                                               int LL, int sign, double scale, const double* tw64,
-                                               const int* skip) {
-  if (skip && *skip) return;
-  extern __shared__ double sm[];
-  const int L = 1 << LL;
-  const int half = L >> 1;
-  const int lpw = 256 / half > 0 ? 256 / half : 1;
-  const int tl = threadIdx.x / half;   // line within workgroup
-  const int tj = threadIdx.x % half;   // butterfly within line
-  int li = blockIdx.x * lpw + tl;
-  bool act = (tl < lpw) && (li < nlines);
-  z2* a = (z2*)sm + (size_t)tl * 2 * L;
-  z2* b = a + L;
-  long base = 0;
-  if (act) {
-    int outer = li / inner_n, inner = li % inner_n;
-    base = outer * os + inner * is;
-    for (int j = tj; j < L; j += half) a[j] = ((z2*)buf)[base + j * es];
-  }
-  __syncthreads();
+// Stockham radix-2 DFTs of nl lines of length L, line i at a + i * ls, using
+// b as the ping-pong buffer; every thread of the workgroup takes part.
+// Returns the buffer holding the result.
+__device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const double* tw64) {
   const z2* tw = (const z2*)tw64 + (L - 1);
-  // Stockham radix-2: stage with sub-length p (1, 2, 4, ...)
+  const int half = L >> 1;
   for (int p = 1; p < L; p <<= 1) {
-    if (act) {
-      int k = tj;                 // butterfly 0..L/2-1
-      int i = k % p;
-      z2 x0 = a[k], x1 = a[k + half];
-      z2 w = tw[(i * (L / (2 * p))) & (L - 1)];
+    for (int t = threadIdx.x; t < nl * half; t += LWG) {
+      const int line = t / half, k = t - line * half;
+      const z2* la = a + line * ls;
+      z2* lb = b + line * ls;
+      const int i = k & (p - 1);
+      z2 x0 = la[k], x1 = la[k + half];
+      z2 w = tw[i * (L / (2 * p))];
       if (sign > 0) w.y = -w.y;
       x1 = zmul(x1, w);
-      int o = (k - i) * 2 + i;
-      b[o] = {x0.x + x1.x, x0.y + x1.y};
-      b[o + p] = {x0.x - x1.x, x0.y - x1.y};
+      const int o = ((k - i) << 1) + i;
+      lb[o] = {x0.x + x1.x, x0.y + x1.y};
+      lb[o + p] = {x0.x - x1.x, x0.y - x1.y};
     }
     __syncthreads();
     z2* t = a;
     a = b;
     b = t;
   }
-  if (act) {
-    for (int j = tj; j < L; j += half) {
-      z2 v = a[j];
-      ((z2*)buf)[base + j * es] = {v.x * scale, v.y * scale};
-    }
-  }
+  return a;
 }
 
 __device__ __forceinline__ int padpos(int k, int n) {
@@ -184,63 +158,212 @@ __device__ __forceinline__ int unpad(int a2, int n) {
   return -1;
 }
 
-// B[n][a2][b2] = h[a][b] A[n][a][b] at the padded positions, 0 elsewhere (whole grid)
-__global__ void k_pad_full(double* B, const double* A, const double* h, int Nd, int nf1, int nf2, const int* skip) {
-  if (skip && *skip) return;
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  size_t G4 = (size_t)4 * nf1 * nf2;
-  if (i >= Nd * G4) return;
-  int n = (int)(i / G4);
-  int r = (int)(i % G4);
-  int a2 = r / (2 * nf2), b2 = r % (2 * nf2);
-  int a = unpad(a2, nf1), b = unpad(b2, nf2);
-  z2 o{0.0, 0.0};
-  if (a >= 0 && b >= 0) {
-    size_t q = (size_t)n * nf1 * nf2 + (size_t)a * nf2 + b;
-    z2 v{A[2 * q], A[2 * q + 1]};
-    z2 hv{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
-    o = zmul(v, hv);
-  }
-  B[2 * i] = o.x;
-  B[2 * i + 1] = o.y;
-}
+__device__ __forceinline__ int lines_per_wg(int Lmax) { return Lmax >= LINE_ELEMS ? 1 : LINE_ELEMS / Lmax; }
 
-// A[n][a][b] = conj(h[a][b]) * B[n][pad(a)][pad(b)]
-__global__ void k_crop(double* A, const double* B, const double* h, int Nd, int nf1, int nf2, const int* skip) {
+// rows of F_n: F[n][a][b] = c[n][p] e^{j phi_p} where a nf2 + b = pix[p], 0 elsewhere;
+// DFT along axis 2 -> A[n][a][:]
+__global__ void __launch_bounds__(LWG) k_rows_fwd(double* A, const double* c, const double* phi, const int32_t* inv,
+                                                  int Nd, int P, int nf1, int nf2, const double* tw64,
+                                                  const int* skip) {
   if (skip && *skip) return;
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  size_t G = (size_t)nf1 * nf2;
-  if (i >= Nd * G) return;
-  int n = (int)(i / G);
-  int r = (int)(i % G);
-  int a = r / nf2, b = r % nf2;
-  size_t q = ((size_t)n * 4 * G + (size_t)padpos(a, nf1) * 2 * nf2 + padpos(b, nf2)) * 2;
-  z2 v{B[q], B[q + 1]};
-  z2 hv{h[2 * r], h[2 * r + 1]};
-  z2 o = zmulc(v, hv);
-  A[2 * i] = o.x;
-  A[2 * i + 1] = o.y;
-}
-
-// r = I - |a|^2, a <- a r (in place); partial sums of r^2 per (image, block)
-// into gpart[n * gridDim.y + blockIdx.y]
-__global__ void __launch_bounds__(256) k_resid(double* B, const float* Id, double* gpart, int npix, const int* skip) {
-  if (skip && *skip) return;
-  __shared__ double red[4];
-  int n = blockIdx.x;
-  double s = 0;
-  for (int i = blockIdx.y * 256 + threadIdx.x; i < npix; i += 256 * gridDim.y) {
-    size_t q = (size_t)n * npix + i;
-    z2 v{B[2 * q], B[2 * q + 1]};
-    double r = (double)Id[q] - (v.x * v.x + v.y * v.y);
-    s += r * r;
-    B[2 * q] = v.x * r;
-    B[2 * q + 1] = v.y * r;
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  const int L = nf2, nl = lines_per_wg(L), nlines = Nd * nf1;
+  const int l0 = blockIdx.x * nl;
+  for (int t = threadIdx.x; t < nl * L; t += LWG) {
+    const int line = t / L, j = t - line * L, gl = l0 + line;
+    z2 v{0.0, 0.0};
+    if (gl < nlines) {
+      const int n = gl / nf1, a = gl - n * nf1;
+      const int p = inv[a * nf2 + j];
+      if (p >= 0) {
+        z2 cv{c[((size_t)n * P + p) * 2], c[((size_t)n * P + p) * 2 + 1]};
+        double sn, cs;
+        sincos(phi[p], &sn, &cs);
+        v = zmul(cv, z2{cs, sn});
+      }
+    }
+    sa[line * L + j] = v;
   }
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) gpart[(size_t)n * gridDim.y + blockIdx.y] = red[0] + red[1] + red[2] + red[3];
+  const z2* r = lds_fft(sa, sb, nl, L, L, -1, tw64);
+  const double sc = 1.0 / sqrt((double)L);
+  for (int t = threadIdx.x; t < nl * L; t += LWG) {
+    const int line = t / L, gl = l0 + line;
+    if (gl < nlines) {
+      z2 v = r[t];
+      ((z2*)A)[(size_t)gl * L + (t - line * L)] = {v.x * sc, v.y * sc};
+    }
+  }
+}
+
+// columns: A[n][:][b] -> DFT (nf1), times h[:][b], pad to 2 nf1, inverse DFT -> B[n][:][b]
+__global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, const double* h, int Nd, int nf1,
+                                                  int nf2, const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  const int L1 = nf1, L2 = 2 * nf1, nl = lines_per_wg(L2), ncols = Nd * nf2;
+  const int l0 = blockIdx.x * nl;
+  // consecutive threads read consecutive columns of one row
+  for (int t = threadIdx.x; t < nl * L1; t += LWG) {
+    const int a = t / nl, line = t - a * nl, gl = l0 + line;
+    z2 v{0.0, 0.0};
+    if (gl < ncols) {
+      const int n = gl / nf2, b = gl - n * nf2;
+      v = ((const z2*)A)[((size_t)n * nf1 + a) * nf2 + b];
+    }
+    sa[line * L2 + a] = v;
+  }
+  __syncthreads();
+  z2* r = lds_fft(sa, sb, nl, L2, L1, -1, tw64);
+  z2* q = (r == sa) ? sb : sa;
+  const double s1 = 1.0 / sqrt((double)L1);
+  for (int t = threadIdx.x; t < nl * L2; t += LWG) {
+    const int line = t / L2, a2 = t - line * L2, gl = l0 + line;
+    const int a = unpad(a2, nf1);
+    z2 v{0.0, 0.0};
+    if (a >= 0 && gl < ncols) {
+      const int b = gl % nf2;
+      z2 hv{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
+      z2 x = r[line * L2 + a];
+      v = zmul(z2{x.x * s1, x.y * s1}, hv);
+    }
+    q[t] = v;
+  }
+  __syncthreads();
+  const z2* o = lds_fft(q, r, nl, L2, L2, +1, tw64);
+  const double s2 = 1.0 / sqrt((double)L2);
+  for (int t = threadIdx.x; t < nl * L2; t += LWG) {
+    const int a2 = t / nl, line = t - a2 * nl, gl = l0 + line;
+    if (gl < ncols) {
+      const int n = gl / nf2, b = gl - n * nf2;
+      z2 v = o[line * L2 + a2];
+      ((z2*)B)[((size_t)n * L2 + a2) * nf2 + b] = {v.x * s2, v.y * s2};
+    }
+  }
+}
+
+// image rows: B[n][a2][:] -> pad to 2 nf2, inverse DFT = a_n[a2][:].
+// Id != null: r = I - |a|^2, partial sum of r^2 per workgroup into gpart,
+// a r -> DFT (2 nf2) -> crop -> B[n][a2][:]. Id == null: |a|^2 -> I_out.
+__global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, double* gpart, float* I_out, int Nd,
+                                                  int nf1, int nf2, const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  __shared__ double red[LWG / 64];
+  const int L = 2 * nf2, nl = lines_per_wg(L), nlines = Nd * 2 * nf1;
+  const int l0 = blockIdx.x * nl;
+  for (int t = threadIdx.x; t < nl * L; t += LWG) {
+    const int line = t / L, b2 = t - line * L, gl = l0 + line;
+    const int b = unpad(b2, nf2);
+    z2 v{0.0, 0.0};
+    if (b >= 0 && gl < nlines) v = ((const z2*)B)[(size_t)gl * nf2 + b];
+    sa[t] = v;
+  }
+  __syncthreads();
+  z2* r = lds_fft(sa, sb, nl, L, L, +1, tw64);
+  const double s2 = 1.0 / sqrt((double)L);
+  if (!Id) {
+    for (int t = threadIdx.x; t < nl * L; t += LWG) {
+      const int gl = l0 + t / L;
+      if (gl < nlines) {
+        z2 v = r[t];
+        I_out[(size_t)l0 * L + t] = (float)((v.x * v.x + v.y * v.y) * (s2 * s2));
+      }
+    }
+    return;
+  }
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nl * L; t += LWG) {
+    const int gl = l0 + t / L;
+    z2 v = r[t];
+    v = {v.x * s2, v.y * s2};
+    double res = 0.0;
+    if (gl < nlines) {
+      res = (double)Id[(size_t)l0 * L + t] - (v.x * v.x + v.y * v.y);
+      acc += res * res;
+    }
+    r[t] = {v.x * res, v.y * res};
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) gpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  z2* q = (r == sa) ? sb : sa;
+  const z2* o = lds_fft(r, q, nl, L, L, -1, tw64);
+  for (int t = threadIdx.x; t < nl * nf2; t += LWG) {
+    const int line = t / nf2, b = t - line * nf2, gl = l0 + line;
+    if (gl < nlines) {
+      z2 v = o[line * L + padpos(b, nf2)];
+      ((z2*)B)[(size_t)gl * nf2 + b] = {v.x * s2, v.y * s2};
+    }
+  }
+}
+
+// columns: B[n][:][b] -> DFT (2 nf1), crop, times conj(h[:][b]), inverse DFT (nf1) -> A[n][:][b]
+__global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, const double* h, int Nd, int nf1,
+                                                  int nf2, const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  const int L1 = nf1, L2 = 2 * nf1, nl = lines_per_wg(L2), ncols = Nd * nf2;
+  const int l0 = blockIdx.x * nl;
+  for (int t = threadIdx.x; t < nl * L2; t += LWG) {
+    const int a2 = t / nl, line = t - a2 * nl, gl = l0 + line;
+    z2 v{0.0, 0.0};
+    if (gl < ncols) {
+      const int n = gl / nf2, b = gl - n * nf2;
+      v = ((const z2*)B)[((size_t)n * L2 + a2) * nf2 + b];
+    }
+    sa[line * L2 + a2] = v;
+  }
+  __syncthreads();
+  z2* r = lds_fft(sa, sb, nl, L2, L2, -1, tw64);
+  z2* q = (r == sa) ? sb : sa;
+  const double s2 = 1.0 / sqrt((double)L2);
+  for (int t = threadIdx.x; t < nl * L1; t += LWG) {
+    const int line = t / L1, a = t - line * L1, gl = l0 + line;
+    z2 v{0.0, 0.0};
+    if (gl < ncols) {
+      const int b = gl % nf2;
+      z2 hv{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
+      z2 x = r[line * L2 + padpos(a, nf1)];
+      v = zmulc(z2{x.x * s2, x.y * s2}, hv);
+    }
+    q[line * L2 + a] = v;
+  }
+  __syncthreads();
+  const z2* o = lds_fft(q, r, nl, L2, L1, +1, tw64);
+  const double s1 = 1.0 / sqrt((double)L1);
+  for (int t = threadIdx.x; t < nl * L1; t += LWG) {
+    const int a = t / nl, line = t - a * nl, gl = l0 + line;
+    if (gl < ncols) {
+      const int n = gl / nf2, b = gl - n * nf2;
+      z2 v = o[line * L2 + a];
+      ((z2*)A)[((size_t)n * nf1 + a) * nf2 + b] = {v.x * s1, v.y * s1};
+    }
+  }
+}
+
+// rows: A[n][a][:] -> inverse DFT along axis 2 (in place)
+__global__ void __launch_bounds__(LWG) k_rows_adj(double* A, int Nd, int nf1, int nf2, const double* tw64,
+                                                  const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  const int L = nf2, nl = lines_per_wg(L), nlines = Nd * nf1;
+  const int l0 = blockIdx.x * nl;
+  for (int t = threadIdx.x; t < nl * L; t += LWG) {
+    const int gl = l0 + t / L;
+    sa[t] = (gl < nlines) ? ((const z2*)A)[(size_t)l0 * L + t] : z2{0.0, 0.0};
+  }
+  __syncthreads();
+  const z2* r = lds_fft(sa, sb, nl, L, L, +1, tw64);
+  const double sc = 1.0 / sqrt((double)L);
+  for (int t = threadIdx.x; t < nl * L; t += LWG) {
+    const int gl = l0 + t / L;
+    if (gl < nlines) {
+      z2 v = r[t];
+      ((z2*)A)[(size_t)l0 * L + t] = {v.x * sc, v.y * sc};
+    }
+  }
 }
 
 // Partial w_s[p] = sum over the images n of slice s of conj(c[n][p]) A[n][pix[p]]:
@@ -294,36 +417,29 @@ __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, cons
   }
 }
 
-int lines(double* buf, int nlines, int inner_n, long os, long is, long es, int L, int sign, double scale,
-          const double* tw64, hipStream_t s, const int* skip) {
-  int LL = ilog2(L);
-  int half = L / 2 > 0 ? L / 2 : 1;
-  int lpw = 256 / half > 0 ? 256 / half : 1;
-  int blocks = (nlines + lpw - 1) / lpw;
-  size_t lds = (size_t)lpw * 2 * L * 16;
-  if (L == 1) {
-    return 0;
-  }
-  k_lines<<<blocks, 256, lds, s>>>(buf, nlines, inner_n, os, is, es, LL, sign, scale, tw64, skip);
-  return (int)hipGetLastError();
+int grid_of(int nlines, int Lmax) {
+  const int nl = Lmax >= LINE_ELEMS ? 1 : LINE_ELEMS / Lmax;
+  return (nlines + nl - 1) / nl;
 }
 
-// 2-D transform of Nd grids g1 x g2 in buf; sign -1 forward, +1 inverse, unitary scaling.
-int fft2(double* buf, int Nd, int g1, int g2, int sign, const double* tw64, hipStream_t s, const int* skip) {
-  int e;
-  // along axis 2 (contiguous rows): lines = Nd*g1, element stride 1
-  if ((e = lines(buf, Nd * g1, 1, g2, 0, 1, g2, sign, 1.0 / sqrt((double)g2), tw64, s, skip))) return e;
-  // along axis 1: lines = Nd*g2, outer n stride g1*g2, inner column stride 1, element stride g2
-  if ((e = lines(buf, Nd * g2, g2, (long)g1 * g2, 1, g2, g1, sign, 1.0 / sqrt((double)g1), tw64, s, skip))) return e;
-  return 0;
+// workgroups of the image-row kernel = objective partial sums per evaluation
+int mid_groups(const PhaseDims& d) { return grid_of(d.Nd * 2 * d.nf1, 2 * d.nf2); }
+
+// scatter + forward model up to the image rows (B holds image rows in the
+// unpadded axis-2 frequency order)
+int forward_to_rows(const PhaseDims& d, const double* phi, PhaseWork& w, const double* tw64, hipStream_t s) {
+  k_rows_fwd<<<grid_of(d.Nd * d.nf1, d.nf2), LWG, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, d.nf1, d.nf2, tw64,
+                                                          w.skip);
+  k_cols_fwd<<<grid_of(d.Nd * d.nf2, 2 * d.nf1), LWG, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2, tw64, w.skip);
+  return (int)hipGetLastError();
 }
 
 }  // namespace
 
 size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
-  size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 4 * G * 2 +
-               (size_t)d.Nd * RESID_BLOCKS + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1;
+  size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 2 * G * 2 +
+               (size_t)mid_groups(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1;
   return dbl * sizeof(double) + 8 * 256;
 }
 
@@ -338,8 +454,8 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->c = take((size_t)d.Nd * d.P * 2);
   w->h = take(G * 2);
   w->A = take((size_t)d.Nd * G * 2);
-  w->B = take((size_t)d.Nd * 4 * G * 2);
-  w->gpart = take((size_t)d.Nd * RESID_BLOCKS);
+  w->B = take((size_t)d.Nd * 2 * G * 2);
+  w->gpart = take((size_t)mid_groups(d));
   w->w = take((size_t)GATHER_SLICES * d.P * 2);
   w->gval = take(8);
   w->inv = (int32_t*)take(G);
@@ -364,53 +480,26 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
   hipStream_t s = (hipStream_t)stream;
   int e;
   const int G = d.nf1 * d.nf2;
-  const size_t nA = (size_t)d.Nd * G * 2, nB = (size_t)d.Nd * 4 * G * 2;
-  auto blocks = [](size_t n) { return (unsigned)((n + 255) / 256 > 65535 ? 65535 : (n + 255) / 256); };
-  (void)nA;
-  (void)nB;
-  (void)blocks;
-  const size_t nG = (size_t)d.Nd * G, nG4 = (size_t)d.Nd * 4 * G;
-  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G, w.skip);
+  if ((e = forward_to_rows(d, phi, w, tw64, s))) return e;
+  const int ngp = mid_groups(d);
+  k_rows_mid<<<ngp, LWG, 0, s>>>(w.B, Id, w.gpart, nullptr, d.Nd, d.nf1, d.nf2, tw64, w.skip);
+  k_cols_adj<<<grid_of(d.Nd * d.nf2, 2 * d.nf1), LWG, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2, tw64, w.skip);
+  k_rows_adj<<<grid_of(d.Nd * d.nf1, d.nf2), LWG, 0, s>>>(w.A, d.Nd, d.nf1, d.nf2, tw64, w.skip);
   if ((e = (int)hipGetLastError())) return e;
-  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s, w.skip))) return e;
-  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2, w.skip);
-  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s, w.skip))) return e;
-  k_resid<<<dim3(d.Nd, RESID_BLOCKS), 256, 0, s>>>(w.B, Id, w.gpart, 4 * G, w.skip);
-  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, -1, tw64, s, w.skip))) return e;
-  k_crop<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2, w.skip);
-  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, +1, tw64, s, w.skip))) return e;
   const int per = (d.Nd + GATHER_SLICES - 1) / GATHER_SLICES;
   const int nsl = (d.Nd + per - 1) / per;
   k_gather_part<<<dim3((d.P + 255) / 256, nsl), 256, 0, s>>>(w.w, w.A, w.c, pix, d.Nd, d.P, G, per, w.skip);
-  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, d.Nd * RESID_BLOCKS, nsl, d.P, w.skip);
+  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, ngp, nsl, d.P, w.skip);
   return (int)hipGetLastError();
 }
 
-namespace {
-__global__ void k_absq(const double* B, float* out, size_t n) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[i] = (float)(B[2 * i] * B[2 * i] + B[2 * i + 1] * B[2 * i + 1]);
-}
-}  // namespace
-
 int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, float* I_out, PhaseWork& w,
                  const double* tw64, void* stream) {
+  (void)pix;
   hipStream_t s = (hipStream_t)stream;
   int e;
-  const int G = d.nf1 * d.nf2;
-  const size_t nA = (size_t)d.Nd * G * 2, nB = (size_t)d.Nd * 4 * G * 2;
-  auto blocks = [](size_t n) { return (unsigned)((n + 255) / 256 > 65535 ? 65535 : (n + 255) / 256); };
-  (void)nA;
-  (void)nB;
-  (void)blocks;
-  const size_t nG = (size_t)d.Nd * G, nG4 = (size_t)d.Nd * 4 * G;
-  k_scatter_full<<<(unsigned)((nG + 255) / 256), 256, 0, s>>>(w.A, w.c, phi, w.inv, d.Nd, d.P, G, w.skip);
-  if ((e = (int)hipGetLastError())) return e;
-  if ((e = fft2(w.A, d.Nd, d.nf1, d.nf2, -1, tw64, s, w.skip))) return e;
-  k_pad_full<<<(unsigned)((nG4 + 255) / 256), 256, 0, s>>>(w.B, w.A, w.h, d.Nd, d.nf1, d.nf2, w.skip);
-  if ((e = fft2(w.B, d.Nd, 2 * d.nf1, 2 * d.nf2, +1, tw64, s, w.skip))) return e;
-  size_t n = (size_t)d.Nd * 4 * G;
-  k_absq<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.B, I_out, n);
+  if ((e = forward_to_rows(d, phi, w, tw64, s))) return e;
+  k_rows_mid<<<mid_groups(d), LWG, 0, s>>>(w.B, nullptr, nullptr, I_out, d.Nd, d.nf1, d.nf2, tw64, w.skip);
   return (int)hipGetLastError();
 }
 

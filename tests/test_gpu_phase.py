@@ -76,3 +76,29 @@ def test_rejects_bad_pixels(ctx):
     with pytest.raises(tm.TMError, match="repeats"):
         tm.tm_phase_objective(ctx, torch.from_numpy(bad).to(dev()), c64(tm_est), c64(theta), f32(Id),
                               (LAM, PS, 0.6, 20.0), torch.zeros(P, dtype=torch.float64, device=dev()), nf, nf)
+
+
+@pytest.mark.parametrize("nf1,nf2,P,N,Nd", [(8, 16, 50, 24, 3), (32, 4, 60, 16, 2), (2, 2, 3, 8, 2),
+                                            (256, 4, 40, 8, 2), (4, 256, 40, 8, 2)])
+def test_rectangular_grids_images_objective(ctx, nf1, nf2, P, N, Nd):
+    # non-square field grids, line lengths from 2 to 512 (one line per workgroup)
+    print(f"rectangular nf1={nf1} nf2={nf2} P={P}", flush=True)
+    g = np.random.default_rng(nf1 * 1000 + nf2)
+    pix = np.sort(g.choice(nf1 * nf2, P, replace=False))
+    tm_est = tm_synth.tm_iid(P, N, tm_synth.rng(953, 1)).astype(np.complex64)
+    theta = tm_synth.defocus_phases(Nd, N, tm_synth.rng(953, 4)).astype(np.complex64)
+    mdl = df.DefocusModel(tm_est.astype(np.complex128), theta.astype(np.complex128), pix, nf1, nf2, LAM, PS, 0.6,
+                          20 * LAM)
+    phi = g.random(P) * 2 * np.pi
+    pix_d = torch.from_numpy(pix.astype(np.int32)).to(dev())
+    img = tm.tm_defocus_forward(ctx, pix_d, c64(tm_est), c64(theta), (LAM, PS, 0.6, 20 * LAM),
+                                torch.from_numpy(phi).to(dev()), nf1, nf2)
+    ref = mdl.images(phi)
+    assert img.shape == ref.shape
+    assert relerr(img.cpu().numpy(), ref) < 1e-6
+    Id = (ref * (1 + 0.05 * g.standard_normal(ref.shape))).astype(np.float32)
+    gref, grad_ref = mdl.objective(Id.astype(np.float64), phi)
+    gv, grad = tm.tm_phase_objective(ctx, pix_d, c64(tm_est), c64(theta), f32(Id), (LAM, PS, 0.6, 20 * LAM),
+                                     torch.from_numpy(phi).to(dev()), nf1, nf2)
+    assert abs(gv.item() - gref) <= 1e-9 * gref
+    assert relerr(grad.cpu().numpy(), grad_ref) < 1e-9
