@@ -48,13 +48,12 @@ struct PhaseLb {
   double* d;      // [P]
   double* S;      // [m][P]
   double* Y;      // [m][P]
-  double* sc;     // [8 + 2m] iteration state (see phase_kernels.hip)
+  double* sc;     // [9 + 2m] iteration state (see phase_kernels.hip)
 };
 // Device-controlled iterations (see phase_kernels.hip): init after the first
-// evaluation, then per iteration step, trial, evaluation at phit, decide.
+// evaluation, then per iteration phase_lb_iter (decide on the pending trial,
+// new direction or halved step, trial point) and the evaluation at phit.
 int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream);
-int phase_lb_step(PhaseLb& L, int P, int m, int iters, int* skip, void* stream);
-int phase_lb_trial(PhaseLb& L, int P, const int* skip, void* stream);
-int phase_lb_decide(PhaseLb& L, int P, int m, const double* gval, const int* skip, void* stream);
+int phase_lb_iter(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, void* stream);
 
 }  // namespace tmk

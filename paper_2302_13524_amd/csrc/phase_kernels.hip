@@ -117,25 +117,61 @@ __global__ void k_invmap2(int32_t* inv, const int32_t* pix, int P) {
 constexpr int LINE_ELEMS = 512;  // complex doubles per LDS buffer (lines per workgroup x longest line)
 constexpr int LWG = 256;
 
-// Stockham radix-2 DFTs of nl lines of length L, line i at a + i * ls, using
-// b as the ping-pong buffer; every thread of the workgroup takes part.
+// Stockham (self-sorting) DFTs of nl lines of length L = 2^l, line i at
+// a + i * ls, using b as the ping-pong buffer; every thread of the
+// workgroup takes part. Radix-4 steps, with one radix-2 step first when l is
+// odd. A step with sub-length p maps butterfly k (i = k mod p) from inputs
+// a[k + r L/R] (r < R), twiddled by W_{Rp}^{i r}, through a length-R DFT to
+// b[(k - i) R + i + s p]. sign -1: forward (W = e^{-2 pi j / n}); +1: inverse.
 // Returns the buffer holding the result.
 __device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const double* tw64) {
   const z2* tw = (const z2*)tw64 + (L - 1);
-  const int half = L >> 1;
-  for (int p = 1; p < L; p <<= 1) {
+  int p = 1;
+  if (__builtin_ctz((unsigned)L) & 1) {  // radix-2 step
+    const int half = L >> 1;
     for (int t = threadIdx.x; t < nl * half; t += LWG) {
       const int line = t / half, k = t - line * half;
       const z2* la = a + line * ls;
       z2* lb = b + line * ls;
-      const int i = k & (p - 1);
       z2 x0 = la[k], x1 = la[k + half];
-      z2 w = tw[i * (L / (2 * p))];
-      if (sign > 0) w.y = -w.y;
-      x1 = zmul(x1, w);
-      const int o = ((k - i) << 1) + i;
-      lb[o] = {x0.x + x1.x, x0.y + x1.y};
-      lb[o + p] = {x0.x - x1.x, x0.y - x1.y};
+      lb[2 * k] = {x0.x + x1.x, x0.y + x1.y};
+      lb[2 * k + 1] = {x0.x - x1.x, x0.y - x1.y};
+    }
+    __syncthreads();
+    z2* t = a;
+    a = b;
+    b = t;
+    p = 2;
+  }
+  const int q = L >> 2;
+  for (; p < L; p <<= 2) {
+    const int ts = L / (4 * p);  // twiddle stride: W_{4p}^m = tw[m ts]
+    for (int t = threadIdx.x; t < nl * q; t += LWG) {
+      const int line = t / q, k = t - line * q;
+      const z2* la = a + line * ls;
+      z2* lb = b + line * ls;
+      const int i = k & (p - 1);
+      z2 x0 = la[k], x1 = la[k + q], x2 = la[k + 2 * q], x3 = la[k + 3 * q];
+      if (p > 1) {
+        z2 w1 = tw[i * ts], w2 = tw[2 * i * ts], w3 = tw[3 * i * ts];
+        if (sign > 0) {
+          w1.y = -w1.y;
+          w2.y = -w2.y;
+          w3.y = -w3.y;
+        }
+        x1 = zmul(x1, w1);
+        x2 = zmul(x2, w2);
+        x3 = zmul(x3, w3);
+      }
+      // length-4 DFT: the odd outputs turn x1 - x3 by -j (forward) or +j (inverse)
+      const z2 s02{x0.x + x2.x, x0.y + x2.y}, d02{x0.x - x2.x, x0.y - x2.y};
+      const z2 s13{x1.x + x3.x, x1.y + x3.y}, d13{x1.x - x3.x, x1.y - x3.y};
+      const z2 rd = (sign < 0) ? z2{d13.y, -d13.x} : z2{-d13.y, d13.x};
+      const int o = ((k - i) << 2) + i;
+      lb[o] = {s02.x + s13.x, s02.y + s13.y};
+      lb[o + p] = {d02.x + rd.x, d02.y + rd.y};
+      lb[o + 2 * p] = {s02.x - s13.x, s02.y - s13.y};
+      lb[o + 3 * p] = {d02.x - rd.x, d02.y - rd.y};
     }
     __syncthreads();
     z2* t = a;
@@ -527,15 +563,17 @@ __device__ double dotv(const double* a, const double* b, int P, double* red) {
 // back-to-back without host synchronisation. State sc (doubles):
 // [0] head, [1] count, [2] slope of d, [3] step a, [4] objective f at phi,
 // [5] accepted iterations, [6] last trial accepted, [7] halvings of this
-// direction; [8..8+m) s^T y, [8+m..8+2m) y^T y. *skip = 1 ends the solve
-// (every later kernel returns at once).
-// Per iteration: k_pstep (new direction after an accepted trial, else halve
-// a), k_ptrial (phi_t = phi + a d), objective and gradient at phi_t,
-// k_pdecide (Armijo f_t <= f + 1e-4 a slope: accept and update the history).
+// direction, [8] a trial is pending; [9..9+m) s^T y, [9+m..9+2m) y^T y.
+// *skip = 1 ends the solve (every later kernel returns at once).
+// One iteration is k_piter followed by the objective and gradient at phit:
+// k_piter first decides on the pending trial (Armijo f_t <= f + 1e-4 a slope:
+// accept, update the history), then takes a new direction after an accepted
+// trial or halves a, and sets the trial point phit = phi + a d.
+constexpr int SC_HIST = 9;
 __device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc) {
   int head = (int)sc[0], count = (int)sc[1];
-  const double* sy = sc + 8;
-  const double* yy = sc + 8 + m;
+  const double* sy = sc + SC_HIST;
+  const double* yy = sc + SC_HIST + m;
   for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = L.g[i];
   __syncthreads();
   double al[16];
@@ -577,45 +615,14 @@ __device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc) {
   if (threadIdx.x == 0) sc[2] = slope;
 }
 
-__global__ void __launch_bounds__(PWG) k_pstep(PhaseLb L, int P, int m, int iters, int* skip) {
-  __shared__ double red[PWG / 64];
-  double* sc = L.sc;
-  if (*skip) return;
-  __syncthreads();  // every thread has read *skip before thread 0 may set it
-  if (sc[6] != 0.0) {
-    if (sc[5] >= (double)iters) {
-      if (threadIdx.x == 0) *skip = 1;
-      return;
-    }
-    direction(L, P, m, red, sc);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      sc[3] = 1.0;
-      sc[7] = 0.0;
-      if (!(sc[2] < 0.0)) *skip = 1;  // zero gradient
-    }
-  } else if (threadIdx.x == 0) {
-    sc[7] += 1.0;
-    if (sc[7] >= 40.0) *skip = 1;  // no sufficient decrease along d: stop
-    else sc[3] *= 0.5;
-  }
-}
-
-__global__ void k_ptrial(PhaseLb L, int P, const int* skip) {
-  if (*skip) return;
-  int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < P) L.phit[i] = L.phi[i] + L.sc[3] * L.d[i];
-}
-
-__global__ void __launch_bounds__(PWG) k_pdecide(PhaseLb L, int P, int m, const double* gval, const int* skip) {
-  __shared__ double red[PWG / 64];
-  if (*skip) return;
-  double* sc = L.sc;
+// Armijo decision on the trial whose objective is gval[0] and gradient L.gt.
+__device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red, double* sc) {
   double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
   bool ok = fn <= f + 1e-4 * a * slope;
-  __syncthreads();
   if (!ok) {
+    __syncthreads();
     if (threadIdx.x == 0) sc[6] = 0.0;
+    __syncthreads();
     return;
   }
   int head = (int)sc[0], count = (int)sc[1];
@@ -632,10 +639,11 @@ __global__ void __launch_bounds__(PWG) k_pdecide(PhaseLb L, int P, int m, const 
     L.phi[i] = L.phi[i] + Sh[i];
     L.g[i] = L.gt[i];
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     if (sy > 0.0) {
-      sc[8 + head] = sy;
-      sc[8 + m + head] = yy;
+      sc[SC_HIST + head] = sy;
+      sc[SC_HIST + m + head] = yy;
       sc[0] = (head + 1) % m;
       sc[1] = count < m ? count + 1 : m;
     }
@@ -643,6 +651,45 @@ __global__ void __launch_bounds__(PWG) k_pdecide(PhaseLb L, int P, int m, const 
     sc[5] += 1.0;
     sc[6] = 1.0;
   }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, const double* gval, int* skip) {
+  __shared__ double red[PWG / 64];
+  __shared__ int stop;
+  double* sc = L.sc;
+  if (*skip) return;
+  if (threadIdx.x == 0) stop = 0;
+  __syncthreads();  // every thread has read *skip before thread 0 may set it
+  if (sc[8] != 0.0) decide(L, P, m, gval, red, sc);
+  if (sc[6] != 0.0) {
+    if (sc[5] >= (double)iters) {
+      if (threadIdx.x == 0) *skip = 1;
+      return;
+    }
+    direction(L, P, m, red, sc);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sc[3] = 1.0;
+      sc[7] = 0.0;
+      if (!(sc[2] < 0.0)) stop = 1;  // zero gradient
+    }
+  } else if (threadIdx.x == 0) {
+    sc[7] += 1.0;
+    if (sc[7] >= 40.0) stop = 1;  // no sufficient decrease along d: stop
+    else sc[3] *= 0.5;
+  }
+  __syncthreads();
+  if (stop) {
+    if (threadIdx.x == 0) {
+      *skip = 1;
+      sc[8] = 0.0;
+    }
+    return;
+  }
+  const double a = sc[3];
+  for (int i = threadIdx.x; i < P; i += PWG) L.phit[i] = L.phi[i] + a * L.d[i];
+  if (threadIdx.x == 0) sc[8] = 1.0;
 }
 
 // start: clear the state, take f at the start point, allow the first direction
@@ -659,19 +706,11 @@ __global__ void k_pinit(double* sc, int n, const double* gval, int* skip) {
 }  // namespace
 
 int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream) {
-  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, 8 + 2 * m, gval, skip);
+  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, SC_HIST + 2 * m, gval, skip);
   return (int)hipGetLastError();
 }
-int phase_lb_step(PhaseLb& L, int P, int m, int iters, int* skip, void* stream) {
-  k_pstep<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, iters, skip);
-  return (int)hipGetLastError();
-}
-int phase_lb_trial(PhaseLb& L, int P, const int* skip, void* stream) {
-  k_ptrial<<<(P + 255) / 256, 256, 0, (hipStream_t)stream>>>(L, P, skip);
-  return (int)hipGetLastError();
-}
-int phase_lb_decide(PhaseLb& L, int P, int m, const double* gval, const int* skip, void* stream) {
-  k_pdecide<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, gval, skip);
+int phase_lb_iter(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, void* stream) {
+  k_piter<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, iters, gval, skip);
   return (int)hipGetLastError();
 }
 

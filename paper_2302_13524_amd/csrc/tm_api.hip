@@ -548,18 +548,17 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
     hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
     if (he == hipSuccess) {
-      e = tmk::phase_lb_step(L, P, m, po->iters, w.skip, cap);
-      if (!e) e = tmk::phase_lb_trial(L, P, w.skip, cap);
+      e = tmk::phase_lb_iter(L, P, m, po->iters, w.gval, w.skip, cap);
       if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
-      if (!e) e = tmk::phase_lb_decide(L, P, m, w.gval, w.skip, cap);
       hipError_t he2 = hipStreamEndCapture(cap, &graph);
       if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
       if (!e && he2 != hipSuccess) e = (int)he2;
     } else {
       e = (int)he;
     }
-    // at most 40 trials per accepted iteration, plus the replay that ends the solve
-    const long limit = (long)po->iters * 41 + 1;
+    // at most 40 trials per accepted iteration, plus the replay that decides
+    // the last trial and ends the solve
+    const long limit = (long)po->iters * 40 + 2;
     long launched = 0, batch = po->iters + 8;
     while (!e && launched < limit) {
       long nb = std::min(batch, limit - launched);
