@@ -48,8 +48,9 @@ struct PhaseLb {
   double* d;      // [P]
   double* S;      // [m][P]
   double* Y;      // [m][P]
-  double* sc;     // [9 + 2m] iteration state (see phase_kernels.hip)
+  double* sc;     // [phase_lb_state_doubles(m)] iteration state (see phase_kernels.hip)
 };
+int phase_lb_state_doubles(int m);
 // Device-controlled iterations (see phase_kernels.hip): init after the first
 // evaluation, then per iteration phase_lb_iter (decide on the pending trial,
 // new direction or halved step, trial point) and the evaluation at phit.

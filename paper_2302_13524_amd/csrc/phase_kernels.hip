@@ -543,109 +543,185 @@ int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, floa
 namespace {
 constexpr int PWG = 1024;
 
-__device__ double bsum(double v, double* red) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0;
-  for (int i = 0; i < PWG / 64; ++i) s += red[i];
-  return s;
+// Block-wide sums of several values: each wave adds its lanes' x into
+// red[wave][j] (wave_put), then bsum_finish adds the waves: out[0..nv) for
+// every thread. red holds (PWG / 64) * MAXV doubles.
+constexpr int MAXV = 34;
+__device__ __forceinline__ void wave_put(double x, int j, double* red) {
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * MAXV + j] = x;
 }
-
-__device__ double dotv(const double* a, const double* b, int P, double* red) {
-  double s = 0;
-  for (int i = threadIdx.x; i < P; i += PWG) s += a[i] * b[i];
-  return bsum(s, red);
+__device__ void bsum_finish(int nv, double* red, double* out) {
+  __syncthreads();
+  for (int j = threadIdx.x; j < nv; j += PWG) {
+    double s = 0;
+    for (int i = 0; i < PWG / 64; ++i) s += red[i * MAXV + j];
+    out[j] = s;
+  }
+  __syncthreads();
 }
 
 // Line search and iteration control on the device, so that iterations replay
 // back-to-back without host synchronisation. State sc (doubles):
 // [0] head, [1] count, [2] slope of d, [3] step a, [4] objective f at phi,
 // [5] accepted iterations, [6] last trial accepted, [7] halvings of this
-// direction, [8] a trial is pending; [9..9+m) s^T y, [9+m..9+2m) y^T y.
+// direction, [8] a trial is pending; then the m x m matrices SY[i][j] =
+// s_i^T y_j and YY[i][j] = y_i^T y_j over the history slots.
 // *skip = 1 ends the solve (every later kernel returns at once).
 // One iteration is k_piter followed by the objective and gradient at phit:
 // k_piter first decides on the pending trial (Armijo f_t <= f + 1e-4 a slope:
 // accept, update the history), then takes a new direction after an accepted
 // trial or halves a, and sets the trial point phit = phi + a d.
+// The direction is the L-BFGS product -H g in the compact form of Byrd,
+// Nocedal and Schnabel (1994): with a = S^T g, b = Y^T g over the k stored
+// pairs (oldest first), R the upper triangle of S^T Y, D its diagonal and
+// gamma = s^T y / y^T y of the newest pair, H g = gamma g + S p - gamma Y u
+// where R u = a and R^T p = (D + gamma Y^T Y) u - gamma b. This equals the
+// two-loop recursion, but needs one pass over the vectors for all the dot
+// products instead of one reduction per stored pair.
 constexpr int SC_HIST = 9;
-__device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc) {
-  int head = (int)sc[0], count = (int)sc[1];
-  const double* sy = sc + SC_HIST;
-  const double* yy = sc + SC_HIST + m;
-  for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = L.g[i];
+
+__device__ __forceinline__ int slot_of(double* sc, int m, int i) {
+  return ((int)sc[0] - (int)sc[1] + i + 2 * m) % m;  // i-th oldest stored pair
+}
+
+__device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, double* sh) {
+  const int k = (int)sc[1];
+  const double* SY = sc + SC_HIST;
+  const double* YY = sc + SC_HIST + m * m;
+  // one pass: a_j = s_j^T g, b_j = y_j^T g, g^T g
+  for (int j = 0; j < k; ++j) {
+    const double* Sj = L.S + (size_t)slot_of(sc, m, j) * P;
+    const double* Yj = L.Y + (size_t)slot_of(sc, m, j) * P;
+    double xa = 0.0, xb = 0.0;
+    for (int i = threadIdx.x; i < P; i += PWG) {
+      const double gi = L.g[i];
+      xa += Sj[i] * gi;
+      xb += Yj[i] * gi;
+    }
+    wave_put(xa, j, red);
+    wave_put(xb, k + j, red);
+  }
+  double xg = 0.0;
+  for (int i = threadIdx.x; i < P; i += PWG) xg += L.g[i] * L.g[i];
+  wave_put(xg, 2 * k, red);
+  double* dots = sh;              // [2k + 1]
+  double* coef = sh + MAXV;       // [0] g coefficient, [1..1+k) S, [1+k..1+2k) Y, [1+2k] slope
+  bsum_finish(2 * k + 1, red, dots);
+  if (threadIdx.x == 0) {
+    const double gg = dots[2 * k];
+    double cg, slope;
+    if (k == 0) {
+      cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
+      slope = cg * gg;
+    } else {
+      int sl[16];
+      for (int j = 0; j < k; ++j) sl[j] = slot_of(sc, m, j);
+      const double gam = SY[sl[k - 1] * m + sl[k - 1]] / YY[sl[k - 1] * m + sl[k - 1]];
+      double u[16], p[16];
+      for (int i = k - 1; i >= 0; --i) {  // R u = a (R_ij = s_i^T y_j, i <= j)
+        double t = dots[i];
+        for (int j = i + 1; j < k; ++j) t -= SY[sl[i] * m + sl[j]] * u[j];
+        u[i] = t / SY[sl[i] * m + sl[i]];
+      }
+      for (int i = 0; i < k; ++i) {  // R^T p = (D + gam Y^T Y) u - gam b
+        double t = SY[sl[i] * m + sl[i]] * u[i] - gam * dots[k + i];
+        for (int j = 0; j < k; ++j) t += gam * YY[sl[i] * m + sl[j]] * u[j];
+        for (int j = 0; j < i; ++j) t -= SY[sl[j] * m + sl[i]] * p[j];
+        p[i] = t / SY[sl[i] * m + sl[i]];
+      }
+      // d = -H g = -gam g - S p + gam Y u
+      cg = -gam;
+      slope = -gam * gg;
+      for (int j = 0; j < k; ++j) {
+        coef[1 + j] = -p[j];
+        coef[1 + k + j] = gam * u[j];
+        slope += -p[j] * dots[j] + gam * u[j] * dots[k + j];
+      }
+      if (!(slope < 0.0)) {  // not a descent direction: drop the history, use -g/||g||
+        cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
+        slope = cg * gg;
+        for (int j = 0; j < 2 * k; ++j) coef[1 + j] = 0.0;
+        sc[1] = 0;
+      }
+    }
+    coef[0] = cg;
+    coef[1 + 2 * k] = slope;
+    sc[2] = slope;
+  }
   __syncthreads();
-  double al[16];
-  for (int j = 0; j < count; ++j) {
-    int idx = (head - 1 - j + 2 * m) % m;
-    double a = dotv(L.S + (size_t)idx * P, L.d, P, red) / sy[idx];
-    al[j] = a;
-    for (int i = threadIdx.x; i < P; i += PWG) L.d[i] -= a * L.Y[(size_t)idx * P + i];
-    __syncthreads();
+  const int kk = (int)sc[1] < k ? 0 : k;  // history dropped above
+  for (int i = threadIdx.x; i < P; i += PWG) {
+    double d = coef[0] * L.g[i];
+    for (int j = 0; j < kk; ++j) {
+      const int sl = slot_of(sc, m, j);
+      d += coef[1 + j] * L.S[(size_t)sl * P + i] + coef[1 + k + j] * L.Y[(size_t)sl * P + i];
+    }
+    L.d[i] = d;
   }
-  double gam;
-  if (count > 0) {
-    int nw = (head - 1 + m) % m;
-    gam = sy[nw] / yy[nw];
-  } else {
-    double gn = sqrt(dotv(L.g, L.g, P, red));
-    gam = gn > 0 ? 1.0 / gn : 0.0;
-  }
-  for (int i = threadIdx.x; i < P; i += PWG) L.d[i] *= gam;
   __syncthreads();
-  for (int j = count - 1; j >= 0; --j) {
-    int idx = (head - 1 - j + 2 * m) % m;
-    double b = dotv(L.Y + (size_t)idx * P, L.d, P, red) / sy[idx];
-    double cf = al[j] - b;
-    for (int i = threadIdx.x; i < P; i += PWG) L.d[i] += cf * L.S[(size_t)idx * P + i];
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = -L.d[i];
-  __syncthreads();
-  double slope = dotv(L.g, L.d, P, red);
-  if (!(slope < 0.0)) {  // not a descent direction: drop the history, use -g/||g||
-    double gn = sqrt(dotv(L.g, L.g, P, red));
-    double inv = gn > 0 ? 1.0 / gn : 0.0;
-    for (int i = threadIdx.x; i < P; i += PWG) L.d[i] = -L.g[i] * inv;
-    __syncthreads();
-    slope = dotv(L.g, L.d, P, red);
-    if (threadIdx.x == 0) sc[1] = 0;
-  }
-  if (threadIdx.x == 0) sc[2] = slope;
 }
 
 // Armijo decision on the trial whose objective is gval[0] and gradient L.gt.
-__device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red, double* sc) {
-  double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
-  bool ok = fn <= f + 1e-4 * a * slope;
+// An accepted trial goes into the history slot head: s = a d, y = g_t - g,
+// with its dot products against the stored pairs (one pass).
+__device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red, double* sc, double* sh) {
+  const double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
+  const bool ok = fn <= f + 1e-4 * a * slope;
   if (!ok) {
     __syncthreads();
     if (threadIdx.x == 0) sc[6] = 0.0;
     __syncthreads();
     return;
   }
-  int head = (int)sc[0], count = (int)sc[1];
+  const int head = (int)sc[0], count = (int)sc[1];
+  const int keep = count < m ? count : m - 1;  // stored pairs that stay (the oldest is overwritten when full)
   double* Sh = L.S + (size_t)head * P;
   double* Yh = L.Y + (size_t)head * P;
-  for (int i = threadIdx.x; i < P; i += PWG) {
-    Sh[i] = a * L.d[i];
-    Yh[i] = L.gt[i] - L.g[i];
+  for (int j = 0; j < keep; ++j) {
+    const int sl = (head - keep + j + 2 * m) % m;
+    const double* Sj = L.S + (size_t)sl * P;
+    const double* Yj = L.Y + (size_t)sl * P;
+    double xs = 0.0, xy = 0.0;
+    for (int i = threadIdx.x; i < P; i += PWG) {
+      const double yi = L.gt[i] - L.g[i];
+      xs += Sj[i] * yi;
+      xy += Yj[i] * yi;
+    }
+    wave_put(xs, j, red);
+    wave_put(xy, keep + j, red);
   }
-  __syncthreads();
-  double sy = dotv(Sh, Yh, P, red);
-  double yy = dotv(Yh, Yh, P, red);
+  double xsy = 0.0, xyy = 0.0;
   for (int i = threadIdx.x; i < P; i += PWG) {
-    L.phi[i] = L.phi[i] + Sh[i];
+    const double si = a * L.d[i], yi = L.gt[i] - L.g[i];
+    xsy += si * yi;
+    xyy += yi * yi;
+    Sh[i] = si;
+    Yh[i] = yi;
+    L.phi[i] = L.phi[i] + si;
     L.g[i] = L.gt[i];
   }
-  __syncthreads();
+  wave_put(xsy, 2 * keep, red);
+  wave_put(xyy, 2 * keep + 1, red);
+  double* dots = sh;
+  bsum_finish(2 * keep + 2, red, dots);
   if (threadIdx.x == 0) {
+    double* SY = sc + SC_HIST;
+    double* YY = sc + SC_HIST + m * m;
+    const double sy = dots[2 * keep], yy = dots[2 * keep + 1];
     if (sy > 0.0) {
-      sc[SC_HIST + head] = sy;
-      sc[SC_HIST + m + head] = yy;
+      for (int j = 0; j < keep; ++j) {
+        const int sl = (head - keep + j + 2 * m) % m;
+        SY[sl * m + head] = dots[j];
+        YY[sl * m + head] = dots[keep + j];
+        YY[head * m + sl] = dots[keep + j];
+      }
+      SY[head * m + head] = sy;
+      YY[head * m + head] = yy;
       sc[0] = (head + 1) % m;
-      sc[1] = count < m ? count + 1 : m;
+      sc[1] = keep + 1;
+    } else {
+      sc[1] = keep;  // slot head no longer holds a stored pair
     }
     sc[4] = fn;
     sc[5] += 1.0;
@@ -655,20 +731,20 @@ __device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red
 }
 
 __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, const double* gval, int* skip) {
-  __shared__ double red[PWG / 64];
+  __shared__ double red[(PWG / 64) * MAXV];
+  __shared__ double sh[2 * MAXV];
   __shared__ int stop;
   double* sc = L.sc;
   if (*skip) return;
   if (threadIdx.x == 0) stop = 0;
   __syncthreads();  // every thread has read *skip before thread 0 may set it
-  if (sc[8] != 0.0) decide(L, P, m, gval, red, sc);
+  if (sc[8] != 0.0) decide(L, P, m, gval, red, sc, sh);
   if (sc[6] != 0.0) {
     if (sc[5] >= (double)iters) {
       if (threadIdx.x == 0) *skip = 1;
       return;
     }
-    direction(L, P, m, red, sc);
-    __syncthreads();
+    direction(L, P, m, red, sc, sh);
     if (threadIdx.x == 0) {
       sc[3] = 1.0;
       sc[7] = 0.0;
@@ -694,10 +770,9 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
 
 // start: clear the state, take f at the start point, allow the first direction
 __global__ void k_pinit(double* sc, int n, const double* gval, int* skip) {
-  int i = threadIdx.x;
-  if (i < n) sc[i] = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) sc[i] = 0.0;
   __syncthreads();
-  if (i == 0) {
+  if (threadIdx.x == 0) {
     sc[4] = gval[0];
     sc[6] = 1.0;
     *skip = 0;
@@ -705,8 +780,10 @@ __global__ void k_pinit(double* sc, int n, const double* gval, int* skip) {
 }
 }  // namespace
 
+int phase_lb_state_doubles(int m) { return SC_HIST + 2 * m * m; }
+
 int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream) {
-  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, SC_HIST + 2 * m, gval, skip);
+  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, phase_lb_state_doubles(m), gval, skip);
   return (int)hipGetLastError();
 }
 int phase_lb_iter(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, void* stream) {

@@ -520,7 +520,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   if ((r = phase_prepare(c, dd, pix, tm_est, theta, o, pd, w, stream))) return r;
   const int P = dd->P, m = po->m;
   size_t vb = ((P * sizeof(double) + 255) / 256) * 256;
-  char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (5 + 2 * m) + 256 * sizeof(double));
+  char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (5 + 2 * m) + tmk::phase_lb_state_doubles(m) * sizeof(double));
   if (!lb) return fail(c, TM_ENOMEM, "phase L-BFGS workspace");
   tmk::PhaseLb L;
   L.phi = (double*)(lb);
