@@ -46,7 +46,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--spectral-iters", type=int, default=40)
+    ap.add_argument("--spectral-iters", type=int, default=32)
+    ap.add_argument("--spectral-tau", type=float, default=2.5, help="truncation of the spectral weights")
+    ap.add_argument("--spectral-momentum", type=float, default=0.999,
+                    help="heavy-ball factor c of the spectral start (beta = (c lambda)^2 / 4)")
     ap.add_argument("--phase-iters", type=int, default=100)
     ap.add_argument("--max-iters", type=int, default=300)
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows in the CPU-baseline sample (0: auto)")
@@ -139,8 +142,9 @@ def main():
     beta = args.er_momentum
 
     def opts(method, iters, start="spectral"):
-        return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=3.0,
-                                spectral_momentum=0.98, er_momentum=beta if method == "er" else 0.0)
+        return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=args.spectral_tau,
+                                spectral_momentum=args.spectral_momentum,
+                                er_momentum=beta if method == "er" else 0.0)
 
     # ---- untimed instrumented run: iterations to mean fidelity 0.99 (each count run
     # from the start, since the momentum iteration carries the previous iterate)
@@ -248,7 +252,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "P": P, "N": N, "grid": [n1, n2], "K": K,
-                   "start": f"truncated spectral, {sp} heavy-ball steps",
+                   "start": f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
+                            f"(c {args.spectral_momentum})",
                    "solver": f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction",
                    "iters_to_0.99": n_er, "phase_iters": args.phase_iters},
         "roofline": roofline,
@@ -294,11 +299,15 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
     train_s = time.perf_counter() - a
     f_start = float(fidelity(tm.tm_mlp_start(ctx, net, It, K, N)).mean().item())
     t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp,
+                                                   spectral_tau=args.spectral_tau,
+                                                   spectral_momentum=args.spectral_momentum,
                                                    er_momentum=args.er_momentum)
     torch.cuda.synchronize()
     a = time.perf_counter()
     for _ in range(3):
         t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp,
+                                                   spectral_tau=args.spectral_tau,
+                                                   spectral_momentum=args.spectral_momentum,
                                                    er_momentum=args.er_momentum)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) * 1e3 / 3
@@ -337,6 +346,8 @@ def batch_variant(ctx, args):
     tuned = {f"{n1}x{n2}": tm.autotune(ctx, n1, n2, 4, 512, bf16=True) for n1, n2, _, _ in shapes[:4]}
     iters, sp, beta = args.batch_iters, args.spectral_iters, args.er_momentum
     b = tm.Batch(ctx, probs, tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True,
+                                              spectral_tau=args.spectral_tau,
+                                              spectral_momentum=args.spectral_momentum,
                                               er_momentum=beta), use_graph=True)
 
     def run():
@@ -379,7 +390,8 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P):
 
     def run(rows):
         I = I_np[rows].astype(np.float64)
-        t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=3.0, momentum=0.98)
+        t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau,
+                              momentum=args.spectral_momentum)
         return rt.er_accelerated(op, I, t, n_er, beta)
 
     g = np.random.default_rng(123)

@@ -124,8 +124,10 @@ constexpr int LWG = 256;
 // a[k + r L/R] (r < R), twiddled by W_{Rp}^{i r}, through a length-R DFT to
 // b[(k - i) R + i + s p]. sign -1: forward (W = e^{-2 pi j / n}); +1: inverse.
 // Returns the buffer holding the result.
-__device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const double* tw64) {
-  const z2* tw = (const z2*)tw64 + (L - 1);
+// The twiddles come from an LDS copy of the table of the longest line
+// length Lt (W_L^m = twl[m Lt / L]).
+__device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const z2* twl, int Lt) {
+  const int tsc = Lt / L;
   int p = 1;
   if (__builtin_ctz((unsigned)L) & 1) {  // radix-2 step
     const int half = L >> 1;
@@ -145,7 +147,7 @@ __device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const doub
   }
   const int q = L >> 2;
   for (; p < L; p <<= 2) {
-    const int ts = L / (4 * p);  // twiddle stride: W_{4p}^m = tw[m ts]
+    const int ts = (L / (4 * p)) * tsc;  // twiddle stride: W_{4p}^m = twl[m ts]
     for (int t = threadIdx.x; t < nl * q; t += LWG) {
       const int line = t / q, k = t - line * q;
       const z2* la = a + line * ls;
@@ -153,7 +155,7 @@ __device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const doub
       const int i = k & (p - 1);
       z2 x0 = la[k], x1 = la[k + q], x2 = la[k + 2 * q], x3 = la[k + 3 * q];
       if (p > 1) {
-        z2 w1 = tw[i * ts], w2 = tw[2 * i * ts], w3 = tw[3 * i * ts];
+        z2 w1 = twl[i * ts], w2 = twl[2 * i * ts], w3 = twl[3 * i * ts];
         if (sign > 0) {
           w1.y = -w1.y;
           w2.y = -w2.y;
@@ -181,6 +183,13 @@ __device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const doub
   return a;
 }
 
+// LDS copy of the twiddle table W_L^m (m < L); the caller's next barrier
+// publishes it.
+__device__ __forceinline__ void load_tw(z2* twl, const double* tw64, int L) {
+  const z2* tw = (const z2*)tw64 + (L - 1);
+  for (int t = threadIdx.x; t < L; t += LWG) twl[t] = tw[t];
+}
+
 __device__ __forceinline__ int padpos(int k, int n) {
   int s = (k < (n + 1) / 2) ? k : k - n;
   return (s + 2 * n) % (2 * n);
@@ -202,9 +211,10 @@ __global__ void __launch_bounds__(LWG) k_rows_fwd(double* A, const double* c, co
                                                   int Nd, int P, int nf1, int nf2, const double* tw64,
                                                   const int* skip) {
   if (skip && *skip) return;
-  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS], stw[LINE_ELEMS];
   const int L = nf2, nl = lines_per_wg(L), nlines = Nd * nf1;
   const int l0 = blockIdx.x * nl;
+  load_tw(stw, tw64, L);
   for (int t = threadIdx.x; t < nl * L; t += LWG) {
     const int line = t / L, j = t - line * L, gl = l0 + line;
     z2 v{0.0, 0.0};
@@ -221,7 +231,7 @@ __global__ void __launch_bounds__(LWG) k_rows_fwd(double* A, const double* c, co
     sa[line * L + j] = v;
   }
   __syncthreads();
-  const z2* r = lds_fft(sa, sb, nl, L, L, -1, tw64);
+  const z2* r = lds_fft(sa, sb, nl, L, L, -1, stw, L);
   const double sc = 1.0 / sqrt((double)L);
   for (int t = threadIdx.x; t < nl * L; t += LWG) {
     const int line = t / L, gl = l0 + line;
@@ -236,9 +246,10 @@ __global__ void __launch_bounds__(LWG) k_rows_fwd(double* A, const double* c, co
 __global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, const double* h, int Nd, int nf1,
                                                   int nf2, const double* tw64, const int* skip) {
   if (skip && *skip) return;
-  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS], stw[LINE_ELEMS];
   const int L1 = nf1, L2 = 2 * nf1, nl = lines_per_wg(L2), ncols = Nd * nf2;
   const int l0 = blockIdx.x * nl;
+  load_tw(stw, tw64, L2);
   // consecutive threads read consecutive columns of one row
   for (int t = threadIdx.x; t < nl * L1; t += LWG) {
     const int a = t / nl, line = t - a * nl, gl = l0 + line;
@@ -250,7 +261,7 @@ __global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, co
     sa[line * L2 + a] = v;
   }
   __syncthreads();
-  z2* r = lds_fft(sa, sb, nl, L2, L1, -1, tw64);
+  z2* r = lds_fft(sa, sb, nl, L2, L1, -1, stw, L2);
   z2* q = (r == sa) ? sb : sa;
   const double s1 = 1.0 / sqrt((double)L1);
   for (int t = threadIdx.x; t < nl * L2; t += LWG) {
@@ -266,7 +277,7 @@ __global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, co
     q[t] = v;
   }
   __syncthreads();
-  const z2* o = lds_fft(q, r, nl, L2, L2, +1, tw64);
+  const z2* o = lds_fft(q, r, nl, L2, L2, +1, stw, L2);
   const double s2 = 1.0 / sqrt((double)L2);
   for (int t = threadIdx.x; t < nl * L2; t += LWG) {
     const int a2 = t / nl, line = t - a2 * nl, gl = l0 + line;
@@ -284,10 +295,11 @@ __global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, co
 __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, double* gpart, float* I_out, int Nd,
                                                   int nf1, int nf2, const double* tw64, const int* skip) {
   if (skip && *skip) return;
-  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS], stw[LINE_ELEMS];
   __shared__ double red[LWG / 64];
   const int L = 2 * nf2, nl = lines_per_wg(L), nlines = Nd * 2 * nf1;
   const int l0 = blockIdx.x * nl;
+  load_tw(stw, tw64, L);
   for (int t = threadIdx.x; t < nl * L; t += LWG) {
     const int line = t / L, b2 = t - line * L, gl = l0 + line;
     const int b = unpad(b2, nf2);
@@ -296,7 +308,7 @@ __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, do
     sa[t] = v;
   }
   __syncthreads();
-  z2* r = lds_fft(sa, sb, nl, L, L, +1, tw64);
+  z2* r = lds_fft(sa, sb, nl, L, L, +1, stw, L);
   const double s2 = 1.0 / sqrt((double)L);
   if (!Id) {
     for (int t = threadIdx.x; t < nl * L; t += LWG) {
@@ -325,7 +337,7 @@ __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, do
   __syncthreads();
   if (threadIdx.x == 0) gpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
   z2* q = (r == sa) ? sb : sa;
-  const z2* o = lds_fft(r, q, nl, L, L, -1, tw64);
+  const z2* o = lds_fft(r, q, nl, L, L, -1, stw, L);
   for (int t = threadIdx.x; t < nl * nf2; t += LWG) {
     const int line = t / nf2, b = t - line * nf2, gl = l0 + line;
     if (gl < nlines) {
@@ -339,9 +351,10 @@ __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, do
 __global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, const double* h, int Nd, int nf1,
                                                   int nf2, const double* tw64, const int* skip) {
   if (skip && *skip) return;
-  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS], stw[LINE_ELEMS];
   const int L1 = nf1, L2 = 2 * nf1, nl = lines_per_wg(L2), ncols = Nd * nf2;
   const int l0 = blockIdx.x * nl;
+  load_tw(stw, tw64, L2);
   for (int t = threadIdx.x; t < nl * L2; t += LWG) {
     const int a2 = t / nl, line = t - a2 * nl, gl = l0 + line;
     z2 v{0.0, 0.0};
@@ -352,7 +365,7 @@ __global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, co
     sa[line * L2 + a2] = v;
   }
   __syncthreads();
-  z2* r = lds_fft(sa, sb, nl, L2, L2, -1, tw64);
+  z2* r = lds_fft(sa, sb, nl, L2, L2, -1, stw, L2);
   z2* q = (r == sa) ? sb : sa;
   const double s2 = 1.0 / sqrt((double)L2);
   for (int t = threadIdx.x; t < nl * L1; t += LWG) {
@@ -367,7 +380,7 @@ __global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, co
     q[line * L2 + a] = v;
   }
   __syncthreads();
-  const z2* o = lds_fft(q, r, nl, L2, L1, +1, tw64);
+  const z2* o = lds_fft(q, r, nl, L2, L1, +1, stw, L2);
   const double s1 = 1.0 / sqrt((double)L1);
   for (int t = threadIdx.x; t < nl * L1; t += LWG) {
     const int a = t / nl, line = t - a * nl, gl = l0 + line;
@@ -383,15 +396,16 @@ __global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, co
 __global__ void __launch_bounds__(LWG) k_rows_adj(double* A, int Nd, int nf1, int nf2, const double* tw64,
                                                   const int* skip) {
   if (skip && *skip) return;
-  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS];
+  __shared__ z2 sa[LINE_ELEMS], sb[LINE_ELEMS], stw[LINE_ELEMS];
   const int L = nf2, nl = lines_per_wg(L), nlines = Nd * nf1;
   const int l0 = blockIdx.x * nl;
+  load_tw(stw, tw64, L);
   for (int t = threadIdx.x; t < nl * L; t += LWG) {
     const int gl = l0 + t / L;
     sa[t] = (gl < nlines) ? ((const z2*)A)[(size_t)l0 * L + t] : z2{0.0, 0.0};
   }
   __syncthreads();
-  const z2* r = lds_fft(sa, sb, nl, L, L, +1, tw64);
+  const z2* r = lds_fft(sa, sb, nl, L, L, +1, stw, L);
   const double sc = 1.0 / sqrt((double)L);
   for (int t = threadIdx.x; t < nl * L; t += LWG) {
     const int gl = l0 + t / L;
