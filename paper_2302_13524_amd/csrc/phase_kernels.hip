@@ -126,7 +126,7 @@ constexpr int LWG = 256;
 // Returns the buffer holding the result.
 // The twiddles come from an LDS copy of the table of the longest line
 // length Lt (W_L^m = twl[m Lt / L]).
-__device__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const z2* twl, int Lt) {
+__device__ __forceinline__ z2* lds_fft(z2* a, z2* b, int nl, int ls, int L, int sign, const z2* twl, int Lt) {
   const int tsc = Lt / L;
   int p = 1;
   if (__builtin_ctz((unsigned)L) & 1) {  // radix-2 step
@@ -203,6 +203,13 @@ __device__ __forceinline__ int unpad(int a2, int n) {
   return -1;
 }
 
+// complex entry i of an interleaved (re, im) double array
+__device__ __forceinline__ z2 ldz(const double* p, size_t i) { return z2{p[2 * i], p[2 * i + 1]}; }
+__device__ __forceinline__ void stz(double* p, size_t i, z2 v) {
+  p[2 * i] = v.x;
+  p[2 * i + 1] = v.y;
+}
+
 __device__ __forceinline__ int lines_per_wg(int Lmax) { return Lmax >= LINE_ELEMS ? 1 : LINE_ELEMS / Lmax; }
 
 // rows of F_n: F[n][a][b] = c[n][p] e^{j phi_p} where a nf2 + b = pix[p], 0 elsewhere;
@@ -237,7 +244,7 @@ __global__ void __launch_bounds__(LWG) k_rows_fwd(double* A, const double* c, co
     const int line = t / L, gl = l0 + line;
     if (gl < nlines) {
       z2 v = r[t];
-      ((z2*)A)[(size_t)gl * L + (t - line * L)] = {v.x * sc, v.y * sc};
+      stz(A, (size_t)gl * L + (t - line * L), z2{v.x * sc, v.y * sc});
     }
   }
 }
@@ -256,23 +263,34 @@ __global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, co
     z2 v{0.0, 0.0};
     if (gl < ncols) {
       const int n = gl / nf2, b = gl - n * nf2;
-      v = ((const z2*)A)[((size_t)n * nf1 + a) * nf2 + b];
+      v = ldz(A, ((size_t)n * nf1 + a) * nf2 + b);
     }
     sa[line * L2 + a] = v;
+  }
+  // kernel values of this thread's padded elements, loaded before the transforms
+  z2 hv[LINE_ELEMS / LWG];
+#pragma unroll
+  for (int k = 0; k < LINE_ELEMS / LWG; ++k) {
+    const int t = threadIdx.x + k * LWG, line = t / L2, gl = l0 + line;
+    const int a = unpad(t - line * L2, nf1);
+    hv[k] = z2{0.0, 0.0};
+    if (a >= 0 && gl < ncols) {
+      const int b = gl % nf2;
+      hv[k] = z2{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
+    }
   }
   __syncthreads();
   z2* r = lds_fft(sa, sb, nl, L2, L1, -1, stw, L2);
   z2* q = (r == sa) ? sb : sa;
   const double s1 = 1.0 / sqrt((double)L1);
-  for (int t = threadIdx.x; t < nl * L2; t += LWG) {
-    const int line = t / L2, a2 = t - line * L2, gl = l0 + line;
+#pragma unroll
+  for (int k = 0; k < LINE_ELEMS / LWG; ++k) {
+    const int t = threadIdx.x + k * LWG, line = t / L2, a2 = t - line * L2, gl = l0 + line;
     const int a = unpad(a2, nf1);
     z2 v{0.0, 0.0};
     if (a >= 0 && gl < ncols) {
-      const int b = gl % nf2;
-      z2 hv{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
       z2 x = r[line * L2 + a];
-      v = zmul(z2{x.x * s1, x.y * s1}, hv);
+      v = zmul(z2{x.x * s1, x.y * s1}, hv[k]);
     }
     q[t] = v;
   }
@@ -284,7 +302,7 @@ __global__ void __launch_bounds__(LWG) k_cols_fwd(double* B, const double* A, co
     if (gl < ncols) {
       const int n = gl / nf2, b = gl - n * nf2;
       z2 v = o[line * L2 + a2];
-      ((z2*)B)[((size_t)n * L2 + a2) * nf2 + b] = {v.x * s2, v.y * s2};
+      stz(B, ((size_t)n * L2 + a2) * nf2 + b, z2{v.x * s2, v.y * s2});
     }
   }
 }
@@ -304,8 +322,15 @@ __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, do
     const int line = t / L, b2 = t - line * L, gl = l0 + line;
     const int b = unpad(b2, nf2);
     z2 v{0.0, 0.0};
-    if (b >= 0 && gl < nlines) v = ((const z2*)B)[(size_t)gl * nf2 + b];
+    if (b >= 0 && gl < nlines) v = ldz(B, (size_t)gl * nf2 + b);
     sa[t] = v;
+  }
+  // the measured intensities of this thread's elements, loaded before the transforms
+  float idv[LINE_ELEMS / LWG];
+#pragma unroll
+  for (int k = 0; k < LINE_ELEMS / LWG; ++k) {
+    const int t = threadIdx.x + k * LWG, gl = l0 + t / L;
+    idv[k] = (Id && gl < nlines) ? Id[(size_t)l0 * L + t] : 0.f;
   }
   __syncthreads();
   z2* r = lds_fft(sa, sb, nl, L, L, +1, stw, L);
@@ -321,13 +346,14 @@ __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, do
     return;
   }
   double acc = 0.0;
-  for (int t = threadIdx.x; t < nl * L; t += LWG) {
-    const int gl = l0 + t / L;
+#pragma unroll
+  for (int k = 0; k < LINE_ELEMS / LWG; ++k) {
+    const int t = threadIdx.x + k * LWG, gl = l0 + t / L;
     z2 v = r[t];
     v = {v.x * s2, v.y * s2};
     double res = 0.0;
     if (gl < nlines) {
-      res = (double)Id[(size_t)l0 * L + t] - (v.x * v.x + v.y * v.y);
+      res = (double)idv[k] - (v.x * v.x + v.y * v.y);
       acc += res * res;
     }
     r[t] = {v.x * res, v.y * res};
@@ -342,7 +368,7 @@ __global__ void __launch_bounds__(LWG) k_rows_mid(double* B, const float* Id, do
     const int line = t / nf2, b = t - line * nf2, gl = l0 + line;
     if (gl < nlines) {
       z2 v = o[line * L + padpos(b, nf2)];
-      ((z2*)B)[(size_t)gl * nf2 + b] = {v.x * s2, v.y * s2};
+      stz(B, (size_t)gl * nf2 + b, z2{v.x * s2, v.y * s2});
     }
   }
 }
@@ -360,24 +386,37 @@ __global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, co
     z2 v{0.0, 0.0};
     if (gl < ncols) {
       const int n = gl / nf2, b = gl - n * nf2;
-      v = ((const z2*)B)[((size_t)n * L2 + a2) * nf2 + b];
+      v = ldz(B, ((size_t)n * L2 + a2) * nf2 + b);
     }
     sa[line * L2 + a2] = v;
+  }
+  // kernel values of this thread's cropped elements, loaded before the transforms
+  constexpr int NC = (LINE_ELEMS / 2 + LWG - 1) / LWG;
+  z2 hv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int t = threadIdx.x + k * LWG, line = t / L1, a = t - line * L1, gl = l0 + line;
+    hv[k] = z2{0.0, 0.0};
+    if (t < nl * L1 && gl < ncols) {
+      const int b = gl % nf2;
+      hv[k] = z2{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
+    }
   }
   __syncthreads();
   z2* r = lds_fft(sa, sb, nl, L2, L2, -1, stw, L2);
   z2* q = (r == sa) ? sb : sa;
   const double s2 = 1.0 / sqrt((double)L2);
-  for (int t = threadIdx.x; t < nl * L1; t += LWG) {
-    const int line = t / L1, a = t - line * L1, gl = l0 + line;
-    z2 v{0.0, 0.0};
-    if (gl < ncols) {
-      const int b = gl % nf2;
-      z2 hv{h[2 * (a * nf2 + b)], h[2 * (a * nf2 + b) + 1]};
-      z2 x = r[line * L2 + padpos(a, nf1)];
-      v = zmulc(z2{x.x * s2, x.y * s2}, hv);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int t = threadIdx.x + k * LWG, line = t / L1, a = t - line * L1, gl = l0 + line;
+    if (t < nl * L1) {
+      z2 v{0.0, 0.0};
+      if (gl < ncols) {
+        z2 x = r[line * L2 + padpos(a, nf1)];
+        v = zmulc(z2{x.x * s2, x.y * s2}, hv[k]);
+      }
+      q[line * L2 + a] = v;
     }
-    q[line * L2 + a] = v;
   }
   __syncthreads();
   const z2* o = lds_fft(q, r, nl, L2, L1, +1, stw, L2);
@@ -387,7 +426,7 @@ __global__ void __launch_bounds__(LWG) k_cols_adj(double* A, const double* B, co
     if (gl < ncols) {
       const int n = gl / nf2, b = gl - n * nf2;
       z2 v = o[line * L2 + a];
-      ((z2*)A)[((size_t)n * nf1 + a) * nf2 + b] = {v.x * s1, v.y * s1};
+      stz(A, ((size_t)n * nf1 + a) * nf2 + b, z2{v.x * s1, v.y * s1});
     }
   }
 }
@@ -402,7 +441,7 @@ __global__ void __launch_bounds__(LWG) k_rows_adj(double* A, int Nd, int nf1, in
   load_tw(stw, tw64, L);
   for (int t = threadIdx.x; t < nl * L; t += LWG) {
     const int gl = l0 + t / L;
-    sa[t] = (gl < nlines) ? ((const z2*)A)[(size_t)l0 * L + t] : z2{0.0, 0.0};
+    sa[t] = (gl < nlines) ? ldz(A, (size_t)l0 * L + t) : z2{0.0, 0.0};
   }
   __syncthreads();
   const z2* r = lds_fft(sa, sb, nl, L, L, +1, stw, L);
@@ -411,7 +450,7 @@ __global__ void __launch_bounds__(LWG) k_rows_adj(double* A, int Nd, int nf1, in
     const int gl = l0 + t / L;
     if (gl < nlines) {
       z2 v = r[t];
-      ((z2*)A)[(size_t)l0 * L + t] = {v.x * sc, v.y * sc};
+      stz(A, (size_t)l0 * L + t, z2{v.x * sc, v.y * sc});
     }
   }
 }
@@ -595,18 +634,27 @@ __device__ void bsum_finish(int nv, double* red, double* out) {
 // products instead of one reduction per stored pair.
 constexpr int SC_HIST = 9;
 
-__device__ __forceinline__ int slot_of(double* sc, int m, int i) {
-  return ((int)sc[0] - (int)sc[1] + i + 2 * m) % m;  // i-th oldest stored pair
-}
+// smat (LDS, SMAT doubles): the k x k blocks of SY and YY in age order, then
+// the small solve's u and p.
+constexpr int SMAT = 2 * 16 * 16 + 2 * 16;
 
-__device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, double* sh) {
-  const int k = (int)sc[1];
-  const double* SY = sc + SC_HIST;
-  const double* YY = sc + SC_HIST + m * m;
+__device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, double* sh, double* smat) {
+  const int head = (int)sc[0], k = (int)sc[1];
+  double* R = smat;             // R[i][j] = s_i^T y_j (age order), row stride 16
+  double* W = smat + 256;       // W[i][j] = y_i^T y_j
+  double* u = smat + 512;
+  double* p = smat + 528;
+  for (int t = threadIdx.x; t < k * k; t += PWG) {
+    const int i = t / k, j = t - (t / k) * k;
+    const int si = (head - k + i + 2 * m) % m, sj = (head - k + j + 2 * m) % m;
+    R[i * 16 + j] = sc[SC_HIST + si * m + sj];
+    W[i * 16 + j] = sc[SC_HIST + m * m + si * m + sj];
+  }
   // one pass: a_j = s_j^T g, b_j = y_j^T g, g^T g
   for (int j = 0; j < k; ++j) {
-    const double* Sj = L.S + (size_t)slot_of(sc, m, j) * P;
-    const double* Yj = L.Y + (size_t)slot_of(sc, m, j) * P;
+    const int sl = (head - k + j + 2 * m) % m;
+    const double* Sj = L.S + (size_t)sl * P;
+    const double* Yj = L.Y + (size_t)sl * P;
     double xa = 0.0, xb = 0.0;
     for (int i = threadIdx.x; i < P; i += PWG) {
       const double gi = L.g[i];
@@ -620,29 +668,24 @@ __device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, dou
   for (int i = threadIdx.x; i < P; i += PWG) xg += L.g[i] * L.g[i];
   wave_put(xg, 2 * k, red);
   double* dots = sh;              // [2k + 1]
-  double* coef = sh + MAXV;       // [0] g coefficient, [1..1+k) S, [1+k..1+2k) Y, [1+2k] slope
+  double* coef = sh + MAXV;       // [0] g coefficient, [1..1+k) S, [1+k..1+2k) Y, [1+2k] history kept
   bsum_finish(2 * k + 1, red, dots);
   if (threadIdx.x == 0) {
     const double gg = dots[2 * k];
     double cg, slope;
-    if (k == 0) {
-      cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
-      slope = cg * gg;
-    } else {
-      int sl[16];
-      for (int j = 0; j < k; ++j) sl[j] = slot_of(sc, m, j);
-      const double gam = SY[sl[k - 1] * m + sl[k - 1]] / YY[sl[k - 1] * m + sl[k - 1]];
-      double u[16], p[16];
-      for (int i = k - 1; i >= 0; --i) {  // R u = a (R_ij = s_i^T y_j, i <= j)
+    bool keep = k > 0;
+    if (k > 0) {
+      const double gam = R[(k - 1) * 17] / W[(k - 1) * 17];
+      for (int i = k - 1; i >= 0; --i) {  // R u = a (upper triangle)
         double t = dots[i];
-        for (int j = i + 1; j < k; ++j) t -= SY[sl[i] * m + sl[j]] * u[j];
-        u[i] = t / SY[sl[i] * m + sl[i]];
+        for (int j = i + 1; j < k; ++j) t -= R[i * 16 + j] * u[j];
+        u[i] = t / R[i * 17];
       }
       for (int i = 0; i < k; ++i) {  // R^T p = (D + gam Y^T Y) u - gam b
-        double t = SY[sl[i] * m + sl[i]] * u[i] - gam * dots[k + i];
-        for (int j = 0; j < k; ++j) t += gam * YY[sl[i] * m + sl[j]] * u[j];
-        for (int j = 0; j < i; ++j) t -= SY[sl[j] * m + sl[i]] * p[j];
-        p[i] = t / SY[sl[i] * m + sl[i]];
+        double t = R[i * 17] * u[i] - gam * dots[k + i];
+        for (int j = 0; j < k; ++j) t += gam * W[i * 16 + j] * u[j];
+        for (int j = 0; j < i; ++j) t -= R[j * 16 + i] * p[j];
+        p[i] = t / R[i * 17];
       }
       // d = -H g = -gam g - S p + gam Y u
       cg = -gam;
@@ -652,23 +695,23 @@ __device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, dou
         coef[1 + k + j] = gam * u[j];
         slope += -p[j] * dots[j] + gam * u[j] * dots[k + j];
       }
-      if (!(slope < 0.0)) {  // not a descent direction: drop the history, use -g/||g||
-        cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
-        slope = cg * gg;
-        for (int j = 0; j < 2 * k; ++j) coef[1 + j] = 0.0;
-        sc[1] = 0;
-      }
+      if (!(slope < 0.0)) keep = false;  // not a descent direction: drop the history
+    }
+    if (!keep) {  // -g / ||g||
+      cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
+      slope = cg * gg;
+      sc[1] = 0;
     }
     coef[0] = cg;
-    coef[1 + 2 * k] = slope;
+    coef[1 + 2 * k] = keep ? 1.0 : 0.0;
     sc[2] = slope;
   }
   __syncthreads();
-  const int kk = (int)sc[1] < k ? 0 : k;  // history dropped above
+  const int kk = coef[1 + 2 * k] != 0.0 ? k : 0;
   for (int i = threadIdx.x; i < P; i += PWG) {
     double d = coef[0] * L.g[i];
     for (int j = 0; j < kk; ++j) {
-      const int sl = slot_of(sc, m, j);
+      const int sl = (head - k + j + 2 * m) % m;
       d += coef[1 + j] * L.S[(size_t)sl * P + i] + coef[1 + k + j] * L.Y[(size_t)sl * P + i];
     }
     L.d[i] = d;
@@ -747,6 +790,7 @@ __device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red
 __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, const double* gval, int* skip) {
   __shared__ double red[(PWG / 64) * MAXV];
   __shared__ double sh[2 * MAXV];
+  __shared__ double smat[SMAT];
   __shared__ int stop;
   double* sc = L.sc;
   if (*skip) return;
@@ -758,7 +802,7 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
       if (threadIdx.x == 0) *skip = 1;
       return;
     }
-    direction(L, P, m, red, sc, sh);
+    direction(L, P, m, red, sc, sh, smat);
     if (threadIdx.x == 0) {
       sc[3] = 1.0;
       sc[7] = 0.0;
