@@ -20,6 +20,7 @@ struct BatchProb {
   const void* I;
   cx<float>* t;
   cx<float>* vprev;
+  float* vscale;        // [P] spectral previous-iterate scale
   float* sums;          // [P][6] or null
   const float* rowmean;
   int K, P, code;
@@ -36,7 +37,7 @@ struct BatchArgs {
   int with_sums;         // pass the problems' sums pointers (else null)
   float tau, momentum;
   float er_beta;         // ER Nesterov factor; t and t_prev alternate between t and vprev
-  int er_swap;           // with er_beta: the current iterate is in vprev (odd iterations)
+  int swap;              // spectral steps, ER with er_beta: the current iterate is in vprev (odd steps)
   const cx<float>* tw32;
 };
 

@@ -55,15 +55,16 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.P = pr.P;
     a.K = pr.K;
     a.masks = pr.masks;
-    // ER with momentum reads t and t_prev and overwrites t_prev; the two
-    // buffers swap roles every iteration
+    // spectral steps and ER with momentum read the iterate and the previous
+    // one and overwrite the previous one; the two buffers swap roles every step
     const bool mom = MODE == BATCH_ER && b.er_beta != 0.f;
-    cx<float>* cur = (mom && b.er_swap) ? pr.vprev : pr.t;
-    cx<float>* oth = (mom && b.er_swap) ? pr.t : pr.vprev;
+    const bool two = mom || MODE == BATCH_SPEC;
+    cx<float>* cur = (two && b.swap) ? pr.vprev : pr.t;
+    cx<float>* oth = (two && b.swap) ? pr.t : pr.vprev;
     a.tin = cur;
-    a.tout = mom ? oth : cur;
+    a.tout = two ? oth : cur;
     a.din = oth;
-    a.tout2 = oth;
+    a.vscale = pr.vscale;
     a.I = pr.I;
     a.yin = nullptr;
     a.yout = nullptr;

@@ -12,7 +12,7 @@ enum Mode : int {
   M_ADJ = 2,         // x = A^H y                                   -> tout
   M_ER = 3,          // t <- A^H(sqrt(I) y/|y|)/(K N)               -> tout, sums {amp_res, f}
   M_GRAD = 4,        // g = -4 A^H(y (I - |y|^2))                   -> tout, sums {f}
-  M_SPEC = 5,        // heavy-ball power step on A^H diag(w) A      -> tout (v), tout2 (v_prev)
+  M_SPEC = 5,        // heavy-ball power step on A^H diag(w) A      -> tout (v), vscale
   M_LS = 6,          // quartic line-search sums for y = A t, z = A d -> sums[6]
   M_RES64 = 7,       // FP64 residual: sums64 {sum r^2, sum I^2}
   M_BACKPROP = 8     // x = A^H sqrt(I) / (K N)                     -> tout
@@ -24,11 +24,11 @@ struct RowArgs {
   int P, K;
   const cx<float>* masks;  // [K][N]
   const cx<float>* tin;    // [P][N]
-  const cx<float>* din;    // [P][N]  (M_LS: direction d; M_SPEC: previous v)
+  const cx<float>* din;    // [P][N]  (M_LS: direction d; M_SPEC: previous v / vscale; M_ER: t_prev)
   const void* I;           // [P][K][N] float or bf16
   const cx<float>* yin;    // [P][K][N] (M_ADJ)
   cx<float>* tout;         // [P][N]
-  cx<float>* tout2;        // [P][N]  (M_SPEC: new previous v)
+  float* vscale;           // [P] M_SPEC: scale of din (read), of the new previous iterate tin (written)
   void* yout;              // [P][K][N] (M_FWD_*)
   float* sums;             // [P][NSUM]
   double* sums64;          // [P][2] (M_RES64)
@@ -360,36 +360,39 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       for (int i = 0; i < NSUM; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
     }
   } else if constexpr (MODE == M_SPEC) {
-    // lambda = Re <v, M v> (v has unit norm), x = M v - beta v_prev, normalise.
+    // lambda = Re <v, M v> (v has unit norm), x = M v - beta v_prev, v <- x / ||x||
+    // and v_prev <- v / ||x||. v_prev is held as u (din) times the per-row
+    // scale s, and the caller swaps the two row buffers every step, so the
+    // step writes only x / ||x|| (over u) and the new scale 1 / ||x||.
+    // ||x||^2 = |g|^2 - 2 beta s Re<u, g> + (beta s)^2 |u|^2 comes out of the
+    // same single reduction as lambda.
+    const float sp = valid ? gc(a.vscale)[prow] : 0.f;
     C vp[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) vp[i] = gload(drow + E0(i));
-    KSum l1[1] = {KSum{0.f, 0.f}};
+    KSum q[4] = {KSum{0.f, 0.f}, KSum{0.f, 0.f}, KSum{0.f, 0.f}, KSum{0.f, 0.f}};
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       C ti = TROW(i);
-      l1[0].add(ti.x * g[i].x + ti.y * g[i].y);
+      q[0].add(ti.x * g[i].x + ti.y * g[i].y);
+      q[1].add(norm2(g[i]));
+      q[2].add(vp[i].x * g[i].x + vp[i].y * g[i].y);
+      q[3].add(norm2(vp[i]));
     }
-    float lam;
-    row_reduce<PL::T, WG, 1>(l1, red, tid, &lam);
-    float cl = a.momentum * lam;
-    float beta = 0.25f * cl * cl;
-    KSum n1[1] = {KSum{0.f, 0.f}};
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      g[i] = g[i] - scl(vp[i], beta);
-      n1[0].add(norm2(g[i]));
-    }
-    float nn;
-    row_reduce<PL::T, WG, 1>(n1, red, tid, &nn);
-    float inv = (nn > 0.f) ? rsqrtf(nn) : 1.f;
+    float out[4];
+    row_reduce<PL::T, WG, 4>(q, red, tid, out);
+    const float lam = out[0];
+    const float cl = a.momentum * lam;
+    const float bs = 0.25f * cl * cl * sp;  // beta s
+    const float nn = fmaxf(out[1] - 2.f * bs * out[2] + bs * bs * out[3], 0.f);
+    const float inv = (nn > 0.f) ? rsqrtf(nn) : 1.f;
     if (valid) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        gstore(a.tout + prow * N + E0(i), scl(g[i], inv));
-        gstore(a.tout2 + prow * N + E0(i), scl(TROW(i), inv));
+      for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i] - scl(vp[i], bs), inv));
+      if (ltid == 0) {
+        gw(a.vscale)[prow] = inv;
+        if (a.sums) gw(a.sums)[prow * NSUM + 0] = lam;
       }
-      if (ltid == 0 && a.sums) gw(a.sums)[prow * NSUM + 0] = lam;
     }
   } else {
     float scale = 1.f;

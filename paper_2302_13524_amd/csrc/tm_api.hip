@@ -101,7 +101,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
-  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV,
+  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE,
   WS_PH_BASE = 100
 };
 
@@ -366,25 +366,30 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     double* rowsum = (double*)ws_get(c, WS_ROWSUM, (size_t)d.P * sizeof(double));
     float* rowmean = (float*)ws_get(c, WS_ROWMEAN, (size_t)d.P * sizeof(float));
     void* vprev = ws_get(c, WS_VPREV, (size_t)d.P * N * sizeof(tm_c32));
-    if (!rowsum || !rowmean || !vprev) return fail(c, TM_ENOMEM, "workspace");
+    float* vscale = (float*)ws_get(c, WS_VSCALE, (size_t)d.P * sizeof(float));
+    if (!rowsum || !rowmean || !vprev || !vscale) return fail(c, TM_ENOMEM, "workspace");
     int e = tmk::launch_row_isum(I, ibf, (int64_t)d.K * N, d.P, rowsum, rowmean, stream);
     if (!e) e = tmk::launch_row_rescale(t, N, d.P, 0, nullptr, 1.0, stream);
     if (!e) e = tmk::launch_fill_zero(vprev, (int64_t)d.P * N * sizeof(tm_c32), stream);
+    if (!e) e = tmk::launch_fill_zero(vscale, (int64_t)d.P * sizeof(float), stream);
     if (e) return hipfail(c, e, "spectral setup");
+    // v and the previous iterate alternate between t and the workspace row buffer
+    tmk::cx<float>* vb[2] = {tt, (tmk::cx<float>*)vprev};
     tmk::RowArgs s = a;
-    s.tin = tt;
-    s.tout = tt;
-    s.din = (const tmk::cx<float>*)vprev;
-    s.tout2 = (tmk::cx<float>*)vprev;
     s.rowmean = rowmean;
+    s.vscale = vscale;
     s.tau = o->spectral_tau;
     s.momentum = o->spectral_momentum;
     s.sums = sums;
     for (int it = 0; it < o->spectral_iters; ++it) {
+      s.tin = vb[it & 1];
+      s.din = vb[(it & 1) ^ 1];
+      s.tout = vb[(it & 1) ^ 1];
       r = run_row(c, fn, tmk::M_SPEC, ibf, s, stream);
       if (r) return r;
     }
-    e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
+    if (o->spectral_iters & 1) e = tmk::launch_copy(t, vprev, (int64_t)d.P * N * sizeof(tm_c32), stream);
+    if (!e) e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
     if (e) return hipfail(c, e, "spectral scale");
   }
 
@@ -786,6 +791,7 @@ struct tm_batch {
   std::vector<double*> rowsum, sums64;
   std::vector<float*> rowmean, sums;
   std::vector<void*> vprev;
+  std::vector<float*> vscale;
   hipStream_t cap = nullptr;
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
@@ -805,14 +811,21 @@ static int batch_enqueue(tm_batch* b, void* stream) {
       if (!e) e = tmk::launch_row_isum(p.I, ibf, (int64_t)p.d.K * N, p.d.P, b->rowsum[i], b->rowmean[i], stream);
       if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 0, nullptr, 1.0, stream);
       if (!e) e = tmk::launch_fill_zero(b->vprev[i], (int64_t)p.d.P * N * sizeof(tm_c32), stream);
+      if (!e) e = tmk::launch_fill_zero(b->vscale[i], (int64_t)p.d.P * sizeof(float), stream);
     }
     tmk::BatchArgs a = b->args;
     a.tau = o.spectral_tau;
     a.momentum = o.spectral_momentum;
-    for (int it = 0; it < o.spectral_iters && !e; ++it) e = tmk::batch_launch(tmk::BATCH_SPEC, ibf, 0, a, b->grid, stream);
+    for (int it = 0; it < o.spectral_iters && !e; ++it) {
+      a.swap = it & 1;  // v and the previous iterate alternate between t and vprev
+      e = tmk::batch_launch(tmk::BATCH_SPEC, ibf, 0, a, b->grid, stream);
+    }
     for (int i = 0; i < n && !e; ++i) {
       const tm_problem& p = b->probs[i];
-      if (p.d.P) e = tmk::launch_row_rescale(p.t, p.d.n1 * p.d.n2, p.d.P, 1, b->rowsum[i], (double)p.d.K * p.d.n1 * p.d.n2, stream);
+      if (!p.d.P) continue;
+      const int N = p.d.n1 * p.d.n2;
+      if (o.spectral_iters & 1) e = tmk::launch_copy(p.t, b->vprev[i], (int64_t)p.d.P * N * sizeof(tm_c32), stream);
+      if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 1, b->rowsum[i], (double)p.d.K * N, stream);
     }
   } else if (o.start == TM_START_BACKPROP) {
     for (int i = 0; i < n && !e; ++i) {
@@ -836,7 +849,7 @@ static int batch_enqueue(tm_batch* b, void* stream) {
     ea.er_beta = o.er_momentum;
   }
   for (int it = 0; it < o.iters && !e; ++it) {
-    ea.er_swap = mom ? (it & 1) : 0;
+    ea.swap = mom ? (it & 1) : 0;
     e = tmk::batch_launch(tmk::BATCH_ER, ibf, it == o.iters - 1, ea, b->grid, stream);
   }
   if (mom && (o.iters & 1)) {
@@ -898,7 +911,8 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     int rpi = tmk::batch_rows_per_item(gid);
     for (int blk = 0; blk * rpi < p.d.P; ++blk) items.push_back({i, blk});
     size_t N = (size_t)p.d.n1 * p.d.n2;
-    ws_bytes += al(p.d.P * 8) + al(p.d.P * 4) + al(p.d.P * tmk::NSUM * 4) + al(p.d.P * 16) + al(p.d.P * N * 8);
+    ws_bytes += al(p.d.P * 8) + al(p.d.P * 4) + al(p.d.P * tmk::NSUM * 4) + al(p.d.P * 16) + al(p.d.P * N * 8) +
+                al(p.d.P * 4);
   }
   size_t tab = al(n * sizeof(tmk::BatchProb)) + al(items.size() * sizeof(tmk::BatchItem));
   if (hipMalloc(&b->dmem, tab + ws_bytes + 256) != hipSuccess) { delete b; return fail(c, TM_ENOMEM, "batch workspace"); }
@@ -911,10 +925,12 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     b->sums.push_back((float*)w); w += al(p.d.P * tmk::NSUM * 4);
     b->sums64.push_back((double*)w); w += al(p.d.P * 16);
     b->vprev.push_back(w); w += al(p.d.P * N * 8);
+    b->vscale.push_back((float*)w); w += al(p.d.P * 4);
     hp[i].masks = (const tmk::cx<float>*)p.masks;
     hp[i].I = p.I;
     hp[i].t = (tmk::cx<float>*)p.t;
     hp[i].vprev = (tmk::cx<float>*)b->vprev[i];
+    hp[i].vscale = b->vscale[i];
     hp[i].sums = b->sums[i];
     hp[i].rowmean = b->rowmean[i];
     hp[i].K = p.d.K;

@@ -147,7 +147,7 @@ def test_spectral_start_steps(ctx, mom):
     masks, T, I, _ = problem(n1, n2, 4, P, cfg=909, noise=1e4)
     v0 = tm_synth.random_start(P, n1 * n2, np.ones(P), tm_synth.rng(909, 3))
     m, v, Ir = rounded(masks, v0, I)
-    for steps in (1, 3):
+    for steps in (1, 2, 3):
         ref = rt.spectral_start(ops.FFTOp(m, n1, n2), Ir, v, steps, tau=3.0, momentum=mom)
         tt = c64(v0)
         tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
