@@ -9,10 +9,12 @@ z = 20 wavelengths for the phase-offset step. All inputs are seeded and
 synthetic (the paper's measured data are not available).
 
 A step is one pass of the whole path over the batch: truncated spectral
-start (heavy-ball power iteration), error-reduction iterations up to the
-count at which the mean per-row fidelity first reaches 0.99 (found by an
-untimed instrumented run), the FP64 acceptance residual, and the per-row
-phase-offset correction from the defocus images. value = P / step time.
+start (heavy-ball power iteration), Nesterov-accelerated error-reduction
+iterations up to the count at which the mean per-row fidelity first reaches
+0.99, the FP64 acceptance residual, and the per-row phase-offset correction
+from the defocus images, run for the iteration count at which the offsets
+have converged (both counts found by untimed instrumented runs).
+value = P / step time.
 
 Also printed in the same JSON line: the roofline of the dominant kernel
 (the fused spectral-step or error-reduction kernel, whichever takes more of
@@ -51,7 +53,13 @@ def parse():
     ap.add_argument("--spectral-tau", type=float, default=2.5, help="truncation of the spectral weights")
     ap.add_argument("--spectral-momentum", type=float, default=0.999,
                     help="heavy-ball factor c of the spectral start (beta = (c lambda)^2 / 4)")
-    ap.add_argument("--phase-iters", type=int, default=100)
+    ap.add_argument("--phase-iters", type=int, default=200,
+                    help="phase L-BFGS iterations (with --phase-auto: the reference count and upper bound)")
+    ap.add_argument("--phase-auto", type=int, default=1,
+                    help="1: use the smallest count (multiple of 10) whose offset spread is within 1%% of the "
+                         "reference, found by an untimed run")
+    ap.add_argument("--phase-ftol", type=float, default=0.0,
+                    help="stop the phase solve after an accepted iteration lowering g by <= ftol * g")
     ap.add_argument("--max-iters", type=int, default=300)
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows in the CPU-baseline sample (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -235,6 +243,28 @@ def main():
     if n_er is None:
         raise SystemExit(f"error reduction did not reach mean fidelity 0.99 in {args.max_iters} iterations")
     log(f"spectral start fidelity {f_start:.4f}; ER reaches 0.99 after {n_er} iterations")
+
+    # ---- untimed instrumented run: phase iterations at which the offsets have converged (circular
+    # spread over the rows at fidelity >= 0.99 within 1 % of the spread after phase_iters_max)
+    t = v0t.clone()
+    tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", n_er), stats=False)
+    good0 = fidelity(t) >= 0.99
+    off_t = torch.angle(torch.sum(torch.conj(t) * Tt, dim=1)).double()
+
+    def spread_of(iters):
+        phi = torch.zeros(P, dtype=torch.float64, device=dev)
+        tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=iters, m=5, ftol=args.phase_ftol)
+        z = torch.exp(1j * (off_t - phi)[good0])
+        return float(torch.sqrt(-2 * torch.log(torch.abs(z.mean()) + 1e-300)).item())
+
+    n_ph = args.phase_iters
+    if args.phase_auto:
+        ref = spread_of(args.phase_iters)
+        for k in range(20, args.phase_iters, 10):
+            if spread_of(k) <= 1.01 * ref:
+                n_ph = k
+                break
+        log(f"phase offsets converge after {n_ph} iterations (spread {ref:.5f} rad at {args.phase_iters})")
     n_lb = None
     for k in () if args.no_lbfgs else (5, 10, 15, 20, 25, 30, 40, 50, 70, 100):
         t = v0t.clone()
@@ -250,7 +280,8 @@ def main():
         phi = None
         if phase:
             phi = torch.zeros(P, dtype=torch.float64, device=dev)
-            tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=args.phase_iters, m=5)
+            tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=n_ph, m=5,
+                                       ftol=args.phase_ftol)
         return t, raw, phi
 
     for _ in range(args.warmup):
@@ -349,7 +380,7 @@ def main():
                    "start": f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
                             f"(c {args.spectral_momentum})",
                    "solver": f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction",
-                   "iters_to_0.99": n_er, "phase_iters": args.phase_iters},
+                   "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_ftol": args.phase_ftol},
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
         "roofline_" + other: roofs[other]["alu"],

@@ -203,8 +203,10 @@ typedef struct {
 } tm_optics;
 
 typedef struct {
-  int32_t iters;       /* L-BFGS iterations over phi            */
-  int32_t m;           /* L-BFGS memory (1..16)                 */
+  int32_t iters;       /* L-BFGS iterations over phi (upper bound)                  */
+  int32_t m;           /* L-BFGS memory (1..16)                                     */
+  double ftol;         /* stop after an accepted iteration that lowers g by at most
+                          ftol * g (>= 0; 0 runs all iters)                         */
 } tm_phase_opts;
 
 /* Solve the per-row phase offsets phi of TM_true = diag(e^{j phi}) TM_est

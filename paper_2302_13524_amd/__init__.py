@@ -58,7 +58,7 @@ class tm_optics(ctypes.Structure):
 
 
 class tm_phase_opts(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("m", ctypes.c_int32)]
+    _fields_ = [("iters", ctypes.c_int32), ("m", ctypes.c_int32), ("ftol", ctypes.c_double)]
 
 
 class tm_mlp_dims(ctypes.Structure):
@@ -294,13 +294,14 @@ def tm_phase_objective(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, 
     return g, grad
 
 
-def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2, iters=100, m=5):
-    """Solve the per-row phase offsets in place in phi ([P] float64); returns g."""
+def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2, iters=100, m=5, ftol=0.0):
+    """Solve the per-row phase offsets in place in phi ([P] float64); returns g.
+    Stops early after an accepted iteration that lowers g by at most ftol * g."""
     P, N = tm_est.shape
     Nd = theta.shape[0]
     dd = _ddims(P, N, Nd, nf1, nf2)
     op = tm_optics(*[float(v) for v in optics])
-    po = tm_phase_opts(int(iters), int(m))
+    po = tm_phase_opts(int(iters), int(m), float(ftol))
     g = ctypes.c_double(0.0)
     rc = ctx.lib.tm_phase_offset_correct(ctx.h, ctypes.byref(dd), _ptr(pix), _ptr(tm_est), _ptr(theta),
                                          _ptr(I_d), ctypes.byref(op), _ptr(phi), ctypes.byref(po),

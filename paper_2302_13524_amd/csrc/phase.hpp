@@ -55,6 +55,6 @@ int phase_lb_state_doubles(int m);
 // evaluation, then per iteration phase_lb_iter (decide on the pending trial,
 // new direction or halved step, trial point) and the evaluation at phit.
 int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream);
-int phase_lb_iter(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, void* stream);
+int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip, void* stream);
 
 }  // namespace tmk

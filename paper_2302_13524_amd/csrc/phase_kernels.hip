@@ -618,7 +618,8 @@ __device__ void bsum_finish(int nv, double* red, double* out) {
 // back-to-back without host synchronisation. State sc (doubles):
 // [0] head, [1] count, [2] slope of d, [3] step a, [4] objective f at phi,
 // [5] accepted iterations, [6] last trial accepted, [7] halvings of this
-// direction, [8] a trial is pending; then the m x m matrices SY[i][j] =
+// direction, [8] a trial is pending, [9] converged (the last accepted trial
+// lowered f by at most ftol f); then the m x m matrices SY[i][j] =
 // s_i^T y_j and YY[i][j] = y_i^T y_j over the history slots.
 // *skip = 1 ends the solve (every later kernel returns at once).
 // One iteration is k_piter followed by the objective and gradient at phit:
@@ -632,7 +633,7 @@ __device__ void bsum_finish(int nv, double* red, double* out) {
 // where R u = a and R^T p = (D + gamma Y^T Y) u - gamma b. This equals the
 // two-loop recursion, but needs one pass over the vectors for all the dot
 // products instead of one reduction per stored pair.
-constexpr int SC_HIST = 9;
+constexpr int SC_HIST = 10;
 
 // smat (LDS, SMAT doubles): the k x k blocks of SY and YY in age order, then
 // the small solve's u and p.
@@ -722,7 +723,8 @@ __device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, dou
 // Armijo decision on the trial whose objective is gval[0] and gradient L.gt.
 // An accepted trial goes into the history slot head: s = a d, y = g_t - g,
 // with its dot products against the stored pairs (one pass).
-__device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red, double* sc, double* sh) {
+__device__ void decide(PhaseLb& L, int P, int m, double ftol, const double* gval, double* red, double* sc,
+                       double* sh) {
   const double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
   const bool ok = fn <= f + 1e-4 * a * slope;
   if (!ok) {
@@ -780,6 +782,7 @@ __device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red
     } else {
       sc[1] = keep;  // slot head no longer holds a stored pair
     }
+    sc[9] = (f - fn <= ftol * fabs(fn)) ? 1.0 : 0.0;
     sc[4] = fn;
     sc[5] += 1.0;
     sc[6] = 1.0;
@@ -787,7 +790,8 @@ __device__ void decide(PhaseLb& L, int P, int m, const double* gval, double* red
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, const double* gval, int* skip) {
+__global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, double ftol, const double* gval,
+                                                int* skip) {
   __shared__ double red[(PWG / 64) * MAXV];
   __shared__ double sh[2 * MAXV];
   __shared__ double smat[SMAT];
@@ -796,9 +800,9 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
   if (*skip) return;
   if (threadIdx.x == 0) stop = 0;
   __syncthreads();  // every thread has read *skip before thread 0 may set it
-  if (sc[8] != 0.0) decide(L, P, m, gval, red, sc, sh);
+  if (sc[8] != 0.0) decide(L, P, m, ftol, gval, red, sc, sh);
   if (sc[6] != 0.0) {
-    if (sc[5] >= (double)iters) {
+    if (sc[5] >= (double)iters || (ftol > 0.0 && sc[9] != 0.0)) {
       if (threadIdx.x == 0) *skip = 1;
       return;
     }
@@ -844,8 +848,8 @@ int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void*
   k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, phase_lb_state_doubles(m), gval, skip);
   return (int)hipGetLastError();
 }
-int phase_lb_iter(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, void* stream) {
-  k_piter<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, iters, gval, skip);
+int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip, void* stream) {
+  k_piter<<<1, PWG, 0, (hipStream_t)stream>>>(L, P, m, iters, ftol, gval, skip);
   return (int)hipGetLastError();
 }
 

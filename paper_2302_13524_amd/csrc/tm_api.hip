@@ -518,6 +518,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   if (r) return r;
   if (!phi || !po) return fail(c, TM_EINVAL, "null pointer argument");
   if (po->iters < 0 || po->m < 1 || po->m > 16) return fail(c, TM_EINVAL, "iters >= 0 and 1 <= m <= 16");
+  if (!(po->ftol >= 0.0)) return fail(c, TM_EINVAL, "ftol must be >= 0");
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
   tmk::PhaseDims pd;
@@ -553,7 +554,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
     hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
     if (he == hipSuccess) {
-      e = tmk::phase_lb_iter(L, P, m, po->iters, w.gval, w.skip, cap);
+      e = tmk::phase_lb_iter(L, P, m, po->iters, po->ftol, w.gval, w.skip, cap);
       if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
       hipError_t he2 = hipStreamEndCapture(cap, &graph);
       if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);

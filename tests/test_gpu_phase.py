@@ -102,3 +102,26 @@ def test_rectangular_grids_images_objective(ctx, nf1, nf2, P, N, Nd):
                                      torch.from_numpy(phi).to(dev()), nf1, nf2)
     assert abs(gv.item() - gref) <= 1e-9 * gref
     assert relerr(grad.cpu().numpy(), grad_ref) < 1e-9
+
+
+def test_ftol_stops_early(ctx):
+    # a relative-decrease tolerance ends the solve after an accepted iteration:
+    # an enormous one after the first (same result as iters=1), a tiny one
+    # still at the converged offsets
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, 0.6, 0.6, cfg=954)
+    args = (torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta), f32(Id),
+            (LAM, PS, 0.6, 20 * LAM))
+
+    def solve(iters, ftol):
+        phi = torch.zeros(P, dtype=torch.float64, device=dev())
+        g = tm.tm_phase_offset_correct(ctx, *args, phi, nf, nf, iters=iters, m=5, ftol=ftol)
+        return phi.cpu().numpy(), g
+
+    one, g1 = solve(1, 0.0)
+    big, gb = solve(200, 1e300)
+    assert np.array_equal(one, big) and g1 == gb
+    tight, gt = solve(200, 1e-14)
+    assert np.max(np.abs(df.circular_offset_error(tight, phi_true))) < 1e-5
+    with pytest.raises(tm.TMError, match="ftol"):
+        solve(10, -1.0)
