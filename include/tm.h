@@ -127,6 +127,11 @@ typedef struct {
   float spectral_tau;      /* weight truncation w = min(I/mean(I_p), tau), e.g. 3        */
   float spectral_momentum; /* heavy-ball factor c in [0, 1): beta = (c lambda)^2/4       */
   float er_momentum;       /* ER only: Nesterov factor b in [0, 1): t <- ER(t + b (t - t_prev)); 0 = plain ER */
+  float spectral_lower;    /* lower end l of the rest of the spectrum, as a fraction of lambda,
+                              in [-1, c]: step x <- (M - s) x - beta x_prev with
+                              s = (c + l) lambda / 2, beta = ((c - l) lambda / 2)^2 / 4;
+                              l = -c is the unshifted heavy-ball step, l = 0 uses that
+                              A^H diag(w) A is positive semidefinite                      */
 } tm_retrieve_opts;
 
 /* Per-row results written to device memory. */

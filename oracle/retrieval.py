@@ -111,7 +111,7 @@ def spectral_weights(I: np.ndarray, tau: float) -> np.ndarray:
 
 
 def spectral_start(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3.0,
-                   momentum: float = 0.0) -> np.ndarray:
+                   momentum: float = 0.0, lower: float | None = None) -> np.ndarray:
     """Truncated spectral start: power iteration on M = A^H diag(w) A from v0
     (unit-normalised each step), then scaled to ||t||^2 = sum(I)/(K N).
 
@@ -121,7 +121,15 @@ def spectral_start(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3
     Rayleigh quotient of the current unit vector; both x_{k+1} and x_k are
     divided by ||x_{k+1}|| so the recurrence keeps its ratios. It converges
     to the same top eigenvector in fewer steps. c = 0 is plain power
-    iteration."""
+    iteration.
+
+    The recurrence is the Chebyshev-type iteration for the rest of the
+    spectrum assumed in [-c lambda, c lambda]. M is positive semidefinite,
+    so the rest lies in [0, c lambda]: lower = l centres the iteration on
+    the interval [l lambda, c lambda], x_{k+1} = (M - sigma_k) x_k -
+    beta_k x_{k-1} with sigma_k = (c + l) lambda_k / 2 and beta_k =
+    ((c - l) lambda_k / 2)^2 / 4 (the shifted matrix has the same
+    eigenvectors). lower = None is l = -c (no shift)."""
     w = spectral_weights(I, tau)
     v = np.array(v0, dtype=np.complex128)
     n = np.linalg.norm(v, axis=1)
@@ -130,8 +138,10 @@ def spectral_start(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3
     for _ in range(iters):
         Mv = op.adjoint(w * op.forward(v))
         lam = rdot(v, Mv)
-        beta = (momentum * lam) ** 2 / 4.0
-        x = Mv - beta[:, None] * vp
+        lo = -momentum if lower is None else lower
+        sigma = (momentum + lo) * lam / 2.0
+        beta = ((momentum - lo) * lam / 2.0) ** 2 / 4.0
+        x = Mv - sigma[:, None] * v - beta[:, None] * vp
         n = np.linalg.norm(x, axis=1)
         n = np.where(n > 0, n, 1.0)[:, None]
         vp = v / n

@@ -44,7 +44,7 @@ class tm_retrieve_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("iters", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
                 ("I_dtype", ctypes.c_int32), ("start", ctypes.c_int32), ("spectral_iters", ctypes.c_int32),
                 ("spectral_tau", ctypes.c_float), ("spectral_momentum", ctypes.c_float),
-                ("er_momentum", ctypes.c_float)]
+                ("er_momentum", ctypes.c_float), ("spectral_lower", ctypes.c_float)]
 
 
 class tm_defocus_dims(ctypes.Structure):
@@ -255,11 +255,13 @@ def decode_stats(raw: torch.Tensor) -> RowStats:
 
 
 def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", spectral_iters=30,
-                  spectral_tau=3.0, spectral_momentum=0.98, er_momentum=0.0) -> tm_retrieve_opts:
+                  spectral_tau=3.0, spectral_momentum=0.98, er_momentum=0.0,
+                  spectral_lower=None) -> tm_retrieve_opts:
     m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS}[method]
     s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL}[start]
     return tm_retrieve_opts(m, int(iters), int(lbfgs_m), TM_BF16 if bf16 else TM_F32, s, int(spectral_iters),
-                            float(spectral_tau), float(spectral_momentum), float(er_momentum))
+                            float(spectral_tau), float(spectral_momentum), float(er_momentum),
+                            float(-spectral_momentum if spectral_lower is None else spectral_lower))
 
 
 def tm_retrieve(ctx: Context, masks, I, t, n1, n2, opts: tm_retrieve_opts | None = None, stats=True, **kw):

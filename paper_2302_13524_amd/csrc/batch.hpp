@@ -35,7 +35,7 @@ struct BatchArgs {
   const BatchItem* items;
   int n_items;
   int with_sums;         // pass the problems' sums pointers (else null)
-  float tau, momentum;
+  float tau, momentum, lower;
   float er_beta;         // ER Nesterov factor; t and t_prev alternate between t and vprev
   int swap;              // spectral steps, ER with er_beta: the current iterate is in vprev (odd steps)
   const cx<float>* tw32;

@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.rowmean = pr.rowmean;
     a.tau = b.tau;
     a.momentum = b.momentum;
+    a.spec_lower = b.lower;
     a.er_beta = mom ? b.er_beta : 0.f;
     a.out_bf16 = 0;
     a.tw32 = b.tw32;

@@ -35,6 +35,7 @@ struct RowArgs {
   const float* rowmean;    // [P] mean of I per row (M_SPEC)
   float tau;               // M_SPEC truncation
   float momentum;          // M_SPEC heavy-ball factor c
+  float spec_lower;        // M_SPEC lower end l of the rest of the spectrum (fraction of lambda)
   float er_beta;           // M_ER Nesterov factor b: iterate from z = tin + b (tin - din), din = t_prev
   int out_bf16;            // M_FWD_INT output type
   const cx<float>* tw32;   // twiddle tables, table of length L at offset L-1
@@ -360,17 +361,21 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       for (int i = 0; i < NSUM; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
     }
   } else if constexpr (MODE == M_SPEC) {
-    // lambda = Re <v, M v> (v has unit norm), x = M v - beta v_prev, v <- x / ||x||
-    // and v_prev <- v / ||x||. v_prev is held as u (din) times the per-row
-    // scale s, and the caller swaps the two row buffers every step, so the
-    // step writes only x / ||x|| (over u) and the new scale 1 / ||x||.
-    // ||x||^2 = |g|^2 - 2 beta s Re<u, g> + (beta s)^2 |u|^2 comes out of the
-    // same single reduction as lambda.
+    // lambda = Re <v, M v> (v has unit norm); x = (M - sigma) v - beta v_prev
+    // with sigma = (c + l) lambda / 2, beta = ((c - l) lambda / 2)^2 / 4;
+    // v <- x / ||x|| and v_prev <- v / ||x||. v_prev is held as u (din) times
+    // the per-row scale s, and the caller swaps the two row buffers every
+    // step, so the step writes only x / ||x|| (over u) and the new scale.
+    // ||x||^2 expands in sums that come out of the same single reduction as
+    // lambda (b = beta s):
+    //   |g|^2 + sigma^2 |v|^2 + b^2 |u|^2 - 2 sigma lambda - 2 b Re<u, g> + 2 sigma b Re<u, v>.
     const float sp = valid ? gc(a.vscale)[prow] : 0.f;
     C vp[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) vp[i] = gload(drow + E0(i));
-    KSum q[4] = {KSum{0.f, 0.f}, KSum{0.f, 0.f}, KSum{0.f, 0.f}, KSum{0.f, 0.f}};
+    KSum q[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) q[i] = KSum{0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       C ti = TROW(i);
@@ -378,17 +383,23 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       q[1].add(norm2(g[i]));
       q[2].add(vp[i].x * g[i].x + vp[i].y * g[i].y);
       q[3].add(norm2(vp[i]));
+      q[4].add(norm2(ti));
+      q[5].add(vp[i].x * ti.x + vp[i].y * ti.y);
     }
-    float out[4];
-    row_reduce<PL::T, WG, 4>(q, red, tid, out);
+    float out[6];
+    row_reduce<PL::T, WG, 6>(q, red, tid, out);
     const float lam = out[0];
-    const float cl = a.momentum * lam;
-    const float bs = 0.25f * cl * cl * sp;  // beta s
-    const float nn = fmaxf(out[1] - 2.f * bs * out[2] + bs * bs * out[3], 0.f);
+    const float sig = 0.5f * (a.momentum + a.spec_lower) * lam;
+    const float rad = 0.5f * (a.momentum - a.spec_lower) * lam;
+    const float bs = 0.25f * rad * rad * sp;  // beta s
+    const float nn = fmaxf(out[1] + sig * sig * out[4] + bs * bs * out[3] - 2.f * sig * lam - 2.f * bs * out[2] +
+                               2.f * sig * bs * out[5],
+                           0.f);
     const float inv = (nn > 0.f) ? rsqrtf(nn) : 1.f;
     if (valid) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i] - scl(vp[i], bs), inv));
+      for (int i = 0; i < E; ++i)
+        gstore(a.tout + prow * N + E0(i), scl(g[i] - scl(TROW(i), sig) - scl(vp[i], bs), inv));
       if (ltid == 0) {
         gw(a.vscale)[prow] = inv;
         if (a.sums) gw(a.sums)[prow * NSUM + 0] = lam;

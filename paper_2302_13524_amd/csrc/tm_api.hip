@@ -341,6 +341,8 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     if (!(o->spectral_tau > 0.f)) return fail(c, TM_EINVAL, "spectral_tau must be > 0");
     if (!(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f))
       return fail(c, TM_EINVAL, "spectral_momentum must be in [0, 1)");
+    if (!(o->spectral_lower >= -1.f && o->spectral_lower <= o->spectral_momentum))
+      return fail(c, TM_EINVAL, "spectral_lower must be in [-1, spectral_momentum]");
   }
   if (!(o->er_momentum >= 0.f && o->er_momentum < 1.f)) return fail(c, TM_EINVAL, "er_momentum must be in [0, 1)");
   if (o->method == TM_METHOD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
@@ -380,6 +382,7 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     s.vscale = vscale;
     s.tau = o->spectral_tau;
     s.momentum = o->spectral_momentum;
+    s.spec_lower = o->spectral_lower;
     s.sums = sums;
     for (int it = 0; it < o->spectral_iters; ++it) {
       s.tin = vb[it & 1];
@@ -817,6 +820,7 @@ static int batch_enqueue(tm_batch* b, void* stream) {
     tmk::BatchArgs a = b->args;
     a.tau = o.spectral_tau;
     a.momentum = o.spectral_momentum;
+    a.lower = o.spectral_lower;
     for (int it = 0; it < o.spectral_iters && !e; ++it) {
       a.swap = it & 1;  // v and the previous iterate alternate between t and vprev
       e = tmk::batch_launch(tmk::BATCH_SPEC, ibf, 0, a, b->grid, stream);
@@ -886,7 +890,8 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
       o->start > TM_START_SPECTRAL)
     return fail(c, TM_EINVAL, "bad options");
   if (o->start == TM_START_SPECTRAL &&
-      (o->spectral_iters < 0 || !(o->spectral_tau > 0.f) || !(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f)))
+      (o->spectral_iters < 0 || !(o->spectral_tau > 0.f) || !(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f) ||
+       !(o->spectral_lower >= -1.f && o->spectral_lower <= o->spectral_momentum)))
     return fail(c, TM_EINVAL, "bad spectral options");
   HIPCHK(c, hipSetDevice(c->device));
   tm_batch* b = new tm_batch;

@@ -55,7 +55,7 @@ def test_create_reports_missing_device_or_bad_index():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(tm.tm_dims) == 16
-    assert ctypes.sizeof(tm.tm_retrieve_opts) == 36
+    assert ctypes.sizeof(tm.tm_retrieve_opts) == 40
     assert ctypes.sizeof(tm.tm_defocus_dims) == 20
     assert ctypes.sizeof(tm.tm_optics) == 32
     assert tm.ROW_STATS_BYTES == 24

@@ -141,18 +141,18 @@ def test_backprop_start(ctx):
     assert relerr(tt.cpu().numpy(), ref) < OPTOL
 
 
-@pytest.mark.parametrize("mom", [0.0, 0.98])
-def test_spectral_start_steps(ctx, mom):
+@pytest.mark.parametrize("mom,lower", [(0.0, None), (0.98, None), (0.999, 0.0), (0.9, 0.3)])
+def test_spectral_start_steps(ctx, mom, lower):
     n1, n2, P = 32, 32, 21
     masks, T, I, _ = problem(n1, n2, 4, P, cfg=909, noise=1e4)
     v0 = tm_synth.random_start(P, n1 * n2, np.ones(P), tm_synth.rng(909, 3))
     m, v, Ir = rounded(masks, v0, I)
     for steps in (1, 2, 3):
-        ref = rt.spectral_start(ops.FFTOp(m, n1, n2), Ir, v, steps, tau=3.0, momentum=mom)
+        ref = rt.spectral_start(ops.FFTOp(m, n1, n2), Ir, v, steps, tau=3.0, momentum=mom, lower=lower)
         tt = c64(v0)
         tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
                        tm.retrieve_opts("er", iters=0, start="spectral", spectral_iters=steps,
-                                        spectral_momentum=mom))
+                                        spectral_momentum=mom, spectral_lower=lower))
         assert relerr(tt.cpu().numpy(), ref) < 1e-4 * steps
 
 

@@ -324,3 +324,27 @@ def test_accelerated_er_converges_faster_on_noiseless_rows():
     assert f[0.8].min() > 0.95 and f[0.0].mean() < 0.95
     assert f[-0.3].mean() < f[0.0].mean() < f[0.8].mean()
     assert rt.fidelity(rt.er_accelerated(op, I, t0, 40, 0.8), T).min() > 0.999
+
+
+def test_shifted_momentum_power_iteration():
+    # M is PSD, so the rest of its spectrum lies in [0, lambda_2]: centring the
+    # heavy-ball recurrence on that interval (lower = 0) reaches the top
+    # eigenvector of the dense matrix (numpy.linalg.eigh) in fewer steps than
+    # the symmetric interval; lower = -c is the unshifted recurrence
+    masks, t, g = small_problem(4, 4, K=4, P=1, seed=23)
+    d = ops.DenseOp(masks, 4, 4)
+    I = ops.intensities(d, t)
+    w = rt.spectral_weights(I, 3.0).reshape(-1)
+    ev, V = np.linalg.eigh(d.A.conj().T @ (w[:, None] * d.A))
+    assert ev[0] >= -1e-9 * ev[-1]
+    c = ev[-2] / ev[-1]
+    v0 = g.standard_normal((1, 16)) + 1j * g.standard_normal((1, 16))
+
+    def overlap(v):
+        return np.abs(np.vdot(V[:, -1], v[0])) ** 2 / np.vdot(v[0], v[0]).real
+
+    a = rt.spectral_start(d, I, v0, 12, momentum=c)
+    assert np.array_equal(a, rt.spectral_start(d, I, v0, 12, momentum=c, lower=-c))
+    b = rt.spectral_start(d, I, v0, 12, momentum=c, lower=0.0)
+    assert 1 - overlap(b) < 0.5 * (1 - overlap(a))
+    assert overlap(rt.spectral_start(d, I, v0, 300, momentum=c, lower=0.0)) > 1 - 1e-10
