@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--spectral-iters", type=int, default=32)
+    ap.add_argument("--spectral-iters", type=int, default=24)
     ap.add_argument("--spectral-tau", type=float, default=2.5, help="truncation of the spectral weights")
-    ap.add_argument("--spectral-momentum", type=float, default=0.999,
-                    help="heavy-ball factor c of the spectral start (beta = (c lambda)^2 / 4)")
+    ap.add_argument("--spectral-momentum", type=float, default=0.99,
+                    help="heavy-ball factor c of the spectral start")
+    ap.add_argument("--spectral-lower", type=float, default=0.0,
+                    help="lower end of the rest of the spectrum (fraction of lambda); -c: unshifted heavy ball")
     ap.add_argument("--phase-iters", type=int, default=200,
                     help="phase L-BFGS iterations (with --phase-auto: the reference count and upper bound)")
     ap.add_argument("--phase-auto", type=int, default=1,
@@ -226,6 +228,7 @@ def main():
     def opts(method, iters, start="spectral"):
         return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=args.spectral_tau,
                                 spectral_momentum=args.spectral_momentum,
+                                spectral_lower=args.spectral_lower,
                                 er_momentum=beta if method == "er" else 0.0)
 
     # ---- untimed instrumented run: iterations to mean fidelity 0.99 (each count run
@@ -378,7 +381,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "P": P, "N": N, "grid": [n1, n2], "K": K,
                    "start": f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
-                            f"(c {args.spectral_momentum})",
+                            f"(c {args.spectral_momentum}, interval [{args.spectral_lower}, c] lambda)",
                    "solver": f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction",
                    "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_ftol": args.phase_ftol},
         "roofline": roofline,
@@ -427,6 +430,7 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
     t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp,
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
+                                                   spectral_lower=args.spectral_lower,
                                                    er_momentum=args.er_momentum)
     torch.cuda.synchronize()
     a = time.perf_counter()
@@ -434,6 +438,7 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
         t, redone = learned.retrieve_with_fallback(ctx, net, mk, It, n1, n2, n_er, v0t, spectral_iters=sp,
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
+                                                   spectral_lower=args.spectral_lower,
                                                    er_momentum=args.er_momentum)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) * 1e3 / 3
@@ -474,6 +479,7 @@ def batch_variant(ctx, args):
     b = tm.Batch(ctx, probs, tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True,
                                               spectral_tau=args.spectral_tau,
                                               spectral_momentum=args.spectral_momentum,
+                                              spectral_lower=args.spectral_lower,
                                               er_momentum=beta), use_graph=True)
 
     def run():
@@ -517,7 +523,7 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P):
     def run(rows):
         I = I_np[rows].astype(np.float64)
         t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau,
-                              momentum=args.spectral_momentum)
+                              momentum=args.spectral_momentum, lower=args.spectral_lower)
         return rt.er_accelerated(op, I, t, n_er, beta)
 
     g = np.random.default_rng(123)
