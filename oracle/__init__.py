@@ -18,4 +18,5 @@ Modules:
              L-BFGS with exact quartic line search (Alg. 1), fidelity
   defocus    angular-spectrum defocus model and phase-offset solve (Sec. 2.3)
   mlp        learned-start network in FP64 (forward, backward, loss, Adam)
+  preprocess half-sampling, fiber mask and per-pixel rows of the image stack
 """
