@@ -60,7 +60,7 @@ typedef struct {
 } tm_dims;
 
 /* Intensity storage type. */
-enum { TM_F32 = 0, TM_BF16 = 1 };
+enum { TM_F32 = 0, TM_BF16 = 1, TM_U16 = 2 /* camera images only */ };
 
 /* ---- context ----------------------------------------------------------- */
 
@@ -308,6 +308,38 @@ int tm_profile_enable(tm_ctx *ctx, int enable);
  * 7 FP64 residual, 8 back-propagation) since enabling. Synchronises the
  * context's device. */
 int tm_profile_query(tm_ctx *ctx, int mode, double *ms, int64_t *launches);
+
+/* ---------------------------------------------------------------------------
+ * Preprocessing of the measured image stack (Sec. 2.2, the paragraph after
+ * Algorithm 1): the images are half-sampled (the 1-based odd rows and
+ * columns, i.e. 0-based even: an (H/2) x (W/2) grid, raster index
+ * q = y (W/2) + x), a binary fiber mask keeps the pixels holding frac
+ * (0.999 in the paper) of the total intensity, and each kept pixel becomes
+ * one row of K N intensities (one per image, in image order = the row order
+ * of A).
+ *   stack  [n_img][H][W] device, TM_U16 (camera counts) or TM_F32, H and W even
+ */
+
+/* energy [(H/2)(W/2)] double (device): intensity of each kept pixel summed
+ * over all images, FP64 (exact for TM_U16 stacks). */
+int tm_pre_energy(tm_ctx *ctx, const void *stack, int32_t stack_dtype, int64_t n_img, int32_t H, int32_t W,
+                  double *energy, void *stream);
+
+/* The smallest set of pixels, taken by decreasing energy (ties by increasing
+ * raster index), whose summed energy first reaches frac (0 < frac <= 1) of
+ * the total; an all-zero energy gives the empty set. pix [npix] int32
+ * (device) receives the set in increasing raster order, *P_out (host) its
+ * size. npix <= 8192 (the sort runs in one workgroup's LDS); energies must be
+ * non-negative. Synchronous with respect to the host. */
+int tm_pre_fiber_mask(tm_ctx *ctx, const double *energy, int32_t npix, double frac, int32_t *pix,
+                      int32_t *P_out, void *stream);
+
+/* out [P][n_img] (device, TM_F32 or TM_BF16 with round-to-nearest-even):
+ * out[p][i] = stack[i][2 y_p][2 x_p] with pix[p] = y_p (W/2) + x_p, i.e. the
+ * rows tm_retrieve takes as I [P][K][n1][n2] when n_img = K n1 n2. pix
+ * entries are checked on the host (outside the grid: TM_EINVAL). */
+int tm_pre_gather(tm_ctx *ctx, const void *stack, int32_t stack_dtype, int64_t n_img, int32_t H, int32_t W,
+                  const int32_t *pix, int32_t P, void *out, int32_t out_dtype, void *stream);
 
 #ifdef __cplusplus
 }

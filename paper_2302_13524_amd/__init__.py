@@ -31,6 +31,7 @@ EXPORTED = (
     "tm_defocus_forward", "tm_profile_enable", "tm_profile_query",
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
+    "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -128,6 +129,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_tune_time.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
     lib.tm_set_variant.argtypes = [vp, i32, i32, i32]
     lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
+    i64 = ctypes.c_int64
+    lib.tm_pre_energy.argtypes = [vp, vp, i32, i64, i32, i32, vp, vp]
+    lib.tm_pre_fiber_mask.argtypes = [vp, vp, i32, dp, vp, ctypes.POINTER(i32), vp]
+    lib.tm_pre_gather.argtypes = [vp, vp, i32, i64, i32, i32, vp, i32, vp, i32, vp]
     _lib = lib
     return lib
 
@@ -310,6 +315,52 @@ def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, 
                                          ctypes.byref(g), _stream(tm_est.device))
     ctx.check(rc, "tm_phase_offset_correct")
     return g.value
+
+
+TM_U16 = 2
+
+
+def _stack_dtype(stack) -> int:
+    if stack.dim() != 3:
+        raise TMError("stack must be [n_img, H, W]")
+    if stack.dtype in (torch.int16, torch.uint16):  # camera counts (int16 tensors carry the uint16 bits)
+        return TM_U16
+    if stack.dtype == torch.float32:
+        return TM_F32
+    raise TMError(f"stack dtype {stack.dtype}: uint16 camera counts or float32")
+
+
+def tm_pre_energy(ctx: Context, stack):
+    """Summed intensity of every half-sampled pixel, [(H/2)*(W/2)] float64."""
+    n, H, W = stack.shape
+    out = torch.empty(((H // 2) * (W // 2),), dtype=torch.float64, device=stack.device)
+    rc = ctx.lib.tm_pre_energy(ctx.h, _ptr(stack), _stack_dtype(stack), int(n), int(H), int(W), _ptr(out),
+                               _stream(stack.device))
+    ctx.check(rc, "tm_pre_energy")
+    return out
+
+
+def tm_pre_fiber_mask(ctx: Context, energy, frac=0.999):
+    """Ascending raster indices of the brightest-first pixel set holding frac of the total, int32 [P]."""
+    npix = energy.numel()
+    pix = torch.empty((npix,), dtype=torch.int32, device=energy.device)
+    P = ctypes.c_int32(0)
+    rc = ctx.lib.tm_pre_fiber_mask(ctx.h, _ptr(energy), int(npix), float(frac), _ptr(pix), ctypes.byref(P),
+                                   _stream(energy.device))
+    ctx.check(rc, "tm_pre_fiber_mask")
+    return pix[:P.value].clone()
+
+
+def tm_pre_gather(ctx: Context, stack, pix, bf16=False):
+    """Per-pixel rows [P, n_img]: out[p][i] = stack[i][2y][2x] for pix[p] = y*(W/2) + x."""
+    n, H, W = stack.shape
+    P = pix.numel()
+    out = torch.empty((P, n), dtype=torch.bfloat16 if bf16 else torch.float32, device=stack.device)
+    rc = ctx.lib.tm_pre_gather(ctx.h, _ptr(stack), _stack_dtype(stack), int(n), int(H), int(W),
+                               _ptr(pix) if P else None, int(P), _ptr(out) if P else None,
+                               TM_BF16 if bf16 else TM_F32, _stream(stack.device))
+    ctx.check(rc, "tm_pre_gather")
+    return out
 
 
 def tm_defocus_forward(ctx: Context, pix, tm_rows, theta, optics, phi, nf1, nf2):

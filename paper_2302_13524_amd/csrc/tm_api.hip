@@ -20,6 +20,7 @@
 #include "lbfgs.hpp"
 #include "mlp.hpp"
 #include "phase.hpp"
+#include "pre.hpp"
 #include "row_kernels.hpp"
 
 struct tm_ctx {
@@ -101,7 +102,8 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
-  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE,
+  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_PRE_PART,
+  WS_PRE_COUNT,
   WS_PH_BASE = 100
 };
 
@@ -1054,5 +1056,71 @@ extern "C" int tm_tune_time(tm_ctx* c, int32_t n1, int32_t n2, int32_t K, int32_
   hipEventDestroy(e1);
   if (e) return hipfail(c, e, "tuning launch");
   *us = 1e3 * ms / reps;
+  return TM_OK;
+}
+
+// ------------------------------------------------------------ preprocessing
+static int pre_check(tm_ctx* c, const void* stack, int32_t dtype, int64_t n_img, int32_t H, int32_t W) {
+  if (!stack) return fail(c, TM_EINVAL, "stack is NULL");
+  if (dtype != TM_F32 && dtype != TM_U16) return fail(c, TM_EINVAL, "stack dtype %d (TM_F32 or TM_U16)", dtype);
+  if (n_img < 1) return fail(c, TM_EINVAL, "n_img=%lld must be >= 1", (long long)n_img);
+  if (H < 2 || W < 2 || (H & 1) || (W & 1)) return fail(c, TM_EINVAL, "image %dx%d: even sizes >= 2", H, W);
+  if ((int64_t)(H / 2) * (W / 2) > (int64_t)1 << 30) return fail(c, TM_EINVAL, "image too large");
+  return TM_OK;
+}
+
+extern "C" int tm_pre_energy(tm_ctx* c, const void* stack, int32_t stack_dtype, int64_t n_img, int32_t H, int32_t W,
+                             double* energy, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = pre_check(c, stack, stack_dtype, n_img, H, W);
+  if (r) return r;
+  if (!energy) return fail(c, TM_EINVAL, "energy is NULL");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int npix = (H / 2) * (W / 2);
+  const int nch = tmk::pre_energy_chunks(n_img, npix);
+  double* part = (double*)ws_get(c, WS_PRE_PART, (size_t)nch * npix * sizeof(double));
+  if (!part) return fail(c, TM_ENOMEM, "workspace");
+  int e = tmk::launch_pre_energy(stack, stack_dtype == TM_U16, n_img, H, W, part, nch, energy, stream);
+  if (e) return hipfail(c, e, "energy");
+  return TM_OK;
+}
+
+extern "C" int tm_pre_fiber_mask(tm_ctx* c, const double* energy, int32_t npix, double frac, int32_t* pix,
+                                 int32_t* P_out, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (!energy || !pix || !P_out) return fail(c, TM_EINVAL, "null pointer argument");
+  if (npix < 1 || npix > tmk::PRE_MASK_MAX) return fail(c, TM_EINVAL, "npix=%d outside 1..%d", npix, tmk::PRE_MASK_MAX);
+  if (!(frac > 0.0 && frac <= 1.0)) return fail(c, TM_EINVAL, "frac must be in (0, 1]");
+  HIPCHK(c, hipSetDevice(c->device));
+  int32_t* cnt = (int32_t*)ws_get(c, WS_PRE_COUNT, sizeof(int32_t));
+  if (!cnt) return fail(c, TM_ENOMEM, "workspace");
+  int e = tmk::launch_pre_mask(energy, npix, frac, pix, cnt, stream);
+  if (e) return hipfail(c, e, "fiber mask");
+  int32_t h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+  *P_out = h;
+  return TM_OK;
+}
+
+extern "C" int tm_pre_gather(tm_ctx* c, const void* stack, int32_t stack_dtype, int64_t n_img, int32_t H, int32_t W,
+                             const int32_t* pix, int32_t P, void* out, int32_t out_dtype, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = pre_check(c, stack, stack_dtype, n_img, H, W);
+  if (r) return r;
+  if (P < 0) return fail(c, TM_EINVAL, "P=%d < 0", P);
+  if (out_dtype != TM_F32 && out_dtype != TM_BF16) return fail(c, TM_EINVAL, "out dtype %d (TM_F32 or TM_BF16)", out_dtype);
+  if (P == 0) return TM_OK;
+  if (!pix || !out) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  // the pixel indices address the half-sampled grid: check them on the host
+  const int npix = (H / 2) * (W / 2);
+  std::vector<int32_t> hp(P);
+  if (hipMemcpy(hp.data(), pix, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, TM_EHIP, "reading pix");
+  for (int i = 0; i < P; ++i)
+    if (hp[i] < 0 || hp[i] >= npix) return fail(c, TM_EINVAL, "pix[%d]=%d outside the half-sampled grid", i, hp[i]);
+  int e = tmk::launch_pre_gather(stack, stack_dtype == TM_U16, n_img, H, W, pix, P, out, out_dtype == TM_BF16, stream);
+  if (e) return hipfail(c, e, "gather");
   return TM_OK;
 }

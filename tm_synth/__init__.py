@@ -100,3 +100,20 @@ def to_bf16_bits(x: np.ndarray) -> np.ndarray:
 
 def from_bf16_bits(b: np.ndarray) -> np.ndarray:
     return (np.asarray(b, dtype=np.uint32) << 16).view(np.float32)
+
+
+def fiber_disk(H: int, W: int, radius: float) -> np.ndarray:
+    """Boolean [H, W] disk centred on the image (the fiber core seen by the camera)."""
+    y, x = np.mgrid[0:H, 0:W]
+    return (y - (H - 1) / 2) ** 2 + (x - (W - 1) / 2) ** 2 <= radius ** 2
+
+
+def camera_stack(n_img: int, H: int, W: int, radius: float, g: np.random.Generator, peak: float = 4000.0,
+                 background: float = 0.05) -> np.ndarray:
+    """uint16 [n_img, H, W] camera counts: exponential (speckle-like) intensities
+    of mean peak/4 inside the fiber disk, Poisson background of mean
+    `background` outside."""
+    inside = fiber_disk(H, W, radius)
+    speckle = np.minimum(g.exponential(peak / 4, size=(n_img, H, W)), 65535.0)
+    bg = g.poisson(background, size=(n_img, H, W)).astype(np.float64)
+    return np.where(inside[None], np.floor(speckle), bg).astype(np.uint16)
