@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 12-TM batch")
+    ap.add_argument("--no-preprocess", action="store_true", help="skip the camera-stack preprocessing")
     ap.add_argument("--train-rows", type=int, default=51200)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
@@ -406,6 +407,8 @@ def main():
         out["learned"] = learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, P)
     if not args.no_batch and not args.small:
         out["batch"] = batch_variant(ctx, args)
+    if not args.no_preprocess and not args.small:
+        out["preprocess"] = preprocess_variant(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P)
     ctx.close()
@@ -446,6 +449,59 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
             "plain_retrieval_ms": round(ret_ms, 3), "start_fidelity": round(f_start, 5),
             "rows_redone_from_fallback": redone, "final_mean_fidelity": round(float(fidelity(t).mean().item()), 6),
             "train_rows": args.train_rows, "train_s": round(train_s, 2), "train_loss": [round(h, 5) for h in hist]}
+
+
+def preprocess_variant(ctx, args):
+    """Preprocessing at the paper's camera layout: K N = 32768 images of
+    128 x 128 uint16 counts (speckle inside a fiber disk of radius 54, dim
+    background), half-sampled energy, 99.9 % fiber mask, per-pixel rows.
+    The stack is synthesised on the GPU (seeded); each call is event-timed."""
+    import torch
+
+    import paper_2302_13524_amd as tm
+
+    dev = torch.device("cuda:0")
+    n_img, H, W, radius = 4 * 8192, 128, 128, 54.0
+    g = torch.Generator(device=dev)
+    g.manual_seed(77)
+    y = torch.arange(H, device=dev, dtype=torch.float32)[:, None] - (H - 1) / 2
+    x = torch.arange(W, device=dev, dtype=torch.float32)[None, :] - (W - 1) / 2
+    inside = (y * y + x * x) <= radius * radius
+    stack = torch.empty((n_img, H, W), dtype=torch.int16, device=dev)
+    for i0 in range(0, n_img, 4096):  # in slabs, to bound the float temporaries
+        u = torch.rand((min(4096, n_img - i0), H, W), generator=g, device=dev)
+        v = torch.where(inside, torch.floor(-1000.0 * torch.log1p(-u)).clamp_(max=65535.0),
+                        torch.floor(u * 1.05))  # background: 0, or 1 with probability 0.05
+        stack[i0:i0 + v.shape[0]] = v.to(torch.int32).to(torch.int16)  # uint16 bits
+        del u, v
+    torch.cuda.synchronize()
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / reps
+
+    E, e_ms = timed(lambda: tm.tm_pre_energy(ctx, stack))
+    pix, m_ms = timed(lambda: tm.tm_pre_fiber_mask(ctx, E, 0.999))
+    rows, g_ms = timed(lambda: tm.tm_pre_gather(ctx, stack, pix))
+    P = int(pix.numel())
+    kept = n_img * (H // 2) * (W // 2) * 2  # bytes of the values used
+    e_bytes, g_bytes = kept, P * n_img * (2 + 4)
+    out = {"n_img": n_img, "image": [H, W], "P": P, "energy_ms": round(e_ms, 4), "mask_ms": round(m_ms, 4),
+           "gather_ms": round(g_ms, 4), "total_ms": round(e_ms + m_ms + g_ms, 4),
+           "energy_GBps": round(e_bytes / (e_ms * 1e-3) / 1e9, 1),
+           "gather_GBps": round(g_bytes / (g_ms * 1e-3) / 1e9, 1),
+           "energy_frac_hbm": round(e_bytes / (e_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "gather_frac_hbm": round(g_bytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "alg_bytes": {"energy": e_bytes, "gather": g_bytes}}
+    del stack, rows
+    return out
 
 
 def batch_variant(ctx, args):

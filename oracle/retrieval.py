@@ -61,6 +61,33 @@ def intensity_grad(op, I: np.ndarray, t: np.ndarray):
     return np.sum(r.reshape(r.shape[0], -1) ** 2, axis=1), g, y
 
 
+def amplitude_grad(op, I: np.ndarray, t: np.ndarray):
+    """Amplitude cost f_a = sum (sqrt(I) - |A t|)^2 (the Poisson-noise cost of
+    the Discussion) and its packed gradient -2 A^H((sqrt(I) - |y|) y/|y|),
+    with y/|y| := 1 at y = 0. Returns (f_a, grad, y)."""
+    y = op.forward(t)
+    r = np.sqrt(I) - np.abs(y)
+    g = -2.0 * op.adjoint(r * phase_of(y))
+    return np.sum(r.reshape(r.shape[0], -1) ** 2, axis=1), g, y
+
+
+AMP_STEPS = 2.0 ** np.arange(-3, 5)  # trial steps of the amplitude line search: 1/8 .. 16
+
+
+def amplitude_step(I: np.ndarray, y: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """Line search of the amplitude L-BFGS along d with y = A t, z = A d:
+    f_a(t + a d) = sum (sqrt(I) - |y + a z|)^2 at the trial steps AMP_STEPS;
+    the smallest value wins (ties to the smaller step) if it is below
+    f_a(t), else the step is 0. Returns a per row."""
+    amp = np.sqrt(I)
+    ax = tuple(range(1, I.ndim))
+    f0 = np.sum((amp - np.abs(y)) ** 2, axis=ax)
+    fs = np.stack([np.sum((amp - np.abs(y + a * z)) ** 2, axis=ax) for a in AMP_STEPS], axis=1)
+    j = np.argmin(fs, axis=1)  # first minimum = smaller step on ties
+    best = fs[np.arange(fs.shape[0]), j]
+    return np.where(best < f0, AMP_STEPS[j], 0.0)
+
+
 def acceptance_residual(op, I: np.ndarray, t: np.ndarray) -> np.ndarray:
     """rho_p = ||I_p - |A t_p|^2||^2 / ||I_p||^2, a ground-truth-free
     per-row error flag."""
@@ -193,10 +220,13 @@ def exact_step(c1: float, c2: float, c3: float, c4: float) -> float:
 
 
 def lbfgs_core(eval_fg, line_min, t0: np.ndarray, iters: int, m: int = 5,
-               gamma: float | None = None, callback=None):
+               gamma: float | None = None, callback=None, h0: float = 1.0,
+               reset_on_zero: bool = False):
     """Generic per-row L-BFGS loop of Algorithm 1: `eval_fg(t) -> (f, g, aux)`
     gives the error and packed gradient, `line_min(t, d, aux) -> alpha` the
-    step along d. Returns (t, per-iteration f history [iters+1, P])."""
+    step along d. With an empty history the direction is -h0 g (also after a
+    non-descent reset); reset_on_zero drops a row's history when its step is
+    0. Returns (t, per-iteration f history [iters+1, P])."""
     t = np.array(t0, dtype=np.complex128)
     P = t.shape[0]
     S = [[] for _ in range(P)]
@@ -204,14 +234,17 @@ def lbfgs_core(eval_fg, line_min, t0: np.ndarray, iters: int, m: int = 5,
     f, g, aux = eval_fg(t)
     hist = [f.copy()]
     for _ in range(iters):
-        d = two_loop(g, S, Y, gamma)
+        d = two_loop(g, S, Y, gamma, h0)
         slope = rdot(g, d)
         bad = ~(slope < 0)
         if np.any(bad):
             for p in np.nonzero(bad)[0]:
                 S[p], Y[p] = [], []
-            d[bad] = -g[bad]
+            d[bad] = -h0 * g[bad]
         alpha = line_min(t, d, aux)
+        if reset_on_zero:
+            for p in np.nonzero(alpha == 0)[0]:
+                S[p], Y[p] = [], []
         t_new = t + alpha[:, None] * d
         f_new, g_new, aux_new = eval_fg(t_new)
         s_vec = t_new - t
@@ -251,10 +284,10 @@ def lbfgs(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5,
     return lbfgs_core(eval_fg, line_min, t0, iters, m, gamma, callback)
 
 
-def two_loop(g: np.ndarray, S, Y, gamma: float | None) -> np.ndarray:
+def two_loop(g: np.ndarray, S, Y, gamma: float | None, h0: float = 1.0) -> np.ndarray:
     """L-BFGS two-loop recursion per row (Nocedal & Wright Alg. 7.4):
     returns d = -H g with the inverse-Hessian approximation built from the
-    stored pairs, oldest first in S[p], Y[p]."""
+    stored pairs, oldest first in S[p], Y[p]; H = h0 I with no pairs."""
     d = np.empty_like(g)
     for p in range(g.shape[0]):
         q = g[p].copy()
@@ -268,9 +301,30 @@ def two_loop(g: np.ndarray, S, Y, gamma: float | None) -> np.ndarray:
             q = q * gamma
         elif S[p]:
             q = q * (np.real(np.vdot(S[p][-1], Y[p][-1])) / np.real(np.vdot(Y[p][-1], Y[p][-1])))
+        else:
+            q = q * h0
         for (s_, y_), ai in zip(zip(S[p], Y[p]), reversed(a)):
             rho = 1.0 / np.real(np.vdot(y_, s_))
             b = rho * np.real(np.vdot(y_, q))
             q = q + (ai - b) * s_
         d[p] = -q
     return d
+
+
+def lbfgs_amplitude(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5, callback=None):
+    """L-BFGS on the amplitude cost (the Poisson-noise variant the Discussion
+    names, same two-loop recursion as Algorithm 1): gradient amplitude_grad,
+    line search amplitude_step over the trial steps, and with no stored pairs
+    the direction -g/(2KN), along which the unit step is one error-reduction
+    step (the amplitude gradient is 2KN (t - ER(t))). A row whose line search
+    finds no decrease drops its history, so its next step is again of that
+    kind, which never increases f_a. Returns (t, f_a history)."""
+
+    def eval_fg(t):
+        return amplitude_grad(op, I, t)
+
+    def line_min(t, d, y):
+        return amplitude_step(I, y, op.forward(d))
+
+    return lbfgs_core(eval_fg, line_min, t0, iters, m, None, callback, h0=1.0 / (2.0 * op.K * op.N),
+                      reset_on_zero=True)

@@ -9,8 +9,8 @@ namespace tmk {
 constexpr int PRE_MASK_MAX = 8192;  // half-sampled pixels the one-workgroup mask kernel sorts in LDS
 
 // partial[c][q] = sum over the images of chunk c of stack[i][2y][2x], q = y (W/2) + x (FP64);
-// nchunks = pre_energy_chunks(n_img, npix). u16: 1 for uint16 pixels, 0 for float.
-int pre_energy_chunks(int64_t n_img, int npix);
+// nchunks = pre_energy_chunks(...). u16: 1 for uint16 pixels, 0 for float.
+int pre_energy_chunks(const void* stack, int u16, int64_t n_img, int H, int W);
 int launch_pre_energy(const void* stack, int u16, int64_t n_img, int H, int W, double* partial, int nchunks,
                       double* energy, void* stream);
 // Brightest-first mask reaching frac of the total; pix[0..count) ascending, count into *count_dev.

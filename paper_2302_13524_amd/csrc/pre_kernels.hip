@@ -31,7 +31,8 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// grid (ceil(npix / 256), nchunks): thread = kept pixel, loop over the chunk's images
+// Scalar form: grid (ceil(npix / 256), nchunks), thread = kept pixel, loop
+// over the chunk's images.
 __global__ void __launch_bounds__(256) k_energy_part(const void* stack, int u16, int64_t n_img, int H, int W,
                                                      int64_t chunk, double* partial) {
   const int npix = (H / 2) * (W / 2);
@@ -42,25 +43,53 @@ __global__ void __launch_bounds__(256) k_energy_part(const void* stack, int u16,
   const int64_t i0 = (int64_t)blockIdx.y * chunk;
   const int64_t i1 = (i0 + chunk < n_img) ? i0 + chunk : n_img;
   double s = 0.0;
-  int64_t i = i0;
-  for (; i + 4 <= i1; i += 4) {
-    float v0 = pix_val(stack, u16, (size_t)i * H * W + off);
-    float v1 = pix_val(stack, u16, (size_t)(i + 1) * H * W + off);
-    float v2 = pix_val(stack, u16, (size_t)(i + 2) * H * W + off);
-    float v3 = pix_val(stack, u16, (size_t)(i + 3) * H * W + off);
-    s += (double)v0;
-    s += (double)v1;
-    s += (double)v2;
-    s += (double)v3;
-  }
-  for (; i < i1; ++i) s += (double)pix_val(stack, u16, (size_t)i * H * W + off);
+  for (int64_t i = i0; i < i1; ++i) s += (double)pix_val(stack, u16, (size_t)i * H * W + off);
   partial[(size_t)blockIdx.y * npix + q] = s;
+}
+
+// Vector form (16-byte rows segments): a thread owns one 16-byte segment of an
+// even row, i.e. KP kept pixels (4 for uint16, 2 for float), and loops over
+// the chunk's images with one 16-byte load each. grid (ceil(nseg / 256),
+// nchunks), nseg = (H/2) * (W * sizeof / 16).
+template <bool U16>
+__global__ void __launch_bounds__(256) k_energy_vec(const void* stack, int64_t n_img, int H, int W, int64_t chunk,
+                                                    double* partial) {
+  constexpr int EPS = U16 ? 8 : 4;  // elements per segment
+  constexpr int KP = EPS / 2;       // kept pixels per segment
+  const int segs = W / EPS, npix = (H / 2) * (W / 2);
+  const int sgi = blockIdx.x * 256 + threadIdx.x;
+  if (sgi >= (H / 2) * segs) return;
+  const int y = sgi / segs, sx = sgi - y * segs;
+  const size_t off = (size_t)(2 * y) * W + (size_t)sx * EPS;
+  const size_t plane = (size_t)H * W;
+  const int64_t i0 = (int64_t)blockIdx.y * chunk;
+  const int64_t i1 = (i0 + chunk < n_img) ? i0 + chunk : n_img;
+  double acc[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) acc[k] = 0.0;
+#pragma unroll 4
+  for (int64_t i = i0; i < i1; ++i) {
+    const uint4 v = *(const uint4*)((const char*)stack + (i * plane + off) * (U16 ? 2 : 4));
+    if (U16) {
+      acc[0] += (double)(v.x & 0xffffu);
+      acc[1] += (double)(v.y & 0xffffu);
+      acc[2] += (double)(v.z & 0xffffu);
+      acc[3] += (double)(v.w & 0xffffu);
+    } else {
+      acc[0] += (double)__uint_as_float(v.x);
+      acc[1] += (double)__uint_as_float(v.z);
+    }
+  }
+  const int q = y * (W / 2) + sx * KP;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) partial[(size_t)blockIdx.y * npix + q + k] = acc[k];
 }
 
 __global__ void __launch_bounds__(256) k_energy_final(const double* partial, int nchunks, int npix, double* energy) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= npix) return;
   double s = 0.0;
+#pragma unroll 8
   for (int c = 0; c < nchunks; ++c) s += partial[(size_t)c * npix + q];
   energy[q] = s;
 }
@@ -151,9 +180,10 @@ __global__ void __launch_bounds__(MWG) k_mask(const double* energy, int npix, do
   if (threadIdx.x == 0) *count_dev = count;
 }
 
-constexpr int GT_I = 64, GT_P = 256;
+constexpr int GT_I = 32, GT_P = 256;
 
-// grid (ceil(P / 256), ceil(n_img / 64)), 256 threads
+// grid (ceil(P / 256), ceil(n_img / 32)), 256 threads; the LDS tile (32 images
+// x 256 pixels, 33 KiB) leaves room for four workgroups per CU
 __global__ void __launch_bounds__(256) k_gather(const void* stack, int u16, int64_t n_img, int H, int W,
                                                const int32_t* pix, int P, void* out, int out_bf16) {
   __shared__ float tile[GT_I][GT_P + 1];
@@ -166,33 +196,61 @@ __global__ void __launch_bounds__(256) k_gather(const void* stack, int u16, int6
     const int y = q / (W / 2), x = q - y * (W / 2);
     off = (size_t)(2 * y) * W + 2 * x;
   }
+  const size_t plane = (size_t)H * W;
+#pragma unroll 8
   for (int r = 0; r < GT_I; ++r) {
     const int64_t i = i0 + r;
-    tile[r][threadIdx.x] = (p < P && i < n_img) ? pix_val(stack, u16, (size_t)i * H * W + off) : 0.f;
+    tile[r][threadIdx.x] = (p < P && i < n_img) ? pix_val(stack, u16, (size_t)i * plane + off) : 0.f;
   }
   __syncthreads();
-  // 4 pixels x 64 consecutive images per pass
-  const int r = threadIdx.x & (GT_I - 1);
-  for (int pp = threadIdx.x >> 6; pp < GT_P; pp += 256 / GT_I) {
+  // 4 consecutive images per thread, 8 threads per pixel, 32 pixels per pass
+  const int r4 = (threadIdx.x & 7) * 4;
+  for (int pp = threadIdx.x >> 3; pp < GT_P; pp += 32) {
     const int pg = p0 + pp;
-    const int64_t i = i0 + r;
-    if (pg < P && i < n_img) {
-      const float v = tile[r][pp];
-      const size_t o = (size_t)pg * n_img + i;
-      if (out_bf16) ((uint16_t*)out)[o] = to_bf16(v);
-      else ((float*)out)[o] = v;
+    if (pg >= P) break;
+    const int64_t i = i0 + r4;
+    const size_t o = (size_t)pg * n_img + i;
+    const float v0 = tile[r4][pp], v1 = tile[r4 + 1][pp], v2 = tile[r4 + 2][pp], v3 = tile[r4 + 3][pp];
+    if (i + 3 < n_img && (o & 3) == 0 && ((uintptr_t)out % 16) == 0) {
+      if (out_bf16) {
+        uint2 w;
+        w.x = (uint32_t)to_bf16(v0) | ((uint32_t)to_bf16(v1) << 16);
+        w.y = (uint32_t)to_bf16(v2) | ((uint32_t)to_bf16(v3) << 16);
+        *(uint2*)((uint16_t*)out + o) = w;
+      } else {
+        *(float4*)((float*)out + o) = make_float4(v0, v1, v2, v3);
+      }
+    } else {
+      const float v[4] = {v0, v1, v2, v3};
+      for (int k = 0; k < 4; ++k) {
+        if (i + k < n_img) {
+          if (out_bf16) ((uint16_t*)out)[o + k] = to_bf16(v[k]);
+          else ((float*)out)[o + k] = v[k];
+        }
+      }
     }
   }
 }
 
 }  // namespace
 
-int pre_energy_chunks(int64_t n_img, int npix) {
-  // enough workgroups to fill the chip, at least 64 images per chunk
-  const int blocks_x = (npix + 255) / 256;
-  int64_t want = (2048 + blocks_x - 1) / blocks_x;
-  int64_t maxc = (n_img + 63) / 64;
-  int64_t c = want < maxc ? want : maxc;
+// The vector form needs whole 16-byte segments per row and a 16-byte aligned stack.
+static bool energy_vec(const void* stack, int u16, int W) {
+  return (W % (u16 ? 8 : 4)) == 0 && ((uintptr_t)stack % 16) == 0;
+}
+
+static int energy_threads(const void* stack, int u16, int H, int W) {
+  return energy_vec(stack, u16, W) ? (H / 2) * (W / (u16 ? 8 : 4)) : (H / 2) * (W / 2);
+}
+
+int pre_energy_chunks(const void* stack, int u16, int64_t n_img, int H, int W) {
+  // about 1024 workgroups, at least 32 images per chunk, at most 128 chunks (the
+  // final pass adds the chunks of each pixel in order)
+  const int blocks_x = (energy_threads(stack, u16, H, W) + 255) / 256;
+  int64_t c = (1024 + blocks_x - 1) / blocks_x;
+  const int64_t maxc = (n_img + 31) / 32;
+  if (c > maxc) c = maxc;
+  if (c > 128) c = 128;
   return (int)(c < 1 ? 1 : c);
 }
 
@@ -201,7 +259,10 @@ int launch_pre_energy(const void* stack, int u16, int64_t n_img, int H, int W, d
   const int npix = (H / 2) * (W / 2);
   const int64_t chunk = (n_img + nchunks - 1) / nchunks;
   hipStream_t s = (hipStream_t)stream;
-  k_energy_part<<<dim3((npix + 255) / 256, nchunks), 256, 0, s>>>(stack, u16, n_img, H, W, chunk, partial);
+  dim3 g((energy_threads(stack, u16, H, W) + 255) / 256, nchunks);
+  if (!energy_vec(stack, u16, W)) k_energy_part<<<g, 256, 0, s>>>(stack, u16, n_img, H, W, chunk, partial);
+  else if (u16) k_energy_vec<true><<<g, 256, 0, s>>>(stack, n_img, H, W, chunk, partial);
+  else k_energy_vec<false><<<g, 256, 0, s>>>(stack, n_img, H, W, chunk, partial);
   k_energy_final<<<(npix + 255) / 256, 256, 0, s>>>(partial, nchunks, npix, energy);
   return (int)hipGetLastError();
 }

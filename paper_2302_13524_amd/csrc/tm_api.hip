@@ -1077,7 +1077,7 @@ extern "C" int tm_pre_energy(tm_ctx* c, const void* stack, int32_t stack_dtype, 
   if (!energy) return fail(c, TM_EINVAL, "energy is NULL");
   HIPCHK(c, hipSetDevice(c->device));
   const int npix = (H / 2) * (W / 2);
-  const int nch = tmk::pre_energy_chunks(n_img, npix);
+  const int nch = tmk::pre_energy_chunks(stack, stack_dtype == TM_U16, n_img, H, W);
   double* part = (double*)ws_get(c, WS_PRE_PART, (size_t)nch * npix * sizeof(double));
   if (!part) return fail(c, TM_ENOMEM, "workspace");
   int e = tmk::launch_pre_energy(stack, stack_dtype == TM_U16, n_img, H, W, part, nch, energy, stream);

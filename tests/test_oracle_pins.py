@@ -348,3 +348,59 @@ def test_shifted_momentum_power_iteration():
     b = rt.spectral_start(d, I, v0, 12, momentum=c, lower=0.0)
     assert 1 - overlap(b) < 0.5 * (1 - overlap(a))
     assert overlap(rt.spectral_start(d, I, v0, 300, momentum=c, lower=0.0)) > 1 - 1e-10
+
+
+def test_amplitude_gradient_finite_differences_and_er_identity():
+    # the packed gradient of f_a = sum (sqrt(I) - |A t|)^2 against central
+    # differences, and the identity grad f_a = 2 K N (t - ER(t)) that follows
+    # from A^H A = K N I
+    masks, t, g = small_problem(4, 4, K=3, P=2, seed=31)
+    op = ops.FFTOp(masks, 4, 4)
+    I = ops.intensities(op, t) * 1.3
+    x = t + 0.3 * (g.standard_normal(t.shape) + 1j * g.standard_normal(t.shape))
+    f, grad, _ = rt.amplitude_grad(op, I, x)
+    for _ in range(3):
+        v = g.standard_normal(t.shape) + 1j * g.standard_normal(t.shape)
+        h = 1e-6
+        fp, _, _ = rt.amplitude_grad(op, I, x + h * v)
+        fm, _, _ = rt.amplitude_grad(op, I, x - h * v)
+        fd = (fp - fm) / (2 * h)
+        assert np.max(np.abs(fd - rt.rdot(grad, v))) <= 1e-6 * np.max(np.abs(fd))
+    ident = 2 * op.K * op.N * (x - rt.er_step(op, I, x))
+    assert np.max(np.abs(grad - ident)) <= 1e-10 * np.max(np.abs(grad))
+
+
+def test_amplitude_line_search_picks_the_best_decreasing_trial():
+    masks, t, g = small_problem(4, 4, K=4, P=3, seed=32)
+    op = ops.FFTOp(masks, 4, 4)
+    I = ops.intensities(op, t)
+    x = t + 0.5 * (g.standard_normal(t.shape) + 1j * g.standard_normal(t.shape))
+    f0, grad, y = rt.amplitude_grad(op, I, x)
+    for d in (-grad / (2 * op.K * op.N), grad):  # a descent direction and an ascent one
+        a = rt.amplitude_step(I, y, op.forward(d))
+        fa = np.array([rt.amplitude_grad(op, I, x + s * d)[0] for s in rt.AMP_STEPS])  # [steps, P]
+        for p in range(3):
+            if a[p] == 0:
+                assert np.all(fa[:, p] >= f0[p])
+            else:
+                fb = rt.amplitude_grad(op, I, x[p:p + 1] + a[p] * d[p:p + 1])[0][0]
+                assert fb < f0[p] and fb <= fa[:, p].min() + 1e-12 * f0[p]
+
+
+def test_amplitude_lbfgs_monotone_and_recovers():
+    n1 = n2 = 16
+    N, K, P = n1 * n2, 4, 16
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(5, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(5, 1))
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, T)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(5, 3))
+    t0 = rt.spectral_start(op, I, v0, 40, momentum=0.98)
+    t, hist = rt.lbfgs_amplitude(op, I, t0, 30)
+    assert np.all(np.diff(hist, axis=0) <= 1e-12 * hist[0])
+    assert rt.fidelity(t, T).min() > 0.999
+    # its first step from an empty history is an error-reduction step when the unit trial wins
+    t1, _ = rt.lbfgs_amplitude(op, I, t0, 1)
+    f0, g0, y0 = rt.amplitude_grad(op, I, t0)
+    a = rt.amplitude_step(I, y0, op.forward(-g0 / (2 * K * N)))
+    assert np.allclose(t1, t0 + a[:, None] * (-g0 / (2 * K * N)))
