@@ -383,7 +383,7 @@ def test_amplitude_line_search_picks_the_best_decreasing_trial():
             if a[p] == 0:
                 assert np.all(fa[:, p] >= f0[p])
             else:
-                fb = rt.amplitude_grad(op, I, x[p:p + 1] + a[p] * d[p:p + 1])[0][0]
+                fb = rt.amplitude_grad(op, I[p:p + 1], x[p:p + 1] + a[p] * d[p:p + 1])[0][0]
                 assert fb < f0[p] and fb <= fa[:, p].min() + 1e-12 * f0[p]
 
 
