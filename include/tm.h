@@ -101,6 +101,13 @@ int tm_adjoint(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const tm_c32 *y,
 int tm_gradient(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, int I_dtype,
                 const tm_c32 *t, tm_c32 *grad, float *f, void *stream);
 
+/* Packed gradient of the amplitude cost f_a(t) = || sqrt(I) - |A t| ||^2
+ * (the Poisson-noise cost of the Discussion):
+ *   grad = -2 A^H ( (sqrt(I) - |A t|) (A t)/|A t| ), (A t)/|A t| := 1 where A t = 0,
+ *   f [P] float (may be NULL): f_a per row. Same layouts as tm_gradient. */
+int tm_amp_gradient(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, int I_dtype,
+                    const tm_c32 *t, tm_c32 *grad, float *f, void *stream);
+
 /* FP64 acceptance residual per row:
  *   rho_p = ||I_p - |A t_p|^2||^2 / ||I_p||^2
  * evaluated with FP64 FFTs and FP64 sums from the FP32 inputs.
@@ -110,7 +117,12 @@ int tm_residual_f64(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, 
 
 /* ---- retrieval (Sec. 2.2, Alg. 1) --------------------------------------- */
 
-enum { TM_METHOD_ER = 0, TM_METHOD_LBFGS = 1 };
+/* TM_METHOD_LBFGS_AMP: L-BFGS on the amplitude cost sum (sqrt(I) - |A t|)^2,
+ * the Poisson-noise form the Discussion names: gradient
+ * -2 A^H((sqrt(I) - |y|) y/|y|), line search over the trial steps 1/8 .. 16
+ * (the smallest cost wins if below the cost at t, else no step and the row's
+ * history is dropped), direction -g/(2KN) with no history. */
+enum { TM_METHOD_ER = 0, TM_METHOD_LBFGS = 1, TM_METHOD_LBFGS_AMP = 2 };
 enum {
   TM_START_GIVEN = 0,     /* use t as passed in                                  */
   TM_START_BACKPROP = 1,  /* t = A^H sqrt(I) / (K N)          (Eq. backpropagation) */
@@ -118,7 +130,7 @@ enum {
 };
 
 typedef struct {
-  int32_t method;          /* TM_METHOD_ER (projection) or TM_METHOD_LBFGS (Alg. 1)     */
+  int32_t method;          /* TM_METHOD_ER (projection), TM_METHOD_LBFGS (Alg. 1) or _AMP */
   int32_t iters;           /* solver iterations (the paper's maxiter), >= 0              */
   int32_t lbfgs_m;         /* L-BFGS memory, 1..16 (default 5)                           */
   int32_t I_dtype;         /* TM_F32 or TM_BF16                                          */

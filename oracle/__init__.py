@@ -19,4 +19,5 @@ Modules:
   defocus    angular-spectrum defocus model and phase-offset solve (Sec. 2.3)
   mlp        learned-start network in FP64 (forward, backward, loss, Adam)
   preprocess half-sampling, fiber mask and per-pixel rows of the image stack
+  foci       conjugate-phase foci of the retrieved rows and their power ratio
 """

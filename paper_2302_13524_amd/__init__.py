@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtm.so")
 TM_OK, TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENOMEM = 0, -1, -2, -3, -4
 TM_F32, TM_BF16 = 0, 1
 TM_FIELD, TM_INTENSITY = 0, 1
-TM_METHOD_ER, TM_METHOD_LBFGS = 0, 1
+TM_METHOD_ER, TM_METHOD_LBFGS, TM_METHOD_LBFGS_AMP = 0, 1, 2
 TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL = 0, 1, 2
 
 EXPORTED = (
@@ -31,7 +31,7 @@ EXPORTED = (
     "tm_defocus_forward", "tm_profile_enable", "tm_profile_query",
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
-    "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather",
+    "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_forward.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.tm_adjoint.argtypes = [vp, tm_dims, vp, vp, vp, vp]
     lib.tm_gradient.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.tm_amp_gradient.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.tm_residual_f64.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.tm_retrieve.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), vp, vp]
     lib.tm_phase_offset_correct.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
@@ -230,6 +231,18 @@ def tm_gradient(ctx: Context, masks, I, t, n1, n2):
     return g, f
 
 
+def tm_amp_gradient(ctx: Context, masks, I, t, n1, n2):
+    """Packed gradient -2 A^H((sqrt(I) - |A t|)(A t)/|A t|) and the amplitude cost per row."""
+    K, N = masks.shape
+    P = t.shape[0]
+    g = torch.empty((P, N), dtype=torch.complex64, device=t.device)
+    f = torch.empty((P,), dtype=torch.float32, device=t.device)
+    rc = ctx.lib.tm_amp_gradient(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t), _ptr(g),
+                                 _ptr(f), _stream(t.device))
+    ctx.check(rc, "tm_amp_gradient")
+    return g, f
+
+
 def tm_residual_f64(ctx: Context, masks, I, t, n1, n2):
     """FP64 acceptance residual ||I - |A t|^2||^2 / ||I||^2 per row."""
     K, N = masks.shape
@@ -262,7 +275,7 @@ def decode_stats(raw: torch.Tensor) -> RowStats:
 def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", spectral_iters=30,
                   spectral_tau=3.0, spectral_momentum=0.98, er_momentum=0.0,
                   spectral_lower=None) -> tm_retrieve_opts:
-    m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS}[method]
+    m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS, "lbfgs_amp": TM_METHOD_LBFGS_AMP}[method]
     s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL}[start]
     return tm_retrieve_opts(m, int(iters), int(lbfgs_m), TM_BF16 if bf16 else TM_F32, s, int(spectral_iters),
                             float(spectral_tau), float(spectral_momentum), float(er_momentum),

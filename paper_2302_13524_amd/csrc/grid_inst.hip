@@ -33,6 +33,11 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
       break;
     case M_SPEC: row_kernel<PLg, M_SPEC, IT><<<grid, block, 0, s>>>(a); break;
     case M_LS: row_kernel<PLg, M_LS, IT><<<grid, block, 0, s>>>(a); break;
+    case M_AGRAD:
+      if (a.sums) row_kernel<PLg, M_AGRAD, IT, true><<<grid, block, 0, s>>>(a);
+      else row_kernel<PLg, M_AGRAD, IT, false><<<grid, block, 0, s>>>(a);
+      break;
+    case M_ALS: row_kernel<PLg, M_ALS, IT><<<grid, block, 0, s>>>(a); break;
     case M_BACKPROP: row_kernel<PLg, M_BACKPROP, IT><<<grid, block, 0, s>>>(a); break;
     case M_RES64: {
       using LD = Launch<PLd>;

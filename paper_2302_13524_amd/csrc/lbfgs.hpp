@@ -19,8 +19,9 @@ struct LbfgsBuffers {
   float* sums;  // [P][NSUM]
 };
 
-// Runs `iters` iterations starting from t (in place). Returns a hipError_t.
+// Runs `iters` iterations starting from t (in place), on the intensity cost
+// (amplitude = 0) or the amplitude cost (1). Returns a hipError_t.
 int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters, int m,
-              void* t, LbfgsBuffers& b, void* stream);
+              void* t, LbfgsBuffers& b, void* stream, int amplitude);
 
 }  // namespace tmk

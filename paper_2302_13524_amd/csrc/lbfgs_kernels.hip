@@ -5,6 +5,12 @@
 // d, descent check; [line sums] fused FFT kernel M_LS gives the six sums of
 // the quartic f(t + a d); [step] exact minimiser a > 0 in FP64, t += a d,
 // s = a d kept as the pending pair; [gradient] fused FFT kernel M_GRAD.
+//
+// The amplitude cost (the Poisson-noise variant of the Discussion) runs the
+// same loop with M_AGRAD for the gradient and M_ALS for the line: the cost at
+// the trial steps 1/8 .. 16, the smallest wins if it is below the cost at t,
+// otherwise the step is 0 and the row's history is dropped. With no history
+// the direction is -g / (2 K N), whose unit step is an error-reduction step.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -29,6 +35,7 @@ struct LbArgs {
   const float* sums;
   float2* t;
   int first;         // no pending pair
+  float h0;          // inverse-Hessian scale with no stored pairs
 };
 
 __device__ __forceinline__ void ts_add(float& s, float& c, float v) {
@@ -139,9 +146,12 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
       q[i].y -= af * y.y;
     }
   }
-  if (count > 0) {
-    int nw = (head - 1 + m) % m;
-    float gam = (float)(sy[nw] / yy[nw]);
+  {
+    float gam = a.h0;
+    if (count > 0) {
+      int nw = (head - 1 + m) % m;
+      gam = (float)(sy[nw] / yy[nw]);
+    }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       q[i].x *= gam;
@@ -185,7 +195,7 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
   for (int i = 0; i < EPT; ++i) {
     if (!act[i]) continue;
     int e = tid + i * LWG;
-    float2 v = reset ? a.g[rb + e] : q[i];
+    float2 v = reset ? make_float2(a.h0 * a.g[rb + e].x, a.h0 * a.g[rb + e].y) : q[i];
     a.d[rb + e] = make_float2(-v.x, -v.y);
   }
   if (tid == 0) {
@@ -279,6 +289,41 @@ __global__ void __launch_bounds__(LWG) k_step(LbArgs a) {
   }
 }
 
+// Amplitude line search: sums {f_a(t), f_a(t + a_j d)} with a_j = 2^(j-3).
+template <int EPT>
+__global__ void __launch_bounds__(LWG) k_step_amp(LbArgs a) {
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int N = a.N, m = a.m;
+  const size_t rb = (size_t)p * N;
+  double* sc = a.sc + (size_t)p * LB_SCALARS(m);
+  const float* s = a.sums + (size_t)p * NSUM;
+  int jb = 0;
+  for (int j = 1; j < AMP_TRIALS; ++j)
+    if (s[1 + j] < s[1 + jb]) jb = j;  // first minimum: the smaller step on ties
+  const double al = (s[1 + jb] < s[0]) ? ldexp(1.0, jb - 3) : 0.0;
+  int head = (int)sc[0];
+  const float af = (float)al;
+  float2* Sh = a.S + ((size_t)p * m + head) * N;
+  if (al > 0.0) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      int e = tid + i * LWG;
+      if (e >= N) continue;
+      float2 dv = a.d[rb + e];
+      float2 st = make_float2(af * dv.x, af * dv.y);
+      float2 tv = a.t[rb + e];
+      a.t[rb + e] = make_float2(tv.x + st.x, tv.y + st.y);
+      Sh[e] = st;
+    }
+  }
+  if (tid == 0) {
+    sc[2] = al;
+    sc[3] = (al > 0.0) ? 1.0 : 0.0;  // pending pair exists
+    if (al == 0.0) sc[1] = 0.0;      // no decrease: drop the history
+  }
+}
+
 __global__ void k_lb_init(double* sc, int P, int m) {
   int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
@@ -287,21 +332,23 @@ __global__ void k_lb_init(double* sc, int P, int m) {
 }
 
 template <int EPT>
-int launch_dir_step(bool dir, const LbArgs& a, hipStream_t s) {
-  if (dir) k_direction<EPT><<<a.P, LWG, 0, s>>>(a);
-  else k_step<EPT><<<a.P, LWG, 0, s>>>(a);
+int launch_dir_step(int what, const LbArgs& a, hipStream_t s) {
+  if (what == 0) k_direction<EPT><<<a.P, LWG, 0, s>>>(a);
+  else if (what == 1) k_step<EPT><<<a.P, LWG, 0, s>>>(a);
+  else k_step_amp<EPT><<<a.P, LWG, 0, s>>>(a);
   return (int)hipGetLastError();
 }
 
-int dispatch(bool dir, const LbArgs& a, hipStream_t s) {
+// what: 0 direction, 1 exact quartic step, 2 amplitude trial step
+int dispatch(int what, const LbArgs& a, hipStream_t s) {
   int ept = (a.N + LWG - 1) / LWG;
   switch (ept) {
-    case 1: return launch_dir_step<1>(dir, a, s);
-    case 2: return launch_dir_step<2>(dir, a, s);
-    case 4: return launch_dir_step<4>(dir, a, s);
-    case 8: return launch_dir_step<8>(dir, a, s);
-    case 16: return launch_dir_step<16>(dir, a, s);
-    case 32: return launch_dir_step<32>(dir, a, s);
+    case 1: return launch_dir_step<1>(what, a, s);
+    case 2: return launch_dir_step<2>(what, a, s);
+    case 4: return launch_dir_step<4>(what, a, s);
+    case 8: return launch_dir_step<8>(what, a, s);
+    case 16: return launch_dir_step<16>(what, a, s);
+    case 32: return launch_dir_step<32>(what, a, s);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -309,7 +356,8 @@ int dispatch(bool dir, const LbArgs& a, hipStream_t s) {
 }  // namespace
 
 int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters, int m, void* t,
-              LbfgsBuffers& b, void* stream) {
+              LbfgsBuffers& b, void* stream, int amplitude) {
+  const int gmode = amplitude ? M_AGRAD : M_GRAD, lmode = amplitude ? M_ALS : M_LS;
   hipStream_t s = (hipStream_t)stream;
   const int P = base.P;
   k_lb_init<<<(P + 255) / 256, 256, 0, s>>>((double*)b.sc, P, m);
@@ -321,7 +369,7 @@ int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters,
   ga.tin = (const cx<float>*)t;
   ga.tout = (cx<float>*)gcur;
   ga.sums = (iters == 0) ? b.sums : nullptr;  // f is reported for the final point only
-  if ((e = fn(M_GRAD, ibf16, ga, stream))) return e;
+  if ((e = fn(gmode, ibf16, ga, stream))) return e;
   for (int it = 0; it < iters; ++it) {
     LbArgs la;
     la.P = P;
@@ -336,20 +384,21 @@ int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters,
     la.sums = b.sums;
     la.t = (float2*)t;
     la.first = (it == 0);
-    if ((e = dispatch(true, la, s))) return e;
+    la.h0 = amplitude ? 1.f / (2.f * (float)base.K * (float)N) : 1.f;
+    if ((e = dispatch(0, la, s))) return e;
     RowArgs ls = base;
     ls.tin = (const cx<float>*)t;
     ls.din = (const cx<float>*)b.d;
     ls.sums = b.sums;
-    if ((e = fn(M_LS, ibf16, ls, stream))) return e;
-    if ((e = dispatch(false, la, s))) return e;
+    if ((e = fn(lmode, ibf16, ls, stream))) return e;
+    if ((e = dispatch(amplitude ? 2 : 1, la, s))) return e;
     // gradient at the new t into the other buffer
     void* tmp = gprev;
     gprev = gcur;
     gcur = tmp;
     ga.tout = (cx<float>*)gcur;
     ga.sums = (it == iters - 1) ? b.sums : nullptr;
-    if ((e = fn(M_GRAD, ibf16, ga, stream))) return e;
+    if ((e = fn(gmode, ibf16, ga, stream))) return e;
   }
   return 0;
 }

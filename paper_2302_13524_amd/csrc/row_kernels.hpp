@@ -15,10 +15,13 @@ enum Mode : int {
   M_SPEC = 5,        // heavy-ball power step on A^H diag(w) A      -> tout (v), vscale
   M_LS = 6,          // quartic line-search sums for y = A t, z = A d -> sums[6]
   M_RES64 = 7,       // FP64 residual: sums64 {sum r^2, sum I^2}
-  M_BACKPROP = 8     // x = A^H sqrt(I) / (K N)                     -> tout
+  M_BACKPROP = 8,    // x = A^H sqrt(I) / (K N)                     -> tout
+  M_AGRAD = 9,       // g = -2 A^H((sqrt(I) - |y|) y/|y|)           -> tout, sums {f_a}
+  M_ALS = 10         // amplitude cost at t + a_j d, a_j = 2^(j-3), j < 8 -> sums {f_a(t), f_a(t + a_j d)}
 };
 
-constexpr int NSUM = 6;
+constexpr int NSUM = 9;
+constexpr int AMP_TRIALS = 8;  // M_ALS trial steps 1/8 .. 16
 
 struct RowArgs {
   int P, K;
@@ -172,7 +175,7 @@ struct Launch {
   // double-buffered LDS exchange when two copies of the rows fit in 160 KiB
   static constexpr bool DB = 2 * RPW * PL::LDS_ROW * 8 <= 160 * 1024 - 4096;
   static constexpr int LDS_ELEMS = (DB ? 2 : 1) * RPW * PL::LDS_ROW;
-  static constexpr int RED_FLOATS = (WG / 64 + 1) * 6 * 2;
+  static constexpr int RED_FLOATS = (WG / 64 + 1) * NSUM * 2;
 };
 
 // ---------------------------------------------------------------- FP32 kernel
@@ -292,6 +295,29 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         }
       }
       continue;
+    } else if constexpr (MODE == M_ALS) {
+      // f_a(t + a d) = sum (sqrt(I) - |y + a z|)^2 at a = 0 and the trial steps
+      C y[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) y[i] = x[i];
+#pragma unroll
+      for (int i = 0; i < E; ++i) x[i] = cmul(gload(drow + E0(i)), gload(mk + E0(i)));
+      fft_forward<PL, T>(x, xb, ltid, tw);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        int k = KL(i);
+        const float amp = hw_sqrt(fmaxf(load_I<IT>(a.I, mbase + k), 0.f));
+        const float r0 = amp - hw_sqrt(norm2(y[i]));
+        acc[0].add(r0 * r0);
+#pragma unroll
+        for (int j = 0; j < AMP_TRIALS; ++j) {
+          const float st = ldexpf(1.f, j - 3);
+          const C w = C{y[i].x + st * x[i].x, y[i].y + st * x[i].y};
+          const float r = amp - hw_sqrt(norm2(w));
+          acc[1 + j].add(r * r);
+        }
+      }
+      continue;
     } else if constexpr (MODE == M_LS) {
       C y[E];
 #pragma unroll
@@ -315,7 +341,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       }
       continue;
     } else {
-      if constexpr (MODE == M_ER || MODE == M_GRAD || MODE == M_SPEC) {
+      if constexpr (MODE == M_ER || MODE == M_GRAD || MODE == M_SPEC || MODE == M_AGRAD) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           int k = KL(i);
@@ -339,6 +365,14 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
             float r = iv - n;
             if constexpr (SUMS) acc[0].add(r * r);
             x[i] = scl(x[i], r);
+          } else if constexpr (MODE == M_AGRAD) {
+            // -2 (sqrt(I) - |y|) y/|y|, with y/|y| := 1 at y = 0
+            float amp = hw_sqrt(fmaxf(iv, 0.f));
+            float rs = hw_rsq(n);
+            bool nz = n > 0.f;
+            float r = amp - (nz ? n * rs : 0.f);
+            if constexpr (SUMS) acc[0].add(r * r);
+            x[i] = nz ? scl(x[i], -2.f * r * rs) : C{-2.f * r, 0.f};
           } else {
             float w = fminf(iv * inv_mean, a.tau);
             x[i] = scl(x[i], w);
@@ -353,12 +387,13 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 
   if constexpr (MODE == M_FWD_FIELD || MODE == M_FWD_INT) {
     return;
-  } else if constexpr (MODE == M_LS) {
-    float out[NSUM];
-    row_reduce<PL::T, WG, NSUM>(acc, red, tid, out);
+  } else if constexpr (MODE == M_LS || MODE == M_ALS) {
+    constexpr int NS = (MODE == M_LS) ? 6 : 1 + AMP_TRIALS;
+    float out[NS];
+    row_reduce<PL::T, WG, NS>(acc, red, tid, out);
     if (valid && ltid == 0) {
 #pragma unroll
-      for (int i = 0; i < NSUM; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
+      for (int i = 0; i < NS; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
     }
   } else if constexpr (MODE == M_SPEC) {
     // lambda = Re <v, M v> (v has unit norm); x = (M - sigma) v - beta v_prev
@@ -413,7 +448,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 #pragma unroll
       for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i], scale));
     }
-    if constexpr ((MODE == M_ER || MODE == M_GRAD) && SUMS) {
+    if constexpr ((MODE == M_ER || MODE == M_GRAD || MODE == M_AGRAD) && SUMS) {
       float out[NSUM];
       row_reduce<PL::T, WG, (MODE == M_ER) ? 2 : 1>(acc, red, tid, out);
       if (valid && ltid == 0 && a.sums) {

@@ -270,8 +270,21 @@ int tm_adjoint(tm_ctx* c, tm_dims d, const tm_c32* masks, const tm_c32* y, tm_c3
   return run_row(c, fn, tmk::M_ADJ, 0, a, stream);
 }
 
+static int gradient_mode(tm_ctx* c, int mode, tm_dims d, const tm_c32* masks, const void* I, int I_dtype,
+                         const tm_c32* t, tm_c32* grad, float* f, void* stream);
+
 int tm_gradient(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, int I_dtype,
                 const tm_c32* t, tm_c32* grad, float* f, void* stream) {
+  return gradient_mode(c, tmk::M_GRAD, d, masks, I, I_dtype, t, grad, f, stream);
+}
+
+int tm_amp_gradient(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, int I_dtype,
+                    const tm_c32* t, tm_c32* grad, float* f, void* stream) {
+  return gradient_mode(c, tmk::M_AGRAD, d, masks, I, I_dtype, t, grad, f, stream);
+}
+
+static int gradient_mode(tm_ctx* c, int mode, tm_dims d, const tm_c32* masks, const void* I, int I_dtype,
+                         const tm_c32* t, tm_c32* grad, float* f, void* stream) {
   if (!c) return TM_EINVAL;
   tmk::row_launcher fn;
   int r = check_dims(c, d, &fn);
@@ -287,7 +300,7 @@ int tm_gradient(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, int I_
   a.tin = (const tmk::cx<float>*)t;
   a.tout = (tmk::cx<float>*)grad;
   a.sums = sums;
-  r = run_row(c, fn, tmk::M_GRAD, I_dtype == TM_BF16, a, stream);
+  r = run_row(c, fn, mode, I_dtype == TM_BF16, a, stream);
   if (r) return r;
   if (f) {
     HIPCHK(c, hipMemcpy2DAsync(f, sizeof(float), sums, tmk::NSUM * sizeof(float), sizeof(float), d.P,
@@ -334,7 +347,8 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   int r = check_dims(c, d, &fn);
   if (r) return r;
   if (!o) return fail(c, TM_EINVAL, "opts is NULL");
-  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_LBFGS) return fail(c, TM_EINVAL, "method %d", o->method);
+  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_LBFGS && o->method != TM_METHOD_LBFGS_AMP)
+    return fail(c, TM_EINVAL, "method %d", o->method);
   if (o->iters < 0) return fail(c, TM_EINVAL, "iters %d < 0", o->iters);
   if (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", o->I_dtype);
   if (o->start < TM_START_GIVEN || o->start > TM_START_SPECTRAL) return fail(c, TM_EINVAL, "start %d", o->start);
@@ -347,7 +361,7 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
       return fail(c, TM_EINVAL, "spectral_lower must be in [-1, spectral_momentum]");
   }
   if (!(o->er_momentum >= 0.f && o->er_momentum < 1.f)) return fail(c, TM_EINVAL, "er_momentum must be in [0, 1)");
-  if (o->method == TM_METHOD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
+  if (o->method != TM_METHOD_ER && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
     return fail(c, TM_EINVAL, "lbfgs_m %d outside 1..16", o->lbfgs_m);
   if (d.P == 0) return TM_OK;
   if (!masks || !I || !t) return fail(c, TM_EINVAL, "null pointer argument");
@@ -443,9 +457,11 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     b.sc = ws_get(c, WS_LB_SC, (size_t)d.P * tmk::LB_SCALARS(o->lbfgs_m) * sizeof(double));
     if (!b.g || !b.gp || !b.d || !b.S || !b.Y || !b.sc) return fail(c, TM_ENOMEM, "L-BFGS workspace");
     b.sums = sums;
-    int e = tmk::run_lbfgs(fn, a, ibf, N, o->iters, o->lbfgs_m, tt, b, stream);
+    const int amp = o->method == TM_METHOD_LBFGS_AMP;
+    int e = tmk::run_lbfgs(fn, a, ibf, N, o->iters, o->lbfgs_m, tt, b, stream, amp);
     if (e) return hipfail(c, e, "L-BFGS");
-    f_idx = 0;
+    if (amp) amp_idx = 0;  // the amplitude cost sum (sqrt(I) - |A t|)^2
+    else f_idx = 0;
   }
 
   // ---- FP64 acceptance residual and per-row record

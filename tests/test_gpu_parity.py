@@ -93,6 +93,33 @@ def test_gradient(ctx, n1, n2):
     assert relerr(f.cpu().numpy(), f_ref) < OPTOL
 
 
+@pytest.mark.parametrize("n1,n2", [(8, 8), (32, 32), (64, 32), (128, 64), (1, 1024)])
+def test_amplitude_gradient(ctx, n1, n2):
+    P = rows_for(n1 * n2)
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=913, noise=1e4)
+    t0 = T + 0.3 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(913, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    fo, go, _ = rt.amplitude_grad(ops.FFTOp(m, n1, n2), Ir, t)
+    g, f = tm.tm_amp_gradient(ctx, c64(masks), f32(I), c64(t0), n1, n2)
+    assert relerr(g.cpu().numpy(), go) < OPTOL
+    assert relerr(f.cpu().numpy(), fo) < OPTOL
+
+
+@pytest.mark.parametrize("iters", [1, 2, 3])
+def test_amplitude_lbfgs_steps(ctx, iters):
+    n1, n2, P = 32, 32, 13
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=914, noise=1e4)
+    t0 = T + 0.5 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(914, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    ref, _ = rt.lbfgs_amplitude(ops.FFTOp(m, n1, n2), Ir, t, iters)
+    tt = c64(t0)
+    raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("lbfgs_amp", iters=iters))
+    assert relerr(tt.cpu().numpy(), ref) < 1e-4 * iters
+    st = tm.decode_stats(raw)
+    fa = rt.amplitude_residual(Ir, ops.FFTOp(m, n1, n2).forward(ref))
+    assert relerr(st.amp_res.numpy(), fa) < 1e-4
+
+
 @pytest.mark.parametrize("n1,n2", [(8, 8), (32, 32), (128, 64)])
 def test_residual_f64(ctx, n1, n2):
     P = rows_for(n1 * n2)
@@ -172,7 +199,7 @@ def _fid(a, b):
     return rt.fidelity(a, b)
 
 
-@pytest.mark.parametrize("method,iters", [("er", 200), ("lbfgs", 100)])
+@pytest.mark.parametrize("method,iters", [("er", 200), ("lbfgs", 100), ("lbfgs_amp", 60)])
 def test_retrieve_noiseless_tiny(ctx, method, iters):
     # 8x8 modes, 32 rows, K = 4, noiseless: spectral start then the solver
     n1, n2, P = 8, 8, 32
@@ -188,8 +215,10 @@ def test_retrieve_noiseless_tiny(ctx, method, iters):
         ref = s0
         for _ in range(iters):
             ref = rt.er_step(opr, Ir, ref)
-    else:
+    elif method == "lbfgs":
         ref, _ = rt.lbfgs(opr, Ir, s0, iters)
+    else:
+        ref, _ = rt.lbfgs_amplitude(opr, Ir, s0, iters)
     tt = c64(v0)
     raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
                          tm.retrieve_opts(method, iters=iters, start="spectral", spectral_iters=30))
