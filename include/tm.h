@@ -353,6 +353,22 @@ int tm_pre_fiber_mask(tm_ctx *ctx, const double *energy, int32_t npix, double fr
 int tm_pre_gather(tm_ctx *ctx, const void *stack, int32_t stack_dtype, int64_t n_img, int32_t H, int32_t W,
                   const int32_t *pix, int32_t P, void *out, int32_t out_dtype, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Validation by foci (Sec. 3): the phase of the conjugate of each retrieved
+ * row, u_p = exp(-j arg tm_est[p]) (1 where tm_est is 0), is displayed on the
+ * modulator; the focus image is |sum_n tm_true[q][n] u_p[n]|^2 over the TM's
+ * pixels q (one complex FP32 GEMM through rocBLAS), and its power ratio is
+ * the power in the (2w+1) x (2w+1) grid window around the brightest pixel
+ * (first in raster order on ties; the window is clipped at the grid border)
+ * over the image's total power (w = 3: the paper's 7 x 7 window).
+ *   tm_true, tm_est [P][N] tm_c32 (device); pix [P] int32 distinct raster
+ *   indices of the rows' pixels on a g1 x g2 grid (checked on the host);
+ *   pr [P] float, peak [P] int32 raster index of each image's peak (-1 and
+ *   PR 0 for an image with no power). Workspace P N + P^2 complex floats. */
+int tm_foci_power_ratio(tm_ctx *ctx, int32_t P, int32_t N, const tm_c32 *tm_true, const tm_c32 *tm_est,
+                        const int32_t *pix, int32_t g1, int32_t g2, int32_t w, float *pr, int32_t *peak,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

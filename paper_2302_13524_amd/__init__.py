@@ -31,7 +31,7 @@ EXPORTED = (
     "tm_defocus_forward", "tm_profile_enable", "tm_profile_query",
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
-    "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient",
+    "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_pre_energy.argtypes = [vp, vp, i32, i64, i32, i32, vp, vp]
     lib.tm_pre_fiber_mask.argtypes = [vp, vp, i32, dp, vp, ctypes.POINTER(i32), vp]
     lib.tm_pre_gather.argtypes = [vp, vp, i32, i64, i32, i32, vp, i32, vp, i32, vp]
+    lib.tm_foci_power_ratio.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -374,6 +375,17 @@ def tm_pre_gather(ctx: Context, stack, pix, bf16=False):
                                TM_BF16 if bf16 else TM_F32, _stream(stack.device))
     ctx.check(rc, "tm_pre_gather")
     return out
+
+
+def tm_foci_power_ratio(ctx: Context, tm_true, tm_est, pix, g1, g2, w=3):
+    """Power ratio [P] float32 and peak raster index [P] int32 of the conjugate-phase focus of every row."""
+    P, N = tm_true.shape
+    pr = torch.empty((P,), dtype=torch.float32, device=tm_true.device)
+    peak = torch.empty((P,), dtype=torch.int32, device=tm_true.device)
+    rc = ctx.lib.tm_foci_power_ratio(ctx.h, int(P), int(N), _ptr(tm_true), _ptr(tm_est), _ptr(pix), int(g1), int(g2),
+                                     int(w), _ptr(pr), _ptr(peak), _stream(tm_true.device))
+    ctx.check(rc, "tm_foci_power_ratio")
+    return pr, peak
 
 
 def tm_defocus_forward(ctx: Context, pix, tm_rows, theta, optics, phi, nf1, nf2):

@@ -1,0 +1,16 @@
+// Conjugate-phase foci of retrieved TM rows and their power ratio (Sec. 3).
+#pragma once
+#include <stdint.h>
+
+namespace tmk {
+
+// u[p][n] = exp(-j arg tm_est[p][n]) (1 where tm_est is 0), [P][N] complex float
+int launch_conj_phase(const void* tm_est, void* u, int64_t n, void* stream);
+// For every focus p (row p of E [P][P] complex, E[p][q] = sum_n u[p][n] tm_true[q][n]):
+// peak = brightest pixel (first in raster order on ties), PR = power in the
+// (2w+1)^2 grid window around the peak / total power. pix [P] raster indices
+// on a g1 x g2 grid.
+int launch_foci_pr(const void* E, int P, const int32_t* pix, int g1, int g2, int w, float* pr, int32_t* peak,
+                   void* stream);
+
+}  // namespace tmk

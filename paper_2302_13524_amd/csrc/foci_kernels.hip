@@ -1,0 +1,129 @@
+// Conjugate-phase foci of retrieved TM rows and their power ratio (Sec. 3):
+// the pattern of row p is the phase of the conjugate of the retrieved row,
+// the focus image is |TM_true u_p|^2 on the TM's pixels (one complex GEMM,
+// done by the caller), and PR is the power in a (2w+1) x (2w+1) grid window
+// around the image's peak over its total power.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "foci.hpp"
+
+namespace tmk {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_conj_phase(const float2* t, float2* u, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) {
+    const float2 v = t[i];
+    const float m2 = v.x * v.x + v.y * v.y;
+    if (m2 > 0.f) {
+      const float r = rsqrtf(m2);
+      u[i] = make_float2(v.x * r, -v.y * r);
+    } else {
+      u[i] = make_float2(1.f, 0.f);
+    }
+  }
+}
+
+constexpr int FWG = 256;
+
+// one workgroup per focus image (row p of E)
+__global__ void __launch_bounds__(FWG) k_foci_pr(const float2* E, int P, const int32_t* pix, int g2, int w, float* pr,
+                                                int32_t* peak) {
+  __shared__ float bv[FWG / 64];
+  __shared__ int bq[FWG / 64];
+  __shared__ double red[FWG / 64];
+  __shared__ int pk;
+  const int p = blockIdx.x;
+  const float2* row = E + (size_t)p * P;
+  // brightest pixel, ties to the smaller raster index; and the total power
+  float best = -1.f;
+  int bestq = 0x7fffffff;
+  double tot = 0.0;
+  for (int q = threadIdx.x; q < P; q += FWG) {
+    const float2 v = row[q];
+    const float I = v.x * v.x + v.y * v.y;
+    const int r = pix[q];
+    tot += (double)I;
+    if (I > best || (I == best && r < bestq)) {
+      best = I;
+      bestq = r;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float ov = __shfl_xor(best, off, 64);
+    const int oq = __shfl_xor(bestq, off, 64);
+    if (ov > best || (ov == best && oq < bestq)) {
+      best = ov;
+      bestq = oq;
+    }
+    tot += __shfl_xor(tot, off, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    bv[wv] = best;
+    bq[wv] = bestq;
+    red[wv] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = bv[0];
+    int bqq = bq[0];
+    double t = red[0];
+    for (int i = 1; i < FWG / 64; ++i) {
+      if (bv[i] > b || (bv[i] == b && bq[i] < bqq)) {
+        b = bv[i];
+        bqq = bq[i];
+      }
+      t += red[i];
+    }
+    pk = bqq;
+    red[0] = t;
+  }
+  __syncthreads();
+  const double total = red[0];
+  const int py = pk / g2, px = pk - (pk / g2) * g2;
+  __syncthreads();
+  double sig = 0.0;
+  for (int q = threadIdx.x; q < P; q += FWG) {
+    const int r = pix[q];
+    const int y = r / g2, x = r - (r / g2) * g2;
+    if (abs(y - py) <= w && abs(x - px) <= w) {
+      const float2 v = row[q];
+      sig += (double)(v.x * v.x + v.y * v.y);
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) sig += __shfl_xor(sig, off, 64);
+  if ((threadIdx.x & 63) == 0) red[wv] = sig;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < FWG / 64; ++i) s += red[i];
+    const bool lit = total > 0.0;
+    pr[p] = lit ? (float)(s / total) : 0.f;
+    peak[p] = lit ? pk : -1;
+  }
+}
+
+}  // namespace
+
+int launch_conj_phase(const void* tm_est, void* u, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_conj_phase<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((const float2*)tm_est, (float2*)u, n);
+  return (int)hipGetLastError();
+}
+
+int launch_foci_pr(const void* E, int P, const int32_t* pix, int g1, int g2, int w, float* pr, int32_t* peak,
+                   void* stream) {
+  (void)g1;
+  if (P <= 0) return 0;
+  k_foci_pr<<<P, FWG, 0, (hipStream_t)stream>>>((const float2*)E, P, pix, g2, w, pr, peak);
+  return (int)hipGetLastError();
+}
+
+}  // namespace tmk

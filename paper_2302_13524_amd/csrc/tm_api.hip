@@ -13,8 +13,11 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "../../include/tm.h"
 #include "aux.hpp"
+#include "foci.hpp"
 #include "batch.hpp"
 #include "grids.hpp"
 #include "lbfgs.hpp"
@@ -45,6 +48,7 @@ struct tm_ctx {
   int64_t acc_n[16] = {0};
   std::map<int, int> variant;  // (L1 << 8 | L2) -> FFT digit-order variant
   double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
+  rocblas_handle blas = nullptr;  // plain complex GEMM of the foci synthesis
 };
 
 namespace {
@@ -103,7 +107,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
   WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_PRE_PART,
-  WS_PRE_COUNT,
+  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E,
   WS_PH_BASE = 100
 };
 
@@ -225,6 +229,7 @@ int tm_destroy(tm_ctx* c) {
   prof_drain(c);
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->pinned) hipHostFree(c->pinned);
+  if (c->blas) rocblas_destroy_handle(c->blas);
   for (auto& kv : c->ws) hipFree(kv.second.p);
   hipFree(c->tw32);
   hipFree(c->tw64);
@@ -468,7 +473,7 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   r = residual_into(c, fn, d, masks, I, o->I_dtype, t, s64, stream);
   if (r) return r;
   if (stats) {
-    int e = tmk::launch_finalize(stats, d.P, s64, (f_idx >= 0) ? sums : nullptr, tmk::NSUM, f_idx,
+    int e = tmk::launch_finalize(stats, d.P, s64, (f_idx >= 0 || amp_idx >= 0) ? sums : nullptr, tmk::NSUM, f_idx,
                                  amp_idx, o->iters, 1e-2, stream);
     if (e) return hipfail(c, e, "finalize");
   }
@@ -1138,5 +1143,45 @@ extern "C" int tm_pre_gather(tm_ctx* c, const void* stack, int32_t stack_dtype, 
     if (hp[i] < 0 || hp[i] >= npix) return fail(c, TM_EINVAL, "pix[%d]=%d outside the half-sampled grid", i, hp[i]);
   int e = tmk::launch_pre_gather(stack, stack_dtype == TM_U16, n_img, H, W, pix, P, out, out_dtype == TM_BF16, stream);
   if (e) return hipfail(c, e, "gather");
+  return TM_OK;
+}
+
+// ------------------------------------------------------------ foci and power ratio
+extern "C" int tm_foci_power_ratio(tm_ctx* c, int32_t P, int32_t N, const tm_c32* tm_true, const tm_c32* tm_est,
+                                   const int32_t* pix, int32_t g1, int32_t g2, int32_t w, float* pr, int32_t* peak,
+                                   void* stream) {
+  if (!c) return TM_EINVAL;
+  if (P < 0 || N < 1 || g1 < 1 || g2 < 1 || w < 0) return fail(c, TM_EINVAL, "P >= 0, N >= 1, grid >= 1, w >= 0");
+  if (P == 0) return TM_OK;
+  if (!tm_true || !tm_est || !pix || !pr || !peak) return fail(c, TM_EINVAL, "null pointer argument");
+  if ((int64_t)P > (int64_t)g1 * g2) return fail(c, TM_EINVAL, "P=%d exceeds the %dx%d grid", P, g1, g2);
+  HIPCHK(c, hipSetDevice(c->device));
+  std::vector<int32_t> hp(P);
+  if (hipMemcpy(hp.data(), pix, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, TM_EHIP, "reading pix");
+  std::vector<char> seen((size_t)g1 * g2, 0);
+  for (int i = 0; i < P; ++i) {
+    if (hp[i] < 0 || hp[i] >= g1 * g2) return fail(c, TM_EINVAL, "pix[%d]=%d outside the grid", i, hp[i]);
+    if (seen[hp[i]]) return fail(c, TM_EINVAL, "pix[%d]=%d repeats a pixel", i, hp[i]);
+    seen[hp[i]] = 1;
+  }
+  void* u = ws_get(c, WS_FOCI_U, (size_t)P * N * sizeof(tm_c32));
+  void* E = ws_get(c, WS_FOCI_E, (size_t)P * P * sizeof(tm_c32));
+  if (!u || !E) return fail(c, TM_ENOMEM, "workspace");
+  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return fail(c, TM_EHIP, "rocblas_create_handle failed");
+  }
+  int e = tmk::launch_conj_phase(tm_est, u, (int64_t)P * N, stream);
+  if (e) return hipfail(c, e, "conjugate phase");
+  // E[p][q] = sum_n u[p][n] tm_true[q][n]: in column-major terms E^T = T^T U with T, U stored N x P
+  const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
+  if (rocblas_set_stream(c->blas, (hipStream_t)stream) != rocblas_status_success ||
+      rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, P, P, N, &one,
+                    (const rocblas_float_complex*)tm_true, N, (const rocblas_float_complex*)u, N, &zero,
+                    (rocblas_float_complex*)E, P) != rocblas_status_success)
+    return fail(c, TM_EHIP, "rocblas_cgemm failed");
+  e = tmk::launch_foci_pr(E, P, pix, g1, g2, w, pr, peak, stream);
+  if (e) return hipfail(c, e, "power ratio");
   return TM_OK;
 }

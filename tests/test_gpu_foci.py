@@ -1,0 +1,57 @@
+"""GPU parity of the foci power ratio against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2302_13524_amd as tm
+import tm_synth
+from oracle import foci
+
+from gpu_util import c64, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("g,P,N,noise,w", [(16, 100, 64, 0.3, 3), (32, 700, 256, 0.6, 3), (8, 7, 33, 0.1, 1),
+                                           (64, 2286, 1024, 0.5, 3)])
+def test_power_ratio_matches_oracle(ctx, g, P, N, noise, w):
+    print(f"foci g={g} P={P} N={N}", flush=True)
+    pix = tm_synth.nearest_pixels(g, P)
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(995, 1))
+    est = T + noise * tm_synth.tm_iid(P, N, tm_synth.rng(995, 2))
+    Tt, Et = c64(T), c64(est)
+    pr, peak = tm.tm_foci_power_ratio(ctx, Tt, Et, torch.from_numpy(pix.astype(np.int32)).to(dev()), g, g, w)
+    # the oracle on the FP32-rounded rows the device uses
+    r32 = lambda x: x.astype(np.complex64).astype(np.complex128)
+    pro, pko = foci.foci_power_ratios(r32(T), r32(est), pix, g, g, w)
+    pr, peak = pr.cpu().numpy(), peak.cpu().numpy()
+    F = foci.focus_intensities(r32(T), r32(est))
+    # peaks agree wherever the brightest pixel leads the runner-up by more than rounding
+    top2 = np.sort(F, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 1e-4 * top2[:, 1]
+    assert np.array_equal(peak[clear], pko[clear])
+    assert np.max(np.abs(pr[clear] - pro[clear])) < 1e-5
+    assert clear.mean() > 0.95
+
+
+def test_exact_rows_focus_at_their_pixels(ctx):
+    g, P, N = 32, 500, 512
+    pix = tm_synth.nearest_pixels(g, P)
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(996, 1))
+    pr, peak = tm.tm_foci_power_ratio(ctx, c64(T), c64(T * np.exp(1j * 0.4)), torch.from_numpy(pix.astype(np.int32)).to(dev()), g, g)
+    assert np.array_equal(peak.cpu().numpy(), pix)  # an exact row (any phase) focuses on its own pixel
+
+
+def test_errors(ctx):
+    T = c64(np.ones((3, 4)))
+    with pytest.raises(tm.TMError, match="repeats"):
+        tm.tm_foci_power_ratio(ctx, T, T, torch.tensor([0, 1, 1], dtype=torch.int32, device=dev()), 4, 4)
+    with pytest.raises(tm.TMError, match="outside the grid"):
+        tm.tm_foci_power_ratio(ctx, T, T, torch.tensor([0, 1, 16], dtype=torch.int32, device=dev()), 4, 4)
