@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 12-TM batch")
     ap.add_argument("--no-preprocess", action="store_true", help="skip the camera-stack preprocessing")
+    ap.add_argument("--no-foci", action="store_true", help="skip the foci power ratio")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-probing comparator")
     ap.add_argument("--train-rows", type=int, default=51200)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
@@ -277,6 +279,14 @@ def main():
             n_lb = k
             break
     log(f"L-BFGS reaches 0.99 within {n_lb} iterations")
+    n_la = None
+    for k in () if args.no_lbfgs else (5, 8, 10, 12, 15, 20, 25, 30, 40, 50, 70, 100):
+        t = v0t.clone()
+        tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("lbfgs_amp", k), stats=False)
+        if fidelity(t).mean().item() >= 0.99:
+            n_la = k
+            break
+    log(f"amplitude L-BFGS reaches 0.99 within {n_la} iterations")
 
     def step(method="er", iters=n_er, phase=True):
         t = v0t.clone()
@@ -315,6 +325,7 @@ def main():
 
     ret_ms = timed(lambda: step(phase=False))
     lb_ms = timed(lambda: step("lbfgs", n_lb, phase=False)) if n_lb else None
+    la_ms = timed(lambda: step("lbfgs_amp", n_la, phase=False)) if n_la else None
 
     fid = fidelity(t).cpu().numpy()
     st = tm.decode_stats(raw)
@@ -392,6 +403,7 @@ def main():
         "retrieval_rows_per_s": round(P / (ret_ms * 1e-3), 1),
         "phase_correction_ms": round(ms_step - ret_ms, 3),
         "lbfgs": {"iters_to_0.99": n_lb, "retrieval_ms": round(lb_ms, 3) if lb_ms else None},
+        "lbfgs_amplitude": {"iters_to_0.99": n_la, "retrieval_ms": round(la_ms, 3) if la_ms else None},
         "quality": {"mean_fidelity": round(float(fid.mean()), 6), "min_fidelity": round(float(fid.min()), 6),
                     "frac_rows_ge_0.99": round(float((fid >= 0.99).mean()), 4),
                     "spectral_start_fidelity": round(f_start, 4),
@@ -403,6 +415,10 @@ def main():
                       "residual_f64_avg": round(rs_ms / max(rs_n, 1), 5)},
     }
 
+    if not args.no_foci:
+        out["foci"] = foci_variant(ctx, Tt, t, pixt, grid, P, N)
+    if not args.no_dense and not args.small:
+        out["dense_comparator"] = dense_variant(ctx, mk, It, t, n1, n2)
     if not args.no_learned:
         out["learned"] = learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, P)
     if not args.no_batch and not args.small:
@@ -449,6 +465,71 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
             "plain_retrieval_ms": round(ret_ms, 3), "start_fidelity": round(f_start, 5),
             "rows_redone_from_fallback": redone, "final_mean_fidelity": round(float(fidelity(t).mean().item()), 6),
             "train_rows": args.train_rows, "train_s": round(train_s, 2), "train_loss": [round(h, 5) for h in hist]}
+
+
+def foci_variant(ctx, Tt, t, pixt, grid, P, N):
+    """Foci of the retrieved rows (Sec. 3 validation): the phase of each row's
+    conjugate on the modulator, the true TM forms the image, PR = power in the
+    7 x 7 window around the peak over the total. Also the true TM's own PR
+    (the reference the paper takes from holography)."""
+    import torch
+
+    import paper_2302_13524_amd as tm
+
+    pr, peak = tm.tm_foci_power_ratio(ctx, Tt, t, pixt, grid, grid, 3)
+    pr_ref, _ = tm.tm_foci_power_ratio(ctx, Tt, Tt, pixt, grid, grid, 3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        tm.tm_foci_power_ratio(ctx, Tt, t, pixt, grid, grid, 3)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    flops = 8.0 * P * P * N  # the complex GEMM
+    on_target = float((peak == pixt).float().mean().item())
+    return {"pr_mean": round(float(pr.mean().item()), 4), "pr_mean_true_tm": round(float(pr_ref.mean().item()), 4),
+            "frac_peak_on_pixel": round(on_target, 4), "ms": round(ms, 3),
+            "gemm_tflops": round(flops / (ms * 1e-3) / 1e12, 1), "window": 7}
+
+
+def dense_variant(ctx, mk, It, t, n1, n2):
+    """Comparator without FFTs (Table time of the paper, on this GPU): one
+    gradient evaluation of the intensity cost with a dense random-phase
+    probing matrix Q [K N][N] (two complex FP32 GEMMs through rocBLAS, plus
+    the pointwise step) against the fused FFT gradient kernel on the same rows."""
+    import torch
+
+    import paper_2302_13524_amd as tm
+
+    dev = torch.device("cuda:0")
+    K, N = mk.shape
+    P = t.shape[0]
+    g = torch.Generator(device=dev)
+    g.manual_seed(91)
+    Q = torch.polar(torch.ones((K * N, N), device=dev), 2 * np.pi * torch.rand((K * N, N), generator=g, device=dev))
+    Q = Q.to(torch.complex64).contiguous()
+    I2 = It.reshape(P, K * N).contiguous()
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    d_ms = timed(lambda: tm.tm_dense_gradient(ctx, Q, I2, t))
+    f_ms = timed(lambda: tm.tm_gradient(ctx, mk, It, t, n1, n2), reps=10)
+    flops = 2 * 8.0 * P * N * K * N
+    del Q
+    torch.cuda.empty_cache()
+    return {"dense_gradient_ms": round(d_ms, 2), "fft_gradient_ms": round(f_ms, 4),
+            "speedup_fft": round(d_ms / f_ms, 1), "dense_gemm_tflops": round(flops / (d_ms * 1e-3) / 1e12, 1),
+            "M": K * N, "N": N, "P": P}
 
 
 def preprocess_variant(ctx, args):

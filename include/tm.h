@@ -369,6 +369,15 @@ int tm_foci_power_ratio(tm_ctx *ctx, int32_t P, int32_t N, const tm_c32 *tm_true
                         const int32_t *pix, int32_t g1, int32_t g2, int32_t w, float *pr, int32_t *peak,
                         void *stream);
 
+/* Comparator without FFTs (Sec. 2.2, Table time): the gradient of
+ * f(t) = ||I - |Q t|^2||^2 for an explicit dense probing matrix Q [M][N]
+ * (e.g. random phases), grad = -4 Q^H((Q t)(I - |Q t|^2)), as two complex
+ * FP32 GEMMs (rocBLAS, Theta(M N) per row) around a fused pointwise kernel.
+ *   Q [M][N] tm_c32, I [P][M] float, t [P][N] tm_c32, grad [P][N] tm_c32,
+ *   f [P] float (may be NULL). Workspace P M complex floats. */
+int tm_dense_gradient(tm_ctx *ctx, int32_t M, int32_t N, int32_t P, const tm_c32 *Q, const float *I,
+                      const tm_c32 *t, tm_c32 *grad, float *f, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,3 +87,19 @@ class FFTOp:
 def intensities(op, t: np.ndarray) -> np.ndarray:
     """I = |A t|^2 per row, [P, K, N] (Eq. forwardmodel, per pixel as Eq. optTMsmall2)."""
     return np.abs(op.forward(t)) ** 2
+
+
+class MatrixOp:
+    """y = Q t and x = Q^H y for an explicit dense probing matrix Q [M][N]
+    (the random-phase probing of the prior art the paper compares with,
+    whose products cost Theta(M N) without FFTs, Sec. 2.2 and Table time)."""
+
+    def __init__(self, Q: np.ndarray):
+        self.Q = np.asarray(Q, dtype=np.complex128)
+        self.M, self.N = self.Q.shape
+
+    def forward(self, t: np.ndarray) -> np.ndarray:
+        return np.atleast_2d(t) @ self.Q.T
+
+    def adjoint(self, y: np.ndarray) -> np.ndarray:
+        return y @ self.Q.conj()

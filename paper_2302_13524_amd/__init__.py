@@ -32,6 +32,7 @@ EXPORTED = (
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
+    "tm_dense_gradient",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -135,6 +136,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_pre_fiber_mask.argtypes = [vp, vp, i32, dp, vp, ctypes.POINTER(i32), vp]
     lib.tm_pre_gather.argtypes = [vp, vp, i32, i64, i32, i32, vp, i32, vp, i32, vp]
     lib.tm_foci_power_ratio.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
+    lib.tm_dense_gradient.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -375,6 +377,18 @@ def tm_pre_gather(ctx: Context, stack, pix, bf16=False):
                                TM_BF16 if bf16 else TM_F32, _stream(stack.device))
     ctx.check(rc, "tm_pre_gather")
     return out
+
+
+def tm_dense_gradient(ctx: Context, Q, I, t):
+    """Gradient -4 Q^H((Q t)(I - |Q t|^2)) and f per row for a dense probing matrix Q [M, N]."""
+    M, N = Q.shape
+    P = t.shape[0]
+    g = torch.empty((P, N), dtype=torch.complex64, device=t.device)
+    f = torch.empty((P,), dtype=torch.float32, device=t.device)
+    rc = ctx.lib.tm_dense_gradient(ctx.h, int(M), int(N), int(P), _ptr(Q), _ptr(I), _ptr(t), _ptr(g), _ptr(f),
+                                   _stream(t.device))
+    ctx.check(rc, "tm_dense_gradient")
+    return g, f
 
 
 def tm_foci_power_ratio(ctx: Context, tm_true, tm_est, pix, g1, g2, w=3):

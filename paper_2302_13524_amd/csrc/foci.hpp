@@ -14,3 +14,11 @@ int launch_foci_pr(const void* E, int P, const int32_t* pix, int g1, int g2, int
                    void* stream);
 
 }  // namespace tmk
+
+namespace tmk {
+// Dense-probing gradient helpers (the Theta(M N) comparator without FFTs):
+// given Y [P][M] = Q t, w[p][i] = -4 conj(Y (I - |Y|^2)) in place and f[p] = sum (I - |Y|^2)^2;
+// afterwards grad = conj(H) in place.
+int launch_dense_pointwise(void* Y, const float* I, int P, int64_t M, float* f, void* stream);
+int launch_conj_inplace(void* x, int64_t n, void* stream);
+}  // namespace tmk

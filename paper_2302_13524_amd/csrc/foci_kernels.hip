@@ -127,3 +127,49 @@ int launch_foci_pr(const void* E, int P, const int32_t* pix, int g1, int g2, int
 }
 
 }  // namespace tmk
+
+namespace tmk {
+namespace {
+
+// one workgroup per row p: w = -4 conj(y (I - |y|^2)), f_p = sum (I - |y|^2)^2 (FP64 accumulation)
+__global__ void __launch_bounds__(256) k_dense_pointwise(float2* Y, const float* I, int64_t M, float* f) {
+  __shared__ double red[4];
+  const int p = blockIdx.x;
+  float2* y = Y + (size_t)p * M;
+  const float* ip = I + (size_t)p * M;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < M; i += 256) {
+    const float2 v = y[i];
+    const float r = ip[i] - (v.x * v.x + v.y * v.y);
+    s += (double)r * (double)r;
+    y[i] = make_float2(-4.f * r * v.x, 4.f * r * v.y);
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0 && f) f[p] = (float)((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+__global__ void __launch_bounds__(256) k_conj(float2* x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) x[i].y = -x[i].y;
+}
+
+}  // namespace
+
+int launch_dense_pointwise(void* Y, const float* I, int P, int64_t M, float* f, void* stream) {
+  if (P <= 0) return 0;
+  k_dense_pointwise<<<P, 256, 0, (hipStream_t)stream>>>((float2*)Y, I, M, f);
+  return (int)hipGetLastError();
+}
+
+int launch_conj_inplace(void* x, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_conj<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((float2*)x, n);
+  return (int)hipGetLastError();
+}
+
+}  // namespace tmk

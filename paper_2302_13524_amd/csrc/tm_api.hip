@@ -107,7 +107,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
   WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_PRE_PART,
-  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E,
+  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E, WS_DENSE_Y,
   WS_PH_BASE = 100
 };
 
@@ -1183,5 +1183,45 @@ extern "C" int tm_foci_power_ratio(tm_ctx* c, int32_t P, int32_t N, const tm_c32
     return fail(c, TM_EHIP, "rocblas_cgemm failed");
   e = tmk::launch_foci_pr(E, P, pix, g1, g2, w, pr, peak, stream);
   if (e) return hipfail(c, e, "power ratio");
+  return TM_OK;
+}
+
+// ------------------------------------------------------------ dense-probing comparator
+static int blas_ready(tm_ctx* c, void* stream) {
+  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return fail(c, TM_EHIP, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(c->blas, (hipStream_t)stream) != rocblas_status_success)
+    return fail(c, TM_EHIP, "rocblas_set_stream failed");
+  return TM_OK;
+}
+
+extern "C" int tm_dense_gradient(tm_ctx* c, int32_t M, int32_t N, int32_t P, const tm_c32* Q, const float* I,
+                                 const tm_c32* t, tm_c32* grad, float* f, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (M < 1 || N < 1 || P < 0) return fail(c, TM_EINVAL, "M, N >= 1 and P >= 0");
+  if (P == 0) return TM_OK;
+  if (!Q || !I || !t || !grad) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  void* Y = ws_get(c, WS_DENSE_Y, (size_t)P * M * sizeof(tm_c32));
+  if (!Y) return fail(c, TM_ENOMEM, "workspace");
+  int r = blas_ready(c, stream);
+  if (r) return r;
+  const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
+  // Y [P][M] = t Q^T: column-major Y (M x P) = Q_cm^T t_cm with Q_cm (N x M), t_cm (N x P)
+  if (rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, M, P, N, &one,
+                    (const rocblas_float_complex*)Q, N, (const rocblas_float_complex*)t, N, &zero,
+                    (rocblas_float_complex*)Y, M) != rocblas_status_success)
+    return fail(c, TM_EHIP, "rocblas_cgemm failed");
+  int e = tmk::launch_dense_pointwise(Y, I, P, M, f, stream);
+  if (e) return hipfail(c, e, "dense pointwise");
+  // conj(grad) [P][N] = Q_cm conj(w): column-major (N x P) = (N x M)(M x P)
+  if (rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_none, N, P, M, &one,
+                    (const rocblas_float_complex*)Q, N, (const rocblas_float_complex*)Y, M, &zero,
+                    (rocblas_float_complex*)grad, N) != rocblas_status_success)
+    return fail(c, TM_EHIP, "rocblas_cgemm failed");
+  e = tmk::launch_conj_inplace(grad, (int64_t)P * N, stream);
+  if (e) return hipfail(c, e, "conjugate");
   return TM_OK;
 }

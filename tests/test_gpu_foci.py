@@ -55,3 +55,19 @@ def test_errors(ctx):
         tm.tm_foci_power_ratio(ctx, T, T, torch.tensor([0, 1, 1], dtype=torch.int32, device=dev()), 4, 4)
     with pytest.raises(tm.TMError, match="outside the grid"):
         tm.tm_foci_power_ratio(ctx, T, T, torch.tensor([0, 1, 16], dtype=torch.int32, device=dev()), 4, 4)
+
+
+@pytest.mark.parametrize("M,N,P", [(64, 16, 5), (1000, 256, 37), (4096, 1024, 9)])
+def test_dense_gradient(ctx, M, N, P):
+    from oracle import operators as ops
+    from oracle import retrieval as rt
+    Q = tm_synth.random_phase_matrix(M, N, tm_synth.rng(997, 0)).astype(np.complex64)
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(997, 1))
+    t0 = (T + 0.3 * tm_synth.tm_iid(P, N, tm_synth.rng(997, 2))).astype(np.complex64)
+    I = (np.abs(T.astype(np.complex64).astype(np.complex128) @ Q.T.astype(np.complex128)) ** 2).astype(np.float32)
+    f_ref, g_ref, _ = rt.intensity_grad(ops.MatrixOp(Q.astype(np.complex128)), I.astype(np.float64),
+                                        t0.astype(np.complex128))
+    g, f = tm.tm_dense_gradient(ctx, c64(Q), torch.from_numpy(I).to(dev()), c64(t0))
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    assert rel(g.cpu().numpy(), g_ref) < 1e-4
+    assert rel(f.cpu().numpy(), f_ref) < 1e-4

@@ -404,3 +404,24 @@ def test_amplitude_lbfgs_monotone_and_recovers():
     f0, g0, y0 = rt.amplitude_grad(op, I, t0)
     a = rt.amplitude_step(I, y0, op.forward(-g0 / (2 * K * N)))
     assert np.allclose(t1, t0 + a[:, None] * (-g0 / (2 * K * N)))
+
+
+def test_matrix_operator_gradient_matches_probing_form():
+    # the dense operator with Q = A reproduces the structured gradient, and
+    # with a random-phase Q its gradient passes central differences
+    masks, t, g = small_problem(4, 4, K=3, P=2, seed=41)
+    d = ops.DenseOp(masks, 4, 4)
+    I = ops.intensities(d, t).reshape(2, -1) * 1.1
+    mo = ops.MatrixOp(d.A)
+    f1, g1, _ = rt.intensity_grad(mo, I, t + 0.2)
+    f2, g2, _ = rt.intensity_grad(d, I.reshape(2, 3, 16), t + 0.2)
+    assert np.allclose(f1, f2, rtol=1e-12) and np.allclose(g1, g2, rtol=1e-11, atol=1e-9)
+    Q = tm_synth.random_phase_matrix(40, 16, tm_synth.rng(41, 7))
+    mq = ops.MatrixOp(Q)
+    Iq = np.abs(mq.forward(t)) ** 2
+    x = t + 0.3
+    f, grad, _ = rt.intensity_grad(mq, Iq, x)
+    v = g.standard_normal(t.shape) + 1j * g.standard_normal(t.shape)
+    fp = rt.intensity_grad(mq, Iq, x + 1e-6 * v)[0]
+    fm = rt.intensity_grad(mq, Iq, x - 1e-6 * v)[0]
+    assert np.max(np.abs((fp - fm) / 2e-6 - rt.rdot(grad, v))) <= 1e-5 * np.max(np.abs(fp))

@@ -117,3 +117,9 @@ def camera_stack(n_img: int, H: int, W: int, radius: float, g: np.random.Generat
     speckle = np.minimum(g.exponential(peak / 4, size=(n_img, H, W)), 65535.0)
     bg = g.poisson(background, size=(n_img, H, W)).astype(np.float64)
     return np.where(inside[None], np.floor(speckle), bg).astype(np.uint16)
+
+
+def random_phase_matrix(M: int, N: int, g: np.random.Generator) -> np.ndarray:
+    """Dense probing matrix with i.i.d. uniform phases, unit modulus [M, N]
+    (the prior-art random-phase probing)."""
+    return np.exp(2j * np.pi * g.random((M, N)))
