@@ -19,10 +19,17 @@ Readings where the paper is silent:
   * The paper's two exposures (a short one for the window, a long one scaled
     by 20 for the background) only extend the camera's range; in simulation
     both sums come from the same image.
+  * The propagated TM at a defocus distance z (Sec. 4, 3-D foci) applies the
+    free-space angular-spectrum propagation of Eq. angularspectrum (pupil
+    NA, same kernel as the phase-correction model) to every column of the TM
+    laid out on the output grid (rows outside the TM's pixels are zero), and
+    keeps every grid pixel: TM_z [g1 g2][N].
 """
 from __future__ import annotations
 
 import numpy as np
+
+from .defocus import pupil_kernel
 
 
 def focus_patterns(tm_est: np.ndarray) -> np.ndarray:
@@ -34,6 +41,19 @@ def focus_intensities(tm_true: np.ndarray, tm_est: np.ndarray) -> np.ndarray:
     """[P foci][P pixels]: |sum_n tm_true[q][n] u_p[n]|^2."""
     E = focus_patterns(tm_est) @ tm_true.T
     return np.abs(E) ** 2
+
+
+def propagate_tm(tm: np.ndarray, pix: np.ndarray, g1: int, g2: int, lam: float, ps: float, NA: float,
+                 z: float) -> np.ndarray:
+    """TM_z [g1 g2][N]: each column on the g1 x g2 grid, propagated by z with
+    the angular-spectrum kernel (fft2, times h, inverse fft2)."""
+    P, N = tm.shape
+    grid = np.zeros((g1 * g2, N), dtype=np.complex128)
+    grid[pix] = tm
+    cols = grid.T.reshape(N, g1, g2)
+    h, _ = pupil_kernel(g1, g2, ps, lam, NA, z)
+    out = np.fft.ifft2(np.fft.fft2(cols, axes=(1, 2)) * h[None], axes=(1, 2))
+    return out.reshape(N, g1 * g2).T.copy()
 
 
 def power_ratio(img: np.ndarray, pix: np.ndarray, g1: int, g2: int, w: int = 3):
@@ -52,7 +72,8 @@ def power_ratio(img: np.ndarray, pix: np.ndarray, g1: int, g2: int, w: int = 3):
 
 
 def foci_power_ratios(tm_true: np.ndarray, tm_est: np.ndarray, pix: np.ndarray, g1: int, g2: int, w: int = 3):
-    """PR [P] and peak [P] of the focus of every retrieved row."""
+    """PR and peak of the focus of every row of tm_est [Pf][N] (the patterns),
+    with images over the rows of tm_true [G][N] at the pixels pix [G]."""
     F = focus_intensities(tm_true, tm_est)
     out = [power_ratio(F[p], pix, g1, g2, w) for p in range(F.shape[0])]
     return np.array([o[0] for o in out]), np.array([o[1] for o in out])

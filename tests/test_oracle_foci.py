@@ -53,3 +53,37 @@ def test_power_ratio_on_a_pixel_subset_by_loops():
     py, px = divmod(peak, g2)
     sig = sum(v for q, v in grid.items() if abs(q // g2 - py) <= 2 and abs(q % g2 - px) <= 2)
     assert abs(pr - sig / img.sum()) < 1e-14 and peak == pix[np.argmax(img)]
+
+
+def _band_limited(g1, g2, N, NA, ps, lam, seed):
+    # columns whose spectrum lies inside the pupil (so propagation is exact)
+    from oracle.defocus import pupil_kernel
+    _, pupil = pupil_kernel(g1, g2, ps, lam, NA, 0.0)
+    g = np.random.default_rng(seed)
+    spec = (g.standard_normal((N, g1, g2)) + 1j * g.standard_normal((N, g1, g2))) * pupil[None]
+    return np.fft.ifft2(spec, axes=(1, 2)).reshape(N, g1 * g2).T.copy()
+
+
+def test_propagation_identities():
+    g1, g2, N, lam, ps, NA = 16, 8, 5, 1.0, 0.5, 0.6
+    cols = _band_limited(g1, g2, N, NA, ps, lam, 7)      # [G][N] on every pixel
+    pix = np.arange(g1 * g2)
+    assert np.allclose(foci.propagate_tm(cols, pix, g1, g2, lam, ps, NA, 0.0), cols, atol=1e-12)
+    a = foci.propagate_tm(cols, pix, g1, g2, lam, ps, NA, 3.0)
+    b = foci.propagate_tm(a, pix, g1, g2, lam, ps, NA, 4.5)
+    assert np.allclose(b, foci.propagate_tm(cols, pix, g1, g2, lam, ps, NA, 7.5), atol=1e-12)
+    assert np.allclose(np.linalg.norm(a, axis=0), np.linalg.norm(cols, axis=0), rtol=1e-12)  # unitary in band
+    back = foci.propagate_tm(a, pix, g1, g2, lam, ps, NA, -3.0)
+    assert np.allclose(back, cols, atol=1e-12)
+
+
+def test_plane_wave_takes_the_angular_spectrum_phase():
+    # a grid plane wave of frequency (u, v) propagates by exp(j 2 pi / lambda sqrt(1 - lambda^2 (u^2 + v^2)) z)
+    g1, g2, lam, ps, NA, z = 16, 16, 1.0, 0.5, 0.9, 2.5
+    k1, k2 = 3, -2
+    y, x = np.mgrid[0:g1, 0:g2]
+    wave = np.exp(2j * np.pi * (k1 * y / g1 + k2 * x / g2)).reshape(-1, 1)
+    out = foci.propagate_tm(wave, np.arange(g1 * g2), g1, g2, lam, ps, NA, z)
+    u, v = k1 / (g1 * ps), k2 / (g2 * ps)
+    phase = np.exp(1j * 2 * np.pi / lam * np.sqrt(1 - lam ** 2 * (u * u + v * v)) * z)
+    assert np.allclose(out, wave * phase, atol=1e-12)
