@@ -417,6 +417,7 @@ def main():
 
     if not args.no_foci:
         out["foci"] = foci_variant(ctx, Tt, t, pixt, grid, P, N)
+        out["foci_3d"] = foci3d_variant(ctx, Tt, t, phi, pixt, grid, (lam, ps, NA), P, N)
     if not args.no_dense and not args.small:
         out["dense_comparator"] = dense_variant(ctx, mk, It, t, n1, n2)
     if not args.no_learned:
@@ -491,6 +492,50 @@ def foci_variant(ctx, Tt, t, pixt, grid, P, N):
     return {"pr_mean": round(float(pr.mean().item()), 4), "pr_mean_true_tm": round(float(pr_ref.mean().item()), 4),
             "frac_peak_on_pixel": round(on_target, 4), "ms": round(ms, 3),
             "gemm_tflops": round(flops / (ms * 1e-3) / 1e12, 1), "window": 7}
+
+
+def foci3d_variant(ctx, Tt, t, phi, pixt, grid, lam_ps_na, P, N, zs=(10.0, 20.0, 40.0)):
+    """3-D foci (Sec. 4): the TM at a plane z for every pixel of the output
+    grid (angular-spectrum propagation of each column), foci there from the
+    retrieved rows with and without the phase-offset correction, images
+    formed by the true TM propagated the same way. The correction is what
+    makes the propagated estimate usable: without it every row carries its
+    own unknown phase."""
+    import torch
+
+    import paper_2302_13524_amd as tm
+
+    G = grid * grid
+    allpix = torch.arange(G, dtype=torch.int32, device=pixt.device)
+    tc = t * torch.exp(1j * phi).to(torch.complex64)[:, None]
+    res = []
+    prop_ms = None
+    for z in zs:
+        optics = (*lam_ps_na, z)
+        Tz = tm.tm_propagate_tm(ctx, Tt, pixt, grid, grid, optics)
+        tcz = tm.tm_propagate_tm(ctx, tc, pixt, grid, grid, optics)
+        tuz = tm.tm_propagate_tm(ctx, t, pixt, grid, grid, optics)
+        if prop_ms is None:
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                tm.tm_propagate_tm(ctx, tc, pixt, grid, grid, optics)
+            e1.record()
+            torch.cuda.synchronize()
+            prop_ms = e0.elapsed_time(e1) / 3
+        # foci aimed at the fiber-core pixels, images over the whole grid
+        tgt = pixt.long()
+        pr_c, pk_c = tm.tm_foci_power_ratio(ctx, Tz, tcz[tgt].contiguous(), allpix, grid, grid, 3)
+        pr_u, _ = tm.tm_foci_power_ratio(ctx, Tz, tuz[tgt].contiguous(), allpix, grid, grid, 3)
+        pr_t, pk_t = tm.tm_foci_power_ratio(ctx, Tz, Tz[tgt].contiguous(), allpix, grid, grid, 3)
+        res.append({"z": z, "pr_mean_corrected": round(float(pr_c.mean().item()), 4),
+                    "pr_mean_uncorrected": round(float(pr_u.mean().item()), 4),
+                    "pr_mean_true_tm": round(float(pr_t.mean().item()), 4),
+                    "frac_peak_on_target_corrected": round(float((pk_c == pixt).float().mean().item()), 4),
+                    "frac_peak_on_target_true_tm": round(float((pk_t == pixt).float().mean().item()), 4)})
+        del Tz, tcz, tuz
+    return {"planes": res, "propagate_ms": round(prop_ms, 3), "grid": [grid, grid], "window": 7}
 
 
 def dense_variant(ctx, mk, It, t, n1, n2):

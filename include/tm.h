@@ -354,19 +354,20 @@ int tm_pre_gather(tm_ctx *ctx, const void *stack, int32_t stack_dtype, int64_t n
                   const int32_t *pix, int32_t P, void *out, int32_t out_dtype, void *stream);
 
 /* ---------------------------------------------------------------------------
- * Validation by foci (Sec. 3): the phase of the conjugate of each retrieved
- * row, u_p = exp(-j arg tm_est[p]) (1 where tm_est is 0), is displayed on the
- * modulator; the focus image is |sum_n tm_true[q][n] u_p[n]|^2 over the TM's
- * pixels q (one complex FP32 GEMM through rocBLAS), and its power ratio is
- * the power in the (2w+1) x (2w+1) grid window around the brightest pixel
- * (first in raster order on ties; the window is clipped at the grid border)
- * over the image's total power (w = 3: the paper's 7 x 7 window).
- *   tm_true, tm_est [P][N] tm_c32 (device); pix [P] int32 distinct raster
- *   indices of the rows' pixels on a g1 x g2 grid (checked on the host);
- *   pr [P] float, peak [P] int32 raster index of each image's peak (-1 and
- *   PR 0 for an image with no power). Workspace P N + P^2 complex floats. */
-int tm_foci_power_ratio(tm_ctx *ctx, int32_t P, int32_t N, const tm_c32 *tm_true, const tm_c32 *tm_est,
-                        const int32_t *pix, int32_t g1, int32_t g2, int32_t w, float *pr, int32_t *peak,
+ * Validation by foci (Sec. 3): the phase of the conjugate of each row of
+ * tm_est, u_p = exp(-j arg tm_est[p]) (1 where tm_est is 0), is displayed on
+ * the modulator; the focus image is |sum_n tm_true[q][n] u_p[n]|^2 over the
+ * rows q of tm_true (one complex FP32 GEMM through rocBLAS), and its power
+ * ratio is the power in the (2w+1) x (2w+1) grid window around the brightest
+ * pixel (first in raster order on ties; the window is clipped at the grid
+ * border) over the image's total power (w = 3: the paper's 7 x 7 window).
+ *   tm_est [Pf][N] tm_c32 (the patterns), tm_true [G][N] tm_c32 (the system,
+ *   one row per image pixel), pix [G] int32 distinct raster indices of those
+ *   pixels on a g1 x g2 grid (checked on the host); pr [Pf] float, peak [Pf]
+ *   int32 raster index of each image's peak (-1 and PR 0 for an image with no
+ *   power). Workspace Pf N + Pf G complex floats. */
+int tm_foci_power_ratio(tm_ctx *ctx, int32_t Pf, int32_t G, int32_t N, const tm_c32 *tm_true, const int32_t *pix,
+                        const tm_c32 *tm_est, int32_t g1, int32_t g2, int32_t w, float *pr, int32_t *peak,
                         void *stream);
 
 /* Comparator without FFTs (Sec. 2.2, Table time): the gradient of
@@ -377,6 +378,17 @@ int tm_foci_power_ratio(tm_ctx *ctx, int32_t P, int32_t N, const tm_c32 *tm_true
  *   f [P] float (may be NULL). Workspace P M complex floats. */
 int tm_dense_gradient(tm_ctx *ctx, int32_t M, int32_t N, int32_t P, const tm_c32 *Q, const float *I,
                       const tm_c32 *t, tm_c32 *grad, float *f, void *stream);
+
+/* Propagated TM (Sec. 4, 3-D foci): every column of tm [P][N], laid out on
+ * the g1 x g2 output grid at the pixels pix [P] (zero elsewhere), propagated
+ * by optics->z with the angular-spectrum kernel of Eq. angularspectrum
+ * (pupil NA, wavelength lambda, grid pixel ps_field):
+ *   out [g1 g2][N] tm_c32 = ifft2(h_z .* fft2(column)) for every column,
+ * i.e. the TM at the plane z for every grid pixel. (g1, g2) must be a
+ * compiled FFT grid (tm_grid_supported); the 2-D FFTs run in the fused row
+ * kernel, one column per row group. Workspace N g1 g2 complex floats. */
+int tm_propagate_tm(tm_ctx *ctx, int32_t P, int32_t N, const tm_c32 *tm, const int32_t *pix, int32_t g1, int32_t g2,
+                    const tm_optics *optics, tm_c32 *out, void *stream);
 
 #ifdef __cplusplus
 }

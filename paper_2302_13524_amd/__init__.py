@@ -32,7 +32,7 @@ EXPORTED = (
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
-    "tm_dense_gradient",
+    "tm_dense_gradient", "tm_propagate_tm",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -135,8 +135,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_pre_energy.argtypes = [vp, vp, i32, i64, i32, i32, vp, vp]
     lib.tm_pre_fiber_mask.argtypes = [vp, vp, i32, dp, vp, ctypes.POINTER(i32), vp]
     lib.tm_pre_gather.argtypes = [vp, vp, i32, i64, i32, i32, vp, i32, vp, i32, vp]
-    lib.tm_foci_power_ratio.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
+    lib.tm_foci_power_ratio.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
     lib.tm_dense_gradient.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.tm_propagate_tm.argtypes = [vp, i32, i32, vp, vp, i32, i32, ctypes.POINTER(tm_optics), vp, vp]
     _lib = lib
     return lib
 
@@ -379,6 +380,17 @@ def tm_pre_gather(ctx: Context, stack, pix, bf16=False):
     return out
 
 
+def tm_propagate_tm(ctx: Context, tm_rows, pix, g1, g2, optics):
+    """TM at the plane optics[3] (= z) for every pixel of the g1 x g2 grid: [g1*g2, N] complex64."""
+    P, N = tm_rows.shape
+    out = torch.empty((g1 * g2, N), dtype=torch.complex64, device=tm_rows.device)
+    op = tm_optics(*[float(v) for v in optics])
+    rc = ctx.lib.tm_propagate_tm(ctx.h, int(P), int(N), _ptr(tm_rows), _ptr(pix), int(g1), int(g2),
+                                 ctypes.byref(op), _ptr(out), _stream(tm_rows.device))
+    ctx.check(rc, "tm_propagate_tm")
+    return out
+
+
 def tm_dense_gradient(ctx: Context, Q, I, t):
     """Gradient -4 Q^H((Q t)(I - |Q t|^2)) and f per row for a dense probing matrix Q [M, N]."""
     M, N = Q.shape
@@ -392,12 +404,14 @@ def tm_dense_gradient(ctx: Context, Q, I, t):
 
 
 def tm_foci_power_ratio(ctx: Context, tm_true, tm_est, pix, g1, g2, w=3):
-    """Power ratio [P] float32 and peak raster index [P] int32 of the conjugate-phase focus of every row."""
-    P, N = tm_true.shape
-    pr = torch.empty((P,), dtype=torch.float32, device=tm_true.device)
-    peak = torch.empty((P,), dtype=torch.int32, device=tm_true.device)
-    rc = ctx.lib.tm_foci_power_ratio(ctx.h, int(P), int(N), _ptr(tm_true), _ptr(tm_est), _ptr(pix), int(g1), int(g2),
-                                     int(w), _ptr(pr), _ptr(peak), _stream(tm_true.device))
+    """Power ratio [Pf] float32 and peak raster index [Pf] int32 of the conjugate-phase focus of every
+    row of tm_est [Pf, N], with images over the rows of tm_true [G, N] at the pixels pix [G]."""
+    G, N = tm_true.shape
+    Pf = tm_est.shape[0]
+    pr = torch.empty((Pf,), dtype=torch.float32, device=tm_true.device)
+    peak = torch.empty((Pf,), dtype=torch.int32, device=tm_true.device)
+    rc = ctx.lib.tm_foci_power_ratio(ctx.h, int(Pf), int(G), int(N), _ptr(tm_true), _ptr(pix), _ptr(tm_est),
+                                     int(g1), int(g2), int(w), _ptr(pr), _ptr(peak), _stream(tm_true.device))
     ctx.check(rc, "tm_foci_power_ratio")
     return pr, peak
 

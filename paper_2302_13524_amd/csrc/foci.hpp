@@ -6,11 +6,11 @@ namespace tmk {
 
 // u[p][n] = exp(-j arg tm_est[p][n]) (1 where tm_est is 0), [P][N] complex float
 int launch_conj_phase(const void* tm_est, void* u, int64_t n, void* stream);
-// For every focus p (row p of E [P][P] complex, E[p][q] = sum_n u[p][n] tm_true[q][n]):
+// For every focus p (row p of E [Pf][G] complex, E[p][q] = sum_n u[p][n] tm_true[q][n]):
 // peak = brightest pixel (first in raster order on ties), PR = power in the
-// (2w+1)^2 grid window around the peak / total power. pix [P] raster indices
+// (2w+1)^2 grid window around the peak / total power. pix [G] raster indices
 // on a g1 x g2 grid.
-int launch_foci_pr(const void* E, int P, const int32_t* pix, int g1, int g2, int w, float* pr, int32_t* peak,
+int launch_foci_pr(const void* E, int Pf, int G, const int32_t* pix, int g1, int g2, int w, float* pr, int32_t* peak,
                    void* stream);
 
 }  // namespace tmk
@@ -21,4 +21,13 @@ namespace tmk {
 // afterwards grad = conj(H) in place.
 int launch_dense_pointwise(void* Y, const float* I, int P, int64_t M, float* f, void* stream);
 int launch_conj_inplace(void* x, int64_t n, void* stream);
+}  // namespace tmk
+
+namespace tmk {
+// Propagated TM helpers: X [N][G] = columns of tm [P][N] on the grid (pix [P], zero elsewhere);
+// H [g1 g2] angular-spectrum kernel; out [G][N] = X^T.
+int launch_cols_to_grid(const void* tm, int P, int N, const int32_t* pix, int G, void* X, void* stream);
+int launch_make_prop_filter(void* H, int g1, int g2, double lam, double ps, double NA, double z, void* stream);
+int launch_fill_c32(void* x, int64_t n, float re, float im, void* stream);
+int launch_grid_to_rows(const void* X, int N, int G, void* out, void* stream);
 }  // namespace tmk

@@ -31,19 +31,19 @@ __global__ void __launch_bounds__(256) k_conj_phase(const float2* t, float2* u, 
 constexpr int FWG = 256;
 
 // one workgroup per focus image (row p of E)
-__global__ void __launch_bounds__(FWG) k_foci_pr(const float2* E, int P, const int32_t* pix, int g2, int w, float* pr,
+__global__ void __launch_bounds__(FWG) k_foci_pr(const float2* E, int G, const int32_t* pix, int g2, int w, float* pr,
                                                 int32_t* peak) {
   __shared__ float bv[FWG / 64];
   __shared__ int bq[FWG / 64];
   __shared__ double red[FWG / 64];
   __shared__ int pk;
   const int p = blockIdx.x;
-  const float2* row = E + (size_t)p * P;
+  const float2* row = E + (size_t)p * G;
   // brightest pixel, ties to the smaller raster index; and the total power
   float best = -1.f;
   int bestq = 0x7fffffff;
   double tot = 0.0;
-  for (int q = threadIdx.x; q < P; q += FWG) {
+  for (int q = threadIdx.x; q < G; q += FWG) {
     const float2 v = row[q];
     const float I = v.x * v.x + v.y * v.y;
     const int r = pix[q];
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(FWG) k_foci_pr(const float2* E, int P, const i
   const int py = pk / g2, px = pk - (pk / g2) * g2;
   __syncthreads();
   double sig = 0.0;
-  for (int q = threadIdx.x; q < P; q += FWG) {
+  for (int q = threadIdx.x; q < G; q += FWG) {
     const int r = pix[q];
     const int y = r / g2, x = r - (r / g2) * g2;
     if (abs(y - py) <= w && abs(x - px) <= w) {
@@ -118,11 +118,11 @@ int launch_conj_phase(const void* tm_est, void* u, int64_t n, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_foci_pr(const void* E, int P, const int32_t* pix, int g1, int g2, int w, float* pr, int32_t* peak,
+int launch_foci_pr(const void* E, int Pf, int G, const int32_t* pix, int g1, int g2, int w, float* pr, int32_t* peak,
                    void* stream) {
   (void)g1;
-  if (P <= 0) return 0;
-  k_foci_pr<<<P, FWG, 0, (hipStream_t)stream>>>((const float2*)E, P, pix, g2, w, pr, peak);
+  if (Pf <= 0) return 0;
+  k_foci_pr<<<Pf, FWG, 0, (hipStream_t)stream>>>((const float2*)E, G, pix, g2, w, pr, peak);
   return (int)hipGetLastError();
 }
 
@@ -169,6 +169,103 @@ int launch_conj_inplace(void* x, int64_t n, void* stream) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   k_conj<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((float2*)x, n);
+  return (int)hipGetLastError();
+}
+
+}  // namespace tmk
+
+// ------------------------------------------------------------ propagated TM
+namespace tmk {
+namespace {
+
+constexpr int TT = 32;  // transpose tiles of 32 x 32 complex values, 256 threads (8 rows per pass)
+
+// X[n][pix[p]] = tm[p][n]: tiles of 32 rows p x 32 columns n
+__global__ void __launch_bounds__(256) k_cols_to_grid(const float2* tm, int P, int N, const int32_t* pix, int G,
+                                                     float2* X) {
+  __shared__ float2 tile[TT][TT + 1];
+  const int n0 = blockIdx.x * TT, p0 = blockIdx.y * TT;
+  const int tx = threadIdx.x & (TT - 1), ty = threadIdx.x / TT;
+  for (int r = ty; r < TT; r += 256 / TT) {
+    const int p = p0 + r, n = n0 + tx;
+    tile[r][tx] = (p < P && n < N) ? tm[(size_t)p * N + n] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int r = ty; r < TT; r += 256 / TT) {
+    const int n = n0 + r, p = p0 + tx;
+    if (n < N && p < P) X[(size_t)n * G + pix[p]] = tile[tx][r];
+  }
+}
+
+// out[q][n] = X[n][q]
+__global__ void __launch_bounds__(256) k_grid_to_rows(const float2* X, int N, int G, float2* out) {
+  __shared__ float2 tile[TT][TT + 1];
+  const int q0 = blockIdx.x * TT, n0 = blockIdx.y * TT;
+  const int tx = threadIdx.x & (TT - 1), ty = threadIdx.x / TT;
+  for (int r = ty; r < TT; r += 256 / TT) {
+    const int n = n0 + r, q = q0 + tx;
+    tile[r][tx] = (n < N && q < G) ? X[(size_t)n * G + q] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int r = ty; r < TT; r += 256 / TT) {
+    const int q = q0 + r, n = n0 + tx;
+    if (q < G && n < N) out[(size_t)q * N + n] = tile[tx][r];
+  }
+}
+
+__device__ __forceinline__ double sfreq(int k, int n, double ps) {
+  const int s = (k < (n + 1) / 2) ? k : k - n;
+  return (double)s / ((double)n * ps);
+}
+
+// H[k1 g2 + k2] = exp(j 2 pi / lambda sqrt(1 - lambda^2 (u^2 + v^2)) z) inside the pupil, 0 outside
+__global__ void __launch_bounds__(256) k_prop_filter(float2* H, int g1, int g2, double lam, double ps, double NA,
+                                                    double z) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= g1 * g2) return;
+  const int k1 = i / g2, k2 = i - (i / g2) * g2;
+  const double u = sfreq(k1, g1, ps), v = sfreq(k2, g2, ps);
+  const double rho2 = (lam * u) * (lam * u) + (lam * v) * (lam * v);
+  float2 h = make_float2(0.f, 0.f);
+  if (sqrt(rho2) <= NA) {
+    const double ph = 2.0 * M_PI / lam * sqrt(1.0 - rho2) * z;
+    h = make_float2((float)cos(ph), (float)sin(ph));
+  }
+  H[i] = h;
+}
+
+__global__ void __launch_bounds__(256) k_fill_c32(float2* x, int64_t n, float re, float im) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) x[i] = make_float2(re, im);
+}
+
+}  // namespace
+
+int launch_cols_to_grid(const void* tm, int P, int N, const int32_t* pix, int G, void* X, void* stream) {
+  if (P <= 0 || N <= 0) return 0;
+  dim3 g((N + TT - 1) / TT, (P + TT - 1) / TT);
+  k_cols_to_grid<<<g, 256, 0, (hipStream_t)stream>>>((const float2*)tm, P, N, pix, G, (float2*)X);
+  return (int)hipGetLastError();
+}
+
+int launch_grid_to_rows(const void* X, int N, int G, void* out, void* stream) {
+  if (N <= 0 || G <= 0) return 0;
+  dim3 g((G + TT - 1) / TT, (N + TT - 1) / TT);
+  k_grid_to_rows<<<g, 256, 0, (hipStream_t)stream>>>((const float2*)X, N, G, (float2*)out);
+  return (int)hipGetLastError();
+}
+
+int launch_make_prop_filter(void* H, int g1, int g2, double lam, double ps, double NA, double z, void* stream) {
+  k_prop_filter<<<(g1 * g2 + 255) / 256, 256, 0, (hipStream_t)stream>>>((float2*)H, g1, g2, lam, ps, NA, z);
+  return (int)hipGetLastError();
+}
+
+int launch_fill_c32(void* x, int64_t n, float re, float im, void* stream) {
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_fill_c32<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((float2*)x, n, re, im);
   return (int)hipGetLastError();
 }
 

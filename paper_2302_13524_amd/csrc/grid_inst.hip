@@ -38,6 +38,7 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
       else row_kernel<PLg, M_AGRAD, IT, false><<<grid, block, 0, s>>>(a);
       break;
     case M_ALS: row_kernel<PLg, M_ALS, IT><<<grid, block, 0, s>>>(a); break;
+    case M_FILT: row_kernel<PLg, M_FILT, IT><<<grid, block, 0, s>>>(a); break;
     case M_BACKPROP: row_kernel<PLg, M_BACKPROP, IT><<<grid, block, 0, s>>>(a); break;
     case M_RES64: {
       using LD = Launch<PLd>;

@@ -17,7 +17,8 @@ enum Mode : int {
   M_RES64 = 7,       // FP64 residual: sums64 {sum r^2, sum I^2}
   M_BACKPROP = 8,    // x = A^H sqrt(I) / (K N)                     -> tout
   M_AGRAD = 9,       // g = -2 A^H((sqrt(I) - |y|) y/|y|)           -> tout, sums {f_a}
-  M_ALS = 10         // amplitude cost at t + a_j d, a_j = 2^(j-3), j < 8 -> sums {f_a(t), f_a(t + a_j d)}
+  M_ALS = 10,        // amplitude cost at t + a_j d, a_j = 2^(j-3), j < 8 -> sums {f_a(t), f_a(t + a_j d)}
+  M_FILT = 11        // x = A^H(H .* A t) / (K N), H = yin [N] in natural frequency order -> tout
 };
 
 constexpr int NSUM = 9;
@@ -341,6 +342,11 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       }
       continue;
     } else {
+      if constexpr (MODE == M_FILT) {
+        // multiply the spectrum by the filter (read at each slot's natural frequency)
+#pragma unroll
+        for (int i = 0; i < E; ++i) x[i] = cmul(x[i], gload(a.yin + KL(i)));
+      }
       if constexpr (MODE == M_ER || MODE == M_GRAD || MODE == M_SPEC || MODE == M_AGRAD) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -442,7 +448,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
     }
   } else {
     float scale = 1.f;
-    if constexpr (MODE == M_ER || MODE == M_BACKPROP) scale = 1.f / (float)(a.K * N);
+    if constexpr (MODE == M_ER || MODE == M_BACKPROP || MODE == M_FILT) scale = 1.f / (float)(a.K * N);
     if constexpr (MODE == M_GRAD) scale = -4.f;
     if (valid) {
 #pragma unroll

@@ -107,7 +107,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
   WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_PRE_PART,
-  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E, WS_DENSE_Y,
+  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E, WS_DENSE_Y, WS_PROP_X, WS_PROP_H, WS_PROP_ONES,
   WS_PH_BASE = 100
 };
 
@@ -1147,41 +1147,41 @@ extern "C" int tm_pre_gather(tm_ctx* c, const void* stack, int32_t stack_dtype, 
 }
 
 // ------------------------------------------------------------ foci and power ratio
-extern "C" int tm_foci_power_ratio(tm_ctx* c, int32_t P, int32_t N, const tm_c32* tm_true, const tm_c32* tm_est,
-                                   const int32_t* pix, int32_t g1, int32_t g2, int32_t w, float* pr, int32_t* peak,
-                                   void* stream) {
+static int blas_ready(tm_ctx* c, void* stream);
+
+extern "C" int tm_foci_power_ratio(tm_ctx* c, int32_t Pf, int32_t G, int32_t N, const tm_c32* tm_true,
+                                   const int32_t* pix, const tm_c32* tm_est, int32_t g1, int32_t g2, int32_t w,
+                                   float* pr, int32_t* peak, void* stream) {
   if (!c) return TM_EINVAL;
-  if (P < 0 || N < 1 || g1 < 1 || g2 < 1 || w < 0) return fail(c, TM_EINVAL, "P >= 0, N >= 1, grid >= 1, w >= 0");
-  if (P == 0) return TM_OK;
+  if (Pf < 0 || G < 1 || N < 1 || g1 < 1 || g2 < 1 || w < 0)
+    return fail(c, TM_EINVAL, "Pf >= 0, G >= 1, N >= 1, grid >= 1, w >= 0");
+  if (Pf == 0) return TM_OK;
   if (!tm_true || !tm_est || !pix || !pr || !peak) return fail(c, TM_EINVAL, "null pointer argument");
-  if ((int64_t)P > (int64_t)g1 * g2) return fail(c, TM_EINVAL, "P=%d exceeds the %dx%d grid", P, g1, g2);
+  if ((int64_t)G > (int64_t)g1 * g2) return fail(c, TM_EINVAL, "G=%d exceeds the %dx%d grid", G, g1, g2);
   HIPCHK(c, hipSetDevice(c->device));
-  std::vector<int32_t> hp(P);
-  if (hipMemcpy(hp.data(), pix, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+  std::vector<int32_t> hp(G);
+  if (hipMemcpy(hp.data(), pix, (size_t)G * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(c, TM_EHIP, "reading pix");
   std::vector<char> seen((size_t)g1 * g2, 0);
-  for (int i = 0; i < P; ++i) {
+  for (int i = 0; i < G; ++i) {
     if (hp[i] < 0 || hp[i] >= g1 * g2) return fail(c, TM_EINVAL, "pix[%d]=%d outside the grid", i, hp[i]);
     if (seen[hp[i]]) return fail(c, TM_EINVAL, "pix[%d]=%d repeats a pixel", i, hp[i]);
     seen[hp[i]] = 1;
   }
-  void* u = ws_get(c, WS_FOCI_U, (size_t)P * N * sizeof(tm_c32));
-  void* E = ws_get(c, WS_FOCI_E, (size_t)P * P * sizeof(tm_c32));
+  void* u = ws_get(c, WS_FOCI_U, (size_t)Pf * N * sizeof(tm_c32));
+  void* E = ws_get(c, WS_FOCI_E, (size_t)Pf * G * sizeof(tm_c32));
   if (!u || !E) return fail(c, TM_ENOMEM, "workspace");
-  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
-    c->blas = nullptr;
-    return fail(c, TM_EHIP, "rocblas_create_handle failed");
-  }
-  int e = tmk::launch_conj_phase(tm_est, u, (int64_t)P * N, stream);
+  int r = blas_ready(c, stream);
+  if (r) return r;
+  int e = tmk::launch_conj_phase(tm_est, u, (int64_t)Pf * N, stream);
   if (e) return hipfail(c, e, "conjugate phase");
-  // E[p][q] = sum_n u[p][n] tm_true[q][n]: in column-major terms E^T = T^T U with T, U stored N x P
+  // E[p][q] = sum_n u[p][n] tm_true[q][n]: in column-major terms E^T = T^T U with T (N x G), U (N x Pf)
   const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
-  if (rocblas_set_stream(c->blas, (hipStream_t)stream) != rocblas_status_success ||
-      rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, P, P, N, &one,
+  if (rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, G, Pf, N, &one,
                     (const rocblas_float_complex*)tm_true, N, (const rocblas_float_complex*)u, N, &zero,
-                    (rocblas_float_complex*)E, P) != rocblas_status_success)
+                    (rocblas_float_complex*)E, G) != rocblas_status_success)
     return fail(c, TM_EHIP, "rocblas_cgemm failed");
-  e = tmk::launch_foci_pr(E, P, pix, g1, g2, w, pr, peak, stream);
+  e = tmk::launch_foci_pr(E, Pf, G, pix, g1, g2, w, pr, peak, stream);
   if (e) return hipfail(c, e, "power ratio");
   return TM_OK;
 }
@@ -1223,5 +1223,51 @@ extern "C" int tm_dense_gradient(tm_ctx* c, int32_t M, int32_t N, int32_t P, con
     return fail(c, TM_EHIP, "rocblas_cgemm failed");
   e = tmk::launch_conj_inplace(grad, (int64_t)P * N, stream);
   if (e) return hipfail(c, e, "conjugate");
+  return TM_OK;
+}
+
+// ------------------------------------------------------------ propagated TM
+extern "C" int tm_propagate_tm(tm_ctx* c, int32_t P, int32_t N, const tm_c32* tm, const int32_t* pix, int32_t g1,
+                               int32_t g2, const tm_optics* o, tm_c32* out, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (P < 0 || N < 1) return fail(c, TM_EINVAL, "P >= 0 and N >= 1");
+  if (!o || !out || (P > 0 && (!tm || !pix))) return fail(c, TM_EINVAL, "null pointer argument");
+  if (!(o->lambda > 0) || !(o->ps_field > 0) || !(o->NA > 0) || !std::isfinite(o->z))
+    return fail(c, TM_EINVAL, "optics: lambda, ps_field, NA > 0 and finite z");
+  tmk::row_launcher fn;
+  tm_dims gd{g1, g2, 1, N};  // the grid's 2-D FFT is the row kernel's, one "row" per TM column
+  int r = check_dims(c, gd, &fn);
+  if (r) return r;
+  const int G = g1 * g2;
+  if (P > G) return fail(c, TM_EINVAL, "P=%d exceeds the %dx%d grid", P, g1, g2);
+  HIPCHK(c, hipSetDevice(c->device));
+  if (P > 0) {
+    std::vector<int32_t> hp(P);
+    if (hipMemcpy(hp.data(), pix, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, TM_EHIP, "reading pix");
+    std::vector<char> seen((size_t)G, 0);
+    for (int i = 0; i < P; ++i) {
+      if (hp[i] < 0 || hp[i] >= G) return fail(c, TM_EINVAL, "pix[%d]=%d outside the grid", i, hp[i]);
+      if (seen[hp[i]]) return fail(c, TM_EINVAL, "pix[%d]=%d repeats a pixel", i, hp[i]);
+      seen[hp[i]] = 1;
+    }
+  }
+  void* X = ws_get(c, WS_PROP_X, (size_t)N * G * sizeof(tm_c32));
+  void* H = ws_get(c, WS_PROP_H, (size_t)G * sizeof(tm_c32));
+  void* ones = ws_get(c, WS_PROP_ONES, (size_t)G * sizeof(tm_c32));
+  if (!X || !H || !ones) return fail(c, TM_ENOMEM, "workspace");
+  int e = tmk::launch_fill_c32(X, (int64_t)N * G, 0.f, 0.f, stream);
+  if (!e) e = tmk::launch_fill_c32(ones, G, 1.f, 0.f, stream);
+  if (!e) e = tmk::launch_cols_to_grid(tm, P, N, pix, G, X, stream);
+  if (!e) e = tmk::launch_make_prop_filter(H, g1, g2, o->lambda, o->ps_field, o->NA, o->z, stream);
+  if (e) return hipfail(c, e, "propagation setup");
+  tmk::RowArgs a = base_args(c, gd, (const tm_c32*)ones);
+  a.tin = (const tmk::cx<float>*)X;
+  a.tout = (tmk::cx<float>*)X;
+  a.yin = (const tmk::cx<float>*)H;
+  r = run_row(c, fn, tmk::M_FILT, 0, a, stream);
+  if (r) return r;
+  e = tmk::launch_grid_to_rows(X, N, G, out, stream);
+  if (e) return hipfail(c, e, "transpose");
   return TM_OK;
 }
