@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--phase-auto", type=int, default=1,
                     help="1: use the smallest count (multiple of 10) whose offset spread is within 1%% of the "
                          "reference, found by an untimed run")
+    ap.add_argument("--phase-m", type=int, default=5, help="L-BFGS memory of the phase solve")
     ap.add_argument("--phase-ftol", type=float, default=0.0,
                     help="stop the phase solve after an accepted iteration lowering g by <= ftol * g")
     ap.add_argument("--max-iters", type=int, default=300)
@@ -259,7 +260,7 @@ def main():
 
     def spread_of(iters):
         phi = torch.zeros(P, dtype=torch.float64, device=dev)
-        tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=iters, m=5, ftol=args.phase_ftol)
+        tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=iters, m=args.phase_m, ftol=args.phase_ftol)
         z = torch.exp(1j * (off_t - phi)[good0])
         return float(torch.sqrt(-2 * torch.log(torch.abs(z.mean()) + 1e-300)).item())
 
@@ -294,7 +295,7 @@ def main():
         phi = None
         if phase:
             phi = torch.zeros(P, dtype=torch.float64, device=dev)
-            tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=n_ph, m=5,
+            tm.tm_phase_offset_correct(ctx, pixt, t, th, Idt, optics, phi, nf, nf, iters=n_ph, m=args.phase_m,
                                        ftol=args.phase_ftol)
         return t, raw, phi
 
@@ -395,7 +396,8 @@ def main():
                    "start": f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
                             f"(c {args.spectral_momentum}, interval [{args.spectral_lower}, c] lambda)",
                    "solver": f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction",
-                   "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_ftol": args.phase_ftol},
+                   "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_m": args.phase_m,
+                   "phase_ftol": args.phase_ftol},
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
         "roofline_" + other: roofs[other]["alu"],

@@ -242,6 +242,18 @@ int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_
                             const tm_optics *optics, double *phi, const tm_phase_opts *opts,
                             double *g_out, void *stream);
 
+/* Evaluation path of the defocus model in tm_phase_objective and
+ * tm_phase_offset_correct. h (Eq. angularspectrum) vanishes outside the
+ * pupil, so the model only involves the spectrum bins of the pupil's
+ * bounding box. enable = 1 (the default): when that box is at most 16 x 16
+ * bins, the transforms are pruned to it (one pass builds the box spectrum
+ * and its image-axis-2 transform, one pass over the image rows forms a_n,
+ * the residual and the adjoint's first axis, one pass maps back to the
+ * pixels); otherwise, and with enable = 0, every transform is a full FFT
+ * over the field and image grids. Both compute the same objective and
+ * gradient up to rounding. */
+int tm_phase_set_band(tm_ctx *ctx, int32_t enable);
+
 /* Objective and gradient of the phase-offset problem at phi (FP64):
  *   g_dev [1] double, grad [P] double (both device). */
 int tm_phase_objective(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,

@@ -32,7 +32,7 @@ EXPORTED = (
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
-    "tm_dense_gradient", "tm_propagate_tm",
+    "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop"}
@@ -130,6 +130,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_batch_destroy.argtypes = [vp]
     lib.tm_tune_time.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
     lib.tm_set_variant.argtypes = [vp, i32, i32, i32]
+    lib.tm_phase_set_band.argtypes = [vp, i32]
     lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
     i64 = ctypes.c_int64
     lib.tm_pre_energy.argtypes = [vp, vp, i32, i64, i32, i32, vp, vp]
@@ -553,6 +554,11 @@ def tm_tune_time(ctx: Context, n1, n2, K, P, variant, bf16=False, reps=5) -> flo
     ctx.check(ctx.lib.tm_tune_time(ctx.h, n1, n2, K, P, TM_BF16 if bf16 else TM_F32, variant, reps,
                                    ctypes.byref(us)), "tm_tune_time")
     return us.value
+
+
+def tm_phase_set_band(ctx: Context, enable: bool):
+    """Pupil-band (pruned) evaluation of the defocus model when the pupil's box is small (default on)."""
+    ctx.check(ctx.lib.tm_phase_set_band(ctx.h, 1 if enable else 0), "tm_phase_set_band")
 
 
 def tm_set_variant(ctx: Context, n1, n2, variant):

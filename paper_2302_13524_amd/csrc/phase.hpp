@@ -12,6 +12,17 @@ struct PhaseOptics {
   double lambda, ps, NA, z;
 };
 
+// Pupil band: h vanishes outside the pupil, so only the spectrum bins with
+// signed frequencies s1 in [s1lo, s1lo + B1), s2 in [s2lo, s2lo + B2) carry
+// the field through the model. When the box is small (B1, B2 <= 16) the
+// evaluation uses pruned transforms over the box instead of full line FFTs.
+struct PhaseBand {
+  int on;                  // 1: band evaluation, 0: full separable FFTs
+  int s1lo, B1, s2lo, B2;  // the box
+  int RA, CH;              // field rows per workgroup of the spectrum pass, their blocks (CH RA = nf1)
+  int G, CPW, NXB;         // image pass: threads per column, columns per workgroup, column blocks
+};
+
 // Device workspace for one problem (all device pointers).
 struct PhaseWork {
   double* c;      // [Nd][P] complex (2 doubles)  c_n = TM_est e^{j theta_n}
@@ -23,9 +34,17 @@ struct PhaseWork {
   double* gval;   // [1] objective
   int32_t* inv;   // [nf1 nf2] row index of each field pixel, -1 outside the rows
   int* skip;      // [1] set to 1 when the L-BFGS solve has ended: evaluation kernels return at once
+  double* Sp;     // band: [Nd][CH][16][16] complex, box spectrum partials per block of field rows
+  double* U;      // band: [Nd][16][2nf2] complex, adjoint after its image-axis-1 transform
+  double* V;      // band: [Nd][16][16] complex, adjoint box spectrum times conj(h)
+  double* Wn;     // band: [Nd][P] complex, conj(c_n) (A_n^H a_n r_n) at the pixels
+  PhaseBand band; // host-side plan
 };
 
 size_t phase_work_bytes(const PhaseDims& d);
+// Band plan for these optics (host computation of the pupil's support);
+// enable = 0 forces the full separable path.
+PhaseBand phase_band_plan(const PhaseDims& d, const PhaseOptics& o, int enable);
 void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w);
 
 // c = theta * tm_est^T and the kernel table h. Returns hipError_t.

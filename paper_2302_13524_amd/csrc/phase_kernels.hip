@@ -10,6 +10,9 @@
 // with the pointwise steps between them.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
+#include <cmath>
 #include <stdint.h>
 
 #include "phase.hpp"
@@ -506,6 +509,344 @@ __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, cons
   }
 }
 
+
+// ---- pupil-band evaluation
+// The same model and adjoint with the transforms pruned to the box of
+// spectrum bins where h can be nonzero (signed frequencies s1 in
+// [s1lo, s1lo + B1), s2 in [s2lo, s2lo + B2)). Five passes, each spread over
+// many workgroups (the work per evaluation is small, so the passes are
+// bound by latency, not by arithmetic):
+//   band_spec (image x block of field rows): DFT of the field rows at the B2
+//     box frequencies, then along axis 1 at the B1 box frequencies over the
+//     block's rows: partial box spectra Sp[n][chunk][i1][i2]
+//   band_img (image x block of image rows x column chunk): S = sum of the
+//     partials, H = S h, the column's T[i1] = sum_i2 H[i1][i2] e^{+2 pi j s2 x2 / 2nf2};
+//     for each row a = sum_i1 T[i1] e^{+2 pi j s1 x1 / 2nf1}, r = I - |a|^2
+//     (objective partials) and the adjoint along axis 1,
+//     U[i1][x2] = sum_x1 a r e^{-2 pi j s1 x1 / 2nf1}, per row block
+//   band_v (image x box row i1): sum of the row blocks, DFT along axis 2 at
+//     the box frequencies, times conj(h): V[n][i1][i2]
+//   band_pix (image x block of pixels): inverse DFTs back to the field
+//     pixels, times conj(c_n): Wn[n][p]
+//   band_gather: w_p = sum_n Wn[n][p], gradient -4 Im(conj(u_p) w_p), objective
+// Unitary scales as in the separable path: 1/(2 nf1 nf2) for the forward
+// chain and for the adjoint chain.
+constexpr int BM = 16;           // largest box side
+
+__device__ __forceinline__ z2 zfma(z2 a, z2 b, z2 acc) {  // acc + a b
+  return {acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ z2 zfmac(z2 a, z2 b, z2 acc) {  // acc + a conj(b)
+  return {acc.x + a.x * b.x + a.y * b.y, acc.y + a.y * b.x - a.x * b.y};
+}
+__device__ __forceinline__ z2 zadd(z2 a, z2 b) { return {a.x + b.x, a.y + b.y}; }
+
+// e^{-2 pi j m / L} of the table of length L (power of two) into LDS
+__device__ __forceinline__ void load_tab(z2* dst, const double* tw64, int L, int nt) {
+  const z2* tw = (const z2*)tw64 + (L - 1);
+  for (int t = threadIdx.x; t < L; t += nt) dst[t] = tw[t];
+}
+
+__global__ void __launch_bounds__(256) k_band_spec(double* Sp, const double* c, const double* phi,
+                                                   const int32_t* inv, PhaseBand b, int P, int nf1, int nf2,
+                                                   const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 F[512];
+  __shared__ z2 S1[512];
+  __shared__ z2 tw1[256], tw2[256];
+  const int ch = blockIdx.x, n = blockIdx.y, a0 = ch * b.RA;
+  const int ne = b.RA * nf2;  // <= 512 field values
+  // the block's field values: pixel rows first (two per thread, loads issued together)
+  int pp[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int t = threadIdx.x + k * 256;
+    pp[k] = (t < ne) ? inv[(size_t)a0 * nf2 + t] : -1;
+  }
+  load_tab(tw1, tw64, nf1, 256);
+  load_tab(tw2, tw64, nf2, 256);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int t = threadIdx.x + k * 256;
+    z2 v{0.0, 0.0};
+    if (pp[k] >= 0) {
+      double sn, cs;
+      sincos(phi[pp[k]], &sn, &cs);
+      v = zmul(ldz(c, (size_t)n * P + pp[k]), z2{cs, sn});
+    }
+    if (t < ne) F[t] = v;
+  }
+  __syncthreads();
+  // S1[r][i2] = sum_b F[r][b] e^{-2 pi j s2 b / nf2}; the terms of one output split over q threads
+  const int nout = b.RA * b.B2;
+  int q = 1;
+  while (q < 16 && nout * q * 2 <= 256) q *= 2;
+  {
+    const int o = threadIdx.x / q, part = threadIdx.x - o * q;
+    z2 acc{0.0, 0.0};
+    if (o < nout) {
+      const int r = o / b.B2, j2 = o - r * b.B2;
+      const int sm = (b.s2lo + j2) & (nf2 - 1);
+      const z2* fr = F + r * nf2;
+#pragma unroll 4
+      for (int bb = part; bb < nf2; bb += q) acc = zfma(fr[bb], tw2[(sm * bb) & (nf2 - 1)], acc);
+    }
+    for (int off = 1; off < q; off <<= 1) {  // q consecutive lanes of one wave
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (o < nout && part == 0) S1[o] = acc;
+  }
+  __syncthreads();
+  // partial box spectrum over this block's rows
+  for (int t = threadIdx.x; t < b.B1 * b.B2; t += 256) {
+    const int i1 = t / b.B2, i2 = t - i1 * b.B2;
+    const int sm = (b.s1lo + i1) & (nf1 - 1);
+    z2 acc{0.0, 0.0};
+    for (int r = 0; r < b.RA; ++r) acc = zfma(S1[r * b.B2 + i2], tw1[(sm * (a0 + r)) & (nf1 - 1)], acc);
+    stz(Sp, ((size_t)n * b.CH + ch) * (BM * BM) + i1 * BM + i2, acc);
+  }
+}
+
+// cos and sin of 2 pi m / 16, m < 8
+__device__ constexpr double c16(int m) {
+  return m == 0 ? 1.0 : m == 1 ? 0.92387953251128674 : m == 2 ? 0.70710678118654757 : m == 3 ? 0.38268343236508978
+         : m == 4 ? 0.0 : m == 5 ? -0.38268343236508978 : m == 6 ? -0.70710678118654757 : -0.92387953251128674;
+}
+__device__ constexpr double s16(int m) { return c16(m < 4 ? 4 - m : m - 4); }
+__device__ constexpr int bitrev_n(int i, int n) {
+  int r = 0;
+  for (int b = 1; b < n; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register DFT of length N (4, 8 or 16): x_k <- sum_j x_j e^{SIGN 2 pi i j k / N},
+// radix-2 decimation in time with compile-time indices and twiddles.
+template <int N, int SIGN>
+__device__ __forceinline__ void reg_dft(z2* x) {
+  z2 y[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) y[bitrev_n(i, N)] = x[i];
+#pragma unroll
+  for (int half = 1; half < N; half <<= 1) {
+#pragma unroll
+    for (int g = 0; g < N; g += 2 * half) {
+#pragma unroll
+      for (int k = 0; k < half; ++k) {
+        const int m = k * (16 / (2 * half));  // W_{2 half}^k = e^{SIGN 2 pi i m / 16}
+        const z2 v = y[g + k + half];
+        z2 t;
+        if (m == 0) t = v;
+        else if (m == 4) t = (SIGN > 0) ? z2{-v.y, v.x} : z2{v.y, -v.x};
+        else t = zmul(v, z2{c16(m), SIGN * s16(m)});
+        y[g + k + half] = z2{y[g + k].x - t.x, y[g + k].y - t.y};
+        y[g + k] = z2{y[g + k].x + t.x, y[g + k].y + t.y};
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = y[i];
+}
+
+// Image pass. Rows x1 = G k + l (k < BT1) of one column belong to thread l of
+// the column's G = 2nf1 / BT1 threads. With box row j at signed frequency
+// s1lo + j and e^{2 pi i j x1 / 2nf1} = e^{2 pi i j k / BT1} e^{2 pi i j l / 2nf1},
+//   a[G k + l] = e^{2 pi i s1lo x1 / 2nf1} A_k,
+//   A = DFT+_BT1 (T[j] e^{2 pi i j l / 2nf1}),
+// so |a|^2 = |A_k|^2, and the adjoint's first axis,
+// sum_x1 a r e^{-2 pi i (s1lo + j) x1 / 2nf1}, is per thread
+// e^{-2 pi i j l / 2nf1} DFT-_BT1 (A r)[j] (the phase factor cancels). The G
+// threads of a column then add their parts: the workgroup writes whole
+// columns of U. A length-BT1 DFT per BT1 pixels replaces BT1 terms per pixel.
+// BT1: the box's axis-1 side padded to 4, 8 or 16 (rows beyond B1 are zero).
+template <int BT1>
+__global__ void __launch_bounds__(256) k_band_img(double* U, double* gpart, const double* Sp, const float* Id,
+                                                  const double* h, PhaseBand b, int nf1, int nf2,
+                                                  const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 H[BM * BM];
+  __shared__ z2 twl1[512], twl2[512];
+  __shared__ z2 TC[BM * 256];  // box rows of the image-axis-2 transform, [j][column of the workgroup]
+  __shared__ double wred[4];
+  z2* stage = TC;              // reused for the adjoint partials, [j][l][column]
+  const int L1 = 2 * nf1, L2 = 2 * nf2, G = b.G, CPW = b.CPW;
+  const int n = blockIdx.y;
+  const int cl = threadIdx.x % CPW, l = threadIdx.x / CPW;
+  const int col = blockIdx.x * CPW + cl;
+  const bool colok = col < L2;
+  // this thread's measured pixels, loaded first
+  float idv[BT1];
+#pragma unroll
+  for (int k = 0; k < BT1; ++k) idv[k] = colok ? Id[((size_t)n * L1 + G * k + l) * L2 + col] : 0.f;
+  load_tab(twl1, tw64, L1, 256);
+  load_tab(twl2, tw64, L2, 256);
+  // box spectrum (sum of the row-block partials) times h and the forward scale
+  const double sc = 1.0 / (2.0 * (double)nf1 * (double)nf2);
+  for (int t = threadIdx.x; t < BT1 * BM; t += 256) {
+    const int i1 = t / BM, i2 = t % BM;
+    z2 v{0.0, 0.0};
+    if (i1 < b.B1 && i2 < b.B2) {
+      const int k1 = (b.s1lo + i1) & (nf1 - 1), k2 = (b.s2lo + i2) & (nf2 - 1);
+      const z2 hv = ldz(h, (size_t)k1 * nf2 + k2);
+      const double* sp = Sp + ((size_t)n * b.CH * (BM * BM) + i1 * BM + i2) * 2;
+      z2 acc{0.0, 0.0};
+#pragma unroll 8
+      for (int k = 0; k < b.CH; ++k) acc = zadd(acc, z2{sp[(size_t)k * BM * BM * 2], sp[(size_t)k * BM * BM * 2 + 1]});
+      v = zmul(acc, hv);
+      v = z2{v.x * sc, v.y * sc};
+    }
+    H[t] = v;
+  }
+  __syncthreads();
+  // T[j][col] = sum_i2 H[j][i2] e^{+2 pi i s2 col / L2}: the column's threads share the rows j
+  for (int j = l; j < BT1; j += G) {
+    z2 acc{0.0, 0.0};
+    if (colok)
+      for (int i2 = 0; i2 < b.B2; ++i2) {
+        const int sm = (b.s2lo + i2) & (L2 - 1);
+        acc = zfmac(H[j * BM + i2], twl2[(sm * col) & (L2 - 1)], acc);
+      }
+    TC[j * CPW + cl] = acc;
+  }
+  __syncthreads();
+  z2 x[BT1];
+#pragma unroll
+  for (int j = 0; j < BT1; ++j) x[j] = zmulc(TC[j * CPW + cl], twl1[(j * l) & (L1 - 1)]);  // e^{+2 pi i j l / L1}
+  reg_dft<BT1, 1>(x);
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < BT1; ++k) {
+    const double res = colok ? (double)idv[k] - (x[k].x * x[k].x + x[k].y * x[k].y) : 0.0;
+    acc += res * res;
+    x[k] = z2{x[k].x * res, x[k].y * res};
+  }
+  reg_dft<BT1, -1>(x);
+  // objective partial of this workgroup
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = acc;
+  __syncthreads();  // also: every thread has read TC
+  if (threadIdx.x == 0) gpart[(size_t)n * gridDim.x + blockIdx.x] = (wred[0] + wred[1]) + (wred[2] + wred[3]);
+#pragma unroll
+  for (int j = 0; j < BT1; ++j)
+    stage[(j * G + l) * CPW + cl] = zmul(x[j], twl1[(j * l) & (L1 - 1)]);  // e^{-2 pi i j l / L1}
+  __syncthreads();
+  for (int o = threadIdx.x; o < b.B1 * CPW; o += 256) {
+    const int j = o / CPW, c2 = o - (o / CPW) * CPW, cc = blockIdx.x * CPW + c2;
+    if (cc < L2) {
+      z2 sacc{0.0, 0.0};
+      for (int q = 0; q < G; ++q) sacc = zadd(sacc, stage[(j * G + q) * CPW + c2]);
+      stz(U, ((size_t)n * BM + j) * L2 + cc, sacc);
+    }
+  }
+}
+
+// V[n][i1][i2] = conj(h) sc sum_x2 U[n][i1][x2] e^{-2 pi j s2 x2 / 2nf2}
+__global__ void __launch_bounds__(256) k_band_v(double* Vb, const double* U, const double* h, PhaseBand b, int nf1,
+                                                int nf2, const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 ul[512];
+  __shared__ z2 twl2[512];
+  const int i1 = blockIdx.x, n = blockIdx.y, L2 = 2 * nf2;
+  load_tab(twl2, tw64, L2, 256);
+  for (int x = threadIdx.x; x < L2; x += 256) ul[x] = ldz(U, ((size_t)n * BM + i1) * L2 + x);
+  __syncthreads();
+  // output i2 by a group of 16 lanes (one wave holds four outputs)
+  const int g = threadIdx.x / 16, lane = threadIdx.x & 15;
+  const double sc = 1.0 / (2.0 * (double)nf1 * (double)nf2);
+  for (int i2 = g; i2 < ((b.B2 + 15) / 16) * 16; i2 += 16) {
+    z2 acc{0.0, 0.0};
+    if (i2 < b.B2) {
+      const int sm = (b.s2lo + i2) & (L2 - 1);
+      for (int x = lane; x < L2; x += 16) acc = zfma(ul[x], twl2[(sm * x) & (L2 - 1)], acc);
+    }
+    for (int off = 1; off < 16; off <<= 1) {
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (i2 < b.B2 && lane == 0) {
+      const int k1 = (b.s1lo + i1) & (nf1 - 1), k2 = (b.s2lo + i2) & (nf2 - 1);
+      const z2 v = zmulc(acc, ldz(h, (size_t)k1 * nf2 + k2));
+      stz(Vb, ((size_t)n * BM + i1) * BM + i2, z2{v.x * sc, v.y * sc});
+    }
+  }
+}
+
+// Wn[n][p] = conj(c[n][p]) sum_i1 e^{+2 pi j s1 a_p / nf1} sum_i2 V[n][i1][i2] e^{+2 pi j s2 b_p / nf2}
+__global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vb, const double* c,
+                                                  const int32_t* pix, PhaseBand b, int P, int nf1, int nf2,
+                                                  const double* tw64, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ z2 V[BM * BM];
+  __shared__ z2 Z[BM * 256];
+  __shared__ z2 tw1[256], tw2[256];
+  const int n = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  int g = 0;
+  z2 cv{0.0, 0.0};
+  if (p < P) {
+    g = pix[p];
+    cv = ldz(c, (size_t)n * P + p);
+  }
+  for (int t = threadIdx.x; t < b.B1 * BM; t += 256) V[t] = ldz(Vb, (size_t)n * BM * BM + t);
+  load_tab(tw1, tw64, nf1, 256);
+  load_tab(tw2, tw64, nf2, 256);
+  __syncthreads();
+  for (int t = threadIdx.x; t < b.B1 * nf2; t += 256) {
+    const int j1 = t / nf2, bb = t & (nf2 - 1);
+    z2 acc{0.0, 0.0};
+    for (int j2 = 0; j2 < b.B2; ++j2) {
+      const int sm = (b.s2lo + j2) & (nf2 - 1);
+      acc = zfmac(V[j1 * BM + j2], tw2[(sm * bb) & (nf2 - 1)], acc);
+    }
+    Z[j1 * nf2 + bb] = acc;
+  }
+  __syncthreads();
+  if (p < P) {
+    const int a = g / nf2, bb = g & (nf2 - 1);
+    z2 acc{0.0, 0.0};
+    for (int j1 = 0; j1 < b.B1; ++j1) {
+      const int sm = (b.s1lo + j1) & (nf1 - 1);
+      acc = zfmac(Z[j1 * nf2 + bb], tw1[(sm * a) & (nf1 - 1)], acc);
+    }
+    stz(Wn, (size_t)n * P + p, zmulc(acc, cv));
+  }
+}
+
+// grad[p] = -4 Im(conj(u_p) sum_n Wn[n][p]); gval = sum of the objective partials
+__global__ void __launch_bounds__(256) k_band_gather(double* grad, double* gval, const double* Wn, const double* phi,
+                                                     const double* gpart, int ngp, int Nd, int P, const int* skip) {
+  if (skip && *skip) return;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < P) {
+    z2 w{0.0, 0.0};
+#pragma unroll 10
+    for (int n = 0; n < Nd; ++n) w = zadd(w, ldz(Wn, (size_t)n * P + p));
+    double sn, cs;
+    sincos(phi[p], &sn, &cs);
+    grad[p] = -4.0 * zmulc(w, z2{cs, sn}).y;
+  }
+  if (blockIdx.x == 0) {
+    __shared__ double red[4];
+    double s = 0;
+    for (int i = threadIdx.x; i < ngp; i += 256) s += gpart[i];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) gval[0] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// pass geometry (depends on the dimensions only, except BT1 and G: the plan sets them)
+void band_geometry(const PhaseDims& d, PhaseBand* b) {
+  b->RA = std::max(1, std::min(d.nf1, 512 / d.nf2));
+  b->CH = d.nf1 / b->RA;
+}
+
+int band_bt1(int B1) { return B1 <= 4 ? 4 : B1 <= 8 ? 8 : 16; }
+
 int grid_of(int nlines, int Lmax) {
   const int nl = Lmax >= LINE_ELEMS ? 1 : LINE_ELEMS / Lmax;
   return (nlines + nl - 1) / nl;
@@ -525,11 +866,59 @@ int forward_to_rows(const PhaseDims& d, const double* phi, PhaseWork& w, const d
 
 }  // namespace
 
+namespace {
+size_t band_Sp_doubles(const PhaseDims& d) {
+  PhaseBand b;
+  band_geometry(d, &b);
+  return (size_t)d.Nd * b.CH * BM * BM * 2;
+}
+size_t band_U_doubles(const PhaseDims& d) { return (size_t)d.Nd * BM * 2 * d.nf2 * 2; }
+// image-pass workgroups: at most 2 nf2 column blocks per image
+size_t gpart_doubles(const PhaseDims& d) { return std::max((size_t)mid_groups(d), (size_t)d.Nd * 2 * d.nf2); }
+}  // namespace
+
 size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
   size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 2 * G * 2 +
-               (size_t)mid_groups(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1;
-  return dbl * sizeof(double) + 8 * 256;
+               gpart_doubles(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1 + band_Sp_doubles(d) +
+               band_U_doubles(d) + (size_t)d.Nd * BM * BM * 2 + (size_t)d.Nd * d.P * 2;
+  return dbl * sizeof(double) + 13 * 256;
+}
+
+PhaseBand phase_band_plan(const PhaseDims& d, const PhaseOptics& o, int enable) {
+  PhaseBand b{};
+  band_geometry(d, &b);
+  // signed frequencies of the bins inside the pupil (with a relative margin,
+  // so that a bin the device counts in is never left out of the box)
+  int lo1 = d.nf1, hi1 = -d.nf1, lo2 = d.nf2, hi2 = -d.nf2;
+  for (int k1 = 0; k1 < d.nf1; ++k1) {
+    const int s1 = (k1 < (d.nf1 + 1) / 2) ? k1 : k1 - d.nf1;
+    const double u = (double)s1 / ((double)d.nf1 * o.ps);
+    for (int k2 = 0; k2 < d.nf2; ++k2) {
+      const int s2 = (k2 < (d.nf2 + 1) / 2) ? k2 : k2 - d.nf2;
+      const double v = (double)s2 / ((double)d.nf2 * o.ps);
+      const double rho2 = (o.lambda * u) * (o.lambda * u) + (o.lambda * v) * (o.lambda * v);
+      if (std::sqrt(rho2) <= o.NA * (1.0 + 1e-9)) {
+        lo1 = std::min(lo1, s1);
+        hi1 = std::max(hi1, s1);
+        lo2 = std::min(lo2, s2);
+        hi2 = std::max(hi2, s2);
+      }
+    }
+  }
+  if (hi1 < lo1) {  // empty pupil: a one-bin box (h is zero there too)
+    lo1 = hi1 = lo2 = hi2 = 0;
+  }
+  b.s1lo = lo1;
+  b.B1 = hi1 - lo1 + 1;
+  b.s2lo = lo2;
+  b.B2 = hi2 - lo2 + 1;
+  b.on = enable && b.B1 <= BM && b.B2 <= BM;
+  const int bt1 = band_bt1(b.B1);
+  b.G = std::max(1, 2 * d.nf1 / bt1);
+  b.CPW = 256 / b.G;
+  b.NXB = (2 * d.nf2 + b.CPW - 1) / b.CPW;
+  return b;
 }
 
 void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
@@ -544,11 +933,16 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->h = take(G * 2);
   w->A = take((size_t)d.Nd * G * 2);
   w->B = take((size_t)d.Nd * 2 * G * 2);
-  w->gpart = take((size_t)mid_groups(d));
+  w->gpart = take(gpart_doubles(d));
   w->w = take((size_t)GATHER_SLICES * d.P * 2);
   w->gval = take(8);
   w->inv = (int32_t*)take(G);
   w->skip = (int*)take(1);
+  w->Sp = take(band_Sp_doubles(d));
+  w->U = take(band_U_doubles(d));
+  w->V = take((size_t)d.Nd * BM * BM * 2);
+  w->Wn = take((size_t)d.Nd * d.P * 2);
+  w->band = PhaseBand{};
 }
 
 int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
@@ -569,14 +963,30 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
   hipStream_t s = (hipStream_t)stream;
   int e;
   const int G = d.nf1 * d.nf2;
+  const int per = (d.Nd + GATHER_SLICES - 1) / GATHER_SLICES;
+  const int nsl = (d.Nd + per - 1) / per;
+  if (w.band.on) {
+    const PhaseBand& b = w.band;
+    k_band_spec<<<dim3(b.CH, d.Nd), 256, 0, s>>>(w.Sp, w.c, phi, w.inv, b, d.P, d.nf1, d.nf2, tw64, w.skip);
+    const dim3 gi(b.NXB, d.Nd);
+    switch (band_bt1(b.B1)) {
+      case 4: k_band_img<4><<<gi, 256, 0, s>>>(w.U, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
+      case 8: k_band_img<8><<<gi, 256, 0, s>>>(w.U, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
+      default: k_band_img<16><<<gi, 256, 0, s>>>(w.U, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip);
+    }
+    k_band_v<<<dim3(b.B1, d.Nd), 256, 0, s>>>(w.V, w.U, w.h, b, d.nf1, d.nf2, tw64, w.skip);
+    k_band_pix<<<dim3((d.P + 255) / 256, d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, pix, b, d.P, d.nf1, d.nf2, tw64,
+                                                             w.skip);
+    k_band_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
+                                                    w.skip);
+    return (int)hipGetLastError();
+  }
   if ((e = forward_to_rows(d, phi, w, tw64, s))) return e;
   const int ngp = mid_groups(d);
   k_rows_mid<<<ngp, LWG, 0, s>>>(w.B, Id, w.gpart, nullptr, d.Nd, d.nf1, d.nf2, tw64, w.skip);
   k_cols_adj<<<grid_of(d.Nd * d.nf2, 2 * d.nf1), LWG, 0, s>>>(w.A, w.B, w.h, d.Nd, d.nf1, d.nf2, tw64, w.skip);
   k_rows_adj<<<grid_of(d.Nd * d.nf1, d.nf2), LWG, 0, s>>>(w.A, d.Nd, d.nf1, d.nf2, tw64, w.skip);
   if ((e = (int)hipGetLastError())) return e;
-  const int per = (d.Nd + GATHER_SLICES - 1) / GATHER_SLICES;
-  const int nsl = (d.Nd + per - 1) / per;
   k_gather_part<<<dim3((d.P + 255) / 256, nsl), 256, 0, s>>>(w.w, w.A, w.c, pix, d.Nd, d.P, G, per, w.skip);
   k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, ngp, nsl, d.P, w.skip);
   return (int)hipGetLastError();

@@ -49,6 +49,7 @@ struct tm_ctx {
   std::map<int, int> variant;  // (L1 << 8 | L2) -> FFT digit-order variant
   double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
   rocblas_handle blas = nullptr;  // plain complex GEMM of the foci synthesis
+  int phase_band = 1;             // band evaluation of the defocus model when the pupil's box is small
 };
 
 namespace {
@@ -513,8 +514,16 @@ static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pi
   if (!base) return fail(c, TM_ENOMEM, "phase workspace");
   tmk::phase_work_carve(base, pd, &w);
   tmk::PhaseOptics po{o->lambda, o->ps_field, o->NA, o->z};
+  w.band = tmk::phase_band_plan(pd, po, c->phase_band);
   int e = tmk::phase_setup(pd, po, tm_est, theta, pix, w, stream);
   if (e) return hipfail(c, e, "phase setup");
+  return TM_OK;
+}
+
+extern "C" int tm_phase_set_band(tm_ctx* c, int32_t enable) {
+  if (!c) return TM_EINVAL;
+  if (enable != 0 && enable != 1) return fail(c, TM_EINVAL, "enable must be 0 or 1");
+  c->phase_band = enable;
   return TM_OK;
 }
 

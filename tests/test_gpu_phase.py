@@ -36,17 +36,52 @@ def build(nf, P, N, Nd, NA, pupil_frac, cfg, noise=None):
     return pix, tm_est, theta, Id, phi_true, mdl
 
 
-@pytest.mark.parametrize("nf,P,N,Nd", [(16, 40, 24, 12), (32, 512, 1024, 50), (64, 2286, 8192, 50)])
-def test_objective_and_gradient(ctx, nf, P, N, Nd):
-    print(f"phase objective nf={nf} P={P} N={N} Nd={Nd}", flush=True)
-    pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, 0.3, 0.3, cfg=950, noise=1e4)
+@pytest.fixture
+def band(ctx, request):
+    tm.tm_phase_set_band(ctx, request.param)
+    yield request.param
+    tm.tm_phase_set_band(ctx, True)
+
+
+# NA 0.3: pupil boxes of 5, 9 and 19 bins (the last above the band limit, so
+# the band setting falls back to full FFTs); NA 0.22 at 64 x 64 is the
+# 15-bin box of the paper-scale workload
+@pytest.mark.parametrize("band", [True, False], indirect=True)
+@pytest.mark.parametrize("nf,P,N,Nd,NA", [(16, 40, 24, 12, 0.3), (32, 512, 1024, 50, 0.3), (64, 2286, 8192, 50, 0.3),
+                                          (64, 2286, 1024, 50, 0.22)])
+def test_objective_and_gradient(ctx, band, nf, P, N, Nd, NA):
+    print(f"phase objective nf={nf} P={P} N={N} Nd={Nd} NA={NA} band={band}", flush=True)
+    pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, NA, NA, cfg=950, noise=1e4)
     phi = np.random.default_rng(1).random(P) * 2 * np.pi
     gref, grad_ref = mdl.objective(Id.astype(np.float64), phi)
     g, grad = tm.tm_phase_objective(ctx, torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta),
-                                    f32(Id), (LAM, PS, 0.3, 20 * LAM),
+                                    f32(Id), (LAM, PS, NA, 20 * LAM),
                                     torch.from_numpy(phi).to(dev()), nf, nf)
     assert abs(g.item() - gref) <= 1e-9 * gref
     assert relerr(grad.cpu().numpy(), grad_ref) < 1e-9
+
+
+@pytest.mark.parametrize("nf1,nf2,NA", [(64, 64, 0.22), (16, 8, 0.6), (2, 4, 0.9), (8, 8, 0.95), (128, 32, 0.1)])
+def test_band_matches_full_path(ctx, nf1, nf2, NA):
+    # the pruned evaluation against the full-FFT one on the same inputs (both also against the oracle above)
+    print(f"band vs full nf1={nf1} nf2={nf2} NA={NA}", flush=True)
+    g = np.random.default_rng(nf1 * 7 + nf2)
+    P = min(nf1 * nf2, 300)
+    pix = np.sort(g.choice(nf1 * nf2, P, replace=False))
+    tm_est = tm_synth.tm_iid(P, 40, tm_synth.rng(955, 1)).astype(np.complex64)
+    theta = tm_synth.defocus_phases(6, 40, tm_synth.rng(955, 4)).astype(np.complex64)
+    Id = (np.abs(g.standard_normal((6, 2 * nf1, 2 * nf2))) * 1e3).astype(np.float32)
+    phi = torch.from_numpy(g.random(P) * 2 * np.pi).to(dev())
+    args = (torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta), f32(Id),
+            (LAM, PS, NA, 20 * LAM), phi, nf1, nf2)
+    out = {}
+    for on in (True, False):
+        tm.tm_phase_set_band(ctx, on)
+        gv, grad = tm.tm_phase_objective(ctx, *args)
+        out[on] = (gv.item(), grad.cpu().numpy())
+    tm.tm_phase_set_band(ctx, True)
+    assert abs(out[True][0] - out[False][0]) <= 1e-11 * abs(out[False][0])
+    assert relerr(out[True][1], out[False][1]) < 1e-11
 
 
 def test_noiseless_offsets_recovered(ctx):
