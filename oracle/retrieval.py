@@ -5,8 +5,8 @@ f(t) = || I - |A t|^2 ||^2 (Eq. optTMsmall2), its gradient
 (Eq. derivative, App. A), the back-propagation start (Eq.
 backpropagation) and Algorithm 1 (f, gradient, L-BFGS direction, update,
 stop at maxiter). Also the amplitude-projection form (error reduction, the
-Gerchberg-Saxton / Fienup family the paper's Discussion names) and a
-spectral start.
+Gerchberg-Saxton / Fienup family the paper's Discussion names), its cyclic
+form (one mask's projection at a time) and a spectral start.
 
 Readings where the paper is silent:
   * Gradient packing: the paper's (df/dt)^H = df/dx + j df/dy, i.e. the real
@@ -124,6 +124,48 @@ def er_accelerated(op, I: np.ndarray, t0: np.ndarray, iters: int, beta: float) -
         z = t + beta * (t - tp)
         tp, t = t, er_step(op, I, z)
     return t
+
+
+def er_cyclic(masks: np.ndarray, n1: int, n2: int, I: np.ndarray, t0: np.ndarray, iters: int) -> np.ndarray:
+    """Error reduction with the masks taken one at a time (cyclic projections;
+    a solver chosen here, not the paper's): a sweep projects the row onto the
+    measurement set of each mask in turn,
+        y = F(psi_m t),  t <- conj(psi_m) F^H(sqrt(I_m) y/|y|) / N,  m = 1..K,
+    with F the unnormalised 2-D DFT (F^H F = N). F diag(psi_m) / sqrt(N) is
+    unitary, so each update is the nearest point of
+    {t : |F(psi_m t)|^2 = I_m} (the plain ER step averages the K such
+    projections instead). y/|y| := 1 where y = 0."""
+    masks = np.asarray(masks, dtype=np.complex128)
+    K, N = masks.shape
+    t = np.array(np.atleast_2d(t0), dtype=np.complex128)
+    P = t.shape[0]
+    amp = np.sqrt(np.maximum(np.asarray(I, dtype=np.float64).reshape(P, K, N), 0.0))
+    for _ in range(iters):
+        for m in range(K):
+            y = np.fft.fft2((masks[m][None, :] * t).reshape(P, n1, n2)).reshape(P, N)
+            w = amp[:, m, :] * phase_of(y)
+            t = np.conj(masks[m])[None, :] * np.fft.ifft2(w.reshape(P, n1, n2)).reshape(P, N)
+    return t
+
+
+def er_cyclic_sweep_sums(masks: np.ndarray, n1: int, n2: int, I: np.ndarray, t0: np.ndarray):
+    """The residual sums of one sweep from t0, each mask's term taken at the
+    iterate its projection starts from: (sum_m ||sqrt(I_m) - |y_m|||^2,
+    sum_m ||I_m - |y_m|^2||^2) per row."""
+    masks = np.asarray(masks, dtype=np.complex128)
+    K, N = masks.shape
+    t = np.array(np.atleast_2d(t0), dtype=np.complex128)
+    P = t.shape[0]
+    Iv = np.asarray(I, dtype=np.float64).reshape(P, K, N)
+    amp = np.sqrt(np.maximum(Iv, 0.0))
+    sa = np.zeros(P)
+    si = np.zeros(P)
+    for m in range(K):
+        y = np.fft.fft2((masks[m][None, :] * t).reshape(P, n1, n2)).reshape(P, N)
+        sa += np.sum((amp[:, m, :] - np.abs(y)) ** 2, axis=1)
+        si += np.sum((Iv[:, m, :] - np.abs(y) ** 2) ** 2, axis=1)
+        t = np.conj(masks[m])[None, :] * np.fft.ifft2((amp[:, m, :] * phase_of(y)).reshape(P, n1, n2)).reshape(P, N)
+    return sa, si
 
 
 def backprop_start(op, I: np.ndarray) -> np.ndarray:

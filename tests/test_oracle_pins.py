@@ -425,3 +425,98 @@ def test_matrix_operator_gradient_matches_probing_form():
     fp = rt.intensity_grad(mq, Iq, x + 1e-6 * v)[0]
     fm = rt.intensity_grad(mq, Iq, x - 1e-6 * v)[0]
     assert np.max(np.abs((fp - fm) / 2e-6 - rt.rdot(grad, v))) <= 1e-5 * np.max(np.abs(fp))
+
+
+def test_cyclic_er_substep_is_the_nearest_feasible_point():
+    # one mask (K = 1): the update lands on {t : |F(psi t)|^2 = I} and is closer
+    # to the input than any other point of that set (brute force over random
+    # phases of the feasible spectrum, and over small phase perturbations of the
+    # result itself)
+    n1, n2 = 4, 4
+    N = n1 * n2
+    g = np.random.default_rng(41)
+    psi = np.exp(2j * np.pi * g.random((1, N)))
+    t = (g.standard_normal((1, N)) + 1j * g.standard_normal((1, N))) / np.sqrt(2)
+    I = np.abs(g.standard_normal((1, 1, N))) * 3.0
+    tp = rt.er_cyclic(psi, n1, n2, I, t, 1)
+    F = ops.dft2_matrix(n1, n2)
+    y = F @ (psi[0] * tp[0])
+    assert np.max(np.abs(np.abs(y) ** 2 - I.reshape(N))) < 1e-12
+    d0 = np.linalg.norm(tp - t)
+    Finv = np.conj(F).T / N
+    for _ in range(2000):
+        th = np.exp(2j * np.pi * g.random(N))
+        cand = np.conj(psi[0]) * (Finv @ (np.sqrt(I.reshape(N)) * th))
+        assert np.linalg.norm(cand - t[0]) >= d0 - 1e-12
+    ph = np.angle(y)
+    for _ in range(200):
+        cand = np.conj(psi[0]) * (Finv @ (np.sqrt(I.reshape(N)) * np.exp(1j * (ph + 0.05 * g.standard_normal(N)))))
+        assert np.linalg.norm(cand - t[0]) >= d0 - 1e-12
+
+
+def test_cyclic_er_fixed_point_two_mask_monotone_and_recovery():
+    n1 = n2 = 8
+    N, P = n1 * n2, 6
+    masks = tm_synth.mask_phases(4, N, tm_synth.rng(42, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(42, 1))
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, T)
+    # the noiseless truth, with any row phase, is a fixed point of a sweep
+    truth = T * np.exp(1j * np.linspace(0, 3, P))[:, None]
+    assert np.max(np.abs(rt.er_cyclic(masks, n1, n2, I, truth, 3) - truth)) < 1e-12
+    # two sets (K = 2): alternating exact projections never lengthen the step
+    # (the previous iterate lies in the set projected onto next)
+    g = np.random.default_rng(43)
+    t = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))) / np.sqrt(2)
+    I2 = I[:, :2]
+    steps = []
+    for k in range(30):
+        tn = rt.er_cyclic(masks[k % 2: k % 2 + 1], n1, n2, I2[:, k % 2: k % 2 + 1], t, 1)
+        steps.append(np.linalg.norm(tn - t, axis=1))
+        t = tn
+    steps = np.array(steps)
+    assert np.all(steps[2:] <= steps[1:-1] * (1 + 1e-12) + 1e-12)
+    # noiseless recovery from the spectral start (fidelity 0.9999, Sec. 2.2 data)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(42, 3))
+    t0 = rt.spectral_start(op, I, v0, 40, momentum=0.98)
+    assert rt.fidelity(rt.er_cyclic(masks, n1, n2, I, t0, 60), T).min() > 0.9999
+
+
+def test_cyclic_er_sweep_sums_at_a_fixed_point_and_single_mask():
+    # at the noiseless truth every term vanishes; with one mask the sums are
+    # those of the start, computed by loops over the dense DFT
+    n1, n2 = 4, 8
+    N, P = n1 * n2, 3
+    masks = tm_synth.mask_phases(3, N, tm_synth.rng(44, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(44, 1))
+    I = ops.intensities(ops.FFTOp(masks, n1, n2), T)
+    sa, si = rt.er_cyclic_sweep_sums(masks, n1, n2, I, T)
+    assert np.max(sa) < 1e-20 and np.max(si) < 1e-18
+    g = np.random.default_rng(45)
+    t = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))) / np.sqrt(2)
+    sa1, si1 = rt.er_cyclic_sweep_sums(masks[:1], n1, n2, I[:, :1], t)
+    F = ops.dft2_matrix(n1, n2)
+    for p in range(P):
+        y = F @ (masks[0] * t[p])
+        ea = sum((np.sqrt(I[p, 0, k]) - abs(y[k])) ** 2 for k in range(N))
+        ei = sum((I[p, 0, k] - abs(y[k]) ** 2) ** 2 for k in range(N))
+        assert abs(sa1[p] - ea) < 1e-10 * ea and abs(si1[p] - ei) < 1e-10 * ei
+
+
+def test_cyclic_er_needs_fewer_sweeps_than_parallel_er():
+    # from the same spectral start on noiseless 16 x 16 rows, a cyclic sweep
+    # (K projections in turn) gains more fidelity than a parallel ER step
+    # (the average of the K projections)
+    n1 = n2 = 16
+    N, K, P = n1 * n2, 4, 12
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(46, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(46, 1))
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, T)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(46, 3))
+    t0 = rt.spectral_start(op, I, v0, 40, momentum=0.98)
+    par = t0.copy()
+    for _ in range(5):
+        par = rt.er_step(op, I, par)
+    cyc = rt.er_cyclic(masks, n1, n2, I, t0, 5)
+    assert rt.fidelity(cyc, T).mean() > rt.fidelity(par, T).mean()
