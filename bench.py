@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="32x32 modes, 512 rows (quick check)")
     ap.add_argument("--er-iters", type=int, default=0, help="skip the instrumented search and use this count")
+    ap.add_argument("--solver", choices=["er", "er_cyclic"], default="er_cyclic",
+                    help="error reduction averaging the K mask projections (er, with --er-momentum) or taking "
+                         "them one at a time (er_cyclic)")
     ap.add_argument("--er-momentum", type=float, default=0.8,
                     help="Nesterov factor of the error-reduction iterations (0: plain ER)")
     ap.add_argument("--batch-iters", type=int, default=30)
@@ -144,7 +147,9 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
     res = {"P": 2286, "N": 8192, "sources_sha256": sources_digest(),
            "copy": {"kernel": big, "bytes": 512 * 2**20, "fetch_kib": cf[big][0], "write_kib": cw[big][0]},
            "kernels": {}}
-    for key, mode in (("spectral", 5), ("er", 3)):
+    for key, mode in (("spectral", 5), ("er", 3), ("er_cyclic", 12)):
+        if not any(f", {mode}, float, " in k for k in f):
+            continue
         fv, fn = pick(f, mode)
         wv, wn = pick(w, mode)
         res["kernels"][key] = {"fetch_kib": fv, "write_kib": wv, "dispatches": [fn, wn]}
@@ -227,7 +232,9 @@ def main():
 
     sp = args.spectral_iters
 
-    beta = args.er_momentum
+    solver = args.solver
+    beta = args.er_momentum if solver == "er" else 0.0
+    er_mode = 3 if solver == "er" else 12  # row-kernel mode of the solver's iteration
 
     def opts(method, iters, start="spectral"):
         return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=args.spectral_tau,
@@ -235,15 +242,18 @@ def main():
                                 spectral_lower=args.spectral_lower,
                                 er_momentum=beta if method == "er" else 0.0)
 
+    def sopts(iters, start="spectral"):
+        return opts(solver, iters, start) if solver != "er" else opts("er", iters, start)
+
     # ---- untimed instrumented run: iterations to mean fidelity 0.99 (each count run
     # from the start, since the momentum iteration carries the previous iterate)
     t = v0t.clone()
-    tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", 0))
+    tm.tm_retrieve(ctx, mk, It, t, n1, n2, sopts(0))
     f_start = fidelity(t).mean().item()
     n_er = args.er_iters or None
     for it in range(1, 0 if n_er else args.max_iters + 1):
         t = v0t.clone()
-        tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", it), stats=False)
+        tm.tm_retrieve(ctx, mk, It, t, n1, n2, sopts(it), stats=False)
         if fidelity(t).mean().item() >= 0.99:
             n_er = it
             break
@@ -254,7 +264,7 @@ def main():
     # ---- untimed instrumented run: phase iterations at which the offsets have converged (circular
     # spread over the rows at fidelity >= 0.99 within 1 % of the spread after phase_iters_max)
     t = v0t.clone()
-    tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts("er", n_er), stats=False)
+    tm.tm_retrieve(ctx, mk, It, t, n1, n2, sopts(n_er), stats=False)
     good0 = fidelity(t) >= 0.99
     off_t = torch.angle(torch.sum(torch.conj(t) * Tt, dim=1)).double()
 
@@ -289,9 +299,9 @@ def main():
             break
     log(f"amplitude L-BFGS reaches 0.99 within {n_la} iterations")
 
-    def step(method="er", iters=n_er, phase=True):
+    def step(method=None, iters=n_er, phase=True):
         t = v0t.clone()
-        raw = tm.tm_retrieve(ctx, mk, It, t, n1, n2, opts(method, iters))
+        raw = tm.tm_retrieve(ctx, mk, It, t, n1, n2, sopts(iters) if method is None else opts(method, iters))
         phi = None
         if phase:
             phi = torch.zeros(P, dtype=torch.float64, device=dev)
@@ -309,7 +319,7 @@ def main():
         t, raw, phi = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
-    er_ms, er_n = tm.tm_profile_query(ctx, 3)
+    er_ms, er_n = tm.tm_profile_query(ctx, er_mode)
     sp_ms, sp_n = tm.tm_profile_query(ctx, 5)
     rs_ms, rs_n = tm.tm_profile_query(ctx, 7)
     tm.tm_profile_enable(ctx, False)
@@ -352,8 +362,9 @@ def main():
                      "name": "row_kernel<M_SPEC> (mask*FFT, truncated weights, IFFT, conj-mask sum, heavy-ball)",
                      # read I, v and the previous iterate, write the new v
                      "bytes": P * (K * N * 4 + 3 * N * 8)},
-        "er": {"mode": 3, "ms": er_ms, "n": er_n,
-               "name": "row_kernel<M_ER> (mask*FFT, amplitude projection, IFFT, conj-mask sum)",
+        "er": {"mode": er_mode, "ms": er_ms, "n": er_n,
+               "name": "row_kernel<M_ER> (mask*FFT, amplitude projection, IFFT, conj-mask sum)" if solver == "er" else
+                       "row_kernel<M_ERC> (per mask: mask*FFT, amplitude projection, IFFT, conj-mask)",
                # read I, t (and t_prev with momentum), write the new t
                "bytes": P * (K * N * 4 + (3 if beta > 0 else 2) * N * 8)},
     }
@@ -363,7 +374,7 @@ def main():
         avg = kv["ms"] / max(kv["n"], 1)
         tf = P * flops_row / (avg * 1e-3) / 1e12
         gbs = kv["bytes"] / (avg * 1e-3) / 1e9
-        tr = traffic.get(key) if traffic else None
+        tr = traffic.get("er_cyclic" if key == "er" and solver == "er_cyclic" else key) if traffic else None
         roofs[key] = {
             "alu": {"bound": "alu", "kernel": kv["name"], "achieved": round(tf, 2), "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
@@ -395,7 +406,8 @@ def main():
         "config": {"workload": workload, "P": P, "N": N, "grid": [n1, n2], "K": K,
                    "start": f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
                             f"(c {args.spectral_momentum}, interval [{args.spectral_lower}, c] lambda)",
-                   "solver": f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction",
+                   "solver": (f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction")
+                             if solver == "er" else "cyclic error reduction (one mask projection at a time)",
                    "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_m": args.phase_m,
                    "phase_ftol": args.phase_ftol},
         "roofline": roofline,
@@ -429,7 +441,7 @@ def main():
     if not args.no_preprocess and not args.small:
         out["preprocess"] = preprocess_variant(ctx, args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P)
+        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver)
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -453,7 +465,7 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
                                                    spectral_lower=args.spectral_lower,
-                                                   er_momentum=args.er_momentum)
+                                                   er_momentum=beta, method=solver)
     torch.cuda.synchronize()
     a = time.perf_counter()
     for _ in range(3):
@@ -461,7 +473,7 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
                                                    spectral_lower=args.spectral_lower,
-                                                   er_momentum=args.er_momentum)
+                                                   er_momentum=beta, method=solver)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) * 1e3 / 3
     return {"rows_per_s": round(P / (ms * 1e-3), 1), "retrieval_ms": round(ms, 3),
@@ -695,7 +707,7 @@ def batch_variant(ctx, args):
             "iters": iters, "er_momentum": beta, "spectral_iters": sp, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
 
 
-def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P):
+def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver="er"):
     """The FP64 oracle (FFT form of A) on a bounded sample of rows: the same
     spectral start and error-reduction iterations, timed on the host."""
     from oracle import operators as ops
@@ -708,6 +720,8 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P):
         I = I_np[rows].astype(np.float64)
         t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau,
                               momentum=args.spectral_momentum, lower=args.spectral_lower)
+        if solver == "er_cyclic":
+            return rt.er_cyclic(masks, n1, n2, I, t, n_er)
         return rt.er_accelerated(op, I, t, n_er, beta)
 
     g = np.random.default_rng(123)
@@ -722,9 +736,9 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P):
     dt = time.perf_counter() - a
     fid = rt.fidelity(t, T[rows].astype(np.complex128))
     return {"value": round(nrows / dt, 3), "unit": "rows/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nrows} of {P} rows, FP64 numpy FFT form of A, {sp} spectral + {n_er} ER iterations "
-                      f"(Nesterov factor {beta}) "
-                      f"({dt:.1f}s)", "mean_fidelity": round(float(fid.mean()), 6),
+            "sample": f"{nrows} of {P} rows, FP64 numpy FFT form of A, {sp} spectral + {n_er} "
+                      + (f"ER iterations (Nesterov factor {beta}) " if solver == "er" else "cyclic ER sweeps ")
+                      + f"({dt:.1f}s)", "mean_fidelity": round(float(fid.mean()), 6),
             "host_cpus": len(os.sched_getaffinity(0))}
 
 

@@ -122,7 +122,15 @@ int tm_residual_f64(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, 
  * -2 A^H((sqrt(I) - |y|) y/|y|), line search over the trial steps 1/8 .. 16
  * (the smallest cost wins if below the cost at t, else no step and the row's
  * history is dropped), direction -g/(2KN) with no history. */
-enum { TM_METHOD_ER = 0, TM_METHOD_LBFGS = 1, TM_METHOD_LBFGS_AMP = 2 };
+/* TM_METHOD_ER_CYCLIC: error reduction with one mask's projection at a time
+ * (a solver chosen here, not the paper's): a sweep (one of `iters`) takes
+ * m = 1..K in order, y = F(psi_m t), t <- conj(psi_m) F^H(sqrt(I_m) y/|y|)/N,
+ * the nearest point of that mask's measurement set; plain TM_METHOD_ER
+ * averages the K projections instead. Same cost per sweep as one ER
+ * iteration; er_momentum must be 0. The reported f and amp_res are the
+ * last sweep's sums, each mask's term at the iterate its projection starts
+ * from. */
+enum { TM_METHOD_ER = 0, TM_METHOD_LBFGS = 1, TM_METHOD_LBFGS_AMP = 2, TM_METHOD_ER_CYCLIC = 3 };
 enum {
   TM_START_GIVEN = 0,     /* use t as passed in                                  */
   TM_START_BACKPROP = 1,  /* t = A^H sqrt(I) / (K N)          (Eq. backpropagation) */
@@ -130,7 +138,7 @@ enum {
 };
 
 typedef struct {
-  int32_t method;          /* TM_METHOD_ER (projection), TM_METHOD_LBFGS (Alg. 1) or _AMP */
+  int32_t method;          /* TM_METHOD_ER (projection), _ER_CYCLIC, TM_METHOD_LBFGS (Alg. 1) or _AMP */
   int32_t iters;           /* solver iterations (the paper's maxiter), >= 0              */
   int32_t lbfgs_m;         /* L-BFGS memory, 1..16 (default 5)                           */
   int32_t I_dtype;         /* TM_F32 or TM_BF16                                          */

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtm.so")
 TM_OK, TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENOMEM = 0, -1, -2, -3, -4
 TM_F32, TM_BF16 = 0, 1
 TM_FIELD, TM_INTENSITY = 0, 1
-TM_METHOD_ER, TM_METHOD_LBFGS, TM_METHOD_LBFGS_AMP = 0, 1, 2
+TM_METHOD_ER, TM_METHOD_LBFGS, TM_METHOD_LBFGS_AMP, TM_METHOD_ER_CYCLIC = 0, 1, 2, 3
 TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL = 0, 1, 2
 
 EXPORTED = (
@@ -35,7 +35,8 @@ EXPORTED = (
     "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
-              6: "line_sums", 7: "residual_f64", 8: "backprop"}
+              6: "line_sums", 7: "residual_f64", 8: "backprop", 9: "amp_gradient", 10: "amp_line_sums",
+              11: "filter", 12: "er_cyclic"}
 
 
 class tm_dims(ctypes.Structure):
@@ -280,7 +281,8 @@ def decode_stats(raw: torch.Tensor) -> RowStats:
 def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", spectral_iters=30,
                   spectral_tau=3.0, spectral_momentum=0.98, er_momentum=0.0,
                   spectral_lower=None) -> tm_retrieve_opts:
-    m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS, "lbfgs_amp": TM_METHOD_LBFGS_AMP}[method]
+    m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS, "lbfgs_amp": TM_METHOD_LBFGS_AMP,
+         "er_cyclic": TM_METHOD_ER_CYCLIC}[method]
     s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL}[start]
     return tm_retrieve_opts(m, int(iters), int(lbfgs_m), TM_BF16 if bf16 else TM_F32, s, int(spectral_iters),
                             float(spectral_tau), float(spectral_momentum), float(er_momentum),

@@ -27,6 +27,10 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
       if (a.sums) row_kernel<PLg, M_ER, IT, true><<<grid, block, 0, s>>>(a);
       else row_kernel<PLg, M_ER, IT, false><<<grid, block, 0, s>>>(a);
       break;
+    case M_ERC:
+      if (a.sums) row_kernel<PLg, M_ERC, IT, true><<<grid, block, 0, s>>>(a);
+      else row_kernel<PLg, M_ERC, IT, false><<<grid, block, 0, s>>>(a);
+      break;
     case M_GRAD:
       if (a.sums) row_kernel<PLg, M_GRAD, IT, true><<<grid, block, 0, s>>>(a);
       else row_kernel<PLg, M_GRAD, IT, false><<<grid, block, 0, s>>>(a);

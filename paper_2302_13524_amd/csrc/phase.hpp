@@ -47,7 +47,12 @@ size_t phase_work_bytes(const PhaseDims& d);
 PhaseBand phase_band_plan(const PhaseDims& d, const PhaseOptics& o, int enable);
 void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w);
 
-// c = theta * tm_est^T and the kernel table h. Returns hipError_t.
+// FP32 complex [n] -> FP64 complex [n] (the GEMM c_n = TM_est e^{j theta_n} runs
+// in FP64 through rocBLAS on the widened inputs). Returns hipError_t.
+int phase_widen(const void* src, double* dst, int64_t n, void* stream);
+
+// The kernel table h, the pixel map and the solve flag (c is formed by the
+// caller). Returns hipError_t.
 int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
                 const int32_t* pix, PhaseWork& w, void* stream);
 // g(phi) into w.gval[0] and dg/dphi into grad[P].

@@ -35,40 +35,13 @@ int ilog2(int v) {
   return l;
 }
 
-// ---- GEMM c[n][p] = sum_k theta[n][k] * tm[p][k] (FP32 inputs, FP64 accumulation)
-constexpr int GT_N = 8, GT_P = 32, GT_K = 64;
-__global__ void __launch_bounds__(256) k_cgemm(const float2* __restrict__ theta, const float2* __restrict__ tm,
-                                                double* __restrict__ c, int Nd, int P, int N) {
-  __shared__ float2 sa[GT_N][GT_K];
-  __shared__ float2 sb[GT_P][GT_K + 1];
-  int n0 = blockIdx.y * GT_N, p0 = blockIdx.x * GT_P;
-  int tid = threadIdx.x;
-  int tn = tid / GT_P, tp = tid % GT_P;  // 8 x 32 outputs, one per thread
-  double ar = 0, ai = 0;
-  for (int k0 = 0; k0 < N; k0 += GT_K) {
-    for (int i = tid; i < GT_N * GT_K; i += 256) {
-      int r = i / GT_K, k = i % GT_K;
-      int n = n0 + r, kk = k0 + k;
-      sa[r][k] = (n < Nd && kk < N) ? theta[(size_t)n * N + kk] : make_float2(0.f, 0.f);
-    }
-    for (int i = tid; i < GT_P * GT_K; i += 256) {
-      int r = i / GT_K, k = i % GT_K;
-      int p = p0 + r, kk = k0 + k;
-      sb[r][k] = (p < P && kk < N) ? tm[(size_t)p * N + kk] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < GT_K; ++k) {
-      float2 a = sa[tn][k], b = sb[tp][k];
-      ar += (double)a.x * b.x - (double)a.y * b.y;
-      ai += (double)a.x * b.y + (double)a.y * b.x;
-    }
-    __syncthreads();
-  }
-  int n = n0 + tn, p = p0 + tp;
-  if (n < Nd && p < P) {
-    c[((size_t)n * P + p) * 2] = ar;
-    c[((size_t)n * P + p) * 2 + 1] = ai;
+// FP32 complex -> FP64 complex (exact), the inputs of the FP64 GEMM c = theta TM_est^T
+__global__ void __launch_bounds__(256) k_widen(const float2* __restrict__ src, double2* __restrict__ dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n; i += stride) {
+    const float2 v = src[i];
+    dst[i] = make_double2((double)v.x, (double)v.y);
   }
 }
 
@@ -947,9 +920,9 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
 
 int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
                 const int32_t* pix, PhaseWork& w, void* stream) {
+  (void)tm_est;
+  (void)theta;
   hipStream_t s = (hipStream_t)stream;
-  dim3 g((d.P + GT_P - 1) / GT_P, (d.Nd + GT_N - 1) / GT_N);
-  k_cgemm<<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm_est, w.c, d.Nd, d.P, d.N);
   int G = d.nf1 * d.nf2;
   k_make_h<<<(G + 255) / 256, 256, 0, s>>>(w.h, d.nf1, d.nf2, o.lambda, o.ps, o.NA, o.z);
   k_invmap<<<(G + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G);
@@ -1009,7 +982,7 @@ constexpr int PWG = 1024;
 // Block-wide sums of several values: each wave adds its lanes' x into
 // red[wave][j] (wave_put), then bsum_finish adds the waves: out[0..nv) for
 // every thread. red holds (PWG / 64) * MAXV doubles.
-constexpr int MAXV = 34;
+constexpr int MAXV = 4 * 16 + 5;
 __device__ __forceinline__ void wave_put(double x, int j, double* red) {
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
   if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * MAXV + j] = x;
@@ -1033,91 +1006,77 @@ __device__ void bsum_finish(int nv, double* red, double* out) {
 // s_i^T y_j and YY[i][j] = y_i^T y_j over the history slots.
 // *skip = 1 ends the solve (every later kernel returns at once).
 // One iteration is k_piter followed by the objective and gradient at phit:
-// k_piter first decides on the pending trial (Armijo f_t <= f + 1e-4 a slope:
-// accept, update the history), then takes a new direction after an accepted
-// trial or halves a, and sets the trial point phit = phi + a d.
+// k_piter first decides on the pending trial (Armijo f_t <= f + 1e-4 a slope),
+// then, after an accepted trial, stores the pair and takes a new direction,
+// or halves a; and it sets the trial point phit = phi + a d.
 // The direction is the L-BFGS product -H g in the compact form of Byrd,
 // Nocedal and Schnabel (1994): with a = S^T g, b = Y^T g over the k stored
 // pairs (oldest first), R the upper triangle of S^T Y, D its diagonal and
 // gamma = s^T y / y^T y of the newest pair, H g = gamma g + S p - gamma Y u
 // where R u = a and R^T p = (D + gamma Y^T Y) u - gamma b. This equals the
-// two-loop recursion, but needs one pass over the vectors for all the dot
-// products instead of one reduction per stored pair.
+// two-loop recursion; all its dot products, and those of the new pair with
+// the stored ones, come from one pass over the vectors, and the direction
+// and the trial point from a second.
 constexpr int SC_HIST = 10;
 
 // smat (LDS, SMAT doubles): the k x k blocks of SY and YY in age order, then
 // the small solve's u and p.
 constexpr int SMAT = 2 * 16 * 16 + 2 * 16;
 
-__device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, double* sh, double* smat) {
-  const int head = (int)sc[0], k = (int)sc[1];
-  double* R = smat;             // R[i][j] = s_i^T y_j (age order), row stride 16
-  double* W = smat + 256;       // W[i][j] = y_i^T y_j
+// Thread 0: coefficients of d = coef[0] g + sum_j coef[1+j] S_j + coef[1+k+j] Y_j
+// over the k stored pairs (age order, slot of pair j: (head - k + j) mod m)
+// from a_j = s_j^T g (dots[j]), b_j = y_j^T g (dots[k+j]) and g^T g (dots[2k]).
+// Sets sc[1] = 0 (history dropped) when the product is not a descent
+// direction, and sc[2] = the slope g^T d. coef[1 + 2k] = 1 if the pairs are used.
+__device__ void dir_solve(int k, int head, int m, double* sc, const double* dots, double* coef, double* smat) {
+  double* R = smat;        // R[i][j] = s_i^T y_j (age order), row stride 16
+  double* W = smat + 256;  // W[i][j] = y_i^T y_j
   double* u = smat + 512;
   double* p = smat + 528;
-  for (int t = threadIdx.x; t < k * k; t += PWG) {
-    const int i = t / k, j = t - (t / k) * k;
-    const int si = (head - k + i + 2 * m) % m, sj = (head - k + j + 2 * m) % m;
-    R[i * 16 + j] = sc[SC_HIST + si * m + sj];
-    W[i * 16 + j] = sc[SC_HIST + m * m + si * m + sj];
-  }
-  // one pass: a_j = s_j^T g, b_j = y_j^T g, g^T g
-  for (int j = 0; j < k; ++j) {
-    const int sl = (head - k + j + 2 * m) % m;
-    const double* Sj = L.S + (size_t)sl * P;
-    const double* Yj = L.Y + (size_t)sl * P;
-    double xa = 0.0, xb = 0.0;
-    for (int i = threadIdx.x; i < P; i += PWG) {
-      const double gi = L.g[i];
-      xa += Sj[i] * gi;
-      xb += Yj[i] * gi;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      const int si = (head - k + i + 2 * m) % m, sj = (head - k + j + 2 * m) % m;
+      R[i * 16 + j] = sc[SC_HIST + si * m + sj];
+      W[i * 16 + j] = sc[SC_HIST + m * m + si * m + sj];
     }
-    wave_put(xa, j, red);
-    wave_put(xb, k + j, red);
-  }
-  double xg = 0.0;
-  for (int i = threadIdx.x; i < P; i += PWG) xg += L.g[i] * L.g[i];
-  wave_put(xg, 2 * k, red);
-  double* dots = sh;              // [2k + 1]
-  double* coef = sh + MAXV;       // [0] g coefficient, [1..1+k) S, [1+k..1+2k) Y, [1+2k] history kept
-  bsum_finish(2 * k + 1, red, dots);
-  if (threadIdx.x == 0) {
-    const double gg = dots[2 * k];
-    double cg, slope;
-    bool keep = k > 0;
-    if (k > 0) {
-      const double gam = R[(k - 1) * 17] / W[(k - 1) * 17];
-      for (int i = k - 1; i >= 0; --i) {  // R u = a (upper triangle)
-        double t = dots[i];
-        for (int j = i + 1; j < k; ++j) t -= R[i * 16 + j] * u[j];
-        u[i] = t / R[i * 17];
-      }
-      for (int i = 0; i < k; ++i) {  // R^T p = (D + gam Y^T Y) u - gam b
-        double t = R[i * 17] * u[i] - gam * dots[k + i];
-        for (int j = 0; j < k; ++j) t += gam * W[i * 16 + j] * u[j];
-        for (int j = 0; j < i; ++j) t -= R[j * 16 + i] * p[j];
-        p[i] = t / R[i * 17];
-      }
-      // d = -H g = -gam g - S p + gam Y u
-      cg = -gam;
-      slope = -gam * gg;
-      for (int j = 0; j < k; ++j) {
-        coef[1 + j] = -p[j];
-        coef[1 + k + j] = gam * u[j];
-        slope += -p[j] * dots[j] + gam * u[j] * dots[k + j];
-      }
-      if (!(slope < 0.0)) keep = false;  // not a descent direction: drop the history
+  const double gg = dots[2 * k];
+  double cg = 0.0, slope = 0.0;
+  bool keep = k > 0;
+  if (k > 0) {
+    const double gam = R[(k - 1) * 17] / W[(k - 1) * 17];
+    for (int i = k - 1; i >= 0; --i) {  // R u = a (upper triangle)
+      double t = dots[i];
+      for (int j = i + 1; j < k; ++j) t -= R[i * 16 + j] * u[j];
+      u[i] = t / R[i * 17];
     }
-    if (!keep) {  // -g / ||g||
-      cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
-      slope = cg * gg;
-      sc[1] = 0;
+    for (int i = 0; i < k; ++i) {  // R^T p = (D + gam Y^T Y) u - gam b
+      double t = R[i * 17] * u[i] - gam * dots[k + i];
+      for (int j = 0; j < k; ++j) t += gam * W[i * 16 + j] * u[j];
+      for (int j = 0; j < i; ++j) t -= R[j * 16 + i] * p[j];
+      p[i] = t / R[i * 17];
     }
-    coef[0] = cg;
-    coef[1 + 2 * k] = keep ? 1.0 : 0.0;
-    sc[2] = slope;
+    // d = -H g = -gam g - S p + gam Y u
+    cg = -gam;
+    slope = -gam * gg;
+    for (int j = 0; j < k; ++j) {
+      coef[1 + j] = -p[j];
+      coef[1 + k + j] = gam * u[j];
+      slope += -p[j] * dots[j] + gam * u[j] * dots[k + j];
+    }
+    if (!(slope < 0.0)) keep = false;  // not a descent direction: drop the history
   }
-  __syncthreads();
+  if (!keep) {  // -g / ||g||
+    cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
+    slope = cg * gg;
+    sc[1] = 0;
+  }
+  coef[0] = cg;
+  coef[1 + 2 * k] = keep ? 1.0 : 0.0;
+  sc[2] = slope;
+}
+
+// d from the coefficients, and the trial point phit = phi + d (step 1)
+__device__ void dir_apply(PhaseLb& L, int P, int m, int k, int head, const double* coef) {
   const int kk = coef[1 + 2 * k] != 0.0 ? k : 0;
   for (int i = threadIdx.x; i < P; i += PWG) {
     double d = coef[0] * L.g[i];
@@ -1126,117 +1085,209 @@ __device__ void direction(PhaseLb& L, int P, int m, double* red, double* sc, dou
       d += coef[1 + j] * L.S[(size_t)sl * P + i] + coef[1 + k + j] * L.Y[(size_t)sl * P + i];
     }
     L.d[i] = d;
+    L.phit[i] = L.phi[i] + d;
   }
-  __syncthreads();
 }
 
-// Armijo decision on the trial whose objective is gval[0] and gradient L.gt.
-// An accepted trial goes into the history slot head: s = a d, y = g_t - g,
-// with its dot products against the stored pairs (one pass).
-__device__ void decide(PhaseLb& L, int P, int m, double ftol, const double* gval, double* red, double* sc,
-                       double* sh) {
-  const double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
-  const bool ok = fn <= f + 1e-4 * a * slope;
-  if (!ok) {
-    __syncthreads();
-    if (threadIdx.x == 0) sc[6] = 0.0;
-    __syncthreads();
-    return;
+// First direction (no trial yet): -g / ||g|| over the stored pairs (none after
+// the start), then the trial point.
+__device__ void first_direction(PhaseLb& L, int P, int m, double* red, double* sc, double* sh, double* smat) {
+  const int head = (int)sc[0], k = (int)sc[1];
+  for (int j = 0; j < k; ++j) {
+    const int sl = (head - k + j + 2 * m) % m;
+    double xa = 0.0, xb = 0.0;
+    for (int i = threadIdx.x; i < P; i += PWG) {
+      const double gi = L.g[i];
+      xa += L.S[(size_t)sl * P + i] * gi;
+      xb += L.Y[(size_t)sl * P + i] * gi;
+    }
+    wave_put(xa, j, red);
+    wave_put(xb, k + j, red);
   }
+  double xg = 0.0;
+  for (int i = threadIdx.x; i < P; i += PWG) xg += L.g[i] * L.g[i];
+  wave_put(xg, 2 * k, red);
+  double* dots = sh;
+  double* coef = sh + MAXV;
+  bsum_finish(2 * k + 1, red, dots);
+  if (threadIdx.x == 0) dir_solve(k, head, m, sc, dots, coef, smat);
+  __syncthreads();
+  dir_apply(L, P, m, k, head, coef);
+}
+
+// Accepted trial: the pair s = a d, y = g_t - g goes into slot head (its dot
+// products with the stored pairs update SY and YY), phi and g move to the
+// trial, and the dot products of the next direction (with g_t) are taken in
+// the same pass. Returns 1 (to every thread) when the solve ends here.
+__device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double fn, double* red, double* sc,
+                      double* sh, double* smat) {
   const int head = (int)sc[0], count = (int)sc[1];
   const int keep = count < m ? count : m - 1;  // stored pairs that stay (the oldest is overwritten when full)
+  const double a = sc[3];
   double* Sh = L.S + (size_t)head * P;
   double* Yh = L.Y + (size_t)head * P;
-  for (int j = 0; j < keep; ++j) {
-    const int sl = (head - keep + j + 2 * m) % m;
-    const double* Sj = L.S + (size_t)sl * P;
-    const double* Yj = L.Y + (size_t)sl * P;
-    double xs = 0.0, xy = 0.0;
+  // per stored pair j: s_j^T y, y_j^T y, s_j^T g_t, y_j^T g_t (sums 4j..4j+3); then s^T y, y^T y,
+  // s^T g_t, y^T g_t, g_t^T g_t (sums 4 keep..4 keep + 4). The stored pairs go four per pass (one pass
+  // for m <= 5); the last pass also writes the new pair, phi and g.
+  for (int c0 = 0; c0 < (keep > 0 ? keep : 1); c0 += 4) {
+    const bool last = c0 + 4 >= keep;
+    double x[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q][0] = x[q][1] = x[q][2] = x[q][3] = 0.0;
+    double xsy = 0.0, xyy = 0.0, xsg = 0.0, xyg = 0.0, xgg = 0.0;
     for (int i = threadIdx.x; i < P; i += PWG) {
-      const double yi = L.gt[i] - L.g[i];
-      xs += Sj[i] * yi;
-      xy += Yj[i] * yi;
+      const double gti = L.gt[i], si = a * L.d[i], yi = gti - L.g[i];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = c0 + q;
+        if (j < keep) {
+          const int sl = (head - keep + j + 2 * m) % m;
+          const double Sj = L.S[(size_t)sl * P + i], Yj = L.Y[(size_t)sl * P + i];
+          x[q][0] += Sj * yi;
+          x[q][1] += Yj * yi;
+          x[q][2] += Sj * gti;
+          x[q][3] += Yj * gti;
+        }
+      }
+      if (last) {
+        xsy += si * yi;
+        xyy += yi * yi;
+        xsg += si * gti;
+        xyg += yi * gti;
+        xgg += gti * gti;
+        Sh[i] = si;
+        Yh[i] = yi;
+        L.phi[i] = L.phi[i] + si;
+        L.g[i] = gti;
+      }
     }
-    wave_put(xs, j, red);
-    wave_put(xy, keep + j, red);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (c0 + q < keep)
+        for (int r = 0; r < 4; ++r) wave_put(x[q][r], 4 * (c0 + q) + r, red);
+    if (last) {
+      wave_put(xsy, 4 * keep, red);
+      wave_put(xyy, 4 * keep + 1, red);
+      wave_put(xsg, 4 * keep + 2, red);
+      wave_put(xyg, 4 * keep + 3, red);
+      wave_put(xgg, 4 * keep + 4, red);
+    }
   }
-  double xsy = 0.0, xyy = 0.0;
-  for (int i = threadIdx.x; i < P; i += PWG) {
-    const double si = a * L.d[i], yi = L.gt[i] - L.g[i];
-    xsy += si * yi;
-    xyy += yi * yi;
-    Sh[i] = si;
-    Yh[i] = yi;
-    L.phi[i] = L.phi[i] + si;
-    L.g[i] = L.gt[i];
-  }
-  wave_put(xsy, 2 * keep, red);
-  wave_put(xyy, 2 * keep + 1, red);
+  double* sums = smat + SMAT;  // 4 keep + 5 values
   double* dots = sh;
-  bsum_finish(2 * keep + 2, red, dots);
+  double* coef = sh + MAXV;
+  __shared__ int fin, kdir, hdir;
+  bsum_finish(4 * keep + 5, red, sums);
   if (threadIdx.x == 0) {
     double* SY = sc + SC_HIST;
     double* YY = sc + SC_HIST + m * m;
-    const double sy = dots[2 * keep], yy = dots[2 * keep + 1];
+    const double f = sc[4];
+    const double sy = sums[4 * keep], yy = sums[4 * keep + 1];
+    int k = keep, nh = head;
     if (sy > 0.0) {
       for (int j = 0; j < keep; ++j) {
         const int sl = (head - keep + j + 2 * m) % m;
-        SY[sl * m + head] = dots[j];
-        YY[sl * m + head] = dots[keep + j];
-        YY[head * m + sl] = dots[keep + j];
+        SY[sl * m + head] = sums[4 * j];
+        YY[sl * m + head] = sums[4 * j + 1];
+        YY[head * m + sl] = sums[4 * j + 1];
       }
       SY[head * m + head] = sy;
       YY[head * m + head] = yy;
-      sc[0] = (head + 1) % m;
-      sc[1] = keep + 1;
-    } else {
-      sc[1] = keep;  // slot head no longer holds a stored pair
+      nh = (head + 1) % m;
+      k = keep + 1;
     }
+    sc[0] = nh;
+    sc[1] = k;  // without the new pair, slot head no longer holds a stored pair
     sc[9] = (f - fn <= ftol * fabs(fn)) ? 1.0 : 0.0;
     sc[4] = fn;
     sc[5] += 1.0;
     sc[6] = 1.0;
+    fin = (sc[5] >= (double)iters || (ftol > 0.0 && sc[9] != 0.0)) ? 1 : 0;
+    if (!fin) {
+      // a_j, b_j of the pairs in age order: the stored ones, then the new one
+      for (int j = 0; j < keep; ++j) {
+        dots[j] = sums[4 * j + 2];
+        dots[k + j] = sums[4 * j + 3];
+      }
+      if (k > keep) {
+        dots[keep] = sums[4 * keep + 2];
+        dots[k + keep] = sums[4 * keep + 3];
+      }
+      dots[2 * k] = sums[4 * keep + 4];
+      dir_solve(k, nh, m, sc, dots, coef, smat);
+      kdir = k;
+      hdir = nh;
+      sc[3] = 1.0;
+      sc[7] = 0.0;
+      if (!(sc[2] < 0.0)) fin = 1;  // zero gradient
+    }
   }
   __syncthreads();
+  if (fin) return 1;
+  dir_apply(L, P, m, kdir, hdir, coef);
+  return 0;
 }
 
 __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, double ftol, const double* gval,
                                                 int* skip) {
   __shared__ double red[(PWG / 64) * MAXV];
   __shared__ double sh[2 * MAXV];
-  __shared__ double smat[SMAT];
+  __shared__ double smat[SMAT + MAXV];
   __shared__ int stop;
   double* sc = L.sc;
   if (*skip) return;
   if (threadIdx.x == 0) stop = 0;
   __syncthreads();  // every thread has read *skip before thread 0 may set it
-  if (sc[8] != 0.0) decide(L, P, m, ftol, gval, red, sc, sh);
-  if (sc[6] != 0.0) {
-    if (sc[5] >= (double)iters || (ftol > 0.0 && sc[9] != 0.0)) {
-      if (threadIdx.x == 0) *skip = 1;
+  if (sc[8] != 0.0) {
+    const double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
+    if (fn <= f + 1e-4 * a * slope) {  // Armijo: accept, new direction, trial point at step 1
+      const int fin = accept(L, P, m, iters, ftol, fn, red, sc, sh, smat);
+      if (fin) {
+        if (threadIdx.x == 0) {
+          *skip = 1;
+          sc[8] = 0.0;
+        }
+        return;
+      }
+      if (threadIdx.x == 0) sc[8] = 1.0;
       return;
     }
-    direction(L, P, m, red, sc, sh, smat);
+    // rejected: halve the step along d
+    __syncthreads();
     if (threadIdx.x == 0) {
-      sc[3] = 1.0;
-      sc[7] = 0.0;
-      if (!(sc[2] < 0.0)) stop = 1;  // zero gradient
+      sc[6] = 0.0;
+      sc[7] += 1.0;
+      if (sc[7] >= 40.0) stop = 1;  // no sufficient decrease along d: stop
+      else sc[3] *= 0.5;
     }
-  } else if (threadIdx.x == 0) {
-    sc[7] += 1.0;
-    if (sc[7] >= 40.0) stop = 1;  // no sufficient decrease along d: stop
-    else sc[3] *= 0.5;
+    __syncthreads();
+    if (stop) {
+      if (threadIdx.x == 0) {
+        *skip = 1;
+        sc[8] = 0.0;
+      }
+      return;
+    }
+    const double as = sc[3];
+    for (int i = threadIdx.x; i < P; i += PWG) L.phit[i] = L.phi[i] + as * L.d[i];
+    return;
+  }
+  // no pending trial: the first direction after the start
+  if (sc[5] >= (double)iters) {
+    if (threadIdx.x == 0) *skip = 1;
+    return;
+  }
+  first_direction(L, P, m, red, sc, sh, smat);
+  if (threadIdx.x == 0) {
+    sc[3] = 1.0;
+    sc[7] = 0.0;
+    if (!(sc[2] < 0.0)) stop = 1;  // zero gradient
   }
   __syncthreads();
   if (stop) {
-    if (threadIdx.x == 0) {
-      *skip = 1;
-      sc[8] = 0.0;
-    }
+    if (threadIdx.x == 0) *skip = 1;
     return;
   }
-  const double a = sc[3];
-  for (int i = threadIdx.x; i < P; i += PWG) L.phit[i] = L.phi[i] + a * L.d[i];
   if (threadIdx.x == 0) sc[8] = 1.0;
 }
 
@@ -1263,4 +1314,14 @@ int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double
   return (int)hipGetLastError();
 }
 
+}  // namespace tmk
+
+namespace tmk {
+int phase_widen(const void* src, double* dst, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  k_widen<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((const float2*)src, (double2*)dst, n);
+  return (int)hipGetLastError();
+}
 }  // namespace tmk

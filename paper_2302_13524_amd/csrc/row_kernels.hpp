@@ -18,7 +18,8 @@ enum Mode : int {
   M_BACKPROP = 8,    // x = A^H sqrt(I) / (K N)                     -> tout
   M_AGRAD = 9,       // g = -2 A^H((sqrt(I) - |y|) y/|y|)           -> tout, sums {f_a}
   M_ALS = 10,        // amplitude cost at t + a_j d, a_j = 2^(j-3), j < 8 -> sums {f_a(t), f_a(t + a_j d)}
-  M_FILT = 11        // x = A^H(H .* A t) / (K N), H = yin [N] in natural frequency order -> tout
+  M_FILT = 11,       // x = A^H(H .* A t) / (K N), H = yin [N] in natural frequency order -> tout
+  M_ERC = 12         // for m = 1..K: t <- conj(psi_m) F^H(sqrt(I_m) y/|y|)/N, y = F(psi_m t) -> tout, sums
 };
 
 constexpr int NSUM = 9;
@@ -347,13 +348,13 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = cmul(x[i], gload(a.yin + KL(i)));
       }
-      if constexpr (MODE == M_ER || MODE == M_GRAD || MODE == M_SPEC || MODE == M_AGRAD) {
+      if constexpr (MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_SPEC || MODE == M_AGRAD) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           int k = KL(i);
           float iv = load_I<IT>(a.I, mbase + k);
           float n = norm2(x[i]);
-          if constexpr (MODE == M_ER) {
+          if constexpr (MODE == M_ER || MODE == M_ERC) {
             // keep the measured amplitude, keep the phase (y/|y| := 1 at y = 0)
             float amp = hw_sqrt(fmaxf(iv, 0.f));
             float rs = hw_rsq(n);
@@ -386,8 +387,15 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         }
       }
       fft_inverse<PL, T>(x, xb, ltid, tw);
+      if constexpr (MODE == M_ERC) {
+        // this mask's projection replaces the row before the next mask
+        const float inv_n = 1.f / (float)N;
 #pragma unroll
-      for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], gload(mk + E0(i)));
+        for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], gload(mk + E0(i))), inv_n);
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], gload(mk + E0(i)));
+      }
     }
   }
 
@@ -451,14 +459,19 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
     if constexpr (MODE == M_ER || MODE == M_BACKPROP || MODE == M_FILT) scale = 1.f / (float)(a.K * N);
     if constexpr (MODE == M_GRAD) scale = -4.f;
     if (valid) {
+      if constexpr (MODE == M_ERC) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i], scale));
+        for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), treg[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i], scale));
+      }
     }
-    if constexpr ((MODE == M_ER || MODE == M_GRAD || MODE == M_AGRAD) && SUMS) {
+    if constexpr ((MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_AGRAD) && SUMS) {
       float out[NSUM];
-      row_reduce<PL::T, WG, (MODE == M_ER) ? 2 : 1>(acc, red, tid, out);
+      row_reduce<PL::T, WG, (MODE == M_ER || MODE == M_ERC) ? 2 : 1>(acc, red, tid, out);
       if (valid && ltid == 0 && a.sums) {
-        if constexpr (MODE == M_ER) {
+        if constexpr (MODE == M_ER || MODE == M_ERC) {
           gw(a.sums)[prow * NSUM + 0] = out[0];
           gw(a.sums)[prow * NSUM + 1] = out[1];
         } else {

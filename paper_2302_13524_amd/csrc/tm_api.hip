@@ -353,8 +353,10 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   int r = check_dims(c, d, &fn);
   if (r) return r;
   if (!o) return fail(c, TM_EINVAL, "opts is NULL");
-  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_LBFGS && o->method != TM_METHOD_LBFGS_AMP)
+  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_LBFGS && o->method != TM_METHOD_LBFGS_AMP &&
+      o->method != TM_METHOD_ER_CYCLIC)
     return fail(c, TM_EINVAL, "method %d", o->method);
+  const bool er_like = o->method == TM_METHOD_ER || o->method == TM_METHOD_ER_CYCLIC;
   if (o->iters < 0) return fail(c, TM_EINVAL, "iters %d < 0", o->iters);
   if (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", o->I_dtype);
   if (o->start < TM_START_GIVEN || o->start > TM_START_SPECTRAL) return fail(c, TM_EINVAL, "start %d", o->start);
@@ -367,7 +369,9 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
       return fail(c, TM_EINVAL, "spectral_lower must be in [-1, spectral_momentum]");
   }
   if (!(o->er_momentum >= 0.f && o->er_momentum < 1.f)) return fail(c, TM_EINVAL, "er_momentum must be in [0, 1)");
-  if (o->method != TM_METHOD_ER && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
+  if (o->method == TM_METHOD_ER_CYCLIC && o->er_momentum != 0.f)
+    return fail(c, TM_EINVAL, "cyclic error reduction takes no momentum (er_momentum must be 0)");
+  if (!er_like && (o->lbfgs_m < 1 || o->lbfgs_m > 16))
     return fail(c, TM_EINVAL, "lbfgs_m %d outside 1..16", o->lbfgs_m);
   if (d.P == 0) return TM_OK;
   if (!masks || !I || !t) return fail(c, TM_EINVAL, "null pointer argument");
@@ -420,7 +424,19 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
 
   // ---- iterations
   int f_idx = -1, amp_idx = -1;
-  if (o->method == TM_METHOD_ER) {
+  if (o->method == TM_METHOD_ER_CYCLIC) {
+    a.tin = tt;
+    a.tout = tt;
+    for (int it = 0; it < o->iters; ++it) {
+      a.sums = (it == o->iters - 1) ? sums : nullptr;  // only the last sweep's sums are reported
+      r = run_row(c, fn, tmk::M_ERC, ibf, a, stream);
+      if (r) return r;
+    }
+    if (o->iters > 0) {
+      amp_idx = 0;
+      f_idx = 1;
+    }
+  } else if (o->method == TM_METHOD_ER) {
     a.tin = tt;
     a.tout = tt;
     const bool mom = o->er_momentum > 0.f && o->iters > 0;
@@ -506,6 +522,8 @@ static int phase_check(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
   return TM_OK;
 }
 
+static int blas_ready(tm_ctx* c, void* stream);
+
 static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
                          const tm_c32* theta, const tm_optics* o, tmk::PhaseDims& pd, tmk::PhaseWork& w,
                          void* stream) {
@@ -517,6 +535,22 @@ static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pi
   w.band = tmk::phase_band_plan(pd, po, c->phase_band);
   int e = tmk::phase_setup(pd, po, tm_est, theta, pix, w, stream);
   if (e) return hipfail(c, e, "phase setup");
+  // c[n][p] = sum_k theta[n][k] tm_est[p][k] in FP64 (exact products of the FP32 inputs): in
+  // column-major terms c^T (P x Nd) = TM^T Theta with TM (N x P) and Theta (N x Nd)
+  const int64_t nt = (int64_t)dd->P * dd->N, nth = (int64_t)dd->Nd * dd->N;
+  double* tm64 = (double*)ws_get(c, WS_PH_BASE + 2, (size_t)nt * 2 * sizeof(double));
+  double* th64 = (double*)ws_get(c, WS_PH_BASE + 3, (size_t)nth * 2 * sizeof(double));
+  if (!tm64 || !th64) return fail(c, TM_ENOMEM, "phase GEMM workspace");
+  int r = blas_ready(c, stream);
+  if (r) return r;
+  e = tmk::phase_widen(tm_est, tm64, nt, stream);
+  if (!e) e = tmk::phase_widen(theta, th64, nth, stream);
+  if (e) return hipfail(c, e, "widening the GEMM inputs");
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  if (rocblas_zgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, dd->P, dd->Nd, dd->N, &one,
+                    (const rocblas_double_complex*)tm64, dd->N, (const rocblas_double_complex*)th64, dd->N, &zero,
+                    (rocblas_double_complex*)w.c, dd->P) != rocblas_status_success)
+    return fail(c, TM_EHIP, "rocblas_zgemm failed");
   return TM_OK;
 }
 

@@ -158,6 +158,48 @@ def test_er_momentum_steps(ctx, n1, n2, P):
         tm.tm_retrieve(ctx, c64(masks), f32(I), c64(t0), n1, n2, tm.retrieve_opts("er", iters=1, er_momentum=1.0))
 
 
+@pytest.mark.parametrize("n1,n2,P", [(32, 32, 21), (8, 8, 150), (64, 128, 5), (1, 64, 13), (4, 16, 37)])
+def test_er_cyclic_sweeps(ctx, n1, n2, P):
+    # cyclic projections over the masks, sweep by sweep, and the last sweep's sums
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=913, noise=1e4)
+    t0 = T + 0.7 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(913, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    for iters in (1, 2, 4):
+        ref = rt.er_cyclic(m, n1, n2, Ir, t, iters)
+        tt = c64(t0)
+        raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("er_cyclic", iters=iters))
+        assert relerr(tt.cpu().numpy(), ref) < OPTOL * iters, iters
+        prev = rt.er_cyclic(m, n1, n2, Ir, t, iters - 1)
+        sa, si = rt.er_cyclic_sweep_sums(m, n1, n2, Ir, prev)
+        st = tm.decode_stats(raw)
+        assert np.max(np.abs(st.amp_res.numpy() - sa) / sa) < 1e-4
+        assert np.max(np.abs(st.f.numpy() - si) / si) < 1e-4
+    with pytest.raises(tm.TMError, match="momentum"):
+        tm.tm_retrieve(ctx, c64(masks), f32(I), c64(t0), n1, n2,
+                       tm.retrieve_opts("er_cyclic", iters=1, er_momentum=0.5))
+
+
+def test_er_cyclic_bf16_and_full_size_rows(ctx):
+    # BF16-stored intensities (rounded the same way on both sides), and the benchmark's
+    # 2286 x 8192 launch on sampled rows
+    n1, n2, K, P = 128, 64, 4, 2286
+    N = n1 * n2
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
+    g = np.random.default_rng(78)
+    T = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
+    T2 = (T + 0.5 * (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N)))).astype(np.complex64)
+    mk = c64(masks)
+    m = masks.astype(np.complex64).astype(np.complex128)
+    rows = np.unique(np.concatenate([np.sort(g.choice(P, 5, replace=False)), [0, P - 1]]))
+    for bf in (False, True):
+        I = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True, bf16=bf)
+        tt = c64(T2)
+        tm.tm_retrieve(ctx, mk, I, tt, n1, n2, tm.retrieve_opts("er_cyclic", iters=2, bf16=bf))
+        Ig = I.cpu()[torch.from_numpy(rows)].to(torch.float64).numpy()  # BF16 values are exact in FP64
+        ref = rt.er_cyclic(m, n1, n2, Ig, T2[rows].astype(np.complex128), 2)
+        assert relerr(tt.cpu().numpy()[rows], ref) < 2 * OPTOL, bf
+
+
 def test_backprop_start(ctx):
     n1, n2, P = 64, 32, 9
     masks, T, I, _ = problem(n1, n2, 4, P, cfg=908, noise=1e4)
@@ -199,7 +241,7 @@ def _fid(a, b):
     return rt.fidelity(a, b)
 
 
-@pytest.mark.parametrize("method,iters", [("er", 200), ("lbfgs", 100), ("lbfgs_amp", 60)])
+@pytest.mark.parametrize("method,iters", [("er", 200), ("lbfgs", 100), ("lbfgs_amp", 60), ("er_cyclic", 60)])
 def test_retrieve_noiseless_tiny(ctx, method, iters):
     # 8x8 modes, 32 rows, K = 4, noiseless: spectral start then the solver
     n1, n2, P = 8, 8, 32
@@ -215,6 +257,8 @@ def test_retrieve_noiseless_tiny(ctx, method, iters):
         ref = s0
         for _ in range(iters):
             ref = rt.er_step(opr, Ir, ref)
+    elif method == "er_cyclic":
+        ref = rt.er_cyclic(m, n1, n2, Ir, s0, iters)
     elif method == "lbfgs":
         ref, _ = rt.lbfgs(opr, Ir, s0, iters)
     else:
