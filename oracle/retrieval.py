@@ -25,7 +25,9 @@ Readings where the paper is silent:
     back-propagation start does not reach the truth at K = 4): power
     iteration on A^H diag(w) A with truncated weights
     w = min(I / mean(I_p), tau), optionally heavy-ball accelerated, then
-    scaled so that ||t||^2 = sum(I_p) / (K N) (Parseval, A^H A = K N I).
+    scaled so that ||t||^2 = sum(I_p) / (K N) (Parseval, A^H A = K N I);
+    or the same eigenvector estimated by Lanczos steps (the Ritz vector of
+    the largest Ritz value, no reorthogonalisation).
   * Fidelity |t_hat^H t|^2 / (||t_hat||^2 ||t||^2), invariant to a row's
     phase (Sec. 2.3, Eq. phaseoffset) and scale.
 """
@@ -217,6 +219,51 @@ def spectral_start(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3
         v = x / n
     scale = np.sqrt(np.sum(I.reshape(I.shape[0], -1), axis=1) / (op.K * op.N))
     return v * scale[:, None]
+
+
+def spectral_lanczos(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3.0, basis: bool = False):
+    """Truncated spectral start by the Lanczos method (a choice made here):
+    `iters` Lanczos steps on M = A^H diag(w) A (w as in spectral_start) from
+    v_1 = v0 / ||v0||,
+        x = M v_j - alpha_j v_j - beta_j v_{j-1},  alpha_j = Re(v_j^H M v_j),
+        beta_{j+1} = ||x||,  v_{j+1} = x / beta_{j+1}   (beta_1 = 0),
+    then the eigenvector y of the largest eigenvalue of the real symmetric
+    tridiagonal T (diagonal alpha_1..alpha_k, off-diagonal beta_2..beta_k),
+    sign fixed by y_1 >= 0, and t = sum_j y_j v_j, normalised and scaled to
+    ||t||^2 = sum(I_p) / (K N). No reorthogonalisation. With basis=True also
+    returns (alpha [P][k], beta [P][k] (beta[:, j] = beta_{j+1}), V [k+1][P][N])."""
+    w = spectral_weights(I, tau)
+    v = np.array(v0, dtype=np.complex128)
+    P = v.shape[0]
+    n = np.linalg.norm(v, axis=1)
+    v = v / np.where(n > 0, n, 1.0)[:, None]
+    vp = np.zeros_like(v)
+    bp = np.zeros(P)
+    V = [v]
+    al = np.zeros((P, iters))
+    be = np.zeros((P, iters))
+    for j in range(iters):
+        Mv = op.adjoint(w * op.forward(v))
+        a = rdot(v, Mv)
+        x = Mv - a[:, None] * v - bp[:, None] * vp
+        b = np.linalg.norm(x, axis=1)
+        al[:, j] = a
+        be[:, j] = b
+        vp, bp = v, b
+        v = x / np.where(b > 0, b, 1.0)[:, None]
+        V.append(v)
+    t = np.zeros_like(v)
+    for p in range(P):
+        Tm = np.diag(al[p]) + np.diag(be[p, :-1], 1) + np.diag(be[p, :-1], -1)
+        ev, vec = np.linalg.eigh(Tm)
+        y = vec[:, -1] * (1.0 if vec[0, -1] >= 0 else -1.0)
+        t[p] = sum(y[j] * V[j][p] for j in range(iters))
+    nt = np.linalg.norm(t, axis=1)
+    scale = np.sqrt(np.sum(I.reshape(P, -1), axis=1) / (op.K * op.N))
+    t = t / np.where(nt > 0, nt, 1.0)[:, None] * scale[:, None]
+    if basis:
+        return t, al, be, np.array(V)
+    return t
 
 
 def fidelity(t_hat: np.ndarray, t: np.ndarray) -> np.ndarray:

@@ -520,3 +520,75 @@ def test_cyclic_er_needs_fewer_sweeps_than_parallel_er():
         par = rt.er_step(op, I, par)
     cyc = rt.er_cyclic(masks, n1, n2, I, t0, 5)
     assert rt.fidelity(cyc, T).mean() > rt.fidelity(par, T).mean()
+
+
+def _dense_M(masks, n1, n2, I, tau):
+    A = ops.probing_matrix(masks, n1, n2)
+    w = rt.spectral_weights(I, tau)
+    return [np.conj(A).T @ (w[p].reshape(-1)[:, None] * A) for p in range(I.shape[0])]
+
+
+def test_lanczos_start_equals_top_eigenvector_of_dense_M():
+    # with k = N steps the Krylov space is everything: the Ritz vector is the
+    # top eigenvector of the dense A^H diag(w) A (numpy eigh), up to phase
+    n1, n2, K, P = 2, 4, 4, 3
+    N = n1 * n2
+    masks, t, g = small_problem(n1, n2, K=K, P=P, seed=51)
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, t)
+    v0 = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))) / np.sqrt(2)
+    tl = rt.spectral_lanczos(op, I, v0, N, tau=3.0)
+    Ms = _dense_M(masks, n1, n2, I, 3.0)
+    for p in range(P):
+        ev, vec = np.linalg.eigh(Ms[p])
+        top = vec[:, -1]
+        c = abs(np.vdot(top, tl[p])) / np.linalg.norm(tl[p])
+        assert c > 1 - 1e-9
+        assert abs(np.linalg.norm(tl[p]) ** 2 - I[p].sum() / (K * N)) < 1e-9 * I[p].sum()
+
+
+def test_lanczos_basis_is_orthonormal_and_tridiagonalises_M():
+    # exact-arithmetic Lanczos facts on a small problem (few steps, FP64):
+    # V^H V = I and V^H M V = T (alpha on the diagonal, beta beside it);
+    # the top Ritz value grows with k and stays below lambda_max; one step
+    # returns the normalised seed
+    n1, n2, K, P = 4, 4, 4, 2
+    N = n1 * n2
+    masks, t, g = small_problem(n1, n2, K=K, P=P, seed=52)
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, t)
+    v0 = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))) / np.sqrt(2)
+    k = 6
+    _, al, be, V = rt.spectral_lanczos(op, I, v0, k, tau=3.0, basis=True)
+    Ms = _dense_M(masks, n1, n2, I, 3.0)
+    for p in range(P):
+        Vp = V[:k, p, :].T
+        assert np.max(np.abs(np.conj(Vp).T @ Vp - np.eye(k))) < 1e-10
+        Tm = np.diag(al[p]) + np.diag(be[p, :-1], 1) + np.diag(be[p, :-1], -1)
+        assert np.max(np.abs(np.conj(Vp).T @ Ms[p] @ Vp - Tm)) < 1e-9 * np.max(np.abs(Tm))
+        lam = np.linalg.eigvalsh(Ms[p])[-1]
+        ritz = [np.linalg.eigvalsh(Tm[:j, :j])[-1] for j in range(1, k + 1)]
+        assert all(ritz[j] <= ritz[j + 1] + 1e-12 * lam for j in range(k - 1)) and ritz[-1] <= lam * (1 + 1e-12)
+    t1 = rt.spectral_lanczos(op, I, v0, 1, tau=3.0)
+    ref = v0 / np.linalg.norm(v0, axis=1)[:, None] * np.sqrt(I.reshape(P, -1).sum(axis=1) / (K * N))[:, None]
+    assert np.max(np.abs(t1 - ref)) < 1e-12
+
+
+def test_lanczos_start_beats_power_iteration_at_equal_steps():
+    # same number of operator applications: the Lanczos Ritz vector is closer
+    # to the top eigenvector than plain power iteration's iterate
+    n1 = n2 = 8
+    N, K, P = n1 * n2, 4, 6
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(53, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(53, 1))
+    op = ops.FFTOp(masks, n1, n2)
+    I = ops.intensities(op, T)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(53, 3))
+    Ms = _dense_M(masks, n1, n2, I, 3.0)
+    tl = rt.spectral_lanczos(op, I, v0, 8, tau=3.0)
+    tp = rt.spectral_start(op, I, v0, 8, tau=3.0)
+    for p in range(P):
+        top = np.linalg.eigh(Ms[p])[1][:, -1]
+        cl = abs(np.vdot(top, tl[p])) / np.linalg.norm(tl[p])
+        cp = abs(np.vdot(top, tp[p])) / np.linalg.norm(tp[p])
+        assert cl >= cp - 1e-12
