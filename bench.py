@@ -49,7 +49,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--spectral-iters", type=int, default=24)
+    ap.add_argument("--batch-spectral-iters", type=int, default=24,
+                    help="heavy-ball spectral steps in the uneven batch")
+    ap.add_argument("--start", choices=["spectral", "lanczos"], default="lanczos",
+                    help="spectral start by heavy-ball power steps or by Lanczos steps")
+    ap.add_argument("--spectral-iters", type=int, default=None,
+                    help="steps of the spectral start (default 24 heavy-ball or 18 Lanczos)")
     ap.add_argument("--spectral-tau", type=float, default=2.5, help="truncation of the spectral weights")
     ap.add_argument("--spectral-momentum", type=float, default=0.99,
                     help="heavy-ball factor c of the spectral start")
@@ -86,7 +91,10 @@ def parse():
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
                                                         "OUT"),
                     help="summarise rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs into the traffic file (no GPU)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.spectral_iters is None:
+        args.spectral_iters = 18 if args.start == "lanczos" else 24
+    return args
 
 
 KERNEL_SOURCES = ["fft_core.hpp", "row_kernels.hpp", "grid_inst.hip", "grids.hpp"]
@@ -147,7 +155,7 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
     res = {"P": 2286, "N": 8192, "sources_sha256": sources_digest(),
            "copy": {"kernel": big, "bytes": 512 * 2**20, "fetch_kib": cf[big][0], "write_kib": cw[big][0]},
            "kernels": {}}
-    for key, mode in (("spectral", 5), ("er", 3), ("er_cyclic", 12)):
+    for key, mode in (("spectral", 5), ("er", 3), ("er_cyclic", 12), ("lanczos", 13)):
         if not any(f", {mode}, float, " in k for k in f):
             continue
         fv, fn = pick(f, mode)
@@ -236,13 +244,14 @@ def main():
     beta = args.er_momentum if solver == "er" else 0.0
     er_mode = 3 if solver == "er" else 12  # row-kernel mode of the solver's iteration
 
-    def opts(method, iters, start="spectral"):
+    def opts(method, iters, start=None):
+        start = args.start if start is None else start
         return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, spectral_tau=args.spectral_tau,
                                 spectral_momentum=args.spectral_momentum,
                                 spectral_lower=args.spectral_lower,
                                 er_momentum=beta if method == "er" else 0.0)
 
-    def sopts(iters, start="spectral"):
+    def sopts(iters, start=None):
         return opts(solver, iters, start) if solver != "er" else opts("er", iters, start)
 
     # ---- untimed instrumented run: iterations to mean fidelity 0.99 (each count run
@@ -320,7 +329,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
     er_ms, er_n = tm.tm_profile_query(ctx, er_mode)
-    sp_ms, sp_n = tm.tm_profile_query(ctx, 5)
+    sp_mode = 13 if args.start == "lanczos" else 5  # row-kernel mode of the spectral start's step
+    sp_ms, sp_n = tm.tm_profile_query(ctx, sp_mode)
     rs_ms, rs_n = tm.tm_profile_query(ctx, 7)
     tm.tm_profile_enable(ctx, False)
     ms_step = elapsed * 1e3 / args.steps
@@ -358,8 +368,10 @@ def main():
     # against the vector peak; the HBM view carries the algorithmic bytes and the counter-measured traffic.
     flops_row = 2 * K * 5 * N * np.log2(N) + 20 * K * N  # 2K FFTs + pointwise per row-step
     kernels = {
-        "spectral": {"mode": 5, "ms": sp_ms, "n": sp_n,
-                     "name": "row_kernel<M_SPEC> (mask*FFT, truncated weights, IFFT, conj-mask sum, heavy-ball)",
+        "spectral": {"mode": sp_mode, "ms": sp_ms, "n": sp_n,
+                     "name": "row_kernel<M_SPEC> (mask*FFT, truncated weights, IFFT, conj-mask sum, heavy-ball)"
+                             if sp_mode == 5 else
+                             "row_kernel<M_LANCZOS> (mask*FFT, truncated weights, IFFT, conj-mask sum, Lanczos step)",
                      # read I, v and the previous iterate, write the new v
                      "bytes": P * (K * N * 4 + 3 * N * 8)},
         "er": {"mode": er_mode, "ms": er_ms, "n": er_n,
@@ -374,7 +386,9 @@ def main():
         avg = kv["ms"] / max(kv["n"], 1)
         tf = P * flops_row / (avg * 1e-3) / 1e12
         gbs = kv["bytes"] / (avg * 1e-3) / 1e9
-        tr = traffic.get("er_cyclic" if key == "er" and solver == "er_cyclic" else key) if traffic else None
+        tkey = {"er": "er_cyclic" if solver == "er_cyclic" else "er",
+                "spectral": "lanczos" if sp_mode == 13 else "spectral"}[key]
+        tr = traffic.get(tkey) if traffic else None
         roofs[key] = {
             "alu": {"bound": "alu", "kernel": kv["name"], "achieved": round(tf, 2), "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
@@ -404,7 +418,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "P": P, "N": N, "grid": [n1, n2], "K": K,
-                   "start": f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
+                   "start": f"truncated spectral (tau {args.spectral_tau}), {sp} Lanczos steps" if args.start == "lanczos"
+                            else f"truncated spectral (tau {args.spectral_tau}), {sp} heavy-ball steps "
                             f"(c {args.spectral_momentum}, interval [{args.spectral_lower}, c] lambda)",
                    "solver": (f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction")
                              if solver == "er" else "cyclic error reduction (one mask projection at a time)",
@@ -465,7 +480,7 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
                                                    spectral_lower=args.spectral_lower,
-                                                   er_momentum=beta, method=solver)
+                                                   er_momentum=beta, method=solver, start=args.start)
     torch.cuda.synchronize()
     a = time.perf_counter()
     for _ in range(3):
@@ -473,7 +488,7 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
                                                    spectral_lower=args.spectral_lower,
-                                                   er_momentum=beta, method=solver)
+                                                   er_momentum=beta, method=solver, start=args.start)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) * 1e3 / 3
     return {"rows_per_s": round(P / (ms * 1e-3), 1), "retrieval_ms": round(ms, 3),
@@ -671,7 +686,7 @@ def batch_variant(ctx, args):
         truths.append(T / torch.linalg.vector_norm(T, dim=1, keepdim=True))
     log(f"batch inputs {time.perf_counter() - a:.1f}s")
     tuned = {f"{n1}x{n2}": tm.autotune(ctx, n1, n2, 4, 512, bf16=True) for n1, n2, _, _ in shapes[:4]}
-    iters, sp, beta = args.batch_iters, args.spectral_iters, args.er_momentum
+    iters, sp, beta = args.batch_iters, args.batch_spectral_iters, args.er_momentum
     b = tm.Batch(ctx, probs, tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True,
                                               spectral_tau=args.spectral_tau,
                                               spectral_momentum=args.spectral_momentum,
@@ -718,8 +733,11 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver="er
 
     def run(rows):
         I = I_np[rows].astype(np.float64)
-        t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau,
-                              momentum=args.spectral_momentum, lower=args.spectral_lower)
+        if args.start == "lanczos":
+            t = rt.spectral_lanczos(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau)
+        else:
+            t = rt.spectral_start(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau,
+                                  momentum=args.spectral_momentum, lower=args.spectral_lower)
         if solver == "er_cyclic":
             return rt.er_cyclic(masks, n1, n2, I, t, n_er)
         return rt.er_accelerated(op, I, t, n_er, beta)

@@ -134,7 +134,12 @@ enum { TM_METHOD_ER = 0, TM_METHOD_LBFGS = 1, TM_METHOD_LBFGS_AMP = 2, TM_METHOD
 enum {
   TM_START_GIVEN = 0,     /* use t as passed in                                  */
   TM_START_BACKPROP = 1,  /* t = A^H sqrt(I) / (K N)          (Eq. backpropagation) */
-  TM_START_SPECTRAL = 2   /* truncated spectral start seeded with the t passed in  */
+  TM_START_SPECTRAL = 2,  /* truncated spectral start seeded with the t passed in  */
+  TM_START_LANCZOS = 3    /* the same eigenvector by spectral_iters (1..64) Lanczos
+                             steps on A^H diag(w) A from the t passed in: Ritz vector
+                             of the largest Ritz value (tridiagonal eigenproblem in
+                             FP64), scaled to ||t||^2 = sum(I)/(K N); workspace
+                             spectral_iters P N complex floats                       */
 };
 
 typedef struct {
@@ -143,7 +148,7 @@ typedef struct {
   int32_t lbfgs_m;         /* L-BFGS memory, 1..16 (default 5)                           */
   int32_t I_dtype;         /* TM_F32 or TM_BF16                                          */
   int32_t start;           /* TM_START_*                                                 */
-  int32_t spectral_iters;  /* power-iteration steps for TM_START_SPECTRAL                */
+  int32_t spectral_iters;  /* power-iteration (or Lanczos) steps of the spectral start     */
   float spectral_tau;      /* weight truncation w = min(I/mean(I_p), tau), e.g. 3        */
   float spectral_momentum; /* heavy-ball factor c in [0, 1): beta = (c lambda)^2/4       */
   float er_momentum;       /* ER only: Nesterov factor b in [0, 1): t <- ER(t + b (t - t_prev)); 0 = plain ER */

@@ -23,7 +23,7 @@ TM_OK, TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENOMEM = 0, -1, -2, -3, -4
 TM_F32, TM_BF16 = 0, 1
 TM_FIELD, TM_INTENSITY = 0, 1
 TM_METHOD_ER, TM_METHOD_LBFGS, TM_METHOD_LBFGS_AMP, TM_METHOD_ER_CYCLIC = 0, 1, 2, 3
-TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL = 0, 1, 2
+TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL, TM_START_LANCZOS = 0, 1, 2, 3
 
 EXPORTED = (
     "tm_create", "tm_destroy", "tm_last_error", "tm_grid_supported", "tm_forward", "tm_adjoint",
@@ -36,7 +36,7 @@ EXPORTED = (
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop", 9: "amp_gradient", 10: "amp_line_sums",
-              11: "filter", 12: "er_cyclic"}
+              11: "filter", 12: "er_cyclic", 13: "lanczos"}
 
 
 class tm_dims(ctypes.Structure):
@@ -283,7 +283,8 @@ def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", 
                   spectral_lower=None) -> tm_retrieve_opts:
     m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS, "lbfgs_amp": TM_METHOD_LBFGS_AMP,
          "er_cyclic": TM_METHOD_ER_CYCLIC}[method]
-    s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL}[start]
+    s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL,
+         "lanczos": TM_START_LANCZOS}[start]
     return tm_retrieve_opts(m, int(iters), int(lbfgs_m), TM_BF16 if bf16 else TM_F32, s, int(spectral_iters),
                             float(spectral_tau), float(spectral_momentum), float(er_momentum),
                             float(-spectral_momentum if spectral_lower is None else spectral_lower))

@@ -15,4 +15,11 @@ int launch_copy(void* dst, const void* src, int64_t bytes, void* stream);
 int launch_fill_hash(float* p, int64_t n, uint32_t seed, float lo, float hi, void* stream);
 int launch_finalize(void* stats, int P, const double* sums64, const float* sums, int nsum,
                     int f_idx, int amp_idx, int iters, double rho_flag, void* stream);
+// Lanczos start: hist [k][P][2] (alpha_j, beta_{j+1}) -> y [P][k], the unit
+// eigenvector of the largest eigenvalue of each row's tridiagonal T (FP64,
+// bisection on Sturm counts, then inverse iteration), sign y_0 >= 0.
+constexpr int LZ_MAX = 64;
+int launch_lz_ritz(const float* hist, int k, int P, double* y, void* stream);
+// t[p] <- sum_{j<k} y[p][j] V_j[p] with V_0 = t (in place) and V_j = Vw + (j - 1) P N.
+int launch_lz_combine(void* t, const void* Vw, const double* y, int k, int P, int N, void* stream);
 }  // namespace tmk

@@ -169,4 +169,106 @@ int launch_finalize(void* st, int P, const double* sums64, const float* sums, in
   return (int)hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- Lanczos start
+namespace {
+
+// number of eigenvalues below x of the symmetric tridiagonal (al, be[i] coupling i - 1 and i)
+__device__ int sturm_below(const double* al, const double* be, int k, double x) {
+  int c = 0;
+  double q = 1.0;
+  for (int i = 0; i < k; ++i) {
+    q = (al[i] - x) - (i ? be[i] * be[i] / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+__global__ void __launch_bounds__(64) k_lz_ritz(const float* hist, int k, int P, double* y) {
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  if (p >= P) return;
+  double al[LZ_MAX], be[LZ_MAX], cp[LZ_MAX], z[LZ_MAX];
+  for (int i = 0; i < k; ++i) {
+    al[i] = (double)hist[((size_t)i * P + p) * 2];
+    be[i] = i ? (double)hist[((size_t)(i - 1) * P + p) * 2 + 1] : 0.0;
+  }
+  // Gershgorin interval, then bisection for the largest eigenvalue (count below hi == k)
+  double lo = al[0], hi = al[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = fabs(be[i]) + (i + 1 < k ? fabs(be[i + 1]) : 0.0);
+    lo = fmin(lo, al[i] - r);
+    hi = fmax(hi, al[i] + r);
+  }
+  const double mag = fmax(fabs(lo), fabs(hi));
+  if (!(mag > 1e-290)) {  // T = 0 (a zero row): any unit vector; take the seed
+    for (int i = 0; i < k; ++i) y[(size_t)p * k + i] = i == 0 ? 1.0 : 0.0;
+    return;
+  }
+  const double span = hi - lo;
+  hi += 1e-12 * span + 1e-15 * mag;
+  for (int it = 0; it < 200 && hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(al, be, k, mid) == k) hi = mid;
+    else lo = mid;
+  }
+  // inverse iteration just above the largest eigenvalue: T - mu I is negative
+  // definite, so the elimination needs no pivoting
+  const double mu = hi + 1e-10 * span + 1e-12 * mag;
+  for (int i = 0; i < k; ++i) z[i] = 1.0;
+  for (int rep = 0; rep < 3; ++rep) {
+    double m = al[0] - mu;
+    cp[0] = (k > 1 ? be[1] : 0.0) / m;
+    z[0] = z[0] / m;
+    for (int i = 1; i < k; ++i) {
+      m = (al[i] - mu) - be[i] * cp[i - 1];
+      cp[i] = (i + 1 < k ? be[i + 1] : 0.0) / m;
+      z[i] = (z[i] - be[i] * z[i - 1]) / m;
+    }
+    for (int i = k - 2; i >= 0; --i) z[i] -= cp[i] * z[i + 1];
+    double n = 0.0;
+    for (int i = 0; i < k; ++i) n += z[i] * z[i];
+    n = n > 0.0 ? 1.0 / sqrt(n) : 0.0;
+    for (int i = 0; i < k; ++i) z[i] *= n;
+  }
+  const double sg = z[0] < 0.0 ? -1.0 : 1.0;
+  for (int i = 0; i < k; ++i) y[(size_t)p * k + i] = sg * z[i];
+}
+
+__global__ void __launch_bounds__(256) k_lz_combine(float2* t, const float2* Vw, const double* y, int k, int P,
+                                                    int N) {
+  const int64_t n = (int64_t)P * N;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const int64_t p = i / N;
+    const double* yp = y + p * k;
+    const float2 v0 = t[i];
+    double ax = yp[0] * v0.x, ay = yp[0] * v0.y;
+    for (int j = 1; j < k; ++j) {
+      const float2 v = Vw[(size_t)(j - 1) * n + i];
+      ax += yp[j] * v.x;
+      ay += yp[j] * v.y;
+    }
+    t[i] = make_float2((float)ax, (float)ay);
+  }
+}
+
+}  // namespace
+
+int launch_lz_ritz(const float* hist, int k, int P, double* y, void* stream) {
+  if (P <= 0) return 0;
+  if (k < 1 || k > LZ_MAX) return (int)hipErrorInvalidValue;
+  k_lz_ritz<<<(P + 63) / 64, 64, 0, (hipStream_t)stream>>>(hist, k, P, y);
+  return (int)hipGetLastError();
+}
+
+int launch_lz_combine(void* t, const void* Vw, const double* y, int k, int P, int N, void* stream) {
+  if (P <= 0) return 0;
+  const int64_t n = (int64_t)P * N;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  k_lz_combine<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((float2*)t, (const float2*)Vw, y, k, P, N);
+  return (int)hipGetLastError();
+}
+
 }  // namespace tmk

@@ -75,6 +75,8 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.momentum = b.momentum;
     a.spec_lower = b.lower;
     a.er_beta = mom ? b.er_beta : 0.f;
+    a.lz_bprev = nullptr;
+    a.lz_out = nullptr;
     a.out_bf16 = 0;
     a.tw32 = b.tw32;
     a.tw64 = nullptr;

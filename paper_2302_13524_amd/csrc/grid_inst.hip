@@ -36,6 +36,7 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
       else row_kernel<PLg, M_GRAD, IT, false><<<grid, block, 0, s>>>(a);
       break;
     case M_SPEC: row_kernel<PLg, M_SPEC, IT><<<grid, block, 0, s>>>(a); break;
+    case M_LANCZOS: row_kernel<PLg, M_LANCZOS, IT><<<grid, block, 0, s>>>(a); break;
     case M_LS: row_kernel<PLg, M_LS, IT><<<grid, block, 0, s>>>(a); break;
     case M_AGRAD:
       if (a.sums) row_kernel<PLg, M_AGRAD, IT, true><<<grid, block, 0, s>>>(a);

@@ -19,7 +19,8 @@ enum Mode : int {
   M_AGRAD = 9,       // g = -2 A^H((sqrt(I) - |y|) y/|y|)           -> tout, sums {f_a}
   M_ALS = 10,        // amplitude cost at t + a_j d, a_j = 2^(j-3), j < 8 -> sums {f_a(t), f_a(t + a_j d)}
   M_FILT = 11,       // x = A^H(H .* A t) / (K N), H = yin [N] in natural frequency order -> tout
-  M_ERC = 12         // for m = 1..K: t <- conj(psi_m) F^H(sqrt(I_m) y/|y|)/N, y = F(psi_m t) -> tout, sums
+  M_ERC = 12,        // for m = 1..K: t <- conj(psi_m) F^H(sqrt(I_m) y/|y|)/N, y = F(psi_m t) -> tout, sums
+  M_LANCZOS = 13     // Lanczos step on A^H diag(w) A: v_next = (M v - alpha v - beta v_prev)/||.|| -> tout, lz_out
 };
 
 constexpr int NSUM = 9;
@@ -42,6 +43,8 @@ struct RowArgs {
   float momentum;          // M_SPEC heavy-ball factor c
   float spec_lower;        // M_SPEC lower end l of the rest of the spectrum (fraction of lambda)
   float er_beta;           // M_ER Nesterov factor b: iterate from z = tin + b (tin - din), din = t_prev
+  const float* lz_bprev;   // M_LANCZOS: previous step's [P][2] (alpha, beta); beta is this step's beta, or null
+  float* lz_out;           // M_LANCZOS: [P][2] (alpha, ||x||) of this step
   int out_bf16;            // M_FWD_INT output type
   const cx<float>* tw32;   // twiddle tables, table of length L at offset L-1
   const cx<double>* tw64;
@@ -261,7 +264,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
   for (int i = 0; i < NSUM; ++i) acc[i] = KSum{0.f, 0.f};
 
   float inv_mean = 0.f;
-  if constexpr (MODE == M_SPEC) {
+  if constexpr (MODE == M_SPEC || MODE == M_LANCZOS) {
     float m = valid ? gc(a.rowmean)[prow] : 1.f;
     inv_mean = (m > 0.f) ? 1.f / m : 1.f;
   }
@@ -348,7 +351,8 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = cmul(x[i], gload(a.yin + KL(i)));
       }
-      if constexpr (MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_SPEC || MODE == M_AGRAD) {
+      if constexpr (MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_SPEC || MODE == M_LANCZOS ||
+                    MODE == M_AGRAD) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           int k = KL(i);
@@ -408,6 +412,40 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
     if (valid && ltid == 0) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
+    }
+  } else if constexpr (MODE == M_LANCZOS) {
+    // alpha = Re <v, M v>; x = M v - alpha v - beta v_prev with beta = ||x|| of the
+    // previous step (0 at the first, where there is no v_prev); v_next = x / ||x||.
+    // ||x|| is summed from x itself (a second reduction), not expanded.
+    KSum q[1];
+    q[0] = KSum{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < E; ++i) q[0].add(TROW(i).x * g[i].x + TROW(i).y * g[i].y);
+    float o1[1];
+    row_reduce<PL::T, WG, 1>(q, red, tid, o1);
+    const float al = o1[0];
+    if (a.lz_bprev) {
+      const float bp = valid ? gc(a.lz_bprev)[prow * 2 + 1] : 0.f;
+#pragma unroll
+      for (int i = 0; i < E; ++i) g[i] = g[i] - scl(TROW(i), al) - scl(gload(drow + E0(i)), bp);
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) g[i] = g[i] - scl(TROW(i), al);
+    }
+    q[0] = KSum{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < E; ++i) q[0].add(norm2(g[i]));
+    float o2[1];
+    row_reduce<PL::T, WG, 1>(q, red, tid, o2);
+    const float nrm = sqrtf(fmaxf(o2[0], 0.f));
+    const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), scl(g[i], inv));
+      if (ltid == 0) {
+        gw(a.lz_out)[prow * 2 + 0] = al;
+        gw(a.lz_out)[prow * 2 + 1] = nrm;
+      }
     }
   } else if constexpr (MODE == M_SPEC) {
     // lambda = Re <v, M v> (v has unit norm); x = (M - sigma) v - beta v_prev

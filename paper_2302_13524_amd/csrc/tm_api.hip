@@ -107,7 +107,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
-  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_PRE_PART,
+  WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_LZ_V, WS_LZ_H, WS_LZ_Y, WS_PRE_PART,
   WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E, WS_DENSE_Y, WS_PROP_X, WS_PROP_H, WS_PROP_ONES,
   WS_PH_BASE = 100
 };
@@ -359,7 +359,12 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   const bool er_like = o->method == TM_METHOD_ER || o->method == TM_METHOD_ER_CYCLIC;
   if (o->iters < 0) return fail(c, TM_EINVAL, "iters %d < 0", o->iters);
   if (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", o->I_dtype);
-  if (o->start < TM_START_GIVEN || o->start > TM_START_SPECTRAL) return fail(c, TM_EINVAL, "start %d", o->start);
+  if (o->start < TM_START_GIVEN || o->start > TM_START_LANCZOS) return fail(c, TM_EINVAL, "start %d", o->start);
+  if (o->start == TM_START_LANCZOS) {
+    if (o->spectral_iters < 1 || o->spectral_iters > tmk::LZ_MAX)
+      return fail(c, TM_EINVAL, "Lanczos steps (spectral_iters) %d outside 1..%d", o->spectral_iters, tmk::LZ_MAX);
+    if (!(o->spectral_tau > 0.f)) return fail(c, TM_EINVAL, "spectral_tau must be > 0");
+  }
   if (o->start == TM_START_SPECTRAL) {
     if (o->spectral_iters < 0) return fail(c, TM_EINVAL, "spectral_iters %d", o->spectral_iters);
     if (!(o->spectral_tau > 0.f)) return fail(c, TM_EINVAL, "spectral_tau must be > 0");
@@ -420,6 +425,36 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     if (o->spectral_iters & 1) e = tmk::launch_copy(t, vprev, (int64_t)d.P * N * sizeof(tm_c32), stream);
     if (!e) e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
     if (e) return hipfail(c, e, "spectral scale");
+  } else if (o->start == TM_START_LANCZOS) {
+    // v_1 = seed / ||seed|| in t; v_2 .. v_{k+1} in the workspace; (alpha, beta) per step and row
+    const int k = o->spectral_iters;
+    const size_t rowsz = (size_t)d.P * N;
+    double* rowsum = (double*)ws_get(c, WS_ROWSUM, (size_t)d.P * sizeof(double));
+    float* rowmean = (float*)ws_get(c, WS_ROWMEAN, (size_t)d.P * sizeof(float));
+    tmk::cx<float>* Vw = (tmk::cx<float>*)ws_get(c, WS_LZ_V, (size_t)k * rowsz * sizeof(tm_c32));
+    float* hist = (float*)ws_get(c, WS_LZ_H, (size_t)k * d.P * 2 * sizeof(float));
+    double* y = (double*)ws_get(c, WS_LZ_Y, (size_t)k * d.P * sizeof(double));
+    if (!rowsum || !rowmean || !Vw || !hist || !y) return fail(c, TM_ENOMEM, "Lanczos workspace");
+    int e = tmk::launch_row_isum(I, ibf, (int64_t)d.K * N, d.P, rowsum, rowmean, stream);
+    if (!e) e = tmk::launch_row_rescale(t, N, d.P, 0, nullptr, 1.0, stream);
+    if (e) return hipfail(c, e, "Lanczos setup");
+    auto V = [&](int j) { return j == 0 ? tt : Vw + (size_t)(j - 1) * rowsz; };
+    tmk::RowArgs s = a;
+    s.rowmean = rowmean;
+    s.tau = o->spectral_tau;
+    for (int j = 0; j < k; ++j) {
+      s.tin = V(j);
+      s.din = V(j > 0 ? j - 1 : 0);
+      s.tout = V(j + 1);
+      s.lz_bprev = j > 0 ? hist + (size_t)(j - 1) * d.P * 2 : nullptr;
+      s.lz_out = hist + (size_t)j * d.P * 2;
+      r = run_row(c, fn, tmk::M_LANCZOS, ibf, s, stream);
+      if (r) return r;
+    }
+    e = tmk::launch_lz_ritz(hist, k, d.P, y, stream);
+    if (!e) e = tmk::launch_lz_combine(t, Vw, y, k, d.P, N, stream);
+    if (!e) e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
+    if (e) return hipfail(c, e, "Lanczos Ritz vector");
   }
 
   // ---- iterations

@@ -61,7 +61,7 @@ def train(ctx, net: MLP, masks, n1, n2, rows=200_000, epochs=3, batch=512, lr=1e
 
 def retrieve_with_fallback(ctx, net: MLP, masks, I, n1, n2, iters, seed_rows, spectral_iters=30,
                            spectral_momentum=0.98, rho_flag=1e-2, er_momentum=0.0, spectral_tau=3.0,
-                           spectral_lower=None, method="er"):
+                           spectral_lower=None, method="er", start="spectral"):
     """Learned start -> `iters` iterations of the error-reduction `method` -> rows whose FP64
     residual exceeds rho_flag are redone from the spectral start (seeded with
     `seed_rows`). Returns (t, number of rows redone)."""
@@ -78,7 +78,7 @@ def retrieve_with_fallback(ctx, net: MLP, masks, I, n1, n2, iters, seed_rows, sp
         tb = seed_rows.index_select(0, idx).contiguous()
         Ib = I.index_select(0, idx).contiguous()
         tm_retrieve(ctx, masks, Ib, tb, n1, n2,
-                    retrieve_opts(method, iters=iters, start="spectral", spectral_iters=spectral_iters,
+                    retrieve_opts(method, iters=iters, start=start, spectral_iters=spectral_iters,
                                   spectral_tau=spectral_tau, spectral_momentum=spectral_momentum,
                                   spectral_lower=spectral_lower, er_momentum=er_momentum))
         t.index_copy_(0, idx, tb)

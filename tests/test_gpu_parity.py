@@ -200,6 +200,54 @@ def test_er_cyclic_bf16_and_full_size_rows(ctx):
         assert relerr(tt.cpu().numpy()[rows], ref) < 2 * OPTOL, bf
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 16])
+def test_lanczos_start(ctx, k):
+    # Lanczos spectral start: few steps to the per-step operator tolerance; more
+    # steps (where FP32 rounding of the recurrence enters the Ritz vector) to the
+    # fidelity tolerance between the GPU start and the oracle's
+    n1, n2, P = 32, 32, 21
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=914, noise=1e4)
+    v0 = tm_synth.random_start(P, n1 * n2, np.ones(P), tm_synth.rng(914, 3))
+    m, v, Ir = rounded(masks, v0, I)
+    ref = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), Ir, v, k, tau=2.5)
+    tt = c64(v0)
+    tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
+                   tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=k, spectral_tau=2.5))
+    got = tt.cpu().numpy().astype(np.complex128)
+    print(f"lanczos k={k} relerr {relerr(got, ref):.3e} 1-fid {1 - _fid(got, ref).min():.3e}")
+    if k <= 3:
+        assert relerr(got, ref) < OPTOL * k
+    else:
+        assert 1 - _fid(got, ref).min() < 1e-4
+    assert np.allclose(np.linalg.norm(got, axis=1) ** 2, Ir.reshape(P, -1).sum(axis=1) / (4 * n1 * n2), rtol=1e-5)
+
+
+def test_lanczos_start_full_size_rows_and_errors(ctx):
+    # the benchmark's 2286 x 8192 launch, 16 steps, sampled rows against the oracle
+    n1, n2, K, P = 128, 64, 4, 2286
+    N = n1 * n2
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
+    g = np.random.default_rng(79)
+    T = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
+    v0 = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
+    mk = c64(masks)
+    I = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True)
+    tt = c64(v0)
+    tm.tm_retrieve(ctx, mk, I, tt, n1, n2, tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=16,
+                                                             spectral_tau=2.5))
+    rows = np.unique(np.concatenate([np.sort(g.choice(P, 4, replace=False)), [0, P - 1]]))
+    m = masks.astype(np.complex64).astype(np.complex128)
+    ref = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), I.cpu().numpy()[rows].astype(np.float64),
+                              v0[rows].astype(np.complex128), 16, tau=2.5)
+    got = tt.cpu().numpy()[rows].astype(np.complex128)
+    print("full-size lanczos 1-fid", 1 - _fid(got, ref).min())
+    assert 1 - _fid(got, ref).min() < 1e-4
+    for bad in (0, 65):
+        with pytest.raises(tm.TMError, match="Lanczos"):
+            tm.tm_retrieve(ctx, mk, I[:2], c64(v0[:2]), n1, n2,
+                           tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=bad))
+
+
 def test_backprop_start(ctx):
     n1, n2, P = 64, 32, 9
     masks, T, I, _ = problem(n1, n2, 4, P, cfg=908, noise=1e4)
@@ -241,8 +289,10 @@ def _fid(a, b):
     return rt.fidelity(a, b)
 
 
-@pytest.mark.parametrize("method,iters", [("er", 200), ("lbfgs", 100), ("lbfgs_amp", 60), ("er_cyclic", 60)])
-def test_retrieve_noiseless_tiny(ctx, method, iters):
+@pytest.mark.parametrize("method,iters,start", [("er", 200, "spectral"), ("lbfgs", 100, "spectral"),
+                                                ("lbfgs_amp", 60, "spectral"), ("er_cyclic", 60, "spectral"),
+                                                ("er_cyclic", 60, "lanczos")])
+def test_retrieve_noiseless_tiny(ctx, method, iters, start):
     # 8x8 modes, 32 rows, K = 4, noiseless: spectral start then the solver
     n1, n2, P = 8, 8, 32
     masks = tm_synth.mask_phases(4, 64, tm_synth.rng(1, 0))
@@ -252,7 +302,8 @@ def test_retrieve_noiseless_tiny(ctx, method, iters):
     v0 = tm_synth.random_start(P, 64, np.ones(P), tm_synth.rng(1, 3))
     m, v, Ir = rounded(masks, v0, I)
     opr = ops.FFTOp(m, n1, n2)
-    s0 = rt.spectral_start(opr, Ir, v, 30, momentum=0.98)
+    s0 = (rt.spectral_start(opr, Ir, v, 30, momentum=0.98) if start == "spectral"
+          else rt.spectral_lanczos(opr, Ir, v, 30, tau=3.0))
     if method == "er":
         ref = s0
         for _ in range(iters):
@@ -265,7 +316,7 @@ def test_retrieve_noiseless_tiny(ctx, method, iters):
         ref, _ = rt.lbfgs_amplitude(opr, Ir, s0, iters)
     tt = c64(v0)
     raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2,
-                         tm.retrieve_opts(method, iters=iters, start="spectral", spectral_iters=30))
+                         tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=30))
     got = tt.cpu().numpy().astype(np.complex128)
     fg, fo = _fid(got, T), _fid(ref, T)
     print(method, "gpu mean fid", fg.mean(), "oracle", fo.mean())
