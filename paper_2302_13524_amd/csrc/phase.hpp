@@ -47,9 +47,11 @@ size_t phase_work_bytes(const PhaseDims& d);
 PhaseBand phase_band_plan(const PhaseDims& d, const PhaseOptics& o, int enable);
 void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w);
 
-// FP32 complex [n] -> FP64 complex [n] (the GEMM c_n = TM_est e^{j theta_n} runs
-// in FP64 through rocBLAS on the widened inputs). Returns hipError_t.
-int phase_widen(const void* src, double* dst, int64_t n, void* stream);
+// c[n][p] = sum_k theta[n][k] tm_est[p][k] (c_n = TM_est e^{j theta_n}): FP32
+// inputs, FP64 products and sums, K split into phase_cgemm_slices(d) chunks
+// whose partials (part: slices x Nd x P complex) are added in a fixed order.
+int phase_cgemm_slices(const PhaseDims& d);
+int phase_cgemm(const PhaseDims& d, const void* theta, const void* tm, double* part, double* c, void* stream);
 
 // The kernel table h, the pixel map and the solve flag (c is formed by the
 // caller). Returns hipError_t.

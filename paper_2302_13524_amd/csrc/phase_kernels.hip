@@ -35,14 +35,121 @@ int ilog2(int v) {
   return l;
 }
 
-// FP32 complex -> FP64 complex (exact), the inputs of the FP64 GEMM c = theta TM_est^T
-__global__ void __launch_bounds__(256) k_widen(const float2* __restrict__ src, double2* __restrict__ dst, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (; i < n; i += stride) {
-    const float2 v = src[i];
-    dst[i] = make_double2((double)v.x, (double)v.y);
+// ---- c[n][p] = sum_k theta[n][k] tm[p][k]: FP32 complex inputs, exact FP64
+// products, FP64 sums. Workgroup tile 256 p x 16 n, 4 x 4 outputs per thread,
+// K in steps of 32 through LDS (FP32), split over GS chunks of K whose partial
+// sums a second kernel adds in a fixed order.
+constexpr int CG_P = 256, CG_N = 16, CG_K = 32;
+
+// Tile loads: every thread issues all of its global loads of a K step before
+// the first LDS store (pairs of complex values per load when N is even).
+template <bool PAIRS>
+__global__ void __launch_bounds__(256) k_cgemm_part(const float2* __restrict__ theta, const float2* __restrict__ tm,
+                                                    double* __restrict__ part, int Nd, int P, int N, int kchunk) {
+  __shared__ float2 st[CG_K][CG_P + 4];   // tm tile, [k][p]
+  __shared__ float2 sth[CG_K][CG_N];      // theta tile, [k][n]
+  const int p0 = blockIdx.x * CG_P, n0 = blockIdx.y * CG_N, sl = blockIdx.z;
+  const int k0 = sl * kchunk, k1 = min(N, k0 + kchunk);
+  const int tid = threadIdx.x;
+  const int pg = tid % 64, ng = tid / 64;  // outputs p0 + 4 pg + i, n0 + 4 ng + j
+  double ar[4][4], ai[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
+  constexpr int W = PAIRS ? 2 : 1;                 // complex values per load
+  constexpr int LT = CG_P * CG_K / (256 * W);      // tm loads per thread per K step
+  constexpr int LH = CG_N * CG_K / (256 * W);      // theta loads per thread per K step (1 or 2)
+  for (int kb = k0; kb < k1; kb += CG_K) {
+    float2 vt[LT][W], vh[LH][W];
+#pragma unroll
+    for (int q = 0; q < LT; ++q) {
+      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
+      const int p = p0 + r, k = kb + kk;
+      if constexpr (PAIRS) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (p < P && k < k1) v = *(const float4*)(tm + (size_t)p * N + k);
+        vt[q][0] = make_float2(v.x, v.y);
+        vt[q][W - 1] = make_float2(v.z, v.w);
+      } else {
+        vt[q][0] = (p < P && k < k1) ? tm[(size_t)p * N + k] : make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LH; ++q) {
+      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
+      const int n = n0 + r, k = kb + kk;
+      if constexpr (PAIRS) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (n < Nd && k < k1) v = *(const float4*)(theta + (size_t)n * N + k);
+        vh[q][0] = make_float2(v.x, v.y);
+        vh[q][W - 1] = make_float2(v.z, v.w);
+      } else {
+        vh[q][0] = (n < Nd && k < k1) ? theta[(size_t)n * N + k] : make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LT; ++q) {
+      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
+#pragma unroll
+      for (int w = 0; w < W; ++w) st[kk + w][r] = vt[q][w];
+    }
+#pragma unroll
+    for (int q = 0; q < LH; ++q) {
+      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
+#pragma unroll
+      for (int w = 0; w < W; ++w) sth[kk + w][r] = vh[q][w];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < CG_K; ++kk) {
+      double br[4], bi[4], cr[4], ci[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 v = st[kk][4 * pg + i];
+        br[i] = (double)v.x;
+        bi[i] = (double)v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float2 v = sth[kk][4 * ng + j];
+        cr[j] = (double)v.x;
+        ci[j] = (double)v.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ar[i][j] = __builtin_fma(cr[j], br[i], ar[i][j]);
+          ar[i][j] = __builtin_fma(-ci[j], bi[i], ar[i][j]);
+          ai[i][j] = __builtin_fma(cr[j], bi[i], ai[i][j]);
+          ai[i][j] = __builtin_fma(ci[j], br[i], ai[i][j]);
+        }
+    }
+    __syncthreads();
   }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + 4 * ng + j;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = p0 + 4 * pg + i;
+      if (n < Nd && p < P) {
+        const size_t o = (((size_t)sl * Nd + n) * P + p) * 2;
+        part[o] = ar[i][j];
+        part[o + 1] = ai[i][j];
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cgemm_sum(const double* __restrict__ part, double* __restrict__ c,
+                                                   int64_t n, int gs) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < gs; ++k) s += part[(size_t)k * n + i];
+  c[i] = s;
 }
 
 __device__ __forceinline__ double freq(int k, int n, double ps) {
@@ -789,14 +896,24 @@ __global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vb, 
 }
 
 // grad[p] = -4 Im(conj(u_p) sum_n Wn[n][p]); gval = sum of the objective partials
+// 64 pixels x 4 slices of the images per workgroup: each thread adds its
+// slice (loads issued together), the four slices meet in LDS
 __global__ void __launch_bounds__(256) k_band_gather(double* grad, double* gval, const double* Wn, const double* phi,
                                                      const double* gpart, int ngp, int Nd, int P, const int* skip) {
   if (skip && *skip) return;
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  __shared__ z2 part[4][64];
+  const int pl = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + pl;
+  const int per = (Nd + 3) / 4, n0 = sl * per, n1 = min(Nd, n0 + per);
+  z2 w{0.0, 0.0};
   if (p < P) {
-    z2 w{0.0, 0.0};
-#pragma unroll 10
-    for (int n = 0; n < Nd; ++n) w = zadd(w, ldz(Wn, (size_t)n * P + p));
+#pragma unroll 16
+    for (int n = n0; n < n1; ++n) w = zadd(w, ldz(Wn, (size_t)n * P + p));
+  }
+  part[sl][pl] = w;
+  __syncthreads();
+  if (sl == 0 && p < P) {
+    w = zadd(zadd(part[0][pl], part[1][pl]), zadd(part[2][pl], part[3][pl]));
     double sn, cs;
     sincos(phi[p], &sn, &cs);
     grad[p] = -4.0 * zmulc(w, z2{cs, sn}).y;
@@ -950,8 +1067,8 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
     k_band_v<<<dim3(b.B1, d.Nd), 256, 0, s>>>(w.V, w.U, w.h, b, d.nf1, d.nf2, tw64, w.skip);
     k_band_pix<<<dim3((d.P + 255) / 256, d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, pix, b, d.P, d.nf1, d.nf2, tw64,
                                                              w.skip);
-    k_band_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
-                                                    w.skip);
+    k_band_gather<<<(d.P + 63) / 64, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
+                                                  w.skip);
     return (int)hipGetLastError();
   }
   if ((e = forward_to_rows(d, phi, w, tw64, s))) return e;
@@ -977,7 +1094,8 @@ int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, floa
 
 // ------------------------------------------------------------ L-BFGS over phi
 namespace {
-constexpr int PWG = 1024;
+constexpr int PWG = 512;
+constexpr int UE = 4;  // vector elements per thread per pass step (their loads are issued together)
 
 // Block-wide sums of several values: each wave adds its lanes' x into
 // red[wave][j] (wave_put), then bsum_finish adds the waves: out[0..nv) for
@@ -1076,16 +1194,49 @@ __device__ void dir_solve(int k, int head, int m, double* sc, const double* dots
 }
 
 // d from the coefficients, and the trial point phit = phi + d (step 1)
+// (two elements per thread and up to six pairs per pass, so that the loads of a
+// pass are in flight together)
+constexpr int DA_PAIRS = 6;
 __device__ void dir_apply(PhaseLb& L, int P, int m, int k, int head, const double* coef) {
   const int kk = coef[1 + 2 * k] != 0.0 ? k : 0;
-  for (int i = threadIdx.x; i < P; i += PWG) {
-    double d = coef[0] * L.g[i];
-    for (int j = 0; j < kk; ++j) {
-      const int sl = (head - k + j + 2 * m) % m;
-      d += coef[1 + j] * L.S[(size_t)sl * P + i] + coef[1 + k + j] * L.Y[(size_t)sl * P + i];
+  for (int i0 = threadIdx.x; i0 < P; i0 += UE * PWG) {
+    double d[UE], f[UE];
+#pragma unroll
+    for (int e = 0; e < UE; ++e) {
+      const int i = i0 + e * PWG;
+      d[e] = i < P ? coef[0] * L.g[i] : 0.0;
+      f[e] = i < P ? L.phi[i] : 0.0;
     }
-    L.d[i] = d;
-    L.phit[i] = L.phi[i] + d;
+    for (int c0 = 0; c0 < kk; c0 += DA_PAIRS) {
+      double sv[UE][DA_PAIRS], yv[UE][DA_PAIRS];
+#pragma unroll
+      for (int q = 0; q < DA_PAIRS; ++q) {
+        const size_t o = (size_t)((head - k + c0 + q + 2 * m) % m) * P;
+#pragma unroll
+        for (int e = 0; e < UE; ++e) {
+          const int i = i0 + e * PWG;
+          const bool ok = c0 + q < kk && i < P;
+          sv[e][q] = ok ? L.S[o + i] : 0.0;
+          yv[e][q] = ok ? L.Y[o + i] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < DA_PAIRS; ++q) {
+        if (c0 + q < kk) {
+          const double cs = coef[1 + c0 + q], cy = coef[1 + k + c0 + q];
+#pragma unroll
+          for (int e = 0; e < UE; ++e) d[e] += cs * sv[e][q] + cy * yv[e][q];
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < UE; ++e) {
+      const int i = i0 + e * PWG;
+      if (i < P) {
+        L.d[i] = d[e];
+        L.phit[i] = f[e] + d[e];
+      }
+    }
   }
 }
 
@@ -1135,30 +1286,51 @@ __device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double f
 #pragma unroll
     for (int q = 0; q < 4; ++q) x[q][0] = x[q][1] = x[q][2] = x[q][3] = 0.0;
     double xsy = 0.0, xyy = 0.0, xsg = 0.0, xyg = 0.0, xgg = 0.0;
-    for (int i = threadIdx.x; i < P; i += PWG) {
-      const double gti = L.gt[i], si = a * L.d[i], yi = gti - L.g[i];
+    for (int i0 = threadIdx.x; i0 < P; i0 += UE * PWG) {
+      // UE elements per thread, all their loads issued before the arithmetic
+      double gt[UE], dd[UE], gg[UE], ph[UE], Sv[UE][4], Yv[UE][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = c0 + q;
-        if (j < keep) {
-          const int sl = (head - keep + j + 2 * m) % m;
-          const double Sj = L.S[(size_t)sl * P + i], Yj = L.Y[(size_t)sl * P + i];
-          x[q][0] += Sj * yi;
-          x[q][1] += Yj * yi;
-          x[q][2] += Sj * gti;
-          x[q][3] += Yj * gti;
+      for (int e = 0; e < UE; ++e) {
+        const int i = i0 + e * PWG;
+        const bool ok = i < P;
+        gt[e] = ok ? L.gt[i] : 0.0;
+        dd[e] = ok ? L.d[i] : 0.0;
+        gg[e] = ok ? L.g[i] : 0.0;
+        ph[e] = (ok && last) ? L.phi[i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          Sv[e][q] = Yv[e][q] = 0.0;
+          if (ok && c0 + q < keep) {
+            const size_t o = (size_t)((head - keep + c0 + q + 2 * m) % m) * P + i;
+            Sv[e][q] = L.S[o];
+            Yv[e][q] = L.Y[o];
+          }
         }
       }
-      if (last) {
-        xsy += si * yi;
-        xyy += yi * yi;
-        xsg += si * gti;
-        xyg += yi * gti;
-        xgg += gti * gti;
-        Sh[i] = si;
-        Yh[i] = yi;
-        L.phi[i] = L.phi[i] + si;
-        L.g[i] = gti;
+#pragma unroll
+      for (int e = 0; e < UE; ++e) {
+        const int i = i0 + e * PWG;
+        const double gti = gt[e], si = a * dd[e], yi = gti - gg[e];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[q][0] += Sv[e][q] * yi;
+          x[q][1] += Yv[e][q] * yi;
+          x[q][2] += Sv[e][q] * gti;
+          x[q][3] += Yv[e][q] * gti;
+        }
+        if (last) {
+          xsy += si * yi;
+          xyy += yi * yi;
+          xsg += si * gti;
+          xyg += yi * gti;
+          xgg += gti * gti;
+          if (i < P) {
+            Sh[i] = si;
+            Yh[i] = yi;
+            L.phi[i] = ph[e] + si;
+            L.g[i] = gti;
+          }
+        }
       }
     }
 #pragma unroll
@@ -1228,16 +1400,13 @@ __device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double f
   return 0;
 }
 
-__global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, double ftol, const double* gval,
-                                                int* skip) {
-  __shared__ double red[(PWG / 64) * MAXV];
-  __shared__ double sh[2 * MAXV];
-  __shared__ double smat[SMAT + MAXV];
+// One iteration on the state sc (an LDS copy; every branch below is taken by
+// the whole workgroup).
+__device__ void piter_body(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip,
+                           double* sc, double* red, double* sh, double* smat) {
   __shared__ int stop;
-  double* sc = L.sc;
-  if (*skip) return;
   if (threadIdx.x == 0) stop = 0;
-  __syncthreads();  // every thread has read *skip before thread 0 may set it
+  __syncthreads();
   if (sc[8] != 0.0) {
     const double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
     if (fn <= f + 1e-4 * a * slope) {  // Armijo: accept, new direction, trial point at step 1
@@ -1269,7 +1438,18 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
       return;
     }
     const double as = sc[3];
-    for (int i = threadIdx.x; i < P; i += PWG) L.phit[i] = L.phi[i] + as * L.d[i];
+    for (int i0 = threadIdx.x; i0 < P; i0 += UE * PWG) {
+      double f[UE], e[UE];
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const int i = i0 + u * PWG;
+        f[u] = i < P ? L.phi[i] : 0.0;
+        e[u] = i < P ? L.d[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UE; ++u)
+        if (i0 + u * PWG < P) L.phit[i0 + u * PWG] = f[u] + as * e[u];
+    }
     return;
   }
   // no pending trial: the first direction after the start
@@ -1289,6 +1469,22 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
     return;
   }
   if (threadIdx.x == 0) sc[8] = 1.0;
+}
+
+__global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, double ftol, const double* gval,
+                                                int* skip) {
+  __shared__ double red[(PWG / 64) * MAXV];
+  __shared__ double sh[2 * MAXV];
+  __shared__ double smat[SMAT + MAXV];
+  __shared__ double scl[SC_HIST + 2 * 16 * 16];
+  if (*skip) return;
+  // the iteration state lives in LDS for the kernel (one parallel load, one store back)
+  const int nsc = SC_HIST + 2 * m * m;
+  for (int i = threadIdx.x; i < nsc; i += PWG) scl[i] = L.sc[i];
+  __syncthreads();  // also: every thread has read *skip before thread 0 may set it
+  piter_body(L, P, m, iters, ftol, gval, skip, scl, red, sh, smat);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nsc; i += PWG) L.sc[i] = scl[i];
 }
 
 // start: clear the state, take f at the start point, allow the first direction
@@ -1317,11 +1513,25 @@ int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double
 }  // namespace tmk
 
 namespace tmk {
-int phase_widen(const void* src, double* dst, int64_t n, void* stream) {
-  if (n <= 0) return 0;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  k_widen<<<(int)blocks, 256, 0, (hipStream_t)stream>>>((const float2*)src, (double2*)dst, n);
+int phase_cgemm_slices(const PhaseDims& d) {
+  const int tiles = ((d.P + CG_P - 1) / CG_P) * ((d.Nd + CG_N - 1) / CG_N);
+  int gs = 1;
+  while (tiles * gs * 2 <= 1024 && (d.N + 2 * gs - 1) / (2 * gs) >= 256) gs *= 2;
+  return gs;
+}
+
+int phase_cgemm(const PhaseDims& d, const void* theta, const void* tm, double* part, double* c, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int gs = phase_cgemm_slices(d);
+  int kchunk = (d.N + gs - 1) / gs;
+  kchunk = ((kchunk + CG_K - 1) / CG_K) * CG_K;
+  dim3 g((d.P + CG_P - 1) / CG_P, (d.Nd + CG_N - 1) / CG_N, gs);
+  if (d.N % 2 == 0)
+    k_cgemm_part<true><<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm, part, d.Nd, d.P, d.N, kchunk);
+  else
+    k_cgemm_part<false><<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm, part, d.Nd, d.P, d.N, kchunk);
+  const int64_t n = (int64_t)d.Nd * d.P * 2;
+  k_cgemm_sum<<<(int)((n + 255) / 256), 256, 0, s>>>(part, c, n, gs);
   return (int)hipGetLastError();
 }
 }  // namespace tmk

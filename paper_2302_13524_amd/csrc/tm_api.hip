@@ -557,8 +557,6 @@ static int phase_check(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
   return TM_OK;
 }
 
-static int blas_ready(tm_ctx* c, void* stream);
-
 static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
                          const tm_c32* theta, const tm_optics* o, tmk::PhaseDims& pd, tmk::PhaseWork& w,
                          void* stream) {
@@ -570,22 +568,12 @@ static int phase_prepare(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pi
   w.band = tmk::phase_band_plan(pd, po, c->phase_band);
   int e = tmk::phase_setup(pd, po, tm_est, theta, pix, w, stream);
   if (e) return hipfail(c, e, "phase setup");
-  // c[n][p] = sum_k theta[n][k] tm_est[p][k] in FP64 (exact products of the FP32 inputs): in
-  // column-major terms c^T (P x Nd) = TM^T Theta with TM (N x P) and Theta (N x Nd)
-  const int64_t nt = (int64_t)dd->P * dd->N, nth = (int64_t)dd->Nd * dd->N;
-  double* tm64 = (double*)ws_get(c, WS_PH_BASE + 2, (size_t)nt * 2 * sizeof(double));
-  double* th64 = (double*)ws_get(c, WS_PH_BASE + 3, (size_t)nth * 2 * sizeof(double));
-  if (!tm64 || !th64) return fail(c, TM_ENOMEM, "phase GEMM workspace");
-  int r = blas_ready(c, stream);
-  if (r) return r;
-  e = tmk::phase_widen(tm_est, tm64, nt, stream);
-  if (!e) e = tmk::phase_widen(theta, th64, nth, stream);
-  if (e) return hipfail(c, e, "widening the GEMM inputs");
-  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  if (rocblas_zgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, dd->P, dd->Nd, dd->N, &one,
-                    (const rocblas_double_complex*)tm64, dd->N, (const rocblas_double_complex*)th64, dd->N, &zero,
-                    (rocblas_double_complex*)w.c, dd->P) != rocblas_status_success)
-    return fail(c, TM_EHIP, "rocblas_zgemm failed");
+  // c[n][p] = sum_k theta[n][k] tm_est[p][k] in FP64 (exact products of the FP32 inputs)
+  double* part = (double*)ws_get(c, WS_PH_BASE + 2,
+                                 (size_t)tmk::phase_cgemm_slices(pd) * dd->Nd * dd->P * 2 * sizeof(double));
+  if (!part) return fail(c, TM_ENOMEM, "phase GEMM workspace");
+  e = tmk::phase_cgemm(pd, theta, tm_est, part, w.c, stream);
+  if (e) return hipfail(c, e, "phase GEMM");
   return TM_OK;
 }
 
