@@ -480,7 +480,8 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
                                                    spectral_lower=args.spectral_lower,
-                                                   er_momentum=beta, method=solver, start=args.start)
+                                                   er_momentum=args.er_momentum if args.solver == "er" else 0.0,
+                                                   method=args.solver, start=args.start)
     torch.cuda.synchronize()
     a = time.perf_counter()
     for _ in range(3):
@@ -488,7 +489,8 @@ def learned_variant(args, ctx, mk, It, v0t, n1, n2, n_er, sp, fidelity, ret_ms, 
                                                    spectral_tau=args.spectral_tau,
                                                    spectral_momentum=args.spectral_momentum,
                                                    spectral_lower=args.spectral_lower,
-                                                   er_momentum=beta, method=solver, start=args.start)
+                                                   er_momentum=args.er_momentum if args.solver == "er" else 0.0,
+                                                   method=args.solver, start=args.start)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) * 1e3 / 3
     return {"rows_per_s": round(P / (ms * 1e-3), 1), "retrieval_ms": round(ms, 3),
