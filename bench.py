@@ -78,7 +78,8 @@ def parse():
                          "them one at a time (er_cyclic)")
     ap.add_argument("--er-momentum", type=float, default=0.8,
                     help="Nesterov factor of the error-reduction iterations (0: plain ER)")
-    ap.add_argument("--batch-iters", type=int, default=30)
+    ap.add_argument("--batch-iters", type=int, default=None,
+                    help="iterations in the uneven batch (default 30 for er, 6 sweeps for er_cyclic)")
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 12-TM batch")
@@ -92,6 +93,8 @@ def parse():
                                                         "OUT"),
                     help="summarise rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs into the traffic file (no GPU)")
     args = ap.parse_args()
+    if args.batch_iters is None:
+        args.batch_iters = 30 if args.solver == "er" else 6
     if args.spectral_iters is None:
         args.spectral_iters = 18 if args.start == "lanczos" else 24
     return args
@@ -688,8 +691,9 @@ def batch_variant(ctx, args):
         truths.append(T / torch.linalg.vector_norm(T, dim=1, keepdim=True))
     log(f"batch inputs {time.perf_counter() - a:.1f}s")
     tuned = {f"{n1}x{n2}": tm.autotune(ctx, n1, n2, 4, 512, bf16=True) for n1, n2, _, _ in shapes[:4]}
-    iters, sp, beta = args.batch_iters, args.batch_spectral_iters, args.er_momentum
-    b = tm.Batch(ctx, probs, tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True,
+    iters, sp = args.batch_iters, args.batch_spectral_iters
+    beta = args.er_momentum if args.solver == "er" else 0.0
+    b = tm.Batch(ctx, probs, tm.retrieve_opts(args.solver, iters=iters, start="spectral", spectral_iters=sp, bf16=True,
                                               spectral_tau=args.spectral_tau,
                                               spectral_momentum=args.spectral_momentum,
                                               spectral_lower=args.spectral_lower,
@@ -721,7 +725,7 @@ def batch_variant(ctx, args):
                        "rows_flagged": int((tm.decode_stats(p["stats"]).flags.numpy() & 1).sum())})
     b.close()
     return {"rows_per_s": round(rows / (ms * 1e-3), 1), "ms": round(ms, 3), "rows": rows, "tms": len(shapes),
-            "iters": iters, "er_momentum": beta, "spectral_iters": sp, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
+            "solver": args.solver, "iters": iters, "er_momentum": beta, "spectral_iters": sp, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
 
 
 def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver="er"):

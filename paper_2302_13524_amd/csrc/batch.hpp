@@ -41,7 +41,7 @@ struct BatchArgs {
   const cx<float>* tw32;
 };
 
-enum BatchMode { BATCH_ER = 0, BATCH_SPEC = 1 };
+enum BatchMode { BATCH_ER = 0, BATCH_SPEC = 1, BATCH_ERC = 2 };
 // Launch one batched pass (mode BATCH_*) over all items with `grid` workgroups.
 int batch_launch(int mode, int ibf16, int with_sums, const BatchArgs& a, int grid, void* stream);
 

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.out_bf16 = 0;
     a.tw32 = b.tw32;
     a.tw64 = nullptr;
-    constexpr int M = (MODE == BATCH_ER) ? M_ER : M_SPEC;
+    constexpr int M = (MODE == BATCH_ER) ? M_ER : (MODE == BATCH_ERC) ? M_ERC : M_SPEC;
     switch (pr.code) {
       case 0: item_body<Plan<5, 5, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
       case 1: item_body<Plan<5, 5, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
@@ -110,6 +110,8 @@ int batch_launch(int mode, int ibf16, int with_sums, const BatchArgs& a, int gri
   if (a.n_items <= 0) return 0;
   if (mode == BATCH_ER) return ibf16 ? launch_m<BATCH_ER, uint16_t>(with_sums, a, grid, s)
                                      : launch_m<BATCH_ER, float>(with_sums, a, grid, s);
+  if (mode == BATCH_ERC) return ibf16 ? launch_m<BATCH_ERC, uint16_t>(with_sums, a, grid, s)
+                                      : launch_m<BATCH_ERC, float>(with_sums, a, grid, s);
   return ibf16 ? launch_m<BATCH_SPEC, uint16_t>(0, a, grid, s) : launch_m<BATCH_SPEC, float>(0, a, grid, s);
 }
 

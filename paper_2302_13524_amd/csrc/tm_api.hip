@@ -931,7 +931,8 @@ static int batch_enqueue(tm_batch* b, void* stream) {
     }
   }
   tmk::BatchArgs ea = b->args;
-  const bool mom = o.er_momentum > 0.f && o.iters > 0;
+  const bool cyclic = o.method == TM_METHOD_ER_CYCLIC;
+  const bool mom = !cyclic && o.er_momentum > 0.f && o.iters > 0;
   if (mom) {
     // t_prev starts equal to t in the per-problem vprev buffer (free after the
     // spectral start); the two buffers then swap roles every iteration
@@ -944,7 +945,7 @@ static int batch_enqueue(tm_batch* b, void* stream) {
   }
   for (int it = 0; it < o.iters && !e; ++it) {
     ea.swap = mom ? (it & 1) : 0;
-    e = tmk::batch_launch(tmk::BATCH_ER, ibf, it == o.iters - 1, ea, b->grid, stream);
+    e = tmk::batch_launch(cyclic ? tmk::BATCH_ERC : tmk::BATCH_ER, ibf, it == o.iters - 1, ea, b->grid, stream);
   }
   if (mom && (o.iters & 1)) {
     for (int i = 0; i < n && !e; ++i) {
@@ -973,8 +974,11 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
   if (!c) return TM_EINVAL;
   if (!out || !o || n < 1 || !probs) return fail(c, TM_EINVAL, "n >= 1 and non-null probs, opts, out");
   *out = nullptr;
-  if (o->method != TM_METHOD_ER) return fail(c, TM_EUNSUPPORTED, "batches run the error-reduction method");
+  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_ER_CYCLIC)
+    return fail(c, TM_EUNSUPPORTED, "batches run the error-reduction methods (TM_METHOD_ER, TM_METHOD_ER_CYCLIC)");
   if (!(o->er_momentum >= 0.f && o->er_momentum < 1.f)) return fail(c, TM_EINVAL, "er_momentum must be in [0, 1)");
+  if (o->method == TM_METHOD_ER_CYCLIC && o->er_momentum != 0.f)
+    return fail(c, TM_EINVAL, "cyclic error reduction takes no momentum (er_momentum must be 0)");
   if (o->iters < 0 || (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) || o->start < TM_START_GIVEN ||
       o->start > TM_START_SPECTRAL)
     return fail(c, TM_EINVAL, "bad options");

@@ -39,24 +39,26 @@ def make_problems(ctx, shapes, cfg=970, bf16=True):
     return out
 
 
-def opts(mom=0.0, sp=5, iters=4):
-    return tm.retrieve_opts("er", iters=iters, start="spectral", spectral_iters=sp, bf16=True, er_momentum=mom)
+def opts(mom=0.0, sp=5, iters=4, method="er"):
+    return tm.retrieve_opts(method, iters=iters, start="spectral", spectral_iters=sp, bf16=True, er_momentum=mom)
 
 
-def singles(ctx, probs, mom=0.0, sp=5, iters=4):
+def singles(ctx, probs, mom=0.0, sp=5, iters=4, method="er"):
     res = []
     for p in probs:
         t = p["seed"].clone()
-        tm.tm_retrieve(ctx, p["masks"], p["I"], t, p["n1"], p["n2"], opts(mom, sp, iters))
+        tm.tm_retrieve(ctx, p["masks"], p["I"], t, p["n1"], p["n2"], opts(mom, sp, iters, method))
         res.append(t)
     return res
 
 
-@pytest.mark.parametrize("graph,mom,sp,iters", [(False, 0.0, 5, 4), (True, 0.0, 5, 4), (True, 0.8, 4, 3)])
-def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters):
+@pytest.mark.parametrize("graph,mom,sp,iters,method", [(False, 0.0, 5, 4, "er"), (True, 0.0, 5, 4, "er"),
+                                                       (True, 0.8, 4, 3, "er"), (True, 0.0, 4, 3, "er_cyclic"),
+                                                       (False, 0.0, 3, 2, "er_cyclic")])
+def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters, method):
     probs = make_problems(ctx, SHAPES)
-    ref = singles(ctx, probs, mom, sp, iters)
-    b = tm.Batch(ctx, probs, opts(mom, sp, iters), use_graph=graph)
+    ref = singles(ctx, probs, mom, sp, iters, method)
+    b = tm.Batch(ctx, probs, opts(mom, sp, iters, method), use_graph=graph)
     for rep in range(3):
         for p in probs:
             p["t"].copy_(p["seed"])
@@ -65,7 +67,7 @@ def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters):
         for p, r in zip(probs, ref):
             assert torch.equal(p["t"], r), (rep, p["n1"], p["n2"])
         # eager work between replays
-        ref = singles(ctx, probs, mom, sp, iters)
+        ref = singles(ctx, probs, mom, sp, iters, method)
     st = tm.decode_stats(probs[0]["stats"])
     assert np.all(st.iters.numpy() == iters)
     b.close()
