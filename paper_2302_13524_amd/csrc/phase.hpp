@@ -35,8 +35,7 @@ struct PhaseWork {
   int32_t* inv;   // [nf1 nf2] row index of each field pixel, -1 outside the rows
   int* skip;      // [1] set to 1 when the L-BFGS solve has ended: evaluation kernels return at once
   double* Sp;     // band: [Nd][CH][16][16] complex, box spectrum partials per block of field rows
-  double* U;      // band: [Nd][16][2nf2] complex, adjoint after its image-axis-1 transform
-  double* V;      // band: [Nd][16][16] complex, adjoint box spectrum times conj(h)
+  double* V;      // band: [Nd][column blocks][16][16] complex, adjoint box spectrum partials
   double* Wn;     // band: [Nd][P] complex, conj(c_n) (A_n^H a_n r_n) at the pixels
   PhaseBand band; // host-side plan
 };

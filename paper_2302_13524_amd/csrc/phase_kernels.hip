@@ -743,7 +743,7 @@ __device__ __forceinline__ void reg_dft(z2* x) {
 // columns of U. A length-BT1 DFT per BT1 pixels replaces BT1 terms per pixel.
 // BT1: the box's axis-1 side padded to 4, 8 or 16 (rows beyond B1 are zero).
 template <int BT1>
-__global__ void __launch_bounds__(256) k_band_img(double* U, double* gpart, const double* Sp, const float* Id,
+__global__ void __launch_bounds__(256) k_band_img(double* Vp, double* gpart, const double* Sp, const float* Id,
                                                   const double* h, PhaseBand b, int nf1, int nf2,
                                                   const double* tw64, const int* skip) {
   if (skip && *skip) return;
@@ -813,49 +813,30 @@ __global__ void __launch_bounds__(256) k_band_img(double* U, double* gpart, cons
   for (int j = 0; j < BT1; ++j)
     stage[(j * G + l) * CPW + cl] = zmul(x[j], twl1[(j * l) & (L1 - 1)]);  // e^{-2 pi i j l / L1}
   __syncthreads();
+  // the column's adjoint: its G threads' parts added in place (slot q = 0)
   for (int o = threadIdx.x; o < b.B1 * CPW; o += 256) {
-    const int j = o / CPW, c2 = o - (o / CPW) * CPW, cc = blockIdx.x * CPW + c2;
-    if (cc < L2) {
-      z2 sacc{0.0, 0.0};
-      for (int q = 0; q < G; ++q) sacc = zadd(sacc, stage[(j * G + q) * CPW + c2]);
-      stz(U, ((size_t)n * BM + j) * L2 + cc, sacc);
-    }
+    const int j = o / CPW, c2 = o - (o / CPW) * CPW;
+    z2 sacc{0.0, 0.0};
+    for (int q = 0; q < G; ++q) sacc = zadd(sacc, stage[(j * G + q) * CPW + c2]);
+    stage[(j * G) * CPW + c2] = sacc;
   }
-}
-
-// V[n][i1][i2] = conj(h) sc sum_x2 U[n][i1][x2] e^{-2 pi j s2 x2 / 2nf2}
-__global__ void __launch_bounds__(256) k_band_v(double* Vb, const double* U, const double* h, PhaseBand b, int nf1,
-                                                int nf2, const double* tw64, const int* skip) {
-  if (skip && *skip) return;
-  __shared__ z2 ul[512];
-  __shared__ z2 twl2[512];
-  const int i1 = blockIdx.x, n = blockIdx.y, L2 = 2 * nf2;
-  load_tab(twl2, tw64, L2, 256);
-  for (int x = threadIdx.x; x < L2; x += 256) ul[x] = ldz(U, ((size_t)n * BM + i1) * L2 + x);
   __syncthreads();
-  // output i2 by a group of 16 lanes (one wave holds four outputs)
-  const int g = threadIdx.x / 16, lane = threadIdx.x & 15;
-  const double sc = 1.0 / (2.0 * (double)nf1 * (double)nf2);
-  for (int i2 = g; i2 < ((b.B2 + 15) / 16) * 16; i2 += 16) {
+  // adjoint along axis 2 at the box frequencies over this workgroup's columns:
+  // Vp[n][block][i1][i2] = sum_col U[i1][col] e^{-2 pi i s2 col / L2} (the blocks are added by band_pix)
+  for (int t = threadIdx.x; t < b.B1 * b.B2; t += 256) {
+    const int i1 = t / b.B2, i2 = t - (t / b.B2) * b.B2;
+    const int sm = (b.s2lo + i2) & (L2 - 1);
     z2 acc{0.0, 0.0};
-    if (i2 < b.B2) {
-      const int sm = (b.s2lo + i2) & (L2 - 1);
-      for (int x = lane; x < L2; x += 16) acc = zfma(ul[x], twl2[(sm * x) & (L2 - 1)], acc);
+    for (int c2 = 0; c2 < CPW; ++c2) {
+      const int cc = blockIdx.x * CPW + c2;
+      if (cc < L2) acc = zfma(stage[(i1 * G) * CPW + c2], twl2[(sm * cc) & (L2 - 1)], acc);
     }
-    for (int off = 1; off < 16; off <<= 1) {
-      acc.x += __shfl_xor(acc.x, off, 64);
-      acc.y += __shfl_xor(acc.y, off, 64);
-    }
-    if (i2 < b.B2 && lane == 0) {
-      const int k1 = (b.s1lo + i1) & (nf1 - 1), k2 = (b.s2lo + i2) & (nf2 - 1);
-      const z2 v = zmulc(acc, ldz(h, (size_t)k1 * nf2 + k2));
-      stz(Vb, ((size_t)n * BM + i1) * BM + i2, z2{v.x * sc, v.y * sc});
-    }
+    stz(Vp, (((size_t)n * gridDim.x + blockIdx.x) * BM + i1) * BM + i2, acc);
   }
 }
 
 // Wn[n][p] = conj(c[n][p]) sum_i1 e^{+2 pi j s1 a_p / nf1} sum_i2 V[n][i1][i2] e^{+2 pi j s2 b_p / nf2}
-__global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vb, const double* c,
+__global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vp, const double* c, const double* h,
                                                   const int32_t* pix, PhaseBand b, int P, int nf1, int nf2,
                                                   const double* tw64, const int* skip) {
   if (skip && *skip) return;
@@ -870,7 +851,22 @@ __global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vb, 
     g = pix[p];
     cv = ldz(c, (size_t)n * P + p);
   }
-  for (int t = threadIdx.x; t < b.B1 * BM; t += 256) V[t] = ldz(Vb, (size_t)n * BM * BM + t);
+  // V = conj(h) sc (sum of the image pass's column-block partials)
+  const double sc = 1.0 / (2.0 * (double)nf1 * (double)nf2);
+  for (int t = threadIdx.x; t < b.B1 * BM; t += 256) {
+    const int i1 = t / BM, i2 = t % BM;
+    z2 v{0.0, 0.0};
+    if (i2 < b.B2) {
+      const int k1 = (b.s1lo + i1) & (nf1 - 1), k2 = (b.s2lo + i2) & (nf2 - 1);
+      const z2 hv = ldz(h, (size_t)k1 * nf2 + k2);
+      z2 acc{0.0, 0.0};
+#pragma unroll 4
+      for (int q = 0; q < b.NXB; ++q) acc = zadd(acc, ldz(Vp, ((size_t)n * b.NXB + q) * BM * BM + t));
+      v = zmulc(acc, hv);
+      v = z2{v.x * sc, v.y * sc};
+    }
+    V[t] = v;
+  }
   load_tab(tw1, tw64, nf1, 256);
   load_tab(tw2, tw64, nf2, 256);
   __syncthreads();
@@ -962,7 +958,11 @@ size_t band_Sp_doubles(const PhaseDims& d) {
   band_geometry(d, &b);
   return (size_t)d.Nd * b.CH * BM * BM * 2;
 }
-size_t band_U_doubles(const PhaseDims& d) { return (size_t)d.Nd * BM * 2 * d.nf2 * 2; }
+// image-pass column blocks, at most: 256 / G columns per block with G <= 2 nf1 / 4
+size_t band_nxb_max(const PhaseDims& d) {
+  const size_t cols = (size_t)std::max(1, 256 / std::max(1, 2 * d.nf1 / 4));
+  return (2 * (size_t)d.nf2 + cols - 1) / cols;
+}
 // image-pass workgroups: at most 2 nf2 column blocks per image
 size_t gpart_doubles(const PhaseDims& d) { return std::max((size_t)mid_groups(d), (size_t)d.Nd * 2 * d.nf2); }
 }  // namespace
@@ -971,7 +971,7 @@ size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
   size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 2 * G * 2 +
                gpart_doubles(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1 + band_Sp_doubles(d) +
-               band_U_doubles(d) + (size_t)d.Nd * BM * BM * 2 + (size_t)d.Nd * d.P * 2;
+               (size_t)d.Nd * band_nxb_max(d) * BM * BM * 2 + (size_t)d.Nd * d.P * 2;
   return dbl * sizeof(double) + 13 * 256;
 }
 
@@ -1029,8 +1029,7 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->inv = (int32_t*)take(G);
   w->skip = (int*)take(1);
   w->Sp = take(band_Sp_doubles(d));
-  w->U = take(band_U_doubles(d));
-  w->V = take((size_t)d.Nd * BM * BM * 2);
+  w->V = take((size_t)d.Nd * band_nxb_max(d) * BM * BM * 2);
   w->Wn = take((size_t)d.Nd * d.P * 2);
   w->band = PhaseBand{};
 }
@@ -1060,12 +1059,11 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
     k_band_spec<<<dim3(b.CH, d.Nd), 256, 0, s>>>(w.Sp, w.c, phi, w.inv, b, d.P, d.nf1, d.nf2, tw64, w.skip);
     const dim3 gi(b.NXB, d.Nd);
     switch (band_bt1(b.B1)) {
-      case 4: k_band_img<4><<<gi, 256, 0, s>>>(w.U, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
-      case 8: k_band_img<8><<<gi, 256, 0, s>>>(w.U, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
-      default: k_band_img<16><<<gi, 256, 0, s>>>(w.U, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip);
+      case 4: k_band_img<4><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
+      case 8: k_band_img<8><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
+      default: k_band_img<16><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip);
     }
-    k_band_v<<<dim3(b.B1, d.Nd), 256, 0, s>>>(w.V, w.U, w.h, b, d.nf1, d.nf2, tw64, w.skip);
-    k_band_pix<<<dim3((d.P + 255) / 256, d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, pix, b, d.P, d.nf1, d.nf2, tw64,
+    k_band_pix<<<dim3((d.P + 255) / 256, d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, w.h, pix, b, d.P, d.nf1, d.nf2, tw64,
                                                              w.skip);
     k_band_gather<<<(d.P + 63) / 64, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
                                                   w.skip);

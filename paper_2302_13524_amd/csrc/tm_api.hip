@@ -50,7 +50,24 @@ struct tm_ctx {
   double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
   rocblas_handle blas = nullptr;  // plain complex GEMM of the foci synthesis
   int phase_band = 1;             // band evaluation of the defocus model when the pupil's box is small
+  // The captured phase iteration of the last tm_phase_offset_correct call, reused
+  // while everything it captured (pointers, sizes, options, band plan) is unchanged.
+  struct PhaseGraph {
+    std::vector<double> key;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+  } pg;
 };
+
+constexpr int PHASE_GRAPH_ITERS = 10;  // phase L-BFGS iterations captured per graph replay
+
+static void phase_graph_release(tm_ctx* c) {
+  if (c->pg.exec) hipGraphExecDestroy(c->pg.exec);
+  if (c->pg.g) hipGraphDestroy(c->pg.g);
+  if (c->pg.cap) hipStreamDestroy(c->pg.cap);
+  c->pg = tm_ctx::PhaseGraph{};
+}
 
 namespace {
 
@@ -230,6 +247,7 @@ int tm_destroy(tm_ctx* c) {
   prof_drain(c);
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->pinned) hipHostFree(c->pinned);
+  phase_graph_release(c);
   if (c->blas) rocblas_destroy_handle(c->blas);
   for (auto& kv : c->ws) hipFree(kv.second.p);
   hipFree(c->tw32);
@@ -640,24 +658,46 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   // control lives in device state, so replays are queued back-to-back and
   // the host reads the state only between batches of replays.
   if (po->iters > 0) {
-    hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    if (he == hipSuccess) {
-      e = tmk::phase_lb_iter(L, P, m, po->iters, po->ftol, w.gval, w.skip, cap);
-      if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
-      hipError_t he2 = hipStreamEndCapture(cap, &graph);
-      if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-      if (!e && he2 != hipSuccess) e = (int)he2;
-    } else {
-      e = (int)he;
+    // everything the captured iteration depends on
+    const tmk::PhaseBand& bd = w.band;
+    std::vector<double> key = {(double)pd.P, (double)pd.N, (double)pd.Nd, (double)pd.nf1, (double)pd.nf2,
+                               (double)(uintptr_t)pix, (double)(uintptr_t)I_d, (double)(uintptr_t)lb,
+                               (double)(uintptr_t)w.c, (double)(uintptr_t)c->tw64, (double)m, (double)po->iters,
+                               po->ftol, (double)bd.on, (double)bd.s1lo, (double)bd.B1, (double)bd.s2lo,
+                               (double)bd.B2, (double)bd.RA, (double)bd.CH, (double)bd.G, (double)bd.CPW,
+                               (double)bd.NXB, (double)c->device};
+    if (!(c->pg.exec && c->pg.key == key)) {
+      phase_graph_release(c);
+      hipStream_t cap = nullptr;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t gexec = nullptr;
+      hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+      if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+      if (he == hipSuccess) {
+        // several iterations per replay, so that one launch from the host covers
+        // them (an iteration after the solve has ended returns at once)
+        for (int r = 0; r < PHASE_GRAPH_ITERS && !e; ++r) {
+          e = tmk::phase_lb_iter(L, P, m, po->iters, po->ftol, w.gval, w.skip, cap);
+          if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
+        }
+        hipError_t he2 = hipStreamEndCapture(cap, &graph);
+        if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (!e && he2 != hipSuccess) e = (int)he2;
+      } else {
+        e = (int)he;
+      }
+      c->pg.g = graph;
+      c->pg.exec = gexec;
+      c->pg.cap = cap;
+      if (!e) c->pg.key = key;
+      else phase_graph_release(c);
     }
+    hipGraphExec_t gexec = c->pg.exec;
+    hipError_t he = hipSuccess;
     // at most 40 trials per accepted iteration, plus the replay that decides
-    // the last trial and ends the solve
-    const long limit = (long)po->iters * 40 + 2;
-    long launched = 0, batch = po->iters + 8;
+    // the last trial and ends the solve; PHASE_GRAPH_ITERS of them per replay
+    const long limit = ((long)po->iters * 40 + 2 + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
+    long launched = 0, batch = (po->iters + 8 + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
     while (!e && launched < limit) {
       long nb = std::min(batch, limit - launched);
       for (long i = 0; i < nb && !e; ++i) e = (int)hipGraphLaunch(gexec, s);
@@ -672,11 +712,8 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
         break;
       }
       if (*hs != 0 || hb[0] >= (double)po->iters) break;
-      batch = 16;
+      batch = 2;
     }
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (graph) hipGraphDestroy(graph);
-    if (cap) hipStreamDestroy(cap);
     if (e) return hipfail(c, e, "phase iterations");
   }
   HIPCHK(c, hipMemcpyAsync(hb + 3, L.sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));

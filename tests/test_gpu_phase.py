@@ -160,3 +160,32 @@ def test_ftol_stops_early(ctx):
     assert np.max(np.abs(df.circular_offset_error(tight, phi_true))) < 1e-5
     with pytest.raises(tm.TMError, match="ftol"):
         solve(10, -1.0)
+
+
+def test_repeated_solves_reuse_the_captured_iteration(ctx):
+    # the captured iteration is kept between calls while its inputs' addresses
+    # and sizes are unchanged: repeated and changed solves equal fresh contexts'
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, 0.6, 0.6, cfg=956, noise=1e4)
+    pix_d, tm_d, th_d, Id_d = (torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta), f32(Id))
+    opt = (LAM, PS, 0.6, 20 * LAM)
+
+    def solve(c, iters, Idt=Id_d):
+        phi = torch.zeros(P, dtype=torch.float64, device=dev())
+        g = tm.tm_phase_offset_correct(c, pix_d, tm_d, th_d, Idt, opt, phi, nf, nf, iters=iters, m=5)
+        return phi.cpu().numpy(), g
+
+    a1, g1 = solve(ctx, 50)
+    a2, g2 = solve(ctx, 50)
+    assert np.array_equal(a1, a2) and g1 == g2
+    Id_d.mul_(1.01)  # same address, new contents
+    b1, _ = solve(ctx, 50)
+    b2, _ = solve(ctx, 30)
+    fresh = tm.Context(0)
+    try:
+        fb1, _ = solve(fresh, 50)
+        fb2, _ = solve(fresh, 30)
+    finally:
+        fresh.close()
+    assert np.array_equal(b1, fb1) and np.array_equal(b2, fb2)
+    assert not np.array_equal(a1, b1)
