@@ -51,11 +51,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch-spectral-iters", type=int, default=24,
                     help="heavy-ball spectral steps in the uneven batch")
+    ap.add_argument("--batch-spectral-tau", type=float, default=2.5,
+                    help="truncation of the spectral weights in the uneven batch")
     ap.add_argument("--start", choices=["spectral", "lanczos"], default="lanczos",
                     help="spectral start by heavy-ball power steps or by Lanczos steps")
     ap.add_argument("--spectral-iters", type=int, default=None,
-                    help="steps of the spectral start (default 24 heavy-ball or 18 Lanczos)")
-    ap.add_argument("--spectral-tau", type=float, default=2.5, help="truncation of the spectral weights")
+                    help="steps of the spectral start (default 24 heavy-ball or 17 Lanczos)")
+    ap.add_argument("--spectral-tau", type=float, default=None,
+                    help="truncation of the spectral weights (default 2.5 heavy-ball, 3.0 Lanczos)")
     ap.add_argument("--spectral-momentum", type=float, default=0.99,
                     help="heavy-ball factor c of the spectral start")
     ap.add_argument("--spectral-lower", type=float, default=0.0,
@@ -95,8 +98,10 @@ def parse():
     args = ap.parse_args()
     if args.batch_iters is None:
         args.batch_iters = 30 if args.solver == "er" else 6
+    if args.spectral_tau is None:
+        args.spectral_tau = 3.0 if args.start == "lanczos" else 2.5
     if args.spectral_iters is None:
-        args.spectral_iters = 18 if args.start == "lanczos" else 24
+        args.spectral_iters = 17 if args.start == "lanczos" else 24
     return args
 
 
@@ -694,7 +699,7 @@ def batch_variant(ctx, args):
     iters, sp = args.batch_iters, args.batch_spectral_iters
     beta = args.er_momentum if args.solver == "er" else 0.0
     b = tm.Batch(ctx, probs, tm.retrieve_opts(args.solver, iters=iters, start="spectral", spectral_iters=sp, bf16=True,
-                                              spectral_tau=args.spectral_tau,
+                                              spectral_tau=args.batch_spectral_tau,
                                               spectral_momentum=args.spectral_momentum,
                                               spectral_lower=args.spectral_lower,
                                               er_momentum=beta), use_graph=True)
@@ -725,7 +730,8 @@ def batch_variant(ctx, args):
                        "rows_flagged": int((tm.decode_stats(p["stats"]).flags.numpy() & 1).sum())})
     b.close()
     return {"rows_per_s": round(rows / (ms * 1e-3), 1), "ms": round(ms, 3), "rows": rows, "tms": len(shapes),
-            "solver": args.solver, "iters": iters, "er_momentum": beta, "spectral_iters": sp, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
+            "solver": args.solver, "iters": iters, "er_momentum": beta, "spectral_iters": sp,
+            "spectral_tau": args.batch_spectral_tau, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
 
 
 def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver="er"):
