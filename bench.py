@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch-spectral-iters", type=int, default=24,
-                    help="heavy-ball spectral steps in the uneven batch")
-    ap.add_argument("--batch-spectral-tau", type=float, default=2.5,
-                    help="truncation of the spectral weights in the uneven batch")
+    ap.add_argument("--batch-start", choices=["spectral", "lanczos"], default="lanczos",
+                    help="spectral start of the uneven batch")
+    ap.add_argument("--batch-spectral-iters", type=int, default=None,
+                    help="spectral steps in the uneven batch (default 24 heavy-ball, 17 Lanczos)")
+    ap.add_argument("--batch-spectral-tau", type=float, default=None,
+                    help="truncation of the spectral weights in the uneven batch (default 2.5 heavy-ball, 3.0 Lanczos)")
     ap.add_argument("--start", choices=["spectral", "lanczos"], default="lanczos",
                     help="spectral start by heavy-ball power steps or by Lanczos steps")
     ap.add_argument("--spectral-iters", type=int, default=None,
@@ -82,7 +84,8 @@ def parse():
     ap.add_argument("--er-momentum", type=float, default=0.8,
                     help="Nesterov factor of the error-reduction iterations (0: plain ER)")
     ap.add_argument("--batch-iters", type=int, default=None,
-                    help="iterations in the uneven batch (default 30 for er, 6 sweeps for er_cyclic)")
+                    help="iterations in the uneven batch (default 30 for er; er_cyclic: 5 sweeps after the "
+                         "Lanczos start, 6 after the heavy-ball start)")
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 12-TM batch")
@@ -96,8 +99,12 @@ def parse():
                                                         "OUT"),
                     help="summarise rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs into the traffic file (no GPU)")
     args = ap.parse_args()
-    if args.batch_iters is None:
-        args.batch_iters = 30 if args.solver == "er" else 6
+    if args.batch_iters is None:  # each TM's mean fidelity reaches 0.99 (GPU sweep)
+        args.batch_iters = 30 if args.solver == "er" else (5 if args.batch_start == "lanczos" else 6)
+    if args.batch_spectral_iters is None:
+        args.batch_spectral_iters = 17 if args.batch_start == "lanczos" else 24
+    if args.batch_spectral_tau is None:
+        args.batch_spectral_tau = 3.0 if args.batch_start == "lanczos" else 2.5
     if args.spectral_tau is None:
         args.spectral_tau = 3.0 if args.start == "lanczos" else 2.5
     if args.spectral_iters is None:
@@ -698,7 +705,8 @@ def batch_variant(ctx, args):
     tuned = {f"{n1}x{n2}": tm.autotune(ctx, n1, n2, 4, 512, bf16=True) for n1, n2, _, _ in shapes[:4]}
     iters, sp = args.batch_iters, args.batch_spectral_iters
     beta = args.er_momentum if args.solver == "er" else 0.0
-    b = tm.Batch(ctx, probs, tm.retrieve_opts(args.solver, iters=iters, start="spectral", spectral_iters=sp, bf16=True,
+    b = tm.Batch(ctx, probs, tm.retrieve_opts(args.solver, iters=iters, start=args.batch_start, spectral_iters=sp,
+                                              bf16=True,
                                               spectral_tau=args.batch_spectral_tau,
                                               spectral_momentum=args.spectral_momentum,
                                               spectral_lower=args.spectral_lower,
@@ -730,7 +738,8 @@ def batch_variant(ctx, args):
                        "rows_flagged": int((tm.decode_stats(p["stats"]).flags.numpy() & 1).sum())})
     b.close()
     return {"rows_per_s": round(rows / (ms * 1e-3), 1), "ms": round(ms, 3), "rows": rows, "tms": len(shapes),
-            "solver": args.solver, "iters": iters, "er_momentum": beta, "spectral_iters": sp,
+            "solver": args.solver, "start": args.batch_start, "iters": iters, "er_momentum": beta,
+            "spectral_iters": sp,
             "spectral_tau": args.batch_spectral_tau, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
 
 

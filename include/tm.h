@@ -191,7 +191,7 @@ typedef struct {
 typedef struct tm_batch tm_batch;
 
 /* Plan the retrieval of n problems with the same options (method ER or
- * ER_CYCLIC; start GIVEN, BACKPROP or SPECTRAL). Every iteration is one persistent
+ * ER_CYCLIC; start GIVEN, BACKPROP, SPECTRAL or LANCZOS). Every iteration is one persistent
  * launch whose work items are (problem, row tile): 1 row of 8192 modes, 2 of
  * 4096, 4 of 2048 or 8 of 1024, each run with its grid's FFT specialisation
  * and the digit order chosen by tm_set_variant. With use_graph = 1 the whole

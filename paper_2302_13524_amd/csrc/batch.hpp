@@ -23,7 +23,9 @@ struct BatchProb {
   float* vscale;        // [P] spectral previous-iterate scale
   float* sums;          // [P][6] or null
   const float* rowmean;
-  int K, P, code;
+  cx<float>* lzV;       // Lanczos basis v_2 .. v_{k+1} [k][P][N] (v_1 is t)
+  float* lzH;           // Lanczos (alpha, beta) [k][P][2]
+  int K, P, code, N;
 };
 
 struct BatchItem {
@@ -38,10 +40,11 @@ struct BatchArgs {
   float tau, momentum, lower;
   float er_beta;         // ER Nesterov factor; t and t_prev alternate between t and vprev
   int swap;              // spectral steps, ER with er_beta: the current iterate is in vprev (odd steps)
+  int lz_j;              // Lanczos step index (BATCH_LZ)
   const cx<float>* tw32;
 };
 
-enum BatchMode { BATCH_ER = 0, BATCH_SPEC = 1, BATCH_ERC = 2 };
+enum BatchMode { BATCH_ER = 0, BATCH_SPEC = 1, BATCH_ERC = 2, BATCH_LZ = 3 };
 // Launch one batched pass (mode BATCH_*) over all items with `grid` workgroups.
 int batch_launch(int mode, int ibf16, int with_sums, const BatchArgs& a, int grid, void* stream);
 

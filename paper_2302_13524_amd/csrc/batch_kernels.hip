@@ -77,10 +77,21 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.er_beta = mom ? b.er_beta : 0.f;
     a.lz_bprev = nullptr;
     a.lz_out = nullptr;
+    if constexpr (MODE == BATCH_LZ) {
+      // step j from V(j) to V(j + 1), V(0) = t, V(i) = lzV + (i - 1) P N; (alpha, beta) into row j of lzH
+      const int j = b.lz_j;
+      const size_t rs = (size_t)pr.P * pr.N;
+      auto V = [&](int i) { return i == 0 ? pr.t : pr.lzV + (size_t)(i - 1) * rs; };
+      a.tin = V(j);
+      a.din = V(j > 0 ? j - 1 : 0);
+      a.tout = V(j + 1);
+      a.lz_bprev = j > 0 ? pr.lzH + (size_t)(j - 1) * pr.P * 2 : nullptr;
+      a.lz_out = pr.lzH + (size_t)j * pr.P * 2;
+    }
     a.out_bf16 = 0;
     a.tw32 = b.tw32;
     a.tw64 = nullptr;
-    constexpr int M = (MODE == BATCH_ER) ? M_ER : (MODE == BATCH_ERC) ? M_ERC : M_SPEC;
+    constexpr int M = (MODE == BATCH_ER) ? M_ER : (MODE == BATCH_ERC) ? M_ERC : (MODE == BATCH_LZ) ? M_LANCZOS : M_SPEC;
     switch (pr.code) {
       case 0: item_body<Plan<5, 5, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
       case 1: item_body<Plan<5, 5, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
@@ -112,6 +123,7 @@ int batch_launch(int mode, int ibf16, int with_sums, const BatchArgs& a, int gri
                                      : launch_m<BATCH_ER, float>(with_sums, a, grid, s);
   if (mode == BATCH_ERC) return ibf16 ? launch_m<BATCH_ERC, uint16_t>(with_sums, a, grid, s)
                                       : launch_m<BATCH_ERC, float>(with_sums, a, grid, s);
+  if (mode == BATCH_LZ) return ibf16 ? launch_m<BATCH_LZ, uint16_t>(0, a, grid, s) : launch_m<BATCH_LZ, float>(0, a, grid, s);
   return ibf16 ? launch_m<BATCH_SPEC, uint16_t>(0, a, grid, s) : launch_m<BATCH_SPEC, float>(0, a, grid, s);
 }
 

@@ -922,6 +922,9 @@ struct tm_batch {
   std::vector<float*> rowmean, sums;
   std::vector<void*> vprev;
   std::vector<float*> vscale;
+  std::vector<void*> lzV;
+  std::vector<float*> lzH;
+  std::vector<double*> lzY;
   hipStream_t cap = nullptr;
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
@@ -956,6 +959,28 @@ static int batch_enqueue(tm_batch* b, void* stream) {
       if (!p.d.P) continue;
       const int N = p.d.n1 * p.d.n2;
       if (o.spectral_iters & 1) e = tmk::launch_copy(p.t, b->vprev[i], (int64_t)p.d.P * N * sizeof(tm_c32), stream);
+      if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 1, b->rowsum[i], (double)p.d.K * N, stream);
+    }
+  } else if (o.start == TM_START_LANCZOS) {
+    for (int i = 0; i < n; ++i) {
+      const tm_problem& p = b->probs[i];
+      const int N = p.d.n1 * p.d.n2;
+      if (p.d.P == 0) continue;
+      if (!e) e = tmk::launch_row_isum(p.I, ibf, (int64_t)p.d.K * N, p.d.P, b->rowsum[i], b->rowmean[i], stream);
+      if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 0, nullptr, 1.0, stream);
+    }
+    tmk::BatchArgs a = b->args;
+    a.tau = o.spectral_tau;
+    for (int j = 0; j < o.spectral_iters && !e; ++j) {
+      a.lz_j = j;
+      e = tmk::batch_launch(tmk::BATCH_LZ, ibf, 0, a, b->grid, stream);
+    }
+    for (int i = 0; i < n && !e; ++i) {
+      const tm_problem& p = b->probs[i];
+      if (!p.d.P) continue;
+      const int N = p.d.n1 * p.d.n2;
+      e = tmk::launch_lz_ritz(b->lzH[i], o.spectral_iters, p.d.P, b->lzY[i], stream);
+      if (!e) e = tmk::launch_lz_combine(p.t, b->lzV[i], b->lzY[i], o.spectral_iters, p.d.P, N, stream);
       if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 1, b->rowsum[i], (double)p.d.K * N, stream);
     }
   } else if (o.start == TM_START_BACKPROP) {
@@ -1017,8 +1042,10 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
   if (o->method == TM_METHOD_ER_CYCLIC && o->er_momentum != 0.f)
     return fail(c, TM_EINVAL, "cyclic error reduction takes no momentum (er_momentum must be 0)");
   if (o->iters < 0 || (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) || o->start < TM_START_GIVEN ||
-      o->start > TM_START_SPECTRAL)
+      o->start > TM_START_LANCZOS)
     return fail(c, TM_EINVAL, "bad options");
+  if (o->start == TM_START_LANCZOS && (o->spectral_iters < 1 || o->spectral_iters > tmk::LZ_MAX || !(o->spectral_tau > 0.f)))
+    return fail(c, TM_EINVAL, "Lanczos steps (spectral_iters) 1..%d and spectral_tau > 0", tmk::LZ_MAX);
   if (o->start == TM_START_SPECTRAL &&
       (o->spectral_iters < 0 || !(o->spectral_tau > 0.f) || !(o->spectral_momentum >= 0.f && o->spectral_momentum < 1.f) ||
        !(o->spectral_lower >= -1.f && o->spectral_lower <= o->spectral_momentum)))
@@ -1032,6 +1059,7 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
   std::vector<tmk::BatchItem> items;
   size_t ws_bytes = 0;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const int lzk = o->start == TM_START_LANCZOS ? o->spectral_iters : 0;
   for (int i = 0; i < n; ++i) {
     const tm_problem& p = probs[i];
     tmk::row_launcher fn;
@@ -1049,6 +1077,8 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     size_t N = (size_t)p.d.n1 * p.d.n2;
     ws_bytes += al(p.d.P * 8) + al(p.d.P * 4) + al(p.d.P * tmk::NSUM * 4) + al(p.d.P * 16) + al(p.d.P * N * 8) +
                 al(p.d.P * 4);
+    if (o->start == TM_START_LANCZOS)
+      ws_bytes += al((size_t)lzk * p.d.P * N * 8) + al((size_t)lzk * p.d.P * 8) + al((size_t)lzk * p.d.P * 8);
   }
   size_t tab = al(n * sizeof(tmk::BatchProb)) + al(items.size() * sizeof(tmk::BatchItem));
   if (hipMalloc(&b->dmem, tab + ws_bytes + 256) != hipSuccess) { delete b; return fail(c, TM_ENOMEM, "batch workspace"); }
@@ -1062,6 +1092,17 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     b->sums64.push_back((double*)w); w += al(p.d.P * 16);
     b->vprev.push_back(w); w += al(p.d.P * N * 8);
     b->vscale.push_back((float*)w); w += al(p.d.P * 4);
+    b->lzV.push_back(nullptr);
+    b->lzH.push_back(nullptr);
+    b->lzY.push_back(nullptr);
+    if (lzk) {
+      b->lzV[i] = w; w += al((size_t)lzk * p.d.P * N * 8);
+      b->lzH[i] = (float*)w; w += al((size_t)lzk * p.d.P * 8);
+      b->lzY[i] = (double*)w; w += al((size_t)lzk * p.d.P * 8);
+    }
+    hp[i].lzV = (tmk::cx<float>*)b->lzV[i];
+    hp[i].lzH = b->lzH[i];
+    hp[i].N = (int)N;
     hp[i].masks = (const tmk::cx<float>*)p.masks;
     hp[i].I = p.I;
     hp[i].t = (tmk::cx<float>*)p.t;

@@ -39,26 +39,27 @@ def make_problems(ctx, shapes, cfg=970, bf16=True):
     return out
 
 
-def opts(mom=0.0, sp=5, iters=4, method="er"):
-    return tm.retrieve_opts(method, iters=iters, start="spectral", spectral_iters=sp, bf16=True, er_momentum=mom)
+def opts(mom=0.0, sp=5, iters=4, method="er", start="spectral"):
+    return tm.retrieve_opts(method, iters=iters, start=start, spectral_iters=sp, bf16=True, er_momentum=mom)
 
 
-def singles(ctx, probs, mom=0.0, sp=5, iters=4, method="er"):
+def singles(ctx, probs, mom=0.0, sp=5, iters=4, method="er", start="spectral"):
     res = []
     for p in probs:
         t = p["seed"].clone()
-        tm.tm_retrieve(ctx, p["masks"], p["I"], t, p["n1"], p["n2"], opts(mom, sp, iters, method))
+        tm.tm_retrieve(ctx, p["masks"], p["I"], t, p["n1"], p["n2"], opts(mom, sp, iters, method, start))
         res.append(t)
     return res
 
 
-@pytest.mark.parametrize("graph,mom,sp,iters,method", [(False, 0.0, 5, 4, "er"), (True, 0.0, 5, 4, "er"),
-                                                       (True, 0.8, 4, 3, "er"), (True, 0.0, 4, 3, "er_cyclic"),
-                                                       (False, 0.0, 3, 2, "er_cyclic")])
-def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters, method):
+@pytest.mark.parametrize("graph,mom,sp,iters,method,start", [
+    (False, 0.0, 5, 4, "er", "spectral"), (True, 0.0, 5, 4, "er", "spectral"), (True, 0.8, 4, 3, "er", "spectral"),
+    (True, 0.0, 4, 3, "er_cyclic", "spectral"), (False, 0.0, 3, 2, "er_cyclic", "spectral"),
+    (True, 0.0, 6, 2, "er_cyclic", "lanczos"), (False, 0.0, 1, 1, "er_cyclic", "lanczos")])
+def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters, method, start):
     probs = make_problems(ctx, SHAPES)
-    ref = singles(ctx, probs, mom, sp, iters, method)
-    b = tm.Batch(ctx, probs, opts(mom, sp, iters, method), use_graph=graph)
+    ref = singles(ctx, probs, mom, sp, iters, method, start)
+    b = tm.Batch(ctx, probs, opts(mom, sp, iters, method, start), use_graph=graph)
     for rep in range(3):
         for p in probs:
             p["t"].copy_(p["seed"])
@@ -67,7 +68,7 @@ def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters, method):
         for p, r in zip(probs, ref):
             assert torch.equal(p["t"], r), (rep, p["n1"], p["n2"])
         # eager work between replays
-        ref = singles(ctx, probs, mom, sp, iters, method)
+        ref = singles(ctx, probs, mom, sp, iters, method, start)
     st = tm.decode_stats(probs[0]["stats"])
     assert np.all(st.iters.numpy() == iters)
     b.close()
