@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--phase-iters", type=int, default=200,
                     help="phase L-BFGS iterations (with --phase-auto: the reference count and upper bound)")
     ap.add_argument("--phase-auto", type=int, default=1,
-                    help="1: use the smallest count (multiple of 10) whose offset spread is within 1%% of the "
+                    help="1: use the smallest count (multiple of 5, from 20) whose offset spread is within 1%% of the "
                          "reference, found by an untimed run")
     ap.add_argument("--phase-m", type=int, default=5, help="L-BFGS memory of the phase solve")
     ap.add_argument("--phase-ftol", type=float, default=0.0,
@@ -301,7 +301,7 @@ def main():
     n_ph = args.phase_iters
     if args.phase_auto:
         ref = spread_of(args.phase_iters)
-        for k in range(20, args.phase_iters, 10):
+        for k in range(20, args.phase_iters, 5):
             if spread_of(k) <= 1.01 * ref:
                 n_ph = k
                 break
@@ -349,6 +349,8 @@ def main():
     rs_ms, rs_n = tm.tm_profile_query(ctx, 7)
     tm.tm_profile_enable(ctx, False)
     ms_step = elapsed * 1e3 / args.steps
+    ph_it, ph_ev = tm.tm_phase_last_counts(ctx)
+    log(f"phase solve of the last step: {ph_it} iterations, {ph_ev} objective evaluations")
 
     # component timings (retrieval only; phase correction only; L-BFGS variant)
     def timed(fn, reps=3):
@@ -438,7 +440,7 @@ def main():
                             f"(c {args.spectral_momentum}, interval [{args.spectral_lower}, c] lambda)",
                    "solver": (f"error reduction, Nesterov factor {beta}" if beta > 0 else "error reduction")
                              if solver == "er" else "cyclic error reduction (one mask projection at a time)",
-                   "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_m": args.phase_m,
+                   "iters_to_0.99": n_er, "phase_iters": n_ph, "phase_evals": ph_ev, "phase_m": args.phase_m,
                    "phase_ftol": args.phase_ftol},
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,

@@ -248,12 +248,23 @@ typedef struct {
  *   I_d    [Nd][2nf1][2nf2] float defocus images
  *   phi    [P] double: start on entry (zeros in the paper), result on exit
  *   g_out  host double* (may be NULL): final objective value.
- * Synchronous with respect to the host (the line search reads the
- * objective back); work is queued on `stream`. */
+ * Synchronous with respect to the host (the line search runs on the
+ * device; the host reads its state between batches of iterations); work
+ * is queued on `stream`. */
 int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,
                             const tm_c32 *tm_est, const tm_c32 *theta, const float *I_d,
                             const tm_optics *optics, double *phi, const tm_phase_opts *opts,
                             double *g_out, void *stream);
+
+/* Counts of the last tm_phase_offset_correct call on ctx (0 before any):
+ * accepted L-BFGS iterations and objective evaluations, the start point's
+ * included. The line search (Sec. 2.3 leaves it open) tries a = 1 first,
+ * doubles a while the trial satisfies Armijo (c1 = 1e-4) but the slope there
+ * is still below 0.9 times the slope at phi (at most 20 times) and takes the
+ * best such trial; with no acceptable trial it halves a (at most 40 times).
+ *   iterations, evaluations: host int32_t* (not NULL).
+ * Returns TM_EINVAL on a null argument. */
+int tm_phase_last_counts(tm_ctx *ctx, int32_t *iterations, int32_t *evaluations);
 
 /* Evaluation path of the defocus model in tm_phase_objective and
  * tm_phase_offset_correct. h (Eq. angularspectrum) vanishes outside the

@@ -24,8 +24,10 @@ Readings:
     of the doubled grid; the Nyquist bin is zero under the pupil whenever
     NA < lambda / (2 ps), so its split is moot.
   * L-BFGS over phi in R^P from phi = 0 (the commented-out Algorithm 2),
-    memory m, backtracking Armijo line search (c = 1e-4, halving, first
-    trial a = 1, first direction -g/||g||), pairs with s^T y <= 0 skipped.
+    memory m, first direction -g/||g||, pairs with s^T y <= 0 skipped; line
+    search from a = 1 that doubles the step while a trial satisfies Armijo
+    (c = 1e-4) but not the curvature condition (c2 = 0.9) and takes the last
+    such trial, or halves it while no trial satisfies Armijo.
   * phi is defined up to a constant; comparisons remove the circular mean
     of the difference.
 """
@@ -137,9 +139,16 @@ class DefocusModel:
 
 
 def lbfgs_phase(model: DefocusModel, Id: np.ndarray, phi0: np.ndarray, iters: int, m: int = 5,
-                c_armijo: float = 1e-4, max_halvings: int = 40):
-    """L-BFGS over phi (real R^P) with backtracking Armijo steps. Returns
-    (phi, history of g)."""
+                c_armijo: float = 1e-4, max_halvings: int = 40, c_curv: float = 0.9, max_doublings: int = 20,
+                trace: list | None = None):
+    """L-BFGS over phi (real R^P). Line search from a = 1: a trial that lowers
+    g enough (Armijo, c_armijo) while g still falls steeply along d (the
+    curvature condition d^T grad(trial) >= c_curv d^T grad fails) is kept and
+    the step doubled, at most max_doublings times; the iteration takes the last
+    kept trial once a doubled trial is no better, or a trial that meets both
+    conditions. Before any trial is kept, failing trials halve the step (at
+    most max_halvings times). Returns (phi, history of g); `trace` (a list)
+    receives (a, f_trial, slope_trial, kept) per trial."""
     x = np.array(phi0, dtype=np.float64)
     f, g = model.objective(Id, x)
     S, Y = [], []
@@ -169,13 +178,30 @@ def lbfgs_phase(model: DefocusModel, Id: np.ndarray, phi0: np.ndarray, iters: in
             d = -g / gn
             slope = float(np.dot(g, d))
         a = 1.0
-        for _h in range(max_halvings):
+        best = None
+        halvings = doublings = 0
+        while True:
             fn, gn_ = model.objective(Id, x + a * d)
-            if fn <= f + c_armijo * a * slope:
+            ok = fn <= f + c_armijo * a * slope and (best is None or fn < best[1])
+            slope_n = float(np.dot(gn_, d))
+            if trace is not None:
+                trace.append((a, fn, slope_n, ok))
+            if ok:
+                best = (a, fn, gn_)
+                if halvings > 0 or slope_n >= c_curv * slope or doublings >= max_doublings:
+                    break
+                a *= 2.0
+                doublings += 1
+            elif best is not None:
                 break
-            a *= 0.5
-        else:
+            else:
+                halvings += 1
+                if halvings >= max_halvings:
+                    break
+                a *= 0.5
+        if best is None:
             break
+        a, fn, gn_ = best
         s_vec = a * d
         y_vec = gn_ - g
         if np.dot(s_vec, y_vec) > 0:

@@ -32,7 +32,7 @@ EXPORTED = (
     "tm_mlp_sync_bf16", "tm_mlp_start", "tm_mlp_gradients", "tm_mlp_train_step", "tm_gemm_bf16",
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
-    "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band",
+    "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band", "tm_phase_last_counts",
 )
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop", 9: "amp_gradient", 10: "amp_line_sums",
@@ -132,6 +132,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_tune_time.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
     lib.tm_set_variant.argtypes = [vp, i32, i32, i32]
     lib.tm_phase_set_band.argtypes = [vp, i32]
+    lib.tm_phase_last_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
     i64 = ctypes.c_int64
     lib.tm_pre_energy.argtypes = [vp, vp, i32, i64, i32, i32, vp, vp]
@@ -562,6 +563,13 @@ def tm_tune_time(ctx: Context, n1, n2, K, P, variant, bf16=False, reps=5) -> flo
 def tm_phase_set_band(ctx: Context, enable: bool):
     """Pupil-band (pruned) evaluation of the defocus model when the pupil's box is small (default on)."""
     ctx.check(ctx.lib.tm_phase_set_band(ctx.h, 1 if enable else 0), "tm_phase_set_band")
+
+
+def tm_phase_last_counts(ctx: Context):
+    """(accepted iterations, objective evaluations) of the context's last tm_phase_offset_correct."""
+    it, ev = ctypes.c_int32(0), ctypes.c_int32(0)
+    ctx.check(ctx.lib.tm_phase_last_counts(ctx.h, ctypes.byref(it), ctypes.byref(ev)), "tm_phase_last_counts")
+    return it.value, ev.value
 
 
 def tm_set_variant(ctx: Context, n1, n2, variant):

@@ -37,6 +37,7 @@ struct PhaseWork {
   double* Sp;     // band: [Nd][CH][16][16] complex, box spectrum partials per block of field rows
   double* V;      // band: [Nd][column blocks][16][16] complex, adjoint box spectrum partials
   double* Wn;     // band: [Nd][P] complex, conj(c_n) (A_n^H a_n r_n) at the pixels
+  double* dpart;  // [4 ceil(P / 256)] dvec^T grad over pixels 64 i .. 64 i + 63 (phase_eval with dvec)
   PhaseBand band; // host-side plan
 };
 
@@ -56,9 +57,10 @@ int phase_cgemm(const PhaseDims& d, const void* theta, const void* tm, double* p
 // caller). Returns hipError_t.
 int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, const void* theta,
                 const int32_t* pix, PhaseWork& w, void* stream);
-// g(phi) into w.gval[0] and dg/dphi into grad[P].
+// g(phi) into w.gval[0] and dg/dphi into grad[P]; with dvec (else null) also
+// the partial sums of dvec^T grad over each 64 pixels into w.dpart.
 int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const double* phi,
-               double* grad, PhaseWork& w, const double* tw64, void* stream);
+               double* grad, PhaseWork& w, const double* tw64, void* stream, const double* dvec = nullptr);
 
 // |A_n e^{j phi}|^2 into I_out [Nd][2nf1][2nf2] (float).
 int phase_images(const PhaseDims& d, const int32_t* pix, const double* phi, float* I_out, PhaseWork& w,
@@ -69,11 +71,13 @@ struct PhaseLb {
   double* phi;    // [P]
   double* g;      // [P] gradient at phi
   double* gt;     // [P] gradient at trial
+  double* gb;     // [P] gradient at the best trial kept while the step grows
   double* phit;   // [P] trial point
   double* d;      // [P]
   double* S;      // [m][P]
   double* Y;      // [m][P]
   double* sc;     // [phase_lb_state_doubles(m)] iteration state (see phase_kernels.hip)
+  const double* dpart;  // [(P + 63) / 64] partials of d^T gt from the evaluation at the trial
 };
 int phase_lb_state_doubles(int m);
 // Device-controlled iterations (see phase_kernels.hip): init after the first

@@ -561,12 +561,22 @@ __global__ void __launch_bounds__(256) k_gather_part(double* wpart, const double
   wpart[((size_t)blockIdx.y * P + p) * 2 + 1] = w.y;
 }
 
+// Partial sum of dvec^T grad over the 64 pixels of this wave (wave-uniform
+// call; lanes past P pass gr = 0), into dpart[pixel / 64].
+__device__ __forceinline__ void dot_part(const double* dvec, double* dpart, int p, int P, double gr) {
+  double x = (p < P) ? dvec[p] * gr : 0.0;
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  if ((threadIdx.x & 63) == 0) dpart[p >> 6] = x;
+}
+
 // grad[p] = -4 Im(conj(u_p) w[p]) with w the sum of the slices; gval = sum of
-// the residual partials
+// the residual partials; with dvec, the partials of dvec^T grad
 __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, const double* wpart, const double* phi,
-                                                 const double* gpart, int ngp, int nslice, int P, const int* skip) {
+                                                 const double* gpart, int ngp, int nslice, int P, const int* skip,
+                                                 const double* dvec, double* dpart) {
   if (skip && *skip) return;
   int p = blockIdx.x * 256 + threadIdx.x;
+  double gr = 0.0;
   if (p < P) {
     z2 w{0.0, 0.0};
     for (int sl = 0; sl < nslice; ++sl) {
@@ -576,8 +586,10 @@ __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, cons
     double sn, cs;
     sincos(phi[p], &sn, &cs);
     z2 q = zmulc(w, z2{cs, sn});  // w conj(u)
-    grad[p] = -4.0 * q.y;
+    gr = -4.0 * q.y;
+    grad[p] = gr;
   }
+  if (dvec) dot_part(dvec, dpart, p, P, gr);
   if (blockIdx.x == 0) {  // objective: block-wide sum of the residual partials
     __shared__ double red[4];
     double s = 0;
@@ -891,11 +903,13 @@ __global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vp, 
   }
 }
 
-// grad[p] = -4 Im(conj(u_p) sum_n Wn[n][p]); gval = sum of the objective partials
+// grad[p] = -4 Im(conj(u_p) sum_n Wn[n][p]); gval = sum of the objective partials;
+// with dvec, the partial of dvec^T grad over the workgroup's 64 pixels.
 // 64 pixels x 4 slices of the images per workgroup: each thread adds its
 // slice (loads issued together), the four slices meet in LDS
 __global__ void __launch_bounds__(256) k_band_gather(double* grad, double* gval, const double* Wn, const double* phi,
-                                                     const double* gpart, int ngp, int Nd, int P, const int* skip) {
+                                                     const double* gpart, int ngp, int Nd, int P, const int* skip,
+                                                     const double* dvec, double* dpart) {
   if (skip && *skip) return;
   __shared__ z2 part[4][64];
   const int pl = threadIdx.x & 63, sl = threadIdx.x >> 6;
@@ -908,11 +922,16 @@ __global__ void __launch_bounds__(256) k_band_gather(double* grad, double* gval,
   }
   part[sl][pl] = w;
   __syncthreads();
-  if (sl == 0 && p < P) {
-    w = zadd(zadd(part[0][pl], part[1][pl]), zadd(part[2][pl], part[3][pl]));
-    double sn, cs;
-    sincos(phi[p], &sn, &cs);
-    grad[p] = -4.0 * zmulc(w, z2{cs, sn}).y;
+  if (sl == 0) {  // the first wave
+    double gr = 0.0;
+    if (p < P) {
+      w = zadd(zadd(part[0][pl], part[1][pl]), zadd(part[2][pl], part[3][pl]));
+      double sn, cs;
+      sincos(phi[p], &sn, &cs);
+      gr = -4.0 * zmulc(w, z2{cs, sn}).y;
+      grad[p] = gr;
+    }
+    if (dvec) dot_part(dvec, dpart, p, P, gr);
   }
   if (blockIdx.x == 0) {
     __shared__ double red[4];
@@ -965,14 +984,16 @@ size_t band_nxb_max(const PhaseDims& d) {
 }
 // image-pass workgroups: at most 2 nf2 column blocks per image
 size_t gpart_doubles(const PhaseDims& d) { return std::max((size_t)mid_groups(d), (size_t)d.Nd * 2 * d.nf2); }
+// one partial per wave of the gather kernels (64 pixels each, four waves per 256-pixel workgroup)
+size_t dpart_doubles(const PhaseDims& d) { return 4 * (((size_t)d.P + 255) / 256); }
 }  // namespace
 
 size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
   size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 2 * G * 2 +
                gpart_doubles(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1 + band_Sp_doubles(d) +
-               (size_t)d.Nd * band_nxb_max(d) * BM * BM * 2 + (size_t)d.Nd * d.P * 2;
-  return dbl * sizeof(double) + 13 * 256;
+               (size_t)d.Nd * band_nxb_max(d) * BM * BM * 2 + (size_t)d.Nd * d.P * 2 + dpart_doubles(d);
+  return dbl * sizeof(double) + 14 * 256;
 }
 
 PhaseBand phase_band_plan(const PhaseDims& d, const PhaseOptics& o, int enable) {
@@ -1031,6 +1052,7 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->Sp = take(band_Sp_doubles(d));
   w->V = take((size_t)d.Nd * band_nxb_max(d) * BM * BM * 2);
   w->Wn = take((size_t)d.Nd * d.P * 2);
+  w->dpart = take(dpart_doubles(d));
   w->band = PhaseBand{};
 }
 
@@ -1048,7 +1070,7 @@ int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, co
 }
 
 int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const double* phi, double* grad,
-               PhaseWork& w, const double* tw64, void* stream) {
+               PhaseWork& w, const double* tw64, void* stream, const double* dvec) {
   hipStream_t s = (hipStream_t)stream;
   int e;
   const int G = d.nf1 * d.nf2;
@@ -1066,7 +1088,7 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
     k_band_pix<<<dim3((d.P + 255) / 256, d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, w.h, pix, b, d.P, d.nf1, d.nf2, tw64,
                                                              w.skip);
     k_band_gather<<<(d.P + 63) / 64, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
-                                                  w.skip);
+                                                  w.skip, dvec, w.dpart);
     return (int)hipGetLastError();
   }
   if ((e = forward_to_rows(d, phi, w, tw64, s))) return e;
@@ -1076,7 +1098,8 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
   k_rows_adj<<<grid_of(d.Nd * d.nf1, d.nf2), LWG, 0, s>>>(w.A, d.Nd, d.nf1, d.nf2, tw64, w.skip);
   if ((e = (int)hipGetLastError())) return e;
   k_gather_part<<<dim3((d.P + 255) / 256, nsl), 256, 0, s>>>(w.w, w.A, w.c, pix, d.Nd, d.P, G, per, w.skip);
-  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, ngp, nsl, d.P, w.skip);
+  k_gather<<<(d.P + 255) / 256, 256, 0, s>>>(grad, w.gval, w.w, phi, w.gpart, ngp, nsl, d.P, w.skip, dvec,
+                                             w.dpart);
   return (int)hipGetLastError();
 }
 
@@ -1115,16 +1138,24 @@ __device__ void bsum_finish(int nv, double* red, double* out) {
 
 // Line search and iteration control on the device, so that iterations replay
 // back-to-back without host synchronisation. State sc (doubles):
-// [0] head, [1] count, [2] slope of d, [3] step a, [4] objective f at phi,
-// [5] accepted iterations, [6] last trial accepted, [7] halvings of this
-// direction, [8] a trial is pending, [9] converged (the last accepted trial
-// lowered f by at most ftol f); then the m x m matrices SY[i][j] =
-// s_i^T y_j and YY[i][j] = y_i^T y_j over the history slots.
+// [0] head, [1] count, [2] slope of d, [3] step a of the pending trial,
+// [4] objective f at phi, [5] accepted iterations, [6] objective evaluations
+// (the start point and every trial point set so far),
+// [7] halvings of this direction, [8] a trial is pending, [9] converged (the
+// last accepted trial lowered f by at most ftol f), [10] a best trial is kept,
+// [11] its step, [12] its objective, [13] doublings of this direction; then
+// the m x m matrices SY[i][j] = s_i^T y_j and YY[i][j] = y_i^T y_j over the
+// history slots.
 // *skip = 1 ends the solve (every later kernel returns at once).
-// One iteration is k_piter followed by the objective and gradient at phit:
-// k_piter first decides on the pending trial (Armijo f_t <= f + 1e-4 a slope),
-// then, after an accepted trial, stores the pair and takes a new direction,
-// or halves a; and it sets the trial point phit = phi + a d.
+// One iteration is k_piter followed by the objective and gradient at phit
+// (with the partials of d^T g there): k_piter first decides on the pending
+// trial and sets the next trial point phit = phi + a d. Line search: a trial
+// that satisfies Armijo (f_t <= f + 1e-4 a slope) and is below the kept one
+// is kept; while no halving has happened and the slope there is still below
+// 0.9 slope (the curvature condition fails), the step doubles (at most 20
+// times); otherwise, or when a trial fails after one was kept, the kept trial
+// is accepted: the pair is stored and a new direction taken with a = 1. While
+// nothing is kept, a failing trial halves the step (at most 40 times).
 // The direction is the L-BFGS product -H g in the compact form of Byrd,
 // Nocedal and Schnabel (1994): with a = S^T g, b = Y^T g over the k stored
 // pairs (oldest first), R the upper triangle of S^T Y, D its diagonal and
@@ -1133,7 +1164,9 @@ __device__ void bsum_finish(int nv, double* red, double* out) {
 // two-loop recursion; all its dot products, and those of the new pair with
 // the stored ones, come from one pass over the vectors, and the direction
 // and the trial point from a second.
-constexpr int SC_HIST = 10;
+constexpr int SC_HIST = 14;
+constexpr double LS_C1 = 1e-4, LS_C2 = 0.9;
+constexpr int LS_HALVINGS = 40, LS_DOUBLINGS = 20;
 
 // smat (LDS, SMAT doubles): the k x k blocks of SY and YY in age order, then
 // the small solve's u and p.
@@ -1264,15 +1297,15 @@ __device__ void first_direction(PhaseLb& L, int P, int m, double* red, double* s
   dir_apply(L, P, m, k, head, coef);
 }
 
-// Accepted trial: the pair s = a d, y = g_t - g goes into slot head (its dot
-// products with the stored pairs update SY and YY), phi and g move to the
-// trial, and the dot products of the next direction (with g_t) are taken in
-// the same pass. Returns 1 (to every thread) when the solve ends here.
-__device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double fn, double* red, double* sc,
-                      double* sh, double* smat) {
+// Accepted trial at step a with objective fn and gradient gsrc (the pending
+// trial's or the kept one's): the pair s = a d, y = g_t - g goes into slot
+// head (its dot products with the stored pairs update SY and YY), phi and g
+// move to the trial, and the dot products of the next direction (with g_t)
+// are taken in the same pass. Returns 1 (to every thread) when the solve ends here.
+__device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, const double* gsrc, double a, double fn,
+                      double* red, double* sc, double* sh, double* smat) {
   const int head = (int)sc[0], count = (int)sc[1];
   const int keep = count < m ? count : m - 1;  // stored pairs that stay (the oldest is overwritten when full)
-  const double a = sc[3];
   double* Sh = L.S + (size_t)head * P;
   double* Yh = L.Y + (size_t)head * P;
   // per stored pair j: s_j^T y, y_j^T y, s_j^T g_t, y_j^T g_t (sums 4j..4j+3); then s^T y, y^T y,
@@ -1291,7 +1324,7 @@ __device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double f
       for (int e = 0; e < UE; ++e) {
         const int i = i0 + e * PWG;
         const bool ok = i < P;
-        gt[e] = ok ? L.gt[i] : 0.0;
+        gt[e] = ok ? gsrc[i] : 0.0;
         dd[e] = ok ? L.d[i] : 0.0;
         gg[e] = ok ? L.g[i] : 0.0;
         ph[e] = (ok && last) ? L.phi[i] : 0.0;
@@ -1371,7 +1404,8 @@ __device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double f
     sc[9] = (f - fn <= ftol * fabs(fn)) ? 1.0 : 0.0;
     sc[4] = fn;
     sc[5] += 1.0;
-    sc[6] = 1.0;
+    sc[10] = 0.0;
+    sc[13] = 0.0;
     fin = (sc[5] >= (double)iters || (ftol > 0.0 && sc[9] != 0.0)) ? 1 : 0;
     if (!fin) {
       // a_j, b_j of the pairs in age order: the stored ones, then the new one
@@ -1398,6 +1432,42 @@ __device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, double f
   return 0;
 }
 
+// phit = phi + as d
+__device__ void trial_point(PhaseLb& L, int P, double as, bool keep_gt) {
+  for (int i0 = threadIdx.x; i0 < P; i0 += UE * PWG) {
+    double f[UE], e[UE], gk[UE];
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+      const int i = i0 + u * PWG;
+      f[u] = i < P ? L.phi[i] : 0.0;
+      e[u] = i < P ? L.d[i] : 0.0;
+      gk[u] = (keep_gt && i < P) ? L.gt[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+      const int i = i0 + u * PWG;
+      if (i < P) {
+        L.phit[i] = f[u] + as * e[u];
+        if (keep_gt) L.gb[i] = gk[u];
+      }
+    }
+  }
+}
+
+// A trial point is set: the evaluation that follows is pending.
+__device__ __forceinline__ void new_trial(double* sc) {
+  sc[8] = 1.0;
+  sc[6] += 1.0;
+}
+
+// The solve ends: flag it for every later kernel.
+__device__ void end_solve(int* skip, double* sc) {
+  if (threadIdx.x == 0) {
+    *skip = 1;
+    sc[8] = 0.0;
+  }
+}
+
 // One iteration on the state sc (an LDS copy; every branch below is taken by
 // the whole workgroup).
 __device__ void piter_body(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip,
@@ -1407,47 +1477,56 @@ __device__ void piter_body(PhaseLb& L, int P, int m, int iters, double ftol, con
   __syncthreads();
   if (sc[8] != 0.0) {
     const double fn = gval[0], f = sc[4], a = sc[3], slope = sc[2];
-    if (fn <= f + 1e-4 * a * slope) {  // Armijo: accept, new direction, trial point at step 1
-      const int fin = accept(L, P, m, iters, ftol, fn, red, sc, sh, smat);
-      if (fin) {
-        if (threadIdx.x == 0) {
-          *skip = 1;
-          sc[8] = 0.0;
-        }
+    const bool kept = sc[10] != 0.0;
+    if (fn <= f + LS_C1 * a * slope && (!kept || fn < sc[12])) {
+      bool take = sc[7] > 0.0 || sc[13] >= (double)LS_DOUBLINGS;
+      if (!take) {  // curvature condition: the slope d^T g_t from the evaluation's partials
+        double x = 0.0;
+        for (int i = threadIdx.x; i < (P + 63) / 64; i += PWG) x += L.dpart[i];
+        wave_put(x, 0, red);
+        bsum_finish(1, red, sh);
+        take = sh[0] >= LS_C2 * slope;
+        __syncthreads();  // sh is reused below
+      }
+      if (take) {
+        if (accept(L, P, m, iters, ftol, L.gt, a, fn, red, sc, sh, smat)) end_solve(skip, sc);
+        else if (threadIdx.x == 0) new_trial(sc);
         return;
       }
-      if (threadIdx.x == 0) sc[8] = 1.0;
+      // keep this trial and double the step
+      if (threadIdx.x == 0) {
+        sc[10] = 1.0;
+        sc[11] = a;
+        sc[12] = fn;
+        sc[13] += 1.0;
+        sc[3] = 2.0 * a;
+        new_trial(sc);
+      }
+      trial_point(L, P, 2.0 * a, true);
       return;
     }
-    // rejected: halve the step along d
+    if (kept) {  // the doubled step is no better: take the kept trial
+      if (accept(L, P, m, iters, ftol, L.gb, sc[11], sc[12], red, sc, sh, smat)) end_solve(skip, sc);
+      else if (threadIdx.x == 0) new_trial(sc);
+      return;
+    }
+    // rejected, nothing kept: halve the step along d
     __syncthreads();
     if (threadIdx.x == 0) {
-      sc[6] = 0.0;
       sc[7] += 1.0;
-      if (sc[7] >= 40.0) stop = 1;  // no sufficient decrease along d: stop
-      else sc[3] *= 0.5;
+      if (sc[7] >= (double)LS_HALVINGS) {
+        stop = 1;  // no sufficient decrease along d: stop
+      } else {
+        sc[3] *= 0.5;
+        new_trial(sc);
+      }
     }
     __syncthreads();
     if (stop) {
-      if (threadIdx.x == 0) {
-        *skip = 1;
-        sc[8] = 0.0;
-      }
+      end_solve(skip, sc);
       return;
     }
-    const double as = sc[3];
-    for (int i0 = threadIdx.x; i0 < P; i0 += UE * PWG) {
-      double f[UE], e[UE];
-#pragma unroll
-      for (int u = 0; u < UE; ++u) {
-        const int i = i0 + u * PWG;
-        f[u] = i < P ? L.phi[i] : 0.0;
-        e[u] = i < P ? L.d[i] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < UE; ++u)
-        if (i0 + u * PWG < P) L.phit[i0 + u * PWG] = f[u] + as * e[u];
-    }
+    trial_point(L, P, sc[3], false);
     return;
   }
   // no pending trial: the first direction after the start
@@ -1459,6 +1538,8 @@ __device__ void piter_body(PhaseLb& L, int P, int m, int iters, double ftol, con
   if (threadIdx.x == 0) {
     sc[3] = 1.0;
     sc[7] = 0.0;
+    sc[10] = 0.0;
+    sc[13] = 0.0;
     if (!(sc[2] < 0.0)) stop = 1;  // zero gradient
   }
   __syncthreads();
@@ -1466,7 +1547,7 @@ __device__ void piter_body(PhaseLb& L, int P, int m, int iters, double ftol, con
     if (threadIdx.x == 0) *skip = 1;
     return;
   }
-  if (threadIdx.x == 0) sc[8] = 1.0;
+  if (threadIdx.x == 0) new_trial(sc);
 }
 
 __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iters, double ftol, const double* gval,
@@ -1491,7 +1572,7 @@ __global__ void k_pinit(double* sc, int n, const double* gval, int* skip) {
   __syncthreads();
   if (threadIdx.x == 0) {
     sc[4] = gval[0];
-    sc[6] = 1.0;
+    sc[6] = 1.0;  // the start point
     *skip = 0;
   }
 }

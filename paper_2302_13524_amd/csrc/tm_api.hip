@@ -58,6 +58,7 @@ struct tm_ctx {
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
   } pg;
+  int32_t ph_iters = 0, ph_evals = 0;  // accepted iterations and evaluations of the last phase solve
 };
 
 constexpr int PHASE_GRAPH_ITERS = 10;  // phase L-BFGS iterations captured per graph replay
@@ -636,7 +637,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   if ((r = phase_prepare(c, dd, pix, tm_est, theta, o, pd, w, stream))) return r;
   const int P = dd->P, m = po->m;
   size_t vb = ((P * sizeof(double) + 255) / 256) * 256;
-  char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (5 + 2 * m) + tmk::phase_lb_state_doubles(m) * sizeof(double));
+  char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (6 + 2 * m) + tmk::phase_lb_state_doubles(m) * sizeof(double));
   if (!lb) return fail(c, TM_ENOMEM, "phase L-BFGS workspace");
   tmk::PhaseLb L;
   L.phi = (double*)(lb);
@@ -644,17 +645,19 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   L.gt = (double*)(lb + 2 * vb);
   L.phit = (double*)(lb + 3 * vb);
   L.d = (double*)(lb + 4 * vb);
-  L.S = (double*)(lb + 5 * vb);
-  L.Y = (double*)(lb + (5 + m) * vb);
-  L.sc = (double*)(lb + (5 + 2 * m) * vb);
+  L.gb = (double*)(lb + 5 * vb);
+  L.S = (double*)(lb + 6 * vb);
+  L.Y = (double*)(lb + (6 + m) * vb);
+  L.sc = (double*)(lb + (6 + 2 * m) * vb);
+  L.dpart = w.dpart;
   HIPCHK(c, hipMemcpyAsync(L.phi, phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   int e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
   if (!e) e = tmk::phase_lb_init(L, P, m, w.gval, w.skip, stream);
   if (e) return hipfail(c, e, "phase start");
   if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
   double* hb = c->pinned;
-  // One iteration (new direction or halved step, trial point, objective and
-  // gradient there, Armijo decision) is a captured graph; the line-search
+  // One iteration (decision on the pending trial, new direction or changed
+  // step, trial point, objective and gradient there) is a captured graph; the line-search
   // control lives in device state, so replays are queued back-to-back and
   // the host reads the state only between batches of replays.
   if (po->iters > 0) {
@@ -678,7 +681,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
         // them (an iteration after the solve has ended returns at once)
         for (int r = 0; r < PHASE_GRAPH_ITERS && !e; ++r) {
           e = tmk::phase_lb_iter(L, P, m, po->iters, po->ftol, w.gval, w.skip, cap);
-          if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap);
+          if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, cap, L.d);
         }
         hipError_t he2 = hipStreamEndCapture(cap, &graph);
         if (!e && he2 == hipSuccess) he2 = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
@@ -716,12 +719,22 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
     }
     if (e) return hipfail(c, e, "phase iterations");
   }
-  HIPCHK(c, hipMemcpyAsync(hb + 3, L.sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+  // f, accepted iterations and evaluations (state entries 4, 5, 6)
+  HIPCHK(c, hipMemcpyAsync(hb + 3, L.sc + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   double f = hb[3];
+  c->ph_iters = (int32_t)hb[4];
+  c->ph_evals = (int32_t)hb[5];
   HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (g_out) *g_out = f;
+  return TM_OK;
+}
+
+extern "C" int tm_phase_last_counts(tm_ctx* c, int32_t* iterations, int32_t* evaluations) {
+  if (!c || !iterations || !evaluations) return TM_EINVAL;
+  *iterations = c->ph_iters;
+  *evaluations = c->ph_evals;
   return TM_OK;
 }
 

@@ -99,6 +99,24 @@ def test_noiseless_offsets_recovered(ctx):
     assert np.max(np.abs(err - err_o)) < 1e-5
 
 
+@pytest.mark.parametrize("iters", [1, 2, 3, 6, 12])
+def test_iterations_follow_the_oracle(ctx, iters):
+    # the device line search (growing step, kept trial, halving) and the
+    # compact L-BFGS direction take the oracle's steps iteration by iteration
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, 0.6, 0.6, cfg=957, noise=1e4)
+    trace = []
+    phi_o, hist = df.lbfgs_phase(mdl, Id.astype(np.float64), np.zeros(P), iters, trace=trace)
+    phi = torch.zeros(P, dtype=torch.float64, device=dev())
+    g = tm.tm_phase_offset_correct(ctx, torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta),
+                                   f32(Id), (LAM, PS, 0.6, 20 * LAM), phi, nf, nf, iters=iters, m=5)
+    print(f"iters {iters}: {len(trace)} oracle trials, steps {[t[0] for t in trace][:8]}", flush=True)
+    assert np.max(np.abs(phi.cpu().numpy() - phi_o)) <= 1e-9 * max(1.0, np.max(np.abs(phi_o)))
+    assert abs(g - hist[-1]) <= 1e-11 * hist[-1]
+    # the same trials: one evaluation at the start plus one per trial point
+    assert tm.tm_phase_last_counts(ctx) == (iters, 1 + len(trace))
+
+
 def test_rejects_bad_pixels(ctx):
     nf, P, N, Nd = 16, 40, 24, 12
     pix, tm_est, theta, Id, _, _ = build(nf, P, N, Nd, 0.6, 0.6, cfg=952)

@@ -114,3 +114,36 @@ def test_noiseless_offsets_recovered():
     err = df.circular_offset_error(phi, phi_true)
     assert np.max(np.abs(err)) < 1e-8, np.max(np.abs(err))
     assert np.all(np.diff(hist) <= 0)
+
+
+def test_line_search_postconditions_and_expansion_pays():
+    # Every accepted step satisfies Armijo, checked on the objective evaluated
+    # afresh; a step that grew was followed by a trial that failed (or hit the
+    # doubling cap), and one that did not grow either met the curvature
+    # condition or came after a halving.
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix = tm_synth.nearest_pixels(nf, P)
+    tm_true = tm_synth.speckle_tm(N, nf, 0.6, pix, tm_synth.rng(43, 1))
+    phi_true = tm_synth.offsets(P, tm_synth.rng(43, 5))
+    tm_est = np.exp(-1j * phi_true)[:, None] * tm_true
+    theta = tm_synth.defocus_phases(Nd, N, tm_synth.rng(43, 4))
+    mdl = df.DefocusModel(tm_est, theta, pix, nf, nf, LAM, PS, 0.6, 20 * LAM)
+    Id = tm_synth.poisson_counts(mdl.images(phi_true), 1e4, tm_synth.rng(43, 6))
+    trace = []
+    phi, hist = df.lbfgs_phase(mdl, Id, np.zeros(P), 3, trace=trace)
+    # replay the first iteration independently: d = -g / ||g||
+    f0, g0 = mdl.objective(Id, np.zeros(P))
+    d = -g0 / np.linalg.norm(g0)
+    slope = g0 @ d
+    a_steps = [t[0] for t in trace]
+    assert a_steps[0] == 1.0
+    # the first iteration doubles from a = 1 (a unit step is tiny against ||phi|| ~ sqrt(P))
+    assert a_steps[1] == 2.0
+    i = 0
+    while trace[i + 1][0] == 2 * trace[i][0] and trace[i][3]:
+        i += 1
+    a_acc = trace[i][0] if trace[i][3] else trace[i - 1][0]
+    f_acc, g_acc = mdl.objective(Id, a_acc * d)
+    assert f_acc <= f0 + 1e-4 * a_acc * slope
+    assert np.isclose(hist[1], f_acc, rtol=1e-13)
+    assert (not trace[i][3]) or g_acc @ d >= 0.9 * slope or i == 20
