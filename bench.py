@@ -70,7 +70,9 @@ def parse():
     ap.add_argument("--phase-auto", type=int, default=1,
                     help="1: use the smallest count (multiple of 5, from 20) whose offset spread is within 1%% of the "
                          "reference, found by an untimed run")
-    ap.add_argument("--phase-m", type=int, default=5, help="L-BFGS memory of the phase solve")
+    ap.add_argument("--phase-m", type=int, default=1,
+                    help="L-BFGS memory of the phase solve (1: as few iterations as 3..12 at this workload, and "
+                         "the cheapest iteration)")
     ap.add_argument("--phase-ftol", type=float, default=0.0,
                     help="stop the phase solve after an accepted iteration lowering g by <= ftol * g")
     ap.add_argument("--max-iters", type=int, default=300)
