@@ -340,14 +340,29 @@ struct LdsStride {
   static constexpr int value = (G::AXIS == 1 && PL::PADSH < 30) ? G::S * (PL::N2 + 1) : G::hstride();
 };
 
+// FP32 complex values go to LDS as 8-byte pairs. FP64 complex values go as
+// two planes (real parts, then imaginary parts, each LDS_ROW doubles in the
+// row's region): every access is then 8 bytes wide with the FP32 addressing,
+// which the padding keeps free of bank conflicts (16-byte elements are not).
 template <class PL, int P, typename T>
 __device__ __forceinline__ void lds_store(cx<T>* lds, const cx<T>* x, int ltid) {
   using G = PassGeo<PL, P>;
 #pragma unroll
   for (int j = 0; j < G::NB; ++j) {
-    cx<T>* p = lds + PL::lds_addr(bf_base<PL, P>(ltid, j));
+    const int a = PL::lds_addr(bf_base<PL, P>(ltid, j));
+    if constexpr (sizeof(T) == 8) {
+      double* re = (double*)lds + a;
+      double* im = re + PL::LDS_ROW;
 #pragma unroll
-    for (int h = 0; h < G::R; ++h) p[h * LdsStride<PL, P>::value] = x[j * G::R + h];
+      for (int h = 0; h < G::R; ++h) {
+        re[h * LdsStride<PL, P>::value] = x[j * G::R + h].x;
+        im[h * LdsStride<PL, P>::value] = x[j * G::R + h].y;
+      }
+    } else {
+      cx<T>* p = lds + a;
+#pragma unroll
+      for (int h = 0; h < G::R; ++h) p[h * LdsStride<PL, P>::value] = x[j * G::R + h];
+    }
   }
 }
 
@@ -356,9 +371,18 @@ __device__ __forceinline__ void lds_load(const cx<T>* lds, cx<T>* x, int ltid) {
   using G = PassGeo<PL, P>;
 #pragma unroll
   for (int j = 0; j < G::NB; ++j) {
-    const cx<T>* p = lds + PL::lds_addr(bf_base<PL, P>(ltid, j));
+    const int a = PL::lds_addr(bf_base<PL, P>(ltid, j));
+    if constexpr (sizeof(T) == 8) {
+      const double* re = (const double*)lds + a;
+      const double* im = re + PL::LDS_ROW;
 #pragma unroll
-    for (int h = 0; h < G::R; ++h) x[j * G::R + h] = p[h * LdsStride<PL, P>::value];
+      for (int h = 0; h < G::R; ++h)
+        x[j * G::R + h] = cx<T>{re[h * LdsStride<PL, P>::value], im[h * LdsStride<PL, P>::value]};
+    } else {
+      const cx<T>* p = lds + a;
+#pragma unroll
+      for (int h = 0; h < G::R; ++h) x[j * G::R + h] = p[h * LdsStride<PL, P>::value];
+    }
   }
 }
 
