@@ -22,4 +22,7 @@ constexpr int LZ_MAX = 64;
 int launch_lz_ritz(const float* hist, int k, int P, double* y, void* stream);
 // t[p] <- sum_{j<k} y[p][j] V_j[p] with V_0 = t (in place) and V_j = Vw + (j - 1) P N.
 int launch_lz_combine(void* t, const void* Vw, const double* y, int k, int P, int N, void* stream);
+// launch_lz_combine followed by launch_row_rescale(mode 1, rowsum, denom)
+int launch_lz_combine_scaled(void* t, const void* Vw, const double* y, int k, int P, int N, const double* rowsum,
+                             double denom, void* stream);
 }  // namespace tmk

@@ -471,8 +471,7 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
       if (r) return r;
     }
     e = tmk::launch_lz_ritz(hist, k, d.P, y, stream);
-    if (!e) e = tmk::launch_lz_combine(t, Vw, y, k, d.P, N, stream);
-    if (!e) e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
+    if (!e) e = tmk::launch_lz_combine_scaled(t, Vw, y, k, d.P, N, rowsum, (double)d.K * N, stream);
     if (e) return hipfail(c, e, "Lanczos Ritz vector");
   }
 
@@ -993,8 +992,8 @@ static int batch_enqueue(tm_batch* b, void* stream) {
       if (!p.d.P) continue;
       const int N = p.d.n1 * p.d.n2;
       e = tmk::launch_lz_ritz(b->lzH[i], o.spectral_iters, p.d.P, b->lzY[i], stream);
-      if (!e) e = tmk::launch_lz_combine(p.t, b->lzV[i], b->lzY[i], o.spectral_iters, p.d.P, N, stream);
-      if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 1, b->rowsum[i], (double)p.d.K * N, stream);
+      if (!e) e = tmk::launch_lz_combine_scaled(p.t, b->lzV[i], b->lzY[i], o.spectral_iters, p.d.P, N,
+                                                b->rowsum[i], (double)p.d.K * N, stream);
     }
   } else if (o.start == TM_START_BACKPROP) {
     for (int i = 0; i < n && !e; ++i) {
