@@ -276,6 +276,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
   // cyclic ER step measured slower (0.357 -> 0.413 ms).
   constexpr bool PF = MODE == M_SPEC || MODE == M_LANCZOS;
   float icur[PF ? E : 1];
+  C mv[PF ? E : 1];  // the mask's values, kept for the conjugate multiply
   for (int m = 0; m < a.K; ++m) {
     const C* mk = a.masks + (size_t)m * N;
     const size_t mbase = (prow * a.K + m) * (size_t)N;
@@ -291,7 +292,6 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       if constexpr (PF) {
         // the mask's values, then this mask's intensities: the wait for the
         // mask leaves the intensity loads in flight under the forward transform
-        C mv[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) mv[i] = gload(mk + E0(i));
         __builtin_amdgcn_sched_barrier(0);
@@ -420,7 +420,10 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], gload(mk + E0(i))), inv_n);
       } else {
 #pragma unroll
-        for (int i = 0; i < E; ++i) g[i] = g[i] + cmulc(x[i], gload(mk + E0(i)));
+        for (int i = 0; i < E; ++i) {
+          if constexpr (PF) g[i] = g[i] + cmulc(x[i], mv[i]);
+          else g[i] = g[i] + cmulc(x[i], gload(mk + E0(i)));
+        }
       }
     }
   }
