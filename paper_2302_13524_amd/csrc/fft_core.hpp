@@ -469,12 +469,19 @@ __device__ __forceinline__ void fwd_from(cx<T>* x, Xbuf<T>& xb, int ltid, const 
   }
 }
 
-template <class PL, int P, typename T>
-__device__ __forceinline__ void inv_from(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
+// before_last() runs after the last exchange, before the last radix pass
+// (loads issued there are in flight during that pass).
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <class PL, int P, typename T, class H>
+__device__ __forceinline__ void inv_from(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw, const H& before_last) {
   if constexpr (P >= 0) {
     if constexpr (P < PL::NP - 1) exchange<PL, P + 1, P, T>(x, xb, ltid);
+    if constexpr (P == 0) before_last();
     inv_pass<PL, P, T>(x, ltid, tw_of<PL, P, T>(tw));
-    inv_from<PL, P - 1, T>(x, xb, ltid, tw);
+    inv_from<PL, P - 1, T>(x, xb, ltid, tw, before_last);
   }
 }
 
@@ -482,9 +489,10 @@ template <class PL, typename T>
 __device__ __forceinline__ void fft_forward(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
   fwd_from<PL, 0, T>(x, xb, ltid, tw);
 }
-template <class PL, typename T>
-__device__ __forceinline__ void fft_inverse(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw) {
-  inv_from<PL, PL::NP - 1, T>(x, xb, ltid, tw);
+template <class PL, typename T, class H = NoHook>
+__device__ __forceinline__ void fft_inverse(cx<T>* x, Xbuf<T>& xb, int ltid, const Tw<T>& tw,
+                                            const H& before_last = H{}) {
+  inv_from<PL, PL::NP - 1, T>(x, xb, ltid, tw, before_last);
 }
 
 // Digit reversal of one axis: slot index s (digits high to low as laid out by

@@ -276,7 +276,12 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
   // cyclic ER step measured slower (0.357 -> 0.413 ms).
   constexpr bool PF = MODE == M_SPEC || MODE == M_LANCZOS;
   float icur[PF ? E : 1];
-  C mv[PF ? E : 1];  // the mask's values, kept for the conjugate multiply
+  C mv[PF ? E : 1];     // the mask's values, kept for the conjugate multiply
+  C mnext[PF ? E : 1];  // the next mask's values, loaded during the last inverse pass
+  if constexpr (PF) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) mnext[i] = gload(a.masks + E0(i));
+  }
   for (int m = 0; m < a.K; ++m) {
     const C* mk = a.masks + (size_t)m * N;
     const size_t mbase = (prow * a.K + m) * (size_t)N;
@@ -293,7 +298,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         // the mask's values, then this mask's intensities: the wait for the
         // mask leaves the intensity loads in flight under the forward transform
 #pragma unroll
-        for (int i = 0; i < E; ++i) mv[i] = gload(mk + E0(i));
+        for (int i = 0; i < E; ++i) mv[i] = mnext[i];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < E; ++i) icur[i] = load_I<IT>(a.I, mbase + KL(i));
@@ -412,7 +417,18 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
           }
         }
       }
-      fft_inverse<PL, T>(x, xb, ltid, tw);
+      if constexpr (PF) {
+        const C* mk1 = mk + N;
+        const bool more = m + 1 < a.K;
+        fft_inverse<PL, T>(x, xb, ltid, tw, [&]() {
+          if (more) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) mnext[i] = gload(mk1 + E0(i));
+          }
+        });
+      } else {
+        fft_inverse<PL, T>(x, xb, ltid, tw);
+      }
       if constexpr (MODE == M_ERC) {
         // this mask's projection replaces the row before the next mask
         const float inv_n = 1.f / (float)N;
