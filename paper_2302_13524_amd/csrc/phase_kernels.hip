@@ -1595,7 +1595,7 @@ namespace tmk {
 int phase_cgemm_slices(const PhaseDims& d) {
   const int tiles = ((d.P + CG_P - 1) / CG_P) * ((d.Nd + CG_N - 1) / CG_N);
   int gs = 1;
-  while (tiles * gs * 2 <= 1024 && (d.N + 2 * gs - 1) / (2 * gs) >= 256) gs *= 2;
+  while (tiles * gs * 2 <= 2048 && (d.N + 2 * gs - 1) / (2 * gs) >= 256) gs *= 2;
   return gs;
 }
 
