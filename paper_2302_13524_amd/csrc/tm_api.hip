@@ -59,6 +59,7 @@ struct tm_ctx {
     hipStream_t cap = nullptr;
   } pg;
   int32_t ph_iters = 0, ph_evals = 0;  // accepted iterations and evaluations of the last phase solve
+  int32_t ph_iters_req = -1;           // the iteration count that solve was asked for
 };
 
 constexpr int PHASE_GRAPH_ITERS = 10;  // phase L-BFGS iterations captured per graph replay
@@ -699,7 +700,11 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
     // at most 40 trials per accepted iteration, plus the replay that decides
     // the last trial and ends the solve; PHASE_GRAPH_ITERS of them per replay
     const long limit = ((long)po->iters * 40 + 2 + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
-    long launched = 0, batch = (po->iters + 8 + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
+    // first batch: enough replays for the evaluations the last solve of the same
+    // iteration count took (every graph iteration but the last evaluates one
+    // trial), else for one trial per iteration plus a margin
+    const long guess = (c->ph_evals > 0 && c->ph_iters_req == po->iters) ? (long)c->ph_evals : (long)po->iters + 8;
+    long launched = 0, batch = (guess + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
     while (!e && launched < limit) {
       long nb = std::min(batch, limit - launched);
       for (long i = 0; i < nb && !e; ++i) e = (int)hipGraphLaunch(gexec, s);
@@ -724,6 +729,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   double f = hb[3];
   c->ph_iters = (int32_t)hb[4];
   c->ph_evals = (int32_t)hb[5];
+  c->ph_iters_req = po->iters;
   HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (g_out) *g_out = f;
