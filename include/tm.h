@@ -250,7 +250,9 @@ typedef struct {
  *   g_out  host double* (may be NULL): final objective value.
  * Synchronous with respect to the host (the line search runs on the
  * device; the host reads its state between batches of iterations); work
- * is queued on `stream`. */
+ * is queued on `stream`. Errors: TM_EINVAL for bad sizes, optics or
+ * options, and for a pix entry outside the grid or shared by two rows
+ * (checked on the device, reported when the call returns, phi unchanged). */
 int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,
                             const tm_c32 *tm_est, const tm_c32 *theta, const float *I_d,
                             const tm_optics *optics, double *phi, const tm_phase_opts *opts,

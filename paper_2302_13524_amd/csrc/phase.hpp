@@ -34,6 +34,7 @@ struct PhaseWork {
   double* gval;   // [1] objective
   int32_t* inv;   // [nf1 nf2] row index of each field pixel, -1 outside the rows
   int* skip;      // [1] set to 1 when the L-BFGS solve has ended: evaluation kernels return at once
+  int* chk;       // [3] pixel check: problem bits (1 outside the grid, 2 repeated), smallest row of each
   double* Sp;     // band: [Nd][CH][16][16] complex, box spectrum partials per block of field rows
   double* V;      // band: [Nd][column blocks][16][16] complex, adjoint box spectrum partials
   double* Wn;     // band: [Nd][P] complex, conj(c_n) (A_n^H a_n r_n) at the pixels
@@ -83,7 +84,10 @@ int phase_lb_state_doubles(int m);
 // Device-controlled iterations (see phase_kernels.hip): init after the first
 // evaluation, then per iteration phase_lb_iter (decide on the pending trial,
 // new direction or halved step, trial point) and the evaluation at phit.
-int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream);
+int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, const int* chk, void* stream);
 int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip, void* stream);
+// phi (unless the pixel check failed) to phi_out, and rec[0..6] = f, accepted
+// iterations, evaluations, solve ended, pixel check bits, first rows (device).
+int phase_lb_finish(const PhaseLb& L, const PhaseWork& w, int P, double* phi_out, double* rec, void* stream);
 
 }  // namespace tmk

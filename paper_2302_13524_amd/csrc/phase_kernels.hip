@@ -175,13 +175,41 @@ __global__ void k_make_h(double* h, int nf1, int nf2, double lam, double ps, dou
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
 // inv[g] = p for g = pix[p], -1 elsewhere (pixels are distinct and in range)
-__global__ void k_invmap(int32_t* inv, const int32_t* pix, int P, int G) {
+// Pixel map and its validation on the device. inv[g] = -1, then the largest
+// row p with pix[p] == g; chk[0] |= 1 for an index outside the grid (chk[1] =
+// the smallest such row), |= 2 for a pixel that a later row also has
+// (chk[2] = the smallest such row). Any problem sets *skip, so that no
+// evaluation kernel runs on the map.
+__global__ void k_invmap(int32_t* inv, const int32_t* pix, int P, int G, int* chk) {
   int i = blockIdx.x * 256 + threadIdx.x;
   if (i < G) inv[i] = -1;
+  if (i == 0) {
+    chk[0] = 0;
+    chk[1] = P;
+    chk[2] = P;
+  }
 }
-__global__ void k_invmap2(int32_t* inv, const int32_t* pix, int P) {
+__global__ void k_invmap2(int32_t* inv, const int32_t* pix, int P, int G, int* chk, int* skip) {
   int p = blockIdx.x * 256 + threadIdx.x;
-  if (p < P) inv[pix[p]] = p;
+  if (p >= P) return;
+  const int g = pix[p];
+  if (g >= 0 && g < G) {
+    atomicMax(&inv[g], p);
+  } else {
+    atomicOr(&chk[0], 1);
+    atomicMin(&chk[1], p);
+    *skip = 1;
+  }
+}
+__global__ void k_invmap3(const int32_t* inv, const int32_t* pix, int P, int G, int* chk, int* skip) {
+  int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const int g = pix[p];
+  if (g >= 0 && g < G && inv[g] != p) {
+    atomicOr(&chk[0], 2);
+    atomicMin(&chk[2], p);
+    *skip = 1;
+  }
 }
 
 // ---- separable evaluation of the forward model and its adjoint
@@ -991,7 +1019,7 @@ size_t dpart_doubles(const PhaseDims& d) { return 4 * (((size_t)d.P + 255) / 256
 size_t phase_work_bytes(const PhaseDims& d) {
   size_t G = (size_t)d.nf1 * d.nf2;
   size_t dbl = (size_t)d.Nd * d.P * 2 + G * 2 + (size_t)d.Nd * G * 2 + (size_t)d.Nd * 2 * G * 2 +
-               gpart_doubles(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 1 + band_Sp_doubles(d) +
+               gpart_doubles(d) + (size_t)GATHER_SLICES * d.P * 2 + 8 + G + 2 + band_Sp_doubles(d) +
                (size_t)d.Nd * band_nxb_max(d) * BM * BM * 2 + (size_t)d.Nd * d.P * 2 + dpart_doubles(d);
   return dbl * sizeof(double) + 14 * 256;
 }
@@ -1048,7 +1076,8 @@ void phase_work_carve(void* base, const PhaseDims& d, PhaseWork* w) {
   w->w = take((size_t)GATHER_SLICES * d.P * 2);
   w->gval = take(8);
   w->inv = (int32_t*)take(G);
-  w->skip = (int*)take(1);
+  w->skip = (int*)take(2);
+  w->chk = w->skip + 1;
   w->Sp = take(band_Sp_doubles(d));
   w->V = take((size_t)d.Nd * band_nxb_max(d) * BM * BM * 2);
   w->Wn = take((size_t)d.Nd * d.P * 2);
@@ -1063,9 +1092,10 @@ int phase_setup(const PhaseDims& d, const PhaseOptics& o, const void* tm_est, co
   hipStream_t s = (hipStream_t)stream;
   int G = d.nf1 * d.nf2;
   k_make_h<<<(G + 255) / 256, 256, 0, s>>>(w.h, d.nf1, d.nf2, o.lambda, o.ps, o.NA, o.z);
-  k_invmap<<<(G + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G);
-  k_invmap2<<<(d.P + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P);
   k_set_int<<<1, 1, 0, s>>>(w.skip, 0);
+  k_invmap<<<(G + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G, w.chk);
+  k_invmap2<<<(d.P + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G, w.chk, w.skip);
+  k_invmap3<<<(d.P + 255) / 256, 256, 0, s>>>(w.inv, pix, d.P, G, w.chk, w.skip);
   return (int)hipGetLastError();
 }
 
@@ -1567,21 +1597,47 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
 }
 
 // start: clear the state, take f at the start point, allow the first direction
-__global__ void k_pinit(double* sc, int n, const double* gval, int* skip) {
+// (unless the pixel check failed)
+__global__ void k_pinit(double* sc, int n, const double* gval, int* skip, const int* chk) {
   for (int i = threadIdx.x; i < n; i += 64) sc[i] = 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     sc[4] = gval[0];
     sc[6] = 1.0;  // the start point
-    *skip = 0;
+    *skip = chk[0] != 0 ? 1 : 0;
+  }
+}
+
+// End of a batch of iterations: the current phi to the caller's buffer (unless
+// the pixel check failed) and one record for the host: f, accepted
+// iterations, evaluations, the solve-ended flag and the pixel check.
+__global__ void __launch_bounds__(256) k_pfinish(const double* sc, const int* skip, const int* chk,
+                                                 const double* phi_src, double* phi_dst, int P, double* rec) {
+  const bool ok = chk[0] == 0;
+  const int stride = gridDim.x * 256;
+  for (int i = blockIdx.x * 256 + threadIdx.x; ok && i < P; i += stride) phi_dst[i] = phi_src[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    rec[0] = sc[4];
+    rec[1] = sc[5];
+    rec[2] = sc[6];
+    rec[3] = (double)*skip;
+    rec[4] = (double)chk[0];
+    rec[5] = (double)chk[1];
+    rec[6] = (double)chk[2];
   }
 }
 }  // namespace
 
 int phase_lb_state_doubles(int m) { return SC_HIST + 2 * m * m; }
 
-int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, void* stream) {
-  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, phase_lb_state_doubles(m), gval, skip);
+int phase_lb_finish(const PhaseLb& L, const PhaseWork& w, int P, double* phi_out, double* rec, void* stream) {
+  const int blocks = std::max(1, std::min(64, (P + 255) / 256));
+  k_pfinish<<<blocks, 256, 0, (hipStream_t)stream>>>(L.sc, w.skip, w.chk, L.phi, phi_out, P, rec);
+  return (int)hipGetLastError();
+}
+
+int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, const int* chk, void* stream) {
+  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, phase_lb_state_doubles(m), gval, skip, chk);
   return (int)hipGetLastError();
 }
 int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip, void* stream) {

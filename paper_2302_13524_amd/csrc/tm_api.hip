@@ -553,8 +553,11 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
 
 }  // extern "C"
 
+// Argument checks of the phase entry points. host_pix: also read pix back and
+// check its range and distinctness here (tm_phase_offset_correct checks it on
+// the device instead, so that it does not wait for earlier work on the stream).
 static int phase_check(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
-                       const tm_c32* theta, const float* I_d, const tm_optics* o) {
+                       const tm_c32* theta, const float* I_d, const tm_optics* o, bool host_pix = true) {
   if (!dd || !o) return fail(c, TM_EINVAL, "dims/optics pointer is NULL");
   if (dd->P < 1 || dd->N < 1 || dd->Nd < 1) return fail(c, TM_EINVAL, "P=%d N=%d Nd=%d must be >= 1", dd->P, dd->N, dd->Nd);
   if (!is_pow2(dd->nf1) || !is_pow2(dd->nf2) || dd->nf1 < 2 || dd->nf2 < 2 || dd->nf1 > 256 || dd->nf2 > 256)
@@ -563,6 +566,7 @@ static int phase_check(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
   if (!pix || !tm_est || !theta || !I_d) return fail(c, TM_EINVAL, "null pointer argument");
   if (!(o->lambda > 0) || !(o->ps_field > 0) || !(o->NA > 0) || !(o->NA < 1) || !std::isfinite(o->z))
     return fail(c, TM_EINVAL, "optics: lambda, ps_field > 0, 0 < NA < 1, finite z");
+  if (!host_pix) return TM_OK;
   // pixel indices address the field grid: check range and distinctness on the host
   std::vector<int32_t> hp(dd->P);
   if (hipMemcpy(hp.data(), pix, dd->P * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
@@ -625,7 +629,7 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
                                        const tm_optics* o, double* phi, const tm_phase_opts* po,
                                        double* g_out, void* stream) {
   if (!c) return TM_EINVAL;
-  int r = phase_check(c, dd, pix, tm_est, theta, I_d, o);
+  int r = phase_check(c, dd, pix, tm_est, theta, I_d, o, false);
   if (r) return r;
   if (!phi || !po) return fail(c, TM_EINVAL, "null pointer argument");
   if (po->iters < 0 || po->m < 1 || po->m > 16) return fail(c, TM_EINVAL, "iters >= 0 and 1 <= m <= 16");
@@ -637,7 +641,8 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   if ((r = phase_prepare(c, dd, pix, tm_est, theta, o, pd, w, stream))) return r;
   const int P = dd->P, m = po->m;
   size_t vb = ((P * sizeof(double) + 255) / 256) * 256;
-  char* lb = (char*)ws_get(c, WS_PH_BASE + 1, vb * (6 + 2 * m) + tmk::phase_lb_state_doubles(m) * sizeof(double));
+  char* lb = (char*)ws_get(c, WS_PH_BASE + 1,
+                          vb * (6 + 2 * m) + (tmk::phase_lb_state_doubles(m) + 8) * sizeof(double));
   if (!lb) return fail(c, TM_ENOMEM, "phase L-BFGS workspace");
   tmk::PhaseLb L;
   L.phi = (double*)(lb);
@@ -650,12 +655,21 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   L.Y = (double*)(lb + (6 + m) * vb);
   L.sc = (double*)(lb + (6 + 2 * m) * vb);
   L.dpart = w.dpart;
+  double* rec = L.sc + tmk::phase_lb_state_doubles(m);  // 8 doubles: the end-of-batch record
   HIPCHK(c, hipMemcpyAsync(L.phi, phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   int e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
-  if (!e) e = tmk::phase_lb_init(L, P, m, w.gval, w.skip, stream);
+  if (!e) e = tmk::phase_lb_init(L, P, m, w.gval, w.skip, w.chk, stream);
   if (e) return hipfail(c, e, "phase start");
   if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
   double* hb = c->pinned;
+  // end of a batch: phi out (device-side, skipped after a failed pixel check)
+  // and the record (f, iterations, evaluations, ended, pixel check) read back
+  auto finish = [&]() -> int {
+    int fe = tmk::phase_lb_finish(L, w, P, phi, rec, stream);
+    hipError_t fh = fe ? hipSuccess : hipMemcpyAsync(hb, rec, 7 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (!fe && fh == hipSuccess) fh = hipStreamSynchronize(s);
+    return fe ? fe : (int)fh;
+  };
   // One iteration (decision on the pending trial, new direction or changed
   // step, trial point, objective and gradient there) is a captured graph; the line-search
   // control lives in device state, so replays are queued back-to-back and
@@ -696,7 +710,6 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
       else phase_graph_release(c);
     }
     hipGraphExec_t gexec = c->pg.exec;
-    hipError_t he = hipSuccess;
     // at most 40 trials per accepted iteration, plus the replay that decides
     // the last trial and ends the solve; PHASE_GRAPH_ITERS of them per replay
     const long limit = ((long)po->iters * 40 + 2 + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
@@ -709,29 +722,27 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
       long nb = std::min(batch, limit - launched);
       for (long i = 0; i < nb && !e; ++i) e = (int)hipGraphLaunch(gexec, s);
       launched += nb;
-      if (e) break;
-      int* hs = (int*)(hb + 2);
-      he = hipMemcpyAsync(hb, L.sc + 5, sizeof(double), hipMemcpyDeviceToHost, s);
-      if (he == hipSuccess) he = hipMemcpyAsync(hs, w.skip, sizeof(int), hipMemcpyDeviceToHost, s);
-      if (he == hipSuccess) he = hipStreamSynchronize(s);
-      if (he != hipSuccess) {
-        e = (int)he;
-        break;
-      }
-      if (*hs != 0 || hb[0] >= (double)po->iters) break;
+      if (!e) e = finish();
+      if (e || hb[3] != 0.0) break;  // error, or the solve has ended
       batch = 2;
     }
     if (e) return hipfail(c, e, "phase iterations");
+  } else {
+    e = finish();
+    if (e) return hipfail(c, e, "phase result");
   }
-  // f, accepted iterations and evaluations (state entries 4, 5, 6)
-  HIPCHK(c, hipMemcpyAsync(hb + 3, L.sc + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  double f = hb[3];
-  c->ph_iters = (int32_t)hb[4];
-  c->ph_evals = (int32_t)hb[5];
+  if (hb[4] != 0.0) {  // pixel check failed: phi is left as it was
+    const bool range = ((int)hb[4] & 1) != 0;
+    const int32_t bp = (int32_t)(range ? hb[5] : hb[6]);
+    int32_t gv = -1;
+    if (bp >= 0 && bp < P) HIPCHK(c, hipMemcpy(&gv, pix + bp, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (range) return fail(c, TM_EINVAL, "pix[%d]=%d outside the field grid", bp, gv);
+    return fail(c, TM_EINVAL, "pix[%d]=%d repeats a pixel", bp, gv);
+  }
+  const double f = hb[0];
+  c->ph_iters = (int32_t)hb[1];
+  c->ph_evals = (int32_t)hb[2];
   c->ph_iters_req = po->iters;
-  HIPCHK(c, hipMemcpyAsync(phi, L.phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(c, hipStreamSynchronize(s));
   if (g_out) *g_out = f;
   return TM_OK;
 }

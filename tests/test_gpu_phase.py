@@ -131,6 +131,44 @@ def test_rejects_bad_pixels(ctx):
                               (LAM, PS, 0.6, 20.0), torch.zeros(P, dtype=torch.float64, device=dev()), nf, nf)
 
 
+def test_solve_rejects_bad_pixels_on_the_device(ctx):
+    # tm_phase_offset_correct checks pix on the device: an index outside the
+    # grid or a pixel two rows share is reported when the call returns, phi is
+    # left as it was, and the next solve on the same context is unaffected
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix, tm_est, theta, Id, _, _ = build(nf, P, N, Nd, 0.6, 0.6, cfg=958)
+    args = (c64(tm_est), c64(theta), f32(Id), (LAM, PS, 0.6, 20 * LAM))
+
+    def solve(c, p, iters=20):
+        phi = torch.full((P,), 0.25, dtype=torch.float64, device=dev())
+        g = tm.tm_phase_offset_correct(c, torch.from_numpy(p.astype(np.int32)).to(dev()), *args, phi, nf, nf,
+                                       iters=iters, m=5)
+        return phi.cpu().numpy(), g
+
+    good, g_good = solve(ctx, pix)
+    for bad, msg in (((7, nf * nf + 5), r"pix\[7\]=\d+ outside the field grid"), ((9, -1), r"pix\[9\]=-1 outside"),
+                     ((11, None), r"pix\[5\]=\d+ repeats a pixel")):
+        q = pix.astype(np.int64).copy()
+        if bad[1] is None:
+            q[bad[0]] = q[5]
+        else:
+            q[bad[0]] = bad[1]
+        for iters in (0, 20):
+            phi = torch.full((P,), 0.25, dtype=torch.float64, device=dev())
+            with pytest.raises(tm.TMError, match=msg):
+                tm.tm_phase_offset_correct(ctx, torch.from_numpy(q.astype(np.int32)).to(dev()), *args, phi, nf, nf,
+                                           iters=iters, m=5)
+            assert torch.all(phi == 0.25)
+    again, g_again = solve(ctx, pix)
+    assert np.array_equal(good, again) and g_good == g_again
+    c2 = tm.Context(0)
+    try:
+        fresh, g_fresh = solve(c2, pix)
+    finally:
+        c2.close()
+    assert np.array_equal(good, fresh) and g_good == g_fresh
+
+
 @pytest.mark.parametrize("nf1,nf2,P,N,Nd", [(8, 16, 50, 24, 3), (32, 4, 60, 16, 2), (2, 2, 3, 8, 2),
                                             (256, 4, 40, 8, 2), (4, 256, 40, 8, 2)])
 def test_rectangular_grids_images_objective(ctx, nf1, nf2, P, N, Nd):
