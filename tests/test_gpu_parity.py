@@ -222,6 +222,32 @@ def test_lanczos_start(ctx, k):
     assert np.allclose(np.linalg.norm(got, axis=1) ** 2, Ir.reshape(P, -1).sum(axis=1) / (4 * n1 * n2), rtol=1e-5)
 
 
+def test_lanczos_start_unaligned_buffers(ctx):
+    # rows and intensities that start 8 and 4 bytes past a 16-byte boundary take
+    # the scalar-load forms of the row sums, the Ritz combination and the
+    # rescaling; the result matches the aligned call and the oracle
+    n1, n2, P, K, k = 32, 32, 21, 4, 3
+    N = n1 * n2
+    masks, T, I, _ = problem(n1, n2, K, P, cfg=915, noise=1e4)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(915, 3))
+    m, v, Ir = rounded(masks, v0, I)
+    opts = tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=k, spectral_tau=2.5)
+    ta = c64(v0)
+    tm.tm_retrieve(ctx, c64(masks), f32(I), ta, n1, n2, opts)
+    tbuf = torch.zeros(P * N + 1, dtype=torch.complex64, device=dev())
+    tu = tbuf[1:].view(P, N)
+    tu.copy_(c64(v0))
+    ibuf = torch.zeros(I.size + 1, dtype=torch.float32, device=dev())
+    iu = ibuf[1:].view(I.shape)
+    iu.copy_(f32(I))
+    assert tu.data_ptr() % 16 == 8 and iu.data_ptr() % 16 == 4
+    tm.tm_retrieve(ctx, c64(masks), iu, tu, n1, n2, opts)
+    got = tu.cpu().numpy().astype(np.complex128)
+    assert relerr(got, ta.cpu().numpy().astype(np.complex128)) < 1e-6
+    ref = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), Ir, v, k, tau=2.5)
+    assert relerr(got, ref) < OPTOL * k
+
+
 def test_lanczos_start_full_size_rows_and_errors(ctx):
     # the benchmark's 2286 x 8192 launch, 16 steps, sampled rows against the oracle
     n1, n2, K, P = 128, 64, 4, 2286

@@ -131,6 +131,28 @@ def test_rejects_bad_pixels(ctx):
                               (LAM, PS, 0.6, 20.0), torch.zeros(P, dtype=torch.float64, device=dev()), nf, nf)
 
 
+def test_zero_iterations_and_repeated_counts(ctx):
+    # iters = 0 evaluates the start only (phi unchanged, g = g(phi0)); repeated
+    # solves of the same size report the same counts (the replay batch is sized
+    # from the previous solve's evaluations)
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix, tm_est, theta, Id, _, mdl = build(nf, P, N, Nd, 0.6, 0.6, cfg=959, noise=1e4)
+    args = (torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta), f32(Id),
+            (LAM, PS, 0.6, 20 * LAM))
+    phi0 = np.random.default_rng(959).random(P)
+    phi = torch.from_numpy(phi0.copy()).to(dev())
+    g = tm.tm_phase_offset_correct(ctx, *args, phi, nf, nf, iters=0, m=5)
+    assert tm.tm_phase_last_counts(ctx) == (0, 1)
+    assert np.array_equal(phi.cpu().numpy(), phi0)
+    assert abs(g - mdl.objective(Id.astype(np.float64), phi0)[0]) <= 1e-9 * g
+    counts = []
+    for _ in range(3):
+        phi = torch.zeros(P, dtype=torch.float64, device=dev())
+        tm.tm_phase_offset_correct(ctx, *args, phi, nf, nf, iters=15, m=5)
+        counts.append(tm.tm_phase_last_counts(ctx))
+    assert counts[0] == counts[1] == counts[2] and counts[0][0] == 15 and counts[0][1] >= 16
+
+
 def test_solve_rejects_bad_pixels_on_the_device(ctx):
     # tm_phase_offset_correct checks pix on the device: an index outside the
     # grid or a pixel two rows share is reported when the call returns, phi is
