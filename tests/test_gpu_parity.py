@@ -363,6 +363,12 @@ def test_empty_and_errors(ctx):
     big = torch.zeros((1, 16384), dtype=torch.complex64, device=dev())
     with pytest.raises(tm.TMError, match="N=16384"):
         tm.tm_forward(ctx, torch.zeros((1, 16384), dtype=torch.complex64, device=dev()), big, 128, 128)
+    # no rows: every start and solver returns at once
+    Ie = torch.empty((0, 4, 64), dtype=torch.float32, device=dev())
+    for method, start in (("er_cyclic", "lanczos"), ("er", "spectral"), ("er", "backprop"), ("lbfgs", "given")):
+        te = torch.empty((0, 64), dtype=torch.complex64, device=dev())
+        tm.tm_retrieve(ctx, c64(masks), Ie, te, 8, 8, tm.retrieve_opts(method, iters=2, start=start))
+        assert te.shape == (0, 64)
 
 
 def test_full_size_sampled_rows(ctx):
