@@ -269,11 +269,14 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
     inv_mean = (m > 0.f) ? 1.f / m : 1.f;
   }
 
-  // The spectral and Lanczos steps issue each mask's intensity loads right
-  // after its mask loads, so that they are in flight during the forward
-  // transform (Lanczos step 0.394 -> 0.380 ms at 2286 x 8192). The ER and
-  // gradient steps load them after the transform: issued early there, the
-  // cyclic ER step measured slower (0.357 -> 0.413 ms).
+  // Global-load latency in the spectral and Lanczos steps: the next mask's
+  // values are loaded during the last radix pass of the inverse transform (the
+  // first mask's before the loop) and kept for the conjugate multiply, and each
+  // mask's intensity loads are issued before its forward transform, so that
+  // they are in flight during it (Lanczos step 0.394 -> 0.360 ms at
+  // 2286 x 8192). The ER and gradient steps load the mask twice and the
+  // intensities after the transform: the same changes measured slower there
+  // (cyclic ER 0.357 -> 0.376 and 0.413 ms).
   constexpr bool PF = MODE == M_SPEC || MODE == M_LANCZOS;
   float icur[PF ? E : 1];
   C mv[PF ? E : 1];     // the mask's values, kept for the conjugate multiply
@@ -295,8 +298,9 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       }
     } else {
       if constexpr (PF) {
-        // the mask's values, then this mask's intensities: the wait for the
-        // mask leaves the intensity loads in flight under the forward transform
+        // the intensity loads go out after the (earlier) mask loads, so the
+        // wait for the mask values leaves them in flight under the forward
+        // transform; the scheduling barriers keep that order
 #pragma unroll
         for (int i = 0; i < E; ++i) mv[i] = mnext[i];
         __builtin_amdgcn_sched_barrier(0);
