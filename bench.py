@@ -9,19 +9,20 @@ z = 20 wavelengths for the phase-offset step. All inputs are seeded and
 synthetic (the paper's measured data are not available).
 
 A step is one pass of the whole path over the batch: truncated spectral
-start (heavy-ball power iteration), Nesterov-accelerated error-reduction
-iterations up to the count at which the mean per-row fidelity first reaches
-0.99, the FP64 acceptance residual, and the per-row phase-offset correction
-from the defocus images, run for the iteration count at which the offsets
-have converged (both counts found by untimed instrumented runs).
-value = P / step time.
+start (Lanczos steps on the weighted operator, Ritz vector), cyclic
+error-reduction sweeps up to the count at which the mean per-row fidelity
+first reaches 0.99, the FP64 acceptance residual, and the per-row
+phase-offset correction from the defocus images, run for the iteration count
+at which the offsets have converged (both counts found by untimed
+instrumented runs). value = P / step time. --start and --solver select the
+heavy-ball start and the averaged (Nesterov) error reduction instead.
 
 Also printed in the same JSON line: the roofline of the dominant kernel
-(the fused spectral-step or error-reduction kernel, whichever takes more of
-the timed region, event-timed live on the library's stream),
-the learned-start variant when a trained network is given, and the FP64
-oracle timed on the host's cores over a bounded sample of rows
-(`cpu_baseline`).
+(the fused Lanczos-step kernel, event-timed live on the library's stream)
+and of the solver's kernel, counter-measured HBM traffic while the kernel
+sources match the committed summary, the variants (L-BFGS, learned start,
+foci, dense comparator, preprocessing, uneven batch), and the FP64 oracle
+timed on the host's cores over a bounded sample of rows (`cpu_baseline`).
 """
 from __future__ import annotations
 
