@@ -260,7 +260,8 @@ int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_
 
 /* Counts of the last tm_phase_offset_correct call on ctx (0 before any):
  * accepted L-BFGS iterations and objective evaluations, the start point's
- * included. The line search (Sec. 2.3 leaves it open) tries a = 1 first,
+ * included. The first direction is -sqrt(P) g/||g|| (a = 1 moves the
+ * offsets by 1 rad RMS). The line search (Sec. 2.3 leaves it open) tries a = 1 first,
  * doubles a while the trial satisfies Armijo (c1 = 1e-4) but the slope there
  * is still below 0.9 times the slope at phi (at most 20 times) and takes the
  * best such trial; with no acceptable trial it halves a (at most 40 times).

@@ -24,10 +24,12 @@ Readings:
     of the doubled grid; the Nyquist bin is zero under the pupil whenever
     NA < lambda / (2 ps), so its split is moot.
   * L-BFGS over phi in R^P from phi = 0 (the commented-out Algorithm 2),
-    memory m, first direction -g/||g||, pairs with s^T y <= 0 skipped; line
-    search from a = 1 that doubles the step while a trial satisfies Armijo
-    (c = 1e-4) but not the curvature condition (c2 = 0.9) and takes the last
-    such trial, or halves it while no trial satisfies Armijo.
+    memory m, first direction -sqrt(P) g/||g|| (a = 1 changes the offsets by
+    1 rad RMS; the same after a reset of the history), pairs with s^T y <= 0
+    skipped; line search from a = 1 that doubles the step while a trial
+    satisfies Armijo (c = 1e-4) but not the curvature condition (c2 = 0.9)
+    and takes the last such trial, or halves it while no trial satisfies
+    Armijo.
   * phi is defined up to a constant; comparisons remove the circular mean
     of the difference.
 """
@@ -164,7 +166,7 @@ def lbfgs_phase(model: DefocusModel, Id: np.ndarray, phi0: np.ndarray, iters: in
             q *= np.dot(S[-1], Y[-1]) / np.dot(Y[-1], Y[-1])
         else:
             gn = np.linalg.norm(g)
-            q *= 1.0 / gn if gn > 0 else 0.0
+            q *= np.sqrt(x.size) / gn if gn > 0 else 0.0  # a = 1 moves the offsets by 1 rad RMS
         for (s_, y_), a in zip(zip(S, Y), reversed(al)):
             b = np.dot(y_, q) / np.dot(y_, s_)
             q += (a - b) * s_
@@ -175,7 +177,7 @@ def lbfgs_phase(model: DefocusModel, Id: np.ndarray, phi0: np.ndarray, iters: in
             gn = np.linalg.norm(g)
             if gn == 0:
                 break
-            d = -g / gn
+            d = -np.sqrt(x.size) * g / gn
             slope = float(np.dot(g, d))
         a = 1.0
         best = None

@@ -1207,7 +1207,8 @@ constexpr int SMAT = 2 * 16 * 16 + 2 * 16;
 // from a_j = s_j^T g (dots[j]), b_j = y_j^T g (dots[k+j]) and g^T g (dots[2k]).
 // Sets sc[1] = 0 (history dropped) when the product is not a descent
 // direction, and sc[2] = the slope g^T d. coef[1 + 2k] = 1 if the pairs are used.
-__device__ void dir_solve(int k, int head, int m, double* sc, const double* dots, double* coef, double* smat) {
+__device__ void dir_solve(int k, int head, int m, int P, double* sc, const double* dots, double* coef,
+                          double* smat) {
   double* R = smat;        // R[i][j] = s_i^T y_j (age order), row stride 16
   double* W = smat + 256;  // W[i][j] = y_i^T y_j
   double* u = smat + 512;
@@ -1244,8 +1245,8 @@ __device__ void dir_solve(int k, int head, int m, double* sc, const double* dots
     }
     if (!(slope < 0.0)) keep = false;  // not a descent direction: drop the history
   }
-  if (!keep) {  // -g / ||g||
-    cg = gg > 0 ? -1.0 / sqrt(gg) : 0.0;
+  if (!keep) {  // -sqrt(P) g / ||g||: a step of 1 moves the offsets by 1 rad RMS
+    cg = gg > 0 ? -sqrt((double)P) / sqrt(gg) : 0.0;
     slope = cg * gg;
     sc[1] = 0;
   }
@@ -1301,8 +1302,8 @@ __device__ void dir_apply(PhaseLb& L, int P, int m, int k, int head, const doubl
   }
 }
 
-// First direction (no trial yet): -g / ||g|| over the stored pairs (none after
-// the start), then the trial point.
+// First direction (no trial yet): the L-BFGS product over the stored pairs,
+// which after the start are none, so -sqrt(P) g / ||g||; then the trial point.
 __device__ void first_direction(PhaseLb& L, int P, int m, double* red, double* sc, double* sh, double* smat) {
   const int head = (int)sc[0], k = (int)sc[1];
   for (int j = 0; j < k; ++j) {
@@ -1322,7 +1323,7 @@ __device__ void first_direction(PhaseLb& L, int P, int m, double* red, double* s
   double* dots = sh;
   double* coef = sh + MAXV;
   bsum_finish(2 * k + 1, red, dots);
-  if (threadIdx.x == 0) dir_solve(k, head, m, sc, dots, coef, smat);
+  if (threadIdx.x == 0) dir_solve(k, head, m, P, sc, dots, coef, smat);
   __syncthreads();
   dir_apply(L, P, m, k, head, coef);
 }
@@ -1448,7 +1449,7 @@ __device__ int accept(PhaseLb& L, int P, int m, int iters, double ftol, const do
         dots[k + keep] = sums[4 * keep + 3];
       }
       dots[2 * k] = sums[4 * keep + 4];
-      dir_solve(k, nh, m, sc, dots, coef, smat);
+      dir_solve(k, nh, m, P, sc, dots, coef, smat);
       kdir = k;
       hdir = nh;
       sc[3] = 1.0;

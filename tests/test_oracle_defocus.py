@@ -116,11 +116,12 @@ def test_noiseless_offsets_recovered():
     assert np.all(np.diff(hist) <= 0)
 
 
-def test_line_search_postconditions_and_expansion_pays():
-    # Every accepted step satisfies Armijo, checked on the objective evaluated
-    # afresh; a step that grew was followed by a trial that failed (or hit the
-    # doubling cap), and one that did not grow either met the curvature
-    # condition or came after a halving.
+def test_line_search_postconditions():
+    # The first direction is -sqrt(P) g/||g||. Replaying the first iteration's
+    # trials on the objective evaluated afresh: the accepted step satisfies
+    # Armijo; a step that grew stopped when a doubled trial was no better or the
+    # curvature condition held (or at the cap); a halved step is the first trial
+    # that satisfies Armijo.
     nf, P, N, Nd = 16, 40, 24, 12
     pix = tm_synth.nearest_pixels(nf, P)
     tm_true = tm_synth.speckle_tm(N, nf, 0.6, pix, tm_synth.rng(43, 1))
@@ -129,21 +130,30 @@ def test_line_search_postconditions_and_expansion_pays():
     theta = tm_synth.defocus_phases(Nd, N, tm_synth.rng(43, 4))
     mdl = df.DefocusModel(tm_est, theta, pix, nf, nf, LAM, PS, 0.6, 20 * LAM)
     Id = tm_synth.poisson_counts(mdl.images(phi_true), 1e4, tm_synth.rng(43, 6))
-    trace = []
-    phi, hist = df.lbfgs_phase(mdl, Id, np.zeros(P), 3, trace=trace)
-    # replay the first iteration independently: d = -g / ||g||
-    f0, g0 = mdl.objective(Id, np.zeros(P))
-    d = -g0 / np.linalg.norm(g0)
-    slope = g0 @ d
-    a_steps = [t[0] for t in trace]
-    assert a_steps[0] == 1.0
-    # the first iteration doubles from a = 1 (a unit step is tiny against ||phi|| ~ sqrt(P))
-    assert a_steps[1] == 2.0
-    i = 0
-    while trace[i + 1][0] == 2 * trace[i][0] and trace[i][3]:
-        i += 1
-    a_acc = trace[i][0] if trace[i][3] else trace[i - 1][0]
-    f_acc, g_acc = mdl.objective(Id, a_acc * d)
-    assert f_acc <= f0 + 1e-4 * a_acc * slope
-    assert np.isclose(hist[1], f_acc, rtol=1e-13)
-    assert (not trace[i][3]) or g_acc @ d >= 0.9 * slope or i == 20
+    for scale in (1.0, 1e-3, 30.0):  # first-step sizes that need no change, doublings, halvings
+        phi0 = np.zeros(P)
+        trace = []
+        m2 = df.DefocusModel(tm_est, theta, pix, nf, nf, LAM, PS, 0.6, 20 * LAM)
+        m2.objective = (lambda Idv, x, s=scale: (lambda fg: (fg[0], fg[1] * s))(mdl.objective(Idv, phi0 + x * s)))
+        _, hist = df.lbfgs_phase(m2, Id, np.zeros(P), 1, trace=trace)
+        f0, g0 = m2.objective(Id, np.zeros(P))
+        d = -np.sqrt(P) * g0 / np.linalg.norm(g0)
+        slope = g0 @ d
+        steps = [t[0] for t in trace]
+        assert steps[0] == 1.0
+        grew = len(steps) > 1 and steps[1] == 2.0
+        if grew:
+            kept = [t for t in trace if t[3]]
+            a_acc = kept[-1][0]
+            f_acc, g_acc = m2.objective(Id, a_acc * d)
+            last = trace[-1]
+            assert (not last[3]) or g_acc @ d >= 0.9 * slope or len(steps) == 21
+        else:
+            a_acc = steps[-1]
+            assert all(s2 == 0.5 * s1 for s1, s2 in zip(steps, steps[1:]))
+            f_acc, _ = m2.objective(Id, a_acc * d)
+            for a_rej in steps[:-1]:
+                assert m2.objective(Id, a_rej * d)[0] > f0 + 1e-4 * a_rej * slope
+        assert f_acc <= f0 + 1e-4 * a_acc * slope
+        assert np.isclose(hist[1], f_acc, rtol=1e-13)
+        print("scale", scale, "trials", steps)
