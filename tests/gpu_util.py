@@ -41,3 +41,24 @@ def rounded(masks, T, I):
     """FP32-rounded copies (what the GPU receives), as FP64 arrays."""
     return (masks.astype(np.complex64).astype(np.complex128), T.astype(np.complex64).astype(np.complex128),
             I.astype(np.float32).astype(np.float64))
+
+
+def oracle_intensities(masks, T, n1, n2, chunk=128):
+    """|A t|^2 of every row in FP64 by the oracle's FFT form, from the
+    FP32-rounded masks and rows the GPU receives (row chunks bound the memory)."""
+    m = np.asarray(masks).astype(np.complex64).astype(np.complex128)
+    op = ops.FFTOp(m, n1, n2)
+    T = np.asarray(T)
+    out = np.empty((T.shape[0], m.shape[0], n1 * n2), dtype=np.float64)
+    for i0 in range(0, T.shape[0], chunk):
+        out[i0:i0 + chunk] = ops.intensities(op, T[i0:i0 + chunk].astype(np.complex64).astype(np.complex128))
+    return out
+
+
+def device_intensities(I, bf16=False):
+    """FP64 intensities as the GPU's input (FP32, or BF16 rounded to nearest
+    even on the host), and the same values back as FP64 for the oracle."""
+    t = torch.from_numpy(np.ascontiguousarray(I, dtype=np.float32))
+    if bf16:
+        t = t.to(torch.bfloat16)
+    return t.to(dev()), t.to(torch.float64).numpy()

@@ -12,7 +12,7 @@ import tm_synth
 from oracle import operators as ops
 from oracle import retrieval as rt
 
-from gpu_util import c64, dev, f32, relerr
+from gpu_util import c64, dev, device_intensities, f32, oracle_intensities, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -30,11 +30,12 @@ def make_problems(ctx, shapes, cfg=970, bf16=True):
     out = []
     for i, (n1, n2, P) in enumerate(shapes):
         N = n1 * n2
-        masks = c64(tm_synth.mask_phases(4, N, tm_synth.rng(cfg + i, 0)))
-        T = c64(tm_synth.tm_iid(P, N, tm_synth.rng(cfg + i, 1)))
-        I = tm.tm_forward(ctx, masks, T, n1, n2, intensity=True, bf16=bf16)
+        mh = tm_synth.mask_phases(4, N, tm_synth.rng(cfg + i, 0))
+        Th = tm_synth.tm_iid(P, N, tm_synth.rng(cfg + i, 1))
+        masks, T = c64(mh), c64(Th)
+        I, Iv = device_intensities(oracle_intensities(mh, Th, n1, n2), bf16)
         seed = c64(tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(cfg + i, 3)))
-        out.append({"n1": n1, "n2": n2, "masks": masks, "I": I, "t": seed.clone(), "seed": seed, "T": T,
+        out.append({"n1": n1, "n2": n2, "masks": masks, "I": I, "Iv": Iv, "t": seed.clone(), "seed": seed, "T": T,
                     "stats": torch.empty((P, tm.ROW_STATS_BYTES), dtype=torch.uint8, device=dev())})
     return out
 
@@ -81,9 +82,8 @@ def test_batch_rows_match_oracle(ctx):
     b.run()
     torch.cuda.synchronize()
     for p in probs:
-        I = p["I"].float().cpu().numpy().astype(np.float64)
         m = p["masks"].cpu().numpy().astype(np.complex128)
-        ref = rt.er_step(ops.FFTOp(m, p["n1"], p["n2"]), I, p["seed"].cpu().numpy().astype(np.complex128))
+        ref = rt.er_step(ops.FFTOp(m, p["n1"], p["n2"]), p["Iv"], p["seed"].cpu().numpy().astype(np.complex128))
         assert relerr(p["t"].cpu().numpy(), ref) < 1e-5
     b.close()
 

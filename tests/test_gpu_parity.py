@@ -10,7 +10,7 @@ import tm_synth
 from oracle import operators as ops
 from oracle import retrieval as rt
 
-from gpu_util import c64, dev, f32, problem, relerr, rounded
+from gpu_util import c64, dev, device_intensities, f32, oracle_intensities, problem, relerr, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -191,12 +191,12 @@ def test_er_cyclic_bf16_and_full_size_rows(ctx):
     mk = c64(masks)
     m = masks.astype(np.complex64).astype(np.complex128)
     rows = np.unique(np.concatenate([np.sort(g.choice(P, 5, replace=False)), [0, P - 1]]))
+    I64 = oracle_intensities(masks, T, n1, n2)
     for bf in (False, True):
-        I = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True, bf16=bf)
+        I, Iv = device_intensities(I64, bf)  # the same rounded values on both sides
         tt = c64(T2)
         tm.tm_retrieve(ctx, mk, I, tt, n1, n2, tm.retrieve_opts("er_cyclic", iters=2, bf16=bf))
-        Ig = I.cpu()[torch.from_numpy(rows)].to(torch.float64).numpy()  # BF16 values are exact in FP64
-        ref = rt.er_cyclic(m, n1, n2, Ig, T2[rows].astype(np.complex128), 2)
+        ref = rt.er_cyclic(m, n1, n2, Iv[rows], T2[rows].astype(np.complex128), 2)
         assert relerr(tt.cpu().numpy()[rows], ref) < 2 * OPTOL, bf
 
 
@@ -257,14 +257,13 @@ def test_lanczos_start_full_size_rows_and_errors(ctx):
     T = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
     v0 = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
     mk = c64(masks)
-    I = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True)
+    I, Iv = device_intensities(oracle_intensities(masks, T, n1, n2))
     tt = c64(v0)
     tm.tm_retrieve(ctx, mk, I, tt, n1, n2, tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=16,
                                                              spectral_tau=2.5))
     rows = np.unique(np.concatenate([np.sort(g.choice(P, 4, replace=False)), [0, P - 1]]))
     m = masks.astype(np.complex64).astype(np.complex128)
-    ref = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), I.cpu().numpy()[rows].astype(np.float64),
-                              v0[rows].astype(np.complex128), 16, tau=2.5)
+    ref = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), Iv[rows], v0[rows].astype(np.complex128), 16, tau=2.5)
     got = tt.cpu().numpy()[rows].astype(np.complex128)
     print("full-size lanczos 1-fid", 1 - _fid(got, ref).min())
     assert 1 - _fid(got, ref).min() < 1e-4
@@ -382,20 +381,23 @@ def test_full_size_sampled_rows(ctx):
     T = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
     T2 = (T + 0.5 * (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N)))).astype(np.complex64)
     mk = c64(masks)
-    I = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True)
+    # the forward pass of the full launch against the oracle on the sampled rows
+    rows = np.sort(g.choice(P, 6, replace=False))
+    rows = np.unique(np.concatenate([rows, [0, P - 1]]))
+    m = masks.astype(np.complex64).astype(np.complex128)
+    op = ops.FFTOp(m, n1, n2)
+    Iref = ops.intensities(op, T[rows].astype(np.complex128))
+    Igpu = tm.tm_forward(ctx, mk, c64(T), n1, n2, intensity=True).cpu().numpy()[rows].astype(np.float64)
+    assert relerr(Igpu, Iref) < 2 * OPTOL
+    # the iterations from the oracle's intensities (FP32-rounded on both sides)
+    I, Iv = device_intensities(oracle_intensities(masks, T, n1, n2))
     grad, f = tm.tm_gradient(ctx, mk, I, c64(T2), n1, n2)
     t_er = c64(T2)
     tm.tm_retrieve(ctx, mk, I, t_er, n1, n2, tm.retrieve_opts("er", iters=1))
     t_sp = c64(T2)
     tm.tm_retrieve(ctx, mk, I, t_sp, n1, n2, tm.retrieve_opts("er", iters=0, start="spectral", spectral_iters=1,
                                                                spectral_momentum=0.0))
-    rows = np.sort(g.choice(P, 6, replace=False))
-    rows = np.unique(np.concatenate([rows, [0, P - 1]]))
-    m = masks.astype(np.complex64).astype(np.complex128)
-    op = ops.FFTOp(m, n1, n2)
-    Iref = ops.intensities(op, T[rows].astype(np.complex128))
-    Ig = I.cpu().numpy()[rows].astype(np.float64)
-    assert relerr(Ig, Iref) < 2 * OPTOL
+    Ig = Iv[rows]
     t2 = T2[rows].astype(np.complex128)
     _, gref, _ = rt.intensity_grad(op, Ig, t2)
     assert relerr(grad.cpu().numpy()[rows], gref) < OPTOL
