@@ -64,17 +64,19 @@ def test_uint16_stacks_bit_exact(ctx, n, H, W, radius):
 
 
 def test_float_stack(ctx):
-    # float32 images: energies agree to rounding; the mask computed from the
-    # device energies equals the oracle's mask of those same energies
+    # float32 images: energies agree to rounding; the mask of the oracle's
+    # energies, computed on the device, equals the oracle's mask of them, and
+    # the rows gathered for it equal the oracle's
     g = tm_synth.rng(970, 0)
     stack = (tm_synth.camera_stack(300, 64, 64, 25.0, g).astype(np.float32) * 0.37).astype(np.float32)
     st = f32(stack)
     E = tm.tm_pre_energy(ctx, st)
     Eo = pp.energy(stack)
     assert np.max(np.abs(E.cpu().numpy() - Eo)) <= 1e-12 * np.max(Eo)
-    pix = tm.tm_pre_fiber_mask(ctx, E, 0.999)
-    assert np.array_equal(pix.cpu().numpy(), pp.fiber_mask(E.cpu().numpy(), 0.999))
-    assert np.array_equal(tm.tm_pre_gather(ctx, st, pix).cpu().numpy(), pp.gather_rows(stack, pix.cpu().numpy()))
+    po = pp.fiber_mask(Eo, 0.999)
+    pix = tm.tm_pre_fiber_mask(ctx, torch.from_numpy(Eo).to(dev()), 0.999)
+    assert np.array_equal(pix.cpu().numpy(), po)
+    assert np.array_equal(tm.tm_pre_gather(ctx, st, pix).cpu().numpy(), pp.gather_rows(stack, po))
 
 
 def test_fiber_disk_is_the_mask(ctx):
