@@ -476,7 +476,7 @@ def main():
     if not args.no_preprocess and not args.small:
         out["preprocess"] = preprocess_variant(ctx, args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver)
+        out["cpu_baseline"] = cpu_baseline(args, masks, n1, n2, v0, T, sp, n_er, beta, P, solver, cfg_id)
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -748,17 +748,23 @@ def batch_variant(ctx, args):
             "spectral_tau": args.batch_spectral_tau, "dtype_I": "bf16", "variants": tuned, "per_tm": per_tm}
 
 
-def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver="er"):
+def cpu_baseline(args, masks, n1, n2, v0, T, sp, n_er, beta, P, solver="er", cfg_id=3):
     """The FP64 oracle (FFT form of A) on a bounded sample of rows: the same
-    spectral start and error-reduction iterations, timed on the host."""
+    spectral start and error-reduction iterations, timed on the host. The
+    sampled rows' intensities come from the oracle's own forward model with
+    Poisson noise at the workload's level (seeded), outside the timed region."""
+    import tm_synth
     from oracle import operators as ops
     from oracle import retrieval as rt
 
     op = ops.FFTOp(masks, n1, n2)
     K, N = masks.shape
 
-    def run(rows):
-        I = I_np[rows].astype(np.float64)
+    def intens(rows, k):
+        Ic = ops.intensities(op, T[rows].astype(np.complex128))
+        return tm_synth.poisson_counts(Ic, 1e4, tm_synth.rng(cfg_id, 7 + k))
+
+    def run(rows, I):
         if args.start == "lanczos":
             t = rt.spectral_lanczos(op, I, v0[rows].astype(np.complex128), sp, tau=args.spectral_tau)
         else:
@@ -770,17 +776,20 @@ def cpu_baseline(args, masks, n1, n2, I_np, v0, T, sp, n_er, beta, P, solver="er
 
     g = np.random.default_rng(123)
     probe = np.sort(g.choice(P, 4, replace=False))
+    Ip = intens(probe, 0)
     a = time.perf_counter()
-    run(probe)
+    run(probe, Ip)
     dt = time.perf_counter() - a
     nrows = args.cpu_rows or int(max(4, min(P, 4 * 15.0 / max(dt, 1e-3))))
     rows = np.sort(g.choice(P, nrows, replace=False))
+    Ir = intens(rows, 1)
     a = time.perf_counter()
-    t = run(rows)
+    t = run(rows, Ir)
     dt = time.perf_counter() - a
     fid = rt.fidelity(t, T[rows].astype(np.complex128))
     return {"value": round(nrows / dt, 3), "unit": "rows/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nrows} of {P} rows, FP64 numpy FFT form of A, {sp} spectral + {n_er} "
+            "sample": f"{nrows} of {P} rows (intensities by the oracle's forward model, Poisson 1e4), FP64 numpy "
+                      f"FFT form of A, {sp} spectral + {n_er} "
                       + (f"ER iterations (Nesterov factor {beta}) " if solver == "er" else "cyclic ER sweeps ")
                       + f"({dt:.1f}s)", "mean_fidelity": round(float(fid.mean()), 6),
             "host_cpus": len(os.sched_getaffinity(0))}
