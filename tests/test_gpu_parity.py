@@ -273,6 +273,34 @@ def test_lanczos_start_full_size_rows_and_errors(ctx):
                            tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=bad))
 
 
+def test_default_path_full_size_sampled_rows(ctx):
+    # the benchmark's retrieval as launched there: 2286 x 8192, K = 4, Poisson
+    # intensities, 17 Lanczos steps (truncation 3.0) then 5 cyclic sweeps;
+    # sampled rows against the oracle's same pipeline
+    n1, n2, K, P = 128, 64, 4, 2286
+    N = n1 * n2
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(921, 1)).astype(np.complex64)
+    I64 = tm_synth.poisson_counts(oracle_intensities(masks, T, n1, n2), 1e4, tm_synth.rng(921, 2))
+    I, Iv = device_intensities(I64)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(921, 3)).astype(np.complex64)
+    tt = c64(v0)
+    raw = tm.tm_retrieve(ctx, c64(masks), I, tt, n1, n2,
+                         tm.retrieve_opts("er_cyclic", iters=5, start="lanczos", spectral_iters=17, spectral_tau=3.0))
+    g = np.random.default_rng(921)
+    rows = np.unique(np.concatenate([np.sort(g.choice(P, 4, replace=False)), [0, P - 1]]))
+    m = masks.astype(np.complex64).astype(np.complex128)
+    t0 = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), Iv[rows], v0[rows].astype(np.complex128), 17, tau=3.0)
+    ref = rt.er_cyclic(m, n1, n2, Iv[rows], t0, 5)
+    got = tt.cpu().numpy()[rows].astype(np.complex128)
+    print("default path 1-fid vs oracle", 1 - _fid(got, ref).min(), "fidelity to truth",
+          rt.fidelity(got, T[rows].astype(np.complex128)).min())
+    assert 1 - _fid(got, ref).min() < 1e-6  # measured 3e-11: the sweeps contract the start's FP32 drift
+    st = tm.decode_stats(raw)
+    assert np.all(st.iters.numpy() == 5)
+    assert np.all(np.isfinite(st.rho.numpy()))
+
+
 def test_backprop_start(ctx):
     n1, n2, P = 64, 32, 9
     masks, T, I, _ = problem(n1, n2, 4, P, cfg=908, noise=1e4)
