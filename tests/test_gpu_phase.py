@@ -117,6 +117,23 @@ def test_iterations_follow_the_oracle(ctx, iters):
     assert tm.tm_phase_last_counts(ctx) == (iters, 1 + len(trace))
 
 
+def test_full_size_iterations_follow_the_oracle(ctx):
+    # the benchmark's phase solve (2286 pixels of a 64 x 64 field, 8192 modes,
+    # 50 defocus images, NA 0.22, memory 1) for its first iterations
+    nf, P, N, Nd, NA = 64, 2286, 8192, 50, 0.22
+    pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, NA, 0.22, cfg=960, noise=1e4)
+    for iters in (1, 4):
+        trace = []
+        phi_o, hist = df.lbfgs_phase(mdl, Id.astype(np.float64), np.zeros(P), iters, m=1, trace=trace)
+        phi = torch.zeros(P, dtype=torch.float64, device=dev())
+        g = tm.tm_phase_offset_correct(ctx, torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est),
+                                       c64(theta), f32(Id), (LAM, PS, NA, 20 * LAM), phi, nf, nf, iters=iters, m=1)
+        print(f"full-size phase iters {iters}: trials {[t[0] for t in trace]}", flush=True)
+        assert np.max(np.abs(phi.cpu().numpy() - phi_o)) <= 1e-9 * max(1.0, np.max(np.abs(phi_o)))
+        assert abs(g - hist[-1]) <= 1e-11 * hist[-1]
+        assert tm.tm_phase_last_counts(ctx) == (iters, 1 + len(trace))
+
+
 def test_rejects_bad_pixels(ctx):
     nf, P, N, Nd = 16, 40, 24, 12
     pix, tm_est, theta, Id, _, _ = build(nf, P, N, Nd, 0.6, 0.6, cfg=952)
