@@ -36,30 +36,35 @@ int ilog2(int v) {
 }
 
 // ---- c[n][p] = sum_k theta[n][k] tm[p][k]: FP32 complex inputs, exact FP64
-// products, FP64 sums. Workgroup tile 256 p x 16 n, 4 x 4 outputs per thread,
+// products, FP64 sums. Workgroup tile 256 p x NPT NGR n: NGR groups of
+// 256 / NGR threads along n, each thread NGR p x NPT n outputs (4 x 4 in
+// 256 x 16 tiles, 2 x 5 in 256 x 10 tiles, which fit 50 images without padding),
 // K in steps of 32 through LDS (FP32), split over GS chunks of K whose partial
-// sums a second kernel adds in a fixed order.
-constexpr int CG_P = 256, CG_N = 16, CG_K = 32;
+// sums a second kernel adds in a fixed order. Each output's sum runs over k in
+// the same order whatever the tile.
+constexpr int CG_P = 256, CG_K = 32;
 
 // Tile loads: every thread issues all of its global loads of a K step before
 // the first LDS store (pairs of complex values per load when N is even).
-template <bool PAIRS>
+template <int NPT, int NGR, bool PAIRS>
 __global__ void __launch_bounds__(256) k_cgemm_part(const float2* __restrict__ theta, const float2* __restrict__ tm,
                                                     double* __restrict__ part, int Nd, int P, int N, int kchunk) {
+  constexpr int CN = NPT * NGR, PG = 256 / NGR;
   __shared__ float2 st[CG_K][CG_P + 4];   // tm tile, [k][p]
-  __shared__ float2 sth[CG_K][CG_N];      // theta tile, [k][n]
-  const int p0 = blockIdx.x * CG_P, n0 = blockIdx.y * CG_N, sl = blockIdx.z;
+  __shared__ float2 sth[CG_K][CN];        // theta tile, [k][n]
+  const int p0 = blockIdx.x * CG_P, n0 = blockIdx.y * CN, sl = blockIdx.z;
   const int k0 = sl * kchunk, k1 = min(N, k0 + kchunk);
   const int tid = threadIdx.x;
-  const int pg = tid % 64, ng = tid / 64;  // outputs p0 + 4 pg + i, n0 + 4 ng + j
-  double ar[4][4], ai[4][4];
+  const int pg = tid % PG, ng = tid / PG;  // outputs p0 + NGR pg + i, n0 + NPT ng + j
+  double ar[NGR][NPT], ai[NGR][NPT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NGR; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
-  constexpr int W = PAIRS ? 2 : 1;                 // complex values per load
-  constexpr int LT = CG_P * CG_K / (256 * W);      // tm loads per thread per K step
-  constexpr int LH = CG_N * CG_K / (256 * W);      // theta loads per thread per K step (1 or 2)
+    for (int j = 0; j < NPT; ++j) ar[i][j] = ai[i][j] = 0.0;
+  constexpr int W = PAIRS ? 2 : 1;                        // complex values per load
+  constexpr int LT = CG_P * CG_K / (256 * W);             // tm loads per thread per K step
+  constexpr int NH = CN * CG_K / W;                       // theta loads per K step
+  constexpr int LH = (NH + 255) / 256;                    // per thread
   for (int kb = k0; kb < k1; kb += CG_K) {
     float2 vt[LT][W], vh[LH][W];
 #pragma unroll
@@ -79,13 +84,14 @@ __global__ void __launch_bounds__(256) k_cgemm_part(const float2* __restrict__ t
     for (int q = 0; q < LH; ++q) {
       const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
       const int n = n0 + r, k = kb + kk;
+      const bool ok = e < NH && n < Nd && k < k1;
       if constexpr (PAIRS) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (n < Nd && k < k1) v = *(const float4*)(theta + (size_t)n * N + k);
+        if (ok) v = *(const float4*)(theta + (size_t)n * N + k);
         vh[q][0] = make_float2(v.x, v.y);
         vh[q][W - 1] = make_float2(v.z, v.w);
       } else {
-        vh[q][0] = (n < Nd && k < k1) ? theta[(size_t)n * N + k] : make_float2(0.f, 0.f);
+        vh[q][0] = ok ? theta[(size_t)n * N + k] : make_float2(0.f, 0.f);
       }
     }
 #pragma unroll
@@ -97,29 +103,31 @@ __global__ void __launch_bounds__(256) k_cgemm_part(const float2* __restrict__ t
 #pragma unroll
     for (int q = 0; q < LH; ++q) {
       const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
+      if (e < NH) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) sth[kk + w][r] = vh[q][w];
+        for (int w = 0; w < W; ++w) sth[kk + w][r] = vh[q][w];
+      }
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < CG_K; ++kk) {
-      double br[4], bi[4], cr[4], ci[4];
+      double br[NGR], bi[NGR], cr[NPT], ci[NPT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float2 v = st[kk][4 * pg + i];
+      for (int i = 0; i < NGR; ++i) {
+        const float2 v = st[kk][NGR * pg + i];
         br[i] = (double)v.x;
         bi[i] = (double)v.y;
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float2 v = sth[kk][4 * ng + j];
+      for (int j = 0; j < NPT; ++j) {
+        const float2 v = sth[kk][NPT * ng + j];
         cr[j] = (double)v.x;
         ci[j] = (double)v.y;
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NGR; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NPT; ++j) {
           ar[i][j] = __builtin_fma(cr[j], br[i], ar[i][j]);
           ar[i][j] = __builtin_fma(-ci[j], bi[i], ar[i][j]);
           ai[i][j] = __builtin_fma(cr[j], bi[i], ai[i][j]);
@@ -129,11 +137,11 @@ __global__ void __launch_bounds__(256) k_cgemm_part(const float2* __restrict__ t
     __syncthreads();
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int n = n0 + 4 * ng + j;
+  for (int j = 0; j < NPT; ++j) {
+    const int n = n0 + NPT * ng + j;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int p = p0 + 4 * pg + i;
+    for (int i = 0; i < NGR; ++i) {
+      const int p = p0 + NGR * pg + i;
       if (n < Nd && p < P) {
         const size_t o = (((size_t)sl * Nd + n) * P + p) * 2;
         part[o] = ar[i][j];
@@ -1649,8 +1657,15 @@ int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double
 }  // namespace tmk
 
 namespace tmk {
+// n rows per tile: 10 when that pads the images less than 16 does by at least 15 %
+static int cgemm_rows(int Nd) {
+  const int p16 = (Nd + 15) / 16 * 16, p10 = (Nd + 9) / 10 * 10;
+  return (p10 * 100 <= p16 * 85) ? 10 : 16;
+}
+
 int phase_cgemm_slices(const PhaseDims& d) {
-  const int tiles = ((d.P + CG_P - 1) / CG_P) * ((d.Nd + CG_N - 1) / CG_N);
+  const int CN = cgemm_rows(d.Nd);
+  const int tiles = ((d.P + CG_P - 1) / CG_P) * ((d.Nd + CN - 1) / CN);
   int gs = 1;
   while (tiles * gs * 2 <= 2048 && (d.N + 2 * gs - 1) / (2 * gs) >= 256) gs *= 2;
   return gs;
@@ -1661,11 +1676,17 @@ int phase_cgemm(const PhaseDims& d, const void* theta, const void* tm, double* p
   const int gs = phase_cgemm_slices(d);
   int kchunk = (d.N + gs - 1) / gs;
   kchunk = ((kchunk + CG_K - 1) / CG_K) * CG_K;
-  dim3 g((d.P + CG_P - 1) / CG_P, (d.Nd + CG_N - 1) / CG_N, gs);
-  if (d.N % 2 == 0)
-    k_cgemm_part<true><<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm, part, d.Nd, d.P, d.N, kchunk);
-  else
-    k_cgemm_part<false><<<g, 256, 0, s>>>((const float2*)theta, (const float2*)tm, part, d.Nd, d.P, d.N, kchunk);
+  const int CN = cgemm_rows(d.Nd);
+  dim3 g((d.P + CG_P - 1) / CG_P, (d.Nd + CN - 1) / CN, gs);
+  const float2* th = (const float2*)theta;
+  const float2* tmv = (const float2*)tm;
+  if (CN == 10) {
+    if (d.N % 2 == 0) k_cgemm_part<5, 2, true><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
+    else k_cgemm_part<5, 2, false><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
+  } else {
+    if (d.N % 2 == 0) k_cgemm_part<4, 4, true><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
+    else k_cgemm_part<4, 4, false><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
+  }
   const int64_t n = (int64_t)d.Nd * d.P * 2;
   k_cgemm_sum<<<(int)((n + 255) / 256), 256, 0, s>>>(part, c, n, gs);
   return (int)hipGetLastError();
