@@ -310,18 +310,22 @@ def exact_step(c1: float, c2: float, c3: float, c4: float) -> float:
 
 def lbfgs_core(eval_fg, line_min, t0: np.ndarray, iters: int, m: int = 5,
                gamma: float | None = None, callback=None, h0: float = 1.0,
-               reset_on_zero: bool = False):
+               reset_on_zero: bool = False, events: dict | None = None):
     """Generic per-row L-BFGS loop of Algorithm 1: `eval_fg(t) -> (f, g, aux)`
     gives the error and packed gradient, `line_min(t, d, aux) -> alpha` the
     step along d. With an empty history the direction is -h0 g (also after a
     non-descent reset); reset_on_zero drops a row's history when its step is
-    0. Returns (t, per-iteration f history [iters+1, P])."""
+    0. Returns (t, per-iteration f history [iters+1, P]). If `events` is a
+    dict it receives per-row counts of what happened to the history:
+    "skipped" (nonzero steps whose pair had s^T y <= 0), "evicted" (pairs
+    dropped because m were stored), "zero_steps" and "resets" (non-descent)."""
     t = np.array(t0, dtype=np.complex128)
     P = t.shape[0]
     S = [[] for _ in range(P)]
     Y = [[] for _ in range(P)]
     f, g, aux = eval_fg(t)
     hist = [f.copy()]
+    ev = {k: np.zeros(P, dtype=np.int64) for k in ("skipped", "evicted", "zero_steps", "resets")}
     for _ in range(iters):
         d = two_loop(g, S, Y, gamma, h0)
         slope = rdot(g, d)
@@ -330,7 +334,9 @@ def lbfgs_core(eval_fg, line_min, t0: np.ndarray, iters: int, m: int = 5,
             for p in np.nonzero(bad)[0]:
                 S[p], Y[p] = [], []
             d[bad] = -h0 * g[bad]
+            ev["resets"] += bad
         alpha = line_min(t, d, aux)
+        ev["zero_steps"] += alpha == 0
         if reset_on_zero:
             for p in np.nonzero(alpha == 0)[0]:
                 S[p], Y[p] = [], []
@@ -346,15 +352,20 @@ def lbfgs_core(eval_fg, line_min, t0: np.ndarray, iters: int, m: int = 5,
                 if len(S[p]) > m:
                     S[p].pop(0)
                     Y[p].pop(0)
+                    ev["evicted"][p] += 1
+            elif alpha[p] != 0:
+                ev["skipped"][p] += 1
         t, f, g, aux = t_new, f_new, g_new, aux_new
         hist.append(f.copy())
         if callback is not None:
             callback(t)
+    if events is not None:
+        events.update(ev)
     return t, np.array(hist)
 
 
 def lbfgs(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5,
-          gamma: float | None = None, callback=None):
+          gamma: float | None = None, callback=None, events: dict | None = None):
     """Algorithm 1 of the paper for every row at once: per iteration the
     error and gradient at the current t (Eq. optTMsmall2, Eq. derivative),
     an L-BFGS direction from the last m (s, y) pairs (two-loop recursion
@@ -370,7 +381,7 @@ def lbfgs(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5,
         c1, c2, c3, c4 = quartic_coeffs(I, y, z)
         return np.array([exact_step(c1[p], c2[p], c3[p], c4[p]) for p in range(t.shape[0])])
 
-    return lbfgs_core(eval_fg, line_min, t0, iters, m, gamma, callback)
+    return lbfgs_core(eval_fg, line_min, t0, iters, m, gamma, callback, events=events)
 
 
 def two_loop(g: np.ndarray, S, Y, gamma: float | None, h0: float = 1.0) -> np.ndarray:
@@ -400,7 +411,8 @@ def two_loop(g: np.ndarray, S, Y, gamma: float | None, h0: float = 1.0) -> np.nd
     return d
 
 
-def lbfgs_amplitude(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5, callback=None):
+def lbfgs_amplitude(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5, callback=None,
+                    events: dict | None = None):
     """L-BFGS on the amplitude cost (the Poisson-noise variant the Discussion
     names, same two-loop recursion as Algorithm 1): gradient amplitude_grad,
     line search amplitude_step over the trial steps, and with no stored pairs
@@ -416,4 +428,4 @@ def lbfgs_amplitude(op, I: np.ndarray, t0: np.ndarray, iters: int, m: int = 5, c
         return amplitude_step(I, y, op.forward(d))
 
     return lbfgs_core(eval_fg, line_min, t0, iters, m, None, callback, h0=1.0 / (2.0 * op.K * op.N),
-                      reset_on_zero=True)
+                      reset_on_zero=True, events=events)

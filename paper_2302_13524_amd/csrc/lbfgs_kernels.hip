@@ -36,6 +36,7 @@ struct LbArgs {
   float2* t;
   int first;         // no pending pair
   float h0;          // inverse-Hessian scale with no stored pairs
+  int unit_first;    // with no stored pairs use -g/||g|| instead of -h0 g
 };
 
 __device__ __forceinline__ void ts_add(float& s, float& c, float v) {
@@ -85,8 +86,9 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
   const size_t rb = (size_t)p * N;
   double* sc = a.sc + (size_t)p * LB_SCALARS(m);
   int head = (int)sc[0], count = (int)sc[1];
+  const int R = m + 1;  // ring slots: m stored pairs + the pending one
   double* sy = sc + 4;
-  double* yy = sc + 4 + m;
+  double* yy = sc + 4 + R;
   float2 q[EPT];
   bool act[EPT];
 #pragma unroll
@@ -95,10 +97,11 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
     act[i] = e < N;
     q[i] = act[i] ? a.g[rb + e] : make_float2(0.f, 0.f);
   }
-  // finalise the pending pair: y = g - g_prev, accept if s^T y > 0
+  // finalise the pending pair (slot head, outside the m stored pairs):
+  // y = g - g_prev, accept if s^T y > 0
   if (!a.first && sc[3] != 0.0) {
-    float2* Sh = a.S + ((size_t)p * m + head) * N;
-    float2* Yh = a.Y + ((size_t)p * m + head) * N;
+    float2* Sh = a.S + ((size_t)p * R + head) * N;
+    float2* Yh = a.Y + ((size_t)p * R + head) * N;
     float s2[2] = {0.f, 0.f}, c2[2] = {0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -116,16 +119,16 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
     if (o[0] > 0.0 && isfinite(o[0]) && o[1] > 0.0) {
       sy[head] = o[0];
       yy[head] = o[1];
-      head = (head + 1) % m;
+      head = (head + 1) % R;  // with count == m this drops the oldest pair
       count = count < m ? count + 1 : m;
     }
   }
   // two-loop recursion
   double al[16];
   for (int j = 0; j < count; ++j) {
-    int idx = (head - 1 - j + 2 * m) % m;
-    const float2* Si = a.S + ((size_t)p * m + idx) * N;
-    const float2* Yi = a.Y + ((size_t)p * m + idx) * N;
+    int idx = (head - 1 - j + 2 * R) % R;
+    const float2* Si = a.S + ((size_t)p * R + idx) * N;
+    const float2* Yi = a.Y + ((size_t)p * R + idx) * N;
     float s1[1] = {0.f}, c1[1] = {0.f};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -149,7 +152,7 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
   {
     float gam = a.h0;
     if (count > 0) {
-      int nw = (head - 1 + m) % m;
+      int nw = (head - 1 + R) % R;
       gam = (float)(sy[nw] / yy[nw]);
     }
 #pragma unroll
@@ -159,9 +162,9 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
     }
   }
   for (int j = count - 1; j >= 0; --j) {
-    int idx = (head - 1 - j + 2 * m) % m;
-    const float2* Si = a.S + ((size_t)p * m + idx) * N;
-    const float2* Yi = a.Y + ((size_t)p * m + idx) * N;
+    int idx = (head - 1 - j + 2 * R) % R;
+    const float2* Si = a.S + ((size_t)p * R + idx) * N;
+    const float2* Yi = a.Y + ((size_t)p * R + idx) * N;
     float s1[1] = {0.f}, c1[1] = {0.f};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -180,22 +183,29 @@ __global__ void __launch_bounds__(LWG) k_direction(LbArgs a) {
       q[i].y += cf * s.y;
     }
   }
-  // d = -q; if not a descent direction, drop the history and use -g
-  float s1[1] = {0.f}, c1[1] = {0.f};
+  // d = -q; if not a descent direction, drop the history and use the
+  // negative gradient. For the exact line search the scale of d does not
+  // change the new iterate (the step scales inversely), so with no stored
+  // pairs the gradient direction is normalised (unit_first): the quartic's
+  // coefficients grow as ||d||^4 and -g itself can overflow their FP32 sums.
+  float s1[2] = {0.f, 0.f}, c1[2] = {0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     if (!act[i]) continue;
     float2 g = a.g[rb + tid + i * LWG];
     ts_add(s1[0], c1[0], -(g.x * q[i].x + g.y * q[i].y));
+    ts_add(s1[1], c1[1], g.x * g.x + g.y * g.y);
   }
-  double slope[1];
-  block_sums<1>(s1, c1, red, slope);
-  bool reset = !(slope[0] < 0.0);
+  double sl[2];
+  block_sums<2>(s1, c1, red, sl);
+  bool reset = !(sl[0] < 0.0);
+  const bool plain = reset || count == 0;
+  const float gs = (a.unit_first && plain) ? (sl[1] > 0.0 ? (float)(1.0 / sqrt(sl[1])) : 0.f) : a.h0;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     if (!act[i]) continue;
     int e = tid + i * LWG;
-    float2 v = reset ? make_float2(a.h0 * a.g[rb + e].x, a.h0 * a.g[rb + e].y) : q[i];
+    float2 v = plain ? make_float2(gs * a.g[rb + e].x, gs * a.g[rb + e].y) : q[i];
     a.d[rb + e] = make_float2(-v.x, -v.y);
   }
   if (tid == 0) {
@@ -272,7 +282,7 @@ __global__ void __launch_bounds__(LWG) k_step(LbArgs a) {
   double al = exact_step(c1, c2, c3, c4);
   int head = (int)sc[0];
   float af = (float)al;
-  float2* Sh = a.S + ((size_t)p * m + head) * N;
+  float2* Sh = a.S + ((size_t)p * (m + 1) + head) * N;  // pending slot
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     int e = tid + i * LWG;
@@ -304,7 +314,7 @@ __global__ void __launch_bounds__(LWG) k_step_amp(LbArgs a) {
   const double al = (s[1 + jb] < s[0]) ? ldexp(1.0, jb - 3) : 0.0;
   int head = (int)sc[0];
   const float af = (float)al;
-  float2* Sh = a.S + ((size_t)p * m + head) * N;
+  float2* Sh = a.S + ((size_t)p * (m + 1) + head) * N;  // pending slot
   if (al > 0.0) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -385,6 +395,7 @@ int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters,
     la.t = (float2*)t;
     la.first = (it == 0);
     la.h0 = amplitude ? 1.f / (2.f * (float)base.K * (float)N) : 1.f;
+    la.unit_first = !amplitude;
     if ((e = dispatch(0, la, s))) return e;
     RowArgs ls = base;
     ls.tin = (const cx<float>*)t;

@@ -528,8 +528,8 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     b.g = ws_get(c, WS_LB_G, vec);
     b.gp = ws_get(c, WS_LB_GP, vec);
     b.d = ws_get(c, WS_LB_D, vec);
-    b.S = ws_get(c, WS_LB_S, vec * o->lbfgs_m);
-    b.Y = ws_get(c, WS_LB_Y, vec * o->lbfgs_m);
+    b.S = ws_get(c, WS_LB_S, vec * tmk::LB_SLOTS(o->lbfgs_m));
+    b.Y = ws_get(c, WS_LB_Y, vec * tmk::LB_SLOTS(o->lbfgs_m));
     b.sc = ws_get(c, WS_LB_SC, (size_t)d.P * tmk::LB_SCALARS(o->lbfgs_m) * sizeof(double));
     if (!b.g || !b.gp || !b.d || !b.S || !b.Y || !b.sc) return fail(c, TM_ENOMEM, "L-BFGS workspace");
     b.sums = sums;

@@ -1,0 +1,128 @@
+"""GPU parity of the paper's Algorithm 1 (Sec. 2.2: intensity cost, packed
+gradient of Eq. derivative, two-loop L-BFGS direction, exact quartic line
+search) and of the amplitude-cost variant of the Discussion, over several
+iterations, against the FP64 oracle on the same seeded inputs; and whole
+retrievals on the mid-size noisy speckle workload (32 x 32 modes, 512 rows,
+pupil 0.3 of Nyquist, Poisson mean 1e4), whose final fidelity to the truth
+must match the oracle's to 1e-4."""
+import numpy as np
+import pytest
+
+import paper_2302_13524_amd as tm
+import tm_synth
+from oracle import operators as ops
+from oracle import retrieval as rt
+
+from gpu_util import c64, device_intensities, f32, oracle_intensities, problem, relerr, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tm.Context(0)
+    yield c
+    c.close()
+
+
+def _start(cfg, n1, n2, P, scale):
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=cfg, noise=1e4)
+    t0 = T + scale * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(cfg, 3))
+    return masks, T, I, t0
+
+
+@pytest.mark.parametrize("iters", [2, 3, 5])
+def test_intensity_lbfgs_iterates(ctx, iters):
+    # Alg. 1 with memory 5, element by element after each iteration count
+    n1, n2, P = 32, 32, 13
+    masks, T, I, t0 = _start(930, n1, n2, P, 0.3)
+    m, t, Ir = rounded(masks, t0, I)
+    ref, hist = rt.lbfgs(ops.FFTOp(m, n1, n2), Ir, t, iters, m=5)
+    tt = c64(t0)
+    raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("lbfgs", iters=iters, lbfgs_m=5))
+    err = relerr(tt.cpu().numpy(), ref)
+    print(f"lbfgs iters={iters} relerr {err:.3e}", flush=True)
+    assert err < 1e-4 * iters
+    st = tm.decode_stats(raw)
+    assert relerr(st.f.numpy(), hist[-1]) < 1e-4 * iters
+    assert np.all(st.iters.numpy() == iters)
+
+
+@pytest.mark.parametrize("method", ["lbfgs", "lbfgs_amp"])
+def test_history_ring_wraps(ctx, method):
+    # memory 2 over 8 iterations: every row's history fills and then drops its
+    # oldest pair six times; the device ring must follow the oracle's list
+    n1, n2, P, iters, mem = 32, 32, 13, 8, 2
+    masks, T, I, t0 = _start(931, n1, n2, P, 0.5)
+    m, t, Ir = rounded(masks, t0, I)
+    op = ops.FFTOp(m, n1, n2)
+    ev = {}
+    solver = rt.lbfgs if method == "lbfgs" else rt.lbfgs_amplitude
+    ref, hist = solver(op, Ir, t, iters, m=mem, events=ev)
+    assert np.all(ev["evicted"] >= 1), ev  # the case exercises the wrap
+    tt = c64(t0)
+    tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts(method, iters=iters, lbfgs_m=mem))
+    got = tt.cpu().numpy().astype(np.complex128)
+    err = relerr(got, ref)
+    print(f"{method} m={mem} iters={iters} relerr {err:.3e} events {({k: int(v.sum()) for k, v in ev.items()})}",
+          flush=True)
+    assert err < 1e-3
+    # the same rows with a longer memory differ, so the wrap is what was compared
+    ref5, _ = solver(op, Ir, t, iters, m=5)
+    assert relerr(ref5, ref) > 10 * err
+
+
+def test_lbfgs_full_size_sampled_rows(ctx):
+    # the benchmark's 2286 x 8192 launch of Alg. 1 (memory 5, 3 iterations) on sampled rows
+    n1, n2, K, P = 128, 64, 4, 2286
+    N = n1 * n2
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
+    g = np.random.default_rng(932)
+    T = (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N))).astype(np.complex64)
+    T2 = (T + 0.3 * (g.standard_normal((P, N)) + 1j * g.standard_normal((P, N)))).astype(np.complex64)
+    rows = np.unique(np.concatenate([np.sort(g.choice(P, 4, replace=False)), [0, P - 1]]))
+    I64 = tm_synth.poisson_counts(oracle_intensities(masks, T, n1, n2), 1e4, tm_synth.rng(932, 2))
+    I, Iv = device_intensities(I64)
+    tt = c64(T2)
+    tm.tm_retrieve(ctx, c64(masks), I, tt, n1, n2, tm.retrieve_opts("lbfgs", iters=3, lbfgs_m=5))
+    m = masks.astype(np.complex64).astype(np.complex128)
+    ref, _ = rt.lbfgs(ops.FFTOp(m, n1, n2), Iv[rows], T2[rows].astype(np.complex128), 3, m=5)
+    err = relerr(tt.cpu().numpy()[rows], ref)
+    print(f"full-size lbfgs relerr {err:.3e}", flush=True)
+    assert err < 3e-4
+
+
+def _mid_workload():
+    # 32 x 32 modes, the 512 pixels of a 32 x 32 output grid nearest its centre,
+    # speckle columns low-passed by a pupil of radius 0.3 of Nyquist, K = 4,
+    # Poisson mean 1e4 (intensities from the oracle's forward model)
+    n1 = n2 = 32
+    N, P, K = 1024, 512, 4
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(2, 0))
+    T = tm_synth.speckle_tm(N, 32, 0.3, tm_synth.nearest_pixels(32, P), tm_synth.rng(2, 1)).astype(np.complex64)
+    I64 = tm_synth.poisson_counts(oracle_intensities(masks, T, n1, n2), 1e4, tm_synth.rng(2, 2))
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(2, 3)).astype(np.complex64)
+    return n1, n2, masks, T.astype(np.complex128), I64, v0
+
+
+@pytest.mark.parametrize("method,iters", [("er_cyclic", 8), ("lbfgs", 30), ("lbfgs_amp", 20)])
+def test_mid_workload_final_fidelity(ctx, method, iters):
+    n1, n2, masks, T, I64, v0 = _mid_workload()
+    I, Iv = device_intensities(I64)
+    m = masks.astype(np.complex64).astype(np.complex128)
+    op = ops.FFTOp(m, n1, n2)
+    s0 = rt.spectral_lanczos(op, Iv, v0.astype(np.complex128), 17, tau=3.0)
+    if method == "er_cyclic":
+        ref = rt.er_cyclic(m, n1, n2, Iv, s0, iters)
+    elif method == "lbfgs":
+        ref, _ = rt.lbfgs(op, Iv, s0, iters)
+    else:
+        ref, _ = rt.lbfgs_amplitude(op, Iv, s0, iters)
+    tt = c64(v0)
+    tm.tm_retrieve(ctx, c64(masks), I, tt, n1, n2,
+                   tm.retrieve_opts(method, iters=iters, start="lanczos", spectral_iters=17, spectral_tau=3.0))
+    got = tt.cpu().numpy().astype(np.complex128)
+    fg, fo = rt.fidelity(got, T), rt.fidelity(ref, T)
+    print(f"mid {method}: gpu mean fidelity {fg.mean():.6f}, oracle {fo.mean():.6f}, "
+          f"rows >= 0.99: {np.mean(fg >= 0.99):.4f} / {np.mean(fo >= 0.99):.4f}", flush=True)
+    assert abs(fg.mean() - fo.mean()) < 1e-4
