@@ -155,6 +155,48 @@ def _ptr(x) -> int | None:
     return x.data_ptr()
 
 
+_C64 = (torch.complex64,)
+_F32 = (torch.float32,)
+_I32 = (torch.int32,)
+_IDT = (torch.float32, torch.bfloat16, torch.int16, torch.uint16)
+
+
+def _chk(x, name: str, shape, dtypes, dev=None) -> None:
+    """Reject a tensor whose shape, dtype or device differs from what the C
+    entry point will assume for its pointer (the library sees only the
+    pointer and the sizes, so it cannot catch these itself)."""
+    if not isinstance(x, torch.Tensor):
+        raise TMError(f"{name}: expected a tensor, got {type(x).__name__}")
+    if tuple(x.shape) != tuple(int(v) for v in shape):
+        raise TMError(f"{name}: shape {tuple(x.shape)}, expected {tuple(int(v) for v in shape)}")
+    if x.dtype not in dtypes:
+        raise TMError(f"{name}: dtype {x.dtype}, expected one of {[str(d) for d in dtypes]}")
+    if dev is not None and x.device != dev:
+        raise TMError(f"{name}: on {x.device}, the other arguments are on {dev}")
+
+
+def _grid(n1, n2, N) -> None:
+    if int(n1) * int(n2) != int(N):
+        raise TMError(f"grid {n1} x {n2} does not hold N = {N} modes")
+
+
+def _masks(masks, n1, n2):
+    if not isinstance(masks, torch.Tensor) or masks.dim() != 2:
+        raise TMError("masks must be a [K, N] tensor")
+    K, N = masks.shape
+    _chk(masks, "masks", (K, N), _C64)
+    _grid(n1, n2, N)
+    return K, N
+
+
+def _rows(t, name: str, N: int, dev) -> int:
+    if not isinstance(t, torch.Tensor) or t.dim() != 2:
+        raise TMError(f"{name} must be a [P, N] tensor")
+    P = t.shape[0]
+    _chk(t, name, (P, N), _C64, dev)
+    return P
+
+
 def _stream(dev: torch.device) -> int:
     return torch.cuda.current_stream(dev).cuda_stream
 
@@ -202,13 +244,23 @@ def _dims(n1, n2, K, P) -> tm_dims:
     return tm_dims(int(n1), int(n2), int(K), int(P))
 
 
+def _rows_and_I(masks, I, t, n1, n2):
+    """Checks of masks [K, N], rows t [P, N] and intensities I [P, K, N]."""
+    K, N = _masks(masks, n1, n2)
+    P = _rows(t, "t", N, masks.device)
+    _chk(I, "I", (P, K, N), _IDT, masks.device)
+    return K, N, P
+
+
 def tm_forward(ctx: Context, masks, t, n1, n2, intensity: bool = False, bf16: bool = False, out=None):
     """y = A t ([P, K, N] complex64) or I = |A t|^2 ([P, K, N] float32 / bfloat16)."""
-    K, N = masks.shape
-    P = t.shape[0]
+    K, N = _masks(masks, n1, n2)
+    P = _rows(t, "t", N, masks.device)
+    dt = torch.complex64 if not intensity else (torch.bfloat16 if bf16 else torch.float32)
     if out is None:
-        dt = torch.complex64 if not intensity else (torch.bfloat16 if bf16 else torch.float32)
         out = torch.empty((P, K, N), dtype=dt, device=t.device)
+    else:
+        _chk(out, "out", (P, K, N), (dt,), t.device)
     rc = ctx.lib.tm_forward(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(t),
                             TM_INTENSITY if intensity else TM_FIELD, TM_BF16 if bf16 else TM_F32,
                             _ptr(out), _stream(t.device))
@@ -218,9 +270,15 @@ def tm_forward(ctx: Context, masks, t, n1, n2, intensity: bool = False, bf16: bo
 
 def tm_adjoint(ctx: Context, masks, y, n1, n2, out=None):
     """x = A^H y, y [P, K, N] complex64 -> [P, N] complex64."""
-    K, N = masks.shape
+    K, N = _masks(masks, n1, n2)
+    if not isinstance(y, torch.Tensor) or y.dim() != 3:
+        raise TMError("y must be a [P, K, N] tensor")
     P = y.shape[0]
-    out = torch.empty((P, N), dtype=torch.complex64, device=y.device) if out is None else out
+    _chk(y, "y", (P, K, N), _C64, masks.device)
+    if out is None:
+        out = torch.empty((P, N), dtype=torch.complex64, device=y.device)
+    else:
+        _chk(out, "out", (P, N), _C64, y.device)
     rc = ctx.lib.tm_adjoint(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(y), _ptr(out), _stream(y.device))
     ctx.check(rc, "tm_adjoint")
     return out
@@ -228,8 +286,7 @@ def tm_adjoint(ctx: Context, masks, y, n1, n2, out=None):
 
 def tm_gradient(ctx: Context, masks, I, t, n1, n2):
     """Packed gradient -4 A^H((A t)(I - |A t|^2)) and f per row."""
-    K, N = masks.shape
-    P = t.shape[0]
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
     g = torch.empty((P, N), dtype=torch.complex64, device=t.device)
     f = torch.empty((P,), dtype=torch.float32, device=t.device)
     rc = ctx.lib.tm_gradient(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t), _ptr(g),
@@ -240,8 +297,7 @@ def tm_gradient(ctx: Context, masks, I, t, n1, n2):
 
 def tm_amp_gradient(ctx: Context, masks, I, t, n1, n2):
     """Packed gradient -2 A^H((sqrt(I) - |A t|)(A t)/|A t|) and the amplitude cost per row."""
-    K, N = masks.shape
-    P = t.shape[0]
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
     g = torch.empty((P, N), dtype=torch.complex64, device=t.device)
     f = torch.empty((P,), dtype=torch.float32, device=t.device)
     rc = ctx.lib.tm_amp_gradient(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t), _ptr(g),
@@ -252,8 +308,7 @@ def tm_amp_gradient(ctx: Context, masks, I, t, n1, n2):
 
 def tm_residual_f64(ctx: Context, masks, I, t, n1, n2):
     """FP64 acceptance residual ||I - |A t|^2||^2 / ||I||^2 per row."""
-    K, N = masks.shape
-    P = t.shape[0]
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
     rho = torch.empty((P,), dtype=torch.float64, device=t.device)
     rc = ctx.lib.tm_residual_f64(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t),
                                  _ptr(rho), _stream(t.device))
@@ -294,10 +349,11 @@ def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", 
 def tm_retrieve(ctx: Context, masks, I, t, n1, n2, opts: tm_retrieve_opts | None = None, stats=True, **kw):
     """Retrieve every row in place in t ([P, N] complex64); returns the raw
     per-row stats tensor ([P, 24] uint8, see decode_stats) or None."""
-    K, N = masks.shape
-    P = t.shape[0]
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
     if opts is None:
         opts = retrieve_opts(bf16=(I.dtype != torch.float32), **kw)
+    if (opts.I_dtype == TM_F32) != (I.dtype == torch.float32):
+        raise TMError(f"I dtype {I.dtype} does not match opts.I_dtype {opts.I_dtype}")
     raw = torch.empty((P, ROW_STATS_BYTES), dtype=torch.uint8, device=t.device) if stats else None
     rc = ctx.lib.tm_retrieve(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _ptr(t), ctypes.byref(opts),
                              _ptr(raw), _stream(t.device))
@@ -309,10 +365,29 @@ def _ddims(P, N, Nd, nf1, nf2):
     return tm_defocus_dims(int(P), int(N), int(Nd), int(nf1), int(nf2))
 
 
+def _defocus_args(pix, tm_rows, theta, nf1, nf2, I_d=None, phi=None):
+    """Checks of the defocus-model arguments: tm_rows [P, N], pix [P] int32,
+    theta [Nd, N] complex64, I_d [Nd, 2 nf1, 2 nf2] float32, phi [P] float64."""
+    if not isinstance(tm_rows, torch.Tensor) or tm_rows.dim() != 2:
+        raise TMError("tm rows must be a [P, N] tensor")
+    P, N = tm_rows.shape
+    dev = tm_rows.device
+    _chk(tm_rows, "tm rows", (P, N), _C64)
+    _chk(pix, "pix", (P,), _I32, dev)
+    if not isinstance(theta, torch.Tensor) or theta.dim() != 2:
+        raise TMError("theta must be a [Nd, N] tensor")
+    Nd = theta.shape[0]
+    _chk(theta, "theta", (Nd, N), _C64, dev)
+    if I_d is not None:
+        _chk(I_d, "I_d", (Nd, 2 * int(nf1), 2 * int(nf2)), _F32, dev)
+    if phi is not None:
+        _chk(phi, "phi", (P,), (torch.float64,), dev)
+    return P, N, Nd
+
+
 def tm_phase_objective(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2):
     """g(phi) and dg/dphi of the defocus problem (FP64)."""
-    P, N = tm_est.shape
-    Nd = theta.shape[0]
+    P, N, Nd = _defocus_args(pix, tm_est, theta, nf1, nf2, I_d, phi)
     g = torch.empty((1,), dtype=torch.float64, device=tm_est.device)
     grad = torch.empty((P,), dtype=torch.float64, device=tm_est.device)
     dd = _ddims(P, N, Nd, nf1, nf2)
@@ -326,8 +401,7 @@ def tm_phase_objective(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, 
 def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2, iters=100, m=5, ftol=0.0):
     """Solve the per-row phase offsets in place in phi ([P] float64); returns g.
     Stops early after an accepted iteration that lowers g by at most ftol * g."""
-    P, N = tm_est.shape
-    Nd = theta.shape[0]
+    P, N, Nd = _defocus_args(pix, tm_est, theta, nf1, nf2, I_d, phi)
     dd = _ddims(P, N, Nd, nf1, nf2)
     op = tm_optics(*[float(v) for v in optics])
     po = tm_phase_opts(int(iters), int(m), float(ftol))
@@ -364,6 +438,9 @@ def tm_pre_energy(ctx: Context, stack):
 
 def tm_pre_fiber_mask(ctx: Context, energy, frac=0.999):
     """Ascending raster indices of the brightest-first pixel set holding frac of the total, int32 [P]."""
+    if not isinstance(energy, torch.Tensor) or energy.dim() != 1:
+        raise TMError("energy must be a 1-D tensor")
+    _chk(energy, "energy", energy.shape, (torch.float64,))
     npix = energy.numel()
     pix = torch.empty((npix,), dtype=torch.int32, device=energy.device)
     P = ctypes.c_int32(0)
@@ -375,7 +452,11 @@ def tm_pre_fiber_mask(ctx: Context, energy, frac=0.999):
 
 def tm_pre_gather(ctx: Context, stack, pix, bf16=False):
     """Per-pixel rows [P, n_img]: out[p][i] = stack[i][2y][2x] for pix[p] = y*(W/2) + x."""
+    _stack_dtype(stack)
     n, H, W = stack.shape
+    if not isinstance(pix, torch.Tensor) or pix.dim() != 1:
+        raise TMError("pix must be a 1-D tensor")
+    _chk(pix, "pix", pix.shape, _I32, stack.device)
     P = pix.numel()
     out = torch.empty((P, n), dtype=torch.bfloat16 if bf16 else torch.float32, device=stack.device)
     rc = ctx.lib.tm_pre_gather(ctx.h, _ptr(stack), _stack_dtype(stack), int(n), int(H), int(W),
@@ -387,7 +468,11 @@ def tm_pre_gather(ctx: Context, stack, pix, bf16=False):
 
 def tm_propagate_tm(ctx: Context, tm_rows, pix, g1, g2, optics):
     """TM at the plane optics[3] (= z) for every pixel of the g1 x g2 grid: [g1*g2, N] complex64."""
+    if not isinstance(tm_rows, torch.Tensor) or tm_rows.dim() != 2:
+        raise TMError("tm_rows must be a [P, N] tensor")
     P, N = tm_rows.shape
+    _chk(tm_rows, "tm_rows", (P, N), _C64)
+    _chk(pix, "pix", (P,), _I32, tm_rows.device)
     out = torch.empty((g1 * g2, N), dtype=torch.complex64, device=tm_rows.device)
     op = tm_optics(*[float(v) for v in optics])
     rc = ctx.lib.tm_propagate_tm(ctx.h, int(P), int(N), _ptr(tm_rows), _ptr(pix), int(g1), int(g2),
@@ -398,8 +483,12 @@ def tm_propagate_tm(ctx: Context, tm_rows, pix, g1, g2, optics):
 
 def tm_dense_gradient(ctx: Context, Q, I, t):
     """Gradient -4 Q^H((Q t)(I - |Q t|^2)) and f per row for a dense probing matrix Q [M, N]."""
+    if not isinstance(Q, torch.Tensor) or Q.dim() != 2:
+        raise TMError("Q must be an [M, N] tensor")
     M, N = Q.shape
-    P = t.shape[0]
+    _chk(Q, "Q", (M, N), _C64)
+    P = _rows(t, "t", N, Q.device)
+    _chk(I, "I", (P, M), _F32, Q.device)
     g = torch.empty((P, N), dtype=torch.complex64, device=t.device)
     f = torch.empty((P,), dtype=torch.float32, device=t.device)
     rc = ctx.lib.tm_dense_gradient(ctx.h, int(M), int(N), int(P), _ptr(Q), _ptr(I), _ptr(t), _ptr(g), _ptr(f),
@@ -411,8 +500,12 @@ def tm_dense_gradient(ctx: Context, Q, I, t):
 def tm_foci_power_ratio(ctx: Context, tm_true, tm_est, pix, g1, g2, w=3):
     """Power ratio [Pf] float32 and peak raster index [Pf] int32 of the conjugate-phase focus of every
     row of tm_est [Pf, N], with images over the rows of tm_true [G, N] at the pixels pix [G]."""
+    if not isinstance(tm_true, torch.Tensor) or tm_true.dim() != 2:
+        raise TMError("tm_true must be a [G, N] tensor")
     G, N = tm_true.shape
-    Pf = tm_est.shape[0]
+    _chk(tm_true, "tm_true", (G, N), _C64)
+    Pf = _rows(tm_est, "tm_est", N, tm_true.device)
+    _chk(pix, "pix", (G,), _I32, tm_true.device)
     pr = torch.empty((Pf,), dtype=torch.float32, device=tm_true.device)
     peak = torch.empty((Pf,), dtype=torch.int32, device=tm_true.device)
     rc = ctx.lib.tm_foci_power_ratio(ctx.h, int(Pf), int(G), int(N), _ptr(tm_true), _ptr(pix), _ptr(tm_est),
@@ -423,8 +516,7 @@ def tm_foci_power_ratio(ctx: Context, tm_true, tm_est, pix, g1, g2, w=3):
 
 def tm_defocus_forward(ctx: Context, pix, tm_rows, theta, optics, phi, nf1, nf2):
     """Defocus images |A_n e^{j phi}|^2, [Nd, 2nf1, 2nf2] float32."""
-    P, N = tm_rows.shape
-    Nd = theta.shape[0]
+    P, N, Nd = _defocus_args(pix, tm_rows, theta, nf1, nf2, None, phi)
     out = torch.empty((Nd, 2 * nf1, 2 * nf2), dtype=torch.float32, device=tm_rows.device)
     dd = _ddims(P, N, Nd, nf1, nf2)
     op = tm_optics(*[float(v) for v in optics])
@@ -475,9 +567,30 @@ class MLP:
                                            _stream(self.W[0].device)), "tm_mlp_sync_bf16")
 
 
+def _mlp_io(net: MLP, K: int, N: int) -> None:
+    if net.dims.n_in != K * N or net.dims.n_out != 2 * N:
+        raise TMError(f"network {net.dims.n_in} -> {net.dims.n_out} does not map K N = {K * N} "
+                      f"intensities to 2 N = {2 * N} values")
+
+
+def _mlp_batch(net: MLP, I, t, K: int, N: int) -> int:
+    if not isinstance(I, torch.Tensor) or I.dim() != 3:
+        raise TMError("I must be a [B, K, N] tensor")
+    B = I.shape[0]
+    dev = net.W[0].device
+    _chk(I, "I", (B, K, N), _F32, dev)
+    _chk(t, "t", (B, N), _C64, dev)
+    _mlp_io(net, K, N)
+    return B
+
+
 def tm_mlp_start(ctx: Context, net: MLP, I, K: int, N: int):
     """Learned start rows [P, N] complex64 from intensities [P, K, N] float32."""
+    if not isinstance(I, torch.Tensor) or I.dim() != 3:
+        raise TMError("I must be a [P, K, N] tensor")
     P = I.shape[0]
+    _chk(I, "I", (P, K, N), _F32, net.W[0].device)
+    _mlp_io(net, K, N)
     t0 = torch.empty((P, N), dtype=torch.complex64, device=I.device)
     rc = ctx.lib.tm_mlp_start(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), K, N, _ptr(I), P, _ptr(t0),
                               _stream(I.device))
@@ -487,7 +600,7 @@ def tm_mlp_start(ctx: Context, net: MLP, I, K: int, N: int):
 
 def tm_mlp_gradients(ctx: Context, net: MLP, I, t, K: int, N: int):
     """(dW list, db list, per-row loss) of the mean loss over the batch."""
-    B = I.shape[0]
+    B = _mlp_batch(net, I, t, K, N)
     dW = [torch.empty_like(w) for w in net.W]
     db = [torch.empty_like(b) for b in net.b]
     loss = torch.empty((B,), dtype=torch.float32, device=I.device)
@@ -500,7 +613,9 @@ def tm_mlp_gradients(ctx: Context, net: MLP, I, t, K: int, N: int):
 
 
 def tm_mlp_train_step(ctx: Context, net: MLP, I, t, K: int, N: int, lr: float, loss=None):
-    B = I.shape[0]
+    B = _mlp_batch(net, I, t, K, N)
+    if loss is not None:
+        _chk(loss, "loss", (B,), _F32, I.device)
     net.step += 1
     rc = ctx.lib.tm_mlp_train_step(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), K, N, _ptr(I), _ptr(t), B,
                                    float(lr), net.step, _ptr(loss), _stream(I.device))
@@ -509,9 +624,13 @@ def tm_mlp_train_step(ctx: Context, net: MLP, I, t, K: int, N: int, lr: float, l
 
 def tm_gemm_bf16(ctx: Context, A, B, ta=False, tb=False):
     """C = op(A) op(B) in FP32 from BF16 A, B."""
+    if not isinstance(A, torch.Tensor) or not isinstance(B, torch.Tensor) or A.dim() != 2 or B.dim() != 2:
+        raise TMError("A and B must be 2-D tensors")
     M = A.shape[1] if ta else A.shape[0]
     K = A.shape[0] if ta else A.shape[1]
     N = B.shape[0] if tb else B.shape[1]
+    _chk(A, "A", A.shape, (torch.bfloat16,))
+    _chk(B, "B", (N, K) if tb else (K, N), (torch.bfloat16,), A.device)
     C = torch.empty((M, N), dtype=torch.float32, device=A.device)
     rc = ctx.lib.tm_gemm_bf16(ctx.h, M, N, K, _ptr(A), int(ta), _ptr(B), int(tb), _ptr(C), _stream(A.device))
     ctx.check(rc, "tm_gemm_bf16")
@@ -528,7 +647,12 @@ class Batch:
         self.problems = problems  # keeps the tensors alive
         arr = (tm_problem * len(problems))()
         for i, p in enumerate(problems):
-            K, N = p["masks"].shape
+            K, N = _masks(p["masks"], p["n1"], p["n2"])
+            P = _rows(p["t"], "t", N, p["masks"].device)
+            _chk(p["I"], "I", (P, K, N), (torch.float32,) if opts.I_dtype == TM_F32 else _IDT[1:],
+                 p["masks"].device)
+            if p.get("stats") is not None:
+                _chk(p["stats"], "stats", (P, ROW_STATS_BYTES), (torch.uint8,), p["masks"].device)
             arr[i] = tm_problem(_dims(p["n1"], p["n2"], K, p["t"].shape[0]), _ptr(p["masks"]), _ptr(p["I"]),
                                 _ptr(p["t"]), _ptr(p.get("stats")))
         h = ctypes.c_void_p()
