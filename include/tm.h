@@ -174,6 +174,23 @@ int tm_retrieve(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I,
                 tm_c32 *t, const tm_retrieve_opts *opts, tm_row_stats *stats,
                 void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tm_retrieve restricted to error reduction (TM_METHOD_ER without momentum,
+ * or TM_METHOD_ER_CYCLIC) from a TM_START_GIVEN or TM_START_BACKPROP start,
+ * with the same arguments, kernels and results. Its per-row sums live in a
+ * static device array of the library (about 1.6 MiB per device, held until
+ * the process ends) instead of context workspace, so the call runs no
+ * hipMalloc, hipFree or other allocating routine and records no events.
+ * Every call on one device shares that array: calls that overlap on one GPU
+ * (other streams, other host threads, other contexts) race and must be
+ * ordered by the caller. Errors: P > TM_NOALLOC_MAX_ROWS -> TM_EINVAL; another
+ * method, start or a nonzero er_momentum -> TM_EUNSUPPORTED (nothing launched). */
+#define TM_NOALLOC_MAX_ROWS 32768
+int tm_retrieve_noalloc(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I,
+                        tm_c32 *t, const tm_retrieve_opts *opts, tm_row_stats *stats,
+                        void *stream);
+
 /* ---- uneven batches of TMs ----------------------------------------------- */
 
 /* One retrieval problem of a batch. d.n1 x d.n2 must be one of the grids

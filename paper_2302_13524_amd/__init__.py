@@ -33,7 +33,9 @@ EXPORTED = (
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
     "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band", "tm_phase_last_counts",
+    "tm_retrieve_noalloc",
 )
+TM_NOALLOC_MAX_ROWS = 32768
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
               6: "line_sums", 7: "residual_f64", 8: "backprop", 9: "amp_gradient", 10: "amp_line_sums",
               11: "filter", 12: "er_cyclic", 13: "lanczos"}
@@ -110,6 +112,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_amp_gradient.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.tm_residual_f64.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.tm_retrieve.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), vp, vp]
+    lib.tm_retrieve_noalloc.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), vp, vp]
     lib.tm_phase_offset_correct.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
                                             ctypes.POINTER(tm_optics), vp, ctypes.POINTER(tm_phase_opts),
                                             ctypes.POINTER(dp), vp]
@@ -359,6 +362,22 @@ def tm_retrieve(ctx: Context, masks, I, t, n1, n2, opts: tm_retrieve_opts | None
                              _ptr(raw), _stream(t.device))
     ctx.check(rc, "tm_retrieve")
     return raw
+
+
+def tm_retrieve_noalloc(ctx: Context, masks, I, t, n1, n2, opts: tm_retrieve_opts, stats=None):
+    """tm_retrieve for error reduction from a given or back-propagation start,
+    with no device allocation in the library (its sums use a static device
+    array shared by every call on the device). stats: None or a caller-owned
+    [P, 24] uint8 device tensor."""
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
+    if (opts.I_dtype == TM_F32) != (I.dtype == torch.float32):
+        raise TMError(f"I dtype {I.dtype} does not match opts.I_dtype {opts.I_dtype}")
+    if stats is not None:
+        _chk(stats, "stats", (P, ROW_STATS_BYTES), (torch.uint8,), t.device)
+    rc = ctx.lib.tm_retrieve_noalloc(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _ptr(t), ctypes.byref(opts),
+                                     _ptr(stats), _stream(t.device))
+    ctx.check(rc, "tm_retrieve_noalloc")
+    return stats
 
 
 def _ddims(P, N, Nd, nf1, nf2):

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,9 +61,26 @@ struct tm_ctx {
   } pg;
   int32_t ph_iters = 0, ph_evals = 0;  // accepted iterations and evaluations of the last phase solve
   int32_t ph_iters_req = -1;           // the iteration count that solve was asked for
+  void* scratch = nullptr;             // device address of the no-allocation scratch on this device
 };
 
 constexpr int PHASE_GRAPH_ITERS = 10;  // phase L-BFGS iterations captured per graph replay
+
+// Scratch of tm_retrieve_noalloc: per-row monitoring sums [rows][NSUM] float,
+// then the FP64 residual sums [rows][2] double. One copy per device, held
+// until the process ends. Host code never passes `scratch` itself to a
+// kernel (in host code it names a host-side stand-in): it uses the device
+// address that tm_create looks up for the context's device.
+constexpr size_t NA_SUMS_BYTES = (size_t)TM_NOALLOC_MAX_ROWS * tmk::NSUM * sizeof(float);
+constexpr size_t NA_S64_OFF = (NA_SUMS_BYTES + 255) / 256 * 256;
+constexpr size_t NA_SCRATCH_BYTES = NA_S64_OFF + (size_t)TM_NOALLOC_MAX_ROWS * 2 * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NA_MAX_DEVICES] = {};  // device address of `scratch`, per device
+}  // namespace
 
 static void phase_graph_release(tm_ctx* c) {
   if (c->pg.exec) hipGraphExecDestroy(c->pg.exec);
@@ -215,8 +233,23 @@ int tm_create(tm_ctx** out, int device) {
     return fail(nullptr, TM_EHIP, "no HIP device available");
   if (device < 0 || device >= ndev) return fail(nullptr, TM_EINVAL, "device %d of %d", device, ndev);
   if (hipSetDevice(device) != hipSuccess) return fail(nullptr, TM_EHIP, "hipSetDevice(%d) failed", device);
+  if (device >= NA_MAX_DEVICES) return fail(nullptr, TM_EINVAL, "device %d >= %d", device, NA_MAX_DEVICES);
+  void* sp = nullptr;
+  {
+    // once per device, with that device current: the device's own address of `scratch`
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      hipError_t se = hipGetSymbolAddress(&g_scratch_ptr[device], HIP_SYMBOL(scratch));
+      if (se != hipSuccess || !g_scratch_ptr[device]) {
+        g_scratch_ptr[device] = nullptr;
+        return fail(nullptr, TM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(se));
+      }
+    }
+    sp = g_scratch_ptr[device];
+  }
   tm_ctx* c = new tm_ctx;
   c->device = device;
+  c->scratch = sp;
   // Twiddle tables W_L^i = exp(-2 pi j i / L) for every power of two L <= TW_MAX,
   // the table of length L at offset L - 1; FP64 values, FP32 rounded once.
   std::vector<tmk::cx<double>> h64(2 * TW_MAX);
@@ -546,6 +579,65 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   if (stats) {
     int e = tmk::launch_finalize(stats, d.P, s64, (f_idx >= 0 || amp_idx >= 0) ? sums : nullptr, tmk::NSUM, f_idx,
                                  amp_idx, o->iters, 1e-2, stream);
+    if (e) return hipfail(c, e, "finalize");
+  }
+  return TM_OK;
+}
+
+int tm_retrieve_noalloc(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32* t,
+                        const tm_retrieve_opts* o, tm_row_stats* stats, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (!o) return fail(c, TM_EINVAL, "opts is NULL");
+  if (o->method != TM_METHOD_ER && o->method != TM_METHOD_ER_CYCLIC)
+    return fail(c, TM_EUNSUPPORTED, "method %d: the allocation-free form runs TM_METHOD_ER or TM_METHOD_ER_CYCLIC",
+                o->method);
+  if (o->start != TM_START_GIVEN && o->start != TM_START_BACKPROP)
+    return fail(c, TM_EUNSUPPORTED, "start %d: the allocation-free form starts from TM_START_GIVEN or "
+                "TM_START_BACKPROP", o->start);
+  if (o->er_momentum != 0.f) return fail(c, TM_EUNSUPPORTED, "er_momentum: the allocation-free form takes none");
+  if (o->iters < 0) return fail(c, TM_EINVAL, "iters %d < 0", o->iters);
+  if (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", o->I_dtype);
+  if (d.P > TM_NOALLOC_MAX_ROWS)
+    return fail(c, TM_EINVAL, "P=%d exceeds the allocation-free limit of %d rows", d.P, TM_NOALLOC_MAX_ROWS);
+  if (d.P == 0) return TM_OK;
+  if (!masks || !I || !t) return fail(c, TM_EINVAL, "null pointer argument");
+  if (!c->scratch) return fail(c, TM_EHIP, "no scratch address for device %d", c->device);
+  HIPCHK(c, hipSetDevice(c->device));
+  // every value read from the scratch is written earlier in this call (sums
+  // and residual sums are stored per row, not accumulated)
+  float* sums = (float*)c->scratch;
+  double* s64 = (double*)((unsigned char*)c->scratch + NA_S64_OFF);
+  const int ibf = o->I_dtype == TM_BF16;
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.I = I;
+  tmk::cx<float>* tt = (tmk::cx<float>*)t;
+  int e = 0;
+  if (o->start == TM_START_BACKPROP) {
+    a.tout = tt;
+    e = fn(tmk::M_BACKPROP, ibf, a, stream);
+    if (e) return hipfail(c, e, "row kernel launch");
+  }
+  const int mode = o->method == TM_METHOD_ER_CYCLIC ? tmk::M_ERC : tmk::M_ER;
+  a.tin = tt;
+  a.tout = tt;
+  for (int it = 0; it < o->iters; ++it) {
+    a.sums = (it == o->iters - 1) ? sums : nullptr;  // only the last iteration's sums are reported
+    e = fn(mode, ibf, a, stream);
+    if (e) return hipfail(c, e, "row kernel launch");
+  }
+  tmk::RowArgs ra = base_args(c, d, masks);
+  ra.I = I;
+  ra.tin = tt;
+  ra.sums64 = s64;
+  e = fn(tmk::M_RES64, ibf, ra, stream);
+  if (e) return hipfail(c, e, "row kernel launch");
+  if (stats) {
+    const bool any = o->iters > 0;
+    e = tmk::launch_finalize(stats, d.P, s64, any ? sums : nullptr, tmk::NSUM, any ? 1 : -1, any ? 0 : -1,
+                             o->iters, 1e-2, stream);
     if (e) return hipfail(c, e, "finalize");
   }
   return TM_OK;
