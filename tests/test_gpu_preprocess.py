@@ -126,7 +126,7 @@ def test_camera_layout_to_retrieval(ctx):
     cam = np.flatnonzero(half)  # half-grid index q -> camera pixel (2y, 2x)
     cam = (2 * (cam // (H // 2))) * H + 2 * (cam % (H // 2))
     v0 = c64(tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(972, 3)))
-    tm.tm_retrieve(ctx, c64(masks), rows, v0, n1, n2,
+    tm.tm_retrieve(ctx, c64(masks), rows.view(P, K, N), v0, n1, n2,  # [pixel][image] is [P][K][N]
                    tm.retrieve_opts("er", iters=150, start="spectral", spectral_iters=40, spectral_lower=0.0))
     fid = rt.fidelity(v0.cpu().numpy().astype(np.complex128), T[cam])
     assert fid.mean() > 0.99
