@@ -135,11 +135,14 @@ enum {
   TM_START_GIVEN = 0,     /* use t as passed in                                  */
   TM_START_BACKPROP = 1,  /* t = A^H sqrt(I) / (K N)          (Eq. backpropagation) */
   TM_START_SPECTRAL = 2,  /* truncated spectral start seeded with the t passed in  */
-  TM_START_LANCZOS = 3    /* the same eigenvector by spectral_iters (1..64) Lanczos
+  TM_START_LANCZOS = 3,   /* the same eigenvector by spectral_iters (1..64) Lanczos
                              steps on A^H diag(w) A from the t passed in: Ritz vector
                              of the largest Ritz value (tridiagonal eigenproblem in
                              FP64), scaled to ||t||^2 = sum(I)/(K N); workspace
                              spectral_iters P N complex floats                       */
+  TM_START_LEARNED = 4    /* TM_START_LANCZOS with the learned weights w = T(I/mean(I_p))
+                             of the table set by tm_set_weight_table instead of the
+                             truncation (not in the paper; see the learned start below) */
 };
 
 typedef struct {
@@ -364,6 +367,63 @@ int tm_mlp_train_step(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p
  * used by the network. */
 int tm_gemm_bf16(tm_ctx *ctx, int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t ta,
                  const uint16_t *B, int32_t tb, float *C, void *stream);
+
+/* ---- learned weighting of the spectral start (not in the paper) -------------
+ * The spectral start takes the top eigenvector of A^H diag(w) A. Its plain
+ * form truncates, w = min(x, tau), x = I / mean(I_p); the learned form uses
+ * w = T(x), a function a small network proposes: per point of a uniform
+ * table x_b = b xmax / (nt - 1), b < nt, the network maps TM_WNET_FEATURES
+ * fixed functions of x_b (the same ones in the library and its tests)
+ * through Linear(64, hidden) -> GELU -> Linear(hidden, hidden) -> GELU ->
+ * Linear(hidden, 1) to T(x_b) (BF16 MFMA GEMMs, FP32 accumulation; the
+ * tm_mlp_dims / tm_mlp_params layout above with n_in = 64, n_out = 1).
+ * Weights between the points are linear interpolations; x beyond xmax reads
+ * T(xmax). It is trained on (intensity, row) pairs of the forward model:
+ * the loss is minus the mean fidelity |t^H u_k|^2 / (||t||^2 ||u_k||^2)
+ * after k normalised power steps u <- M u / ||M u|| from seeds v0, and its
+ * gradient goes back through the k steps to the table and the network. */
+#define TM_WNET_FEATURES 64
+#define TM_WTAB_MAX 4096
+
+/* The table of the network: tab [nt][2] float (device) = (T(x_b), T(x_{b+1}) - T(x_b)),
+ * the last slope 0. 2 <= nt <= TM_WTAB_MAX, xmax > 0. */
+int tm_wnet_table(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, int32_t nt, float xmax,
+                  float *tab, void *stream);
+
+/* Warm start of the network: one Adam step on the mean squared difference
+ * between T(x_b) and the plain truncation min(x_b, tau) over the table
+ * points. loss [1] device float (may be NULL). */
+int tm_wnet_pretrain_step(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, int32_t nt, float xmax,
+                          float tau, float lr, int32_t step, float *loss, void *stream);
+
+/* Training loss of a table and its gradient: d.P rows with true rows t [P][N],
+ * intensities I [P][K][N] (I_dtype), seeds v0 [P][N]; `steps` (1..256) power
+ * steps with the weights of tab [nt][2]; dtab [nt] float receives d loss / d T(x_b)
+ * (overwritten), loss [1] float the loss (both device). */
+int tm_wtab_power_grad(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, int32_t I_dtype,
+                       const tm_c32 *t, const tm_c32 *v0, int32_t steps, const float *tab, int32_t nt, float xmax,
+                       float *dtab, float *loss, void *stream);
+
+/* One training step of the network: its table, the loss and table gradient
+ * as tm_wtab_power_grad, backward through the network, Adam (as
+ * tm_mlp_train_step) and the BF16 copies refreshed. loss [1] device (may be NULL). */
+int tm_wnet_train_step(tm_ctx *ctx, const tm_mlp_dims *md, const tm_mlp_params *p, tm_dims d,
+                       const tm_c32 *masks, const void *I, int32_t I_dtype, const tm_c32 *t, const tm_c32 *v0,
+                       int32_t steps, int32_t nt, float xmax, float lr, int32_t step, float *loss, void *stream);
+
+/* Copy a table [nt][2] into the context for TM_START_LEARNED (stream-ordered). */
+int tm_set_weight_table(tm_ctx *ctx, const float *tab, int32_t nt, float xmax, void *stream);
+
+/* Retrieval from the learned start with the plain start as fallback: tm_retrieve
+ * with opts->start = TM_START_LEARNED; then every row whose FP64 acceptance
+ * residual exceeds rho_fallback is retrieved again from the plain truncated
+ * Lanczos start (opts->spectral_tau, seeded with that row's t as passed in),
+ * and keeps whichever result has the lower residual. *n_fallback (host)
+ * receives the number of rows redone. Synchronises the stream once (to read
+ * that count). stats [P] may be NULL. */
+int tm_retrieve_learned(tm_ctx *ctx, tm_dims d, const tm_c32 *masks, const void *I, tm_c32 *t,
+                        const tm_retrieve_opts *opts, double rho_fallback, tm_row_stats *stats,
+                        int32_t *n_fallback, void *stream);
 
 /* ---- instrumentation ------------------------------------------------------ */
 

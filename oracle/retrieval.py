@@ -221,7 +221,8 @@ def spectral_start(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3
     return v * scale[:, None]
 
 
-def spectral_lanczos(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3.0, basis: bool = False):
+def spectral_lanczos(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float = 3.0, basis: bool = False,
+                     weights: np.ndarray | None = None):
     """Truncated spectral start by the Lanczos method (a choice made here):
     `iters` Lanczos steps on M = A^H diag(w) A (w as in spectral_start) from
     v_1 = v0 / ||v0||,
@@ -231,8 +232,9 @@ def spectral_lanczos(op, I: np.ndarray, v0: np.ndarray, iters: int, tau: float =
     tridiagonal T (diagonal alpha_1..alpha_k, off-diagonal beta_2..beta_k),
     sign fixed by y_1 >= 0, and t = sum_j y_j v_j, normalised and scaled to
     ||t||^2 = sum(I_p) / (K N). No reorthogonalisation. With basis=True also
-    returns (alpha [P][k], beta [P][k] (beta[:, j] = beta_{j+1}), V [k+1][P][N])."""
-    w = spectral_weights(I, tau)
+    returns (alpha [P][k], beta [P][k] (beta[:, j] = beta_{j+1}), V [k+1][P][N]).
+    `weights` [P, K, N] replaces the truncated weights (the learned form)."""
+    w = spectral_weights(I, tau) if weights is None else weights
     v = np.array(v0, dtype=np.complex128)
     P = v.shape[0]
     n = np.linalg.norm(v, axis=1)

@@ -23,7 +23,8 @@ TM_OK, TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENOMEM = 0, -1, -2, -3, -4
 TM_F32, TM_BF16 = 0, 1
 TM_FIELD, TM_INTENSITY = 0, 1
 TM_METHOD_ER, TM_METHOD_LBFGS, TM_METHOD_LBFGS_AMP, TM_METHOD_ER_CYCLIC = 0, 1, 2, 3
-TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL, TM_START_LANCZOS = 0, 1, 2, 3
+TM_START_GIVEN, TM_START_BACKPROP, TM_START_SPECTRAL, TM_START_LANCZOS, TM_START_LEARNED = 0, 1, 2, 3, 4
+TM_WNET_FEATURES, TM_WTAB_MAX = 64, 4096
 
 EXPORTED = (
     "tm_create", "tm_destroy", "tm_last_error", "tm_grid_supported", "tm_forward", "tm_adjoint",
@@ -33,7 +34,8 @@ EXPORTED = (
     "tm_batch_create", "tm_batch_run", "tm_batch_destroy", "tm_tune_time", "tm_set_variant",
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
     "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band", "tm_phase_last_counts",
-    "tm_retrieve_noalloc",
+    "tm_retrieve_noalloc", "tm_wnet_table", "tm_wnet_pretrain_step", "tm_wtab_power_grad", "tm_wnet_train_step",
+    "tm_set_weight_table", "tm_retrieve_learned",
 )
 TM_NOALLOC_MAX_ROWS = 32768
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
@@ -113,6 +115,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_residual_f64.argtypes = [vp, tm_dims, vp, vp, ctypes.c_int, vp, vp, vp]
     lib.tm_retrieve.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), vp, vp]
     lib.tm_retrieve_noalloc.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), vp, vp]
+    f32 = ctypes.c_float
+    lib.tm_wnet_table.argtypes = [vp, ctypes.POINTER(tm_mlp_dims), ctypes.POINTER(tm_mlp_params), i32, f32, vp, vp]
+    lib.tm_wnet_pretrain_step.argtypes = [vp, ctypes.POINTER(tm_mlp_dims), ctypes.POINTER(tm_mlp_params), i32, f32,
+                                          f32, f32, i32, vp, vp]
+    lib.tm_wtab_power_grad.argtypes = [vp, tm_dims, vp, vp, i32, vp, vp, i32, vp, i32, f32, vp, vp, vp]
+    lib.tm_wnet_train_step.argtypes = [vp, ctypes.POINTER(tm_mlp_dims), ctypes.POINTER(tm_mlp_params), tm_dims, vp,
+                                       vp, i32, vp, vp, i32, i32, f32, f32, i32, vp, vp]
+    lib.tm_set_weight_table.argtypes = [vp, vp, i32, f32, vp]
+    lib.tm_retrieve_learned.argtypes = [vp, tm_dims, vp, vp, vp, ctypes.POINTER(tm_retrieve_opts), dp, vp,
+                                        ctypes.POINTER(i32), vp]
     lib.tm_phase_offset_correct.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
                                             ctypes.POINTER(tm_optics), vp, ctypes.POINTER(tm_phase_opts),
                                             ctypes.POINTER(dp), vp]
@@ -343,7 +355,7 @@ def retrieve_opts(method="er", iters=100, lbfgs_m=5, bf16=False, start="given", 
     m = {"er": TM_METHOD_ER, "lbfgs": TM_METHOD_LBFGS, "lbfgs_amp": TM_METHOD_LBFGS_AMP,
          "er_cyclic": TM_METHOD_ER_CYCLIC}[method]
     s = {"given": TM_START_GIVEN, "backprop": TM_START_BACKPROP, "spectral": TM_START_SPECTRAL,
-         "lanczos": TM_START_LANCZOS}[start]
+         "lanczos": TM_START_LANCZOS, "learned": TM_START_LEARNED}[start]
     return tm_retrieve_opts(m, int(iters), int(lbfgs_m), TM_BF16 if bf16 else TM_F32, s, int(spectral_iters),
                             float(spectral_tau), float(spectral_momentum), float(er_momentum),
                             float(-spectral_momentum if spectral_lower is None else spectral_lower))
@@ -742,3 +754,94 @@ def autotune(ctx: Context, n1: int, n2: int, K: int, P: int, bf16: bool = False,
                 json.dump(table, fh, indent=1, sort_keys=True)
     tm_set_variant(ctx, n1, n2, entry["variant"])
     return entry
+
+
+# ---------------------------------------------------------------- learned weighting of the spectral start
+
+def weight_net(hidden: int = 256, device="cuda:0", seed: int = 0) -> MLP:
+    """The network that proposes the spectral start's weights T(x):
+    TM_WNET_FEATURES features of x -> hidden -> hidden -> 1 (tm_wnet_*)."""
+    return MLP(TM_WNET_FEATURES, hidden, 1, device=device, seed=seed)
+
+
+def _wnet_check(net: MLP):
+    if net.dims.n_in != TM_WNET_FEATURES or net.dims.n_out != 1:
+        raise TMError(f"weight network must map {TM_WNET_FEATURES} features to 1 output")
+
+
+def tm_wnet_table(ctx: Context, net: MLP, nt: int = 256, xmax: float = 16.0):
+    """The network's weight table [nt, 2] float32: (T(x_b), T(x_{b+1}) - T(x_b))."""
+    _wnet_check(net)
+    tab = torch.empty((int(nt), 2), dtype=torch.float32, device=net.W[0].device)
+    ctx.check(ctx.lib.tm_wnet_table(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), int(nt), float(xmax),
+                                    _ptr(tab), _stream(tab.device)), "tm_wnet_table")
+    return tab
+
+
+def tm_wnet_pretrain_step(ctx: Context, net: MLP, nt: int, xmax: float, tau: float, lr: float, loss=None):
+    _wnet_check(net)
+    if loss is not None:
+        _chk(loss, "loss", (1,), _F32, net.W[0].device)
+    net.step += 1
+    ctx.check(ctx.lib.tm_wnet_pretrain_step(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), int(nt), float(xmax),
+                                            float(tau), float(lr), net.step, _ptr(loss),
+                                            _stream(net.W[0].device)), "tm_wnet_pretrain_step")
+
+
+def _wtab_rows(masks, I, t, v0, n1, n2):
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
+    _chk(v0, "v0", (P, N), _C64, masks.device)
+    return K, N, P
+
+
+def tm_wtab_power_grad(ctx: Context, masks, I, t, v0, n1, n2, tab, steps: int, xmax: float = 16.0):
+    """(loss, d loss / d table values [nt]) of `steps` power steps with the table's weights."""
+    K, N, P = _wtab_rows(masks, I, t, v0, n1, n2)
+    if not isinstance(tab, torch.Tensor) or tab.dim() != 2:
+        raise TMError("tab must be an [nt, 2] tensor")
+    nt = tab.shape[0]
+    _chk(tab, "tab", (nt, 2), _F32, masks.device)
+    dtab = torch.empty((nt,), dtype=torch.float32, device=masks.device)
+    loss = torch.empty((1,), dtype=torch.float32, device=masks.device)
+    ctx.check(ctx.lib.tm_wtab_power_grad(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _idtype(I), _ptr(t),
+                                         _ptr(v0), int(steps), _ptr(tab), int(nt), float(xmax), _ptr(dtab),
+                                         _ptr(loss), _stream(masks.device)), "tm_wtab_power_grad")
+    return loss, dtab
+
+
+def tm_wnet_train_step(ctx: Context, net: MLP, masks, I, t, v0, n1, n2, steps: int, nt: int = 256,
+                       xmax: float = 16.0, lr: float = 1e-3, loss=None):
+    _wnet_check(net)
+    K, N, P = _wtab_rows(masks, I, t, v0, n1, n2)
+    if loss is not None:
+        _chk(loss, "loss", (1,), _F32, masks.device)
+    net.step += 1
+    ctx.check(ctx.lib.tm_wnet_train_step(ctx.h, ctypes.byref(net.dims), ctypes.byref(net.p), _dims(n1, n2, K, P),
+                                         _ptr(masks), _ptr(I), _idtype(I), _ptr(t), _ptr(v0), int(steps), int(nt),
+                                         float(xmax), float(lr), net.step, _ptr(loss), _stream(masks.device)),
+              "tm_wnet_train_step")
+
+
+def tm_set_weight_table(ctx: Context, tab, xmax: float = 16.0):
+    if not isinstance(tab, torch.Tensor) or tab.dim() != 2:
+        raise TMError("tab must be an [nt, 2] tensor")
+    _chk(tab, "tab", (tab.shape[0], 2), _F32)
+    ctx.check(ctx.lib.tm_set_weight_table(ctx.h, _ptr(tab), int(tab.shape[0]), float(xmax), _stream(tab.device)),
+              "tm_set_weight_table")
+
+
+def tm_retrieve_learned(ctx: Context, masks, I, t, n1, n2, opts: tm_retrieve_opts, rho_fallback: float = 1e-2,
+                        stats=True):
+    """Learned-start retrieval in place in t with the plain start as per-row
+    fallback; returns (raw stats [P, 24] uint8 or None, rows redone)."""
+    K, N, P = _rows_and_I(masks, I, t, n1, n2)
+    if opts.start != TM_START_LEARNED:
+        raise TMError("opts.start must be 'learned'")
+    if (opts.I_dtype == TM_F32) != (I.dtype == torch.float32):
+        raise TMError(f"I dtype {I.dtype} does not match opts.I_dtype {opts.I_dtype}")
+    raw = torch.empty((P, ROW_STATS_BYTES), dtype=torch.uint8, device=t.device) if stats else None
+    nf = ctypes.c_int32(0)
+    ctx.check(ctx.lib.tm_retrieve_learned(ctx.h, _dims(n1, n2, K, P), _ptr(masks), _ptr(I), _ptr(t),
+                                          ctypes.byref(opts), float(rho_fallback), _ptr(raw), ctypes.byref(nf),
+                                          _stream(t.device)), "tm_retrieve_learned")
+    return raw, nf.value

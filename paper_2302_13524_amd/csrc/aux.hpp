@@ -8,6 +8,14 @@ int launch_row_isum(const void* I, int bf16, int64_t len, int P, double* rowsum,
 int launch_row_rescale(void* t, int N, int P, int mode, const double* rowsum, double denom,
                        void* stream);
 int launch_fill_zero(void* p, int64_t bytes, void* stream);
+// indices of the rows whose stats record has rho > thr (or rho not finite), in no particular
+// order, appended at idx[*count] (count must start at 0)
+int launch_flag_rows(const void* stats, int P, double thr, int* idx, int* count, void* stream);
+// dst row j <- src row idx[j] (rows of row_bytes, a multiple of 8)
+int launch_gather_rows(void* dst, const void* src, const int* idx, int rows, int64_t row_bytes, void* stream);
+// for j < rows: row idx[j] of t and its stats record take row j of tf / stf when stf's rho is lower
+int launch_select_rows(void* t, const void* tf, void* stats, const void* stf, const int* idx, int rows,
+                       int64_t row_bytes, void* stream);
 // device-to-device copy by a kernel (graph-capturable); bytes and both
 // pointers must be multiples of 8
 int launch_copy(void* dst, const void* src, int64_t bytes, void* stream);

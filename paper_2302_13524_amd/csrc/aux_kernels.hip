@@ -3,6 +3,8 @@
 // instead of memset so the launches stay graph-capturable), and the per-row
 // result record.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 #include "aux.hpp"
 
@@ -262,6 +264,65 @@ int launch_row_rescale(void* t, int N, int P, int mode, const double* rowsum, do
     k_row_rescale<<<P, 256, 0, (hipStream_t)s>>>((float2*)t, N, P, mode, rowsum, denom);
   return (int)hipGetLastError();
 }
+// rows whose FP64 residual exceeds thr (or is not finite): idx[*count] = p
+__global__ void __launch_bounds__(256) k_flag_rows(const RowStats* __restrict__ st, int P, double thr, int* idx,
+                                                   int* count) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const double r = st[p].rho;
+  if (!(r <= thr)) idx[atomicAdd(count, 1)] = p;
+}
+
+// dst row j <- src row idx[j], rows of `words` 8-byte words
+__global__ void __launch_bounds__(256) k_gather_rows(uint2* __restrict__ dst, const uint2* __restrict__ src,
+                                                     const int* __restrict__ idx, int64_t words) {
+  const int j = blockIdx.y;
+  const uint2* s = src + (size_t)idx[j] * words;
+  uint2* d = dst + (size_t)j * words;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256) d[i] = s[i];
+}
+
+// row idx[j] of t and of st takes the fallback's row j where its residual is lower
+__global__ void __launch_bounds__(256) k_select_rows(uint2* __restrict__ t, const uint2* __restrict__ tf,
+                                                     RowStats* __restrict__ st, const RowStats* __restrict__ stf,
+                                                     const int* __restrict__ idx, int64_t words) {
+  const int j = blockIdx.y;
+  const int p = idx[j];
+  const bool take = stf[j].rho < st[p].rho || !(st[p].rho == st[p].rho);
+  if (!take) return;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256)
+    t[(size_t)p * words + i] = tf[(size_t)j * words + i];
+  __syncthreads();  // every thread has read st[p].rho above before it is replaced
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[p] = stf[j];
+}
+
+int launch_flag_rows(const void* st, int P, double thr, int* idx, int* count, void* s) {
+  if (P <= 0) return 0;
+  k_flag_rows<<<(P + 255) / 256, 256, 0, (hipStream_t)s>>>((const RowStats*)st, P, thr, idx, count);
+  return (int)hipGetLastError();
+}
+
+int launch_gather_rows(void* dst, const void* src, const int* idx, int rows, int64_t row_bytes, void* s) {
+  if (rows <= 0) return 0;
+  if (row_bytes % 8 || (uintptr_t)dst % 8 || (uintptr_t)src % 8) return (int)hipErrorInvalidValue;
+  const int64_t words = row_bytes / 8;
+  dim3 grid((unsigned)std::min<int64_t>((words + 255) / 256, 64), (unsigned)rows);
+  k_gather_rows<<<grid, 256, 0, (hipStream_t)s>>>((uint2*)dst, (const uint2*)src, idx, words);
+  return (int)hipGetLastError();
+}
+
+int launch_select_rows(void* t, const void* tf, void* st, const void* stf, const int* idx, int rows, int64_t row_bytes,
+                       void* s) {
+  if (rows <= 0) return 0;
+  if (row_bytes % 8) return (int)hipErrorInvalidValue;
+  const int64_t words = row_bytes / 8;
+  // one workgroup per row: the residual comparison and the record update stay in one workgroup
+  dim3 grid(1, (unsigned)rows);
+  k_select_rows<<<grid, 256, 0, (hipStream_t)s>>>((uint2*)t, (const uint2*)tf, (RowStats*)st,
+                                                  (const RowStats*)stf, idx, words);
+  return (int)hipGetLastError();
+}
+
 int launch_fill_zero(void* p, int64_t bytes, void* s) {
   int64_t n = bytes / 4;
   if (n <= 0) return 0;

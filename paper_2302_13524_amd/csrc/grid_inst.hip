@@ -37,6 +37,9 @@ static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
       break;
     case M_SPEC: row_kernel<PLg, M_SPEC, IT><<<grid, block, 0, s>>>(a); break;
     case M_LANCZOS: row_kernel<PLg, M_LANCZOS, IT><<<grid, block, 0, s>>>(a); break;
+    case M_LANCZOS_T: row_kernel<PLg, M_LANCZOS_T, IT><<<grid, block, 0, s>>>(a); break;
+    case M_WAPPLY: row_kernel<PLg, M_WAPPLY, IT><<<grid, block, 0, s>>>(a); break;
+    case M_WBACK: row_kernel<PLg, M_WBACK, IT><<<grid, block, 0, s>>>(a); break;
     case M_LS: row_kernel<PLg, M_LS, IT><<<grid, block, 0, s>>>(a); break;
     case M_AGRAD:
       if (a.sums) row_kernel<PLg, M_AGRAD, IT, true><<<grid, block, 0, s>>>(a);

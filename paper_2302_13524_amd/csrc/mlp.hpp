@@ -46,6 +46,10 @@ size_t mlp_work_bytes(const MlpShape& sh, int B);
 void mlp_work_carve(void* base, const MlpShape& sh, int B, MlpWork* w);
 // features, three layers; outputs in w.O (FP32 [B][n_out]) and the row scales w.s
 int mlp_forward(const MlpShape& sh, const MlpParams& P, const float* I, int B, int KN, MlpWork& w, void* stream);
+// the three layers from features already in w.X (BF16 [B][n_in]); outputs in w.O
+int mlp_forward_x(const MlpShape& sh, const MlpParams& P, int B, MlpWork& w, void* stream);
+// all parameter gradients from output gradients already in w.dOh / w.dOf (after a forward)
+int mlp_backward_dout(const MlpShape& sh, const MlpParams& P, int B, MlpWork& w, MlpGrads& G, void* stream);
 // start rows t0 [P][N] complex from w.O and w.s
 int mlp_start(const MlpWork& w, int P, int N, void* t0, void* stream);
 // loss per row into w.loss and all parameter gradients (after mlp_forward)

@@ -354,6 +354,12 @@ int mlp_forward(const MlpShape& sh, const MlpParams& P, const float* I, int B, i
   k_features<<<B, 256, 0, s>>>(I, sh.n_in, B, w.X, w.s, (float)KN);
   int e = (int)hipGetLastError();
   if (e) return e;
+  return mlp_forward_x(sh, P, B, w, stream);
+}
+
+int mlp_forward_x(const MlpShape& sh, const MlpParams& P, int B, MlpWork& w, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int e = 0;
   GemmArgs g1 = ga(B, sh.hidden, sh.n_in, w.X, sh.n_in, 0, P.Wh[0], sh.hidden, 0, MLP_EPI_BIAS_GELU);
   g1.bias = P.b[0];
   g1.outf2 = w.A1;
@@ -382,6 +388,12 @@ int mlp_backward(const MlpShape& sh, const MlpParams& P, const void* t, int B, M
   k_loss<<<B, 256, 0, s>>>(w.O, (const float2*)t, w.s, B, N, w.dOh, w.dOf, w.loss, 1.f / (float)B);
   int e = (int)hipGetLastError();
   if (e) return e;
+  return mlp_backward_dout(sh, P, B, w, G, stream);
+}
+
+int mlp_backward_dout(const MlpShape& sh, const MlpParams& P, int B, MlpWork& w, MlpGrads& G, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int e = 0;
   // layer 3: dW3 = H2^T dO, db3 = colsum(dO), dA2 = (dO W3^T) * gelu'(A2)
   GemmArgs d3 = ga(sh.hidden, sh.n_out, B, w.H2, sh.hidden, 1, w.dOh, sh.n_out, 0, MLP_EPI_STORE);
   d3.outf = G.dW[2];

@@ -20,8 +20,15 @@ enum Mode : int {
   M_ALS = 10,        // amplitude cost at t + a_j d, a_j = 2^(j-3), j < 8 -> sums {f_a(t), f_a(t + a_j d)}
   M_FILT = 11,       // x = A^H(H .* A t) / (K N), H = yin [N] in natural frequency order -> tout
   M_ERC = 12,        // for m = 1..K: t <- conj(psi_m) F^H(sqrt(I_m) y/|y|)/N, y = F(psi_m t) -> tout, sums
-  M_LANCZOS = 13     // Lanczos step on A^H diag(w) A: v_next = (M v - alpha v - beta v_prev)/||.|| -> tout, lz_out
+  M_LANCZOS = 13,    // Lanczos step on A^H diag(w) A: v_next = (M v - alpha v - beta v_prev)/||.|| -> tout, lz_out
+  // learned weighting of the spectral start: w = T(I / mean(I_p)) from the table wtab
+  M_LANCZOS_T = 14,  // M_LANCZOS with the weights read from I (the learned weights, FP32 [P][K][N])
+  M_WAPPLY = 15,     // y = A^H diag(w) A t with the learned weights      -> tout, sums {||y||^2}
+  M_WBACK = 16       // gw = Re(conj(A d) (A t)) -> yout float [P][K][N]; x = A^H diag(w) A d -> tout
 };
+
+// Modes that weight by the learned table (the row kernels look it up per measurement).
+constexpr bool learned_mode(int m) { return m == M_WAPPLY || m == M_WBACK; }
 
 constexpr int NSUM = 9;
 constexpr int AMP_TRIALS = 8;  // M_ALS trial steps 1/8 .. 16
@@ -45,6 +52,9 @@ struct RowArgs {
   float er_beta;           // M_ER Nesterov factor b: iterate from z = tin + b (tin - din), din = t_prev
   const float* lz_bprev;   // M_LANCZOS: previous step's [P][2] (alpha, beta); beta is this step's beta, or null
   float* lz_out;           // M_LANCZOS: [P][2] (alpha, ||x||) of this step
+  const float* wtab;       // learned weights: [nt][2] (T(x_b), T(x_b+1) - T(x_b)), x_b = b / wtab_scale
+  float wtab_scale;        // (nt - 1) / xmax
+  float wtab_last;         // nt - 1
   int out_bf16;            // M_FWD_INT output type
   const cx<float>* tw32;   // twiddle tables, table of length L at offset L-1
   const cx<double>* tw64;
@@ -189,6 +199,15 @@ struct Launch {
 __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Learned weight T(x) by linear interpolation in the table (x clamped to the
+// table's range; NaN reads the first point).
+__device__ __forceinline__ float wtab_eval(const RowArgs& a, float x) {
+  const float s = fminf(fmaxf(x * a.wtab_scale, 0.f), a.wtab_last);
+  const int i0 = min((int)s, (int)a.wtab_last - 1);
+  const tm_v2f e = gc((const tm_v2f*)a.wtab)[i0];
+  return e.x + (s - (float)i0) * e.y;
+}
+
 // SUMS: accumulate the per-row monitoring sums (compensated) and write them;
 // without it the kernel skips that work (used on iterations whose sums are
 // not read).
@@ -264,7 +283,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
   for (int i = 0; i < NSUM; ++i) acc[i] = KSum{0.f, 0.f};
 
   float inv_mean = 0.f;
-  if constexpr (MODE == M_SPEC || MODE == M_LANCZOS) {
+  if constexpr (MODE == M_SPEC || MODE == M_LANCZOS || learned_mode(MODE)) {
     float m = valid ? gc(a.rowmean)[prow] : 1.f;
     inv_mean = (m > 0.f) ? 1.f / m : 1.f;
   }
@@ -277,7 +296,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
   // 2286 x 8192). The ER and gradient steps load the mask twice and the
   // intensities after the transform: the same changes measured slower there
   // (cyclic ER 0.357 -> 0.376 and 0.413 ms).
-  constexpr bool PF = MODE == M_SPEC || MODE == M_LANCZOS;
+  constexpr bool PF = MODE == M_SPEC || MODE == M_LANCZOS || MODE == M_LANCZOS_T || MODE == M_WAPPLY;
   float icur[PF ? E : 1];
   C mv[PF ? E : 1];     // the mask's values, kept for the conjugate multiply
   C mnext[PF ? E : 1];  // the next mask's values, loaded during the last inverse pass
@@ -381,8 +400,25 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = cmul(x[i], gload(a.yin + KL(i)));
       }
+      if constexpr (MODE == M_WBACK) {
+        // second transform z = A d of this mask; gw = Re(conj(z) y) at each
+        // measurement (natural order); then the weighted z goes back
+        C y[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) y[i] = x[i];
+#pragma unroll
+        for (int i = 0; i < E; ++i) x[i] = cmul(gload(drow + E0(i)), gload(mk + E0(i)));
+        fft_forward<PL, T>(x, xb, ltid, tw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int k = KL(i);
+          const float w = wtab_eval(a, load_I<IT>(a.I, mbase + k) * inv_mean);
+          if (valid) gw((float*)a.yout)[mbase + k] = y[i].x * x[i].x + y[i].y * x[i].y;
+          x[i] = scl(x[i], w);
+        }
+      }
       if constexpr (MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_SPEC || MODE == M_LANCZOS ||
-                    MODE == M_AGRAD) {
+                    MODE == M_AGRAD || MODE == M_LANCZOS_T || MODE == M_WAPPLY) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           float iv;
@@ -415,6 +451,10 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
             float r = amp - (nz ? n * rs : 0.f);
             if constexpr (SUMS) acc[0].add(r * r);
             x[i] = nz ? scl(x[i], -2.f * r * rs) : C{-2.f * r, 0.f};
+          } else if constexpr (learned_mode(MODE)) {
+            x[i] = scl(x[i], wtab_eval(a, iv * inv_mean));
+          } else if constexpr (MODE == M_LANCZOS_T) {
+            x[i] = scl(x[i], iv);  // the weight itself, evaluated once per retrieval
           } else {
             float w = fminf(iv * inv_mean, a.tau);
             x[i] = scl(x[i], w);
@@ -458,7 +498,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 #pragma unroll
       for (int i = 0; i < NS; ++i) gw(a.sums)[prow * NSUM + i] = out[i];
     }
-  } else if constexpr (MODE == M_LANCZOS) {
+  } else if constexpr (MODE == M_LANCZOS || MODE == M_LANCZOS_T) {
     // alpha = Re <v, M v>; x = M v - alpha v - beta v_prev with beta = ||x|| of the
     // previous step (0 at the first, where there is no v_prev); v_next = x / ||x||.
     // ||x|| is summed from x itself (a second reduction), not expanded.
@@ -536,6 +576,18 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         gw(a.vscale)[prow] = inv;
         if (a.sums) gw(a.sums)[prow * NSUM + 0] = lam;
       }
+    }
+  } else if constexpr (MODE == M_WAPPLY) {
+    KSum q[1];
+    q[0] = KSum{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < E; ++i) q[0].add(norm2(g[i]));
+    float o1[1];
+    row_reduce<PL::T, WG, 1>(q, red, tid, o1);
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) gstore(a.tout + prow * N + E0(i), g[i]);
+      if (ltid == 0) gw(a.sums)[prow * NSUM + 0] = o1[0];
     }
   } else {
     float scale = 1.f;

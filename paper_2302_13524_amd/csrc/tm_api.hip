@@ -26,6 +26,7 @@
 #include "phase.hpp"
 #include "pre.hpp"
 #include "row_kernels.hpp"
+#include "wnet.hpp"
 
 struct tm_ctx {
   int device = 0;
@@ -62,6 +63,8 @@ struct tm_ctx {
   int32_t ph_iters = 0, ph_evals = 0;  // accepted iterations and evaluations of the last phase solve
   int32_t ph_iters_req = -1;           // the iteration count that solve was asked for
   void* scratch = nullptr;             // device address of the no-allocation scratch on this device
+  int32_t wtab_n = 0;                  // learned weight table (tm_set_weight_table): points, 0 = none
+  float wtab_xmax = 0.f;               // and its range [0, xmax]
 };
 
 constexpr int PHASE_GRAPH_ITERS = 10;  // phase L-BFGS iterations captured per graph replay
@@ -145,7 +148,7 @@ void* ws_get(tm_ctx* c, int id, size_t bytes) {
 enum WsId {
   WS_SUMS = 1, WS_SUMS64, WS_ROWSUM, WS_ROWMEAN, WS_VPREV,
   WS_LB_G, WS_LB_GP, WS_LB_D, WS_LB_S, WS_LB_Y, WS_LB_SC, WS_LB_ST, WS_TPREV, WS_VSCALE, WS_LZ_V, WS_LZ_H, WS_LZ_Y, WS_PRE_PART,
-  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E, WS_DENSE_Y, WS_PROP_X, WS_PROP_H, WS_PROP_ONES,
+  WS_PRE_COUNT, WS_FOCI_U, WS_FOCI_E, WS_DENSE_Y, WS_PROP_X, WS_PROP_H, WS_PROP_ONES, WS_WTAB,
   WS_PH_BASE = 100
 };
 
@@ -412,8 +415,10 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   const bool er_like = o->method == TM_METHOD_ER || o->method == TM_METHOD_ER_CYCLIC;
   if (o->iters < 0) return fail(c, TM_EINVAL, "iters %d < 0", o->iters);
   if (o->I_dtype != TM_F32 && o->I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", o->I_dtype);
-  if (o->start < TM_START_GIVEN || o->start > TM_START_LANCZOS) return fail(c, TM_EINVAL, "start %d", o->start);
-  if (o->start == TM_START_LANCZOS) {
+  if (o->start < TM_START_GIVEN || o->start > TM_START_LEARNED) return fail(c, TM_EINVAL, "start %d", o->start);
+  if (o->start == TM_START_LEARNED && c->wtab_n < 2)
+    return fail(c, TM_EINVAL, "TM_START_LEARNED needs a weight table (tm_set_weight_table)");
+  if (o->start == TM_START_LANCZOS || o->start == TM_START_LEARNED) {
     if (o->spectral_iters < 1 || o->spectral_iters > tmk::LZ_MAX)
       return fail(c, TM_EINVAL, "Lanczos steps (spectral_iters) %d outside 1..%d", o->spectral_iters, tmk::LZ_MAX);
     if (!(o->spectral_tau > 0.f)) return fail(c, TM_EINVAL, "spectral_tau must be > 0");
@@ -478,7 +483,7 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     if (o->spectral_iters & 1) e = tmk::launch_copy(t, vprev, (int64_t)d.P * N * sizeof(tm_c32), stream);
     if (!e) e = tmk::launch_row_rescale(t, N, d.P, 1, rowsum, (double)d.K * N, stream);
     if (e) return hipfail(c, e, "spectral scale");
-  } else if (o->start == TM_START_LANCZOS) {
+  } else if (o->start == TM_START_LANCZOS || o->start == TM_START_LEARNED) {
     // v_1 = seed / ||seed|| in t; v_2 .. v_{k+1} in the workspace; (alpha, beta) per step and row
     const int k = o->spectral_iters;
     const size_t rowsz = (size_t)d.P * N;
@@ -495,13 +500,24 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     tmk::RowArgs s = a;
     s.rowmean = rowmean;
     s.tau = o->spectral_tau;
+    const bool learned = o->start == TM_START_LEARNED;
+    if (learned) {
+      // the learned weights of every measurement, evaluated once: the Lanczos
+      // steps then read them in place of the intensities (same bytes as FP32 I)
+      float* W = (float*)ws_get(c, WS_PH_BASE + 47, (size_t)d.P * d.K * N * sizeof(float));
+      const float* tab = (const float*)ws_get(c, WS_WTAB, (size_t)c->wtab_n * 2 * sizeof(float));
+      if (!W || !tab) return fail(c, TM_ENOMEM, "learned weight workspace");
+      e = tmk::wnet_weights(I, ibf, rowmean, d.P, (int64_t)d.K * N, tab, c->wtab_n, c->wtab_xmax, W, stream);
+      if (e) return hipfail(c, e, "learned weights");
+      s.I = W;
+    }
     for (int j = 0; j < k; ++j) {
       s.tin = V(j);
       s.din = V(j > 0 ? j - 1 : 0);
       s.tout = V(j + 1);
       s.lz_bprev = j > 0 ? hist + (size_t)(j - 1) * d.P * 2 : nullptr;
       s.lz_out = hist + (size_t)j * d.P * 2;
-      r = run_row(c, fn, tmk::M_LANCZOS, ibf, s, stream);
+      r = run_row(c, fn, learned ? tmk::M_LANCZOS_T : tmk::M_LANCZOS, learned ? 0 : ibf, s, stream);
       if (r) return r;
     }
     e = tmk::launch_lz_ritz(hist, k, d.P, y, stream);
@@ -887,7 +903,7 @@ extern "C" int tm_profile_query(tm_ctx* c, int mode, double* ms, int64_t* launch
 // ---------------------------------------------------------------- learned start
 static int mlp_check(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int K, int N, bool train) {
   if (!md || !p) return fail(c, TM_EINVAL, "dims/params pointer is NULL");
-  if (md->n_in < 1 || md->hidden < 1 || md->n_out < 2) return fail(c, TM_EINVAL, "network sizes must be positive");
+  if (md->n_in < 1 || md->hidden < 1 || md->n_out < 1) return fail(c, TM_EINVAL, "network sizes must be positive");
   if (K >= 1 && N >= 1) {
     if (md->n_in != K * N) return fail(c, TM_EINVAL, "n_in=%d must equal K*N=%d", md->n_in, K * N);
     if (md->n_out != 2 * N) return fail(c, TM_EINVAL, "n_out=%d must equal 2N=%d", md->n_out, 2 * N);
@@ -1538,5 +1554,266 @@ extern "C" int tm_propagate_tm(tm_ctx* c, int32_t P, int32_t N, const tm_c32* tm
   if (r) return r;
   e = tmk::launch_grid_to_rows(X, N, G, out, stream);
   if (e) return hipfail(c, e, "transpose");
+  return TM_OK;
+}
+
+// ---------------------------------------------------------------- learned weights of the spectral start
+static int wnet_check(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int nt, float xmax, bool train) {
+  if (!md || !p) return fail(c, TM_EINVAL, "dims/params pointer is NULL");
+  if (md->n_in != tmk::WNET_FEATURES || md->n_out != 1 || md->hidden < 1 || md->hidden > 4096)
+    return fail(c, TM_EINVAL, "weight network must be %d -> hidden (1..4096) -> hidden -> 1", tmk::WNET_FEATURES);
+  if (nt < 2 || nt > TM_WTAB_MAX) return fail(c, TM_EINVAL, "table points %d outside 2..%d", nt, TM_WTAB_MAX);
+  if (!(xmax > 0.f) || !std::isfinite(xmax)) return fail(c, TM_EINVAL, "xmax must be > 0");
+  return mlp_check(c, md, p, 0, 0, train);
+}
+
+// network forward on the table points; outputs in w.O [nt]
+static int wnet_forward(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int nt, float xmax,
+                        tmk::MlpWork& w, void* stream) {
+  tmk::MlpShape sh{md->n_in, md->hidden, md->n_out};
+  void* base = ws_get(c, WS_PH_BASE + 30, tmk::mlp_work_bytes(sh, nt));
+  if (!base) return fail(c, TM_ENOMEM, "network workspace");
+  tmk::mlp_work_carve(base, sh, nt, &w);
+  int e = tmk::wnet_features(nt, xmax, w.X, stream);
+  tmk::MlpParams q = mlp_params(p);
+  if (!e) e = tmk::mlp_forward_x(sh, q, nt, w, stream);
+  if (e) return hipfail(c, e, "weight network forward");
+  return TM_OK;
+}
+
+// backward from w.dOh / w.dOf, Adam on the masters and the BF16 copies refreshed
+static int wnet_update(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int nt, tmk::MlpWork& w, float lr,
+                       int step, void* stream) {
+  size_t nw[3] = {(size_t)md->n_in * md->hidden, (size_t)md->hidden * md->hidden, (size_t)md->hidden * md->n_out};
+  size_t nb[3] = {(size_t)md->hidden, (size_t)md->hidden, (size_t)md->n_out};
+  size_t tot = 0;
+  for (int l = 0; l < 3; ++l) tot += ((nw[l] + nb[l]) * 4 + 512);
+  char* gb = (char*)ws_get(c, WS_PH_BASE + 31, tot);
+  if (!gb) return fail(c, TM_ENOMEM, "gradient workspace");
+  tmk::MlpGrads G;
+  for (int l = 0; l < 3; ++l) {
+    G.dW[l] = (float*)gb;
+    gb += (nw[l] * 4 + 255) / 256 * 256;
+    G.db[l] = (float*)gb;
+    gb += (nb[l] * 4 + 255) / 256 * 256;
+  }
+  tmk::MlpShape sh{md->n_in, md->hidden, md->n_out};
+  tmk::MlpParams q = mlp_params(p);
+  int e = tmk::mlp_backward_dout(sh, q, nt, w, G, stream);
+  if (e) return hipfail(c, e, "weight network backward");
+  tmk::MlpAdam A;
+  for (int l = 0; l < 3; ++l) {
+    A.mW[l] = p->mW[l];
+    A.vW[l] = p->vW[l];
+    A.mb[l] = p->mb[l];
+    A.vb[l] = p->vb[l];
+  }
+  e = tmk::mlp_adam(sh, q, G, A, lr, step, stream);
+  if (e) return hipfail(c, e, "Adam");
+  return TM_OK;
+}
+
+extern "C" int tm_wnet_table(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int32_t nt, float xmax,
+                             float* tab, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = wnet_check(c, md, p, nt, xmax, false);
+  if (r) return r;
+  if (!tab) return fail(c, TM_EINVAL, "tab is NULL");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::MlpWork w;
+  if ((r = wnet_forward(c, md, p, nt, xmax, w, stream))) return r;
+  int e = tmk::wnet_pairs(w.O, nt, tab, stream);
+  if (e) return hipfail(c, e, "table");
+  return TM_OK;
+}
+
+extern "C" int tm_wnet_pretrain_step(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, int32_t nt,
+                                     float xmax, float tau, float lr, int32_t step, float* loss, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = wnet_check(c, md, p, nt, xmax, true);
+  if (r) return r;
+  if (step < 1 || !(lr >= 0.f) || !(tau > 0.f)) return fail(c, TM_EINVAL, "step >= 1, lr >= 0, tau > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::MlpWork w;
+  if ((r = wnet_forward(c, md, p, nt, xmax, w, stream))) return r;
+  int e = tmk::wnet_regress(w.O, nt, xmax, tau, w.dOf, w.dOh, loss ? loss : w.loss, stream);
+  if (e) return hipfail(c, e, "regression");
+  return wnet_update(c, md, p, nt, w, lr, step, stream);
+}
+
+// Loss of k normalised power steps with the table's weights and its gradient
+// with respect to the table (dtab, overwritten).
+static int wtab_grad(tm_ctx* c, tmk::row_launcher fn, const tm_dims& d, const tm_c32* masks, const void* I, int ibf,
+                     const tm_c32* t, const tm_c32* v0, int k, const float* tab, int nt, float xmax, float* dtab,
+                     float* loss, void* stream) {
+  const int N = d.n1 * d.n2, B = d.P;
+  const size_t row = (size_t)B * N * sizeof(tm_c32);
+  char* U = (char*)ws_get(c, WS_PH_BASE + 32, row * (k + 1));
+  void* Y = ws_get(c, WS_PH_BASE + 33, row);
+  void* G = ws_get(c, WS_PH_BASE + 34, row);
+  void* Gy = ws_get(c, WS_PH_BASE + 35, row);
+  float* gw = (float*)ws_get(c, WS_PH_BASE + 36, (size_t)B * d.K * N * sizeof(float));
+  float* nrm = (float*)ws_get(c, WS_PH_BASE + 37, (size_t)k * B * sizeof(float));
+  float* fid = (float*)ws_get(c, WS_PH_BASE + 38, (size_t)B * sizeof(float));
+  double* rowsum = (double*)ws_get(c, WS_ROWSUM, (size_t)B * sizeof(double));
+  float* rowmean = (float*)ws_get(c, WS_ROWMEAN, (size_t)B * sizeof(float));
+  float* sums = (float*)ws_get(c, WS_SUMS, (size_t)B * tmk::NSUM * sizeof(float));
+  if (!U || !Y || !G || !Gy || !gw || !nrm || !fid || !rowsum || !rowmean || !sums)
+    return fail(c, TM_ENOMEM, "training workspace");
+  auto Uj = [&](int j) { return (void*)(U + row * j); };
+  int e = tmk::launch_row_isum(I, ibf, (int64_t)d.K * N, B, rowsum, rowmean, stream);
+  if (!e) e = tmk::launch_copy(Uj(0), v0, (int64_t)row, stream);
+  if (!e) e = tmk::launch_row_rescale(Uj(0), N, B, 0, nullptr, 1.0, stream);
+  if (!e) e = tmk::launch_fill_zero(dtab, (int64_t)nt * sizeof(float), stream);
+  if (e) return hipfail(c, e, "training setup");
+  tmk::RowArgs a = base_args(c, d, masks);
+  a.I = I;
+  a.rowmean = rowmean;
+  a.wtab = tab;
+  a.wtab_scale = (float)(nt - 1) / xmax;
+  a.wtab_last = (float)(nt - 1);
+  a.sums = sums;
+  int r;
+  for (int j = 0; j < k; ++j) {
+    a.tin = (const tmk::cx<float>*)Uj(j);
+    a.tout = (tmk::cx<float>*)Y;
+    if ((r = run_row(c, fn, tmk::M_WAPPLY, ibf, a, stream))) return r;
+    e = tmk::wnet_normalise(Y, sums, tmk::NSUM, B, N, Uj(j + 1), nrm + (size_t)j * B, stream);
+    if (e) return hipfail(c, e, "normalise");
+  }
+  e = tmk::wnet_loss(Uj(k), t, B, N, G, fid, loss, stream);
+  if (e) return hipfail(c, e, "loss");
+  for (int j = k - 1; j >= 0; --j) {
+    e = tmk::wnet_normback(G, Uj(j + 1), nrm + (size_t)j * B, B, N, Gy, stream);
+    if (e) return hipfail(c, e, "normalisation backward");
+    a.tin = (const tmk::cx<float>*)Uj(j);
+    a.din = (const tmk::cx<float>*)Gy;
+    a.yout = gw;
+    a.tout = (tmk::cx<float>*)G;
+    if ((r = run_row(c, fn, tmk::M_WBACK, ibf, a, stream))) return r;
+    e = tmk::wnet_hist(gw, I, ibf, rowmean, B, d.K * N, nt, xmax, dtab, stream);
+    if (e) return hipfail(c, e, "table gradient");
+  }
+  return TM_OK;
+}
+
+static int wtab_args(tm_ctx* c, const tm_dims& d, tmk::row_launcher* fn, const tm_c32* masks, const void* I,
+                     int I_dtype, const tm_c32* t, const tm_c32* v0, int k, int nt, float xmax) {
+  int r = check_dims(c, d, fn);
+  if (r) return r;
+  if (d.P < 1) return fail(c, TM_EINVAL, "P >= 1 training rows");
+  if (k < 1 || k > 256) return fail(c, TM_EINVAL, "power steps %d outside 1..256", k);
+  if (nt < 2 || nt > TM_WTAB_MAX) return fail(c, TM_EINVAL, "table points %d outside 2..%d", nt, TM_WTAB_MAX);
+  if (!(xmax > 0.f) || !std::isfinite(xmax)) return fail(c, TM_EINVAL, "xmax must be > 0");
+  if (I_dtype != TM_F32 && I_dtype != TM_BF16) return fail(c, TM_EINVAL, "I_dtype %d", I_dtype);
+  if (!masks || !I || !t || !v0) return fail(c, TM_EINVAL, "null pointer argument");
+  return TM_OK;
+}
+
+extern "C" int tm_wtab_power_grad(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, int32_t I_dtype,
+                                  const tm_c32* t, const tm_c32* v0, int32_t steps, const float* tab, int32_t nt,
+                                  float xmax, float* dtab, float* loss, void* stream) {
+  if (!c) return TM_EINVAL;
+  tmk::row_launcher fn;
+  int r = wtab_args(c, d, &fn, masks, I, I_dtype, t, v0, steps, nt, xmax);
+  if (r) return r;
+  if (!tab || !dtab || !loss) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  return wtab_grad(c, fn, d, masks, I, I_dtype == TM_BF16, t, v0, steps, tab, nt, xmax, dtab, loss, stream);
+}
+
+extern "C" int tm_wnet_train_step(tm_ctx* c, const tm_mlp_dims* md, const tm_mlp_params* p, tm_dims d,
+                                  const tm_c32* masks, const void* I, int32_t I_dtype, const tm_c32* t,
+                                  const tm_c32* v0, int32_t steps, int32_t nt, float xmax, float lr, int32_t step,
+                                  float* loss, void* stream) {
+  if (!c) return TM_EINVAL;
+  int r = wnet_check(c, md, p, nt, xmax, true);
+  if (r) return r;
+  tmk::row_launcher fn;
+  if ((r = wtab_args(c, d, &fn, masks, I, I_dtype, t, v0, steps, nt, xmax))) return r;
+  if (step < 1 || !(lr >= 0.f)) return fail(c, TM_EINVAL, "step >= 1, lr >= 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  tmk::MlpWork w;
+  if ((r = wnet_forward(c, md, p, nt, xmax, w, stream))) return r;
+  float* tab = (float*)ws_get(c, WS_PH_BASE + 39, (size_t)nt * 2 * sizeof(float));
+  float* dtab = (float*)ws_get(c, WS_PH_BASE + 40, (size_t)nt * sizeof(float));
+  if (!tab || !dtab) return fail(c, TM_ENOMEM, "table workspace");
+  int e = tmk::wnet_pairs(w.O, nt, tab, stream);
+  if (e) return hipfail(c, e, "table");
+  if ((r = wtab_grad(c, fn, d, masks, I, I_dtype == TM_BF16, t, v0, steps, tab, nt, xmax, dtab,
+                     loss ? loss : w.loss, stream)))
+    return r;
+  e = tmk::wnet_dout(dtab, nt, w.dOf, w.dOh, stream);
+  if (e) return hipfail(c, e, "output gradient");
+  return wnet_update(c, md, p, nt, w, lr, step, stream);
+}
+
+extern "C" int tm_set_weight_table(tm_ctx* c, const float* tab, int32_t nt, float xmax, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (nt < 2 || nt > TM_WTAB_MAX) return fail(c, TM_EINVAL, "table points %d outside 2..%d", nt, TM_WTAB_MAX);
+  if (!(xmax > 0.f) || !std::isfinite(xmax)) return fail(c, TM_EINVAL, "xmax must be > 0");
+  if (!tab) return fail(c, TM_EINVAL, "tab is NULL");
+  HIPCHK(c, hipSetDevice(c->device));
+  void* dst = ws_get(c, WS_WTAB, (size_t)nt * 2 * sizeof(float));
+  if (!dst) return fail(c, TM_ENOMEM, "table workspace");
+  int e = tmk::launch_copy(dst, tab, (int64_t)nt * 2 * sizeof(float), stream);
+  if (e) return hipfail(c, e, "table copy");
+  c->wtab_n = nt;
+  c->wtab_xmax = xmax;
+  return TM_OK;
+}
+
+extern "C" int tm_retrieve_learned(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32* t,
+                                   const tm_retrieve_opts* o, double rho_fallback, tm_row_stats* stats,
+                                   int32_t* n_fallback, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (!o) return fail(c, TM_EINVAL, "opts is NULL");
+  if (o->start != TM_START_LEARNED) return fail(c, TM_EINVAL, "opts->start must be TM_START_LEARNED");
+  if (!(rho_fallback >= 0.0)) return fail(c, TM_EINVAL, "rho_fallback must be >= 0");
+  if (!n_fallback) return fail(c, TM_EINVAL, "n_fallback is NULL");
+  *n_fallback = 0;
+  tmk::row_launcher fn;
+  int r = check_dims(c, d, &fn);
+  if (r) return r;
+  if (d.P == 0) return tm_retrieve(c, d, masks, I, t, o, stats, stream);
+  if (!masks || !I || !t) return fail(c, TM_EINVAL, "null pointer argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int N = d.n1 * d.n2;
+  const size_t row = (size_t)N * sizeof(tm_c32);
+  const size_t irow = (size_t)d.K * N * (o->I_dtype == TM_BF16 ? 2 : 4);
+  void* seed = ws_get(c, WS_PH_BASE + 41, (size_t)d.P * row);
+  tm_row_stats* st = stats ? stats : (tm_row_stats*)ws_get(c, WS_PH_BASE + 42, (size_t)d.P * sizeof(tm_row_stats));
+  int* idx = (int*)ws_get(c, WS_PH_BASE + 43, (size_t)(d.P + 1) * sizeof(int));
+  if (!seed || !st || !idx) return fail(c, TM_ENOMEM, "fallback workspace");
+  int e = tmk::launch_copy(seed, t, (int64_t)d.P * row, stream);
+  if (e) return hipfail(c, e, "seed copy");
+  if ((r = tm_retrieve(c, d, masks, I, t, o, st, stream))) return r;
+  // rows whose residual stays above rho_fallback are redone from the plain truncated start
+  int* count = idx + d.P;
+  if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
+  e = tmk::launch_fill_zero(count, sizeof(int), stream);
+  if (!e) e = tmk::launch_flag_rows(st, d.P, rho_fallback, idx, count, stream);
+  if (e) return hipfail(c, e, "flag rows");
+  HIPCHK(c, hipMemcpyAsync(c->pinned, count, sizeof(int), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+  const int nf = *(const int*)c->pinned;
+  *n_fallback = nf;
+  if (nf <= 0) return TM_OK;
+  char* tf = (char*)ws_get(c, WS_PH_BASE + 44, (size_t)nf * row);
+  char* If = (char*)ws_get(c, WS_PH_BASE + 45, (size_t)nf * irow);
+  tm_row_stats* stf = (tm_row_stats*)ws_get(c, WS_PH_BASE + 46, (size_t)nf * sizeof(tm_row_stats));
+  if (!tf || !If || !stf) return fail(c, TM_ENOMEM, "fallback workspace");
+  // BF16 rows are K N 2-byte values: gather them as 8-byte words when K N is a multiple of 4
+  if (irow % 8) return fail(c, TM_EUNSUPPORTED, "fallback rows of %zu bytes", irow);
+  e = tmk::launch_gather_rows(tf, seed, idx, nf, (int64_t)row, stream);
+  if (!e) e = tmk::launch_gather_rows(If, I, idx, nf, (int64_t)irow, stream);
+  if (e) return hipfail(c, e, "fallback gather");
+  tm_retrieve_opts fo = *o;
+  fo.start = TM_START_LANCZOS;
+  tm_dims df = d;
+  df.P = nf;
+  if ((r = tm_retrieve(c, df, masks, If, (tm_c32*)tf, &fo, stf, stream))) return r;
+  e = tmk::launch_select_rows(t, tf, st, stf, idx, nf, (int64_t)row, stream);
+  if (e) return hipfail(c, e, "fallback select");
   return TM_OK;
 }

@@ -1,7 +1,9 @@
-"""Learned start at N = 1024 (32 x 32 modes), K = 4, one fixed mask set:
-train on forward-model rows on the GPU, then compare on held-out rows with
-the plain (spectral-start) method. Records the measured gain; asserts the
-machinery (training lowers the loss, the fallback reaches fidelity 0.99)."""
+"""Learned start at N = 1024 (32 x 32 modes), K = 4, one fixed mask set: the
+weighting network of the spectral start is trained on the GPU on
+forward-model rows (CN(0, 1) rows, Poisson 1e4), then compared on held-out
+rows with the plain truncated start. Each form runs at its own cheapest
+(Lanczos steps, cyclic sweeps) that reaches mean fidelity 0.99 with at least
+99 % of the rows at 0.99; the learned form must be faster."""
 import time
 
 import numpy as np
@@ -14,9 +16,39 @@ from oracle import operators as ops
 from oracle import retrieval as rt
 from paper_2302_13524_amd import learned
 
-from gpu_util import c64, dev, f32
+from gpu_util import c64, device_intensities, oracle_intensities
 
 pytestmark = pytest.mark.gpu
+
+
+def _best(ctx, masks, I, seeds, T, n1, n2, start, ks=range(8, 21), sweeps=range(1, 11)):
+    """Cheapest (k + s, k, s) reaching the fidelity bar, searching k then s."""
+    best = None
+    for k in ks:
+        for s in sweeps:
+            if best is not None and k + s >= best[0]:
+                break
+            t = seeds.clone()
+            tm.tm_retrieve(ctx, masks, I, t, n1, n2, tm.retrieve_opts("er_cyclic", iters=s, start=start,
+                                                                       spectral_iters=k, spectral_tau=3.0),
+                           stats=False)
+            f = rt.fidelity(t.cpu().numpy().astype(np.complex128), T)
+            if f.mean() >= 0.99 and np.mean(f >= 0.99) >= 0.99:
+                best = (k + s, k, s)
+                break
+    return best
+
+
+def _time(fn, reps=20):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    return float(np.median(ts))
 
 
 def test_learned_start_gain():
@@ -25,49 +57,46 @@ def test_learned_start_gain():
     N, K, P = 1024, 4, 512
     masks_np = tm_synth.mask_phases(K, N, tm_synth.rng(4, 0))
     masks = c64(masks_np)
-    net = tm.MLP(K * N, 1024, 2 * N, seed=6)
     t0 = time.perf_counter()
-    hist = learned.train(ctx, net, masks, n1, n2, rows=200_000, epochs=2, batch=512, lr=1e-3, seed=6,
-                         log=lambda s: print(s, flush=True))
+    net, hist = learned.train_weights(ctx, masks, n1, n2, steps=150, rows=128, power_steps=20,
+                                      log=lambda s: print(s, flush=True))
+    learned.install_weights(ctx, net)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    # held-out rows (other seeds), Poisson 1e4
-    T = tm_synth.tm_iid(P, N, tm_synth.rng(40, 1))
-    I = ops.intensities(ops.FFTOp(masks_np, n1, n2), T)
-    I = tm_synth.poisson_counts(I, 1e4, tm_synth.rng(40, 2)).astype(np.float32)
-    It = f32(I)
-    seed_rows = c64(tm_synth.random_start(P, N, I.reshape(P, -1).sum(1) / (K * N * N), tm_synth.rng(40, 3)))
-    fid = lambda t: rt.fidelity(t.cpu().numpy().astype(np.complex128), T)
-    f_learned = fid(tm.tm_mlp_start(ctx, net, It, K, N)).mean()
-    f_random = fid(seed_rows).mean()
-    # plain form: spectral start + ER to mean fidelity 0.99
-    iters = 100
+    h = hist.cpu().numpy()
+    # held-out rows (other seeds) and their intensities by the oracle's forward model
+    T = tm_synth.tm_iid(P, N, tm_synth.rng(40, 1)).astype(np.complex64)
+    I, _ = device_intensities(tm_synth.poisson_counts(oracle_intensities(masks_np, T, n1, n2), 1e4,
+                                                      tm_synth.rng(40, 2)))
+    seeds = c64(tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(40, 3)))
+    T = T.astype(np.complex128)
+    bp = _best(ctx, masks, I, seeds, T, n1, n2, "lanczos")
+    bl = _best(ctx, masks, I, seeds, T, n1, n2, "learned")
+    assert bp is not None and bl is not None, (bp, bl)
 
-    def plain():
-        t = seed_rows.clone()
-        tm.tm_retrieve(ctx, masks, It, t, n1, n2, tm.retrieve_opts("er", iters=iters, start="spectral"))
+    def run(start, k, s):
+        t = seeds.clone()
+        tm.tm_retrieve(ctx, masks, I, t, n1, n2, tm.retrieve_opts("er_cyclic", iters=s, start=start,
+                                                                   spectral_iters=k, spectral_tau=3.0))
         return t
 
-    def learned_form():
-        return learned.retrieve_with_fallback(ctx, net, masks, It, n1, n2, iters, seed_rows)
+    def run_fallback():
+        t = seeds.clone()
+        _, nf = tm.tm_retrieve_learned(ctx, masks, I, t, n1, n2,
+                                       tm.retrieve_opts("er_cyclic", iters=bl[2], start="learned",
+                                                        spectral_iters=bl[1], spectral_tau=3.0))
+        return t, nf
 
-    tp = plain()
-    tl, redone = learned_form()
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    for _ in range(3):
-        plain()
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - a) / 3
-    a = time.perf_counter()
-    for _ in range(3):
-        learned_form()
-    torch.cuda.synchronize()
-    t_learned = (time.perf_counter() - a) / 3
-    fp, fl = fid(tp).mean(), fid(tl).mean()
-    print(f"train {train_s:.1f}s loss {hist}; start fidelity learned {f_learned:.5f} random {f_random:.5f}; "
-          f"rows redone from the fallback {redone}/{P}; final fidelity plain {fp:.5f} learned {fl:.5f}; "
-          f"wall plain {t_plain*1e3:.2f} ms learned {t_learned*1e3:.2f} ms")
-    assert np.all(np.isfinite(hist)) and hist[-1] <= hist[0]
-    assert fp >= 0.99 and fl >= 0.99
+    t_plain = _time(lambda: run("lanczos", bp[1], bp[2]))
+    t_learned = _time(lambda: run("learned", bl[1], bl[2]))
+    t_fb = _time(run_fallback)
+    tf, nf = run_fallback()
+    ff = rt.fidelity(tf.cpu().numpy().astype(np.complex128), T)
+    print(f"training {train_s:.1f}s, loss {h[:10].mean():.4f} -> {h[-10:].mean():.4f}; plain {bp[1]} Lanczos + "
+          f"{bp[2]} sweeps {t_plain * 1e3:.3f} ms; learned {bl[1]} + {bl[2]} {t_learned * 1e3:.3f} ms, with the "
+          f"fallback {t_fb * 1e3:.3f} ms ({nf} rows redone, mean fidelity {ff.mean():.5f})", flush=True)
+    assert h[-10:].mean() < h[:10].mean()
+    assert bl[0] < bp[0]
+    assert t_learned < t_plain
+    assert ff.mean() >= 0.99 and np.mean(ff >= 0.99) >= 0.99
     ctx.close()
