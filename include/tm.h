@@ -433,8 +433,11 @@ int tm_profile_enable(tm_ctx *ctx, int enable);
 /* Accumulated device time (milliseconds) and launch count of the fused row
  * kernel of kind `mode` (0 forward field, 1 forward intensity, 2 adjoint,
  * 3 error reduction, 4 gradient, 5 spectral step, 6 line-search sums,
- * 7 FP64 residual, 8 back-propagation) since enabling. Synchronises the
- * context's device. */
+ * 7 FP64 residual, 8 back-propagation, 9 amplitude gradient, 10 amplitude
+ * line sums, 11 filter, 12 cyclic error reduction, 13 Lanczos step, 14
+ * Lanczos step with learned weights, 15/16 weight-network training), or of the
+ * L-BFGS direction (20: its three kernels together) and step (21), since
+ * enabling; mode < 24. Synchronises the context's device. */
 int tm_profile_query(tm_ctx *ctx, int mode, double *ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------

@@ -28,6 +28,8 @@
 #include "row_kernels.hpp"
 #include "wnet.hpp"
 
+constexpr int TM_PROF_MODES = 24;  // row-kernel modes 0..16, 20 L-BFGS direction, 21 L-BFGS step
+
 struct tm_ctx {
   int device = 0;
   std::string err;
@@ -46,8 +48,8 @@ struct tm_ctx {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  double acc_ms[16] = {0};
-  int64_t acc_n[16] = {0};
+  double acc_ms[TM_PROF_MODES] = {0};
+  int64_t acc_n[TM_PROF_MODES] = {0};
   std::map<int, int> variant;  // (L1 << 8 | L2) -> FFT digit-order variant
   double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
   rocblas_handle blas = nullptr;  // plain complex GEMM of the foci synthesis
@@ -192,7 +194,7 @@ void prof_drain(tm_ctx* c) {
   for (auto& r : c->recs) {
     hipEventSynchronize(r.b);
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.mode >= 0 && r.mode < 16) {
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.mode >= 0 && r.mode < TM_PROF_MODES) {
       c->acc_ms[r.mode] += ms;
       c->acc_n[r.mode] += 1;
     }
@@ -217,6 +219,21 @@ int run_row(tm_ctx* c, tmk::row_launcher fn, int mode, int ibf16, const tmk::Row
   }
   if (e) return hipfail(c, e, "row kernel launch");
   return TM_OK;
+}
+
+// Event timing of the L-BFGS kernels (run_lbfgs calls these around its launches).
+void lb_prof_begin(void* user, int mode, void* stream) {
+  tm_ctx* c = (tm_ctx*)user;
+  if (!c->prof) return;
+  if (c->recs.size() > 4096) prof_drain(c);
+  hipEvent_t ea = ev_get(c), eb = ev_get(c);
+  hipEventRecord(ea, (hipStream_t)stream);
+  c->recs.push_back({mode, ea, eb});
+}
+void lb_prof_end(void* user, int mode, void* stream) {
+  tm_ctx* c = (tm_ctx*)user;
+  if (!c->prof || c->recs.empty() || c->recs.back().mode != mode) return;
+  hipEventRecord(c->recs.back().b, (hipStream_t)stream);
 }
 
 }  // namespace
@@ -580,8 +597,12 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     b.S = ws_get(c, WS_LB_S, vec * tmk::LB_SLOTS(o->lbfgs_m));
     b.Y = ws_get(c, WS_LB_Y, vec * tmk::LB_SLOTS(o->lbfgs_m));
     b.sc = ws_get(c, WS_LB_SC, (size_t)d.P * tmk::LB_SCALARS(o->lbfgs_m) * sizeof(double));
-    if (!b.g || !b.gp || !b.d || !b.S || !b.Y || !b.sc) return fail(c, TM_ENOMEM, "L-BFGS workspace");
+    b.dots = ws_get(c, WS_PH_BASE + 48, (size_t)d.P * tmk::LB_DOTS(N) * sizeof(double));
+    if (!b.g || !b.gp || !b.d || !b.S || !b.Y || !b.sc || !b.dots) return fail(c, TM_ENOMEM, "L-BFGS workspace");
     b.sums = sums;
+    b.hook_user = c;
+    b.hook_begin = lb_prof_begin;
+    b.hook_end = lb_prof_end;
     const int amp = o->method == TM_METHOD_LBFGS_AMP;
     int e = tmk::run_lbfgs(fn, a, ibf, N, o->iters, o->lbfgs_m, tt, b, stream, amp);
     if (e) return hipfail(c, e, "L-BFGS");
@@ -882,7 +903,7 @@ extern "C" int tm_profile_enable(tm_ctx* c, int enable) {
   if (!c) return TM_EINVAL;
   hipSetDevice(c->device);
   prof_drain(c);
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < TM_PROF_MODES; ++i) {
     c->acc_ms[i] = 0;
     c->acc_n[i] = 0;
   }
@@ -892,7 +913,7 @@ extern "C" int tm_profile_enable(tm_ctx* c, int enable) {
 
 extern "C" int tm_profile_query(tm_ctx* c, int mode, double* ms, int64_t* launches) {
   if (!c || !ms || !launches) return TM_EINVAL;
-  if (mode < 0 || mode >= 16) return fail(c, TM_EINVAL, "mode %d", mode);
+  if (mode < 0 || mode >= TM_PROF_MODES) return fail(c, TM_EINVAL, "mode %d", mode);
   hipSetDevice(c->device);
   prof_drain(c);
   *ms = c->acc_ms[mode];
