@@ -172,21 +172,22 @@ struct PlanDesc {
   PassDesc p[8];
 };
 
-// digits (log2 radices) of a length 2^b axis, most significant first
-constexpr int ndigits(int b) { return b == 0 ? 0 : (b <= 4 ? 1 : (b <= 8 ? 2 : (b <= 12 ? 3 : 4))); }
-// Split b bits into ndigits(b) digits of 1..4 bits; variant 0 puts the
+// digits (log2 radices) of a length 2^b axis, most significant first, each
+// of at most mb bits (a thread holds a whole radix-2^mb butterfly)
+constexpr int ndigits(int b, int mb = 4) { return b == 0 ? 0 : (b + mb - 1) / mb; }
+// Split b bits into ndigits(b, mb) digits of 1..mb bits; variant 0 puts the
 // larger digits first (most significant), variant 1 the smaller ones.
-constexpr int digit_bits(int b, int i, int var = 0) {
-  int n = ndigits(b);
+constexpr int digit_bits(int b, int i, int var = 0, int mb = 4) {
+  int n = ndigits(b, mb);
   int base = b / n, extra = b % n;
   int j = var ? (n - 1 - i) : i;
   return base + (j < extra ? 1 : 0);
 }
 
-constexpr PlanDesc make_plan(int L1, int L2, int var) {
+constexpr PlanDesc make_plan(int L1, int L2, int var, int mb = 4) {
   PlanDesc d{};
   d.np = 0;
-  int n1d = ndigits(L1), n2d = ndigits(L2);
+  int n1d = ndigits(L1, mb), n2d = ndigits(L2, mb);
   int lb1 = L1, lb2 = L2;
   auto push = [&](int axis, int bits) {
     int& lb = (axis == 1) ? lb1 : lb2;
@@ -197,9 +198,9 @@ constexpr PlanDesc make_plan(int L1, int L2, int var) {
     d.np++;
   };
   int i1 = 0;
-  if (n1d >= 2) { push(1, digit_bits(L1, 0, var)); i1 = 1; }
-  for (int i = 0; i < n2d; ++i) push(2, digit_bits(L2, i, var));
-  for (int i = i1; i < n1d; ++i) push(1, digit_bits(L1, i, var));
+  if (n1d >= 2) { push(1, digit_bits(L1, 0, var, mb)); i1 = 1; }
+  for (int i = 0; i < n2d; ++i) push(2, digit_bits(L2, i, var, mb));
+  for (int i = i1; i < n1d; ++i) push(1, digit_bits(L1, i, var, mb));
   return d;
 }
 
@@ -214,10 +215,11 @@ struct Plan {
   static constexpr int LN = L1 + L2;
   static constexpr int N1 = 1 << L1, N2 = 1 << L2, N = 1 << LN;
   static constexpr int LE = (LE_ >= 0) ? LE_ : default_le(LN);
+  static constexpr int MB = LE < 4 ? (LE > 0 ? LE : 1) : 4;  // largest digit, bits
   static constexpr int E = 1 << LE;
   static constexpr int LT = LN - LE;
   static constexpr int T = 1 << LT;  // threads per row
-  static constexpr PlanDesc desc = make_plan(L1, L2, VAR_);
+  static constexpr PlanDesc desc = make_plan(L1, L2, VAR_, MB);
   static constexpr int NP = desc.np;
   // LDS: row-major grid with one pad slot after every n2 slots (n2 >= 16)
   static constexpr int PADSH = (L2 >= 4) ? L2 : 30;
@@ -497,13 +499,13 @@ __device__ __forceinline__ void fft_inverse(cx<T>* x, Xbuf<T>& xb, int ltid, con
 
 // Digit reversal of one axis: slot index s (digits high to low as laid out by
 // the DIF passes) -> frequency index k = d_0 + R_0 d_1 + R_0 R_1 d_2 + ...
-template <int LA, int VAR>
+template <int LA, int VAR, int MB = 4>
 __device__ __forceinline__ int digit_rev(int s) {
-  constexpr int nd = ndigits(LA);
+  constexpr int nd = ndigits(LA, MB);
   int k = 0, shift_out = 0, rem = LA;
 #pragma unroll
   for (int i = 0; i < nd; ++i) {
-    int b = digit_bits(LA, i, VAR);
+    int b = digit_bits(LA, i, VAR, MB);
     rem -= b;
     int d = (s >> rem) & ((1 << b) - 1);
     k |= d << shift_out;
@@ -516,7 +518,7 @@ __device__ __forceinline__ int digit_rev(int s) {
 template <class PL>
 __device__ __forceinline__ int spectrum_index(int e) {
   int s1 = e >> PL::L2, s2 = e & (PL::N2 - 1);
-  return (digit_rev<PL::L1, PL::VAR>(s1) << PL::L2) | digit_rev<PL::L2, PL::VAR>(s2);
+  return (digit_rev<PL::L1, PL::VAR, PL::MB>(s1) << PL::L2) | digit_rev<PL::L2, PL::VAR, PL::MB>(s2);
 }
 
 template <class PL>
