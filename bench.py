@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--learned-rho-fallback", type=float, default=0.0,
                     help="FP64 residual above which a row of the learned form is redone from the plain start in the "
                          "timed learned form (0: no fallback; the fallback forms are reported as variants)")
+    ap.add_argument("--profile-lbfgs", type=int, default=0, metavar="ITERS",
+                    help="only run one L-BFGS retrieval of ITERS iterations on the workload (for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
@@ -119,15 +121,16 @@ def parse():
 
 
 KERNEL_SOURCES = ["fft_core.hpp", "row_kernels.hpp", "grid_inst.hip", "grids.hpp"]
+LBFGS_SOURCES = ["lbfgs_kernels.hip", "lbfgs.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2286x8192.json")
 
 
-def sources_digest():
-    """SHA-256 over the fused row kernels' sources: counter-measured traffic is
-    used only while these are unchanged."""
+def sources_digest(files=None):
+    """SHA-256 over the kernels' sources (default: the fused row kernels):
+    counter-measured traffic is used only while these are unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files or KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2302_13524_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -141,11 +144,14 @@ def measured_traffic(P, N):
         return None
     with open(TRAFFIC_FILE) as fh:
         d = json.load(fh)
-    if d.get("sources_sha256") != sources_digest() or d.get("P") != P or d.get("N") != N:
+    if d.get("P") != P or d.get("N") != N:
         return None
     fs = d["copy"]["bytes"] / 1024 / d["copy"]["fetch_kib"]
     ws = d["copy"]["bytes"] / 1024 / d["copy"]["write_kib"]
-    return {k: int(round((v["fetch_kib"] * fs + v["write_kib"] * ws) * 1024)) for k, v in d["kernels"].items()}
+    ok = {"row": d.get("sources_sha256") == sources_digest(),
+          "lbfgs": d.get("lbfgs_sources_sha256") == sources_digest(LBFGS_SOURCES)}
+    return {k: int(round((v["fetch_kib"] * fs + v["write_kib"] * ws) * 1024)) for k, v in d["kernels"].items()
+            if ok["lbfgs" if k.startswith("lbfgs") else "row"]}
 
 
 def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
@@ -174,6 +180,7 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
     cf, cw = per_kernel(copy_fetch_dir, "FETCH_SIZE"), per_kernel(copy_write_dir, "WRITE_SIZE")
     big = max(cf, key=lambda k: cf[k][0])
     res = {"P": 2286, "N": 8192, "sources_sha256": sources_digest(),
+           "lbfgs_sources_sha256": sources_digest(LBFGS_SOURCES),
            "copy": {"kernel": big, "bytes": 512 * 2**20, "fetch_kib": cf[big][0], "write_kib": cw[big][0]},
            "kernels": {}}
     for key, mode in (("spectral", 5), ("er", 3), ("er_cyclic", 12), ("lanczos", 13)):
@@ -182,9 +189,54 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
         fv, fn = pick(f, mode)
         wv, wn = pick(w, mode)
         res["kernels"][key] = {"fetch_kib": fv, "write_kib": wv, "dispatches": [fn, wn]}
+
+    def pick_name(tab, frag):
+        keys = [k for k in tab if frag in k]
+        vals = [tab[k] for k in keys]
+        n = sum(c for _, c in vals)
+        return (sum(v * c for v, c in vals) / n, n) if n else (None, 0)
+
+    # the L-BFGS kernels (one --profile-lbfgs run: iterations with 0..m stored pairs, as in the timed leg)
+    lb = {}
+    for key, frag in (("lbfgs_dots", "k_dir_dots"), ("lbfgs_apply", "k_dir_apply"), ("lbfgs_step", "k_step<")):
+        fv, fn = pick_name(f, frag)
+        wv, wn = pick_name(w, frag)
+        if fv is not None and wv is not None:
+            lb[key] = {"fetch_kib": fv, "write_kib": wv, "dispatches": [fn, wn]}
+    if "lbfgs_dots" in lb and "lbfgs_apply" in lb:
+        lb["lbfgs_direction"] = {k: lb["lbfgs_dots"][k] + lb["lbfgs_apply"][k] for k in ("fetch_kib", "write_kib")}
+        lb["lbfgs_direction"]["dispatches"] = lb["lbfgs_dots"]["dispatches"]
+    res["kernels"].update(lb)
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res))
+
+
+def profile_lbfgs(iters):
+    """One L-BFGS retrieval (Alg. 1, memory 5) of `iters` iterations on the
+    benchmark workload from a spectral start, nothing else: the dispatch
+    sequence the counter runs of the L-BFGS kernels read."""
+    import torch
+
+    import paper_2302_13524_amd as tm
+    import tm_synth
+
+    dev = torch.device("cuda:0")
+    n1, n2, P, grid, pupil, K = 128, 64, 2286, 64, 0.22, 4
+    N = n1 * n2
+    pix = tm_synth.nearest_pixels(grid, P)
+    masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
+    T = tm_synth.speckle_tm(N, grid, pupil, pix, tm_synth.rng(3, 1)).astype(np.complex64)
+    v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(3, 3)).astype(np.complex64)
+    ctx = tm.Context(0)
+    mk = torch.from_numpy(masks.astype(np.complex64)).to(dev)
+    I = tm.tm_forward(ctx, mk, torch.from_numpy(T).to(dev), n1, n2, intensity=True)
+    t = torch.from_numpy(v0).to(dev)
+    tm.tm_retrieve(ctx, mk, I, t, n1, n2, tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=17))
+    tm.tm_retrieve(ctx, mk, I, t, n1, n2, tm.retrieve_opts("lbfgs", iters=iters, lbfgs_m=5), stats=False)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"profile_lbfgs_iters": iters}))
 
 
 def copy_probe():
@@ -204,6 +256,9 @@ def main():
         return
     if args.copy_probe:
         copy_probe()
+        return
+    if args.profile_lbfgs:
+        profile_lbfgs(args.profile_lbfgs)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); rows are independent problems, so "
@@ -393,10 +448,12 @@ def main():
         d_avg = d_ms / max(d_n, 1)
         s_avg = s_ms / max(s_n, 1)
         gbs = dbytes / (d_avg * 1e-3) / 1e9
+        tr_all = measured_traffic(P, N)
+        tr_lb = tr_all.get("lbfgs_direction") if tr_all else None
         roofline_lbfgs = {
             "bound": "hbm", "kernel": "L-BFGS direction (k_dir_dots + k_dir_solve + k_dir_apply, compact form, m = 5)",
             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_launch_ms": round(d_avg, 5), "launches": d_n,
+            "traffic": tr_lb, "avg_launch_ms": round(d_avg, 5), "launches": d_n,
             "alg_bytes_per_launch": int(dbytes), "alg_bytes_full_history": int(full),
             "step_kernel": {"avg_launch_ms": round(s_avg, 5), "launches": s_n, "alg_bytes_per_launch": 4 * 8 * N * P,
                             "achieved_GBps": round(4 * 8 * N * P / (s_avg * 1e-3) / 1e9, 1)},
@@ -510,7 +567,7 @@ def main():
     if not args.no_learned:
         out["learned"] = learned_variant(args, ctx, mk, It, v0t, n1, n2, sp, n_er, fidelity, ret_ms, P)
     if not args.no_batch and not args.small:
-        out["batch"] = batch_variant(ctx, args)
+        out["batch"] = batch_variant(ctx, args, pool)
     if not args.no_preprocess and not args.small:
         out["preprocess"] = preprocess_variant(ctx, args)
     if pool is not None:
@@ -773,9 +830,13 @@ def preprocess_variant(ctx, args):
     return out
 
 
-def batch_variant(ctx, args):
+def batch_variant(ctx, args, pool=None):
     """Twelve TMs of uneven (N, P) in one persistent launch per iteration under
-    a captured HIP graph, BF16 intensities, digit order autotuned per grid."""
+    a captured HIP graph, BF16 intensities, digit order autotuned per grid.
+    With the host workers (pool), the intensities come from the oracle's
+    forward model and a seeded sample of rows of every TM is retrieved by the
+    FP64 oracle from the same BF16-rounded values, so that each TM reports
+    its fidelity against the oracle's rows."""
     import torch
 
     import paper_2302_13524_amd as tm
@@ -791,7 +852,13 @@ def batch_variant(ctx, args):
         masks = torch.from_numpy(tm_synth.mask_phases(4, N, tm_synth.rng(cid, 0)).astype(np.complex64)).to(dev)
         pix = tm_synth.nearest_pixels(grid, P)
         T = torch.from_numpy(tm_synth.speckle_tm(N, grid, 0.22, pix, tm_synth.rng(cid, 1)).astype(np.complex64)).to(dev)
-        Ic = tm.tm_forward(ctx, masks, T, n1, n2, intensity=True).cpu().numpy().astype(np.float64)
+        if pool is not None:
+            mk_np = masks.cpu().numpy()
+            Ic = np.concatenate(list(pool.map(_oracle_intensities, [(mk_np.astype(np.complex128), n1, n2,
+                                                                      T.cpu().numpy()[a0:b0])
+                                                                     for a0, b0 in _cpu_chunks(P, pool.n_workers)])))
+        else:
+            Ic = tm.tm_forward(ctx, masks, T, n1, n2, intensity=True).cpu().numpy().astype(np.float64)
         I = tm_synth.poisson_counts(Ic, 1e4, tm_synth.rng(cid, 2))
         Ib = torch.from_numpy(I.astype(np.float32)).to(dev).to(torch.bfloat16)
         seed = torch.from_numpy(tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(cid, 3)).astype(np.complex64)).to(dev)
@@ -828,11 +895,28 @@ def batch_variant(ctx, args):
         ms += (time.perf_counter() - a) * 1e3 / reps
     rows = sum(P for _, _, P, _ in shapes)
     per_tm = []
-    for p, Tn in zip(probs, truths):
+    jobs = []
+    for i, (p, Tn) in enumerate(zip(probs, truths)):
         c = torch.sum(torch.conj(p["t"]) * Tn, dim=1)
         f = (c.abs() ** 2 / torch.sum(p["t"].abs() ** 2, dim=1)).double()
         per_tm.append({"grid": f"{p['n1']}x{p['n2']}", "P": p["t"].shape[0], "mean_fidelity": round(f.mean().item(), 5),
                        "rows_flagged": int((tm.decode_stats(p["stats"]).flags.numpy() & 1).sum())})
+        if pool is not None:
+            # a seeded sample of rows through the oracle's same pipeline, from the same BF16 values
+            P = p["t"].shape[0]
+            rows_s = np.sort(np.random.default_rng(900 + i).choice(P, 8, replace=False))
+            Iv = p["I"].float().cpu().numpy()[rows_s].astype(np.float64)
+            jobs.append((i, rows_s, pool.submit(_oracle_retrieve, (
+                p["masks"].cpu().numpy().astype(np.complex128), p["n1"], p["n2"], Iv,
+                p["seed"].cpu().numpy()[rows_s].astype(np.complex128), args.batch_start, sp, args.batch_spectral_tau,
+                args.spectral_momentum, args.spectral_lower, args.solver, iters, beta))))
+    for i, rows_s, fut in jobs:
+        from oracle import retrieval as rt
+        t_or, _ = fut.result()
+        got = probs[i]["t"].cpu().numpy()[rows_s].astype(np.complex128)
+        fo = rt.fidelity(got, t_or)
+        per_tm[i]["sampled_rows"] = len(rows_s)
+        per_tm[i]["gpu_vs_oracle_1_minus_fidelity_max"] = float(np.max(1 - fo))
     b.close()
     return {"rows_per_s": round(rows / (ms * 1e-3), 1), "ms": round(ms, 3), "rows": rows, "tms": len(shapes),
             "solver": args.solver, "start": args.batch_start, "iters": iters, "er_momentum": beta,

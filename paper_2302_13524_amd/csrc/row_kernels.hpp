@@ -328,6 +328,17 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), mv[i]);
+      } else if constexpr (MODE == M_ERC) {
+        // each mask's values (and below its intensities) are loaded together
+        // before their first use: where this body is not inlined (the uneven
+        // batch) the compiler otherwise loaded and waited for them one at a
+        // time (batch cyclic sweep 2.60 -> 1.64 ms)
+        C mvals[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) mvals[i] = gload(mk + E0(i));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), mvals[i]);
       } else {
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), gload(mk + E0(i)));
@@ -419,10 +430,17 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       }
       if constexpr (MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_SPEC || MODE == M_LANCZOS ||
                     MODE == M_AGRAD || MODE == M_LANCZOS_T || MODE == M_WAPPLY) {
+        float ierc[MODE == M_ERC ? E : 1];  // cyclic ER: the intensities loaded together
+        if constexpr (MODE == M_ERC) {
+#pragma unroll
+          for (int i = 0; i < E; ++i) ierc[i] = load_I<IT>(a.I, mbase + KL(i));
+          __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           float iv;
           if constexpr (PF) iv = icur[i];
+          else if constexpr (MODE == M_ERC) iv = ierc[i];
           else iv = load_I<IT>(a.I, mbase + KL(i));
           float n = norm2(x[i]);
           if constexpr (MODE == M_ER || MODE == M_ERC) {
@@ -477,7 +495,10 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         // this mask's projection replaces the row before the next mask
         const float inv_n = 1.f / (float)N;
 #pragma unroll
-        for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], gload(mk + E0(i))), inv_n);
+        for (int i = 0; i < E; ++i) g[i] = gload(mk + E0(i));  // g is free in this mode: the mask values
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], g[i]), inv_n);
       } else {
 #pragma unroll
         for (int i = 0; i < E; ++i) {

@@ -16,6 +16,8 @@ LZ = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 13, float, true>(tmk::RowArgs
 ERC = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 12, float, false>(tmk::RowArgs)"
 ERC_S = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 12, float, true>(tmk::RowArgs)"
 COPY = "__amd_rocclr_copyBuffer"
+DOTS = "tmk::(anonymous namespace)::k_dir_dots(tmk::(anonymous namespace)::LbArgs, double*)"
+APPLY = "tmk::(anonymous namespace)::k_dir_apply(tmk::(anonymous namespace)::LbArgs)"
 
 
 def test_more_than_one_gpu_is_refused():
@@ -36,8 +38,10 @@ def _counters(d, counter, rows):
 
 def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, monkeypatch):
     f, w, cf, cw = (str(tmp_path / s) for s in ("f", "w", "cf", "cw"))
-    _counters(f, "FETCH_SIZE", [(LZ, 100.0), (LZ, 200.0), (ERC, 40.0), (ERC_S, 60.0), (ERC, 40.0)])
-    _counters(w, "WRITE_SIZE", [(LZ, 50.0), (LZ, 50.0), (ERC, 30.0), (ERC_S, 30.0), (ERC, 30.0)])
+    _counters(f, "FETCH_SIZE", [(LZ, 100.0), (LZ, 200.0), (ERC, 40.0), (ERC_S, 60.0), (ERC, 40.0), (DOTS, 10.0),
+                                (APPLY, 20.0)])
+    _counters(w, "WRITE_SIZE", [(LZ, 50.0), (LZ, 50.0), (ERC, 30.0), (ERC_S, 30.0), (ERC, 30.0), (DOTS, 1.0),
+                                (APPLY, 2.0)])
     # a 512 MiB copy reads as half its size on the fetch counter, its size on the write counter
     _counters(cf, "FETCH_SIZE", [(COPY, 262144.0), (COPY, 262144.0), ("small", 1.0)])
     _counters(cw, "WRITE_SIZE", [(COPY, 524288.0), (COPY, 524288.0), ("small", 1.0)])
@@ -53,9 +57,16 @@ def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, mon
     t = bench.measured_traffic(2286, 8192)
     assert t["lanczos"] == (150 * 2 + 50 * 1) * 1024
     assert bench.measured_traffic(2286, 4096) is None
+    # the L-BFGS direction is its two streaming kernels together
+    assert t["lbfgs_direction"] == ((10 + 20) * 2 + (1 + 2) * 1) * 1024
+    # each figure is dropped once the sources it was taken on change
     d["sources_sha256"] = "0" * 64
     json.dump(d, open(out, "w"))
-    assert bench.measured_traffic(2286, 8192) is None
+    t = bench.measured_traffic(2286, 8192)
+    assert "lanczos" not in t and "lbfgs_direction" in t
+    d["lbfgs_sources_sha256"] = "0" * 64
+    json.dump(d, open(out, "w"))
+    assert bench.measured_traffic(2286, 8192) == {}
 
 
 def test_sources_digest_is_stable():

@@ -168,7 +168,8 @@ def test_er_cyclic_sweeps(ctx, n1, n2, P):
         ref = rt.er_cyclic(m, n1, n2, Ir, t, iters)
         tt = c64(t0)
         raw = tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("er_cyclic", iters=iters))
-        assert relerr(tt.cpu().numpy(), ref) < OPTOL * iters, iters
+        # a sweep is K = 4 projections in sequence, each a transform pair held to OPTOL
+        assert relerr(tt.cpu().numpy(), ref) < OPTOL * 4 * iters, iters
         prev = rt.er_cyclic(m, n1, n2, Ir, t, iters - 1)
         sa, si = rt.er_cyclic_sweep_sums(m, n1, n2, Ir, prev)
         st = tm.decode_stats(raw)
