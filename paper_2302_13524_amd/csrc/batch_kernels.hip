@@ -41,7 +41,7 @@ constexpr int kLds = cmax(cmax(lds_of<Plan<5, 5>>(), lds_of<Plan<6, 5>>()), cmax
 // allocation instead of the union of all of them.
 template <class PL, int M, typename IT, bool SUMS>
 __device__ __attribute__((noinline)) void item_body(const RowArgs& a, int blk, cx<float>* lds, float* red) {
-  row_body<PL, M, IT, SUMS, BATCH_WG>(a, blk, lds, red);
+  row_body<PL, M, IT, SUMS, BATCH_WG, true>(a, blk, lds, red);
 }
 
 template <int MODE, typename IT, bool SUMS>

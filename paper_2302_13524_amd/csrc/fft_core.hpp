@@ -33,14 +33,19 @@ template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
 __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// The sums of two products name the product that is fused: left to the
+// compiler, the choice can follow where the code sits (an inlined kernel and
+// the same body called out of line rounded differently).
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return {fmadd(a.x, b.x, -(a.y * b.y)), fmadd(a.x, b.y, a.y * b.x)};
 }
 // a * conj(b)
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+  return {fmadd(a.x, b.x, a.y * b.y), fmadd(a.y, b.x, -(a.x * b.y))};
 }
 template <typename T>
 __device__ __forceinline__ cx<T> scl(cx<T> a, T s) { return {a.x * s, a.y * s}; }
@@ -51,7 +56,7 @@ __device__ __forceinline__ cx<T> mulmj(cx<T> a) {
   else return {a.y, -a.x};
 }
 template <typename T>
-__device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ T norm2(cx<T> a) { return fmadd(a.x, a.x, a.y * a.y); }
 
 // ------------------------------------------------------- small DFT kernels
 // In place, natural order in and out. Forward: V[k] = sum v[h] W^{hk},

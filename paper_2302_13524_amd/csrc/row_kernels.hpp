@@ -218,7 +218,12 @@ __device__ __forceinline__ float wtab_eval(const RowArgs& a, float x) {
 // Body of the fused kernel for the rows [blk * RPW, (blk + 1) * RPW) of one
 // problem, run by a workgroup of WGT threads with LDS at lds_all (at least
 // Launch<PL, WGT>::LDS_ELEMS elements) and red (RED_FLOATS floats).
-template <class PL, int MODE, typename IT, bool SUMS, int WGT>
+// OOL: the body is called out of line (the uneven batch). The cyclic ER step
+// then issues each mask's values and intensities together before their first
+// use: there the compiler otherwise loaded and waited for them one at a time
+// (batch sweep over 12 problems 2.60 -> 1.65 ms), while in the inlined kernel
+// the same order costs 5 % (its own schedule overlaps them already).
+template <class PL, int MODE, typename IT, bool SUMS, int WGT, bool OOL = false>
 __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>* lds_all, float* red) {
   // Every buffer is in device global memory: the accesses below go through
   // global-address-space pointers, so that where this body is not inlined into
@@ -328,11 +333,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = cmul(TROW(i), mv[i]);
-      } else if constexpr (MODE == M_ERC) {
-        // each mask's values (and below its intensities) are loaded together
-        // before their first use: where this body is not inlined (the uneven
-        // batch) the compiler otherwise loaded and waited for them one at a
-        // time (batch cyclic sweep 2.60 -> 1.64 ms)
+      } else if constexpr (MODE == M_ERC && OOL) {
         C mvals[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) mvals[i] = gload(mk + E0(i));
@@ -430,8 +431,8 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       }
       if constexpr (MODE == M_ER || MODE == M_ERC || MODE == M_GRAD || MODE == M_SPEC || MODE == M_LANCZOS ||
                     MODE == M_AGRAD || MODE == M_LANCZOS_T || MODE == M_WAPPLY) {
-        float ierc[MODE == M_ERC ? E : 1];  // cyclic ER: the intensities loaded together
-        if constexpr (MODE == M_ERC) {
+        float ierc[MODE == M_ERC && OOL ? E : 1];  // the intensities loaded together (OOL)
+        if constexpr (MODE == M_ERC && OOL) {
 #pragma unroll
           for (int i = 0; i < E; ++i) ierc[i] = load_I<IT>(a.I, mbase + KL(i));
           __builtin_amdgcn_sched_barrier(0);
@@ -440,7 +441,7 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         for (int i = 0; i < E; ++i) {
           float iv;
           if constexpr (PF) iv = icur[i];
-          else if constexpr (MODE == M_ERC) iv = ierc[i];
+          else if constexpr (MODE == M_ERC && OOL) iv = ierc[i];
           else iv = load_I<IT>(a.I, mbase + KL(i));
           float n = norm2(x[i]);
           if constexpr (MODE == M_ER || MODE == M_ERC) {
@@ -494,11 +495,16 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
       if constexpr (MODE == M_ERC) {
         // this mask's projection replaces the row before the next mask
         const float inv_n = 1.f / (float)N;
+        if constexpr (OOL) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) g[i] = gload(mk + E0(i));  // g is free in this mode: the mask values
-        __builtin_amdgcn_sched_barrier(0);
+          for (int i = 0; i < E; ++i) g[i] = gload(mk + E0(i));  // g is free in this mode: the mask values
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], g[i]), inv_n);
+          for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], g[i]), inv_n);
+        } else {
+#pragma unroll
+          for (int i = 0; i < E; ++i) treg[i] = scl(cmulc(x[i], gload(mk + E0(i))), inv_n);
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
