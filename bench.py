@@ -121,7 +121,7 @@ def parse():
 
 
 KERNEL_SOURCES = ["fft_core.hpp", "row_kernels.hpp", "grid_inst.hip", "grids.hpp"]
-LBFGS_SOURCES = ["lbfgs_kernels.hip", "lbfgs.hpp"]
+LBFGS_SOURCES = ["lbfgs_kernels.hip", "lbfgs.hpp", "row_kernels.hpp", "fft_core.hpp", "grids.hpp"]  # with what it includes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2286x8192.json")
 
 
