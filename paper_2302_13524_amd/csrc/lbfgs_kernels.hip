@@ -47,31 +47,78 @@ __device__ __forceinline__ void ts_add(float& s, float& c, float v) {
   s = t;
 }
 
-// Block-wide compensated sum of NS values over WG threads; returns the totals in every thread.
+// Merge of two compensated values (TwoSum: t + err is exactly a + b).
+__device__ __forceinline__ void ts_merge(float& s, float& c, float s2, float c2) {
+  const float t = s + s2, bp = t - s;
+  c = (c + c2) + ((s - (t - bp)) + (s2 - bp));
+  s = t;
+}
+
+// Block-wide compensated sums of NS values over WG threads; thread i < nout
+// writes the i-th total to out[i]. Within a wave, lane bits 5 and 4 first
+// scatter the values: v_permlane32_swap / v_permlane16_swap exchange the upper
+// half of one value's lanes with the lower half of another's, so after one
+// swap and one add each lane holds half of the values, summed over its partner
+// lane (no per-lane selects); the values left are then added over lane bits
+// 3 .. 0 by shuffles. A wave thus exchanges about NS / 2 + 2 NS / 4 ... values
+// instead of 6 NS. The waves' totals meet in FP64 in wave order.
 template <int NS, int WG = LWG>
-__device__ __forceinline__ void block_sums(float* s, float* c, float* red, double* out) {
+__device__ __forceinline__ void block_sums(const float* s, const float* c, float* red, double* out, int nout) {
+  constexpr int LB = NS <= 1 ? 0 : NS <= 2 ? 1 : NS <= 4 ? 2 : NS <= 8 ? 3 : NS <= 16 ? 4 : 5;
+  constexpr int NP = 1 << LB;
+  constexpr int SW = LB < 2 ? LB : 2;  // swap steps (lane bits 5, then 4)
+  constexpr int NR = NP >> SW;         // values a lane holds after them
+  static_assert(NS <= 32, "at most 32 sums");
+  float vs[NP], vc[NP];
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+  for (int i = 0; i < NP; ++i) {
+    vs[i] = i < NS ? s[i] : 0.f;
+    vc[i] = i < NS ? c[i] : 0.f;
+  }
+  if constexpr (SW >= 1) {
+    // lanes 0-31 keep value i and add lane l + 32's; lanes 32-63 keep value i + NP/2 and add lane l - 32's
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      float s2 = __shfl_xor(s[i], off, 64), c2 = __shfl_xor(c[i], off, 64);
-      float t = s[i] + s2, bp = t - s[i];
-      c[i] += c2 + (s[i] - (t - bp)) + (s2 - bp);
-      s[i] = t;
+    for (int i = 0; i < NP / 2; ++i) {
+      auto ps = __builtin_amdgcn_permlane32_swap(__float_as_uint(vs[i]), __float_as_uint(vs[i + NP / 2]), false, false);
+      auto pc = __builtin_amdgcn_permlane32_swap(__float_as_uint(vc[i]), __float_as_uint(vc[i + NP / 2]), false, false);
+      vs[i] = __uint_as_float(ps[0]);
+      vc[i] = __uint_as_float(pc[0]);
+      ts_merge(vs[i], vc[i], __uint_as_float(ps[1]), __uint_as_float(pc[1]));
     }
   }
-  int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
+  if constexpr (SW >= 2) {
+    // the same over lane bit 4 (rows of 16 lanes)
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      red[(w * NS + i) * 2] = s[i];
-      red[(w * NS + i) * 2 + 1] = c[i];
+    for (int i = 0; i < NP / 4; ++i) {
+      auto ps = __builtin_amdgcn_permlane16_swap(__float_as_uint(vs[i]), __float_as_uint(vs[i + NP / 4]), false, false);
+      auto pc = __builtin_amdgcn_permlane16_swap(__float_as_uint(vc[i]), __float_as_uint(vc[i + NP / 4]), false, false);
+      vs[i] = __uint_as_float(ps[0]);
+      vc[i] = __uint_as_float(pc[0]);
+      ts_merge(vs[i], vc[i], __uint_as_float(ps[1]), __uint_as_float(pc[1]));
+    }
+  }
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 32 >> SW; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) ts_merge(vs[i], vc[i], __shfl_xor(vs[i], off, 64), __shfl_xor(vc[i], off, 64));
+  }
+  // lane bits 5 .. 6 - SW name the block of NR values a lane holds
+  const int w = threadIdx.x >> 6, blk = lane >> (6 - SW);
+  __syncthreads();  // the previous call's readers are done with red
+  if ((lane & ((64 >> SW) - 1)) == 0) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int idx = blk * NR + i;
+      if (idx < NS) {
+        red[(w * NS + idx) * 2] = vs[i];
+        red[(w * NS + idx) * 2 + 1] = vc[i];
+      }
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
+  if ((int)threadIdx.x < nout) {
+    const int i = threadIdx.x;
     double acc = 0.0;
     for (int k = 0; k < WG / 64; ++k) acc += (double)red[(k * NS + i) * 2] + (double)red[(k * NS + i) * 2 + 1];
     out[i] = acc;
@@ -102,13 +149,75 @@ __device__ __forceinline__ double* lb_coef(double* sc, int m) { return sc + 4 + 
 
 // dots[(p * split + q) * NDOT + k]: 0..3 s^T y, y^T y, s^T g, y^T g of the pending pair,
 // 4 g^T g, 5 + 4 j + {0..3} s_j^T g, y_j^T g, s_j^T y_new, y_j^T y_new (age order j).
-// Pairs go in groups of DG, one block reduction per group (measured faster at
-// 2286 x 8192 than one pass with every load in flight: 532 against 581 us with
-// 4 values per thread, 630 us with 2).
+// Up to CFIX stored pairs a body specialised on their count issues every load
+// of the slice before the sums and reduces all 5 + 4 C sums at once; beyond
+// that, pairs go in groups of DG with one block reduction per group.
 constexpr int DG = 4;
+constexpr int CFIX = 6;  // 5 + 4 CFIX sums fit one block reduction
+
+// ring slot of stored pair j (age order) given the newest's successor head
+__device__ __forceinline__ size_t pair_base(int p, int R, int head, int count, int j, int N, int q, int L) {
+  return ((size_t)p * R + (head - count + j + 2 * R) % R) * N + (size_t)q * L;
+}
+
+template <int C>
+__device__ __forceinline__ void dots_fixed(const LbArgs& a, float* red, double* out, const float2* gv,
+                                           const bool* act, bool pending, size_t rb, size_t hb, int p, int R,
+                                           int head, int q, int L) {
+  constexpr int NS = 5 + 4 * C, CC = C > 0 ? C : 1;
+  const int tid = threadIdx.x;
+  float2 gp[DEPT], sh[DEPT], sv[CC][DEPT], yy[CC][DEPT];
+#pragma unroll
+  for (int i = 0; i < DEPT; ++i) {
+    gp[i] = sh[i] = make_float2(0.f, 0.f);
+    if (act[i] && pending) {
+      gp[i] = a.gp[rb + tid + i * LWG];
+      sh[i] = a.S[hb + tid + i * LWG];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const size_t sb = pair_base(p, R, head, C, j, a.N, q, L);
+#pragma unroll
+    for (int i = 0; i < DEPT; ++i) {
+      sv[j][i] = yy[j][i] = make_float2(0.f, 0.f);
+      if (act[i]) {
+        sv[j][i] = a.S[sb + tid + i * LWG];
+        yy[j][i] = a.Y[sb + tid + i * LWG];
+      }
+    }
+  }
+  float s[NS], c[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s[k] = c[k] = 0.f;
+#pragma unroll
+  for (int i = 0; i < DEPT; ++i) {
+    if (!act[i]) continue;
+    const float2 g = gv[i];
+    float2 y = make_float2(0.f, 0.f);
+    ts_add(s[4], c[4], g.x * g.x + g.y * g.y);
+    if (pending) {
+      y = make_float2(g.x - gp[i].x, g.y - gp[i].y);
+      a.Y[hb + tid + i * LWG] = y;
+      ts_add(s[0], c[0], sh[i].x * y.x + sh[i].y * y.y);
+      ts_add(s[1], c[1], y.x * y.x + y.y * y.y);
+      ts_add(s[2], c[2], sh[i].x * g.x + sh[i].y * g.y);
+      ts_add(s[3], c[3], y.x * g.x + y.y * g.y);
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const float2 sj = sv[j][i], yj = yy[j][i];
+      ts_add(s[5 + 4 * j + 0], c[5 + 4 * j + 0], sj.x * g.x + sj.y * g.y);
+      ts_add(s[5 + 4 * j + 1], c[5 + 4 * j + 1], yj.x * g.x + yj.y * g.y);
+      ts_add(s[5 + 4 * j + 2], c[5 + 4 * j + 2], sj.x * y.x + sj.y * y.y);
+      ts_add(s[5 + 4 * j + 3], c[5 + 4 * j + 3], yj.x * y.x + yj.y * y.y);
+    }
+  }
+  block_sums<NS>(s, c, red, out, NS);
+}
 
 __global__ void __launch_bounds__(LWG) k_dir_dots(LbArgs a, double* dots) {
-  __shared__ float red[(LWG / 64) * 2 * 4 * DG];
+  __shared__ float red[(LWG / 64) * 2 * (5 + 4 * CFIX)];
   const int p = blockIdx.y, q = blockIdx.x, split = gridDim.x;
   const int tid = threadIdx.x;
   const int N = a.N, m = a.m, R = m + 1;
@@ -126,6 +235,17 @@ __global__ void __launch_bounds__(LWG) k_dir_dots(LbArgs a, double* dots) {
     act[i] = e < L;
     gv[i] = act[i] ? a.g[rb + e] : make_float2(0.f, 0.f);
     yv[i] = make_float2(0.f, 0.f);
+  }
+  const size_t hb0 = ((size_t)p * R + head) * N + (size_t)q * L;
+  switch (count) {  // uniform over the workgroup (one row)
+    case 0: return dots_fixed<0>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    case 1: return dots_fixed<1>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    case 2: return dots_fixed<2>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    case 3: return dots_fixed<3>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    case 4: return dots_fixed<4>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    case 5: return dots_fixed<5>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    case 6: return dots_fixed<6>(a, red, out, gv, act, pending, rb, hb0, p, R, head, q, L);
+    default: break;
   }
   {
     float s5[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, c5[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -147,10 +267,7 @@ __global__ void __launch_bounds__(LWG) k_dir_dots(LbArgs a, double* dots) {
         ts_add(s5[3], c5[3], y.x * gv[i].x + y.y * gv[i].y);
       }
     }
-    double o[5];
-    block_sums<5>(s5, c5, red, o);
-    if (tid == 0)
-      for (int k = 0; k < 5; ++k) out[k] = o[k];
+    block_sums<5>(s5, c5, red, out, 5);
   }
   for (int j0 = 0; j0 < count; j0 += DG) {
     float s4[4 * DG], c4[4 * DG];
@@ -160,7 +277,7 @@ __global__ void __launch_bounds__(LWG) k_dir_dots(LbArgs a, double* dots) {
     for (int u = 0; u < DG; ++u) {
       const int j = j0 + u;
       if (j >= count) break;
-      const size_t sb = ((size_t)p * R + (head - count + j + 2 * R) % R) * N + (size_t)q * L;
+      const size_t sb = pair_base(p, R, head, count, j, N, q, L);
 #pragma unroll
       for (int i = 0; i < DEPT; ++i) {
         if (!act[i]) continue;
@@ -172,10 +289,7 @@ __global__ void __launch_bounds__(LWG) k_dir_dots(LbArgs a, double* dots) {
         ts_add(s4[4 * u + 3], c4[4 * u + 3], y.x * yv[i].x + y.y * yv[i].y);
       }
     }
-    double o[4 * DG];
-    block_sums<4 * DG>(s4, c4, red, o);
-    if (tid == 0)
-      for (int k = 0; k < 4 * DG && j0 * 4 + k < 4 * count; ++k) out[5 + 4 * j0 + k] = o[k];
+    block_sums<4 * DG>(s4, c4, red, out + 5 + 4 * j0, min(4 * DG, 4 * (count - j0)));
   }
 }
 
@@ -281,6 +395,46 @@ __global__ void __launch_bounds__(64) k_dir_solve(LbArgs a, const double* dots, 
   sc[1] = use ? k : 0;
 }
 
+// d over one row slice with C stored pairs, every load issued before the sums
+template <int C>
+__device__ __forceinline__ void apply_fixed(const LbArgs& a, const double* coef, const bool* act, size_t rb, int p,
+                                            int R, int head, int q, int L) {
+  constexpr int CC = C > 0 ? C : 1;
+  const int tid = threadIdx.x;
+  float2 g[DEPT], sv[CC][DEPT], yy[CC][DEPT];
+#pragma unroll
+  for (int i = 0; i < DEPT; ++i) g[i] = act[i] ? a.g[rb + tid + i * LWG] : make_float2(0.f, 0.f);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const size_t sb = pair_base(p, R, head, C, j, a.N, q, L);
+#pragma unroll
+    for (int i = 0; i < DEPT; ++i) {
+      sv[j][i] = yy[j][i] = make_float2(0.f, 0.f);
+      if (act[i]) {
+        sv[j][i] = a.S[sb + tid + i * LWG];
+        yy[j][i] = a.Y[sb + tid + i * LWG];
+      }
+    }
+  }
+  const float cg = (float)coef[0];
+  float cs[CC], cy[CC];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    cs[j] = (float)coef[1 + j];
+    cy[j] = (float)coef[1 + R + j];
+  }
+#pragma unroll
+  for (int i = 0; i < DEPT; ++i) {
+    float2 dv = make_float2(cg * g[i].x, cg * g[i].y);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      dv.x += cs[j] * sv[j][i].x + cy[j] * yy[j][i].x;
+      dv.y += cs[j] * sv[j][i].y + cy[j] * yy[j][i].y;
+    }
+    if (act[i]) a.d[rb + tid + i * LWG] = dv;
+  }
+}
+
 __global__ void __launch_bounds__(LWG) k_dir_apply(LbArgs a) {
   const int p = blockIdx.y, q = blockIdx.x, split = gridDim.x;
   const int tid = threadIdx.x;
@@ -294,14 +448,25 @@ __global__ void __launch_bounds__(LWG) k_dir_apply(LbArgs a) {
   float2 dv[DEPT];
   bool act[DEPT];
 #pragma unroll
+  for (int i = 0; i < DEPT; ++i) act[i] = tid + i * LWG < L;
+  switch (count) {  // uniform over the workgroup (one row)
+    case 0: return apply_fixed<0>(a, coef, act, rb, p, R, head, q, L);
+    case 1: return apply_fixed<1>(a, coef, act, rb, p, R, head, q, L);
+    case 2: return apply_fixed<2>(a, coef, act, rb, p, R, head, q, L);
+    case 3: return apply_fixed<3>(a, coef, act, rb, p, R, head, q, L);
+    case 4: return apply_fixed<4>(a, coef, act, rb, p, R, head, q, L);
+    case 5: return apply_fixed<5>(a, coef, act, rb, p, R, head, q, L);
+    case 6: return apply_fixed<6>(a, coef, act, rb, p, R, head, q, L);
+    default: break;
+  }
+#pragma unroll
   for (int i = 0; i < DEPT; ++i) {
     const int e = tid + i * LWG;
-    act[i] = e < L;
     const float2 g = act[i] ? a.g[rb + e] : make_float2(0.f, 0.f);
     dv[i] = make_float2(cg * g.x, cg * g.y);
   }
   for (int j = 0; j < count; ++j) {
-    const size_t sb = ((size_t)p * R + (head - count + j + 2 * R) % R) * N + (size_t)q * L;
+    const size_t sb = pair_base(p, R, head, count, j, N, q, L);
     const float cs = (float)coef[1 + j], cy = (float)coef[1 + R + j];
 #pragma unroll
     for (int i = 0; i < DEPT; ++i) {

@@ -72,6 +72,23 @@ def test_history_ring_wraps(ctx, method):
     assert relerr(ref5, ref) > 10 * err
 
 
+def test_long_memory(ctx):
+    # memory 8 over 10 iterations: the history holds more pairs than the
+    # direction kernels' count-specialised bodies take, so the grouped path runs
+    n1, n2, P, iters, mem = 32, 32, 13, 10, 8
+    masks, T, I, t0 = _start(933, n1, n2, P, 0.5)
+    m, t, Ir = rounded(masks, t0, I)
+    op = ops.FFTOp(m, n1, n2)
+    ref, _ = rt.lbfgs(op, Ir, t, iters, m=mem)
+    tt = c64(t0)
+    tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts("lbfgs", iters=iters, lbfgs_m=mem))
+    err = relerr(tt.cpu().numpy().astype(np.complex128), ref)
+    assert err < 1e-3
+    # the pairs beyond the sixth change the iterates, so they were compared
+    ref6, _ = rt.lbfgs(op, Ir, t, iters, m=6)
+    assert relerr(ref6, ref) > 10 * err
+
+
 def test_lbfgs_full_size_sampled_rows(ctx):
     # the benchmark's 2286 x 8192 launch of Alg. 1 (memory 5, 3 iterations) on sampled rows
     n1, n2, K, P = 128, 64, 4, 2286
