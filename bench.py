@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3  # published vector FP32 (packed) peak; 78.6 without packed math
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # published dense BF16 matrix peak
 
 
 def log(*a):
@@ -101,6 +102,8 @@ def parse():
                          "timed learned form (0: no fallback; the fallback forms are reported as variants)")
     ap.add_argument("--profile-lbfgs", type=int, default=0, metavar="ITERS",
                     help="only run one L-BFGS retrieval of ITERS iterations on the workload (for counter runs)")
+    ap.add_argument("--gemm-probe", action="store_true",
+                    help="only time the network's BF16 MFMA GEMM at the shapes of one training step (cfg4 network)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
@@ -239,6 +242,47 @@ def profile_lbfgs(iters):
     print(json.dumps({"profile_lbfgs_iters": iters}))
 
 
+def gemm_probe(reps=20):
+    """The BF16 MFMA GEMM (tm_gemm_bf16: 128 x 128 tiles, double-buffered K
+    steps) at the shapes of one training step of the start network
+    (4096 -> 1024 -> 1024 -> 2048, batch 512: forward X W, backward dX = dY W^T
+    and dW = X^T dY), and one 4096^3 product; each timed with events over
+    `reps` launches on the current stream after one warm-up."""
+    import torch
+
+    import paper_2302_13524_amd as tm
+
+    dev = torch.device("cuda:0")
+    ctx = tm.Context(0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    B, dims = 512, (4096, 1024, 1024, 2048)
+    shapes = []
+    for i in range(3):
+        k, n = dims[i], dims[i + 1]
+        shapes.append((f"fwd{i + 1} X W", B, n, k, False, False))
+        shapes.append((f"bwd{i + 1} dY W^T", B, k, n, False, True))
+        shapes.append((f"bwd{i + 1} X^T dY", k, n, B, True, False))
+    shapes.append(("square 4096", 4096, 4096, 4096, False, False))
+    out = []
+    for name, M, N, K, ta, tb in shapes:
+        A = torch.randn((K, M) if ta else (M, K), generator=g, device=dev).to(torch.bfloat16)
+        Bm = torch.randn((N, K) if tb else (K, N), generator=g, device=dev).to(torch.bfloat16)
+        tm.tm_gemm_bf16(ctx, A, Bm, ta, tb)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            tm.tm_gemm_bf16(ctx, A, Bm, ta, tb)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * M * N * K / (ms * 1e-3) / 1e12
+        out.append({"gemm": name, "M": M, "N": N, "K": K, "ms": round(ms, 5), "TFLOPs": round(tf, 1),
+                    "frac_bf16_peak": round(tf / BF16_MFMA_PEAK_TFLOPS, 4)})
+    ctx.close()
+    print(json.dumps({"gemm_probe": out}))
+
+
 def copy_probe():
     import torch
     a = torch.empty(512 * 2**20 // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -256,6 +300,9 @@ def main():
         return
     if args.copy_probe:
         copy_probe()
+        return
+    if args.gemm_probe:
+        gemm_probe()
         return
     if args.profile_lbfgs:
         profile_lbfgs(args.profile_lbfgs)

@@ -39,28 +39,53 @@ __device__ __forceinline__ float gelu_grad(float x) {
 
 constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;  // LDS row stride in bf16 (80 B)
 
-// Tile loads into LDS as [row][k] with k contiguous. Out-of-range elements are 0.
-// `trans`: element (r, k) of the operand is at p[k * ld + r], else p[r * ld + k].
-__device__ __forceinline__ void load_tile(uint16_t* lds, const uint16_t* __restrict__ p, int ld, bool trans,
-                                          int r0, int k0, int R, int Kd) {
+// A K step's tile of one operand, 128 rows x 32 k, staged in registers: each
+// thread holds 16 bf16 (two 16-byte words). Element (r, k) of the operand is
+// at p[k * ld + r] when `trans`, else at p[r * ld + k]; out-of-range elements
+// are 0. `vec`: ld is a multiple of 8 and p 16-byte aligned, so a thread's 16
+// consecutive elements load as two 16-byte words wherever they are in range.
+struct TileRegs {
+  uint4 v[2];
+};
+
+__device__ __forceinline__ void tile_fetch(TileRegs& t, const uint16_t* __restrict__ p, int ld, bool trans, bool vec,
+                                           int r0, int k0, int R, int Kd) {
+  const int tid = threadIdx.x;
+  // not trans: row r0 + tid / 2, k0 + 16 (tid % 2) .. + 15; trans: k0 + tid / 8, rows r0 + 16 (tid % 8) .. + 15
+  const int a = trans ? k0 + (tid >> 3) : r0 + (tid >> 1);     // fixed index
+  const int b = trans ? r0 + (tid & 7) * 16 : k0 + (tid & 1) * 16;  // first of the 16 consecutive
+  const int alim = trans ? Kd : R, blim = trans ? R : Kd;
+  const uint16_t* q = p + (size_t)a * ld + b;
+  if (vec && a < alim && b + 16 <= blim) {
+    t.v[0] = ((const uint4*)q)[0];
+    t.v[1] = ((const uint4*)q)[1];
+  } else {
+    uint32_t w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t lo = (a < alim && b + 2 * i < blim) ? q[2 * i] : 0u;
+      const uint32_t hi = (a < alim && b + 2 * i + 1 < blim) ? q[2 * i + 1] : 0u;
+      w[i] = lo | (hi << 16);
+    }
+    t.v[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    t.v[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  }
+}
+
+// The staged tile into LDS as [row][k] (k contiguous, row stride LDK)
+__device__ __forceinline__ void tile_store(uint16_t* lds, const TileRegs& t, bool trans) {
   const int tid = threadIdx.x;
   if (!trans) {
-    // 128 rows x 32 k: each thread 16 consecutive k of one row
-    int r = tid >> 1, kh = (tid & 1) * 16;
-    int gr = r0 + r;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int gk = k0 + kh + i;
-      lds[r * LDK + kh + i] = (gr < R && gk < Kd) ? p[(size_t)gr * ld + gk] : (uint16_t)0;
-    }
+    uint4* d = (uint4*)&lds[(tid >> 1) * LDK + (tid & 1) * 16];  // LDK * 2 B = 80 B: 16-byte aligned
+    d[0] = t.v[0];
+    d[1] = t.v[1];
   } else {
-    // 32 k x 128 rows: each thread 16 consecutive rows at one k
-    int k = tid >> 3, rh = (tid & 7) * 16;
-    int gk = k0 + k;
+    const int k = tid >> 3, rh = (tid & 7) * 16;
+    const uint32_t w[8] = {t.v[0].x, t.v[0].y, t.v[0].z, t.v[0].w, t.v[1].x, t.v[1].y, t.v[1].z, t.v[1].w};
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int gr = r0 + rh + i;
-      lds[(rh + i) * LDK + k] = (gr < R && gk < Kd) ? p[(size_t)gk * ld + gr] : (uint16_t)0;
+    for (int i = 0; i < 8; ++i) {
+      lds[(rh + 2 * i) * LDK + k] = (uint16_t)(w[i] & 0xffffu);
+      lds[(rh + 2 * i + 1) * LDK + k] = (uint16_t)(w[i] >> 16);
     }
   }
 }
@@ -80,11 +105,53 @@ struct GemmArgs {
   uint16_t* outh;     // [M][N] BF16 output (may be null)
   float* outf2;       // [M][N] second FP32 output (pre-activation)
   float beta;         // outf = beta * outf + result (accumulate across calls), 0 or 1
+  int veca, vecb;     // 16-byte tile loads allowed (leading dimension a multiple of 8, aligned base)
 };
 
+// Epilogue of one wave's 64 x 64 block: lane holds column n = lane % 32 of
+// each 32 x 32 tile, rows 8 q + 4 (lane / 32) + r for acc element 4 q + r.
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16 (&acc)[2][2], int mb, int nb, int lane) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int q = e >> 2, r = e & 3;
+        const int m = mb + i * 32 + 8 * q + 4 * (lane >> 5) + r;
+        const int n = nb + j * 32 + (lane & 31);
+        const float a = acc[i][j][e];
+        if (m < g.M && n < g.N) {
+          const size_t o = (size_t)m * g.N + n;
+          float v = a;
+          if constexpr (EPI == MLP_EPI_BIAS_GELU) {
+            v += g.bias[n];
+            if (g.outf2) g.outf2[o] = v;
+            const float h = gelu(v);
+            if (g.outh) g.outh[o] = f2bf(h);
+            if (g.outf) g.outf[o] = h;
+          } else if constexpr (EPI == MLP_EPI_BIAS) {
+            v += g.bias[n];
+            if (g.outf) g.outf[o] = v;
+            if (g.outh) g.outh[o] = f2bf(v);
+          } else if constexpr (EPI == MLP_EPI_GELU_BWD) {
+            v *= gelu_grad(g.aux[o]);
+            if (g.outf) g.outf[o] = v;
+            if (g.outh) g.outh[o] = f2bf(v);
+          } else {
+            if (g.outf) g.outf[o] = (g.beta != 0.f ? g.outf[o] : 0.f) + v;
+            if (g.outh) g.outh[o] = f2bf(v);
+          }
+        }
+      }
+}
+
+// K steps double-buffered: the next step's tiles are loaded into registers
+// while the MFMAs run on the current one; one barrier per K step.
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ uint16_t sa[BM * LDK];
-  __shared__ uint16_t sb[BN * LDK];
+  __shared__ uint16_t sA[2][BM * LDK];
+  __shared__ uint16_t sB[2][BN * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -96,11 +163,22 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  const bool ta = g.ta != 0, tb = g.tb == 0;  // B as [n][k]: "trans" when stored [K][N]
+  TileRegs ra, rb;
+  tile_fetch(ra, g.A, g.lda, ta, g.veca != 0, m0, 0, g.M, g.K);
+  tile_fetch(rb, g.B, g.ldb, tb, g.vecb != 0, n0, 0, g.N, g.K);
+  const int nk = (g.K + BK - 1) / BK;
+  for (int ks = 0; ks < nk; ++ks) {
+    uint16_t* sa = sA[ks & 1];
+    uint16_t* sb = sB[ks & 1];
+    // this buffer's last readers (step ks - 2) passed the barrier of step ks - 1
+    tile_store(sa, ra, ta);
+    tile_store(sb, rb, tb);
     __syncthreads();
-    load_tile(sa, g.A, g.lda, g.ta != 0, m0, k0, g.M, g.K);
-    load_tile(sb, g.B, g.ldb, g.tb == 0, n0, k0, g.N, g.K);  // B as [n][k]: "trans" when stored [K][N]
-    __syncthreads();
+    if (ks + 1 < nk) {
+      tile_fetch(ra, g.A, g.lda, ta, g.veca != 0, m0, (ks + 1) * BK, g.M, g.K);
+      tile_fetch(rb, g.B, g.ldb, tb, g.vecb != 0, n0, (ks + 1) * BK, g.N, g.K);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       bf16x8 av[2], bv[2];
@@ -115,48 +193,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
   }
-  // epilogue: lane holds column n = lane % 32 of each 32 x 32 tile, rows
-  // 8 q + 4 (lane / 32) + r for acc element 4 q + r
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int q = e >> 2, r = e & 3;
-        int m = m0 + wm + i * 32 + 8 * q + 4 * (lane >> 5) + r;
-        int n = n0 + wn + j * 32 + (lane & 31);
-        if (m >= g.M || n >= g.N) continue;
-        size_t o = (size_t)m * g.N + n;
-        float v = acc[i][j][e];
-        switch (g.epi) {
-          case MLP_EPI_BIAS_GELU: {
-            v += g.bias[n];
-            if (g.outf2) g.outf2[o] = v;
-            float h = gelu(v);
-            if (g.outh) g.outh[o] = f2bf(h);
-            if (g.outf) g.outf[o] = h;
-            break;
-          }
-          case MLP_EPI_BIAS: {
-            v += g.bias[n];
-            if (g.outf) g.outf[o] = v;
-            if (g.outh) g.outh[o] = f2bf(v);
-            break;
-          }
-          case MLP_EPI_GELU_BWD: {
-            v *= gelu_grad(g.aux[o]);
-            if (g.outf) g.outf[o] = v;
-            if (g.outh) g.outh[o] = f2bf(v);
-            break;
-          }
-          default: {  // MLP_EPI_STORE
-            if (g.outf) g.outf[o] = (g.beta != 0.f ? g.outf[o] : 0.f) + v;
-            if (g.outh) g.outh[o] = f2bf(v);
-            break;
-          }
-        }
-      }
+  switch (g.epi) {  // one unrolled epilogue per kind, so the accumulators stay in registers
+    case MLP_EPI_BIAS_GELU: gemm_epilogue<MLP_EPI_BIAS_GELU>(g, acc, m0 + wm, n0 + wn, lane); break;
+    case MLP_EPI_BIAS: gemm_epilogue<MLP_EPI_BIAS>(g, acc, m0 + wm, n0 + wn, lane); break;
+    case MLP_EPI_GELU_BWD: gemm_epilogue<MLP_EPI_GELU_BWD>(g, acc, m0 + wm, n0 + wn, lane); break;
+    default: gemm_epilogue<MLP_EPI_STORE>(g, acc, m0 + wm, n0 + wn, lane); break;
+  }
 }
 
 // features: X[b][i] = bf16(I[b][i] / mean_b), s[b] = sqrt(sum_b / (K N))
@@ -281,7 +323,10 @@ __global__ void k_to_bf16(const float* x, uint16_t* y, size_t n) {
   if (i < n) y[i] = f2bf(x[i]);
 }
 
-int gemm(const GemmArgs& g, hipStream_t s) {
+int gemm(const GemmArgs& g0, hipStream_t s) {
+  GemmArgs g = g0;
+  g.veca = g.lda % 8 == 0 && (uintptr_t)g.A % 16 == 0;
+  g.vecb = g.ldb % 8 == 0 && (uintptr_t)g.B % 16 == 0;
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
   k_gemm<<<grid, 256, 0, s>>>(g);
   return (int)hipGetLastError();

@@ -26,7 +26,7 @@ def bf16_round(x):
     return torch.as_tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
 
 
-@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (200, 72, 40), (64, 300, 96), (1, 5, 3)])
+@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (200, 72, 40), (64, 300, 96), (1, 5, 3), (300, 264, 200)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm_tile_matches_exact_product(ctx, M, N, K, ta, tb):
     g = torch.Generator().manual_seed(M * 7 + N + K + 3 * ta + tb)
