@@ -29,6 +29,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -102,6 +103,9 @@ def parse():
                          "timed learned form (0: no fallback; the fallback forms are reported as variants)")
     ap.add_argument("--profile-lbfgs", type=int, default=0, metavar="ITERS",
                     help="only run one L-BFGS retrieval of ITERS iterations on the workload (for counter runs)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: time every compiled launch configuration of the Lanczos and cyclic ER kernels for the "
+                         "grid before the timed steps and use the fastest; 0: the default configuration")
     ap.add_argument("--gemm-probe", action="store_true",
                     help="only time the network's BF16 MFMA GEMM at the shapes of one training step (cfg4 network)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -139,10 +143,19 @@ def sources_digest(files=None):
     return h.hexdigest()
 
 
-def measured_traffic(P, N):
+def plan_tag(L1, L2, cfg):
+    """The Plan<...> of the row kernels that launch configuration cfg runs
+    (as rocprofv3 names them): eight values per thread with bit 2, the digit
+    order of bit 1."""
+    return f"Plan<{L1}, {L2}, {3 if cfg & 2 else -1}, {cfg & 1}>"
+
+
+def measured_traffic(P, N, plan=None):
     """HBM bytes per launch of the spectral and ER kernels from the committed
     FETCH_SIZE / WRITE_SIZE counter summary, scaled by the counters' reading
-    for a device copy of known size; None when absent or taken on other sources."""
+    for a device copy of known size; None when absent or taken on other
+    sources; a row kernel's entry only when its counters were taken on `plan`
+    (the launch configuration's Plan<...>), if given."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
@@ -154,7 +167,8 @@ def measured_traffic(P, N):
     ok = {"row": d.get("sources_sha256") == sources_digest(),
           "lbfgs": d.get("lbfgs_sources_sha256") == sources_digest(LBFGS_SOURCES)}
     return {k: int(round((v["fetch_kib"] * fs + v["write_kib"] * ws) * 1024)) for k, v in d["kernels"].items()
-            if ok["lbfgs" if k.startswith("lbfgs") else "row"]}
+            if ok["lbfgs" if k.startswith("lbfgs") else "row"]
+            and (plan is None or k.startswith("lbfgs") or v.get("plan") == plan)}
 
 
 def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
@@ -174,10 +188,17 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
         return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
     def pick(tab, mode):
-        keys = [k for k in tab if k.startswith("void tmk::row_kernel<tmk::Plan<7, 6,") and f", {mode}, float, " in k]
-        vals = [tab[k] for k in keys]
+        # the launch configuration's kernels (default or autotuned plan) of this mode, with and
+        # without sums; where several plans ran, the one with the most dispatches
+        plans = {}
+        for k in tab:
+            m = re.match(r"void tmk::row_kernel(?:_w)?<tmk::(Plan<7, 6, -?\d+, \d+>), (\d+), float, ", k)
+            if m and int(m.group(2)) == mode:
+                plans.setdefault(m.group(1), []).append(tab[k])
+        plan = max(plans, key=lambda q: sum(c for _, c in plans[q]))
+        vals = plans[plan]
         n = sum(c for _, c in vals)
-        return sum(v * c for v, c in vals) / n, n
+        return sum(v * c for v, c in vals) / n, n, plan
 
     f, w = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
     cf, cw = per_kernel(copy_fetch_dir, "FETCH_SIZE"), per_kernel(copy_write_dir, "WRITE_SIZE")
@@ -189,9 +210,9 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
     for key, mode in (("spectral", 5), ("er", 3), ("er_cyclic", 12), ("lanczos", 13)):
         if not any(f", {mode}, float, " in k for k in f):
             continue
-        fv, fn = pick(f, mode)
-        wv, wn = pick(w, mode)
-        res["kernels"][key] = {"fetch_kib": fv, "write_kib": wv, "dispatches": [fn, wn]}
+        fv, fn, plan = pick(f, mode)
+        wv, wn, _ = pick(w, mode)
+        res["kernels"][key] = {"fetch_kib": fv, "write_kib": wv, "dispatches": [fn, wn], "plan": plan}
 
     def pick_name(tab, frag):
         keys = [k for k in tab if frag in k]
@@ -364,6 +385,12 @@ def main():
 
     Tn = Tt / torch.linalg.vector_norm(Tt, dim=1, keepdim=True)
 
+    # launch configuration of the Lanczos and cyclic ER kernels for this grid (untimed)
+    tune = {"config": 0}
+    if args.autotune:
+        tune = tm.autotune(ctx, n1, n2, K, P, space="full", reps=5)
+        log(f"autotune {n1}x{n2}: config {tune['config']} {tm.tm_config_info(n1, n2, tune['config'])}")
+
     def fidelity(t):
         c = torch.sum(torch.conj(t) * Tn, dim=1)
         return (c.abs() ** 2 / torch.sum(t.abs() ** 2, dim=1)).double()
@@ -528,6 +555,9 @@ def main():
     # `roofline`. Both are bound by FP32 vector arithmetic (the FFT work), so the primary figure is
     # against the vector peak; the HBM view carries the algorithmic bytes and the counter-measured traffic.
     flops_row = 2 * K * 5 * N * np.log2(N) + 30 * K * N  # 2K FFTs + pointwise per row-step
+    wg_, rpw_, ept_ = tm.tm_config_info(n1, n2, tune["config"])
+    cfg_note = (f" [launch configuration {tune['config']}: {wg_} threads, {rpw_} row(s) per workgroup, "
+                f"{ept_} values per thread]")
     kernels = {
         "spectral": {"mode": sp_mode, "ms": sp_ms, "n": sp_n,
                      "name": "row_kernel<M_SPEC> (mask*FFT, truncated weights, IFFT, conj-mask sum, heavy-ball)"
@@ -541,7 +571,9 @@ def main():
                # read I, t (and t_prev with momentum), write the new t
                "bytes": P * (K * N * 4 + (3 if beta > 0 else 2) * N * 8)},
     }
-    traffic = measured_traffic(P, N)
+    for kv in kernels.values():
+        kv["name"] += cfg_note
+    traffic = measured_traffic(P, N, plan_tag(n1.bit_length() - 1, n2.bit_length() - 1, tune["config"]))
     roofs = {}
     for key, kv in kernels.items():
         avg = kv["ms"] / max(kv["n"], 1)
@@ -594,6 +626,9 @@ def main():
         "phase_correction_ms": round(ms_step - ret_ms, 3),
         "lbfgs": {"iters_to_0.99": n_lb, "retrieval_ms": round(lb_ms, 3) if lb_ms else None},
         "roofline_lbfgs": roofline_lbfgs,
+        "autotune": {"config": tune["config"], "shape_wg_rows_values": tm.tm_config_info(n1, n2, tune["config"]),
+                     "candidates_us": {c: [v["lanczos_us"], v["er_cyclic_us"]]
+                                       for c, v in tune.get("candidates", {}).items()}},
         "lbfgs_amplitude": {"iters_to_0.99": n_la, "retrieval_ms": round(la_ms, 3) if la_ms else None},
         "quality": {"mean_fidelity": round(float(fid.mean()), 6), "min_fidelity": round(float(fid.min()), 6),
                     "frac_rows_ge_0.99": round(float((fid >= 0.99).mean()), 4),

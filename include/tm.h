@@ -236,6 +236,30 @@ int tm_tune_time(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t K, int32_t P, int3
 /* Use digit-order variant `variant` for the grid n1 x n2 in this context. */
 int tm_set_variant(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t variant);
 
+/* Launch configurations of the fused row kernels (the 2-D FFTs of Sec. 2.2,
+ * Eq. probingmatrix): cfg in 0..7, bit 0 the digit-order variant (as
+ * tm_set_variant), bit 1 eight values per thread instead of sixteen, bit 2
+ * twice the rows per workgroup. Bits 1 and 2 change the Lanczos step of the
+ * spectral start and the cyclic error-reduction step; every other kernel
+ * keeps the default plan of the same digit order; the batch takes bit 0 only.
+ * They are compiled for the 32x32, 64x32, 64x64 and 128x64 grids (twice the
+ * rows only where a workgroup stays at 512 threads or fewer).
+ *
+ * tm_config_info: 1 if configuration cfg is compiled for the grid, with its
+ * threads per workgroup, rows per workgroup and values per thread (each
+ * pointer may be NULL); 0 otherwise. No device work. */
+int tm_config_info(int32_t n1, int32_t n2, int32_t cfg, int32_t *wg, int32_t *rows_per_wg,
+                   int32_t *values_per_thread);
+/* Use configuration cfg for the grid n1 x n2 in this context (TM_EUNSUPPORTED
+ * if it is not compiled for the grid). */
+int tm_set_config(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t cfg);
+/* Average device time (microseconds) of one Lanczos-step launch (us[0]) and
+ * one cyclic error-reduction launch (us[1]) over P rows of an n1 x n2 grid
+ * with K masks in configuration cfg, on synthetic data in library workspace
+ * (synchronous, on the null stream). us: host array of 2 doubles. */
+int tm_tune_config(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t K, int32_t P, int32_t I_dtype, int32_t cfg,
+                   int32_t reps, double *us);
+
 /* ---- phase-offset correction (Sec. 2.3) -------------------------------- */
 
 typedef struct {

@@ -35,7 +35,7 @@ EXPORTED = (
     "tm_pre_energy", "tm_pre_fiber_mask", "tm_pre_gather", "tm_amp_gradient", "tm_foci_power_ratio",
     "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band", "tm_phase_last_counts",
     "tm_retrieve_noalloc", "tm_wnet_table", "tm_wnet_pretrain_step", "tm_wtab_power_grad", "tm_wnet_train_step",
-    "tm_set_weight_table", "tm_retrieve_learned",
+    "tm_set_weight_table", "tm_retrieve_learned", "tm_config_info", "tm_set_config", "tm_tune_config",
 )
 TM_NOALLOC_MAX_ROWS = 32768
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
@@ -146,6 +146,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_batch_destroy.argtypes = [vp]
     lib.tm_tune_time.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
     lib.tm_set_variant.argtypes = [vp, i32, i32, i32]
+    lib.tm_config_info.argtypes = [i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.tm_set_config.argtypes = [vp, i32, i32, i32]
+    lib.tm_tune_config.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
     lib.tm_phase_set_band.argtypes = [vp, i32]
     lib.tm_phase_last_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.tm_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
@@ -731,28 +734,73 @@ def tm_set_variant(ctx: Context, n1, n2, variant):
     ctx.check(ctx.lib.tm_set_variant(ctx.h, n1, n2, variant), "tm_set_variant")
 
 
+def tm_config_info(n1, n2, cfg):
+    """(threads per workgroup, rows per workgroup, values per thread) of launch
+    configuration cfg (0..7) for the grid, or None if it is not compiled."""
+    if not isinstance(cfg, int) or isinstance(cfg, bool):
+        raise TMError("cfg must be an int")
+    wg, rpw, ept = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    ok = load().tm_config_info(int(n1), int(n2), int(cfg), ctypes.byref(wg), ctypes.byref(rpw), ctypes.byref(ept))
+    return (wg.value, rpw.value, ept.value) if ok else None
+
+
+def tm_set_config(ctx: Context, n1, n2, cfg):
+    ctx.check(ctx.lib.tm_set_config(ctx.h, n1, n2, cfg), "tm_set_config")
+
+
+def tm_tune_config(ctx: Context, n1, n2, K, P, cfg, bf16=False, reps=5):
+    """(Lanczos-step us, cyclic ER-step us) of configuration cfg on synthetic data."""
+    us = (ctypes.c_double * 2)()
+    ctx.check(ctx.lib.tm_tune_config(ctx.h, n1, n2, K, P, TM_BF16 if bf16 else TM_F32, cfg, reps, us),
+              "tm_tune_config")
+    return us[0], us[1]
+
+
 def autotune(ctx: Context, n1: int, n2: int, K: int, P: int, bf16: bool = False, cache: str | None = None,
-             reps: int = 5) -> dict:
-    """Choose the FFT digit order for an n1 x n2 grid by timing both variants of
-    the error-reduction kernel (P rows, K masks), apply it to the context and
-    record it in the JSON cache `cache` (keyed by architecture, grid, K and
-    intensity type). A cached entry is applied without timing."""
+             reps: int = 5, space: str = "digits") -> dict:
+    """Choose the launch configuration of an n1 x n2 grid, apply it to the
+    context and record it in the JSON cache `cache` (keyed by architecture,
+    grid, K, intensity type and search space); a cached entry is applied
+    without timing.
+
+    space="digits": the two FFT digit orders, timed on the error-reduction
+    kernel over P rows (what the uneven batch takes).
+    space="full": every configuration compiled for the grid (digit order,
+    eight or sixteen values per thread, one or two times the rows per
+    workgroup, hence the waves per SIMD), each timed on the Lanczos step and
+    the cyclic ER step over P rows; the one with the least sum is applied."""
     import json
-    key = f"gfx950:{n1}x{n2}:K{K}:{'bf16' if bf16 else 'f32'}"
+    if space not in ("digits", "full"):
+        raise TMError(f"space {space!r} (digits or full)")
+    key = f"gfx950:{n1}x{n2}:K{K}:{'bf16' if bf16 else 'f32'}" + (":full" if space == "full" else "")
     table = {}
     if cache and os.path.exists(cache):
         with open(cache) as fh:
             table = json.load(fh)
     if key in table:
         entry = table[key]
-    else:
+    elif space == "digits":
         times = [tm_tune_time(ctx, n1, n2, K, P, v, bf16, reps) for v in (0, 1)]
         entry = {"variant": int(times[1] < times[0]), "us": times, "rows": P}
-        if cache:
-            table[key] = entry
-            with open(cache, "w") as fh:
-                json.dump(table, fh, indent=1, sort_keys=True)
-    tm_set_variant(ctx, n1, n2, entry["variant"])
+    else:
+        cand = {}
+        for cfg in range(8):
+            shape = tm_config_info(n1, n2, cfg)
+            if shape is None:
+                continue
+            lz, er = tm_tune_config(ctx, n1, n2, K, P, cfg, bf16, reps)
+            cand[str(cfg)] = {"lanczos_us": round(lz, 2), "er_cyclic_us": round(er, 2), "wg": shape[0],
+                              "rows_per_wg": shape[1], "values_per_thread": shape[2]}
+        best = min(cand, key=lambda k: cand[k]["lanczos_us"] + cand[k]["er_cyclic_us"])
+        entry = {"config": int(best), "variant": int(best) & 1, "candidates": cand, "rows": P}
+    if cache and key not in table:
+        table[key] = entry
+        with open(cache, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+    if "config" in entry:
+        tm_set_config(ctx, n1, n2, entry["config"])
+    else:
+        tm_set_variant(ctx, n1, n2, entry["variant"])
     return entry
 
 

@@ -652,6 +652,16 @@ row_kernel(RowArgs a) {
   row_body<PL, MODE, IT, SUMS, Launch<PL>::WG>(a, blockIdx.x, lds_all, red);
 }
 
+// The same kernel with an explicit workgroup size WGT (WGT / T rows per
+// workgroup): the autotuner's wider configurations.
+template <class PL, int MODE, typename IT, bool SUMS, int WGT>
+__global__ void __launch_bounds__(WGT) __attribute__((amdgpu_waves_per_eu(TM_MINW)))
+row_kernel_w(RowArgs a) {
+  __shared__ cx<float> lds_all[Launch<PL, WGT>::LDS_ELEMS];
+  __shared__ float red[Launch<PL, WGT>::RED_FLOATS];
+  row_body<PL, MODE, IT, SUMS, WGT>(a, blockIdx.x, lds_all, red);
+}
+
 // ---------------------------------------------------------------- FP64 residual
 template <class PL, typename IT>
 __global__ void __launch_bounds__(Launch<PL>::WG)

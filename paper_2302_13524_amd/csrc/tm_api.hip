@@ -50,7 +50,7 @@ struct tm_ctx {
   std::vector<hipEvent_t> pool;
   double acc_ms[TM_PROF_MODES] = {0};
   int64_t acc_n[TM_PROF_MODES] = {0};
-  std::map<int, int> variant;  // (L1 << 8 | L2) -> FFT digit-order variant
+  std::map<int, int> variant;  // (L1 << 8 | L2) -> launch configuration (bit 0: FFT digit-order variant)
   double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
   rocblas_handle blas = nullptr;  // plain complex GEMM of the foci synthesis
   int phase_band = 1;             // band evaluation of the defocus model when the pupil's box is small
@@ -1228,7 +1228,7 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     if (p.d.P > 0 && (!p.masks || !p.I || !p.t)) { delete b; return fail(c, TM_EINVAL, "problem %d: null pointer", i); }
     b->fns.push_back(fn);
     auto v = c->variant.find((ilog2(p.d.n1) << 8) | ilog2(p.d.n2));
-    int var = (v == c->variant.end()) ? 0 : v->second;
+    int var = (v == c->variant.end()) ? 0 : (v->second & 1);  // the batch bodies take the digit order only
     hp[i].code = 2 * gid + var;
     int rpi = tmk::batch_rows_per_item(gid);
     for (int blk = 0; blk * rpi < p.d.P; ++blk) items.push_back({i, blk});
@@ -1383,6 +1383,88 @@ extern "C" int tm_tune_time(tm_ctx* c, int32_t n1, int32_t n2, int32_t K, int32_
   hipEventDestroy(e1);
   if (e) return hipfail(c, e, "tuning launch");
   *us = 1e3 * ms / reps;
+  return TM_OK;
+}
+
+extern "C" int tm_config_info(int32_t n1, int32_t n2, int32_t cfg, int32_t* wg, int32_t* rows_per_wg,
+                              int32_t* values_per_thread) {
+  if (!is_pow2(n1) || !is_pow2(n2) || (int64_t)n1 * n2 > TW_MAX || cfg < 0 || cfg > 7) return 0;
+  const int L1 = ilog2(n1), L2 = ilog2(n2);
+  if (!((tmk::row_cfg_mask(L1, L2) >> cfg) & 1)) return 0;
+  int w = 0, r = 0, e = 0;
+  tmk::row_cfg_shape(L1, L2, cfg, &w, &r, &e);
+  if (wg) *wg = w;
+  if (rows_per_wg) *rows_per_wg = r;
+  if (values_per_thread) *values_per_thread = e;
+  return 1;
+}
+
+extern "C" int tm_set_config(tm_ctx* c, int32_t n1, int32_t n2, int32_t cfg) {
+  if (!c) return TM_EINVAL;
+  if (!tm_grid_supported(n1, n2)) return fail(c, TM_EUNSUPPORTED, "grid %dx%d", n1, n2);
+  if (!tm_config_info(n1, n2, cfg, nullptr, nullptr, nullptr))
+    return fail(c, TM_EUNSUPPORTED, "configuration %d is not compiled for grid %dx%d", cfg, n1, n2);
+  c->variant[(ilog2(n1) << 8) | ilog2(n2)] = cfg;
+  return TM_OK;
+}
+
+extern "C" int tm_tune_config(tm_ctx* c, int32_t n1, int32_t n2, int32_t K, int32_t P, int32_t I_dtype, int32_t cfg,
+                              int32_t reps, double* us) {
+  if (!c) return TM_EINVAL;
+  if (!us || reps < 1 || P < 1 || K < 1 || (I_dtype != TM_F32 && I_dtype != TM_BF16))
+    return fail(c, TM_EINVAL, "bad tuning arguments");
+  tm_dims d{n1, n2, K, P};
+  tmk::row_launcher fn0;
+  int r = check_dims(c, d, &fn0);
+  if (r) return r;
+  if (!tm_config_info(n1, n2, cfg, nullptr, nullptr, nullptr))
+    return fail(c, TM_EUNSUPPORTED, "configuration %d is not compiled for grid %dx%d", cfg, n1, n2);
+  tmk::row_launcher fn = tmk::find_row_launcher(ilog2(n1), ilog2(n2), cfg);
+  HIPCHK(c, hipSetDevice(c->device));
+  size_t N = (size_t)n1 * n2;
+  float* mk = (float*)ws_get(c, WS_PH_BASE + 20, K * N * 8);
+  float* t = (float*)ws_get(c, WS_PH_BASE + 21, P * N * 8);
+  float* I = (float*)ws_get(c, WS_PH_BASE + 22, (size_t)P * K * N * 4);
+  float* t2 = (float*)ws_get(c, WS_PH_BASE + 23, P * N * 8);
+  float* rm = (float*)ws_get(c, WS_PH_BASE + 24, (size_t)P * 4);
+  float* lz = (float*)ws_get(c, WS_PH_BASE + 25, (size_t)P * 8);
+  if (!mk || !t || !I || !t2 || !rm || !lz) return fail(c, TM_ENOMEM, "tuning workspace");
+  hipStream_t s = nullptr;
+  int e = tmk::launch_fill_hash(mk, (int64_t)K * N * 2, 11u, -0.7f, 0.7f, s);
+  if (!e) e = tmk::launch_fill_hash(t, (int64_t)P * N * 2, 12u, -1.f, 1.f, s);
+  if (!e) e = tmk::launch_fill_hash(I, (int64_t)P * K * N, 13u, 0.5f, 2.f, s);  // see tm_tune_time
+  if (!e) e = tmk::launch_fill_hash(rm, (int64_t)P, 14u, 1.f, 1.f, s);
+  if (e) return hipfail(c, e, "tuning data");
+  const int ibf = I_dtype == TM_BF16;
+  tmk::RowArgs lz_a = base_args(c, d, (const tm_c32*)mk);
+  lz_a.I = I;
+  lz_a.tin = lz_a.din = (const tmk::cx<float>*)t;
+  lz_a.tout = (tmk::cx<float>*)t2;
+  lz_a.rowmean = rm;
+  lz_a.tau = 3.f;
+  lz_a.lz_out = lz;
+  tmk::RowArgs er_a = base_args(c, d, (const tm_c32*)mk);
+  er_a.I = I;
+  er_a.tin = (const tmk::cx<float>*)t2;
+  er_a.tout = (tmk::cx<float>*)t2;
+  const int modes[2] = {tmk::M_LANCZOS, tmk::M_ERC};
+  const tmk::RowArgs* args[2] = {&lz_a, &er_a};
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  for (int k = 0; k < 2 && !e; ++k) {
+    e = fn(modes[k], ibf, *args[k], s);  // warm-up
+    hipEventRecord(e0, s);
+    for (int i = 0; i < reps && !e; ++i) e = fn(modes[k], ibf, *args[k], s);
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    us[k] = 1e3 * ms / reps;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e) return hipfail(c, e, "tuning launch");
   return TM_OK;
 }
 

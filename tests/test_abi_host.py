@@ -35,6 +35,30 @@ def test_grid_support_table():
         assert lib.tm_grid_supported(n1, n2) == 0
 
 
+def test_launch_configuration_table():
+    # digit orders everywhere; eight values per thread and twice the rows per
+    # workgroup on the workload grids, within 1024 (512 for twice the rows) threads
+    for n1, n2 in [(8, 8), (64, 128), (1, 1024)]:
+        assert [c for c in range(8) if tm.tm_config_info(n1, n2, c)] == [0, 1]
+    assert tm.tm_config_info(32, 32, 0) == (256, 4, 16)
+    assert tm.tm_config_info(32, 32, 2) == (256, 2, 8)
+    assert tm.tm_config_info(32, 32, 6) == (512, 4, 8)
+    assert tm.tm_config_info(64, 64, 4) == (512, 2, 16)
+    assert tm.tm_config_info(64, 64, 6) is None
+    assert tm.tm_config_info(128, 64, 2) == (1024, 1, 8)
+    assert tm.tm_config_info(128, 64, 4) is None
+    for n1, n2 in [(32, 32), (64, 32), (64, 64), (128, 64)]:
+        for c in range(8):
+            sh = tm.tm_config_info(n1, n2, c)
+            if sh is None:
+                continue
+            wg, rpw, ept = sh
+            assert wg * ept == rpw * n1 * n2  # whole rows per workgroup
+            assert ept in (8, 16) and wg <= 1024 and wg % 64 == 0
+    for bad in [(-1, 32, 32), (8, 32, 32), (0, 3, 8), (0, 128, 128)]:
+        assert tm.tm_config_info(bad[1], bad[2], bad[0]) is None
+
+
 def test_null_context_is_rejected():
     lib = tm.load()
     d = tm.tm_dims(8, 8, 4, 1)

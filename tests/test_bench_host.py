@@ -15,6 +15,7 @@ import bench  # noqa: E402
 LZ = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 13, float, true>(tmk::RowArgs)"
 ERC = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 12, float, false>(tmk::RowArgs)"
 ERC_S = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 12, float, true>(tmk::RowArgs)"
+LZ8 = "void tmk::row_kernel_w<tmk::Plan<7, 6, 3, 1>, 13, float, true, 1024>(tmk::RowArgs)"
 COPY = "__amd_rocclr_copyBuffer"
 DOTS = "tmk::(anonymous namespace)::k_dir_dots(tmk::(anonymous namespace)::LbArgs, double*)"
 APPLY = "tmk::(anonymous namespace)::k_dir_apply(tmk::(anonymous namespace)::LbArgs)"
@@ -38,10 +39,11 @@ def _counters(d, counter, rows):
 
 def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, monkeypatch):
     f, w, cf, cw = (str(tmp_path / s) for s in ("f", "w", "cf", "cw"))
+    # a stray dispatch of another plan (fewer dispatches) is not mixed in
     _counters(f, "FETCH_SIZE", [(LZ, 100.0), (LZ, 200.0), (ERC, 40.0), (ERC_S, 60.0), (ERC, 40.0), (DOTS, 10.0),
-                                (APPLY, 20.0)])
+                                (APPLY, 20.0), (LZ8, 999.0)])
     _counters(w, "WRITE_SIZE", [(LZ, 50.0), (LZ, 50.0), (ERC, 30.0), (ERC_S, 30.0), (ERC, 30.0), (DOTS, 1.0),
-                                (APPLY, 2.0)])
+                                (APPLY, 2.0), (LZ8, 999.0)])
     # a 512 MiB copy reads as half its size on the fetch counter, its size on the write counter
     _counters(cf, "FETCH_SIZE", [(COPY, 262144.0), (COPY, 262144.0), ("small", 1.0)])
     _counters(cw, "WRITE_SIZE", [(COPY, 524288.0), (COPY, 524288.0), ("small", 1.0)])
@@ -49,7 +51,8 @@ def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, mon
     bench.pmc_summary(f, w, cf, cw, out)
     d = json.load(open(out))
     assert d["copy"]["kernel"] == COPY and d["copy"]["fetch_kib"] == 262144.0
-    assert d["kernels"]["lanczos"] == {"fetch_kib": 150.0, "write_kib": 50.0, "dispatches": [2, 2]}
+    assert d["kernels"]["lanczos"] == {"fetch_kib": 150.0, "write_kib": 50.0, "dispatches": [2, 2],
+                                       "plan": "Plan<7, 6, -1, 0>"}
     # dispatches with and without sums are averaged by count
     assert abs(d["kernels"]["er_cyclic"]["fetch_kib"] - 140.0 / 3) < 1e-12
     assert "spectral" not in d["kernels"]
@@ -57,6 +60,11 @@ def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, mon
     t = bench.measured_traffic(2286, 8192)
     assert t["lanczos"] == (150 * 2 + 50 * 1) * 1024
     assert bench.measured_traffic(2286, 4096) is None
+    # row-kernel figures only for the launch configuration they were taken on
+    assert bench.plan_tag(7, 6, 0) == "Plan<7, 6, -1, 0>" and bench.plan_tag(7, 6, 3) == "Plan<7, 6, 3, 1>"
+    assert bench.measured_traffic(2286, 8192, bench.plan_tag(7, 6, 0))["lanczos"] == t["lanczos"]
+    t3 = bench.measured_traffic(2286, 8192, bench.plan_tag(7, 6, 3))
+    assert "lanczos" not in t3 and "lbfgs_direction" in t3
     # the L-BFGS direction is its two streaming kernels together
     assert t["lbfgs_direction"] == ((10 + 20) * 2 + (1 + 2) * 1) * 1024
     # each figure is dropped once the sources it was taken on change

@@ -1,6 +1,8 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
 Per-step operators must agree to 1e-5 relative (max-abs error over max-abs
 value); the FP64 residual to 1e-9."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -274,25 +276,51 @@ def test_lanczos_start_full_size_rows_and_errors(ctx):
                            tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=bad))
 
 
-def test_default_path_full_size_sampled_rows(ctx):
-    # the benchmark's retrieval as launched there: 2286 x 8192, K = 4, Poisson
-    # intensities, 17 Lanczos steps (truncation 3.0) then 5 cyclic sweeps;
-    # sampled rows against the oracle's same pipeline
+def _full_cfgs():
+    try:
+        return [c for c in range(8) if tm.tm_config_info(128, 64, c) is not None]
+    except tm.TMError:  # library not built: collected only (the run would fail on its own)
+        return [0]
+
+
+_FULL_CFGS = _full_cfgs()
+
+
+@functools.lru_cache(maxsize=1)
+def _default_path_inputs():
     n1, n2, K, P = 128, 64, 4, 2286
     N = n1 * n2
     masks = tm_synth.mask_phases(K, N, tm_synth.rng(3, 0))
     T = tm_synth.tm_iid(P, N, tm_synth.rng(921, 1)).astype(np.complex64)
     I64 = tm_synth.poisson_counts(oracle_intensities(masks, T, n1, n2), 1e4, tm_synth.rng(921, 2))
-    I, Iv = device_intensities(I64)
     v0 = tm_synth.random_start(P, N, np.ones(P), tm_synth.rng(921, 3)).astype(np.complex64)
-    tt = c64(v0)
-    raw = tm.tm_retrieve(ctx, c64(masks), I, tt, n1, n2,
-                         tm.retrieve_opts("er_cyclic", iters=5, start="lanczos", spectral_iters=17, spectral_tau=3.0))
     g = np.random.default_rng(921)
     rows = np.unique(np.concatenate([np.sort(g.choice(P, 4, replace=False)), [0, P - 1]]))
     m = masks.astype(np.complex64).astype(np.complex128)
+    Iv = I64.astype(np.float32).astype(np.float64)
     t0 = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), Iv[rows], v0[rows].astype(np.complex128), 17, tau=3.0)
     ref = rt.er_cyclic(m, n1, n2, Iv[rows], t0, 5)
+    return masks, T, I64, v0, rows, ref
+
+
+@pytest.mark.parametrize("cfg", _FULL_CFGS)
+def test_default_path_full_size_sampled_rows(ctx, cfg):
+    # the benchmark's retrieval as launched there: 2286 x 8192, K = 4, Poisson
+    # intensities, 17 Lanczos steps (truncation 3.0) then 5 cyclic sweeps, in
+    # every launch configuration the autotuner can pick for the grid; sampled
+    # rows against the oracle's same pipeline
+    n1, n2 = 128, 64
+    print(f"default path, launch configuration {cfg} {tm.tm_config_info(n1, n2, cfg)}", flush=True)
+    masks, T, I64, v0, rows, ref = _default_path_inputs()
+    I, Iv = device_intensities(I64)
+    tm.tm_set_config(ctx, n1, n2, cfg)
+    try:
+        tt = c64(v0)
+        raw = tm.tm_retrieve(ctx, c64(masks), I, tt, n1, n2,
+                             tm.retrieve_opts("er_cyclic", iters=5, start="lanczos", spectral_iters=17,
+                                              spectral_tau=3.0))
+    finally:
+        tm.tm_set_config(ctx, n1, n2, 0)
     got = tt.cpu().numpy()[rows].astype(np.complex128)
     print("default path 1-fid vs oracle", 1 - _fid(got, ref).min(), "fidelity to truth",
           rt.fidelity(got, T[rows].astype(np.complex128)).min())
