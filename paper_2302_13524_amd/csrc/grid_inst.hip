@@ -86,9 +86,10 @@ int TM_CAT(row_launchv, GL1, GL2)(int mode, int ibf16, const RowArgs& a, void* s
 
 // Wider configurations for the autotuner, cfg bits: 1 the digit order
 // (variant 1), 2 eight values per thread instead of sixteen, 4 twice the rows
-// per workgroup. They apply to the Lanczos and cyclic ER steps (the start's
-// and the iteration's kernels); every other mode runs the default plan of
-// the same digit order. Compiled for the grids of the benchmark workloads.
+// per workgroup. They apply to the iteration and start kernels the batch also
+// runs (error reduction, averaged and cyclic; heavy-ball spectral and Lanczos
+// steps); every other mode runs the default plan of the same digit order.
+// Compiled for the grids of the benchmark workloads.
 constexpr bool kExt = (GL1 == 5 && GL2 == 5) || (GL1 == 6 && GL2 == 5) || (GL1 == 6 && GL2 == 6) ||
                       (GL1 == 7 && GL2 == 6);
 
@@ -111,6 +112,11 @@ static int launch_x(int mode, const RowArgs& a, hipStream_t s) {
   switch (mode) {
     case M_LANCZOS: row_kernel_w<PX, M_LANCZOS, IT, true, WG><<<grid, block, 0, s>>>(a); break;
     case M_LANCZOS_T: row_kernel_w<PX, M_LANCZOS_T, IT, true, WG><<<grid, block, 0, s>>>(a); break;
+    case M_SPEC: row_kernel_w<PX, M_SPEC, IT, true, WG><<<grid, block, 0, s>>>(a); break;
+    case M_ER:
+      if (a.sums) row_kernel_w<PX, M_ER, IT, true, WG><<<grid, block, 0, s>>>(a);
+      else row_kernel_w<PX, M_ER, IT, false, WG><<<grid, block, 0, s>>>(a);
+      break;
     case M_ERC:
       if (a.sums) row_kernel_w<PX, M_ERC, IT, true, WG><<<grid, block, 0, s>>>(a);
       else row_kernel_w<PX, M_ERC, IT, false, WG><<<grid, block, 0, s>>>(a);
@@ -127,7 +133,7 @@ static int launch_cfg(int mode, int ibf16, const RowArgs& a, void* stream) {
     return (int)hipErrorInvalidValue;
   } else {
     hipStream_t s = (hipStream_t)stream;
-    if (mode == M_LANCZOS || mode == M_ERC)
+    if (mode == M_LANCZOS || mode == M_ERC || mode == M_ER || mode == M_SPEC)
       return ibf16 ? launch_x<typename X::PX, X::WG, uint16_t>(mode, a, s)
                    : launch_x<typename X::PX, X::WG, float>(mode, a, s);
     if (mode == M_LANCZOS_T && !ibf16) return launch_x<typename X::PX, X::WG, float>(mode, a, s);

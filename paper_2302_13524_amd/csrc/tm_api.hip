@@ -1228,7 +1228,9 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     if (p.d.P > 0 && (!p.masks || !p.I || !p.t)) { delete b; return fail(c, TM_EINVAL, "problem %d: null pointer", i); }
     b->fns.push_back(fn);
     auto v = c->variant.find((ilog2(p.d.n1) << 8) | ilog2(p.d.n2));
-    int var = (v == c->variant.end()) ? 0 : (v->second & 1);  // the batch bodies take the digit order only
+    // the batch bodies take the digit order only (eight values per thread in its 512-thread
+    // workgroups measured slower: 45.1 against 42.6 ms for 12 problems)
+    int var = (v == c->variant.end()) ? 0 : (v->second & 1);
     hp[i].code = 2 * gid + var;
     int rpi = tmk::batch_rows_per_item(gid);
     for (int blk = 0; blk * rpi < p.d.P; ++blk) items.push_back({i, blk});

@@ -75,6 +75,30 @@ def test_batch_equals_single_problem_runs(ctx, graph, mom, sp, iters, method, st
     b.close()
 
 
+def test_batch_takes_the_digit_order_of_a_wider_configuration(ctx):
+    # configuration 3 (eight values per thread, digit order 1) on every grid:
+    # the batch runs its sixteen-value bodies in digit order 1, so it equals
+    # single-problem runs in configuration 1
+    probs = make_problems(ctx, SHAPES, cfg=975)
+    try:
+        for p in probs:
+            tm.tm_set_config(ctx, p["n1"], p["n2"], 3)
+        b = tm.Batch(ctx, probs, opts(0.0, 3, 2, "er_cyclic", "lanczos"), use_graph=True)
+        for p in probs:
+            tm.tm_set_config(ctx, p["n1"], p["n2"], 1)
+        ref = singles(ctx, probs, 0.0, 3, 2, "er_cyclic", "lanczos")
+        for p in probs:
+            p["t"].copy_(p["seed"])
+        b.run()
+        torch.cuda.synchronize()
+        for p, r in zip(probs, ref):
+            assert torch.equal(p["t"], r), (p["n1"], p["n2"])
+        b.close()
+    finally:
+        for p in probs:
+            tm.tm_set_config(ctx, p["n1"], p["n2"], 0)
+
+
 def test_batch_rows_match_oracle(ctx):
     probs = make_problems(ctx, SHAPES, cfg=980)
     o = tm.retrieve_opts("er", iters=1, start="given", bf16=True)
