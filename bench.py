@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: time every compiled launch configuration of the Lanczos and cyclic ER kernels for the "
                          "grid before the timed steps and use the fastest; 0: the default configuration")
+    ap.add_argument("--config", type=int, default=None,
+                    help="use this launch configuration (tm_config_info) instead of tuning (profiling runs)")
     ap.add_argument("--gemm-probe", action="store_true",
                     help="only time the network's BF16 MFMA GEMM at the shapes of one training step (cfg4 network)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -387,7 +389,10 @@ def main():
 
     # launch configuration of the Lanczos and cyclic ER kernels for this grid (untimed)
     tune = {"config": 0}
-    if args.autotune:
+    if args.config is not None:
+        tm.tm_set_config(ctx, n1, n2, args.config)
+        tune = {"config": args.config}
+    elif args.autotune:
         tune = tm.autotune(ctx, n1, n2, K, P, space="full", reps=5)
         log(f"autotune {n1}x{n2}: config {tune['config']} {tm.tm_config_info(n1, n2, tune['config'])}")
 
