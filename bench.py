@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: time every compiled launch configuration of the Lanczos and cyclic ER kernels for the "
                          "grid before the timed steps and use the fastest; 0: the default configuration")
+    ap.add_argument("--pipeline", type=int, default=1,
+                    help="1: overlap step i's phase solve (second stream) with step i+1's retrieval; 0: serial steps")
     ap.add_argument("--config", type=int, default=None,
                     help="use this launch configuration (tm_config_info) instead of tuning (profiling runs)")
     ap.add_argument("--gemm-probe", action="store_true",
@@ -480,14 +482,52 @@ def main():
                                        ftol=args.phase_ftol)
         return t, raw, phi
 
-    for _ in range(args.warmup):
-        step()
+    # Pipelined steps: the K steps are K independent TMs, so step i's phase solve (its own library
+    # contexts, a second stream at the default priority) runs while step i + 1's retrieval runs on this
+    # stream; two row buffers alternate, and a retrieval waits for the phase solve that last read its
+    # buffer. Every step still runs its whole path inside the timed region. The phase solve's kernels are
+    # latency-bound and small, so they fill the gaps of the retrieval's CU-filling kernels.
+    if args.pipeline:
+        ctx_ph = [tm.Context(0), tm.Context(0)]  # one per buffer: each keeps its captured phase graph
+        s_ph = torch.cuda.Stream()
+        tb = [v0t.clone(), v0t.clone()]
+        pb = [torch.zeros(P, dtype=torch.float64, device=dev) for _ in range(2)]
+        ev_r = [torch.cuda.Event(), torch.cuda.Event()]
+        ev_p = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def pipelined(k):
+        main = torch.cuda.current_stream()
+        raws = [None, None]
+
+        def retrieve(i):
+            b = i % 2
+            if i >= 2:
+                main.wait_event(ev_p[b])  # step i - 2's phase solve has read this buffer
+            tb[b].copy_(v0t)
+            raws[b] = tm.tm_retrieve(ctx, mk, It, tb[b], n1, n2, sopts(n_er))
+            ev_r[b].record(main)
+
+        retrieve(0)
+        for i in range(k):
+            if i + 1 < k:
+                retrieve(i + 1)
+            b = i % 2
+            with torch.cuda.stream(s_ph):
+                s_ph.wait_event(ev_r[b])
+                pb[b].zero_()
+                tm.tm_phase_offset_correct(ctx_ph[b], pixt, tb[b], th, Idt, optics, pb[b], nf, nf, iters=n_ph,
+                                           m=args.phase_m, ftol=args.phase_ftol)
+                ev_p[b].record(s_ph)
+        main.wait_event(ev_p[(k - 1) % 2])
+        return tb[(k - 1) % 2], raws[(k - 1) % 2], pb[(k - 1) % 2]
+
+    run_steps = pipelined if args.pipeline else (lambda k: [step() for _ in range(k)][-1])
+    run_steps(max(args.warmup, 2 if args.pipeline else 0))  # with the pipeline: both phase contexts warm
     torch.cuda.synchronize()
     tm.tm_profile_enable(ctx, True)
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    for _ in range(args.steps):
-        t, raw, phi = step()
+    t, raw, phi = run_steps(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
     er_ms, er_n = tm.tm_profile_query(ctx, er_mode)
@@ -496,7 +536,7 @@ def main():
     rs_ms, rs_n = tm.tm_profile_query(ctx, 7)
     tm.tm_profile_enable(ctx, False)
     ms_step = elapsed * 1e3 / args.steps
-    ph_it, ph_ev = tm.tm_phase_last_counts(ctx)
+    ph_it, ph_ev = tm.tm_phase_last_counts(ctx_ph[(args.steps - 1) % 2] if args.pipeline else ctx)
     log(f"phase solve of the last step: {ph_it} iterations, {ph_ev} objective evaluations")
 
     # component timings (retrieval only; phase correction only; L-BFGS variant)
@@ -509,6 +549,25 @@ def main():
         return (time.perf_counter() - a) * 1e3 / reps
 
     ret_ms = timed(lambda: step(phase=False))
+    serial_kernels = None
+    if args.pipeline:
+        # the same steps one after another (no overlap): the step time, and the kernels' durations alone
+        tm.tm_profile_enable(ctx, True)
+        serial_ms = timed(step)
+        sk = {m: tm.tm_profile_query(ctx, m) for m in (sp_mode, er_mode)}
+        tm.tm_profile_enable(ctx, False)
+        serial_kernels = {"spectral_avg": round(sk[sp_mode][0] / max(sk[sp_mode][1], 1), 5),
+                          "er_avg": round(sk[er_mode][0] / max(sk[er_mode][1], 1), 5)}
+    else:
+        serial_ms = ms_step
+    if args.pipeline:
+        # the pipelined steps computed what the serial path computes
+        t_s, _, phi_s = step()
+        torch.cuda.synchronize()
+        same_t = bool(torch.equal(t_s, t))
+        same_phi = bool(torch.equal(phi_s, phi))
+        if not (same_t and same_phi):
+            raise SystemExit(f"pipelined steps differ from the serial path (t equal: {same_t}, phi equal: {same_phi})")
     roofline_lbfgs = None
     if n_lb:
         # the paper's Alg. 1: its direction kernels (dot products over the history, small solve, direction)
@@ -628,7 +687,14 @@ def main():
         "roofline_" + other: roofs[other]["alu"],
         "retrieval_ms": round(ret_ms, 3),
         "retrieval_rows_per_s": round(P / (ret_ms * 1e-3), 1),
-        "phase_correction_ms": round(ms_step - ret_ms, 3),
+        "phase_correction_ms": round(serial_ms - ret_ms, 3),
+        "pipeline": {"enabled": bool(args.pipeline), "serial_ms_per_step": round(serial_ms, 3),
+                     "serial_kernel_ms": serial_kernels,
+                     "serial_roofline_frac": ({k: round(P * flops_row / (v * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)
+                                               for k, v in serial_kernels.items()} if serial_kernels else None),
+                     "serial_rows_per_s": round(P / (serial_ms * 1e-3), 1),
+                     "note": "step i's phase solve on a second stream overlaps step i+1's retrieval; results "
+                             "checked equal to the serial path" if args.pipeline else None},
         "lbfgs": {"iters_to_0.99": n_lb, "retrieval_ms": round(lb_ms, 3) if lb_ms else None},
         "roofline_lbfgs": roofline_lbfgs,
         "autotune": {"config": tune["config"], "shape_wg_rows_values": tm.tm_config_info(n1, n2, tune["config"]),
