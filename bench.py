@@ -114,6 +114,9 @@ def parse():
                     help="only time the network's BF16 MFMA GEMM at the shapes of one training step (cfg4 network)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (reference for HBM byte counters)")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="kernel calls and durations inside the timed region of a rocprofv3 --kernel-trace "
+                         "--marker-trace run (no GPU)")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
                                                         "OUT"),
                     help="summarise rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs into the traffic file (no GPU)")
@@ -134,6 +137,7 @@ def parse():
 KERNEL_SOURCES = ["fft_core.hpp", "row_kernels.hpp", "grid_inst.hip", "grids.hpp"]
 LBFGS_SOURCES = ["lbfgs_kernels.hip", "lbfgs.hpp", "row_kernels.hpp", "fft_core.hpp", "grids.hpp"]  # with what it includes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2286x8192.json")
+TIMED_RANGE = "bench timed steps"
 
 
 def sources_digest(files=None):
@@ -240,6 +244,40 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
     print(json.dumps(res))
 
 
+def trace_summary(d, top=16):
+    """Per-kernel calls and average duration over the dispatches inside the
+    bench's timed region, from a rocprofv3 run with --kernel-trace and
+    --marker-trace (the region is the roctx range TIMED_RANGE; every kernel of
+    the timed steps starts and ends inside it, since the range opens and closes
+    on a synchronised device). Prints a markdown table."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", pattern), recursive=True):
+            out += list(csv.DictReader(open(f)))
+        return out
+
+    marks = [r for r in rows("*marker_api_trace.csv") if any(TIMED_RANGE in str(v) for v in r.values())]
+    if not marks:
+        raise SystemExit(f"no '{TIMED_RANGE}' range in {d} (run rocprofv3 with --marker-trace)")
+    lo = min(int(r["Start_Timestamp"]) for r in marks)
+    hi = max(int(r["End_Timestamp"]) for r in marks)
+    acc = {}
+    for r in rows("*kernel_trace.csv"):
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if a >= lo and b <= hi:
+            acc.setdefault(r["Kernel_Name"], []).append((b - a) * 1e-3)
+    tot = sum(sum(v) for v in acc.values())
+    print(f"timed region {(hi - lo) * 1e-6:.3f} ms, {sum(len(v) for v in acc.values())} dispatches")
+    print("| calls | avg (us) | total (ms) | share | kernel |\n|---:|---:|---:|---:|---|")
+    for k, v in sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        name = k.replace("tmk::(anonymous namespace)::", "").replace("tmk::", "")
+        print(f"| {len(v)} | {sum(v) / len(v):.2f} | {sum(v) * 1e-3:.3f} | {100 * sum(v) / tot:.1f}% | `{name[:100]}` |")
+    return acc
+
+
 def profile_lbfgs(iters):
     """One L-BFGS retrieval (Alg. 1, memory 5) of `iters` iterations on the
     benchmark workload from a spectral start, nothing else: the dispatch
@@ -322,6 +360,9 @@ def main():
     args = parse()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
         return
     if args.copy_probe:
         copy_probe()
@@ -526,10 +567,12 @@ def main():
     torch.cuda.synchronize()
     tm.tm_profile_enable(ctx, True)
     torch.cuda.synchronize()
+    torch.cuda.nvtx.range_push(TIMED_RANGE)  # a roctx range: --trace-summary picks the timed region's kernels
     ts = time.perf_counter()
     t, raw, phi = run_steps(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
+    torch.cuda.nvtx.range_pop()
     er_ms, er_n = tm.tm_profile_query(ctx, er_mode)
     sp_mode = 13 if args.start == "lanczos" else 5  # row-kernel mode of the spectral start's step
     sp_ms, sp_n = tm.tm_profile_query(ctx, sp_mode)

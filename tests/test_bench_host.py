@@ -80,3 +80,23 @@ def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, mon
 def test_sources_digest_is_stable():
     assert bench.sources_digest() == bench.sources_digest()
     assert len(bench.sources_digest()) == 64
+
+
+def test_trace_summary_keeps_the_timed_region(tmp_path):
+    # kernels that start and end inside the roctx range are the timed region's
+    d = str(tmp_path)
+    with open(os.path.join(d, "x_marker_api_trace.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Domain", "Function", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        w.writerow({"Domain": "MARKER_CORE_API", "Function": bench.TIMED_RANGE, "Start_Timestamp": 1000,
+                    "End_Timestamp": 5000})
+        w.writerow({"Domain": "MARKER_CORE_API", "Function": "other", "Start_Timestamp": 0, "End_Timestamp": 9000})
+    with open(os.path.join(d, "x_kernel_trace.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for a, b, n in ((500, 900, "k"), (1100, 1500, "k"), (2000, 2600, "k"), (4900, 5100, "k"), (3000, 3100, "j")):
+            w.writerow({"Kernel_Name": n, "Start_Timestamp": a, "End_Timestamp": b})
+    acc = bench.trace_summary(d)
+    assert sorted(acc["k"]) == [0.4, 0.6] and acc["j"] == [0.1]
+    with pytest.raises(SystemExit):
+        bench.trace_summary(str(tmp_path / "missing"))
