@@ -660,6 +660,14 @@ __global__ void __launch_bounds__(256) k_gather(double* grad, double* gval, cons
 // Unitary scales as in the separable path: 1/(2 nf1 nf2) for the forward
 // chain and for the adjoint chain.
 constexpr int BM = 16;           // largest box side
+// Field values per workgroup of the spectrum pass (RA = SPEC_FIELD / nf2 rows)
+// and blocks of 256 pixels per workgroup of the pass back to the pixels (which
+// share one image's Z). Measured at 64 x 64 with 50 images: 1024 values and 3
+// blocks (200 and 150 workgroups per evaluation instead of 400 and 450) left
+// the pipelined step unchanged (10.23 against 10.28 ms) and made the phase
+// solve alone 0.1 ms slower.
+constexpr int SPEC_FIELD = 512;
+constexpr int PIX_BLOCKS = 1;
 
 __device__ __forceinline__ z2 zfma(z2 a, z2 b, z2 acc) {  // acc + a b
   return {acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
@@ -679,22 +687,23 @@ __global__ void __launch_bounds__(256) k_band_spec(double* Sp, const double* c, 
                                                    const int32_t* inv, PhaseBand b, int P, int nf1, int nf2,
                                                    const double* tw64, const int* skip) {
   if (skip && *skip) return;
-  __shared__ z2 F[512];
-  __shared__ z2 S1[512];
+  __shared__ z2 F[SPEC_FIELD];
+  __shared__ z2 S1[SPEC_FIELD];  // RA B2 <= (SPEC_FIELD / nf2) nf2 outputs
   __shared__ z2 tw1[256], tw2[256];
   const int ch = blockIdx.x, n = blockIdx.y, a0 = ch * b.RA;
-  const int ne = b.RA * nf2;  // <= 512 field values
-  // the block's field values: pixel rows first (two per thread, loads issued together)
-  int pp[2];
+  const int ne = b.RA * nf2;  // <= SPEC_FIELD field values
+  // the block's field values: pixel rows first (loads issued together)
+  constexpr int FPT = SPEC_FIELD / 256;
+  int pp[FPT];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < FPT; ++k) {
     const int t = threadIdx.x + k * 256;
     pp[k] = (t < ne) ? inv[(size_t)a0 * nf2 + t] : -1;
   }
   load_tab(tw1, tw64, nf1, 256);
   load_tab(tw2, tw64, nf2, 256);
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < FPT; ++k) {
     const int t = threadIdx.x + k * 256;
     z2 v{0.0, 0.0};
     if (pp[k] >= 0) {
@@ -709,8 +718,8 @@ __global__ void __launch_bounds__(256) k_band_spec(double* Sp, const double* c, 
   const int nout = b.RA * b.B2;
   int q = 1;
   while (q < 16 && nout * q * 2 <= 256) q *= 2;
-  {
-    const int o = threadIdx.x / q, part = threadIdx.x - o * q;
+  for (int o0 = 0; o0 < nout; o0 += 256 / q) {  // more outputs than thread groups: several rounds
+    const int o = o0 + threadIdx.x / q, part = threadIdx.x % q;
     z2 acc{0.0, 0.0};
     if (o < nout) {
       const int r = o / b.B2, j2 = o - r * b.B2;
@@ -892,12 +901,18 @@ __global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vp, 
   __shared__ z2 Z[BM * 256];
   __shared__ z2 tw1[256], tw2[256];
   const int n = blockIdx.y;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  int g = 0;
-  z2 cv{0.0, 0.0};
-  if (p < P) {
-    g = pix[p];
-    cv = ldz(c, (size_t)n * P + p);
+  // PIX_BLOCKS blocks of 256 pixels per workgroup share its V and Z (their loads issued first)
+  int g[PIX_BLOCKS];
+  z2 cv[PIX_BLOCKS];
+#pragma unroll
+  for (int k = 0; k < PIX_BLOCKS; ++k) {
+    const int p = (blockIdx.x * PIX_BLOCKS + k) * 256 + threadIdx.x;
+    g[k] = 0;
+    cv[k] = z2{0.0, 0.0};
+    if (p < P) {
+      g[k] = pix[p];
+      cv[k] = ldz(c, (size_t)n * P + p);
+    }
   }
   // V = conj(h) sc (sum of the image pass's column-block partials)
   const double sc = 1.0 / (2.0 * (double)nf1 * (double)nf2);
@@ -928,14 +943,18 @@ __global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vp, 
     Z[j1 * nf2 + bb] = acc;
   }
   __syncthreads();
-  if (p < P) {
-    const int a = g / nf2, bb = g & (nf2 - 1);
-    z2 acc{0.0, 0.0};
-    for (int j1 = 0; j1 < b.B1; ++j1) {
-      const int sm = (b.s1lo + j1) & (nf1 - 1);
-      acc = zfmac(Z[j1 * nf2 + bb], tw1[(sm * a) & (nf1 - 1)], acc);
+#pragma unroll
+  for (int k = 0; k < PIX_BLOCKS; ++k) {
+    const int p = (blockIdx.x * PIX_BLOCKS + k) * 256 + threadIdx.x;
+    if (p < P) {
+      const int a = g[k] / nf2, bb = g[k] & (nf2 - 1);
+      z2 acc{0.0, 0.0};
+      for (int j1 = 0; j1 < b.B1; ++j1) {
+        const int sm = (b.s1lo + j1) & (nf1 - 1);
+        acc = zfmac(Z[j1 * nf2 + bb], tw1[(sm * a) & (nf1 - 1)], acc);
+      }
+      stz(Wn, (size_t)n * P + p, zmulc(acc, cv[k]));
     }
-    stz(Wn, (size_t)n * P + p, zmulc(acc, cv));
   }
 }
 
@@ -982,7 +1001,7 @@ __global__ void __launch_bounds__(256) k_band_gather(double* grad, double* gval,
 
 // pass geometry (depends on the dimensions only, except BT1 and G: the plan sets them)
 void band_geometry(const PhaseDims& d, PhaseBand* b) {
-  b->RA = std::max(1, std::min(d.nf1, 512 / d.nf2));
+  b->RA = std::max(1, std::min(d.nf1, SPEC_FIELD / d.nf2));
   b->CH = d.nf1 / b->RA;
 }
 
@@ -1123,7 +1142,7 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
       case 8: k_band_img<8><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
       default: k_band_img<16><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip);
     }
-    k_band_pix<<<dim3((d.P + 255) / 256, d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, w.h, pix, b, d.P, d.nf1, d.nf2, tw64,
+    k_band_pix<<<dim3((d.P + 256 * PIX_BLOCKS - 1) / (256 * PIX_BLOCKS), d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, w.h, pix, b, d.P, d.nf1, d.nf2, tw64,
                                                              w.skip);
     k_band_gather<<<(d.P + 63) / 64, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
                                                   w.skip, dvec, w.dpart);
