@@ -25,6 +25,7 @@ struct BatchProb {
   const float* rowmean;
   cx<float>* lzV;       // Lanczos basis v_2 .. v_{k+1} [k][P][N] (v_1 is t)
   float* lzH;           // Lanczos (alpha, beta) [k][P][2]
+  const double* lzY;    // Ritz coefficients [P][k]
   int K, P, code, N;
 };
 
@@ -41,6 +42,8 @@ struct BatchArgs {
   float er_beta;         // ER Nesterov factor; t and t_prev alternate between t and vprev
   int swap;              // spectral steps, ER with er_beta: the current iterate is in vprev (odd steps)
   int lz_j;              // Lanczos step index (BATCH_LZ)
+  int lz_fuse;           // BATCH_ERC: this sweep forms each row's Ritz vector from lz_k basis rows first
+  int lz_k;
   const cx<float>* tw32;
 };
 

@@ -88,6 +88,18 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
       a.lz_bprev = j > 0 ? pr.lzH + (size_t)(j - 1) * pr.P * 2 : nullptr;
       a.lz_out = pr.lzH + (size_t)j * pr.P * 2;
     }
+    a.lz_basis = nullptr;
+    a.lz_y = nullptr;
+    a.lz_k = 0;
+    a.lz_rs = 0;
+    if constexpr (MODE == BATCH_ERC) {
+      if (b.lz_fuse) {
+        a.lz_basis = pr.lzV;
+        a.lz_y = pr.lzY;
+        a.lz_k = b.lz_k;
+        a.lz_rs = (int64_t)pr.P * pr.N;
+      }
+    }
     a.out_bf16 = 0;
     a.tw32 = b.tw32;
     a.tw64 = nullptr;

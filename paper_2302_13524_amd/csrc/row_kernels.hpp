@@ -58,6 +58,13 @@ struct RowArgs {
   int out_bf16;            // M_FWD_INT output type
   const cx<float>* tw32;   // twiddle tables, table of length L at offset L-1
   const cx<double>* tw64;
+  // M_ERC with lz_k > 0: the row is the Ritz vector sum_j y_j v_j of a Lanczos
+  // start, formed in the prologue (v_1 = tin, v_j = lz_basis + (j - 2) lz_rs
+  // for j >= 2, y = lz_y [P][lz_k]); the projection does not depend on its scale
+  const cx<float>* lz_basis;
+  const double* lz_y;
+  int lz_k;
+  int64_t lz_rs;
 };
 
 __device__ __forceinline__ float bf16_to_f(uint16_t b) {
@@ -277,6 +284,36 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
         C tp = gload(drow + E0(i));
         treg[i] = C{treg[i].x + b * (treg[i].x - tp.x), treg[i].y + b * (treg[i].y - tp.y)};
       }
+    }
+  }
+  if constexpr (MODE == M_ERC) {
+    if (a.lz_k > 0) {
+      // t = sum_j y_j v_j with FP64 sums in basis order (the same sums as the
+      // separate combination kernel), v_1 already in registers
+      const double* yp = a.lz_y + prow * a.lz_k;
+      double ax[E], ay[E];
+      const double w0 = yp[0];
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        ax[i] = w0 * treg[i].x;
+        ay[i] = w0 * treg[i].y;
+      }
+      // one basis row at a time (groups of rows in flight measured no faster: one
+      // workgroup per CU, so these loads do not overlap the transforms either way)
+      for (int j = 1; j < a.lz_k; ++j) {
+        const C* vr = a.lz_basis + (size_t)(j - 1) * a.lz_rs + prow * N;
+        const double w = yp[j];
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = gload(vr + E0(i));
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          ax[i] += w * v[i].x;
+          ay[i] += w * v[i].y;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < E; ++i) treg[i] = C{(float)ax[i], (float)ay[i]};
     }
   }
 #define TROW(i) treg[i]

@@ -167,6 +167,16 @@ int check_dims(tm_ctx* c, const tm_dims& d, tmk::row_launcher* fn) {
   return TM_OK;
 }
 
+// The first of two or more cyclic sweeps forms the Lanczos start's Ritz vector
+// itself (from the basis rows and the Ritz coefficients): its projections do
+// not depend on the row's scale, so the separate combination and rescaling
+// passes are skipped. With one sweep the last sweep's sums would see the
+// unscaled row, so the combination stays separate.
+bool ritz_in_sweep(const tm_retrieve_opts& o) {
+  return o.method == TM_METHOD_ER_CYCLIC && o.iters >= 2 &&
+         (o.start == TM_START_LANCZOS || o.start == TM_START_LEARNED);
+}
+
 tmk::RowArgs base_args(tm_ctx* c, const tm_dims& d, const tm_c32* masks) {
   tmk::RowArgs a;
   memset(&a, 0, sizeof a);
@@ -464,6 +474,9 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
   tmk::RowArgs a = base_args(c, d, masks);
   a.I = I;
   tmk::cx<float>* tt = (tmk::cx<float>*)t;
+  const tmk::cx<float>* ritz_basis = nullptr;  // Lanczos basis and Ritz coefficients for the first sweep
+  const double* ritz_y = nullptr;
+  int ritz_k = 0;
 
   // ---- start
   if (o->start == TM_START_BACKPROP) {
@@ -538,8 +551,13 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
       if (r) return r;
     }
     e = tmk::launch_lz_ritz(hist, k, d.P, y, stream);
-    if (!e) e = tmk::launch_lz_combine_scaled(t, Vw, y, k, d.P, N, rowsum, (double)d.K * N, stream);
+    if (!e && !ritz_in_sweep(*o)) e = tmk::launch_lz_combine_scaled(t, Vw, y, k, d.P, N, rowsum, (double)d.K * N, stream);
     if (e) return hipfail(c, e, "Lanczos Ritz vector");
+    if (ritz_in_sweep(*o)) {  // the first cyclic sweep forms the Ritz vector (its scale does not matter there)
+      ritz_basis = Vw;
+      ritz_y = y;
+      ritz_k = k;
+    }
   }
 
   // ---- iterations
@@ -549,7 +567,14 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     a.tout = tt;
     for (int it = 0; it < o->iters; ++it) {
       a.sums = (it == o->iters - 1) ? sums : nullptr;  // only the last sweep's sums are reported
-      r = run_row(c, fn, tmk::M_ERC, ibf, a, stream);
+      tmk::RowArgs s = a;
+      if (it == 0 && ritz_k > 0) {
+        s.lz_basis = ritz_basis;
+        s.lz_y = ritz_y;
+        s.lz_k = ritz_k;
+        s.lz_rs = (int64_t)d.P * N;
+      }
+      r = run_row(c, fn, tmk::M_ERC, ibf, s, stream);
       if (r) return r;
     }
     if (o->iters > 0) {
@@ -1138,8 +1163,9 @@ static int batch_enqueue(tm_batch* b, void* stream) {
       if (!p.d.P) continue;
       const int N = p.d.n1 * p.d.n2;
       e = tmk::launch_lz_ritz(b->lzH[i], o.spectral_iters, p.d.P, b->lzY[i], stream);
-      if (!e) e = tmk::launch_lz_combine_scaled(p.t, b->lzV[i], b->lzY[i], o.spectral_iters, p.d.P, N,
-                                                b->rowsum[i], (double)p.d.K * N, stream);
+      if (!e && !ritz_in_sweep(o))
+        e = tmk::launch_lz_combine_scaled(p.t, b->lzV[i], b->lzY[i], o.spectral_iters, p.d.P, N, b->rowsum[i],
+                                          (double)p.d.K * N, stream);
     }
   } else if (o.start == TM_START_BACKPROP) {
     for (int i = 0; i < n && !e; ++i) {
@@ -1165,6 +1191,8 @@ static int batch_enqueue(tm_batch* b, void* stream) {
   }
   for (int it = 0; it < o.iters && !e; ++it) {
     ea.swap = mom ? (it & 1) : 0;
+    ea.lz_fuse = (it == 0 && o.start == TM_START_LANCZOS && ritz_in_sweep(o)) ? 1 : 0;
+    ea.lz_k = o.spectral_iters;
     e = tmk::batch_launch(cyclic ? tmk::BATCH_ERC : tmk::BATCH_ER, ibf, it == o.iters - 1, ea, b->grid, stream);
   }
   if (mom && (o.iters & 1)) {
@@ -1262,6 +1290,7 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     }
     hp[i].lzV = (tmk::cx<float>*)b->lzV[i];
     hp[i].lzH = b->lzH[i];
+    hp[i].lzY = b->lzY[i];
     hp[i].N = (int)N;
     hp[i].masks = (const tmk::cx<float>*)p.masks;
     hp[i].I = p.I;
