@@ -502,7 +502,7 @@ int tm_pre_gather(tm_ctx *ctx, const void *stack, int32_t stack_dtype, int64_t n
  * Validation by foci (Sec. 3): the phase of the conjugate of each row of
  * tm_est, u_p = exp(-j arg tm_est[p]) (1 where tm_est is 0), is displayed on
  * the modulator; the focus image is |sum_n tm_true[q][n] u_p[n]|^2 over the
- * rows q of tm_true (one complex FP32 GEMM through rocBLAS), and its power
+ * rows q of tm_true (one complex FP32 GEMM, tm_cgemm_f32), and its power
  * ratio is the power in the (2w+1) x (2w+1) grid window around the brightest
  * pixel (first in raster order on ties; the window is clipped at the grid
  * border) over the image's total power (w = 3: the paper's 7 x 7 window).
@@ -518,9 +518,20 @@ int tm_foci_power_ratio(tm_ctx *ctx, int32_t Pf, int32_t G, int32_t N, const tm_
 /* Comparator without FFTs (Sec. 2.2, Table time): the gradient of
  * f(t) = ||I - |Q t|^2||^2 for an explicit dense probing matrix Q [M][N]
  * (e.g. random phases), grad = -4 Q^H((Q t)(I - |Q t|^2)), as two complex
- * FP32 GEMMs (rocBLAS, Theta(M N) per row) around a fused pointwise kernel.
+ * FP32 GEMMs (tm_cgemm_f32, Theta(M N) per row) around a fused pointwise kernel.
  *   Q [M][N] tm_c32, I [P][M] float, t [P][N] tm_c32, grad [P][N] tm_c32,
  *   f [P] float (may be NULL). Workspace P M complex floats. */
+/* Complex FP32 GEMM on the matrix cores (the products of the foci and of the
+ * dense comparator): C = A op(B), op(B) = B^T when trans_b (B stored [N][K])
+ * and B otherwise (stored [K][N]); conj(C) when conj_c. Row-major complex64
+ * device arrays with leading dimensions (in complex elements) lda >= K,
+ * ldb >= K (trans_b) or >= N, ldc >= N; C must not overlap A or B. FP32
+ * products and sums (32 x 32 x 2 FP32 MFMAs over K, one per real and one per
+ * imaginary part). TM_EINVAL on bad sizes or null pointers; M or N = 0 does
+ * nothing. */
+int tm_cgemm_f32(tm_ctx *ctx, int32_t M, int32_t N, int32_t K, const tm_c32 *A, int64_t lda, const tm_c32 *B,
+                 int64_t ldb, int32_t trans_b, tm_c32 *C, int64_t ldc, int32_t conj_c, void *stream);
+
 int tm_dense_gradient(tm_ctx *ctx, int32_t M, int32_t N, int32_t P, const tm_c32 *Q, const float *I,
                       const tm_c32 *t, tm_c32 *grad, float *f, void *stream);
 

@@ -36,6 +36,7 @@ EXPORTED = (
     "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band", "tm_phase_last_counts",
     "tm_retrieve_noalloc", "tm_wnet_table", "tm_wnet_pretrain_step", "tm_wtab_power_grad", "tm_wnet_train_step",
     "tm_set_weight_table", "tm_retrieve_learned", "tm_config_info", "tm_set_config", "tm_tune_config",
+    "tm_cgemm_f32",
 )
 TM_NOALLOC_MAX_ROWS = 32768
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
@@ -148,6 +149,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_set_variant.argtypes = [vp, i32, i32, i32]
     lib.tm_config_info.argtypes = [i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.tm_set_config.argtypes = [vp, i32, i32, i32]
+    lib.tm_cgemm_f32.argtypes = [vp, i32, i32, i32, vp, ctypes.c_int64, vp, ctypes.c_int64, i32, vp, ctypes.c_int64,
+                                 i32, vp]
     lib.tm_tune_config.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(dp)]
     lib.tm_phase_set_band.argtypes = [vp, i32]
     lib.tm_phase_last_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -732,6 +735,21 @@ def tm_phase_last_counts(ctx: Context):
 
 def tm_set_variant(ctx: Context, n1, n2, variant):
     ctx.check(ctx.lib.tm_set_variant(ctx.h, n1, n2, variant), "tm_set_variant")
+
+
+def tm_cgemm_f32(ctx: Context, A, B, trans_b=False, conj_c=False):
+    """C = A op(B) (complex64 on the device, matrix cores): A [M, K]; B [N, K]
+    with trans_b, else [K, N]; conj(C) with conj_c."""
+    if not isinstance(A, torch.Tensor) or not isinstance(B, torch.Tensor) or A.dim() != 2 or B.dim() != 2:
+        raise TMError("A and B must be 2-D tensors")
+    M, K = A.shape
+    N = B.shape[0] if trans_b else B.shape[1]
+    _chk(A, "A", (M, K), _C64)
+    _chk(B, "B", (N, K) if trans_b else (K, N), _C64, A.device)
+    C = torch.empty((M, N), dtype=torch.complex64, device=A.device)
+    ctx.check(ctx.lib.tm_cgemm_f32(ctx.h, M, N, K, _ptr(A), K, _ptr(B), B.shape[1], int(bool(trans_b)), _ptr(C), N,
+                                   int(bool(conj_c)), _stream(A.device)), "tm_cgemm_f32")
+    return C
 
 
 def tm_config_info(n1, n2, cfg):

@@ -71,7 +71,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     objs = [u[-1] for u in units]
     tmp = LIB + ".tmp"
     cmd, rc, err = _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-                         "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
+                         "-Wl,-rpath,/opt/rocm/lib"])
     if rc != 0:
         raise RuntimeError("link failed:\n" + err)
     os.replace(tmp, LIB)

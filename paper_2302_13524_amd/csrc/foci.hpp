@@ -21,6 +21,10 @@ namespace tmk {
 // afterwards grad = conj(H) in place.
 int launch_dense_pointwise(void* Y, const float* I, int P, int64_t M, float* f, void* stream);
 int launch_conj_inplace(void* x, int64_t n, void* stream);
+// C [M][N] = A [M][K] op(B) in complex FP32 on the matrix cores: B is [N][K]
+// (trans_b) or [K][N]; conj_c stores conj(C). hipErrorInvalidValue on bad sizes.
+int launch_cgemm(int M, int N, int K, const void* A, int64_t lda, const void* B, int64_t ldb, int trans_b, void* C,
+                 int64_t ldc, int conj_c, void* stream);
 }  // namespace tmk
 
 namespace tmk {

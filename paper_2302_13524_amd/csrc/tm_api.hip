@@ -14,7 +14,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
 
 #include "../../include/tm.h"
 #include "aux.hpp"
@@ -52,7 +51,6 @@ struct tm_ctx {
   int64_t acc_n[TM_PROF_MODES] = {0};
   std::map<int, int> variant;  // (L1 << 8 | L2) -> launch configuration (bit 0: FFT digit-order variant)
   double* pinned = nullptr;    // 8 doubles of pinned host memory for read-backs
-  rocblas_handle blas = nullptr;  // plain complex GEMM of the foci synthesis
   int phase_band = 1;             // band evaluation of the defocus model when the pupil's box is small
   // The captured phase iteration of the last tm_phase_offset_correct call, reused
   // while everything it captured (pointers, sizes, options, band plan) is unchanged.
@@ -313,7 +311,6 @@ int tm_destroy(tm_ctx* c) {
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->pinned) hipHostFree(c->pinned);
   phase_graph_release(c);
-  if (c->blas) rocblas_destroy_handle(c->blas);
   for (auto& kv : c->ws) hipFree(kv.second.p);
   hipFree(c->tw32);
   hipFree(c->tw64);
@@ -1566,7 +1563,6 @@ extern "C" int tm_pre_gather(tm_ctx* c, const void* stack, int32_t stack_dtype, 
 }
 
 // ------------------------------------------------------------ foci and power ratio
-static int blas_ready(tm_ctx* c, void* stream);
 
 extern "C" int tm_foci_power_ratio(tm_ctx* c, int32_t Pf, int32_t G, int32_t N, const tm_c32* tm_true,
                                    const int32_t* pix, const tm_c32* tm_est, int32_t g1, int32_t g2, int32_t w,
@@ -1590,29 +1586,29 @@ extern "C" int tm_foci_power_ratio(tm_ctx* c, int32_t Pf, int32_t G, int32_t N, 
   void* u = ws_get(c, WS_FOCI_U, (size_t)Pf * N * sizeof(tm_c32));
   void* E = ws_get(c, WS_FOCI_E, (size_t)Pf * G * sizeof(tm_c32));
   if (!u || !E) return fail(c, TM_ENOMEM, "workspace");
-  int r = blas_ready(c, stream);
-  if (r) return r;
   int e = tmk::launch_conj_phase(tm_est, u, (int64_t)Pf * N, stream);
   if (e) return hipfail(c, e, "conjugate phase");
-  // E[p][q] = sum_n u[p][n] tm_true[q][n]: in column-major terms E^T = T^T U with T (N x G), U (N x Pf)
-  const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
-  if (rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, G, Pf, N, &one,
-                    (const rocblas_float_complex*)tm_true, N, (const rocblas_float_complex*)u, N, &zero,
-                    (rocblas_float_complex*)E, G) != rocblas_status_success)
-    return fail(c, TM_EHIP, "rocblas_cgemm failed");
+  // E[p][q] = sum_n u[p][n] tm_true[q][n] (both operands n-contiguous)
+  e = tmk::launch_cgemm(Pf, G, N, u, N, tm_true, N, 1, E, G, 0, stream);
+  if (e) return hipfail(c, e, "foci GEMM");
   e = tmk::launch_foci_pr(E, Pf, G, pix, g1, g2, w, pr, peak, stream);
   if (e) return hipfail(c, e, "power ratio");
   return TM_OK;
 }
 
 // ------------------------------------------------------------ dense-probing comparator
-static int blas_ready(tm_ctx* c, void* stream) {
-  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
-    c->blas = nullptr;
-    return fail(c, TM_EHIP, "rocblas_create_handle failed");
-  }
-  if (rocblas_set_stream(c->blas, (hipStream_t)stream) != rocblas_status_success)
-    return fail(c, TM_EHIP, "rocblas_set_stream failed");
+extern "C" int tm_cgemm_f32(tm_ctx* c, int32_t M, int32_t N, int32_t K, const tm_c32* A, int64_t lda,
+                            const tm_c32* B, int64_t ldb, int32_t trans_b, tm_c32* C, int64_t ldc, int32_t conj_c,
+                            void* stream) {
+  if (!c) return TM_EINVAL;
+  if (M < 0 || N < 0 || K < 1) return fail(c, TM_EINVAL, "M, N >= 0 and K >= 1");
+  if (M == 0 || N == 0) return TM_OK;
+  if (!A || !B || !C) return fail(c, TM_EINVAL, "null pointer argument");
+  if (lda < K || (trans_b ? ldb < K : ldb < N) || ldc < N) return fail(c, TM_EINVAL, "leading dimensions too small");
+  if ((M + 127) / 128 > 65535) return fail(c, TM_EINVAL, "M=%d too large", M);
+  HIPCHK(c, hipSetDevice(c->device));
+  int e = tmk::launch_cgemm(M, N, K, A, lda, B, ldb, trans_b ? 1 : 0, C, ldc, conj_c ? 1 : 0, stream);
+  if (e) return hipfail(c, e, "complex GEMM");
   return TM_OK;
 }
 
@@ -1625,23 +1621,14 @@ extern "C" int tm_dense_gradient(tm_ctx* c, int32_t M, int32_t N, int32_t P, con
   HIPCHK(c, hipSetDevice(c->device));
   void* Y = ws_get(c, WS_DENSE_Y, (size_t)P * M * sizeof(tm_c32));
   if (!Y) return fail(c, TM_ENOMEM, "workspace");
-  int r = blas_ready(c, stream);
-  if (r) return r;
-  const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
-  // Y [P][M] = t Q^T: column-major Y (M x P) = Q_cm^T t_cm with Q_cm (N x M), t_cm (N x P)
-  if (rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, M, P, N, &one,
-                    (const rocblas_float_complex*)Q, N, (const rocblas_float_complex*)t, N, &zero,
-                    (rocblas_float_complex*)Y, M) != rocblas_status_success)
-    return fail(c, TM_EHIP, "rocblas_cgemm failed");
-  int e = tmk::launch_dense_pointwise(Y, I, P, M, f, stream);
+  // Y [P][M] = t Q^T (both operands n-contiguous)
+  int e = tmk::launch_cgemm(P, M, N, t, N, Q, N, 1, Y, M, 0, stream);
+  if (e) return hipfail(c, e, "dense GEMM");
+  e = tmk::launch_dense_pointwise(Y, I, P, M, f, stream);
   if (e) return hipfail(c, e, "dense pointwise");
-  // conj(grad) [P][N] = Q_cm conj(w): column-major (N x P) = (N x M)(M x P)
-  if (rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_none, N, P, M, &one,
-                    (const rocblas_float_complex*)Q, N, (const rocblas_float_complex*)Y, M, &zero,
-                    (rocblas_float_complex*)grad, N) != rocblas_status_success)
-    return fail(c, TM_EHIP, "rocblas_cgemm failed");
-  e = tmk::launch_conj_inplace(grad, (int64_t)P * N, stream);
-  if (e) return hipfail(c, e, "conjugate");
+  // grad [P][N] = conj(Y' Q) with Y' = conj(w) from the pointwise kernel (Q read [M][N], n-contiguous)
+  e = tmk::launch_cgemm(P, N, M, Y, M, Q, N, 0, grad, N, 1, stream);
+  if (e) return hipfail(c, e, "dense GEMM");
   return TM_OK;
 }
 
