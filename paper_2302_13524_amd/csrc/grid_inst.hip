@@ -12,7 +12,9 @@ namespace tmk {
 #define TM_CAT2(a, b, c) a##_##b##_##c
 #define TM_CAT(a, b, c) TM_CAT2(a, b, c)
 
-using PLd = Plan<GL1, GL2, (GL1 + GL2 >= 4) ? 4 : GL1 + GL2>;  // FP64 residual: 16 values per thread
+// FP64 residual: 8 values per thread (at 128 x 64: 1024 threads, 128 VGPRs, four
+// waves per SIMD; 16 values per thread took 248 VGPRs and two waves)
+using PLd = Plan<GL1, GL2, (GL1 + GL2 >= 3) ? 3 : GL1 + GL2>;
 
 template <class PLg, typename IT>
 static int launch_t(int mode, const RowArgs& a, hipStream_t s) {
