@@ -562,7 +562,13 @@ def main():
         main.wait_event(ev_p[(k - 1) % 2])
         return tb[(k - 1) % 2], raws[(k - 1) % 2], pb[(k - 1) % 2]
 
-    run_steps = pipelined if args.pipeline else (lambda k: [step() for _ in range(k)][-1])
+    def serial_steps(k):
+        out = None
+        for _ in range(k):
+            out = step()
+        return out
+
+    run_steps = pipelined if args.pipeline else serial_steps
     run_steps(max(args.warmup, 2 if args.pipeline else 0))  # with the pipeline: both phase contexts warm
     torch.cuda.synchronize()
     tm.tm_profile_enable(ctx, True)
