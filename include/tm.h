@@ -304,6 +304,33 @@ int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_
                             const tm_optics *optics, double *phi, const tm_phase_opts *opts,
                             double *g_out, void *stream);
 
+/* The same solve (Eq. phaseoffset, Eq. optphase, Eq. phasederive), stream-
+ * ordered: queues the start, `evals` iterations of the device-side L-BFGS
+ * (each decides the pending trial, moves or changes the step, and evaluates
+ * the next trial; once the solve has ended an iteration returns at once) and
+ * the result, then returns without waiting, so that a caller can overlap the
+ * solve with work on another stream. A solve of opts->iters iterations needs
+ * as many iterations here as the evaluations tm_phase_last_counts reports for
+ * it (the start point's included).
+ *   evals  iterations to queue, 1 .. 40 * opts->iters + 2 (ignored when
+ *          opts->iters == 0); with fewer than the solve needs, each of them
+ *          evaluates a trial (rec[2] = evals + 1) and rec[3] stays 0
+ *   rec    device double[7], written when the queued work runs:
+ *          [0] objective g, [1] accepted iterations, [2] evaluations,
+ *          [3] 1 if the solve ended within `evals` or the pixel check
+ *          failed (0: phi holds the iterate reached), [4] pixel check (0: pix valid; bit 0: an entry
+ *          outside the grid, bit 1: a pixel shared by two rows, phi then
+ *          unchanged), [5], [6] the offending rows.
+ * Other arguments as tm_phase_offset_correct. Allocates its workspace on
+ * the first call of a size, as that call does; tm_phase_last_counts keeps
+ * reporting the last synchronous call. Errors: TM_EINVAL for bad sizes,
+ * optics or options, evals out of range or rec NULL, returned at once; pix
+ * errors only through rec[4]. */
+int tm_phase_offset_correct_async(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,
+                                  const tm_c32 *tm_est, const tm_c32 *theta, const float *I_d,
+                                  const tm_optics *optics, double *phi, const tm_phase_opts *opts,
+                                  int32_t evals, double *rec, void *stream);
+
 /* Counts of the last tm_phase_offset_correct call on ctx (0 before any):
  * accepted L-BFGS iterations and objective evaluations, the start point's
  * included. The first direction is -sqrt(P) g/||g|| (a = 1 moves the

@@ -36,7 +36,7 @@ EXPORTED = (
     "tm_dense_gradient", "tm_propagate_tm", "tm_phase_set_band", "tm_phase_last_counts",
     "tm_retrieve_noalloc", "tm_wnet_table", "tm_wnet_pretrain_step", "tm_wtab_power_grad", "tm_wnet_train_step",
     "tm_set_weight_table", "tm_retrieve_learned", "tm_config_info", "tm_set_config", "tm_tune_config",
-    "tm_cgemm_f32",
+    "tm_cgemm_f32", "tm_phase_offset_correct_async",
 )
 TM_NOALLOC_MAX_ROWS = 32768
 MODE_NAMES = {0: "forward_field", 1: "forward_intensity", 2: "adjoint", 3: "er", 4: "gradient", 5: "spectral",
@@ -129,6 +129,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_phase_offset_correct.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
                                             ctypes.POINTER(tm_optics), vp, ctypes.POINTER(tm_phase_opts),
                                             ctypes.POINTER(dp), vp]
+    lib.tm_phase_offset_correct_async.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
+                                                   ctypes.POINTER(tm_optics), vp, ctypes.POINTER(tm_phase_opts),
+                                                   i32, vp, vp]
     lib.tm_phase_objective.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp, vp,
                                        ctypes.POINTER(tm_optics), vp, vp, vp, vp]
     lib.tm_defocus_forward.argtypes = [vp, ctypes.POINTER(tm_defocus_dims), vp, vp, vp,
@@ -448,6 +451,23 @@ def tm_phase_offset_correct(ctx: Context, pix, tm_est, theta, I_d, optics, phi, 
                                          ctypes.byref(g), _stream(tm_est.device))
     ctx.check(rc, "tm_phase_offset_correct")
     return g.value
+
+
+def tm_phase_offset_correct_async(ctx: Context, pix, tm_est, theta, I_d, optics, phi, nf1, nf2, rec, evals,
+                                  iters=100, m=5, ftol=0.0):
+    """Stream-ordered phase solve: queues `evals` device L-BFGS iterations and returns at once; the
+    record (g, iterations, evaluations, ended, pixel check, rows) lands in rec ([>= 7] float64, device)."""
+    P, N, Nd = _defocus_args(pix, tm_est, theta, nf1, nf2, I_d, phi)
+    if not (isinstance(rec, torch.Tensor) and rec.dtype == torch.float64 and rec.is_contiguous()
+            and rec.numel() >= 7 and rec.device == tm_est.device):
+        raise TMError("rec must be a contiguous float64 tensor of >= 7 values on the device of tm_est")
+    dd = _ddims(P, N, Nd, nf1, nf2)
+    op = tm_optics(*[float(v) for v in optics])
+    po = tm_phase_opts(int(iters), int(m), float(ftol))
+    rc = ctx.lib.tm_phase_offset_correct_async(ctx.h, ctypes.byref(dd), _ptr(pix), _ptr(tm_est), _ptr(theta),
+                                               _ptr(I_d), ctypes.byref(op), _ptr(phi), ctypes.byref(po),
+                                               int(evals), _ptr(rec), _stream(tm_est.device))
+    ctx.check(rc, "tm_phase_offset_correct_async")
 
 
 TM_U16 = 2

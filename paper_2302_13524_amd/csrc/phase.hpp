@@ -84,7 +84,8 @@ int phase_lb_state_doubles(int m);
 // Device-controlled iterations (see phase_kernels.hip): init after the first
 // evaluation, then per iteration phase_lb_iter (decide on the pending trial,
 // new direction or halved step, trial point) and the evaluation at phit.
-int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, const int* chk, void* stream);
+int phase_lb_init(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, const int* chk,
+                  void* stream);
 int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip, void* stream);
 // phi (unless the pixel check failed) to phi_out, and rec[0..6] = f, accepted
 // iterations, evaluations, solve ended, pixel check bits, first rows (device).

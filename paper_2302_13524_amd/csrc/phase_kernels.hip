@@ -1625,14 +1625,15 @@ __global__ void __launch_bounds__(PWG) k_piter(PhaseLb L, int P, int m, int iter
 }
 
 // start: clear the state, take f at the start point, allow the first direction
-// (unless the pixel check failed)
-__global__ void k_pinit(double* sc, int n, const double* gval, int* skip, const int* chk) {
+// (unless the pixel check failed, or no iteration is asked for: the solve has
+// then ended at the start point)
+__global__ void k_pinit(double* sc, int n, const double* gval, int* skip, const int* chk, int iters) {
   for (int i = threadIdx.x; i < n; i += 64) sc[i] = 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     sc[4] = gval[0];
     sc[6] = 1.0;  // the start point
-    *skip = chk[0] != 0 ? 1 : 0;
+    *skip = (chk[0] != 0 || iters <= 0) ? 1 : 0;
   }
 }
 
@@ -1664,8 +1665,9 @@ int phase_lb_finish(const PhaseLb& L, const PhaseWork& w, int P, double* phi_out
   return (int)hipGetLastError();
 }
 
-int phase_lb_init(PhaseLb& L, int P, int m, const double* gval, int* skip, const int* chk, void* stream) {
-  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, phase_lb_state_doubles(m), gval, skip, chk);
+int phase_lb_init(PhaseLb& L, int P, int m, int iters, const double* gval, int* skip, const int* chk,
+                  void* stream) {
+  k_pinit<<<1, 64, 0, (hipStream_t)stream>>>(L.sc, phase_lb_state_doubles(m), gval, skip, chk, iters);
   return (int)hipGetLastError();
 }
 int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double* gval, int* skip, void* stream) {

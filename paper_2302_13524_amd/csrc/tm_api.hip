@@ -775,16 +775,27 @@ extern "C" int tm_phase_objective(tm_ctx* c, const tm_defocus_dims* dd, const in
   return TM_OK;
 }
 
-extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
-                                       const tm_c32* tm_est, const tm_c32* theta, const float* I_d,
-                                       const tm_optics* o, double* phi, const tm_phase_opts* po,
-                                       double* g_out, void* stream) {
+// Graph iterations the solve may take: at most 40 trials per accepted
+// iteration, plus the iteration that decides the last trial and ends it.
+static long phase_max_evals(int iters) { return (long)iters * 40 + 2; }
+
+// The phase solve of tm_phase_offset_correct (rec_dev == NULL: batches of
+// graph replays until the device state says the solve has ended, the host
+// reading that state between batches) and of tm_phase_offset_correct_async
+// (rec_dev != NULL: `evals` graph iterations queued, the end-of-solve record
+// written to rec_dev, no wait).
+static int phase_solve(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix, const tm_c32* tm_est,
+                       const tm_c32* theta, const float* I_d, const tm_optics* o, double* phi,
+                       const tm_phase_opts* po, double* g_out, void* stream, long evals, double* rec_dev) {
   if (!c) return TM_EINVAL;
   int r = phase_check(c, dd, pix, tm_est, theta, I_d, o, false);
   if (r) return r;
   if (!phi || !po) return fail(c, TM_EINVAL, "null pointer argument");
   if (po->iters < 0 || po->m < 1 || po->m > 16) return fail(c, TM_EINVAL, "iters >= 0 and 1 <= m <= 16");
   if (!(po->ftol >= 0.0)) return fail(c, TM_EINVAL, "ftol must be >= 0");
+  const bool async = rec_dev != nullptr;
+  if (async && po->iters > 0 && (evals < 1 || evals > phase_max_evals(po->iters)))
+    return fail(c, TM_EINVAL, "evals=%ld outside 1..%ld", evals, phase_max_evals(po->iters));
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
   tmk::PhaseDims pd;
@@ -809,9 +820,9 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   double* rec = L.sc + tmk::phase_lb_state_doubles(m);  // 8 doubles: the end-of-batch record
   HIPCHK(c, hipMemcpyAsync(L.phi, phi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
   int e = tmk::phase_eval(pd, pix, I_d, L.phi, L.g, w, (const double*)c->tw64, stream);
-  if (!e) e = tmk::phase_lb_init(L, P, m, w.gval, w.skip, w.chk, stream);
+  if (!e) e = tmk::phase_lb_init(L, P, m, po->iters, w.gval, w.skip, w.chk, stream);
   if (e) return hipfail(c, e, "phase start");
-  if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
+  if (!async && !c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, 8 * sizeof(double), hipHostMallocDefault));
   double* hb = c->pinned;
   // end of a batch: phi out (device-side, skipped after a failed pixel check)
   // and the record (f, iterations, evaluations, ended, pixel check) read back
@@ -861,9 +872,19 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
       else phase_graph_release(c);
     }
     hipGraphExec_t gexec = c->pg.exec;
-    // at most 40 trials per accepted iteration, plus the replay that decides
-    // the last trial and ends the solve; PHASE_GRAPH_ITERS of them per replay
-    const long limit = ((long)po->iters * 40 + 2 + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
+    if (async) {
+      // whole replays, then the remaining iterations launched one by one (the same kernels)
+      for (long i = 0; i < evals / PHASE_GRAPH_ITERS && !e; ++i) e = (int)hipGraphLaunch(gexec, s);
+      for (long i = 0; i < evals % PHASE_GRAPH_ITERS && !e; ++i) {
+        e = tmk::phase_lb_iter(L, P, m, po->iters, po->ftol, w.gval, w.skip, stream);
+        if (!e) e = tmk::phase_eval(pd, pix, I_d, L.phit, L.gt, w, (const double*)c->tw64, stream, L.d);
+      }
+      if (!e) e = tmk::phase_lb_finish(L, w, P, phi, rec_dev, stream);
+      if (e) return hipfail(c, e, "phase iterations");
+      return TM_OK;
+    }
+    // PHASE_GRAPH_ITERS graph iterations per replay
+    const long limit = (phase_max_evals(po->iters) + PHASE_GRAPH_ITERS - 1) / PHASE_GRAPH_ITERS;
     // first batch: enough replays for the evaluations the last solve of the same
     // iteration count took (every graph iteration but the last evaluates one
     // trial), else for one trial per iteration plus a margin
@@ -878,6 +899,10 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
       batch = 2;
     }
     if (e) return hipfail(c, e, "phase iterations");
+  } else if (async) {
+    e = tmk::phase_lb_finish(L, w, P, phi, rec_dev, stream);
+    if (e) return hipfail(c, e, "phase result");
+    return TM_OK;
   } else {
     e = finish();
     if (e) return hipfail(c, e, "phase result");
@@ -896,6 +921,22 @@ extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, con
   c->ph_iters_req = po->iters;
   if (g_out) *g_out = f;
   return TM_OK;
+}
+
+extern "C" int tm_phase_offset_correct(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
+                                       const tm_c32* tm_est, const tm_c32* theta, const float* I_d,
+                                       const tm_optics* o, double* phi, const tm_phase_opts* po,
+                                       double* g_out, void* stream) {
+  return phase_solve(c, dd, pix, tm_est, theta, I_d, o, phi, po, g_out, stream, 0, nullptr);
+}
+
+extern "C" int tm_phase_offset_correct_async(tm_ctx* c, const tm_defocus_dims* dd, const int32_t* pix,
+                                             const tm_c32* tm_est, const tm_c32* theta, const float* I_d,
+                                             const tm_optics* o, double* phi, const tm_phase_opts* po,
+                                             int32_t evals, double* rec, void* stream) {
+  if (!c) return TM_EINVAL;
+  if (!rec) return fail(c, TM_EINVAL, "null pointer argument");
+  return phase_solve(c, dd, pix, tm_est, theta, I_d, o, phi, po, nullptr, stream, evals, rec);
 }
 
 extern "C" int tm_phase_last_counts(tm_ctx* c, int32_t* iterations, int32_t* evaluations) {

@@ -284,3 +284,79 @@ def test_repeated_solves_reuse_the_captured_iteration(ctx):
         fresh.close()
     assert np.array_equal(b1, fb1) and np.array_equal(b2, fb2)
     assert not np.array_equal(a1, b1)
+
+
+@pytest.mark.parametrize("nf,P,N,Nd,NA,noise", [(16, 40, 24, 12, 0.6, 1e4), (32, 512, 1024, 50, 0.3, 1e4)])
+def test_async_solve_equals_the_synchronous_one(ctx, nf, P, N, Nd, NA, noise):
+    # the stream-ordered solve, given the evaluations the synchronous solve
+    # reported (or more), computes the same offsets and objective bit for bit
+    # and records the same counts; with fewer it records an unfinished solve
+    pix, tm_est, theta, Id, _, _ = build(nf, P, N, Nd, NA, 0.6, cfg=963, noise=noise)
+    args = (torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta), f32(Id),
+            (LAM, PS, NA, 20 * LAM))
+    phi_s = torch.zeros(P, dtype=torch.float64, device=dev())
+    g_s = tm.tm_phase_offset_correct(ctx, *args, phi_s, nf, nf, iters=25, m=5)
+    it, ev = tm.tm_phase_last_counts(ctx)
+    assert it == 25 and ev > 25
+    other = tm.Context(0)
+    side = torch.cuda.Stream()
+    try:
+        for c in (ctx, other):
+            for evals in (ev, ev + 13, ev + 20):
+                rec = torch.full((8,), -1.0, dtype=torch.float64, device=dev())
+                phi = torch.zeros(P, dtype=torch.float64, device=dev())
+                side.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(side):
+                    tm.tm_phase_offset_correct_async(c, *args, phi, nf, nf, rec, evals, iters=25, m=5)
+                torch.cuda.current_stream().wait_stream(side)
+                r = rec.cpu().numpy()
+                assert torch.equal(phi, phi_s)
+                assert r[0] == g_s and (r[1], r[2], r[3], r[4]) == (25, ev, 1, 0)
+            assert tm.tm_phase_last_counts(ctx) == (it, ev)  # the synchronous call's counts
+        for evals in (1, ev // 2, ev - 1):
+            rec = torch.zeros(8, dtype=torch.float64, device=dev())
+            phi = torch.zeros(P, dtype=torch.float64, device=dev())
+            tm.tm_phase_offset_correct_async(ctx, *args, phi, nf, nf, rec, evals, iters=25, m=5)
+            r = rec.cpu().numpy()
+            assert r[3] == 0 and r[2] == evals + 1 and r[1] < 25 and r[4] == 0
+        # then the synchronous solve again: the same result
+        phi = torch.zeros(P, dtype=torch.float64, device=dev())
+        assert tm.tm_phase_offset_correct(ctx, *args, phi, nf, nf, iters=25, m=5) == g_s
+        assert torch.equal(phi, phi_s)
+    finally:
+        other.close()
+
+
+def test_async_solve_records_bad_pixels_and_rejects_bad_arguments(ctx):
+    nf, P, N, Nd = 16, 40, 24, 12
+    pix, tm_est, theta, Id, _, mdl = build(nf, P, N, Nd, 0.6, 0.6, cfg=964)
+    rest = (c64(tm_est), c64(theta), f32(Id), (LAM, PS, 0.6, 20 * LAM))
+    pix_d = torch.from_numpy(pix.astype(np.int32)).to(dev())
+    for row, val, flag, slot in ((7, nf * nf + 5, 1, 5), (11, None, 2, 6)):
+        q = pix.astype(np.int64).copy()
+        q[row] = q[5] if val is None else val
+        for iters in (0, 20):
+            rec = torch.zeros(8, dtype=torch.float64, device=dev())
+            phi = torch.full((P,), 0.25, dtype=torch.float64, device=dev())
+            tm.tm_phase_offset_correct_async(ctx, torch.from_numpy(q.astype(np.int32)).to(dev()), *rest, phi, nf, nf,
+                                             rec, 30, iters=iters, m=5)
+            r = rec.cpu().numpy()
+            assert r[4] == flag and r[slot] == (row if val is not None else 5) and r[3] == 1
+            assert torch.all(phi == 0.25)
+    # iters = 0: the start point's objective, one evaluation, evals ignored
+    rec = torch.zeros(8, dtype=torch.float64, device=dev())
+    phi0 = np.random.default_rng(964).random(P)
+    phi = torch.from_numpy(phi0.copy()).to(dev())
+    tm.tm_phase_offset_correct_async(ctx, pix_d, *rest, phi, nf, nf, rec, 0, iters=0, m=5)
+    r = rec.cpu().numpy()
+    assert (r[1], r[2], r[3], r[4]) == (0, 1, 1, 0)
+    assert abs(r[0] - mdl.objective(Id.astype(np.float64), phi0)[0]) <= 1e-9 * r[0]
+    assert np.array_equal(phi.cpu().numpy(), phi0)
+    phi = torch.zeros(P, dtype=torch.float64, device=dev())
+    for evals in (0, -1, 40 * 20 + 3):
+        with pytest.raises(tm.TMError, match="evals"):
+            tm.tm_phase_offset_correct_async(ctx, pix_d, *rest, phi, nf, nf, rec, evals, iters=20, m=5)
+    for bad in (torch.zeros(6, dtype=torch.float64, device=dev()), torch.zeros(8, dtype=torch.float32, device=dev()),
+                torch.zeros(8, dtype=torch.float64)):
+        with pytest.raises(tm.TMError, match="rec"):
+            tm.tm_phase_offset_correct_async(ctx, pix_d, *rest, phi, nf, nf, bad, 30, iters=20, m=5)
