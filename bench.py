@@ -231,14 +231,13 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out):
 
     # the L-BFGS kernels (one --profile-lbfgs run: iterations with 0..m stored pairs, as in the timed leg)
     lb = {}
-    for key, frag in (("lbfgs_dots", "k_dir_dots"), ("lbfgs_apply", "k_dir_apply"), ("lbfgs_step", "k_step<")):
+    for key, frag in (("lbfgs_dots", "k_dir_dots"), ("lbfgs_step", "k_step<")):
         fv, fn = pick_name(f, frag)
         wv, wn = pick_name(w, frag)
         if fv is not None and wv is not None:
             lb[key] = {"fetch_kib": fv, "write_kib": wv, "dispatches": [fn, wn]}
-    if "lbfgs_dots" in lb and "lbfgs_apply" in lb:
-        lb["lbfgs_direction"] = {k: lb["lbfgs_dots"][k] + lb["lbfgs_apply"][k] for k in ("fetch_kib", "write_kib")}
-        lb["lbfgs_direction"]["dispatches"] = lb["lbfgs_dots"]["dispatches"]
+    if "lbfgs_dots" in lb:  # the direction's HBM pass (k_dir_solve reads only the partial sums)
+        lb["lbfgs_direction"] = dict(lb["lbfgs_dots"])
     res["kernels"].update(lb)
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1)
@@ -633,26 +632,27 @@ def main():
             raise SystemExit(f"pipelined steps differ from the serial path (t equal: {same_t}, phi equal: {same_phi})")
     roofline_lbfgs = None
     if n_lb:
-        # the paper's Alg. 1: its direction kernels (dot products over the history, small solve, direction)
-        # timed live with HIP events on the library's stream, against HBM. Per row-iteration with c stored
-        # pairs and a pending pair: read g, g_prev, s_new, write y_new, read the 2c history vectors twice,
-        # write d: (2 + 3 + 4 c) 8 N bytes (c = min(iteration, m), no pending pair at the first).
+        # the paper's Alg. 1: its direction kernels (dot products over the history, small solve) timed live
+        # with HIP events on the library's stream, against HBM. Per row-iteration with c stored pairs and a
+        # pending pair: read g, g_prev, s_new, write y_new, read the 2c history vectors: (1 + 3 + 2 c) 8 N
+        # bytes (c = min(iteration, m), no pending pair at the first). The direction itself, d from g and
+        # the history, is formed in the line search's row kernel ((2 + 2 c) 8 N bytes there).
         tm.tm_profile_enable(ctx, True)
         lb_ms = timed(lambda: step("lbfgs", n_lb, phase=False))
         d_ms, d_n = tm.tm_profile_query(ctx, 20)
         s_ms, s_n = tm.tm_profile_query(ctx, 21)
         tm.tm_profile_enable(ctx, False)
         m_lb = 5
-        per_it = [(2 + (3 if it > 0 else 0) + 4 * min(it, m_lb)) * 8 * N * P for it in range(n_lb)]
+        per_it = [(1 + (3 if it > 0 else 0) + 2 * min(it, m_lb)) * 8 * N * P for it in range(n_lb)]
         dbytes = float(np.mean(per_it))
-        full = (2 + 3 + 4 * m_lb) * 8 * N * P
+        full = (1 + 3 + 2 * m_lb) * 8 * N * P
         d_avg = d_ms / max(d_n, 1)
         s_avg = s_ms / max(s_n, 1)
         gbs = dbytes / (d_avg * 1e-3) / 1e9
         tr_all = measured_traffic(P, N)
         tr_lb = tr_all.get("lbfgs_direction") if tr_all else None
         roofline_lbfgs = {
-            "bound": "hbm", "kernel": "L-BFGS direction (k_dir_dots + k_dir_solve + k_dir_apply, compact form, m = 5)",
+            "bound": "hbm", "kernel": "L-BFGS direction (k_dir_dots + k_dir_solve, compact form, m = 5; d formed in the line-search row kernel)",
             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": tr_lb, "avg_launch_ms": round(d_avg, 5), "launches": d_n,
             "alg_bytes_per_launch": int(dbytes), "alg_bytes_full_history": int(full),

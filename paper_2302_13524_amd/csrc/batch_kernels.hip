@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
     a.er_beta = mom ? b.er_beta : 0.f;
     a.lz_bprev = nullptr;
     a.lz_out = nullptr;
+    a.lb_sc = nullptr;  // no L-BFGS modes in the batch
     if constexpr (MODE == BATCH_LZ) {
       // step j from V(j) to V(j + 1), V(0) = t, V(i) = lzV + (i - 1) P N; (alpha, beta) into row j of lzH
       const int j = b.lz_j;

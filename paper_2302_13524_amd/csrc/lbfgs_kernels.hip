@@ -1,10 +1,11 @@
 // Device L-BFGS for every row at once (Sec. 2.2, Alg. 1; two-loop recursion
 // of Nocedal & Wright Alg. 7.4 over R^{2N} with <a, b> = Re(a^H b)).
 //
-// Per iteration: [direction] finalise the pending (s, y) pair, L-BFGS
-// product (compact form) -> d, descent check; [line sums] fused FFT kernel M_LS gives the six sums of
-// the quartic f(t + a d); [step] exact minimiser a > 0 in FP64, t += a d,
-// s = a d kept as the pending pair; [gradient] fused FFT kernel M_GRAD.
+// Per iteration: [direction] finalise the pending (s, y) pair, coefficients
+// of the L-BFGS product (compact form), descent check; [line sums] fused FFT
+// kernel M_LS forms d from them and gives the six sums of the quartic
+// f(t + a d); [step] exact minimiser a > 0 in FP64, t += a d, s = a d kept as
+// the pending pair; [gradient] fused FFT kernel M_GRAD.
 //
 // The amplitude cost (the Poisson-noise variant of the Discussion) runs the
 // same loop with M_AGRAD for the gradient and M_ALS for the line: the cost at
@@ -131,15 +132,17 @@ __device__ __forceinline__ void block_sums(const float* s, const float* c, float
 //   H g = gam g + S p - gam Y u,  R u = S^T g,  R^T p = (D + gam Y^T Y) u - gam Y^T g,
 // the same product as the two-loop recursion of Nocedal & Wright Alg. 7.4,
 // but with every dot product against g and the pending pair's y known after
-// one pass over the history. Three kernels, each row split over DSPLIT
-// workgroups so that both passes stream at full occupancy:
+// one pass over the history. Two kernels, the first with each row split over
+// several workgroups so that its pass streams at full occupancy:
 //   k_dir_dots:  partial dot products of each row slice (the pending pair's y
 //                is formed and stored here);
 //   k_dir_solve: per row, the slices' partials summed in a fixed order, the
 //                pending pair accepted or skipped (S^T Y, Y^T Y updated over the
 //                ring slots), the small triangular solves, the descent check;
-//                writes the coefficients of d = cg g + sum_j cs_j s_j + cy_j y_j;
-//   k_dir_apply: d over each row slice.
+//                writes the coefficients of d = cg g + sum_j cs_j s_j + cy_j y_j.
+// The second pass over the history, d itself, is the prologue of the line
+// search's row kernel (M_LS / M_ALS), where its loads overlap other rows'
+// transforms instead of taking a launch of its own.
 constexpr int MMAX = 16;
 constexpr int NDOT = 5 + 4 * MMAX;  // partial sums per slice: pending pair, g^T g, 4 per stored pair
 constexpr int DEPT = 4;    // values per thread in the split kernels
@@ -395,93 +398,6 @@ __global__ void __launch_bounds__(64) k_dir_solve(LbArgs a, const double* dots, 
   sc[1] = use ? k : 0;
 }
 
-// d over one row slice with C stored pairs, every load issued before the sums
-template <int C>
-__device__ __forceinline__ void apply_fixed(const LbArgs& a, const double* coef, const bool* act, size_t rb, int p,
-                                            int R, int head, int q, int L) {
-  constexpr int CC = C > 0 ? C : 1;
-  const int tid = threadIdx.x;
-  float2 g[DEPT], sv[CC][DEPT], yy[CC][DEPT];
-#pragma unroll
-  for (int i = 0; i < DEPT; ++i) g[i] = act[i] ? a.g[rb + tid + i * LWG] : make_float2(0.f, 0.f);
-#pragma unroll
-  for (int j = 0; j < C; ++j) {
-    const size_t sb = pair_base(p, R, head, C, j, a.N, q, L);
-#pragma unroll
-    for (int i = 0; i < DEPT; ++i) {
-      sv[j][i] = yy[j][i] = make_float2(0.f, 0.f);
-      if (act[i]) {
-        sv[j][i] = a.S[sb + tid + i * LWG];
-        yy[j][i] = a.Y[sb + tid + i * LWG];
-      }
-    }
-  }
-  const float cg = (float)coef[0];
-  float cs[CC], cy[CC];
-#pragma unroll
-  for (int j = 0; j < C; ++j) {
-    cs[j] = (float)coef[1 + j];
-    cy[j] = (float)coef[1 + R + j];
-  }
-#pragma unroll
-  for (int i = 0; i < DEPT; ++i) {
-    float2 dv = make_float2(cg * g[i].x, cg * g[i].y);
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      dv.x += cs[j] * sv[j][i].x + cy[j] * yy[j][i].x;
-      dv.y += cs[j] * sv[j][i].y + cy[j] * yy[j][i].y;
-    }
-    if (act[i]) a.d[rb + tid + i * LWG] = dv;
-  }
-}
-
-__global__ void __launch_bounds__(LWG) k_dir_apply(LbArgs a) {
-  const int p = blockIdx.y, q = blockIdx.x, split = gridDim.x;
-  const int tid = threadIdx.x;
-  const int N = a.N, m = a.m, R = m + 1;
-  const int L = N / split;
-  const size_t rb = (size_t)p * N + (size_t)q * L;
-  const double* sc = a.sc + (size_t)p * LB_SCALARS(m);
-  const double* coef = sc + 4 + 2 * R * R;
-  const int head = (int)sc[0], count = (int)sc[1];
-  const float cg = (float)coef[0];
-  float2 dv[DEPT];
-  bool act[DEPT];
-#pragma unroll
-  for (int i = 0; i < DEPT; ++i) act[i] = tid + i * LWG < L;
-  switch (count) {  // uniform over the workgroup (one row)
-    case 0: return apply_fixed<0>(a, coef, act, rb, p, R, head, q, L);
-    case 1: return apply_fixed<1>(a, coef, act, rb, p, R, head, q, L);
-    case 2: return apply_fixed<2>(a, coef, act, rb, p, R, head, q, L);
-    case 3: return apply_fixed<3>(a, coef, act, rb, p, R, head, q, L);
-    case 4: return apply_fixed<4>(a, coef, act, rb, p, R, head, q, L);
-    case 5: return apply_fixed<5>(a, coef, act, rb, p, R, head, q, L);
-    case 6: return apply_fixed<6>(a, coef, act, rb, p, R, head, q, L);
-    default: break;
-  }
-#pragma unroll
-  for (int i = 0; i < DEPT; ++i) {
-    const int e = tid + i * LWG;
-    const float2 g = act[i] ? a.g[rb + e] : make_float2(0.f, 0.f);
-    dv[i] = make_float2(cg * g.x, cg * g.y);
-  }
-  for (int j = 0; j < count; ++j) {
-    const size_t sb = pair_base(p, R, head, count, j, N, q, L);
-    const float cs = (float)coef[1 + j], cy = (float)coef[1 + R + j];
-#pragma unroll
-    for (int i = 0; i < DEPT; ++i) {
-      if (!act[i]) continue;
-      const int e = tid + i * LWG;
-      const float2 sv = a.S[sb + e], y = a.Y[sb + e];
-      dv[i].x += cs * sv.x + cy * y.x;
-      dv[i].y += cs * sv.y + cy * y.y;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < DEPT; ++i)
-    if (act[i]) a.d[rb + tid + i * LWG] = dv[i];
-}
-
 // phi(a) = c1 a + c2 a^2 + c3 a^3 + c4 a^4
 __device__ __forceinline__ double quart(double c1, double c2, double c3, double c4, double x) {
   return x * (c1 + x * (c2 + x * (c3 + x * c4)));
@@ -623,7 +539,6 @@ int dispatch(int what, const LbArgs& a, hipStream_t s) {
     if (a.N % split || a.N / split > LWG * DEPT || a.m > MMAX) return (int)hipErrorInvalidValue;
     k_dir_dots<<<dim3(split, a.P), LWG, 0, s>>>(a, a.dots);
     k_dir_solve<<<a.P, 64, 0, s>>>(a, a.dots, split);
-    k_dir_apply<<<dim3(split, a.P), LWG, 0, s>>>(a);
     return (int)hipGetLastError();
   }
   int ept = (a.N + LWG - 1) / LWG;
@@ -676,9 +591,15 @@ int run_lbfgs(row_launcher fn, const RowArgs& base, int ibf16, int N, int iters,
     e = dispatch(0, la, s);
     if (b.hook_end) b.hook_end(b.hook_user, 20, stream);
     if (e) return e;
-    RowArgs ls = base;
+    RowArgs ls = base;  // forms d from the coefficients, then the line sums
     ls.tin = (const cx<float>*)t;
-    ls.din = (const cx<float>*)b.d;
+    ls.din = nullptr;
+    ls.lb_g = (const cx<float>*)gcur;
+    ls.lb_S = (const cx<float>*)b.S;
+    ls.lb_Y = (const cx<float>*)b.Y;
+    ls.lb_sc = (const double*)b.sc;
+    ls.lb_d = (cx<float>*)b.d;
+    ls.lb_m = m;
     ls.sums = b.sums;
     if ((e = fn(lmode, ibf16, ls, stream))) return e;
     if (b.hook_begin) b.hook_begin(b.hook_user, 21, stream);

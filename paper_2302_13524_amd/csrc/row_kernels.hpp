@@ -65,6 +65,18 @@ struct RowArgs {
   const double* lz_y;
   int lz_k;
   int64_t lz_rs;
+  // M_LS / M_ALS with lb_sc != null: the L-BFGS direction is formed in the
+  // prologue from the compact-form coefficients of the direction solve,
+  //   d = cg g + sum_j (cs_j s_j + cy_j y_j)  over the row's stored pairs,
+  // written to lb_d (and read back from there by the mask loop; din unused).
+  // lb_S, lb_Y: [P][lb_m + 1][N] rings; lb_sc: [P][LB_SCALARS(lb_m)] with
+  // head, count at 0, 1 and the coefficients from 4 + 2 (lb_m + 1)^2 on.
+  const cx<float>* lb_g;
+  const cx<float>* lb_S;
+  const cx<float>* lb_Y;
+  const double* lb_sc;
+  cx<float>* lb_d;
+  int lb_m;
 };
 
 __device__ __forceinline__ float bf16_to_f(uint16_t b) {
@@ -272,6 +284,53 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
   if constexpr (MODE != M_ADJ && MODE != M_BACKPROP) {
 #pragma unroll
     for (int i = 0; i < E; ++i) treg[i] = gload(trow + E0(i));
+  }
+  if constexpr (MODE == M_LS || MODE == M_ALS) {
+    if (a.lb_sc) {
+      // the L-BFGS direction at this thread's values, two stored pairs' loads in
+      // flight at a time; each thread later reads back only what it wrote here
+      const int R = a.lb_m + 1;
+      const double* sc = a.lb_sc + prow * (size_t)(4 + 2 * R * R + 1 + 2 * R);
+      const int head = (int)sc[0], count = (int)sc[1];
+      const double* coef = sc + 4 + 2 * R * R;
+      const float cg = (float)coef[0];
+      C dv[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const C gv = gload(a.lb_g + prow * N + E0(i));
+        dv[i] = C{cg * gv.x, cg * gv.y};
+      }
+      for (int j = 0; j < count; j += 2) {
+        const bool two = j + 1 < count;
+        const size_t s0 = ((size_t)prow * R + (head - count + j + 2 * R) % R) * N;
+        const size_t s1 = ((size_t)prow * R + (head - count + j + 1 + 2 * R) % R) * N;
+        C sv0[E], yv0[E], sv1[E], yv1[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          sv0[i] = gload(a.lb_S + s0 + E0(i));
+          yv0[i] = gload(a.lb_Y + s0 + E0(i));
+          sv1[i] = two ? gload(a.lb_S + s1 + E0(i)) : C{0.f, 0.f};
+          yv1[i] = two ? gload(a.lb_Y + s1 + E0(i)) : C{0.f, 0.f};
+        }
+        const float cs0 = (float)coef[1 + j], cy0 = (float)coef[1 + R + j];
+        const float cs1 = two ? (float)coef[2 + j] : 0.f, cy1 = two ? (float)coef[2 + R + j] : 0.f;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          dv[i].x = fmadd(cy0, yv0[i].x, fmadd(cs0, sv0[i].x, dv[i].x));
+          dv[i].y = fmadd(cy0, yv0[i].y, fmadd(cs0, sv0[i].y, dv[i].y));
+          if (two) {
+            dv[i].x = fmadd(cy1, yv1[i].x, fmadd(cs1, sv1[i].x, dv[i].x));
+            dv[i].y = fmadd(cy1, yv1[i].y, fmadd(cs1, sv1[i].y, dv[i].y));
+          }
+        }
+      }
+      C* dout = a.lb_d + prow * N;
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) gstore(dout + E0(i), dv[i]);
+      }
+      drow = dout;
+    }
   }
   if constexpr (MODE == M_ER) {
     if (a.er_beta != 0.f) {

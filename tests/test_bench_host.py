@@ -18,7 +18,7 @@ ERC_S = "void tmk::row_kernel<tmk::Plan<7, 6, -1, 0>, 12, float, true>(tmk::RowA
 LZ8 = "void tmk::row_kernel_w<tmk::Plan<7, 6, 3, 1>, 13, float, true, 1024>(tmk::RowArgs)"
 COPY = "__amd_rocclr_copyBuffer"
 DOTS = "tmk::(anonymous namespace)::k_dir_dots(tmk::(anonymous namespace)::LbArgs, double*)"
-APPLY = "tmk::(anonymous namespace)::k_dir_apply(tmk::(anonymous namespace)::LbArgs)"
+SOLVE = "tmk::(anonymous namespace)::k_dir_solve(tmk::(anonymous namespace)::LbArgs, double const*, int)"
 
 
 def test_more_than_one_gpu_is_refused():
@@ -41,9 +41,9 @@ def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, mon
     f, w, cf, cw = (str(tmp_path / s) for s in ("f", "w", "cf", "cw"))
     # a stray dispatch of another plan (fewer dispatches) is not mixed in
     _counters(f, "FETCH_SIZE", [(LZ, 100.0), (LZ, 200.0), (ERC, 40.0), (ERC_S, 60.0), (ERC, 40.0), (DOTS, 10.0),
-                                (APPLY, 20.0), (LZ8, 999.0)])
+                                (SOLVE, 20.0), (LZ8, 999.0)])
     _counters(w, "WRITE_SIZE", [(LZ, 50.0), (LZ, 50.0), (ERC, 30.0), (ERC_S, 30.0), (ERC, 30.0), (DOTS, 1.0),
-                                (APPLY, 2.0), (LZ8, 999.0)])
+                                (SOLVE, 2.0), (LZ8, 999.0)])
     # a 512 MiB copy reads as half its size on the fetch counter, its size on the write counter
     _counters(cf, "FETCH_SIZE", [(COPY, 262144.0), (COPY, 262144.0), ("small", 1.0)])
     _counters(cw, "WRITE_SIZE", [(COPY, 524288.0), (COPY, 524288.0), ("small", 1.0)])
@@ -65,8 +65,8 @@ def test_counter_summary_scales_by_the_copy_and_tracks_the_sources(tmp_path, mon
     assert bench.measured_traffic(2286, 8192, bench.plan_tag(7, 6, 0))["lanczos"] == t["lanczos"]
     t3 = bench.measured_traffic(2286, 8192, bench.plan_tag(7, 6, 3))
     assert "lanczos" not in t3 and "lbfgs_direction" in t3
-    # the L-BFGS direction is its two streaming kernels together
-    assert t["lbfgs_direction"] == ((10 + 20) * 2 + (1 + 2) * 1) * 1024
+    # the L-BFGS direction's HBM pass is k_dir_dots (the solve reads only its partial sums)
+    assert t["lbfgs_direction"] == (10 * 2 + 1 * 1) * 1024
     # each figure is dropped once the sources it was taken on change
     d["sources_sha256"] = "0" * 64
     json.dump(d, open(out, "w"))
