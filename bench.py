@@ -137,7 +137,8 @@ def parse():
 KERNEL_SOURCES = ["fft_core.hpp", "row_kernels.hpp", "grid_inst.hip", "grids.hpp"]
 LBFGS_SOURCES = ["lbfgs_kernels.hip", "lbfgs.hpp", "row_kernels.hpp", "fft_core.hpp", "grids.hpp"]  # with what it includes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2286x8192.json")
-PHASE_EVAL_MARGIN = 10  # evaluations queued beyond the synchronous solve's count (the extra ones return at once)
+PHASE_EVAL_MARGIN = 2  # evaluations queued beyond the synchronous solve's count (the extra ones return at once)
+PIPE_BUFFERS = 3  # row buffers of the pipelined steps: retrieval i reuses the buffer of phase solve i - 3
 TIMED_RANGE = "bench timed steps"
 
 
@@ -525,32 +526,33 @@ def main():
 
     # Pipelined steps: the K steps are K independent TMs, so step i's phase solve (its own library
     # contexts, a second stream at the default priority) runs while step i + 1's retrieval runs on this
-    # stream; two row buffers alternate, and a retrieval waits for the phase solve that last read its
+    # stream; PIPE_BUFFERS row buffers rotate, and a retrieval waits for the phase solve that last read its
     # buffer. Every step still runs its whole path inside the timed region. The phase solve's kernels are
     # latency-bound and small, so they fill the gaps of the retrieval's CU-filling kernels.
     # The phase solves are queued in their stream-ordered form, so the host never waits for one: each
     # queues the evaluations the synchronous solve of this problem took (every step repeats it) plus a
     # margin, and records whether it ended within them; every timed step's record is checked below.
     if args.pipeline:
-        ctx_ph = [tm.Context(0), tm.Context(0)]  # one per buffer: each keeps its captured phase graph
+        NB = PIPE_BUFFERS
+        ctx_ph = [tm.Context(0) for _ in range(NB)]  # one per buffer: each keeps its captured phase graph
         s_ph = torch.cuda.Stream()
-        tb = [v0t.clone(), v0t.clone()]
-        pb = [torch.zeros(P, dtype=torch.float64, device=dev) for _ in range(2)]
-        ev_r = [torch.cuda.Event(), torch.cuda.Event()]
-        ev_p = [torch.cuda.Event(), torch.cuda.Event()]
-        recs = torch.zeros((max(args.steps, args.warmup, 2), 8), dtype=torch.float64, device=dev)
+        tb = [v0t.clone() for _ in range(NB)]
+        pb = [torch.zeros(P, dtype=torch.float64, device=dev) for _ in range(NB)]
+        ev_r = [torch.cuda.Event() for _ in range(NB)]
+        ev_p = [torch.cuda.Event() for _ in range(NB)]
+        recs = torch.zeros((max(args.steps, args.warmup, NB), 8), dtype=torch.float64, device=dev)
         step()
         torch.cuda.synchronize()
         ph_budget = tm.tm_phase_last_counts(ctx)[1] + PHASE_EVAL_MARGIN
 
     def pipelined(k):
         main = torch.cuda.current_stream()
-        raws = [None, None]
+        raws = [None] * NB
 
         def retrieve(i):
-            b = i % 2
-            if i >= 2:
-                main.wait_event(ev_p[b])  # step i - 2's phase solve has read this buffer
+            b = i % NB
+            if i >= NB:
+                main.wait_event(ev_p[b])  # step i - NB's phase solve has read this buffer
             tb[b].copy_(v0t)
             raws[b] = tm.tm_retrieve(ctx, mk, It, tb[b], n1, n2, sopts(n_er))
             ev_r[b].record(main)
@@ -559,15 +561,15 @@ def main():
         for i in range(k):
             if i + 1 < k:
                 retrieve(i + 1)
-            b = i % 2
+            b = i % NB
             with torch.cuda.stream(s_ph):
                 s_ph.wait_event(ev_r[b])
                 pb[b].zero_()
                 tm.tm_phase_offset_correct_async(ctx_ph[b], pixt, tb[b], th, Idt, optics, pb[b], nf, nf, recs[i],
                                                  ph_budget, iters=n_ph, m=args.phase_m, ftol=args.phase_ftol)
                 ev_p[b].record(s_ph)
-        main.wait_event(ev_p[(k - 1) % 2])
-        return tb[(k - 1) % 2], raws[(k - 1) % 2], pb[(k - 1) % 2]
+        main.wait_event(ev_p[(k - 1) % NB])
+        return tb[(k - 1) % NB], raws[(k - 1) % NB], pb[(k - 1) % NB]
 
     def serial_steps(k):
         out = None
@@ -576,7 +578,7 @@ def main():
         return out
 
     run_steps = pipelined if args.pipeline else serial_steps
-    run_steps(max(args.warmup, 2 if args.pipeline else 0))  # with the pipeline: both phase contexts warm
+    run_steps(max(args.warmup, PIPE_BUFFERS if args.pipeline else 0))  # with the pipeline: every phase context warm
     torch.cuda.synchronize()
     tm.tm_profile_enable(ctx, True)
     torch.cuda.synchronize()
