@@ -489,7 +489,8 @@ int tm_profile_enable(tm_ctx *ctx, int enable);
  * 7 FP64 residual, 8 back-propagation, 9 amplitude gradient, 10 amplitude
  * line sums, 11 filter, 12 cyclic error reduction, 13 Lanczos step, 14
  * Lanczos step with learned weights, 15/16 weight-network training), or of the
- * L-BFGS direction (20: its three kernels together) and step (21), since
+ * L-BFGS direction's coefficients (20: its dot-product pass and small solve
+ * together; d itself is formed by the line-search kernel) and step (21), since
  * enabling; mode < 24. Synchronises the context's device. */
 int tm_profile_query(tm_ctx *ctx, int mode, double *ms, int64_t *launches);
 

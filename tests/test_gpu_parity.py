@@ -247,14 +247,14 @@ def test_lanczos_then_cyclic_sweeps(ctx, n1, n2, P, sweeps):
     if sweeps > 1:
         tm.tm_retrieve(ctx, c64(masks), f32(I), ts, n1, n2, tm.retrieve_opts("er_cyclic", iters=sweeps - 1))
     sep = ts.cpu().numpy().astype(np.complex128)
-    print(f"lanczos {k} + {sweeps} sweeps {n1}x{n2}: vs oracle 1-fid {1 - _fid(got, ref).max():.3e} relerr "
+    print(f"lanczos {k} + {sweeps} sweeps {n1}x{n2}: vs oracle worst row 1-fid {1 - _fid(got, ref).min():.3e} relerr "
           f"{relerr(got, ref):.3e}; vs separate path relerr {relerr(got, sep):.3e} (separate vs oracle "
           f"{relerr(sep, ref):.3e})", flush=True)
     # the fused start is the separate one up to the rescaling's rounding; against the
     # oracle the rows agree in direction (the FP32 Lanczos recurrence leaves a small
     # scale drift on slow rows, the same on the separate path)
     assert relerr(got, sep) < OPTOL * 4 * sweeps
-    assert 1 - _fid(got, ref).max() < 1e-9
+    assert 1 - _fid(got, ref).min() < 1e-6  # every row, as for the default path
     # the last sweep's sums describe the returned rows (also when the first sweep formed the start)
     sa, si = rt.er_cyclic_sweep_sums(m, n1, n2, Ir, rt.er_cyclic(m, n1, n2, Ir, t0, sweeps - 1))
     st = tm.decode_stats(raw)
