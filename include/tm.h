@@ -240,8 +240,10 @@ int tm_set_variant(tm_ctx *ctx, int32_t n1, int32_t n2, int32_t variant);
  * Eq. probingmatrix): cfg in 0..7, bit 0 the digit-order variant (as
  * tm_set_variant), bit 1 eight values per thread instead of sixteen, bit 2
  * twice the rows per workgroup. Bits 1 and 2 change the error-reduction steps
- * (averaged and cyclic) and the spectral and Lanczos steps of the start; every
- * other kernel keeps the default plan of the same digit order. The batch
+ * (averaged and cyclic), the spectral and Lanczos steps of the start, the
+ * gradient kernels of the L-BFGS solvers (Alg. 1 and its amplitude-cost form)
+ * and the amplitude cost's line search; every other kernel keeps the default
+ * plan of the same digit order. The batch
  * (tm_batch_create) takes bit 0 only, so its rows equal single-problem runs in
  * configurations 0 and 1.
  * They are compiled for the 32x32, 64x32, 64x64 and 128x64 grids (twice the

@@ -90,7 +90,10 @@ int TM_CAT(row_launchv, GL1, GL2)(int mode, int ibf16, const RowArgs& a, void* s
 // (variant 1), 2 eight values per thread instead of sixteen, 4 twice the rows
 // per workgroup. They apply to the iteration and start kernels the batch also
 // runs (error reduction, averaged and cyclic; heavy-ball spectral and Lanczos
-// steps); every other mode runs the default plan of the same digit order.
+// steps) and to the L-BFGS solvers' gradient kernels and the amplitude cost's
+// line search (the intensity cost's line search, which holds both transforms
+// of a mask at once, spills at eight values per thread and keeps the default
+// plan); every other mode runs the default plan of the same digit order.
 // Compiled for the grids of the benchmark workloads.
 constexpr bool kExt = (GL1 == 5 && GL2 == 5) || (GL1 == 6 && GL2 == 5) || (GL1 == 6 && GL2 == 6) ||
                       (GL1 == 7 && GL2 == 6);
@@ -123,6 +126,15 @@ static int launch_x(int mode, const RowArgs& a, hipStream_t s) {
       if (a.sums) row_kernel_w<PX, M_ERC, IT, true, WG><<<grid, block, 0, s>>>(a);
       else row_kernel_w<PX, M_ERC, IT, false, WG><<<grid, block, 0, s>>>(a);
       break;
+    case M_GRAD:
+      if (a.sums) row_kernel_w<PX, M_GRAD, IT, true, WG><<<grid, block, 0, s>>>(a);
+      else row_kernel_w<PX, M_GRAD, IT, false, WG><<<grid, block, 0, s>>>(a);
+      break;
+    case M_AGRAD:
+      if (a.sums) row_kernel_w<PX, M_AGRAD, IT, true, WG><<<grid, block, 0, s>>>(a);
+      else row_kernel_w<PX, M_AGRAD, IT, false, WG><<<grid, block, 0, s>>>(a);
+      break;
+    case M_ALS: row_kernel_w<PX, M_ALS, IT, true, WG><<<grid, block, 0, s>>>(a); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
@@ -135,7 +147,8 @@ static int launch_cfg(int mode, int ibf16, const RowArgs& a, void* stream) {
     return (int)hipErrorInvalidValue;
   } else {
     hipStream_t s = (hipStream_t)stream;
-    if (mode == M_LANCZOS || mode == M_ERC || mode == M_ER || mode == M_SPEC)
+    if (mode == M_LANCZOS || mode == M_ERC || mode == M_ER || mode == M_SPEC || mode == M_GRAD || mode == M_AGRAD ||
+        mode == M_ALS)
       return ibf16 ? launch_x<typename X::PX, X::WG, uint16_t>(mode, a, s)
                    : launch_x<typename X::PX, X::WG, float>(mode, a, s);
     if (mode == M_LANCZOS_T && !ibf16) return launch_x<typename X::PX, X::WG, float>(mode, a, s);

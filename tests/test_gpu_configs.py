@@ -69,6 +69,30 @@ def test_config_lanczos_and_cyclic_er(ctx, n1, n2, P, cfg):
         tm.tm_set_config(ctx, n1, n2, 0)
 
 
+@pytest.mark.parametrize("n1,n2,P,cfg", _cases())
+def test_config_lbfgs(ctx, n1, n2, P, cfg):
+    # Alg. 1 and its amplitude-cost form in configuration cfg (the gradient
+    # kernels and the amplitude line search in that launch shape): three
+    # iterations against the oracle, as in the default configuration
+    masks, T, I, _ = problem(n1, n2, 4, P, cfg=942, noise=1e4)
+    t0 = T + 0.3 * tm_synth.tm_iid(P, n1 * n2, tm_synth.rng(942, 3))
+    m, t, Ir = rounded(masks, t0, I)
+    op = ops.FFTOp(m, n1, n2)
+    iters = 3
+    ref_i, _ = rt.lbfgs(op, Ir, t, iters, m=5)
+    ref_a, _ = rt.lbfgs_amplitude(op, Ir, t, iters, m=5)
+    tm.tm_set_config(ctx, n1, n2, cfg)
+    try:
+        for method, ref in (("lbfgs", ref_i), ("lbfgs_amp", ref_a)):
+            tt = c64(t0)
+            tm.tm_retrieve(ctx, c64(masks), f32(I), tt, n1, n2, tm.retrieve_opts(method, iters=iters, lbfgs_m=5))
+            err = relerr(tt.cpu().numpy().astype(np.complex128), ref)
+            print(f"config {cfg} grid {n1}x{n2} {method} relerr {err:.3e}", flush=True)
+            assert err < (1e-4 * iters if method == "lbfgs" else 1e-3), (method, err)
+    finally:
+        tm.tm_set_config(ctx, n1, n2, 0)
+
+
 def test_config_rejections(ctx):
     with pytest.raises(tm.TMError, match="not compiled"):
         tm.tm_set_config(ctx, 128, 64, 4)
