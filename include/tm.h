@@ -325,7 +325,9 @@ int tm_phase_offset_correct(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_
  *          unchanged), [5], [6] the offending rows.
  * Other arguments as tm_phase_offset_correct. Allocates its workspace on
  * the first call of a size, as that call does; tm_phase_last_counts keeps
- * reporting the last synchronous call. Errors: TM_EINVAL for bad sizes,
+ * reporting the last synchronous call. The solve's state lives in the
+ * context's workspace: calls on one context must be queued on one stream
+ * (solves meant to overlap each other need a context each). Errors: TM_EINVAL for bad sizes,
  * optics or options, evals out of range or rec NULL, returned at once; pix
  * errors only through rec[4]. */
 int tm_phase_offset_correct_async(tm_ctx *ctx, const tm_defocus_dims *dd, const int32_t *pix,

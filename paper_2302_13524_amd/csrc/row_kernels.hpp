@@ -3,6 +3,7 @@
 // rows independent (the per-pixel decomposition of Sec. 2.2).
 #pragma once
 #include "fft_core.hpp"
+#include "lbfgs.hpp"
 
 namespace tmk {
 
@@ -69,8 +70,8 @@ struct RowArgs {
   // prologue from the compact-form coefficients of the direction solve,
   //   d = cg g + sum_j (cs_j s_j + cy_j y_j)  over the row's stored pairs,
   // written to lb_d (and read back from there by the mask loop; din unused).
-  // lb_S, lb_Y: [P][lb_m + 1][N] rings; lb_sc: [P][LB_SCALARS(lb_m)] with
-  // head, count at 0, 1 and the coefficients from 4 + 2 (lb_m + 1)^2 on.
+  // lb_S, lb_Y: [P][LB_SLOTS(lb_m)][N] rings; lb_sc: [P][LB_SCALARS(lb_m)]
+  // with head, count at 0, 1 and the coefficients from 4 + 2 LB_SLOTS^2 on.
   const cx<float>* lb_g;
   const cx<float>* lb_S;
   const cx<float>* lb_Y;
@@ -289,8 +290,8 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
     if (a.lb_sc) {
       // the L-BFGS direction at this thread's values, two stored pairs' loads in
       // flight at a time; each thread later reads back only what it wrote here
-      const int R = a.lb_m + 1;
-      const double* sc = a.lb_sc + prow * (size_t)(4 + 2 * R * R + 1 + 2 * R);
+      const int R = LB_SLOTS(a.lb_m);
+      const double* sc = a.lb_sc + prow * (size_t)LB_SCALARS(a.lb_m);
       const int head = (int)sc[0], count = (int)sc[1];
       const double* coef = sc + 4 + 2 * R * R;
       const float cg = (float)coef[0];
