@@ -74,6 +74,13 @@ def test_defocus_arguments():
            phi.float(), nf1, nf2, match="phi: dtype")
     raises(tm.tm_defocus_forward, CTX, pix[:2], c64(P, N), c64(Nd, N), (1, .5, .2, 20), phi, nf1, nf2,
            match="pix: shape")
+    rec = torch.zeros((8,), dtype=torch.float64)
+    raises(tm.tm_phase_offset_correct_async, CTX, pix, c64(P, N), c64(Nd, N + 1), Id, (1, .5, .2, 20), phi, nf1,
+           nf2, rec, 10, match="theta: shape")
+    for bad in (torch.zeros((6,), dtype=torch.float64), torch.zeros((8,), dtype=torch.float32),
+                torch.zeros((8, 2), dtype=torch.float64)[:, 0]):
+        raises(tm.tm_phase_offset_correct_async, CTX, pix, c64(P, N), c64(Nd, N), Id, (1, .5, .2, 20), phi, nf1,
+               nf2, bad, 10, match="rec")
 
 
 def test_other_entry_points():
