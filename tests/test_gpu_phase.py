@@ -360,3 +360,40 @@ def test_async_solve_records_bad_pixels_and_rejects_bad_arguments(ctx):
                 torch.zeros(8, dtype=torch.float64)):
         with pytest.raises(tm.TMError, match="rec"):
             tm.tm_phase_offset_correct_async(ctx, pix_d, *rest, phi, nf, nf, bad, 30, iters=20, m=5)
+
+
+def test_async_solves_overlap_on_two_streams(ctx):
+    # two problems solved at once, each on its own context and stream (the
+    # pattern of a pipelined caller): each equals its synchronous solve
+    nf, P, N, Nd, NA = 32, 512, 1024, 50, 0.3
+    probs = []
+    for cfg in (965, 966):
+        pix, tm_est, theta, Id, _, _ = build(nf, P, N, Nd, NA, 0.6, cfg=cfg, noise=1e4)
+        probs.append((torch.from_numpy(pix.astype(np.int32)).to(dev()), c64(tm_est), c64(theta), f32(Id),
+                      (LAM, PS, NA, 20 * LAM)))
+    sync = []
+    for args in probs:
+        phi = torch.zeros(P, dtype=torch.float64, device=dev())
+        g = tm.tm_phase_offset_correct(ctx, *args, phi, nf, nf, iters=30, m=1)
+        sync.append((phi, g, tm.tm_phase_last_counts(ctx)))
+    ctxs = [tm.Context(0), tm.Context(0)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    try:
+        recs = torch.zeros((2, 8), dtype=torch.float64, device=dev())
+        phis = [torch.zeros(P, dtype=torch.float64, device=dev()) for _ in range(2)]
+        for s in streams:
+            s.wait_stream(torch.cuda.current_stream())
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                tm.tm_phase_offset_correct_async(ctxs[k], *probs[k], phis[k], nf, nf, recs[k], sync[k][2][1] + 2,
+                                                 iters=30, m=1)
+        for s in streams:
+            torch.cuda.current_stream().wait_stream(s)
+        r = recs.cpu().numpy()
+        for k in range(2):
+            assert torch.equal(phis[k], sync[k][0])
+            assert r[k, 0] == sync[k][1] and (r[k, 1], r[k, 2], r[k, 3], r[k, 4]) == (30, sync[k][2][1], 1, 0)
+        assert not torch.equal(phis[0], phis[1])
+    finally:
+        for c in ctxs:
+            c.close()
