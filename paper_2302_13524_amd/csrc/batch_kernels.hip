@@ -37,85 +37,124 @@ constexpr int lds_of() {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kLds = cmax(cmax(lds_of<Plan<5, 5>>(), lds_of<Plan<6, 5>>()), cmax(lds_of<Plan<6, 6>>(), lds_of<Plan<7, 6>>()));
 
+// Launch-wide values the item bodies need. They reach the out-of-line bodies as
+// scalars: a struct passed to a non-inlined function goes through private
+// memory (the row arguments were stored there for every item and read back by
+// per-lane loads).
+struct ItemLaunch {
+  float tau, momentum, lower, er_beta;
+  int swap, lz_j, lz_fuse, lz_k;
+};
+
+__device__ __forceinline__ float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+// A table entry at a wave-uniform address, word by word through the constant
+// address space (the tables are not written while the kernel runs), so that
+// every word is a scalar load.
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) uint32_t* WordC;
+  const WordC src = (WordC)p;
+  S v;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(S) / 4); ++k) dst[k] = src[k];
+  return v;
+}
+
 // One out-of-line body per specialisation, so that each gets its own register
-// allocation instead of the union of all of them.
-template <class PL, int M, typename IT, bool SUMS>
-__device__ __attribute__((noinline)) void item_body(const RowArgs& a, int blk, cx<float>* lds, float* red) {
-  row_body<PL, M, IT, SUMS, BATCH_WG, true>(a, blk, lds, red);
+// allocation instead of the union of all of them. It builds the row arguments
+// of item `it` from the problem table (wave-uniform, so scalar loads).
+template <class PL, int M, int MODE, typename IT, bool SUMS>
+__device__ __attribute__((noinline)) void item_body(const BatchProb* probs, const BatchItem* items, int it,
+                                                     const cx<float>* tw32, float tau, float momentum, float lower,
+                                                     float er_beta, int swap, int lz_j, int lz_fuse, int lz_k,
+                                                     cx<float>* lds, float* red) {
+  it = __builtin_amdgcn_readfirstlane(it);
+  const ItemLaunch b{uniform_f(tau), uniform_f(momentum), uniform_f(lower), uniform_f(er_beta),
+                     __builtin_amdgcn_readfirstlane(swap), __builtin_amdgcn_readfirstlane(lz_j),
+                     __builtin_amdgcn_readfirstlane(lz_fuse), __builtin_amdgcn_readfirstlane(lz_k)};
+  const BatchItem w = load_uniform(wave_uniform(items) + it);
+  const BatchProb pr = load_uniform(wave_uniform(probs) + __builtin_amdgcn_readfirstlane(w.prob));
+  RowArgs a;
+  a.P = pr.P;
+  a.K = pr.K;
+  a.masks = pr.masks;
+  // spectral steps and ER with momentum read the iterate and the previous
+  // one and overwrite the previous one; the two buffers swap roles every step
+  const bool mom = MODE == BATCH_ER && b.er_beta != 0.f;
+  const bool two = mom || MODE == BATCH_SPEC;
+  cx<float>* cur = (two && b.swap) ? pr.vprev : pr.t;
+  cx<float>* oth = (two && b.swap) ? pr.t : pr.vprev;
+  a.tin = cur;
+  a.tout = two ? oth : cur;
+  a.din = oth;
+  a.vscale = pr.vscale;
+  a.I = pr.I;
+  a.yin = nullptr;
+  a.yout = nullptr;
+  a.sums = SUMS ? pr.sums : nullptr;
+  a.sums64 = nullptr;
+  a.rowmean = pr.rowmean;
+  a.tau = b.tau;
+  a.momentum = b.momentum;
+  a.spec_lower = b.lower;
+  a.er_beta = mom ? b.er_beta : 0.f;
+  a.lz_bprev = nullptr;
+  a.lz_out = nullptr;
+  a.lb_sc = nullptr;  // no L-BFGS modes in the batch
+  if constexpr (MODE == BATCH_LZ) {
+    // step j from V(j) to V(j + 1), V(0) = t, V(i) = lzV + (i - 1) P N; (alpha, beta) into row j of lzH
+    const int j = b.lz_j;
+    const size_t rs = (size_t)pr.P * pr.N;
+    auto V = [&](int i) { return i == 0 ? pr.t : pr.lzV + (size_t)(i - 1) * rs; };
+    a.tin = V(j);
+    a.din = V(j > 0 ? j - 1 : 0);
+    a.tout = V(j + 1);
+    a.lz_bprev = j > 0 ? pr.lzH + (size_t)(j - 1) * pr.P * 2 : nullptr;
+    a.lz_out = pr.lzH + (size_t)j * pr.P * 2;
+  }
+  a.lz_basis = nullptr;
+  a.lz_y = nullptr;
+  a.lz_k = 0;
+  a.lz_rs = 0;
+  if constexpr (MODE == BATCH_ERC) {
+    if (b.lz_fuse) {
+      a.lz_basis = pr.lzV;
+      a.lz_y = pr.lzY;
+      a.lz_k = b.lz_k;
+      a.lz_rs = (int64_t)pr.P * pr.N;
+    }
+  }
+  a.out_bf16 = 0;
+  a.tw32 = wave_uniform(tw32);
+  a.tw64 = nullptr;
+  row_body<PL, M, IT, SUMS, BATCH_WG, true>(a, w.blk, lds, red);
 }
 
 template <int MODE, typename IT, bool SUMS>
 __global__ void __launch_bounds__(BATCH_WG) batch_kernel(BatchArgs b) {
   __shared__ cx<float> lds[kLds];
   __shared__ float red[Launch<Plan<7, 6>, BATCH_WG>::RED_FLOATS];
+  constexpr int M = (MODE == BATCH_ER) ? M_ER : (MODE == BATCH_ERC) ? M_ERC : (MODE == BATCH_LZ) ? M_LANCZOS : M_SPEC;
   for (int it = blockIdx.x; it < b.n_items; it += gridDim.x) {
-    const BatchItem w = b.items[it];
-    const BatchProb pr = b.probs[w.prob];
-    RowArgs a;
-    a.P = pr.P;
-    a.K = pr.K;
-    a.masks = pr.masks;
-    // spectral steps and ER with momentum read the iterate and the previous
-    // one and overwrite the previous one; the two buffers swap roles every step
-    const bool mom = MODE == BATCH_ER && b.er_beta != 0.f;
-    const bool two = mom || MODE == BATCH_SPEC;
-    cx<float>* cur = (two && b.swap) ? pr.vprev : pr.t;
-    cx<float>* oth = (two && b.swap) ? pr.t : pr.vprev;
-    a.tin = cur;
-    a.tout = two ? oth : cur;
-    a.din = oth;
-    a.vscale = pr.vscale;
-    a.I = pr.I;
-    a.yin = nullptr;
-    a.yout = nullptr;
-    a.sums = SUMS ? pr.sums : nullptr;
-    a.sums64 = nullptr;
-    a.rowmean = pr.rowmean;
-    a.tau = b.tau;
-    a.momentum = b.momentum;
-    a.spec_lower = b.lower;
-    a.er_beta = mom ? b.er_beta : 0.f;
-    a.lz_bprev = nullptr;
-    a.lz_out = nullptr;
-    a.lb_sc = nullptr;  // no L-BFGS modes in the batch
-    if constexpr (MODE == BATCH_LZ) {
-      // step j from V(j) to V(j + 1), V(0) = t, V(i) = lzV + (i - 1) P N; (alpha, beta) into row j of lzH
-      const int j = b.lz_j;
-      const size_t rs = (size_t)pr.P * pr.N;
-      auto V = [&](int i) { return i == 0 ? pr.t : pr.lzV + (size_t)(i - 1) * rs; };
-      a.tin = V(j);
-      a.din = V(j > 0 ? j - 1 : 0);
-      a.tout = V(j + 1);
-      a.lz_bprev = j > 0 ? pr.lzH + (size_t)(j - 1) * pr.P * 2 : nullptr;
-      a.lz_out = pr.lzH + (size_t)j * pr.P * 2;
-    }
-    a.lz_basis = nullptr;
-    a.lz_y = nullptr;
-    a.lz_k = 0;
-    a.lz_rs = 0;
-    if constexpr (MODE == BATCH_ERC) {
-      if (b.lz_fuse) {
-        a.lz_basis = pr.lzV;
-        a.lz_y = pr.lzY;
-        a.lz_k = b.lz_k;
-        a.lz_rs = (int64_t)pr.P * pr.N;
-      }
-    }
-    a.out_bf16 = 0;
-    a.tw32 = b.tw32;
-    a.tw64 = nullptr;
-    constexpr int M = (MODE == BATCH_ER) ? M_ER : (MODE == BATCH_ERC) ? M_ERC : (MODE == BATCH_LZ) ? M_LANCZOS : M_SPEC;
-    switch (pr.code) {
-      case 0: item_body<Plan<5, 5, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
-      case 1: item_body<Plan<5, 5, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
-      case 2: item_body<Plan<6, 5, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
-      case 3: item_body<Plan<6, 5, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
+    const int code = b.probs[b.items[it].prob].code;
+#define TM_ITEM(...)                                                                                      \
+  item_body<__VA_ARGS__, M, MODE, IT, SUMS>(b.probs, b.items, it, b.tw32, b.tau, b.momentum, b.lower, b.er_beta, \
+                                            b.swap, b.lz_j, b.lz_fuse, b.lz_k, lds, red)
+    switch (code) {
+      case 0: TM_ITEM(Plan<5, 5, -1, 0>); break;
+      case 1: TM_ITEM(Plan<5, 5, -1, 1>); break;
+      case 2: TM_ITEM(Plan<6, 5, -1, 0>); break;
+      case 3: TM_ITEM(Plan<6, 5, -1, 1>); break;
       case 4:
-      case 5: item_body<Plan<6, 6, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
-      case 6: item_body<Plan<7, 6, -1, 0>, M, IT, SUMS>(a, w.blk, lds, red); break;
-      case 7: item_body<Plan<7, 6, -1, 1>, M, IT, SUMS>(a, w.blk, lds, red); break;
+      case 5: TM_ITEM(Plan<6, 6, -1, 0>); break;
+      case 6: TM_ITEM(Plan<7, 6, -1, 0>); break;
+      case 7: TM_ITEM(Plan<7, 6, -1, 1>); break;
       default: break;
     }
+#undef TM_ITEM
     __syncthreads();  // LDS of this item is free before the next item writes it
   }
 }
