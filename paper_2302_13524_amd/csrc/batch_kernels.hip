@@ -56,10 +56,11 @@ __device__ __forceinline__ S load_uniform(const S* p) {
   static_assert(sizeof(S) % 4 == 0, "whole words");
   typedef const __attribute__((address_space(4))) uint32_t* WordC;
   const WordC src = (WordC)p;
-  S v;
-  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+  uint32_t words[sizeof(S) / 4];
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(S) / 4); ++k) dst[k] = src[k];
+  for (int k = 0; k < (int)(sizeof(S) / 4); ++k) words[k] = src[k];
+  S v;
+  __builtin_memcpy(&v, words, sizeof(S));
   return v;
 }
 
