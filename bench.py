@@ -708,13 +708,20 @@ def main():
     if fused:
         kernels["er"]["bytes"] += P * (sp - 1) * N * 8 / n_er
         kernels["er"]["name"] += "; the first sweep forms the Ritz vector from the Lanczos basis"
+    # the first Lanczos step also forms the row sums of I and scales the seed to unit norm: one more read
+    # of I, the seed written back and K N + 4 N additions per row; averaged over the start's launches
+    sp_extra_flops = (K * N + 4 * N) / sp if sp_mode == 13 else 0.0
+    if sp_mode == 13:
+        kernels["spectral"]["bytes"] += P * (K * N * 4 + N * 8) / sp
+        kernels["spectral"]["name"] += "; the first step also forms the row sums of I and the unit seed"
+    extra_flops = {"er": er_extra_flops, "spectral": sp_extra_flops}
     for kv in kernels.values():
         kv["name"] += cfg_note
     traffic = measured_traffic(P, N, plan_tag(n1.bit_length() - 1, n2.bit_length() - 1, tune["config"]))
     roofs = {}
     for key, kv in kernels.items():
         avg = kv["ms"] / max(kv["n"], 1)
-        tf = P * (flops_row + (er_extra_flops if key == "er" else 0.0)) / (avg * 1e-3) / 1e12
+        tf = P * (flops_row + extra_flops[key]) / (avg * 1e-3) / 1e12
         gbs = kv["bytes"] / (avg * 1e-3) / 1e9
         tkey = {"er": "er_cyclic" if solver == "er_cyclic" else "er",
                 "spectral": "lanczos" if sp_mode == 13 else "spectral"}[key]
@@ -723,7 +730,7 @@ def main():
             "alu": {"bound": "alu", "kernel": kv["name"], "achieved": round(tf, 2), "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
                     "traffic": tr, "avg_launch_ms": round(avg, 5), "launches": kv["n"],
-                    "alg_flops_per_launch": int(P * (flops_row + (er_extra_flops if key == "er" else 0.0))),
+                    "alg_flops_per_launch": int(P * (flops_row + extra_flops[key])),
                     "alg_bytes_per_launch": int(kv["bytes"])},
             "hbm": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tr},

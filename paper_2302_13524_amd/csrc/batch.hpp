@@ -22,7 +22,8 @@ struct BatchProb {
   cx<float>* vprev;
   float* vscale;        // [P] spectral previous-iterate scale
   float* sums;          // [P][6] or null
-  const float* rowmean;
+  float* rowmean;       // [P] mean of I per row (the first Lanczos step writes it)
+  double* rowsum;       // [P] sum of I per row (the same)
   cx<float>* lzV;       // Lanczos basis v_2 .. v_{k+1} [k][P][N] (v_1 is t)
   float* lzH;           // Lanczos (alpha, beta) [k][P][2]
   const double* lzY;    // Ritz coefficients [P][k]

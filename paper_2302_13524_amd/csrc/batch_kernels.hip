@@ -104,6 +104,8 @@ __device__ __attribute__((noinline)) void item_body(const BatchProb* probs, cons
   a.er_beta = mom ? b.er_beta : 0.f;
   a.lz_bprev = nullptr;
   a.lz_out = nullptr;
+  a.lz_sum = nullptr;
+  a.lz_mean = nullptr;
   a.lb_sc = nullptr;  // no L-BFGS modes in the batch
   if constexpr (MODE == BATCH_LZ) {
     // step j from V(j) to V(j + 1), V(0) = t, V(i) = lzV + (i - 1) P N; (alpha, beta) into row j of lzH
@@ -115,6 +117,10 @@ __device__ __attribute__((noinline)) void item_body(const BatchProb* probs, cons
     a.tout = V(j + 1);
     a.lz_bprev = j > 0 ? pr.lzH + (size_t)(j - 1) * pr.P * 2 : nullptr;
     a.lz_out = pr.lzH + (size_t)j * pr.P * 2;
+    if (j == 0) {  // row sums, means and the unit seed, as the single-problem first step
+      a.lz_sum = pr.rowsum;
+      a.lz_mean = pr.rowmean;
+    }
   }
   a.lz_basis = nullptr;
   a.lz_y = nullptr;

@@ -53,6 +53,12 @@ struct RowArgs {
   float er_beta;           // M_ER Nesterov factor b: iterate from z = tin + b (tin - din), din = t_prev
   const float* lz_bprev;   // M_LANCZOS: previous step's [P][2] (alpha, beta); beta is this step's beta, or null
   float* lz_out;           // M_LANCZOS: [P][2] (alpha, ||x||) of this step
+  // M_LANCZOS with lz_sum != null (the first step): the prologue forms each
+  // row's intensity sum (FP64, into lz_sum [P]) and mean (into lz_mean [P],
+  // used in place of rowmean), and scales the seed in tin to unit norm (FP64
+  // norm), writing it back over tin
+  double* lz_sum;
+  float* lz_mean;
   const float* wtab;       // learned weights: [nt][2] (T(x_b), T(x_b+1) - T(x_b)), x_b = b / wtab_scale
   float wtab_scale;        // (nt - 1) / xmax
   float wtab_last;         // nt - 1
@@ -180,6 +186,40 @@ __device__ __forceinline__ void row_reduce(KSum* acc, float* red, int tid, float
   }
 }
 
+// Two FP64 sums over the T threads of a row group, through the float scratch
+// of row_reduce (each double as two 32-bit halves). Result in every thread.
+template <int T, int WG>
+__device__ __forceinline__ void row_reduce64x2(double& u, double& v, float* red, int tid) {
+  const int n = (T <= 64) ? T / 2 : 32;
+#pragma unroll
+  for (int off = n; off >= 1; off >>= 1) {
+    u += __shfl_xor(u, off, 64);
+    v += __shfl_xor(v, off, 64);
+  }
+  if constexpr (T > 64) {
+    constexpr int WPR = T / 64;
+    const int wave = tid >> 6;
+    __syncthreads();
+    if ((tid & 63) == 0) {
+      const uint64_t bu = (uint64_t)__double_as_longlong(u), bv = (uint64_t)__double_as_longlong(v);
+      red[wave * 4 + 0] = __uint_as_float((uint32_t)bu);
+      red[wave * 4 + 1] = __uint_as_float((uint32_t)(bu >> 32));
+      red[wave * 4 + 2] = __uint_as_float((uint32_t)bv);
+      red[wave * 4 + 3] = __uint_as_float((uint32_t)(bv >> 32));
+    }
+    __syncthreads();
+    const int w0 = (wave / WPR) * WPR;
+    double su = 0.0, sv = 0.0;
+    for (int w = 0; w < WPR; ++w) {
+      const float* q = red + (w0 + w) * 4;
+      su += __longlong_as_double((long long)(((uint64_t)__float_as_uint(q[1]) << 32) | __float_as_uint(q[0])));
+      sv += __longlong_as_double((long long)(((uint64_t)__float_as_uint(q[3]) << 32) | __float_as_uint(q[2])));
+    }
+    u = su;
+    v = sv;
+  }
+}
+
 template <int T, int WG>
 __device__ __forceinline__ double row_reduce64(double v, double* red, int tid) {
   if constexpr (T <= 64) {
@@ -286,6 +326,39 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 #pragma unroll
     for (int i = 0; i < E; ++i) treg[i] = gload(trow + E0(i));
   }
+  float lz_mean0 = 1.f;  // the row's mean intensity when this (first Lanczos) step forms it
+  if constexpr (MODE == M_LANCZOS) {
+    if (a.lz_sum) {
+      // seed norm and intensity sum in FP64; the intensities read along the
+      // row (consecutive threads, consecutive values), mask by mask
+      double sn = 0.0, si = 0.0;
+#pragma unroll
+      for (int i = 0; i < E; ++i)
+        sn += fmadd((double)treg[i].x, (double)treg[i].x, (double)treg[i].y * (double)treg[i].y);
+      const size_t ib = prow * (size_t)a.K * N;
+      for (int m = 0; m < a.K; ++m) {
+        float iv[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) iv[i] = load_I<IT>(a.I, ib + (size_t)m * N + i * PL::T + ltid);
+#pragma unroll
+        for (int i = 0; i < E; ++i) si += (double)iv[i];
+      }
+      row_reduce64x2<PL::T, WG>(sn, si, red, tid);
+      const float f = (float)((sn > 0.0) ? 1.0 / sqrt(sn) : 1.0);
+#pragma unroll
+      for (int i = 0; i < E; ++i) treg[i] = scl(treg[i], f);
+      lz_mean0 = (float)(si / (double)((size_t)a.K * N));
+      if (valid) {
+        C* t1 = const_cast<C*>(trow);
+#pragma unroll
+        for (int i = 0; i < E; ++i) gstore(t1 + E0(i), treg[i]);
+        if (ltid == 0) {
+          gw(a.lz_sum)[prow] = si;
+          gw(a.lz_mean)[prow] = lz_mean0;
+        }
+      }
+    }
+  }
   if constexpr (MODE == M_LS || MODE == M_ALS) {
     if (a.lb_sc) {
       // the L-BFGS direction at this thread's values, two stored pairs' loads in
@@ -386,7 +459,9 @@ __device__ __forceinline__ void row_body(const RowArgs& args, int blk, cx<float>
 
   float inv_mean = 0.f;
   if constexpr (MODE == M_SPEC || MODE == M_LANCZOS || learned_mode(MODE)) {
-    float m = valid ? gc(a.rowmean)[prow] : 1.f;
+    float m = 1.f;
+    if (MODE == M_LANCZOS && a.lz_sum) m = lz_mean0;
+    else if (valid) m = gc(a.rowmean)[prow];
     inv_mean = (m > 0.f) ? 1.f / m : 1.f;
   }
 

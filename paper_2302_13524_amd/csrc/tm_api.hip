@@ -520,14 +520,17 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
     float* hist = (float*)ws_get(c, WS_LZ_H, (size_t)k * d.P * 2 * sizeof(float));
     double* y = (double*)ws_get(c, WS_LZ_Y, (size_t)k * d.P * sizeof(double));
     if (!rowsum || !rowmean || !Vw || !hist || !y) return fail(c, TM_ENOMEM, "Lanczos workspace");
-    int e = tmk::launch_row_isum(I, ibf, (int64_t)d.K * N, d.P, rowsum, rowmean, stream);
-    if (!e) e = tmk::launch_row_rescale(t, N, d.P, 0, nullptr, 1.0, stream);
-    if (e) return hipfail(c, e, "Lanczos setup");
+    const bool learned = o->start == TM_START_LEARNED;
+    int e = 0;
+    if (learned) {  // the weights need the row means before the first step; otherwise that step forms them
+      e = tmk::launch_row_isum(I, ibf, (int64_t)d.K * N, d.P, rowsum, rowmean, stream);
+      if (!e) e = tmk::launch_row_rescale(t, N, d.P, 0, nullptr, 1.0, stream);
+      if (e) return hipfail(c, e, "Lanczos setup");
+    }
     auto V = [&](int j) { return j == 0 ? tt : Vw + (size_t)(j - 1) * rowsz; };
     tmk::RowArgs s = a;
     s.rowmean = rowmean;
     s.tau = o->spectral_tau;
-    const bool learned = o->start == TM_START_LEARNED;
     if (learned) {
       // the learned weights of every measurement, evaluated once: the Lanczos
       // steps then read them in place of the intensities (same bytes as FP32 I)
@@ -544,6 +547,8 @@ int tm_retrieve(tm_ctx* c, tm_dims d, const tm_c32* masks, const void* I, tm_c32
       s.tout = V(j + 1);
       s.lz_bprev = j > 0 ? hist + (size_t)(j - 1) * d.P * 2 : nullptr;
       s.lz_out = hist + (size_t)j * d.P * 2;
+      s.lz_sum = (!learned && j == 0) ? rowsum : nullptr;  // the first step: row sums, means, unit seed
+      s.lz_mean = (!learned && j == 0) ? rowmean : nullptr;
       r = run_row(c, fn, learned ? tmk::M_LANCZOS_T : tmk::M_LANCZOS, learned ? 0 : ibf, s, stream);
       if (r) return r;
     }
@@ -1183,13 +1188,7 @@ static int batch_enqueue(tm_batch* b, void* stream) {
       if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 1, b->rowsum[i], (double)p.d.K * N, stream);
     }
   } else if (o.start == TM_START_LANCZOS) {
-    for (int i = 0; i < n; ++i) {
-      const tm_problem& p = b->probs[i];
-      const int N = p.d.n1 * p.d.n2;
-      if (p.d.P == 0) continue;
-      if (!e) e = tmk::launch_row_isum(p.I, ibf, (int64_t)p.d.K * N, p.d.P, b->rowsum[i], b->rowmean[i], stream);
-      if (!e) e = tmk::launch_row_rescale(p.t, N, p.d.P, 0, nullptr, 1.0, stream);
-    }
+    // the first step forms the row sums and means and scales the seeds
     tmk::BatchArgs a = b->args;
     a.tau = o.spectral_tau;
     for (int j = 0; j < o.spectral_iters && !e; ++j) {
@@ -1337,6 +1336,7 @@ extern "C" int tm_batch_create(tm_ctx* c, int32_t n, const tm_problem* probs, co
     hp[i].vscale = b->vscale[i];
     hp[i].sums = b->sums[i];
     hp[i].rowmean = b->rowmean[i];
+    hp[i].rowsum = b->rowsum[i];
     hp[i].K = p.d.K;
     hp[i].P = p.d.P;
   }

@@ -225,6 +225,25 @@ def test_lanczos_start(ctx, k):
     assert np.allclose(np.linalg.norm(got, axis=1) ** 2, Ir.reshape(P, -1).sum(axis=1) / (4 * n1 * n2), rtol=1e-5)
 
 
+@pytest.mark.parametrize("n1,n2,P", [(32, 32, 21), (8, 8, 150), (64, 32, 9)])
+def test_lanczos_start_bf16_intensities(ctx, n1, n2, P):
+    # BF16-stored intensities (the same rounded values on both sides): the first step's
+    # row sums and means come from the BF16 values, and the start keeps ||t||^2 = sum(I)/(K N)
+    K, k = 4, 3
+    masks, T, I64, _ = problem(n1, n2, K, P, cfg=917, noise=1e4)
+    v0 = tm_synth.random_start(P, n1 * n2, np.ones(P), tm_synth.rng(917, 3))
+    I, Iv = device_intensities(I64, True)
+    m, v, _ = rounded(masks, v0, I64)
+    ref = rt.spectral_lanczos(ops.FFTOp(m, n1, n2), Iv, v, k, tau=2.5)
+    tt = c64(v0)
+    tm.tm_retrieve(ctx, c64(masks), I, tt, n1, n2,
+                   tm.retrieve_opts("er", iters=0, start="lanczos", spectral_iters=k, spectral_tau=2.5, bf16=True))
+    got = tt.cpu().numpy().astype(np.complex128)
+    print(f"lanczos bf16 {n1}x{n2} P={P}: relerr {relerr(got, ref):.3e}")
+    assert relerr(got, ref) < OPTOL * k
+    assert np.allclose(np.linalg.norm(got, axis=1) ** 2, Iv.reshape(P, -1).sum(axis=1) / (K * n1 * n2), rtol=1e-5)
+
+
 @pytest.mark.parametrize("n1,n2,P,sweeps", [(32, 32, 21, 1), (32, 32, 21, 2), (32, 32, 21, 3), (64, 32, 9, 2),
                                              (8, 8, 150, 2)])
 def test_lanczos_then_cyclic_sweeps(ctx, n1, n2, P, sweeps):
@@ -263,9 +282,9 @@ def test_lanczos_then_cyclic_sweeps(ctx, n1, n2, P, sweeps):
 
 
 def test_lanczos_start_unaligned_buffers(ctx):
-    # rows and intensities that start 8 and 4 bytes past a 16-byte boundary take
-    # the scalar-load forms of the row sums, the Ritz combination and the
-    # rescaling; the result matches the aligned call and the oracle
+    # rows and intensities that start 8 and 4 bytes past a 16-byte boundary (read
+    # by the first step's row sums and seed scaling, the Ritz combination and the
+    # rescaling); the result matches the aligned call and the oracle
     n1, n2, P, K, k = 32, 32, 21, 4, 3
     N = n1 * n2
     masks, T, I, _ = problem(n1, n2, K, P, cfg=915, noise=1e4)
