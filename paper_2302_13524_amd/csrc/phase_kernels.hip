@@ -806,9 +806,10 @@ __global__ void __launch_bounds__(256) k_band_img(double* Vp, double* gpart, con
   if (skip && *skip) return;
   __shared__ z2 H[BM * BM];
   __shared__ z2 twl1[512], twl2[512];
-  __shared__ z2 TC[BM * 256];  // box rows of the image-axis-2 transform, [j][column of the workgroup]
+  // box rows of the image-axis-2 transform, [j][column of the workgroup] (BT1 CPW <= BT1 / 2 * 256: G >= 2)
+  __shared__ z2 TC[BT1 / 2 * 256];
   __shared__ double wred[4];
-  z2* stage = TC;              // reused for the adjoint partials, [j][l][column]
+  z2* stage = TC;  // reused for the adjoint partials of half the box rows, [j][l][column], then U [j][column]
   const int L1 = 2 * nf1, L2 = 2 * nf2, G = b.G, CPW = b.CPW;
   const int n = blockIdx.y;
   const int cl = threadIdx.x % CPW, l = threadIdx.x / CPW;
@@ -866,17 +867,40 @@ __global__ void __launch_bounds__(256) k_band_img(double* Vp, double* gpart, con
   if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = acc;
   __syncthreads();  // also: every thread has read TC
   if (threadIdx.x == 0) gpart[(size_t)n * gridDim.x + blockIdx.x] = (wred[0] + wred[1]) + (wred[2] + wred[3]);
+  // the column's adjoint: its G threads' parts added, half the box rows at a
+  // time through LDS (half the bytes of staging them all: two workgroups fit a
+  // CU), the sums held in registers until both halves are done
+  constexpr int JH = BT1 / 2;
+  constexpr int RPH = JH / 2;  // outputs per thread and half: JH CPW / 256 = JH / G with G >= 2
+  z2 us[2][RPH];
 #pragma unroll
-  for (int j = 0; j < BT1; ++j)
-    stage[(j * G + l) * CPW + cl] = zmul(x[j], twl1[(j * l) & (L1 - 1)]);  // e^{-2 pi i j l / L1}
-  __syncthreads();
-  // the column's adjoint: its G threads' parts added in place (slot q = 0)
-  for (int o = threadIdx.x; o < b.B1 * CPW; o += 256) {
-    const int j = o / CPW, c2 = o - (o / CPW) * CPW;
-    z2 sacc{0.0, 0.0};
-    for (int q = 0; q < G; ++q) sacc = zadd(sacc, stage[(j * G + q) * CPW + c2]);
-    stage[(j * G) * CPW + c2] = sacc;
+  for (int hf = 0; hf < 2; ++hf) {
+    if (hf) __syncthreads();  // every thread has read the first half's partials
+#pragma unroll
+    for (int jj = 0; jj < JH; ++jj) {
+      const int j = hf * JH + jj;
+      stage[(jj * G + l) * CPW + cl] = zmul(x[j], twl1[(j * l) & (L1 - 1)]);  // e^{-2 pi i j l / L1}
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPH; ++k) {
+      const int o = threadIdx.x + k * 256;
+      const int jj = o / CPW, c2 = o - jj * CPW;
+      z2 sacc{0.0, 0.0};
+      if (jj < JH && hf * JH + jj < b.B1)
+        for (int q = 0; q < G; ++q) sacc = zadd(sacc, stage[(jj * G + q) * CPW + c2]);
+      us[hf][k] = sacc;
+    }
   }
+  __syncthreads();  // every thread has read the second half's partials
+  // U[j][column] at j CPW + column
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+    for (int k = 0; k < RPH; ++k) {
+      const int o = threadIdx.x + k * 256;
+      if (o < JH * CPW) stage[hf * JH * CPW + o] = us[hf][k];
+    }
   __syncthreads();
   // adjoint along axis 2 at the box frequencies over this workgroup's columns:
   // Vp[n][block][i1][i2] = sum_col U[i1][col] e^{-2 pi i s2 col / L2} (the blocks are added by band_pix)
@@ -886,7 +910,7 @@ __global__ void __launch_bounds__(256) k_band_img(double* Vp, double* gpart, con
     z2 acc{0.0, 0.0};
     for (int c2 = 0; c2 < CPW; ++c2) {
       const int cc = blockIdx.x * CPW + c2;
-      if (cc < L2) acc = zfma(stage[(i1 * G) * CPW + c2], twl2[(sm * cc) & (L2 - 1)], acc);
+      if (cc < L2) acc = zfma(stage[i1 * CPW + c2], twl2[(sm * cc) & (L2 - 1)], acc);
     }
     stz(Vp, (((size_t)n * gridDim.x + blockIdx.x) * BM + i1) * BM + i2, acc);
   }
@@ -898,8 +922,8 @@ __global__ void __launch_bounds__(256) k_band_pix(double* Wn, const double* Vp, 
                                                   const double* tw64, const int* skip) {
   if (skip && *skip) return;
   __shared__ z2 V[BM * BM];
-  __shared__ z2 Z[BM * 256];
   __shared__ z2 tw1[256], tw2[256];
+  extern __shared__ z2 Z[];  // [B1][nf2], sized at launch (fewer bytes, more workgroups per CU)
   const int n = blockIdx.y;
   // PIX_BLOCKS blocks of 256 pixels per workgroup share its V and Z (their loads issued first)
   int g[PIX_BLOCKS];
@@ -1079,7 +1103,8 @@ PhaseBand phase_band_plan(const PhaseDims& d, const PhaseOptics& o, int enable) 
   b.B1 = hi1 - lo1 + 1;
   b.s2lo = lo2;
   b.B2 = hi2 - lo2 + 1;
-  b.on = enable && b.B1 <= BM && b.B2 <= BM;
+  // (the image pass needs at least two threads per column: nf1 >= the padded box side)
+  b.on = enable && b.B1 <= BM && b.B2 <= BM && d.nf1 >= band_bt1(b.B1);
   const int bt1 = band_bt1(b.B1);
   b.G = std::max(1, 2 * d.nf1 / bt1);
   b.CPW = 256 / b.G;
@@ -1142,7 +1167,8 @@ int phase_eval(const PhaseDims& d, const int32_t* pix, const float* Id, const do
       case 8: k_band_img<8><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip); break;
       default: k_band_img<16><<<gi, 256, 0, s>>>(w.V, w.gpart, w.Sp, Id, w.h, b, d.nf1, d.nf2, tw64, w.skip);
     }
-    k_band_pix<<<dim3((d.P + 256 * PIX_BLOCKS - 1) / (256 * PIX_BLOCKS), d.Nd), 256, 0, s>>>(w.Wn, w.V, w.c, w.h, pix, b, d.P, d.nf1, d.nf2, tw64,
+    k_band_pix<<<dim3((d.P + 256 * PIX_BLOCKS - 1) / (256 * PIX_BLOCKS), d.Nd), 256,
+                 (size_t)b.B1 * d.nf2 * sizeof(z2), s>>>(w.Wn, w.V, w.c, w.h, pix, b, d.P, d.nf1, d.nf2, tw64,
                                                              w.skip);
     k_band_gather<<<(d.P + 63) / 64, 256, 0, s>>>(grad, w.gval, w.Wn, phi, w.gpart, d.Nd * b.NXB, d.Nd, d.P,
                                                   w.skip, dvec, w.dpart);
