@@ -799,8 +799,12 @@ __device__ __forceinline__ void reg_dft(z2* x) {
 // threads of a column then add their parts: the workgroup writes whole
 // columns of U. A length-BT1 DFT per BT1 pixels replaces BT1 terms per pixel.
 // BT1: the box's axis-1 side padded to 4, 8 or 16 (rows beyond B1 are zero).
+// At least three waves per SIMD (168 VGPRs at BT1 = 16, a few spilled): with
+// 53 KiB of LDS three workgroups then fit a CU beside each other, which is what
+// counts when the solve runs beside a retrieval (pipelined step 9.77 -> 9.74 ms;
+// the solve alone 0.03 ms slower).
 template <int BT1>
-__global__ void __launch_bounds__(256) k_band_img(double* Vp, double* gpart, const double* Sp, const float* Id,
+__global__ void __launch_bounds__(256, 3) k_band_img(double* Vp, double* gpart, const double* Sp, const float* Id,
                                                   const double* h, PhaseBand b, int nf1, int nf2,
                                                   const double* tw64, const int* skip) {
   if (skip && *skip) return;
