@@ -36,118 +36,130 @@ int ilog2(int v) {
 }
 
 // ---- c[n][p] = sum_k theta[n][k] tm[p][k]: FP32 complex inputs, exact FP64
-// products, FP64 sums. Workgroup tile 256 p x NPT NGR n: NGR groups of
-// 256 / NGR threads along n, each thread NGR p x NPT n outputs (4 x 4 in
-// 256 x 16 tiles, 2 x 5 in 256 x 10 tiles, which fit 50 images without padding),
-// K in steps of 32 through LDS (FP32), split over GS chunks of K whose partial
-// sums a second kernel adds in a fixed order. Each output's sum runs over k in
-// the same order whatever the tile.
-constexpr int CG_P = 256, CG_K = 32;
+// products, FP64 sums, on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// Real embedding with the outputs' real and imaginary parts as alternate
+// columns: D[p][2n + c] = sum over complex k and part q of A[p][(k, q)]
+// B[(k, q)][2n + c] with A = (tm_r, tm_i) and
+//   B[(k, 0)][2n] = th_r, B[(k, 1)][2n] = -th_i   (real part)
+//   B[(k, 0)][2n+1] = th_i, B[(k, 1)][2n+1] = th_r (imaginary part),
+// so one 16 x 16 x 4 product covers two complex k; a column block is 8 images.
+// Workgroup: 64 p (16 per wave) x 64 n (8 column blocks), K in steps of 32
+// complex values staged in LDS, the next step's tile loaded into registers
+// while the products run; K split over slices whose partial sums a second
+// kernel adds in a fixed order. Operand lanes: lane l gives A[l % 16][l / 16]
+// and B[l / 16][l % 16]; the result's register r of lane l is D[l / 16 + 4 r][l % 16].
+constexpr int CG_P = 64, CG_N = 64, CG_K = 32;
+constexpr int CG_LD = CG_K + 1;  // LDS row stride (complex values)
 
-// Tile loads: every thread issues all of its global loads of a K step before
-// the first LDS store (pairs of complex values per load when N is even).
-template <int NPT, int NGR, bool PAIRS>
+template <bool PAIRS>
+__device__ __forceinline__ void cg_fetch(float2 (&v)[8], const float2* __restrict__ src, int row0, int nrows, int N,
+                                         int kb, int k1) {
+  // 64 rows x 32 complex values; thread t: rows t / 16 + 16 q, values 2 (t % 16), +1
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = (int)(threadIdx.x >> 4) + 16 * q, kk = 2 * (int)(threadIdx.x & 15);
+    const int row = row0 + r, k = kb + kk;
+    float2 a = make_float2(0.f, 0.f), b = a;
+    if (row < nrows) {
+      const float2* s = src + (size_t)row * N + k;
+      if (PAIRS) {
+        if (k < k1) {  // k1 - k is even
+          const float4 w = *(const float4*)s;
+          a = make_float2(w.x, w.y);
+          b = make_float2(w.z, w.w);
+        }
+      } else {
+        if (k < k1) a = s[0];
+        if (k + 1 < k1) b = s[1];
+      }
+    }
+    v[2 * q] = a;
+    v[2 * q + 1] = b;
+  }
+}
+
+__device__ __forceinline__ void cg_store(float2* lds, const float2 (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = (int)(threadIdx.x >> 4) + 16 * q, kk = 2 * (int)(threadIdx.x & 15);
+    lds[r * CG_LD + kk] = v[2 * q];
+    lds[r * CG_LD + kk + 1] = v[2 * q + 1];
+  }
+}
+
+// theta as the B operand's four values per complex element: (th_r, -th_i, th_i, th_r)
+// at index part + 2 (column parity)
+__device__ __forceinline__ void cg_store_b(float4* lds, const float2 (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = (int)(threadIdx.x >> 4) + 16 * q, kk = 2 * (int)(threadIdx.x & 15);
+    lds[r * CG_LD + kk] = make_float4(v[2 * q].x, -v[2 * q].y, v[2 * q].y, v[2 * q].x);
+    lds[r * CG_LD + kk + 1] = make_float4(v[2 * q + 1].x, -v[2 * q + 1].y, v[2 * q + 1].y, v[2 * q + 1].x);
+  }
+}
+
+typedef double cg_d4 __attribute__((ext_vector_type(4)));
+
+// NCB column blocks per workgroup (the images of the first n tile; blocks past
+// the last image compute zeros from zero-filled rows)
+template <bool PAIRS, int NCB>
 __global__ void __launch_bounds__(256) k_cgemm_part(const float2* __restrict__ theta, const float2* __restrict__ tm,
                                                     double* __restrict__ part, int Nd, int P, int N, int kchunk) {
-  constexpr int CN = NPT * NGR, PG = 256 / NGR;
-  __shared__ float2 st[CG_K][CG_P + 4];   // tm tile, [k][p]
-  __shared__ float2 sth[CG_K][CN];        // theta tile, [k][n]
-  const int p0 = blockIdx.x * CG_P, n0 = blockIdx.y * CN, sl = blockIdx.z;
+  __shared__ float2 sT[CG_P * CG_LD];  // tm tile [p][k]
+  __shared__ float4 sH[CG_N * CG_LD];  // theta tile [n][k], four B values per element
+  const int p0 = blockIdx.x * CG_P, n0 = blockIdx.y * CG_N, sl = blockIdx.z;
   const int k0 = sl * kchunk, k1 = min(N, k0 + kchunk);
-  const int tid = threadIdx.x;
-  const int pg = tid % PG, ng = tid / PG;  // outputs p0 + NGR pg + i, n0 + NPT ng + j
-  double ar[NGR][NPT], ai[NGR][NPT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;  // operand row / column, and k quarter: complex k 2 s + g / 2, part g % 2
+  cg_d4 acc[NCB];
 #pragma unroll
-  for (int i = 0; i < NGR; ++i)
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) ar[i][j] = ai[i][j] = 0.0;
-  constexpr int W = PAIRS ? 2 : 1;                        // complex values per load
-  constexpr int LT = CG_P * CG_K / (256 * W);             // tm loads per thread per K step
-  constexpr int NH = CN * CG_K / W;                       // theta loads per K step
-  constexpr int LH = (NH + 255) / 256;                    // per thread
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = cg_d4{0.0, 0.0, 0.0, 0.0};
+  float2 vt[8], vh[8];
+  cg_fetch<PAIRS>(vt, tm, p0, P, N, k0, k1);
+  cg_fetch<PAIRS>(vh, theta, n0, Nd, N, k0, k1);
   for (int kb = k0; kb < k1; kb += CG_K) {
-    float2 vt[LT][W], vh[LH][W];
-#pragma unroll
-    for (int q = 0; q < LT; ++q) {
-      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
-      const int p = p0 + r, k = kb + kk;
-      if constexpr (PAIRS) {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (p < P && k < k1) v = *(const float4*)(tm + (size_t)p * N + k);
-        vt[q][0] = make_float2(v.x, v.y);
-        vt[q][W - 1] = make_float2(v.z, v.w);
-      } else {
-        vt[q][0] = (p < P && k < k1) ? tm[(size_t)p * N + k] : make_float2(0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < LH; ++q) {
-      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
-      const int n = n0 + r, k = kb + kk;
-      const bool ok = e < NH && n < Nd && k < k1;
-      if constexpr (PAIRS) {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ok) v = *(const float4*)(theta + (size_t)n * N + k);
-        vh[q][0] = make_float2(v.x, v.y);
-        vh[q][W - 1] = make_float2(v.z, v.w);
-      } else {
-        vh[q][0] = ok ? theta[(size_t)n * N + k] : make_float2(0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < LT; ++q) {
-      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
-#pragma unroll
-      for (int w = 0; w < W; ++w) st[kk + w][r] = vt[q][w];
-    }
-#pragma unroll
-    for (int q = 0; q < LH; ++q) {
-      const int e = tid + q * 256, r = e / (CG_K / W), kk = (e % (CG_K / W)) * W;
-      if (e < NH) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) sth[kk + w][r] = vh[q][w];
-      }
-    }
+    cg_store(sT, vt);
+    cg_store_b(sH, vh);
     __syncthreads();
+    if (kb + CG_K < k1) {
+      cg_fetch<PAIRS>(vt, tm, p0, P, N, kb + CG_K, k1);
+      cg_fetch<PAIRS>(vh, theta, n0, Nd, N, kb + CG_K, k1);
+    }
+    const float2* ta = sT + (wave * 16 + i) * CG_LD + (g >> 1);
+    // this lane's B value of element (n, k): index part + 2 (column parity)
+    const float* hb = (const float*)(sH + (i >> 1) * CG_LD + (g >> 1)) + ((g & 1) + 2 * (i & 1));
 #pragma unroll 4
-    for (int kk = 0; kk < CG_K; ++kk) {
-      double br[NGR], bi[NGR], cr[NPT], ci[NPT];
+    for (int st = 0; st < CG_K / 2; ++st) {
+      const float2 t = ta[2 * st];
+      const double a = (double)((g & 1) ? t.y : t.x);
 #pragma unroll
-      for (int i = 0; i < NGR; ++i) {
-        const float2 v = st[kk][NGR * pg + i];
-        br[i] = (double)v.x;
-        bi[i] = (double)v.y;
+      for (int cb = 0; cb < NCB; ++cb) {
+        const double b = (double)hb[(cb * 8 * CG_LD + 2 * st) * 4];
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
       }
-#pragma unroll
-      for (int j = 0; j < NPT; ++j) {
-        const float2 v = sth[kk][NPT * ng + j];
-        cr[j] = (double)v.x;
-        ci[j] = (double)v.y;
-      }
-#pragma unroll
-      for (int i = 0; i < NGR; ++i)
-#pragma unroll
-        for (int j = 0; j < NPT; ++j) {
-          ar[i][j] = __builtin_fma(cr[j], br[i], ar[i][j]);
-          ar[i][j] = __builtin_fma(-ci[j], bi[i], ar[i][j]);
-          ai[i][j] = __builtin_fma(cr[j], bi[i], ai[i][j]);
-          ai[i][j] = __builtin_fma(ci[j], br[i], ai[i][j]);
-        }
     }
-    __syncthreads();
+    __syncthreads();  // every wave has read the tiles before the next store
   }
 #pragma unroll
-  for (int j = 0; j < NPT; ++j) {
-    const int n = n0 + NPT * ng + j;
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int col = cb * 16 + i, n = n0 + (col >> 1), c = col & 1;
 #pragma unroll
-    for (int i = 0; i < NGR; ++i) {
-      const int p = p0 + NGR * pg + i;
-      if (n < Nd && p < P) {
-        const size_t o = (((size_t)sl * Nd + n) * P + p) * 2;
-        part[o] = ar[i][j];
-        part[o + 1] = ai[i][j];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int p = p0 + wave * 16 + g + 4 * r;
+      if (n < Nd && p < P) part[(((size_t)sl * Nd + n) * P + p) * 2 + c] = acc[cb][r];
     }
+  }
+}
+
+template <bool PAIRS>
+static void cgemm_launch(int ncb, dim3 g, hipStream_t s, const float2* th, const float2* tmv, double* part,
+                         const PhaseDims& d, int kchunk) {
+  switch (ncb) {
+#define TM_CG(K) \
+  case K: k_cgemm_part<PAIRS, K><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk); break;
+    TM_CG(1) TM_CG(2) TM_CG(3) TM_CG(4) TM_CG(5) TM_CG(6) TM_CG(7)
+    default: k_cgemm_part<PAIRS, 8><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
+#undef TM_CG
   }
 }
 
@@ -1708,36 +1720,33 @@ int phase_lb_iter(PhaseLb& L, int P, int m, int iters, double ftol, const double
 }  // namespace tmk
 
 namespace tmk {
-// n rows per tile: 10 when that pads the images less than 16 does by at least 15 %
-static int cgemm_rows(int Nd) {
-  const int p16 = (Nd + 15) / 16 * 16, p10 = (Nd + 9) / 10 * 10;
-  return (p10 * 100 <= p16 * 85) ? 10 : 16;
+// K slices: about one round of workgroups at three per CU of a 256-CU device
+// (a second, partial round left most SIMDs with one wave), each slice a whole
+// number of K steps; *kchunk receives the slice length.
+static int cgemm_split(const PhaseDims& d, int* kchunk) {
+  const int tiles = ((d.P + CG_P - 1) / CG_P) * ((d.Nd + CG_N - 1) / CG_N);
+  const int steps = (d.N + CG_K - 1) / CG_K;
+  const int want = std::max(1, std::min(steps, 768 / tiles));
+  const int per = (steps + want - 1) / want;
+  if (kchunk) *kchunk = per * CG_K;
+  return (steps + per - 1) / per;
 }
 
-int phase_cgemm_slices(const PhaseDims& d) {
-  const int CN = cgemm_rows(d.Nd);
-  const int tiles = ((d.P + CG_P - 1) / CG_P) * ((d.Nd + CN - 1) / CN);
-  int gs = 1;
-  while (tiles * gs * 2 <= 2048 && (d.N + 2 * gs - 1) / (2 * gs) >= 256) gs *= 2;
-  return gs;
-}
+int phase_cgemm_slices(const PhaseDims& d) { return cgemm_split(d, nullptr); }
 
 int phase_cgemm(const PhaseDims& d, const void* theta, const void* tm, double* part, double* c, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  const int gs = phase_cgemm_slices(d);
-  int kchunk = (d.N + gs - 1) / gs;
-  kchunk = ((kchunk + CG_K - 1) / CG_K) * CG_K;
-  const int CN = cgemm_rows(d.Nd);
-  dim3 g((d.P + CG_P - 1) / CG_P, (d.Nd + CN - 1) / CN, gs);
+  int kchunk = 0;
+  const int gs = cgemm_split(d, &kchunk);
+  dim3 g((d.P + CG_P - 1) / CG_P, (d.Nd + CG_N - 1) / CG_N, gs);
   const float2* th = (const float2*)theta;
   const float2* tmv = (const float2*)tm;
-  if (CN == 10) {
-    if (d.N % 2 == 0) k_cgemm_part<5, 2, true><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
-    else k_cgemm_part<5, 2, false><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
-  } else {
-    if (d.N % 2 == 0) k_cgemm_part<4, 4, true><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
-    else k_cgemm_part<4, 4, false><<<g, 256, 0, s>>>(th, tmv, part, d.Nd, d.P, d.N, kchunk);
-  }
+  // 16-byte pair loads need even rows; the operands are hipMalloc'd (16-byte aligned)
+  const int ncb = std::min(8, (2 * std::min(d.Nd, CG_N) + 15) / 16);  // column blocks holding images
+  if (d.N % 2 == 0 && (uintptr_t)th % 16 == 0 && (uintptr_t)tmv % 16 == 0)
+    cgemm_launch<true>(ncb, g, s, th, tmv, part, d, kchunk);
+  else
+    cgemm_launch<false>(ncb, g, s, th, tmv, part, d, kchunk);
   const int64_t n = (int64_t)d.Nd * d.P * 2;
   k_cgemm_sum<<<(int)((n + 255) / 256), 256, 0, s>>>(part, c, n, gs);
   return (int)hipGetLastError();
