@@ -45,10 +45,11 @@ def band(ctx, request):
 
 # NA 0.3: pupil boxes of 5, 9 and 19 bins (the last above the band limit, so
 # the band setting falls back to full FFTs); NA 0.22 at 64 x 64 is the
-# 15-bin box of the paper-scale workload
+# 15-bin box of the paper-scale workload; 70 images over an odd N take the
+# c_n product's second image tile and its element-wise loads
 @pytest.mark.parametrize("band", [True, False], indirect=True)
 @pytest.mark.parametrize("nf,P,N,Nd,NA", [(16, 40, 24, 12, 0.3), (32, 512, 1024, 50, 0.3), (64, 2286, 8192, 50, 0.3),
-                                          (64, 2286, 1024, 50, 0.22)])
+                                          (64, 2286, 1024, 50, 0.22), (16, 70, 25, 70, 0.3)])
 def test_objective_and_gradient(ctx, band, nf, P, N, Nd, NA):
     print(f"phase objective nf={nf} P={P} N={N} Nd={Nd} NA={NA} band={band}", flush=True)
     pix, tm_est, theta, Id, phi_true, mdl = build(nf, P, N, Nd, NA, NA, cfg=950, noise=1e4)
