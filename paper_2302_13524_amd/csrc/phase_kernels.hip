@@ -43,10 +43,10 @@ int ilog2(int v) {
 //   B[(k, 0)][2n] = th_r, B[(k, 1)][2n] = -th_i   (real part)
 //   B[(k, 0)][2n+1] = th_i, B[(k, 1)][2n+1] = th_r (imaginary part),
 // so one 16 x 16 x 4 product covers two complex k; a column block is 8 images.
-// Workgroup: 64 p (16 per wave) x 64 n (8 column blocks), K in steps of 32
-// complex values staged in LDS, the next step's tile loaded into registers
-// while the products run; K split over slices whose partial sums a second
-// kernel adds in a fixed order. Operand lanes: lane l gives A[l % 16][l / 16]
+// Workgroup: 64 p (16 per wave) x up to 64 n (NCB <= 8 column blocks), K in
+// steps of 32 complex values staged in LDS (theta as its B values), the next
+// step's tiles loaded into registers while the products run; K split over
+// slices whose partial sums a second kernel adds in a fixed order. Operand lanes: lane l gives A[l % 16][l / 16]
 // and B[l / 16][l % 16]; the result's register r of lane l is D[l / 16 + 4 r][l % 16].
 constexpr int CG_P = 64, CG_N = 64, CG_K = 32;
 constexpr int CG_LD = CG_K + 1;  // LDS row stride (complex values)
